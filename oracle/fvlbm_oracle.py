@@ -1,0 +1,557 @@
+"""Plain, slow, obviously-correct CPU oracle for one IMEX Runge-Kutta step of the cell-centred
+finite-volume lattice Boltzmann method (D2Q9) coupled with the k-omega SST model.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path (the HIP library and its Python binding)
+may import or call this module; only the tests, the smoke check and the benchmark's CPU-baseline
+leg do.  It shares no code with the HIP path: its only input is the mesh dictionary of the
+seeded generator module (nodes, cells, tagged boundary edges) and a parameter dictionary.
+
+Precision: float64 throughout.  Every field array takes the dtype of the parameters, so passing
+a complex parameter (complex step, h = 1e-30) carries exact first derivatives through the whole
+step; geometry stays real.  Branches (max/min, upwind choice) compare real parts.
+
+Paper: Wang, Zhong, Cao, Zhuo, "A simplified finite volume lattice Boltzmann method ... Part II:
+Extension towards turbulent flow simulation" (arXiv 1812.00394).  Citations below name the
+section and equation label of that paper.  Where the paper defers to its Part I (equilibrium,
+face values, gradients, boundary conditions) or is garbled, the readings used are listed at the
+top of each function and collected in the design notes (readings r1-r27).
+
+Half-face convention: every cell edge, seen from its cell, is one "half-face" h with
+  cell[h], nbr[h] (-1 on a boundary), bface[h] (-1 inside), nl[h] = outward normal times length,
+  xf[h] = edge midpoint, xs[h] = stencil point: the neighbour centroid (shifted by the periodic
+  translation when the edge is periodic) or, on a boundary, the edge midpoint.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# ---- D2Q9 lattice (Section 3.1: the discrete-velocity model of Qian et al.; reading r1) ----
+EX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1], dtype=np.float64)
+EY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1], dtype=np.float64)
+WT = np.array([4 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 9, 1 / 36, 1 / 36, 1 / 36, 1 / 36])
+CS2 = 1.0 / 3.0                       # Eq. (turbtau): lattice sound speed squared
+
+WALL, MOVING_WALL, INLET, OUTLET, FARFIELD, PERIODIC = 1, 2, 3, 4, 5, 6
+NO_WALL_DISTANCE = 1e30               # wall distance used when the mesh has no wall
+
+# ---- IMEX tableau (Section 3.1, the coefficient matrices below Eq. (imextwo)) ----
+MT = np.array([[0, 0, 0], [0.5, 0, 0], [0.5, 0.5, 0]])          # explicit (convection) m~_Jk
+MI = np.array([[0.25, 0, 0], [0, 0.25, 0], [1 / 3, 1 / 3, 1 / 3]])  # implicit (collision) m_Jk
+NT = np.array([1 / 3, 1 / 3, 1 / 3])                             # n~_J
+NI = np.array([1 / 3, 1 / 3, 1 / 3])                             # n_J
+
+# ---- SST constants (Section 2, the constant list after the f2 definition) ----
+SST_DEFAULTS = dict(a1=0.31, beta_star=0.09, kappa=0.41, sigma_k1=0.85, sigma_w1=0.5, beta1=0.075,
+                    sigma_k2=1.0, sigma_w2=0.856, beta2=0.0828)
+
+
+def rmax(a, b):
+    """max by real part (identical to max for real input; keeps the complex-step derivative)."""
+    a, b = np.broadcast_arrays(a, b)
+    return np.where(np.real(a) >= np.real(b), a, b)
+
+
+def rmin(a, b):
+    a, b = np.broadcast_arrays(a, b)
+    return np.where(np.real(a) <= np.real(b), a, b)
+
+
+def default_params(**kw):
+    p = dict(nu=1e-3, dt=1e-2, rho0=1.0, sst=False, theta=0.0,
+             group_u=None, group_rho=None, group_k=None, group_w=None, bface_vals=None,
+             jr_group=-1, jr_xmin=0.0, eps_tau=1.0)
+    p.update(SST_DEFAULTS)
+    p.update(kw)
+    return p
+
+
+# =============================================================================================
+# Geometry (computed once, float64).  Readings: r1 (A, n, dl), G1-G4 of the design notes.
+# =============================================================================================
+class Geometry:
+    def __init__(self, mesh):
+        nodes = np.asarray(mesh["nodes"], dtype=np.float64)
+        ptr = np.asarray(mesh["cell_ptr"], dtype=np.int64)
+        cn = np.asarray(mesh["cell_nodes"], dtype=np.int64)
+        self.n = n = len(ptr) - 1
+        nv = np.diff(ptr)
+        if n == 0 or nv.min() < 3 or nv.max() > 4:
+            raise ValueError("cells must have 3 or 4 nodes")
+        # ---- G1: shoelace area and polygon centroid ----
+        cell_of = np.repeat(np.arange(n), nv)
+        local = np.arange(len(cn)) - ptr[cell_of]
+        nxt = ptr[cell_of] + (local + 1) % nv[cell_of]
+        a, b = nodes[cn], nodes[cn[nxt]]
+        cross = a[:, 0] * b[:, 1] - b[:, 0] * a[:, 1]
+        self.area = np.bincount(cell_of, weights=cross, minlength=n) * 0.5
+        if (self.area <= 0).any():
+            raise ValueError("non-positive cell area (cells must be counter-clockwise)")
+        cx = np.bincount(cell_of, weights=(a[:, 0] + b[:, 0]) * cross, minlength=n) / (6 * self.area)
+        cy = np.bincount(cell_of, weights=(a[:, 1] + b[:, 1]) * cross, minlength=n) / (6 * self.area)
+        self.xc = np.stack([cx, cy], axis=1)
+        # ---- G2: half-faces, outward normal * length, midpoints ----
+        H = len(cn)
+        self.cell = cell_of
+        self.nl = np.stack([b[:, 1] - a[:, 1], -(b[:, 0] - a[:, 0])], axis=1)
+        self.l = np.sqrt(self.nl[:, 0] ** 2 + self.nl[:, 1] ** 2)
+        self.nrm = self.nl / self.l[:, None]
+        self.xf = 0.5 * (a + b)
+        na, nb = cn, cn[nxt]
+        key = np.minimum(na, nb) * (len(nodes) + 1) + np.maximum(na, nb)
+        order = np.argsort(key, kind="stable")
+        ks = key[order]
+        uniq, start, cnt = np.unique(ks, return_index=True, return_counts=True)
+        if (cnt > 2).any():
+            raise ValueError("an edge is shared by more than two cells")
+        self.nbr = -np.ones(H, dtype=np.int64)
+        pair = start[cnt == 2]
+        h0, h1 = order[pair], order[pair + 1]
+        self.nbr[h0], self.nbr[h1] = cell_of[h1], cell_of[h0]
+        self.xs = self.xf.copy()
+        self.xs[h0], self.xs[h1] = self.xc[cell_of[h1]], self.xc[cell_of[h0]]
+        # boundary edges
+        bfn = np.asarray(mesh["bface_nodes"], dtype=np.int64).reshape(-1, 2)
+        bgrp = np.asarray(mesh["bface_group"], dtype=np.int64)
+        self.kinds = np.asarray(mesh["group_kind"], dtype=np.int64)
+        shifts = np.asarray(mesh["periodic_shift"], dtype=np.float64).reshape(-1, 2)
+        bkey = np.minimum(bfn[:, 0], bfn[:, 1]) * (len(nodes) + 1) + np.maximum(bfn[:, 0], bfn[:, 1])
+        single = order[start[cnt == 1]]
+        bmap = {int(k): i for i, k in enumerate(bkey)}
+        if len(bmap) != len(bkey):
+            raise ValueError("duplicate boundary edge")
+        self.bface = -np.ones(H, dtype=np.int64)
+        for h in single:
+            i = bmap.get(int(key[h]))
+            if i is None:
+                raise ValueError("boundary edge without a group")
+            self.bface[h] = i
+        if len(single) != len(bkey):
+            raise ValueError("a boundary edge does not lie on the mesh boundary")
+        self.bgroup = bgrp
+        self.kind = np.zeros(H, dtype=np.int64)          # 0 = interior
+        bh = np.nonzero(self.bface >= 0)[0]
+        self.kind[bh] = self.kinds[bgrp[self.bface[bh]]]
+        # periodic edges: the partner edge is the one whose midpoint equals this one's + shift
+        per = bh[self.kind[bh] == PERIODIC]
+        if len(per):
+            scale = np.ptp(nodes, axis=0).max()
+            tol = 1e-9 * scale
+            lookup = {}
+            for h in per:
+                lookup[tuple(np.round(self.xf[h] / tol).astype(np.int64))] = h
+            for h in per:
+                s = shifts[bgrp[self.bface[h]]]
+                target = tuple(np.round((self.xf[h] + s) / tol).astype(np.int64))
+                p = lookup.get(target)
+                if p is None:
+                    raise ValueError("periodic edge without a partner")
+                nb_cell = cell_of[p]
+                self.nbr[h] = nb_cell
+                self.xs[h] = self.xc[nb_cell] - s     # partner centroid seen from this side
+                self.kind[h] = 0
+        self.interior = self.kind == 0
+        # ---- G3: weighted least-squares coefficients c_cj = M_c^-1 w_j d_j, w_j = 1/|d_j|^2 ----
+        d = self.xs - self.xc[cell_of]
+        w = 1.0 / (d[:, 0] ** 2 + d[:, 1] ** 2)
+        M = np.zeros((n, 2, 2))
+        np.add.at(M, cell_of, w[:, None, None] * d[:, :, None] * d[:, None, :])
+        Minv = np.linalg.inv(M)
+        self.lsq = np.einsum("hij,hj->hi", Minv[cell_of], w[:, None] * d)
+        self.d = d
+        # ---- G4: wall distance, brute force point-to-segment over all wall edges ----
+        wall_b = np.nonzero(np.isin(self.kinds[bgrp], [WALL, MOVING_WALL]))[0]
+        self.wall_dist = np.full(n, NO_WALL_DISTANCE)
+        if len(wall_b):
+            P = nodes[bfn[wall_b, 0]]
+            Q = nodes[bfn[wall_b, 1]]
+            for s in range(0, n, 4096):
+                x = self.xc[s:s + 4096, None, :]
+                seg = Q - P
+                t = np.clip(np.sum((x - P) * seg, axis=2) / np.sum(seg * seg, axis=1), 0.0, 1.0)
+                proj = P + t[:, :, None] * seg
+                self.wall_dist[s:s + 4096] = np.sqrt(np.min(np.sum((x - proj) ** 2, axis=2), axis=1))
+        # distance from the cell centre to a boundary edge along its normal (d_perp)
+        self.dperp = np.einsum("hi,hi->h", self.xf - self.xc[cell_of], self.nrm)
+        self.bidx = np.nonzero(~self.interior)[0]         # boundary half-faces
+
+
+# =============================================================================================
+# Equilibrium and moments (reading r1: second-order D2Q9 equilibrium)
+# =============================================================================================
+def feq(rho, ux, uy):
+    """f_eq,a = w_a rho (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 |u|^2); arrays broadcast to [9, ...]."""
+    eu = EX.reshape(9, *([1] * np.ndim(ux))) * ux + EY.reshape(9, *([1] * np.ndim(uy))) * uy
+    w = WT.reshape(9, *([1] * np.ndim(rho)))
+    return w * rho * (1 + 3 * eu + 4.5 * eu * eu - 1.5 * (ux * ux + uy * uy))
+
+
+def moments(g):
+    """rho = sum_a g_a, rho u = sum_a e_a g_a (the collision invariants, reading r4)."""
+    rho = g.sum(axis=0)
+    jx = np.tensordot(EX, g, axes=(0, 0))
+    jy = np.tensordot(EY, g, axes=(0, 0))
+    return rho, jx, jy
+
+
+def stage_solve(rhs, rho, jx, jy, a):
+    """Eq. (fnewstage): the implicit stage f = rhs + a (f_eq(rho, u) - f), with a = dt m_JJ / tau
+    and (rho, rho u) the stage moments (which equal the moments of rhs, Eq. (collisionvariant)),
+    solved explicitly: f = (rhs + a f_eq) / (1 + a).  Returns (f, f_eq)."""
+    fe = feq(rho, jx / rho, jy / rho)
+    return (rhs + a * fe) / (1 + a), fe
+
+
+class Oracle:
+    def __init__(self, mesh, params):
+        self.m = mesh
+        self.g = Geometry(mesh)
+        self.p = dict(params)
+        p = self.p
+        ng = len(self.g.kinds)
+        self.group_u = np.zeros((ng, 2)) if p["group_u"] is None else np.asarray(p["group_u"], float).reshape(ng, 2)
+        self.group_rho = np.full(ng, p["rho0"]) if p["group_rho"] is None else np.asarray(p["group_rho"], float)
+        self.group_k = np.zeros(ng) if p["group_k"] is None else np.asarray(p["group_k"], float)
+        self.group_w = np.ones(ng) if p["group_w"] is None else np.asarray(p["group_w"], float)
+        cplx = any(np.iscomplexobj(p[k]) for k in ("theta", "a1", "beta_star", "sigma_k1", "sigma_w1"))
+        self.dtype = np.complex128 if cplx else np.float64
+        self._boundary_values()
+
+    # ---------------------------------------------------------------------------------------
+    # Boundary data per boundary half-face.  Reading r20: the inflow angle theta rotates every
+    # inlet / far-field velocity.  Per-face values (bface_vals: u, v, rho, k, omega) replace the
+    # group values where given.
+    # ---------------------------------------------------------------------------------------
+    def _boundary_values(self):
+        g, p = self.g, self.p
+        bh = g.bidx
+        bf = g.bface[bh]
+        grp = g.bgroup[bf]
+        kind = g.kind[bh]
+        ub = self.group_u[grp].astype(self.dtype)
+        rb = self.group_rho[grp].astype(self.dtype)
+        kb = self.group_k[grp].astype(self.dtype)
+        wb = self.group_w[grp].astype(self.dtype)
+        if p["bface_vals"] is not None:
+            v = np.asarray(p["bface_vals"], float).reshape(-1, 5)[bf]
+            ub = v[:, 0:2].astype(self.dtype)
+            rb, kb, wb = v[:, 2].astype(self.dtype), v[:, 3].astype(self.dtype), v[:, 4].astype(self.dtype)
+        th = p["theta"]
+        c, s = np.cos(th), np.sin(th)
+        rot = (kind == INLET) | (kind == FARFIELD)
+        ux = np.where(rot, c * ub[:, 0] - s * ub[:, 1], ub[:, 0])
+        uy = np.where(rot, s * ub[:, 0] + c * ub[:, 1], ub[:, 1])
+        ux = np.where(kind == WALL, 0.0, ux)
+        uy = np.where(kind == WALL, 0.0, uy)
+        self.b_kind, self.b_ux, self.b_uy = kind, ux, uy
+        self.b_rho, self.b_k, self.b_w = rb, kb, wb
+        self.b_cell = g.cell[bh]
+        self.b_n = g.nrm[bh]
+        # far field: inflow where the prescribed velocity points into the domain
+        self.b_inflow = np.real(ux * self.b_n[:, 0] + uy * self.b_n[:, 1]) < 0
+
+    # ---------------------------------------------------------------------------------------
+    # Least-squares gradient (G3, reading r2): grad phi_c = sum_j c_cj (phi_j - phi_c), with
+    # phi_j the neighbour value, or on a boundary half-face the ghost value phi_b.
+    # phi: [..., N]; ghost: [..., Hb] ordered like self.g.bidx.  Returns [..., 2, N].
+    # ---------------------------------------------------------------------------------------
+    def lsq_grad(self, phi, ghost):
+        g = self.g
+        H = len(g.cell)
+        lead = phi.shape[:-1]
+        pj = np.zeros(lead + (H,), dtype=np.result_type(phi, ghost))
+        inner = np.nonzero(g.interior)[0]
+        pj[..., inner] = phi[..., g.nbr[inner]]
+        pj[..., g.bidx] = ghost
+        diff = pj - phi[..., g.cell]
+        out = np.zeros(lead + (2, g.n), dtype=pj.dtype)
+        for k in range(2):
+            acc = np.zeros(lead + (g.n,), dtype=pj.dtype)
+            flat = (diff * g.lsq[:, k]).reshape(-1, H)
+            accf = acc.reshape(-1, g.n)
+            for r in range(flat.shape[0]):
+                accf[r] = np.bincount(g.cell, weights=flat[r].real, minlength=g.n)
+                if np.iscomplexobj(flat):
+                    accf[r] = accf[r] + 1j * np.bincount(g.cell, weights=flat[r].imag, minlength=g.n)
+            out[..., k, :] = accf.reshape(lead + (g.n,))
+        return out
+
+    def _cell_sum(self, vals):
+        """sum over the half-faces of each cell: vals [..., H] -> [..., N]."""
+        g = self.g
+        H = len(g.cell)
+        lead = vals.shape[:-1]
+        flat = vals.reshape(-1, H)
+        out = np.zeros((flat.shape[0], g.n), dtype=vals.dtype)
+        for r in range(flat.shape[0]):
+            out[r] = np.bincount(g.cell, weights=flat[r].real, minlength=g.n)
+            if np.iscomplexobj(vals):
+                out[r] = out[r] + 1j * np.bincount(g.cell, weights=flat[r].imag, minlength=g.n)
+        return out.reshape(lead + (g.n,))
+
+    # ---------------------------------------------------------------------------------------
+    # Ghost distribution at boundary edge midpoints (reading r3, non-equilibrium extrapolation
+    # from the cell state; rho_c, u_c are the moments of g in the boundary cell):
+    #   wall / moving wall (all a):      f_eq(rho_c, u_w) + g_c - f_eq(rho_c, u_c)
+    #   inlet, e.n < 0:                  f_eq(rho_c, u_in) + g_c - f_eq(rho_c, u_c)
+    #   outlet, e.n < 0:                 f_eq(rho_b, u_c) + g_c - f_eq(rho_c, u_c)
+    #   far field, e.n < 0:              f_eq(rho_inf, u_inf)
+    #   open boundaries, e.n >= 0:       g_c
+    # ---------------------------------------------------------------------------------------
+    def ghost_f(self, g_arr, rho, ux, uy):
+        c = self.b_cell
+        gc = g_arr[:, c]
+        rc, uxc, uyc = rho[c], ux[c], uy[c]
+        neq = gc - feq(rc, uxc, uyc)
+        en = EX[:, None] * self.b_n[:, 0] + EY[:, None] * self.b_n[:, 1]
+        incoming = en < 0
+        k = self.b_kind
+        wallv = feq(rc, self.b_ux, self.b_uy) + neq
+        inletv = feq(rc, self.b_ux, self.b_uy) + neq
+        outletv = feq(self.b_rho, uxc, uyc) + neq
+        farv = feq(self.b_rho, self.b_ux, self.b_uy) * np.ones_like(gc)
+        out = gc.copy()
+        iswall = (k == WALL) | (k == MOVING_WALL)
+        out = np.where(iswall, wallv, out)
+        out = np.where((k == INLET) & incoming, inletv, out)
+        out = np.where((k == OUTLET) & incoming, outletv, out)
+        out = np.where((k == FARFIELD) & incoming, farv, out)
+        return out
+
+    # ---------------------------------------------------------------------------------------
+    # Convection term, Eq. (advection): Gamma^a_a = -(1/A) sum_m [(e_a.n) f_a,bc dl]_m.
+    # Face value (reading r2): upwind cell value plus the upwind cell's LSQ gradient dotted with
+    # the vector from its centroid to the edge midpoint.  At walls the ghost value is used for
+    # every a; at open boundaries for incoming a only.
+    # ---------------------------------------------------------------------------------------
+    def advection(self, g_arr):
+        G = self.g
+        rho, jx, jy = moments(g_arr)
+        ux, uy = jx / rho, jy / rho
+        gb = self.ghost_f(g_arr, rho, ux, uy)
+        grad = self.lsq_grad(g_arr, gb)                           # [9, 2, N]
+        c = G.cell
+        en = EX[:, None] * G.nl[:, 0] + EY[:, None] * G.nl[:, 1]  # (e.n) dl, [9, H]
+        rc = G.xf - G.xc[c]
+        v_self = g_arr[:, c] + grad[:, 0, c] * rc[:, 0] + grad[:, 1, c] * rc[:, 1]
+        face = v_self.copy()
+        inner = np.nonzero(G.interior)[0]
+        nb = G.nbr[inner]
+        rn = G.xf[inner] - G.xs[inner]                            # from the (shifted) neighbour centroid
+        v_nbr = g_arr[:, nb] + grad[:, 0, nb] * rn[:, 0] + grad[:, 1, nb] * rn[:, 1]
+        face[:, inner] = np.where(en[:, inner] >= 0, v_self[:, inner], v_nbr)
+        bh = G.bidx
+        wall = (self.b_kind == WALL) | (self.b_kind == MOVING_WALL)
+        face[:, bh] = np.where(wall | (en[:, bh] < 0), gb, v_self[:, bh])
+        return -self._cell_sum(en * face) / G.area
+
+    # ---------------------------------------------------------------------------------------
+    # k-omega SST update (Section 2 equations; Section 3.2 coupling; readings r5-r13).
+    # Returns k^{n+1}, omega^{n+1}, nu_t and the relaxation time tau (Eq. (turbtau)).
+    # ---------------------------------------------------------------------------------------
+    def sst_update(self, rho, ux, uy, k, w):
+        G, p = self.g, self.p
+        nu, dt = p["nu"], p["dt"]
+        a1, bstar, kap = p["a1"], p["beta_star"], p["kappa"]
+        sk1, sw1, b1 = p["sigma_k1"], p["sigma_w1"], p["beta1"]
+        sk2, sw2, b2 = p["sigma_k2"], p["sigma_w2"], p["beta2"]
+        cw1 = b1 / bstar - sw1 * kap ** 2 / np.sqrt(bstar)       # reading r7
+        cw2 = b2 / bstar - sw2 * kap ** 2 / np.sqrt(bstar)
+        d = G.wall_dist
+        mu = rho * nu                                             # reading r13
+        c = self.b_cell
+        kind = self.b_kind
+        wall = (kind == WALL) | (kind == MOVING_WALL)
+        outlet = kind == OUTLET
+        far = kind == FARFIELD
+        # zero-gradient where the flow leaves: outlets and far-field outflow edges
+        zg = outlet | (far & ~self.b_inflow)
+        # ghost values at boundary midpoints
+        gux = np.where(zg, ux[c], self.b_ux)
+        guy = np.where(zg, uy[c], self.b_uy)
+        dperp = G.dperp[G.bidx]
+        w_wall = 60.0 * nu / (b1 * dperp ** 2)                    # Menter's wall value of omega
+        gk = np.where(wall, 0.0, np.where(zg, k[c], self.b_k))
+        gw = np.where(wall, w_wall, np.where(zg, w[c], self.b_w))
+        gu = self.lsq_grad(np.stack([ux, uy]), np.stack([gux, guy]))
+        gkw = self.lsq_grad(np.stack([k, w]), np.stack([gk, gw]))
+        dudx, dudy = gu[0, 0], gu[0, 1]
+        dvdx, dvdy = gu[1, 0], gu[1, 1]
+        dkx, dky = gkw[0, 0], gkw[0, 1]
+        dwx, dwy = gkw[1, 0], gkw[1, 1]
+        s11, s22, s12 = dudx, dvdy, 0.5 * (dudy + dvdx)
+        S2 = 2.0 * (s11 * s11 + s22 * s22 + 2.0 * s12 * s12)     # S^2 = 2 S_ij S_ij
+        S = np.sqrt(S2)
+        div = dudx + dvdy
+        gradkw = dkx * dwx + dky * dwy
+        CD = rmax(2.0 * rho * sw2 / w * gradkw, 1e-20)
+        sk = np.sqrt(k)
+        arg1 = rmin(rmax(sk / (0.09 * w * d), 500.0 * nu / (w * d * d)), 4.0 * rho * sw2 * k / (CD * d * d))
+        F1 = np.tanh(arg1 ** 4)
+        arg2 = rmax(2.0 * sk / (0.09 * w * d), 500.0 * nu / (w * d * d))
+        F2 = np.tanh(arg2 ** 2)
+        den = rmax(a1 * w, S * F2)
+        mut = a1 * rho * k / den
+        sig_k = F1 * sk1 + (1 - F1) * sk2                          # reading r8
+        sig_w = F1 * sw1 + (1 - F1) * sw2
+        beta = F1 * b1 + (1 - F1) * b2                             # reading r6
+        gam = F1 * cw1 + (1 - F1) * cw2                            # reading r7
+        P = mut * (S2 - 2.0 / 3.0 * div * div) - 2.0 / 3.0 * rho * k * div
+        Pw = gam * rho * (S2 - 2.0 / 3.0 * div * div) - 2.0 / 3.0 * gam * rho * (den / a1) * div
+        cross = 2.0 * (1 - F1) * rho * sw2 * gradkw / w
+        # ---- face fluxes (Eq. (SSTequint); second-order upwind convection, central diffusion) ----
+        hc = G.cell
+        inner = np.nonzero(G.interior)[0]
+        nb = G.nbr[inner]
+        H = len(hc)
+        mdot = np.zeros(H, dtype=self.dtype)
+        mdot[inner] = 0.5 * ((rho[hc[inner]] * ux[hc[inner]] + rho[nb] * ux[nb]) * G.nl[inner, 0]
+                             + (rho[hc[inner]] * uy[hc[inner]] + rho[nb] * uy[nb]) * G.nl[inner, 1])
+        bh = G.bidx
+        mdot[bh] = rho[c] * (gux * G.nl[bh, 0] + guy * G.nl[bh, 1])
+        rc = G.xf - G.xc[hc]
+        Gk_cell = mu + sig_k * mut
+        Gw_cell = mu + sig_w * mut
+        out = []
+        for phi, gphi, ghost, Gcell in ((k, gkw[0], gk, Gk_cell), (w, gkw[1], gw, Gw_cell)):
+            # convective: mdot * upwind reconstructed value
+            v_self = phi[hc] + gphi[0, hc] * rc[:, 0] + gphi[1, hc] * rc[:, 1]
+            fv = v_self.copy()
+            rn = G.xf[inner] - G.xs[inner]
+            v_nbr = phi[nb] + gphi[0, nb] * rn[:, 0] + gphi[1, nb] * rn[:, 1]
+            fv[inner] = np.where(np.real(mdot[inner]) >= 0, v_self[inner], v_nbr)
+            fv[bh] = np.where(np.real(mdot[bh]) >= 0, v_self[bh], ghost)
+            conv = mdot * fv
+            # diffusive: Gamma_f (grad phi_f . n) dl with the over-relaxed-free correction
+            diff = np.zeros(H, dtype=self.dtype)
+            dvec = G.d[inner]
+            dist = np.sqrt(dvec[:, 0] ** 2 + dvec[:, 1] ** 2)
+            dh = dvec / dist[:, None]
+            ag = 0.5 * (gphi[:, hc[inner]] + gphi[:, nb])
+            corr = (phi[nb] - phi[hc[inner]]) / dist - (ag[0] * dh[:, 0] + ag[1] * dh[:, 1])
+            gfx = ag[0] + corr * dh[:, 0]
+            gfy = ag[1] + corr * dh[:, 1]
+            Gf = 0.5 * (Gcell[hc[inner]] + Gcell[nb])
+            diff[inner] = Gf * (gfx * G.nl[inner, 0] + gfy * G.nl[inner, 1])
+            dirichlet = ~zg
+            diff[bh] = np.where(dirichlet, Gcell[c] * (ghost - phi[c]) / dperp * G.l[bh], 0.0)
+            out.append(self._cell_sum(-conv + diff))
+        net_k, net_w = out
+        k1 = (k + dt / (rho * G.area) * net_k + dt / rho * P) / (1 + dt * bstar * w)
+        w1 = (w + dt / (rho * G.area) * net_w + dt / rho * (Pw + cross)) / (1 + dt * beta * w)
+        k1 = rmax(k1, 1e-20)
+        w1 = rmax(w1, 1e-20)
+        # eddy viscosity from the updated k, omega (F2 re-evaluated), strain from level n
+        sk1_ = np.sqrt(k1)
+        arg2n = rmax(2.0 * sk1_ / (0.09 * w1 * d), 500.0 * nu / (w1 * d * d))
+        F2n = np.tanh(arg2n ** 2)
+        nut = a1 * k1 / rmax(a1 * w1, S * F2n)
+        tau = (nu + nut) / CS2                                     # Eq. (turbtau)
+        self.last_sst = dict(F1=F1, F2=F2, mut=mut, S=S, P=P, CD=CD, div=div)
+        return k1, w1, nut, tau
+
+    # ---------------------------------------------------------------------------------------
+    # One IMEX step, Section 3.1: Eqs. (imexone), (sumimeximplicitnew), (fnewstage),
+    # (collision), (advection), (imextwo).  tau is frozen over the three stages (reading r12).
+    # ---------------------------------------------------------------------------------------
+    def imex_step(self, f, tau):
+        dt = self.p["dt"]
+        rho_n, jx_n, jy_n = moments(f)
+        Ga, Gc = [], []
+        for J in range(3):
+            # Eq. (sumimeximplicitnew): the stage moments need only f^n and earlier convection
+            rho, jx, jy = rho_n.copy(), jx_n.copy(), jy_n.copy()
+            for kk in range(J):
+                r_a, jx_a, jy_a = moments(Ga[kk])
+                rho = rho + dt * MT[J, kk] * r_a
+                jx = jx + dt * MT[J, kk] * jx_a
+                jy = jy + dt * MT[J, kk] * jy_a
+            rhs = f.copy()
+            for kk in range(J):
+                rhs = rhs + dt * (MT[J, kk] * Ga[kk] + MI[J, kk] * Gc[kk])
+            fJ, fe = stage_solve(rhs, rho, jx, jy, dt * MI[J, J] / tau)
+            Gc.append(-(fJ - fe) / tau)                       # Eq. (collision)
+            Ga.append(self.advection(fJ))                     # Eq. (advection)
+        fn1 = f.copy()
+        for J in range(3):                                    # Eq. (imextwo)
+            fn1 = fn1 + dt * NT[J] * Ga[J] + dt * NI[J] * Gc[J]
+        self.last_stages = dict(Ga=Ga, Gc=Gc)
+        return fn1
+
+    # ---------------------------------------------------------------------------------------
+    # Step 0 .. Step 7 of the algorithm at the end of Section 3.2 (SST once per step, r12).
+    # ---------------------------------------------------------------------------------------
+    def init_state(self, rho, ux, uy, k=None, w=None):
+        f = feq(np.asarray(rho, self.dtype), np.asarray(ux, self.dtype), np.asarray(uy, self.dtype))
+        if self.p["sst"]:
+            return f, np.asarray(k, self.dtype).copy(), np.asarray(w, self.dtype).copy()
+        return f, None, None
+
+    def tau_laminar(self):
+        return np.full(self.g.n, self.p["nu"] / CS2)
+
+    def step(self, f, k=None, w=None):
+        rho, jx, jy = moments(f)
+        ux, uy = jx / rho, jy / rho
+        if self.p["sst"]:
+            k, w, nut, tau = self.sst_update(rho, ux, uy, k, w)     # Step 1
+        else:
+            tau = self.tau_laminar()
+            nut = np.zeros(self.g.n)
+        f = self.imex_step(f, tau)                                  # Steps 2-6
+        self.last_tau, self.last_nut = tau, nut
+        return f, k, w
+
+    def run(self, f, k, w, n_steps):
+        for _ in range(n_steps):
+            f, k, w = self.step(f, k, w)
+        return f, k, w
+
+    # ---------------------------------------------------------------------------------------
+    # Step 7 and the monitors: macro variables, totals, velocity residual (reading r14).
+    # ---------------------------------------------------------------------------------------
+    def macro(self, f):
+        rho, jx, jy = moments(f)
+        return rho, jx / rho, jy / rho, rho * CS2
+
+    def totals(self, f):
+        rho, jx, jy = moments(f)
+        A = self.g.area
+        return np.array([np.sum(A * rho), np.sum(A * jx), np.sum(A * jy)])
+
+    @staticmethod
+    def residual(u_old, v_old, u_new, v_new):
+        num = np.sum((u_new - u_old) ** 2 + (v_new - v_old) ** 2)
+        den = np.sum(u_new ** 2 + v_new ** 2)
+        return np.sqrt(num / den)
+
+    # ---------------------------------------------------------------------------------------
+    # Surface functionals (reading r21-r22): force on the wall edges of the selected groups,
+    # pressure (gauge p - p0) plus the viscous wall shear mu (u_c - u_w)_t / d_perp, and the
+    # smooth reattachment-length proxy sum l (1 - tanh(tau_x / eps)) / 2 over one wall group.
+    # ---------------------------------------------------------------------------------------
+    def forces(self, f, group_mask, jr_group=None, jr_xmin=None, eps_tau=None):
+        G, p = self.g, self.p
+        rho, ux, uy, pr = self.macro(f)
+        p0 = p["rho0"] * CS2
+        bh = G.bidx
+        grp = G.bgroup[G.bface[bh]]
+        c = self.b_cell
+        n = self.b_n
+        l = G.l[bh]
+        dperp = G.dperp[bh]
+        mu = rho[c] * p["nu"]
+        rux, ruy = ux[c] - self.b_ux, uy[c] - self.b_uy
+        un = rux * n[:, 0] + ruy * n[:, 1]
+        tx = mu * (rux - un * n[:, 0]) / dperp
+        ty = mu * (ruy - un * n[:, 1]) / dperp
+        fx = l * ((pr[c] - p0) * n[:, 0] + tx)
+        fy = l * ((pr[c] - p0) * n[:, 1] + ty)
+        wall = (self.b_kind == WALL) | (self.b_kind == MOVING_WALL)
+        sel = wall & (((np.uint64(group_mask) >> grp.astype(np.uint64)) & np.uint64(1)) == 1)
+        F = np.array([np.sum(np.where(sel, fx, 0.0)), np.sum(np.where(sel, fy, 0.0))])
+        jr_group = p["jr_group"] if jr_group is None else jr_group
+        jr_xmin = p["jr_xmin"] if jr_xmin is None else jr_xmin
+        eps = p["eps_tau"] if eps_tau is None else eps_tau
+        jsel = wall & (grp == jr_group) & (G.xf[bh, 0] > jr_xmin)
+        JR = np.sum(np.where(jsel, l * 0.5 * (1.0 - np.tanh(tx / eps)), 0.0))
+        return F, JR
