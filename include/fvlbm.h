@@ -1,0 +1,185 @@
+/*
+ * fvlbm.h — C ABI of the MI355X finite-volume lattice Boltzmann library.
+ *
+ * One call of fvlbm_step advances the cell-centred D2Q9 FVLBM on an unstructured 2D mesh by the
+ * three-stage, second-order IMEX Runge-Kutta scheme of arXiv 1812.00394 (Part II), Section 3.1
+ * (Eqs. (semibgk), (advection), (collision), (imexone), (imextwo), (sumimeximplicitnew),
+ * (fnewstage)), optionally coupled with the k-omega SST model of its Section 2 through the
+ * eddy-viscosity relaxation time of Eq. (turbtau), in the order of the algorithm (Steps 0-8) at
+ * the end of its Section 3.2.
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns fvlbm_status; nothing throws across the ABI.  On a non-OK status
+ *     fvlbm_last_error() returns a message (thread-local, valid until the next call on the
+ *     same thread).
+ *   - Host arrays are plain C arrays in the caller's cell order ("user order"); the library
+ *     renumbers cells internally (Morton or RCM) and never exposes that order.
+ *   - Device memory is owned by the caller: fvlbm_state_bytes() says how much, fvlbm_init()
+ *     receives it.  The library itself allocates no device memory.
+ *   - All device work is enqueued on the HIP stream given to fvlbm_init().  Calls that return
+ *     host values synchronise that stream; the others are asynchronous.
+ *   - Distribution functions are indexed by the D2Q9 direction a = 0..8 with lattice
+ *     velocities e_a = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1) and
+ *     weights 4/9, 1/9 (a=1..4), 1/36 (a=5..8); c_s^2 = 1/3.  Arrays of f are [9][n_cells].
+ */
+#ifndef FVLBM_H
+#define FVLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FVLBM_OK = 0,
+    FVLBM_EINVAL = -1,     /* bad argument: sizes, NULL pointers, tau <= 0, too small workspace */
+    FVLBM_EMESH = -2,      /* malformed mesh: non-positive area, edge shared by >2 cells,
+                              boundary edge unmatched / unassigned, periodic edge without partner */
+    FVLBM_ENOMEM = -3,     /* host allocation failed */
+    FVLBM_EDEVICE = -4,    /* a HIP call failed (message names it) */
+    FVLBM_EDIVERGED = -5,  /* a reduction met a non-finite value */
+    FVLBM_ESTATE = -6      /* call not valid for this state (e.g. SST data asked of a laminar state) */
+} fvlbm_status;
+
+/* boundary group kinds */
+enum {
+    FVLBM_WALL = 1,        /* resting no-slip wall */
+    FVLBM_MOVING_WALL = 2, /* no-slip wall moving tangentially with the group velocity */
+    FVLBM_INLET = 3,       /* prescribed velocity (rotated by theta), k, omega */
+    FVLBM_OUTLET = 4,      /* prescribed density; zero-gradient k, omega */
+    FVLBM_FARFIELD = 5,    /* free stream (rho, u rotated by theta, k, omega) */
+    FVLBM_PERIODIC = 6     /* paired with the edges found at midpoint + periodic_shift */
+};
+
+enum { FVLBM_FP64 = 0, FVLBM_FP32_DEV = 1 };                  /* storage / arithmetic of f */
+enum { FVLBM_ORDER_NONE = 0, FVLBM_ORDER_MORTON = 1, FVLBM_ORDER_RCM = 2 };
+
+#define FVLBM_MAX_GROUPS 16
+
+typedef struct fvlbm_mesh fvlbm_mesh;
+typedef struct fvlbm_state fvlbm_state;
+
+/*
+ * Physical and numerical parameters (lattice units).
+ *   nu         molecular kinematic viscosity; the laminar relaxation time is tau = 3 nu
+ *              (Eq. (turbtau) with nu_t = 0)
+ *   dt         time step
+ *   rho0       reference density (outlet default; the FP32 mode stores f - w_a rho0)
+ *   sst        0: laminar, 1: k-omega SST once per step before the three stages
+ *   a1 ... beta2  the SST constants listed in Section 2 (C_omega1/2 are derived from them)
+ *   theta      inflow angle [rad]: rotates every INLET and FARFIELD velocity
+ *   group_*    per boundary group: velocity (u, v), density, k, omega
+ *   bface_vals NULL, or [n_bfaces][5] = (u, v, rho, k, omega) per boundary edge in the order
+ *              given to fvlbm_mesh_create, replacing the group values (inflow profiles)
+ *   jr_group, jr_xmin, eps_tau   the reattachment proxy J_R of fvlbm_forces
+ */
+typedef struct {
+    double nu, dt, rho0;
+    int32_t sst, n_groups;
+    double a1, beta_star, kappa, sigma_k1, sigma_w1, beta1, sigma_k2, sigma_w2, beta2;
+    double theta;
+    double group_u[FVLBM_MAX_GROUPS][2];
+    double group_rho[FVLBM_MAX_GROUPS];
+    double group_k[FVLBM_MAX_GROUPS];
+    double group_w[FVLBM_MAX_GROUPS];
+    const double *bface_vals;
+    int32_t jr_group, reserved;
+    double jr_xmin, eps_tau;
+} fvlbm_params;
+
+/*
+ * Build a mesh from host arrays (copied; the caller keeps ownership of its arrays).
+ *   node_xy       [n_nodes][2]
+ *   cell_ptr      [n_cells+1] CSR offsets into cell_nodes; every cell has 3 or 4 nodes listed
+ *                 counter-clockwise (positive shoelace area)
+ *   bface_nodes   [n_bfaces][2] node pairs of the boundary edges (any orientation)
+ *   bface_group   [n_bfaces] group id in [0, n_groups)
+ *   group_kind    [n_groups] FVLBM_WALL ... FVLBM_PERIODIC
+ *   periodic_shift [n_groups][2] or NULL: translation taking a periodic group's edges onto their
+ *                 partner edges
+ *   order         internal renumbering (FVLBM_ORDER_*)
+ * Computes, in FP64 on the host: cell areas and centroids, edge normals and midpoints, the
+ * weighted least-squares gradient coefficients, the wall distance (exact nearest point on the
+ * WALL / MOVING_WALL edges) and the renumbering.  Errors: FVLBM_EINVAL, FVLBM_EMESH.
+ */
+fvlbm_status fvlbm_mesh_create(int64_t n_nodes, const double *node_xy,
+                               int64_t n_cells, const int64_t *cell_ptr, const int64_t *cell_nodes,
+                               int64_t n_bfaces, const int64_t *bface_nodes, const int32_t *bface_group,
+                               int32_t n_groups, const int32_t *group_kind, const double *periodic_shift,
+                               int32_t order, fvlbm_mesh **out);
+void fvlbm_mesh_destroy(fvlbm_mesh *mesh);
+
+/* counts[0..3] = cells, interior edges, boundary edges (periodic ones counted as interior),
+ * maximum edges per cell. */
+fvlbm_status fvlbm_mesh_counts(const fvlbm_mesh *mesh, int64_t counts[4]);
+
+/* Host copies of the mesh's FP64 geometry in user order; any pointer may be NULL.
+ * area [n], centroid [n][2], wall_dist [n] (1e30 where the mesh has no wall). */
+fvlbm_status fvlbm_mesh_geometry(const fvlbm_mesh *mesh, double *area, double *centroid, double *wall_dist);
+
+/* Internal renumbering: perm[i] = user index of internal cell i. */
+fvlbm_status fvlbm_mesh_permutation(const fvlbm_mesh *mesh, int64_t *perm);
+
+/* Device bytes fvlbm_init needs for this mesh, precision and SST switch. */
+fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *mesh, int32_t precision, int32_t sst, size_t *bytes);
+
+/*
+ * Step 0 of the algorithm: set f = f_eq(rho, u) per cell (and k, omega when params->sst).
+ *   rho [n], u [n][2], k [n], omega [n]: host arrays in user order (k, omega ignored if !sst)
+ *   workspace: device memory of at least fvlbm_state_bytes() bytes, 256-byte aligned, owned by
+ *              the caller and alive until fvlbm_state_destroy.
+ *   hip_stream: the hipStream_t all work of this state is enqueued on (NULL = default stream).
+ * The mesh must outlive the state.  Errors: FVLBM_EINVAL, FVLBM_EDEVICE.
+ */
+fvlbm_status fvlbm_init(const fvlbm_mesh *mesh, const fvlbm_params *params, int32_t precision,
+                        const double *rho, const double *u, const double *k, const double *omega,
+                        void *workspace, size_t ws_bytes, void *hip_stream, fvlbm_state **out);
+
+/* Replace the state: f [9][n] (FP64, user order, host), and k, omega [n] when SST is on
+ * (may be NULL to keep the current ones).  Synchronises the stream. */
+fvlbm_status fvlbm_set_state(fvlbm_state *st, const double *f, const double *k, const double *omega);
+
+/*
+ * Advance n_steps IMEX steps (Steps 1-7 each).  If residual != NULL, the velocity residual
+ * ||u^{n+1} - u^n||_2 / ||u^{n+1}||_2 of the last step is computed in FP64 and returned (this
+ * synchronises); a non-finite residual returns FVLBM_EDIVERGED.
+ */
+fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *residual);
+
+/*
+ * Macro fields (Step 7) in FP64, user order.  on_device = 0: host pointers (synchronises);
+ * 1: device pointers (asynchronous).  Any field pointer may be NULL.  rho [n], u [n][2],
+ * k, omega, nu_t [n] (FVLBM_ESTATE if asked of a laminar state).  totals (host, may be NULL):
+ * sum A rho, sum A rho u_x, sum A rho u_y in FP64 (synchronises; FVLBM_EDIVERGED if non-finite).
+ */
+fvlbm_status fvlbm_moments(fvlbm_state *st, int32_t on_device, double *rho, double *u, double *k,
+                           double *omega, double *nu_t, double totals[3]);
+
+/* f [9][n] in FP64, user order (for FP32 storage: w_a rho0 added back). */
+fvlbm_status fvlbm_get_f(fvlbm_state *st, int32_t on_device, double *f);
+
+/*
+ * Surface functionals in FP64 (host results; synchronises).  force[2]: the force of the fluid
+ * on the WALL / MOVING_WALL edges of the groups whose bit is set in wall_group_mask, gauge
+ * pressure (p - rho0/3) n l plus the wall shear mu (u_c - u_w)_t / d_perp l with mu = rho_c nu.
+ * j_r (may be NULL): sum over the walls of group params->jr_group with x_f > jr_xmin of
+ * l (1 - tanh(tau_x / eps_tau)) / 2 (smooth reversed-flow length).
+ */
+fvlbm_status fvlbm_forces(fvlbm_state *st, uint64_t wall_group_mask, double force[2], double *j_r);
+
+/*
+ * Diagnostic: the convection term Gamma^a of Eq. (advection) of an arbitrary field g, with the
+ * boundary treatment of fvlbm_step.  g_in, out: host [9][n] FP64 user order.  Synchronises.
+ */
+fvlbm_status fvlbm_apply_advection(fvlbm_state *st, const double *g_in, double *out);
+
+void fvlbm_state_destroy(fvlbm_state *st);
+
+const char *fvlbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVLBM_H */

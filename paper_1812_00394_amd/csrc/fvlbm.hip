@@ -1,0 +1,604 @@
+// C ABI of the FVLBM library: state layout in the caller's workspace, the step driver and the
+// import / export / reduction entry points.  See include/fvlbm.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "kernels.h"
+
+namespace fvlbm {
+
+fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const int64_t *cell_ptr,
+                       const int64_t *cell_nodes, int64_t n_bf, const int64_t *bf_nodes, const int32_t *bf_group,
+                       int32_t n_groups, const int32_t *group_kind, const double *pshift, int32_t order);
+
+namespace {
+thread_local std::string g_last_error;
+
+void check(hipError_t e, const char *what) {
+    if (e != hipSuccess) throw Error(FVLBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr int kBlock = 256;
+constexpr int kRedBlocks = 512;   // fixed reduction grid (deterministic sums)
+
+inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
+
+// Carves the caller's workspace: every array 256-byte aligned.
+struct Carver {
+    size_t off = 0;
+    char *base = nullptr;
+    template <typename P>
+    P *take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        P *p = base ? reinterpret_cast<P *>(base + off) : nullptr;
+        off += count * sizeof(P);
+        return p;
+    }
+};
+
+}  // namespace
+
+void set_last_error(const std::string &msg) { g_last_error = msg; }
+
+}  // namespace fvlbm
+
+using namespace fvlbm;
+
+struct fvlbm_state {
+    const fvlbm_mesh *mesh = nullptr;
+    int precision = FVLBM_FP64;
+    int sst = 0;
+    fvlbm_params par{};
+    hipStream_t stream = nullptr;
+    Geo geo{};
+    int32_t *bzg = nullptr;
+    void *F = nullptr, *X = nullptr, *Y = nullptr, *A = nullptr, *G = nullptr;
+    void *M[2] = {nullptr, nullptr};
+    void *K[2] = {nullptr, nullptr}, *W[2] = {nullptr, nullptr};
+    void *tau = nullptr, *nut = nullptr, *aux = nullptr;
+    int cur_m = 0, cur_kw = 0;
+    double *scratch = nullptr;   // 9 n doubles (staging of user-order FP64 arrays)
+    double *partial = nullptr;   // kRedBlocks * 4
+    double *result = nullptr;    // 4
+    int64_t steps_done = 0;
+};
+
+namespace {
+
+// Layout of the workspace.  Geometry arrays are written by fvlbm_init; the rest is state.
+template <typename T>
+void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
+    const size_t n = (size_t)m->n, nb = m->b_cell.size(), S = kSlots * n;
+    Geo &g = st->geo;
+    g.n = (int32_t)n;
+    g.nb = (int32_t)nb;
+    g.nbr = cv.take<int32_t>(S);
+    g.nlx = cv.take<double>(S);
+    g.nly = cv.take<double>(S);
+    g.rfx = cv.take<double>(S);
+    g.rfy = cv.take<double>(S);
+    g.dx = cv.take<double>(S);
+    g.dy = cv.take<double>(S);
+    g.cx = cv.take<double>(S);
+    g.cy = cv.take<double>(S);
+    g.area = cv.take<double>(n);
+    g.inv_area = cv.take<double>(n);
+    g.wdist = cv.take<double>(n);
+    g.perm = cv.take<int32_t>(n);
+    g.b_kind = cv.take<int32_t>(nb);
+    g.b_cell = cv.take<int32_t>(nb);
+    g.b_group = cv.take<int32_t>(nb);
+    st->bzg = cv.take<int32_t>(nb);
+    g.b_nx = cv.take<double>(nb);
+    g.b_ny = cv.take<double>(nb);
+    g.b_l = cv.take<double>(nb);
+    g.b_dperp = cv.take<double>(nb);
+    g.b_xfx = cv.take<double>(nb);
+    g.b_ux = cv.take<double>(nb);
+    g.b_uy = cv.take<double>(nb);
+    g.b_rho = cv.take<double>(nb);
+    g.b_drho = cv.take<double>(nb);
+    g.b_k = cv.take<double>(nb);
+    g.b_w = cv.take<double>(nb);
+    st->F = cv.take<T>(9 * n);
+    st->X = cv.take<T>(9 * n);
+    st->Y = cv.take<T>(9 * n);
+    st->A = cv.take<T>(9 * n);
+    st->G = cv.take<T>(16 * n);
+    st->M[0] = cv.take<T>(3 * n);
+    st->M[1] = cv.take<T>(3 * n);
+    st->tau = cv.take<T>(n);
+    st->nut = cv.take<T>(n);
+    if (sst) {
+        st->K[0] = cv.take<T>(n);
+        st->K[1] = cv.take<T>(n);
+        st->W[0] = cv.take<T>(n);
+        st->W[1] = cv.take<T>(n);
+        st->aux = cv.take<T>(10 * n);
+    }
+    st->scratch = cv.take<double>(9 * n);
+    st->partial = cv.take<double>((size_t)kRedBlocks * 4);
+    st->result = cv.take<double>(4);
+}
+
+size_t layout_bytes(const fvlbm_mesh *m, int precision, int sst) {
+    Carver cv;
+    fvlbm_state tmp;
+    if (precision == FVLBM_FP64)
+        carve<double>(cv, m, sst, &tmp);
+    else
+        carve<float>(cv, m, sst, &tmp);
+    return cv.off + 256;
+}
+
+template <typename T>
+StepPar<T> step_par(const fvlbm_params &p) {
+    StepPar<T> s;
+    s.rho0 = T(p.rho0);
+    s.dt = T(p.dt);
+    s.nu = T(p.nu);
+    s.a1 = T(p.a1);
+    s.bstar = T(p.beta_star);
+    s.sk1 = T(p.sigma_k1);
+    s.sk2 = T(p.sigma_k2);
+    s.sw1 = T(p.sigma_w1);
+    s.sw2 = T(p.sigma_w2);
+    s.b1 = T(p.beta1);
+    s.b2 = T(p.beta2);
+    // C_omega_i = beta_i / beta* - sigma_omega_i kappa^2 / sqrt(beta*)
+    s.cw1 = T(p.beta1 / p.beta_star - p.sigma_w1 * p.kappa * p.kappa / std::sqrt(p.beta_star));
+    s.cw2 = T(p.beta2 / p.beta_star - p.sigma_w2 * p.kappa * p.kappa / std::sqrt(p.beta_star));
+    return s;
+}
+
+template <typename P>
+void h2d(P *dst, const std::vector<P> &src, hipStream_t s) {
+    if (!src.empty()) check(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(P), hipMemcpyHostToDevice, s), "hipMemcpyAsync H2D");
+}
+
+void upload_scratch(fvlbm_state *st, const double *host, size_t count) {
+    check(hipMemcpyAsync(st->scratch, host, count * sizeof(double), hipMemcpyHostToDevice, st->stream), "hipMemcpyAsync H2D");
+}
+
+// Boundary values from the parameters: velocity rotated by theta for inlets / far field, zero on
+// resting walls; k = 0 and omega = 60 nu / (beta1 d_perp^2) on walls; zero-gradient flag on outlets
+// and far-field outflow edges.
+void boundary_values(const fvlbm_mesh *m, const fvlbm_params &p, std::vector<double> v[6], std::vector<int32_t> &zg) {
+    const size_t nb = m->b_cell.size();
+    for (int i = 0; i < 6; ++i) v[i].assign(nb, 0.0);
+    zg.assign(nb, 0);
+    const double c = std::cos(p.theta), s = std::sin(p.theta);
+    for (size_t b = 0; b < nb; ++b) {
+        const int g = m->b_group[b], kind = m->b_kind[b];
+        double ux = p.group_u[g][0], uy = p.group_u[g][1], rho = p.group_rho[g], k = p.group_k[g], w = p.group_w[g];
+        if (p.bface_vals) {
+            const double *q = p.bface_vals + 5 * m->b_user[b];
+            ux = q[0];
+            uy = q[1];
+            rho = q[2];
+            k = q[3];
+            w = q[4];
+        }
+        if (kind == FVLBM_INLET || kind == FVLBM_FARFIELD) {
+            const double rx = c * ux - s * uy, ry = s * ux + c * uy;
+            ux = rx;
+            uy = ry;
+        }
+        if (kind == FVLBM_WALL) ux = uy = 0.0;
+        if (kind == FVLBM_WALL || kind == FVLBM_MOVING_WALL) {
+            k = 0.0;
+            const double dp = m->b_dperp[b];
+            w = 60.0 * p.nu / (p.beta1 * dp * dp);
+        }
+        if (kind == FVLBM_OUTLET) zg[b] = 1;
+        if (kind == FVLBM_FARFIELD && !(ux * m->b_nx[b] + uy * m->b_ny[b] < 0)) zg[b] = 1;
+        v[0][b] = ux;
+        v[1][b] = uy;
+        v[2][b] = rho;
+        v[3][b] = rho - p.rho0;
+        v[4][b] = k;
+        v[5][b] = w;
+    }
+}
+
+template <typename T>
+void upload_geometry(fvlbm_state *st) {
+    const fvlbm_mesh *m = st->mesh;
+    hipStream_t s = st->stream;
+    Geo &g = st->geo;
+    h2d(const_cast<int32_t *>(g.nbr), m->nbr, s);
+    h2d(const_cast<double *>(g.nlx), m->nlx, s);
+    h2d(const_cast<double *>(g.nly), m->nly, s);
+    h2d(const_cast<double *>(g.rfx), m->rfx, s);
+    h2d(const_cast<double *>(g.rfy), m->rfy, s);
+    h2d(const_cast<double *>(g.dx), m->dx, s);
+    h2d(const_cast<double *>(g.dy), m->dy, s);
+    h2d(const_cast<double *>(g.cx), m->cx, s);
+    h2d(const_cast<double *>(g.cy), m->cy, s);
+    h2d(const_cast<double *>(g.area), m->area, s);
+    std::vector<double> ia(m->n);
+    for (int64_t i = 0; i < m->n; ++i) ia[i] = 1.0 / m->area[i];
+    h2d(const_cast<double *>(g.inv_area), ia, s);
+    h2d(const_cast<double *>(g.wdist), m->wdist, s);
+    std::vector<int32_t> perm(m->n);
+    for (int64_t i = 0; i < m->n; ++i) perm[i] = (int32_t)m->perm[i];
+    h2d(const_cast<int32_t *>(g.perm), perm, s);
+    h2d(const_cast<int32_t *>(g.b_kind), m->b_kind, s);
+    h2d(const_cast<int32_t *>(g.b_cell), m->b_cell, s);
+    h2d(const_cast<int32_t *>(g.b_group), m->b_group, s);
+    h2d(const_cast<double *>(g.b_nx), m->b_nx, s);
+    h2d(const_cast<double *>(g.b_ny), m->b_ny, s);
+    h2d(const_cast<double *>(g.b_l), m->b_l, s);
+    h2d(const_cast<double *>(g.b_dperp), m->b_dperp, s);
+    h2d(const_cast<double *>(g.b_xfx), m->b_xfx, s);
+    std::vector<double> bv[6];
+    std::vector<int32_t> zg;
+    boundary_values(m, st->par, bv, zg);
+    h2d(const_cast<double *>(g.b_ux), bv[0], s);
+    h2d(const_cast<double *>(g.b_uy), bv[1], s);
+    h2d(const_cast<double *>(g.b_rho), bv[2], s);
+    h2d(const_cast<double *>(g.b_drho), bv[3], s);
+    h2d(const_cast<double *>(g.b_k), bv[4], s);
+    h2d(const_cast<double *>(g.b_w), bv[5], s);
+    h2d(st->bzg, zg, s);
+    // host staging vectors must stay alive until the copies ran
+    check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+template <typename T>
+void launch_step(fvlbm_state *st) {
+    const Geo &g = st->geo;
+    const int n = g.n;
+    const int nbk = blocks_for(n);
+    hipStream_t s = st->stream;
+    StepPar<T> p = step_par<T>(st->par);
+    T *F = (T *)st->F, *X = (T *)st->X, *Y = (T *)st->Y, *A = (T *)st->A, *G = (T *)st->G;
+    T *Mcur = (T *)st->M[st->cur_m], *Mnew = (T *)st->M[st->cur_m ^ 1];
+    T *tau = (T *)st->tau;
+    if (st->sst) {
+        T *K0 = (T *)st->K[st->cur_kw], *W0 = (T *)st->W[st->cur_kw];
+        T *K1 = (T *)st->K[st->cur_kw ^ 1], *W1 = (T *)st->W[st->cur_kw ^ 1];
+        k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, p);
+        k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, K1, W1, tau, (T *)st->nut, p);
+        st->cur_kw ^= 1;
+    }
+    k_collide1<T><<<nbk, kBlock, 0, s>>>(n, F, tau, X, p);
+    k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0);
+    k_sweep1<T><<<nbk, kBlock, 0, s>>>(g, F, X, G, tau, Y, A, p);
+    k_grad<T><<<nbk, kBlock, 0, s>>>(g, Y, G, p.rho0);
+    k_sweep2<T><<<nbk, kBlock, 0, s>>>(g, F, Y, G, tau, X, A, p);
+    k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0);
+    k_sweep3<T><<<nbk, kBlock, 0, s>>>(g, X, G, A, F, Mnew, p);
+    st->cur_m ^= 1;
+    check(hipGetLastError(), "kernel launch");
+}
+
+template <typename T>
+double residual(fvlbm_state *st) {
+    const int n = st->geo.n;
+    k_residual<T><<<kRedBlocks, kBlock, 0, st->stream>>>(n, (T *)st->M[st->cur_m], (T *)st->M[st->cur_m ^ 1], st->partial);
+    k_finish<2><<<1, kBlock, 0, st->stream>>>(st->partial, kRedBlocks, st->result);
+    double r[2];
+    check(hipMemcpyAsync(r, st->result, sizeof(r), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+    return std::sqrt(r[0] / r[1]);
+}
+
+template <typename T>
+void import_state(fvlbm_state *st, const double *f, const double *k, const double *w) {
+    const Geo &g = st->geo;
+    const int nbk = blocks_for(g.n);
+    if (f) {
+        upload_scratch(st, f, 9 * (size_t)g.n);
+        k_import_f<T><<<nbk, kBlock, 0, st->stream>>>(g, st->scratch, (T *)st->F, st->par.rho0);
+    }
+    k_macro<T><<<nbk, kBlock, 0, st->stream>>>(g.n, (T *)st->F, (T *)st->M[st->cur_m], T(st->par.rho0));
+    if (st->sst) {
+        if (k) {
+            check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+            upload_scratch(st, k, g.n);
+            k_import_scalar<T><<<nbk, kBlock, 0, st->stream>>>(g, st->scratch, (T *)st->K[st->cur_kw]);
+        }
+        if (w) {
+            check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+            upload_scratch(st, w, g.n);
+            k_import_scalar<T><<<nbk, kBlock, 0, st->stream>>>(g, st->scratch, (T *)st->W[st->cur_kw]);
+        }
+    }
+    check(hipGetLastError(), "kernel launch");
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+}
+
+template <typename T>
+void do_init(fvlbm_state *st, const double *rho, const double *u, const double *k, const double *w) {
+    upload_geometry<T>(st);
+    const Geo &g = st->geo;
+    const int n = g.n, nbk = blocks_for(n);
+    // rho and u staged in the scratch area: rho [n] then u [n][2]
+    check(hipMemcpyAsync(st->scratch, rho, n * sizeof(double), hipMemcpyHostToDevice, st->stream), "hipMemcpyAsync H2D");
+    check(hipMemcpyAsync(st->scratch + n, u, 2 * (size_t)n * sizeof(double), hipMemcpyHostToDevice, st->stream), "hipMemcpyAsync H2D");
+    k_init_feq<T><<<nbk, kBlock, 0, st->stream>>>(g, st->scratch, st->scratch + n, (T *)st->F, st->par.rho0);
+    k_fill<T><<<nbk, kBlock, 0, st->stream>>>(n, (T *)st->tau, T(3.0 * st->par.nu));
+    k_fill<T><<<nbk, kBlock, 0, st->stream>>>(n, (T *)st->nut, T(0));
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+    import_state<T>(st, nullptr, k, w);
+    // the residual of a first step compares with the initial velocity
+    check(hipMemcpyAsync(st->M[st->cur_m ^ 1], st->M[st->cur_m], 3 * (size_t)n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+}
+
+template <typename T>
+void export_moments(fvlbm_state *st, int on_device, double *rho, double *u, double *k, double *w, double *nut) {
+    const Geo &g = st->geo;
+    const int n = g.n, nbk = blocks_for(n);
+    hipStream_t s = st->stream;
+    const T *M = (const T *)st->M[st->cur_m];
+    auto run = [&](double *dst, size_t count, auto launch) {
+        if (!dst) return;
+        double *target = on_device ? dst : st->scratch;
+        launch(target);
+        if (!on_device) {
+            check(hipMemcpyAsync(dst, st->scratch, count * sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+            check(hipStreamSynchronize(s), "hipStreamSynchronize");
+        }
+    };
+    run(rho, n, [&](double *t) { k_export_scalar<T><<<nbk, kBlock, 0, s>>>(g, M, st->par.rho0, t); });
+    run(u, 2 * (size_t)n, [&](double *t) { k_export_vel<T><<<nbk, kBlock, 0, s>>>(g, M, t); });
+    run(k, n, [&](double *t) { k_export_scalar<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->K[st->cur_kw], 0.0, t); });
+    run(w, n, [&](double *t) { k_export_scalar<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->W[st->cur_kw], 0.0, t); });
+    run(nut, n, [&](double *t) { k_export_scalar<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->nut, 0.0, t); });
+    check(hipGetLastError(), "kernel launch");
+}
+
+template <typename T>
+void totals(fvlbm_state *st, double out[3]) {
+    k_totals<T><<<kRedBlocks, kBlock, 0, st->stream>>>(st->geo, (const T *)st->M[st->cur_m], st->par.rho0, st->partial);
+    k_finish<3><<<1, kBlock, 0, st->stream>>>(st->partial, kRedBlocks, st->result);
+    check(hipMemcpyAsync(out, st->result, 3 * sizeof(double), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+}
+
+template <typename T>
+void forces(fvlbm_state *st, uint64_t mask, double out[3]) {
+    k_forces<T><<<kRedBlocks, kBlock, 0, st->stream>>>(st->geo, (const T *)st->M[st->cur_m], st->par.rho0, st->par.nu,
+                                                         (unsigned long long)mask, st->par.jr_group, st->par.jr_xmin,
+                                                         st->par.eps_tau, st->partial);
+    k_finish<3><<<1, kBlock, 0, st->stream>>>(st->partial, kRedBlocks, st->result);
+    check(hipMemcpyAsync(out, st->result, 3 * sizeof(double), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+}
+
+template <typename T>
+void apply_advection(fvlbm_state *st, const double *gin, double *out) {
+    const Geo &g = st->geo;
+    const int n = g.n, nbk = blocks_for(n);
+    hipStream_t s = st->stream;
+    upload_scratch(st, gin, 9 * (size_t)n);
+    k_import_f<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, (T *)st->X, st->par.rho0);
+    k_grad<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (T *)st->G, T(st->par.rho0));
+    k_advect<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->G, (T *)st->Y, T(st->par.rho0));
+    // Gamma^a is exported without the w_a rho0 shift
+    k_export_f<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->Y, st->scratch, 0.0);
+    check(hipGetLastError(), "kernel launch");
+    check(hipMemcpyAsync(out, st->scratch, 9 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+template <typename F>
+fvlbm_status guarded(F &&fn) {
+    try {
+        fn();
+        return FVLBM_OK;
+    } catch (const Error &e) {
+        set_last_error(e.what());
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_last_error("host allocation failed");
+        return FVLBM_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(e.what());
+        return FVLBM_EINVAL;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+fvlbm_status fvlbm_mesh_create(int64_t n_nodes, const double *node_xy, int64_t n_cells, const int64_t *cell_ptr,
+                               const int64_t *cell_nodes, int64_t n_bfaces, const int64_t *bface_nodes,
+                               const int32_t *bface_group, int32_t n_groups, const int32_t *group_kind,
+                               const double *periodic_shift, int32_t order, fvlbm_mesh **out) {
+    return guarded([&] {
+        if (!out) throw Error(FVLBM_EINVAL, "mesh_create: out is NULL");
+        *out = nullptr;
+        *out = build_mesh(n_nodes, node_xy, n_cells, cell_ptr, cell_nodes, n_bfaces, bface_nodes, bface_group,
+                          n_groups, group_kind, periodic_shift, order);
+    });
+}
+
+void fvlbm_mesh_destroy(fvlbm_mesh *mesh) { delete mesh; }
+
+fvlbm_status fvlbm_mesh_counts(const fvlbm_mesh *m, int64_t counts[4]) {
+    return guarded([&] {
+        if (!m || !counts) throw Error(FVLBM_EINVAL, "mesh_counts: NULL argument");
+        counts[0] = m->n;
+        counts[1] = m->n_interior_edges;
+        counts[2] = m->n_boundary_edges;
+        counts[3] = m->max_faces;
+    });
+}
+
+fvlbm_status fvlbm_mesh_geometry(const fvlbm_mesh *m, double *area, double *centroid, double *wall_dist) {
+    return guarded([&] {
+        if (!m) throw Error(FVLBM_EINVAL, "mesh_geometry: NULL mesh");
+        for (int64_t i = 0; i < m->n; ++i) {
+            const int64_t u = m->perm[i];
+            if (area) area[u] = m->area[i];
+            if (centroid) {
+                centroid[2 * u] = m->xc[i];
+                centroid[2 * u + 1] = m->yc[i];
+            }
+            if (wall_dist) wall_dist[u] = m->wdist[i];
+        }
+    });
+}
+
+fvlbm_status fvlbm_mesh_permutation(const fvlbm_mesh *m, int64_t *perm) {
+    return guarded([&] {
+        if (!m || !perm) throw Error(FVLBM_EINVAL, "mesh_permutation: NULL argument");
+        std::memcpy(perm, m->perm.data(), m->n * sizeof(int64_t));
+    });
+}
+
+fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *m, int32_t precision, int32_t sst, size_t *bytes) {
+    return guarded([&] {
+        if (!m || !bytes) throw Error(FVLBM_EINVAL, "state_bytes: NULL argument");
+        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV) throw Error(FVLBM_EINVAL, "state_bytes: bad precision");
+        *bytes = layout_bytes(m, precision, sst ? 1 : 0);
+    });
+}
+
+fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t precision, const double *rho,
+                        const double *u, const double *k, const double *omega, void *workspace, size_t ws_bytes,
+                        void *hip_stream, fvlbm_state **out) {
+    return guarded([&] {
+        if (!out) throw Error(FVLBM_EINVAL, "init: out is NULL");
+        *out = nullptr;
+        if (!m || !p || !rho || !u || !workspace) throw Error(FVLBM_EINVAL, "init: NULL argument");
+        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV) throw Error(FVLBM_EINVAL, "init: bad precision");
+        if (p->n_groups != m->n_groups) throw Error(FVLBM_EINVAL, "init: params.n_groups differs from the mesh");
+        if (!(p->nu > 0) || !(p->dt > 0) || !(p->rho0 > 0)) throw Error(FVLBM_EINVAL, "init: nu, dt and rho0 must be > 0 (tau = 3 nu)");
+        if (p->sst && (!k || !omega)) throw Error(FVLBM_EINVAL, "init: SST needs k and omega");
+        if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "init: workspace must be 256-byte aligned");
+        const size_t need = layout_bytes(m, precision, p->sst ? 1 : 0);
+        if (ws_bytes < need) throw Error(FVLBM_EINVAL, "init: workspace too small (" + std::to_string(ws_bytes) + " < " + std::to_string(need) + ")");
+        auto st = std::make_unique<fvlbm_state>();
+        st->mesh = m;
+        st->precision = precision;
+        st->sst = p->sst ? 1 : 0;
+        st->par = *p;
+        st->par.bface_vals = nullptr;   // only used here, the caller's array is not kept
+        st->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        Carver cv;
+        cv.base = reinterpret_cast<char *>(workspace);
+        fvlbm_params pv = *p;
+        if (precision == FVLBM_FP64) {
+            carve<double>(cv, m, st->sst, st.get());
+            st->par = pv;
+            do_init<double>(st.get(), rho, u, k, omega);
+        } else {
+            carve<float>(cv, m, st->sst, st.get());
+            st->par = pv;
+            do_init<float>(st.get(), rho, u, k, omega);
+        }
+        st->par.bface_vals = nullptr;
+        *out = st.release();
+    });
+}
+
+fvlbm_status fvlbm_set_state(fvlbm_state *st, const double *f, const double *k, const double *omega) {
+    return guarded([&] {
+        if (!st) throw Error(FVLBM_EINVAL, "set_state: NULL state");
+        if ((k || omega) && !st->sst) throw Error(FVLBM_ESTATE, "set_state: k / omega given to a laminar state");
+        if (st->precision == FVLBM_FP64)
+            import_state<double>(st, f, k, omega);
+        else
+            import_state<float>(st, f, k, omega);
+    });
+}
+
+fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *res) {
+    return guarded([&] {
+        if (!st) throw Error(FVLBM_EINVAL, "step: NULL state");
+        if (n_steps < 0) throw Error(FVLBM_EINVAL, "step: n_steps < 0");
+        for (int32_t i = 0; i < n_steps; ++i) {
+            if (st->precision == FVLBM_FP64)
+                launch_step<double>(st);
+            else
+                launch_step<float>(st);
+        }
+        st->steps_done += n_steps;
+        if (res) {
+            const double r = st->precision == FVLBM_FP64 ? residual<double>(st) : residual<float>(st);
+            *res = r;
+            if (!std::isfinite(r)) throw Error(FVLBM_EDIVERGED, "step: non-finite velocity residual");
+        }
+    });
+}
+
+fvlbm_status fvlbm_moments(fvlbm_state *st, int32_t on_device, double *rho, double *u, double *k, double *omega,
+                           double *nu_t, double tot[3]) {
+    return guarded([&] {
+        if (!st) throw Error(FVLBM_EINVAL, "moments: NULL state");
+        if ((k || omega || nu_t) && !st->sst) throw Error(FVLBM_ESTATE, "moments: k / omega / nu_t of a laminar state");
+        if (st->precision == FVLBM_FP64)
+            export_moments<double>(st, on_device, rho, u, k, omega, nu_t);
+        else
+            export_moments<float>(st, on_device, rho, u, k, omega, nu_t);
+        if (tot) {
+            if (st->precision == FVLBM_FP64)
+                totals<double>(st, tot);
+            else
+                totals<float>(st, tot);
+            for (int i = 0; i < 3; ++i)
+                if (!std::isfinite(tot[i])) throw Error(FVLBM_EDIVERGED, "moments: non-finite totals");
+        }
+    });
+}
+
+fvlbm_status fvlbm_get_f(fvlbm_state *st, int32_t on_device, double *f) {
+    return guarded([&] {
+        if (!st || !f) throw Error(FVLBM_EINVAL, "get_f: NULL argument");
+        const Geo &g = st->geo;
+        const int nbk = blocks_for(g.n);
+        double *target = on_device ? f : st->scratch;
+        if (st->precision == FVLBM_FP64)
+            k_export_f<double><<<nbk, kBlock, 0, st->stream>>>(g, (const double *)st->F, target, st->par.rho0);
+        else
+            k_export_f<float><<<nbk, kBlock, 0, st->stream>>>(g, (const float *)st->F, target, st->par.rho0);
+        check(hipGetLastError(), "kernel launch");
+        if (!on_device) {
+            check(hipMemcpyAsync(f, st->scratch, 9 * (size_t)g.n * sizeof(double), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
+            check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+        }
+    });
+}
+
+fvlbm_status fvlbm_forces(fvlbm_state *st, uint64_t mask, double force[2], double *j_r) {
+    return guarded([&] {
+        if (!st || !force) throw Error(FVLBM_EINVAL, "forces: NULL argument");
+        double r[3];
+        if (st->precision == FVLBM_FP64)
+            forces<double>(st, mask, r);
+        else
+            forces<float>(st, mask, r);
+        force[0] = r[0];
+        force[1] = r[1];
+        if (j_r) *j_r = r[2];
+        for (int i = 0; i < 3; ++i)
+            if (!std::isfinite(r[i])) throw Error(FVLBM_EDIVERGED, "forces: non-finite result");
+    });
+}
+
+fvlbm_status fvlbm_apply_advection(fvlbm_state *st, const double *g_in, double *out) {
+    return guarded([&] {
+        if (!st || !g_in || !out) throw Error(FVLBM_EINVAL, "apply_advection: NULL argument");
+        if (st->precision == FVLBM_FP64)
+            apply_advection<double>(st, g_in, out);
+        else
+            apply_advection<float>(st, g_in, out);
+    });
+}
+
+void fvlbm_state_destroy(fvlbm_state *st) { delete st; }
+
+const char *fvlbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

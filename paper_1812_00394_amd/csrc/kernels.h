@@ -1,0 +1,588 @@
+// HIP kernels of one IMEX step (gfx950).  One thread per cell; cells are renumbered along a
+// space-filling curve so that neighbour gathers of a wavefront hit a few cache lines.
+//
+// Per step (Section 3.2 algorithm, SST once per step before the stages):
+//   sst_a    LSQ gradients of u, v, k, omega; S, div u, CD, F1, F2, mu_t, blending, sources
+//   sst_b    k / omega face fluxes (2nd-order upwind convection, central diffusion), point-implicit
+//            update, nu_t from the updated k, omega, tau = 3 (nu + nu_t)        [Eq. (turbtau)]
+//   collide1 f^(1) from f^n (stage 1 has no earlier convection term)          [Eq. (fnewstage)]
+//   grad     LSQ gradient of the stage field (16 planes: directions 1..8)
+//   sweep<J> convection term of stage J [Eq. (advection)] fused with the cell-local epilogue:
+//            J=1: f^(2) = solve(f^n + dt/2 Ga1)          (stores Ga1)
+//            J=2: f^(3) = solve(f^n + dt/2 (Ga1+Ga2) + dt/3 (Gc1+Gc2));  Q = f^(3) - dt/6 (Ga1+Ga2)
+//            J=3: f^{n+1} = Q + dt/3 Ga3                    (= Eq. (imextwo), see below)
+// Eq. (imextwo) with n~ = n = 1/3: f^{n+1} = f^n + dt/3 sum Ga + dt/3 sum Gc.  Since the third
+// stage satisfies f^(3) = rhs3 + dt/3 Gc3 and rhs3 = f^n + dt/2 (Ga1+Ga2) + dt/3 (Gc1+Gc2), this is
+// f^{n+1} = f^(3) + dt/3 Ga3 - dt/6 (Ga1 + Ga2): no stored collision terms are needed.
+#pragma once
+
+#include "lattice.h"
+
+namespace fvlbm {
+
+template <typename T>
+struct StepPar {
+    T rho0, dt, nu;
+    T a1, bstar, sk1, sk2, sw1, sw2, b1, b2, cw1, cw2;
+};
+
+// ----------------------------------------------------------------------------------------------
+// Least-squares gradient of the eight moving directions of a stage field.
+// G layout: plane 2(a-1) = d/dx, 2(a-1)+1 = d/dy of direction a, each [n].
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T *__restrict__ G, T rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gc[a] = f[(size_t)a * n + c];
+    T gx[9], gy[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gx[a] = gy[a] = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int nb = g.nbr[(size_t)s * n + c];
+        if (nb == -1) continue;
+        const T cxs = T(g.cx[(size_t)s * n + c]), cys = T(g.cy[(size_t)s * n + c]);
+        if (nb >= 0) {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T d = f[(size_t)a * n + nb] - gc[a];
+                gx[a] += cxs * d;
+                gy[a] += cys * d;
+            }
+        } else {
+            T drho, rho, ux, uy, gb[9];
+            moments(gc, rho0, drho, rho, ux, uy);
+            ghost(g, -2 - nb, g.nlx[(size_t)s * n + c], g.nly[(size_t)s * n + c], gc, drho, rho, ux, uy, gb);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T d = gb[a] - gc[a];
+                gx[a] += cxs * d;
+                gy[a] += cys * d;
+            }
+        }
+    }
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        G[(size_t)(2 * (a - 1)) * n + c] = gx[a];
+        G[(size_t)(2 * (a - 1) + 1) * n + c] = gy[a];
+    }
+}
+
+// Convection term of cell c (Eq. (advection)): -(1/A) sum over edges of (e.n) dl times the face
+// value, the face value being the upwind cell's value extrapolated to the edge midpoint with its
+// LSQ gradient; on walls the ghost state, on open boundaries the ghost state for incoming
+// directions.  gc: the cell's own values; out[0] = 0 (the rest direction does not move).
+template <typename T>
+__device__ __forceinline__ void advect_cell(const Geo &g, const T *__restrict__ f, const T *__restrict__ G, int c,
+                                            T rho0, const T gc[9], T out[9]) {
+    const int n = g.n;
+    T gxc[9], gyc[9], acc[9];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        gxc[a] = G[(size_t)(2 * (a - 1)) * n + c];
+        gyc[a] = G[(size_t)(2 * (a - 1) + 1) * n + c];
+        acc[a] = T(0);
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        const double nlx = g.nlx[si], nly = g.nly[si];
+        const T rx = T(g.rfx[si]), ry = T(g.rfy[si]);
+        if (nb >= 0) {
+            const T qx = T(g.rfx[si] - g.dx[si]), qy = T(g.rfy[si] - g.dy[si]);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const double end = ex(a) * nlx + ey(a) * nly;
+                T val;
+                if (end >= 0)
+                    val = gc[a] + gxc[a] * rx + gyc[a] * ry;
+                else
+                    val = f[(size_t)a * n + nb] + G[(size_t)(2 * (a - 1)) * n + nb] * qx +
+                          G[(size_t)(2 * (a - 1) + 1) * n + nb] * qy;
+                acc[a] += T(end) * val;
+            }
+        } else {
+            const int b = -2 - nb;
+            T drho, rho, ux, uy, gb[9];
+            moments(gc, rho0, drho, rho, ux, uy);
+            ghost(g, b, nlx, nly, gc, drho, rho, ux, uy, gb);
+            const int kind = g.b_kind[b];
+            const bool wall = (kind == kWall || kind == kMovingWall);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const double end = ex(a) * nlx + ey(a) * nly;
+                const T val = (wall || end < 0) ? gb[a] : gc[a] + gxc[a] * rx + gyc[a] * ry;
+                acc[a] += T(end) * val;
+            }
+        }
+    }
+    const T ia = T(g.inv_area[c]);
+    out[0] = T(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) out[a] = -acc[a] * ia;
+}
+
+// f^(1) = stage solve of f^n with a = dt/(4 tau).
+template <typename T>
+__global__ void __launch_bounds__(256) k_collide1(int n, const T *__restrict__ F, const T *__restrict__ tau,
+                                                  T *__restrict__ X, StepPar<T> p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    T fn[9], f1[9], fe[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fn[a] = F[(size_t)a * n + c];
+    stage_collide(fn, p.dt / (T(4) * tau[c]), p.rho0, f1, fe);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) X[(size_t)a * n + c] = f1[a];
+}
+
+// Sweep 1: Ga1 = Gamma^a(f^(1)); f^(2) = solve(f^n + dt/2 Ga1, a = dt/(4 tau)).
+template <typename T>
+__global__ void __launch_bounds__(256) k_sweep1(Geo g, const T *__restrict__ F, const T *__restrict__ X,
+                                                const T *__restrict__ G, const T *__restrict__ tau,
+                                                T *__restrict__ Y, T *__restrict__ A, StepPar<T> p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], ga[9], rhs[9], f2[9], fe[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gc[a] = X[(size_t)a * n + c];
+    advect_cell(g, X, G, c, p.rho0, gc, ga);
+    const T h = p.dt * T(0.5);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) rhs[a] = F[(size_t)a * n + c] + h * ga[a];
+    stage_collide(rhs, p.dt / (T(4) * tau[c]), p.rho0, f2, fe);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        Y[(size_t)a * n + c] = f2[a];
+        A[(size_t)a * n + c] = ga[a];
+    }
+}
+
+// Sweep 2: Ga2 = Gamma^a(f^(2)); Gc1, Gc2 recomputed cell-locally; f^(3) = solve(rhs3, dt/(3 tau));
+// A <- Q = f^(3) - dt/6 (Ga1 + Ga2).
+template <typename T>
+__global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, const T *__restrict__ Y,
+                                                const T *__restrict__ G, const T *__restrict__ tau,
+                                                T *__restrict__ X, T *__restrict__ A, StepPar<T> p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], ga[9], fn[9], f1[9], fe1[9], rhs[9], f3[9], fe[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gc[a] = Y[(size_t)a * n + c];
+    advect_cell(g, Y, G, c, p.rho0, gc, ga);
+    const T tc = tau[c];
+    const T itau = T(1) / tc;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fn[a] = F[(size_t)a * n + c];
+    stage_collide(fn, p.dt / (T(4) * tc), p.rho0, f1, fe1);      // f^(1), f_eq^(1)
+    T drho2, rho2, ux2, uy2;
+    moments(gc, p.rho0, drho2, rho2, ux2, uy2);                  // stage-2 moments
+    const T h2 = p.dt * T(0.5), h3 = p.dt / T(3);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const T a1 = A[(size_t)a * n + c];
+        const T gc1 = (fe1[a] - f1[a]) * itau;
+        const T gc2 = (dfeq(a, drho2, rho2, ux2, uy2) - gc[a]) * itau;
+        rhs[a] = fn[a] + h2 * (a1 + ga[a]) + h3 * (gc1 + gc2);
+        ga[a] += a1;                                               // Ga1 + Ga2
+    }
+    stage_collide(rhs, p.dt / (T(3) * tc), p.rho0, f3, fe);
+    const T h6 = p.dt / T(6);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        X[(size_t)a * n + c] = f3[a];
+        A[(size_t)a * n + c] = f3[a] - h6 * ga[a];
+    }
+}
+
+// Sweep 3: f^{n+1} = Q + dt/3 Gamma^a(f^(3)); macro variables (Step 7): rho - rho0, u.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sweep3(Geo g, const T *__restrict__ X, const T *__restrict__ G,
+                                                const T *__restrict__ A, T *__restrict__ F, T *__restrict__ M,
+                                                StepPar<T> p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], ga[9], fnew[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gc[a] = X[(size_t)a * n + c];
+    advect_cell(g, X, G, c, p.rho0, gc, ga);
+    const T h3 = p.dt / T(3);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        fnew[a] = A[(size_t)a * n + c] + h3 * ga[a];
+        F[(size_t)a * n + c] = fnew[a];
+    }
+    T drho, rho, ux, uy;
+    moments(fnew, p.rho0, drho, rho, ux, uy);
+    M[c] = drho;
+    M[(size_t)n + c] = ux;
+    M[(size_t)2 * n + c] = uy;
+}
+
+// Convection term alone (diagnostic entry point).
+template <typename T>
+__global__ void __launch_bounds__(256) k_advect(Geo g, const T *__restrict__ X, const T *__restrict__ G,
+                                                T *__restrict__ out, T rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], ga[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gc[a] = X[(size_t)a * n + c];
+    advect_cell(g, X, G, c, rho0, gc, ga);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) out[(size_t)a * n + c] = ga[a];
+}
+
+// ----------------------------------------------------------------------------------------------
+// k-omega SST (Section 2 model; finite-volume form Eq. (SSTequint)).
+// aux planes: 0,1 grad k; 2,3 grad omega; 4 Gamma_k; 5 Gamma_omega; 6 dt P / rho;
+//             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S.
+// Boundary data per edge (set at init): b_ux, b_uy velocity (0 on resting walls), b_k (0 on walls),
+// b_w (60 nu / (beta1 d_perp^2) on walls), and b_zg = 1 where k, omega, u are zero-gradient
+// (outlets, far-field outflow edges).
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T tmax(T a, T b) { return a >= b ? a : b; }
+template <typename T>
+__device__ __forceinline__ T tmin(T a, T b) { return a <= b ? a : b; }
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sst_a(Geo g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
+                                               const T *__restrict__ K, const T *__restrict__ W,
+                                               T *__restrict__ aux, StepPar<T> p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int n = g.n;
+    const T rho = p.rho0 + M[c], ux = M[(size_t)n + c], uy = M[(size_t)2 * n + c];
+    const T kc = K[c], wc = W[c];
+    T gu[2] = {0, 0}, gv[2] = {0, 0}, gk[2] = {0, 0}, gw[2] = {0, 0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        const T cxs = T(g.cx[si]), cys = T(g.cy[si]);
+        T du, dv, dk, dw;
+        if (nb >= 0) {
+            du = M[(size_t)n + nb] - ux;
+            dv = M[(size_t)2 * n + nb] - uy;
+            dk = K[nb] - kc;
+            dw = W[nb] - wc;
+        } else {
+            const int b = -2 - nb;
+            if (bzg[b]) {
+                du = dv = dk = dw = T(0);
+            } else {
+                du = T(g.b_ux[b]) - ux;
+                dv = T(g.b_uy[b]) - uy;
+                dk = T(g.b_k[b]) - kc;
+                dw = T(g.b_w[b]) - wc;
+            }
+        }
+        gu[0] += cxs * du; gu[1] += cys * du;
+        gv[0] += cxs * dv; gv[1] += cys * dv;
+        gk[0] += cxs * dk; gk[1] += cys * dk;
+        gw[0] += cxs * dw; gw[1] += cys * dw;
+    }
+    const T d = T(g.wdist[c]);
+    const T s11 = gu[0], s22 = gv[1], s12 = T(0.5) * (gu[1] + gv[0]);
+    const T S2 = T(2) * (s11 * s11 + s22 * s22 + T(2) * s12 * s12);
+    const T S = sqrt(S2);
+    const T div = gu[0] + gv[1];
+    const T gkgw = gk[0] * gw[0] + gk[1] * gw[1];
+    const T CD = tmax(T(2) * rho * p.sw2 / wc * gkgw, T(1e-20));
+    const T sk = sqrt(kc);
+    const T visc = T(500) * p.nu / (wc * d * d);
+    const T arg1 = tmin(tmax(sk / (T(0.09) * wc * d), visc), T(4) * rho * p.sw2 * kc / (CD * d * d));
+    const T a4 = arg1 * arg1 * arg1 * arg1;
+    const T F1 = tanh(a4);
+    const T arg2 = tmax(T(2) * sk / (T(0.09) * wc * d), visc);
+    const T F2 = tanh(arg2 * arg2);
+    const T den = tmax(p.a1 * wc, S * F2);
+    const T mu = rho * p.nu;
+    const T mut = p.a1 * rho * kc / den;
+    const T sig_k = F1 * p.sk1 + (T(1) - F1) * p.sk2;
+    const T sig_w = F1 * p.sw1 + (T(1) - F1) * p.sw2;
+    const T beta = F1 * p.b1 + (T(1) - F1) * p.b2;
+    const T gam = F1 * p.cw1 + (T(1) - F1) * p.cw2;
+    const T twothird = T(2) / T(3);
+    const T P = mut * (S2 - twothird * div * div) - twothird * rho * kc * div;
+    // gamma rho P / mu_t without the 0/0 at k = 0: rho k / mu_t = den / a1
+    const T Pw = gam * rho * (S2 - twothird * div * div) - twothird * gam * rho * (den / p.a1) * div;
+    const T cross = T(2) * (T(1) - F1) * rho * p.sw2 * gkgw / wc;
+    aux[c] = gk[0];
+    aux[(size_t)1 * n + c] = gk[1];
+    aux[(size_t)2 * n + c] = gw[0];
+    aux[(size_t)3 * n + c] = gw[1];
+    aux[(size_t)4 * n + c] = mu + sig_k * mut;
+    aux[(size_t)5 * n + c] = mu + sig_w * mut;
+    aux[(size_t)6 * n + c] = p.dt / rho * P;
+    aux[(size_t)7 * n + c] = p.dt / rho * (Pw + cross);
+    aux[(size_t)8 * n + c] = beta;
+    aux[(size_t)9 * n + c] = S;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
+                                               const T *__restrict__ K, const T *__restrict__ W,
+                                               const T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
+                                               T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int n = g.n;
+    const T rho = p.rho0 + M[c], ux = M[(size_t)n + c], uy = M[(size_t)2 * n + c];
+    const T kc = K[c], wc = W[c];
+    const T gkc[2] = {aux[c], aux[(size_t)n + c]};
+    const T gwc[2] = {aux[(size_t)2 * n + c], aux[(size_t)3 * n + c]};
+    const T Gkc = aux[(size_t)4 * n + c], Gwc = aux[(size_t)5 * n + c];
+    T net_k = 0, net_w = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        const T nlx = T(g.nlx[si]), nly = T(g.nly[si]);
+        const T rx = T(g.rfx[si]), ry = T(g.rfy[si]);
+        const T ks = kc + gkc[0] * rx + gkc[1] * ry;   // own value extrapolated to the edge
+        const T ws = wc + gwc[0] * rx + gwc[1] * ry;
+        if (nb >= 0) {
+            const T rhoN = p.rho0 + M[nb], uxN = M[(size_t)n + nb], uyN = M[(size_t)2 * n + nb];
+            const T mdot = T(0.5) * ((rho * ux + rhoN * uxN) * nlx + (rho * uy + rhoN * uyN) * nly);
+            const T kN = K[nb], wN = W[nb];
+            const T gkN[2] = {aux[nb], aux[(size_t)n + nb]};
+            const T gwN[2] = {aux[(size_t)2 * n + nb], aux[(size_t)3 * n + nb]};
+            T kf, wf;
+            if (mdot >= T(0)) {
+                kf = ks;
+                wf = ws;
+            } else {
+                const T qx = T(g.rfx[si] - g.dx[si]), qy = T(g.rfy[si] - g.dy[si]);
+                kf = kN + gkN[0] * qx + gkN[1] * qy;
+                wf = wN + gwN[0] * qx + gwN[1] * qy;
+            }
+            const T ddx = T(g.dx[si]), ddy = T(g.dy[si]);
+            const T dist = sqrt(ddx * ddx + ddy * ddy);
+            const T hx = ddx / dist, hy = ddy / dist;
+            const T GkN = aux[(size_t)4 * n + nb], GwN = aux[(size_t)5 * n + nb];
+            // face gradient: average gradient with its component along d replaced by the difference quotient
+            T agx = T(0.5) * (gkc[0] + gkN[0]), agy = T(0.5) * (gkc[1] + gkN[1]);
+            T corr = (kN - kc) / dist - (agx * hx + agy * hy);
+            const T dk = T(0.5) * (Gkc + GkN) * ((agx + corr * hx) * nlx + (agy + corr * hy) * nly);
+            agx = T(0.5) * (gwc[0] + gwN[0]);
+            agy = T(0.5) * (gwc[1] + gwN[1]);
+            corr = (wN - wc) / dist - (agx * hx + agy * hy);
+            const T dw = T(0.5) * (Gwc + GwN) * ((agx + corr * hx) * nlx + (agy + corr * hy) * nly);
+            net_k += -mdot * kf + dk;
+            net_w += -mdot * wf + dw;
+        } else {
+            const int b = -2 - nb;
+            const bool zg = bzg[b] != 0;
+            const T ubx = zg ? ux : T(g.b_ux[b]);
+            const T uby = zg ? uy : T(g.b_uy[b]);
+            const T kb = zg ? kc : T(g.b_k[b]);
+            const T wb = zg ? wc : T(g.b_w[b]);
+            const T mdot = rho * (ubx * nlx + uby * nly);
+            const T kf = mdot >= T(0) ? ks : kb;
+            const T wf = mdot >= T(0) ? ws : wb;
+            T dk = 0, dw = 0;
+            if (!zg) {
+                const T f = T(g.b_l[b]) / T(g.b_dperp[b]);
+                dk = Gkc * (kb - kc) * f;
+                dw = Gwc * (wb - wc) * f;
+            }
+            net_k += -mdot * kf + dk;
+            net_w += -mdot * wf + dw;
+        }
+    }
+    const T fac = p.dt * T(g.inv_area[c]) / rho;
+    T k1 = (kc + fac * net_k + aux[(size_t)6 * n + c]) / (T(1) + p.dt * p.bstar * wc);
+    T w1 = (wc + fac * net_w + aux[(size_t)7 * n + c]) / (T(1) + p.dt * aux[(size_t)8 * n + c] * wc);
+    k1 = tmax(k1, T(1e-20));
+    w1 = tmax(w1, T(1e-20));
+    const T d = T(g.wdist[c]);
+    const T S = aux[(size_t)9 * n + c];
+    const T arg2 = tmax(T(2) * sqrt(k1) / (T(0.09) * w1 * d), T(500) * p.nu / (w1 * d * d));
+    const T F2 = tanh(arg2 * arg2);
+    const T nt = p.a1 * k1 / tmax(p.a1 * w1, S * F2);
+    K1[c] = k1;
+    W1[c] = w1;
+    nut[c] = nt;
+    tau[c] = T(3) * (p.nu + nt);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Reductions (FP64, deterministic two-pass: per-block partials in a fixed grid, then one block).
+// ----------------------------------------------------------------------------------------------
+template <int NV>
+__device__ __forceinline__ void block_store(double v[NV], double *partial) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += __shfl_down(v[k], off, 64);
+    __shared__ double sh[NV][4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) sh[k][wid] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partial[(size_t)blockIdx.x * NV + k] = sh[k][0] + sh[k][1] + sh[k][2] + sh[k][3];
+}
+
+template <int NV>
+__global__ void __launch_bounds__(256) k_finish(const double *__restrict__ partial, int nblocks, double *__restrict__ out) {
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += partial[(size_t)b * NV + k];
+    block_store<NV>(v, out);
+}
+
+// sum |u_new - u_old|^2, sum |u_new|^2
+template <typename T>
+__global__ void __launch_bounds__(256) k_residual(int n, const T *__restrict__ Mn, const T *__restrict__ Mo,
+                                                  double *__restrict__ partial) {
+    double v[2] = {0, 0};
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        const double ux = Mn[(size_t)n + c], uy = Mn[(size_t)2 * n + c];
+        const double dx = ux - (double)Mo[(size_t)n + c], dy = uy - (double)Mo[(size_t)2 * n + c];
+        v[0] += dx * dx + dy * dy;
+        v[1] += ux * ux + uy * uy;
+    }
+    block_store<2>(v, partial);
+}
+
+// sum A rho, sum A rho u
+template <typename T>
+__global__ void __launch_bounds__(256) k_totals(Geo g, const T *__restrict__ M, double rho0, double *__restrict__ partial) {
+    double v[3] = {0, 0, 0};
+    const int n = g.n;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        const double rho = rho0 + (double)M[c];
+        const double A = g.area[c];
+        v[0] += A * rho;
+        v[1] += A * rho * (double)M[(size_t)n + c];
+        v[2] += A * rho * (double)M[(size_t)2 * n + c];
+    }
+    block_store<3>(v, partial);
+}
+
+// force on selected wall edges and the smooth reversed-flow length
+template <typename T>
+__global__ void __launch_bounds__(256) k_forces(Geo g, const T *__restrict__ M, double rho0, double nu,
+                                                unsigned long long mask, int jr_group, double jr_xmin, double eps,
+                                                double *__restrict__ partial) {
+    double v[3] = {0, 0, 0};
+    const int n = g.n;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < g.nb; b += gridDim.x * blockDim.x) {
+        const int kind = g.b_kind[b];
+        if (kind != kWall && kind != kMovingWall) continue;
+        const int grp = g.b_group[b];
+        const int c = g.b_cell[b];
+        const double rho = rho0 + (double)M[c];
+        const double rux = (double)M[(size_t)n + c] - g.b_ux[b], ruy = (double)M[(size_t)2 * n + c] - g.b_uy[b];
+        const double nx = g.b_nx[b], ny = g.b_ny[b], l = g.b_l[b], dp = g.b_dperp[b];
+        const double un = rux * nx + ruy * ny;
+        const double mu = rho * nu;
+        const double tx = mu * (rux - un * nx) / dp, ty = mu * (ruy - un * ny) / dp;
+        const double dpres = (rho - rho0) / 3.0;
+        if ((mask >> grp) & 1ull) {
+            v[0] += l * (dpres * nx + tx);
+            v[1] += l * (dpres * ny + ty);
+        }
+        if (grp == jr_group && g.b_xfx[b] > jr_xmin) v[2] += l * 0.5 * (1.0 - tanh(tx / eps));
+    }
+    block_store<3>(v, partial);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Import / export between the caller's FP64 user-order arrays and the internal state.
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_import_f(Geo g, const double *__restrict__ fu, T *__restrict__ F, double rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int u = g.perm[c];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) F[(size_t)a * g.n + c] = T(fu[(size_t)a * g.n + u] - wt<double>(a) * rho0);
+}
+
+template <typename T>
+__global__ void k_export_f(Geo g, const T *__restrict__ F, double *__restrict__ fu, double rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int u = g.perm[c];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) fu[(size_t)a * g.n + u] = (double)F[(size_t)a * g.n + c] + wt<double>(a) * rho0;
+}
+
+// f = f_eq(rho, u) (Step 0), from user-order rho [n], u [n][2]
+template <typename T>
+__global__ void k_init_feq(Geo g, const double *__restrict__ rho_u, const double *__restrict__ vel_u,
+                           T *__restrict__ F, double rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int u = g.perm[c];
+    const double rho = rho_u[u], ux = vel_u[2 * (size_t)u], uy = vel_u[2 * (size_t)u + 1];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) F[(size_t)a * g.n + c] = T(dfeq<double>(a, rho - rho0, rho, ux, uy));
+}
+
+template <typename T>
+__global__ void k_import_scalar(Geo g, const double *__restrict__ su, T *__restrict__ S) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    S[c] = T(su[g.perm[c]]);
+}
+
+template <typename T>
+__global__ void k_export_scalar(Geo g, const T *__restrict__ S, double add, double *__restrict__ su) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    su[g.perm[c]] = (double)S[c] + add;
+}
+
+template <typename T>
+__global__ void k_export_vel(Geo g, const T *__restrict__ M, double *__restrict__ vu) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= g.n) return;
+    const int u = g.perm[c];
+    vu[2 * (size_t)u] = (double)M[(size_t)g.n + c];
+    vu[2 * (size_t)u + 1] = (double)M[(size_t)2 * g.n + c];
+}
+
+// macro variables of the current f (after import / init)
+template <typename T>
+__global__ void k_macro(int n, const T *__restrict__ F, T *__restrict__ M, T rho0) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    T d[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = F[(size_t)a * n + c];
+    T drho, rho, ux, uy;
+    moments(d, rho0, drho, rho, ux, uy);
+    M[c] = drho;
+    M[(size_t)n + c] = ux;
+    M[(size_t)2 * n + c] = uy;
+}
+
+template <typename T>
+__global__ void k_fill(int n, T *__restrict__ x, T v) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n) x[c] = v;
+}
+
+}  // namespace fvlbm

@@ -1,0 +1,109 @@
+// D2Q9 lattice and the device-side building blocks of the FVLBM step.
+//
+// Distribution functions are stored as deviations from the rest state, d_a = f_a - w_a rho0, in
+// the storage type T (double, or float for the FP32-deviation mode); the equilibrium, the ghost
+// states and the stage collision are written for deviations so that the large constant w_a rho0
+// never enters a rounding (the constant cancels exactly in every linear operation of the step).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fvlbm {
+
+// Lattice velocities of Qian's D2Q9 model and their weights (a = 0 rest, 1-4 axes, 5-8 diagonals).
+__host__ __device__ constexpr int ex(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0); }
+__host__ __device__ constexpr int ey(int a) { return (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0); }
+template <typename T>
+__host__ __device__ constexpr T wt(int a) {
+    return a == 0 ? T(4) / T(9) : (a < 5 ? T(1) / T(9) : T(1) / T(36));
+}
+
+// Geometry and boundary data on the device (pointers into the caller's workspace).
+struct Geo {
+    int32_t n;    // cells
+    int32_t nb;   // boundary edges
+    const int32_t *nbr;                                              // [4][n]
+    const double *nlx, *nly, *rfx, *rfy, *dx, *dy, *cx, *cy;         // [4][n]
+    const double *area, *inv_area, *wdist;                           // [n]
+    const int32_t *perm;                                             // [n] internal -> user
+    const int32_t *b_kind, *b_cell;                                  // [nb]
+    const double *b_nx, *b_ny, *b_l, *b_dperp, *b_xfx;               // [nb]
+    const double *b_ux, *b_uy, *b_rho, *b_drho, *b_k, *b_w;          // [nb] boundary values
+    const int32_t *b_group;                                          // [nb]
+};
+
+// Equilibrium deviation f_eq,a(rho, u) - w_a rho0, with drho = rho - rho0 (second-order D2Q9
+// equilibrium w_a rho (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2)).
+template <typename T>
+__device__ __forceinline__ T dfeq(int a, T drho, T rho, T ux, T uy) {
+    T eu = T(ex(a)) * ux + T(ey(a)) * uy;
+    return wt<T>(a) * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * (ux * ux + uy * uy)));
+}
+
+// Density deviation and velocity of a deviation vector (the collision invariants 1, e_x, e_y).
+template <typename T>
+__device__ __forceinline__ void moments(const T d[9], T rho0, T &drho, T &rho, T &ux, T &uy) {
+    T s = 0, jx = 0, jy = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        s += d[a];
+        jx += T(ex(a)) * d[a];
+        jy += T(ey(a)) * d[a];
+    }
+    drho = s;
+    rho = rho0 + s;
+    ux = jx / rho;
+    uy = jy / rho;
+}
+
+// Implicit stage of the IMEX scheme, solved explicitly: the stage moments equal those of rhs
+// (the collision term has zero invariant moments), so f = (rhs + a f_eq) / (1 + a) with
+// a = dt m_JJ / tau.  Also returns the equilibrium used.
+template <typename T>
+__device__ __forceinline__ void stage_collide(const T rhs[9], T a, T rho0, T out[9], T fe[9]) {
+    T drho, rho, ux, uy;
+    moments(rhs, rho0, drho, rho, ux, uy);
+    T inv = T(1) / (T(1) + a);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        fe[q] = dfeq(q, drho, rho, ux, uy);
+        out[q] = (rhs[q] + a * fe[q]) * inv;
+    }
+}
+
+enum : int32_t { kWall = 1, kMovingWall = 2, kInlet = 3, kOutlet = 4, kFarfield = 5 };
+
+// Ghost deviation at the midpoint of boundary edge b of a cell whose state is gc (moments drho,
+// rho, ux, uy), non-equilibrium extrapolation from the cell:
+//   walls: f_eq(rho_c, u_w) + (g_c - f_eq(rho_c, u_c)) for every direction;
+//   inlet / outlet / far field: replaced for incoming directions (e.n < 0) only.
+template <typename T>
+__device__ __forceinline__ void ghost(const Geo &g, int b, double nlx, double nly, const T gc[9], T drho, T rho,
+                                      T ux, T uy, T gb[9]) {
+    const int kind = g.b_kind[b];
+    const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]);
+    const T rb = T(g.b_rho[b]), drb = T(g.b_drho[b]);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const double en = ex(a) * nlx + ey(a) * nly;
+        const T neq = gc[a] - dfeq(a, drho, rho, ux, uy);
+        T v;
+        if (kind == kWall || kind == kMovingWall) {
+            v = dfeq(a, drho, rho, ubx, uby) + neq;
+        } else if (en < 0) {
+            if (kind == kInlet)
+                v = dfeq(a, drho, rho, ubx, uby) + neq;
+            else if (kind == kOutlet)
+                v = dfeq(a, drb, rb, ux, uy) + neq;
+            else
+                v = dfeq(a, drb, rb, ubx, uby);
+        } else {
+            v = gc[a];
+        }
+        gb[a] = v;
+    }
+}
+
+}  // namespace fvlbm

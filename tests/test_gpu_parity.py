@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded meshes.
+
+Tolerances (FP64 path): relative to max |f - w rho0| (the part of f that carries information),
+<= 1e-12 after one step and <= 1e-10 after the full step count; the convection operator alone
+<= 1e-12 relative to its largest value.  These are rounding-order differences: the oracle sums the
+convection over a cell's edges in a different order and applies Eq. (imextwo) literally, while the
+kernels use the algebraically equal f^(3) + dt/3 Ga3 - dt/6 (Ga1 + Ga2) and deviations f - w rho0.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fvlbm_oracle as O
+from paper_1812_00394_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1812_00394_amd import fvlbm
+    fvlbm.lib()
+    return fvlbm
+
+
+def rel(a, b, scale):
+    return np.abs(a - b).max() / scale
+
+
+def dev_scale(f, rho0=1.0):
+    return np.abs(f - O.WT[:, None] * rho0).max()
+
+
+MESHES = {
+    "cavity": (lambda: mg.cavity(n=16, jitter=0.2, seed=31), dict(group_u=[[0, 0], [0.1, 0]])),
+    "periodic": (lambda: mg.rectangle(9, 8, kind="periodic", jitter=0.25, seed=32), dict()),
+    "duct": (lambda: mg.rectangle(10, 7, Lx=1.4, kind="duct", jitter=0.25, seed=33),
+             dict(group_u=[[0.05, 0.01], [0, 0], [0.05, 0.0]], group_rho=[1.0, 1.002, 1.0])),
+    "channel": (lambda: mg.rectangle(12, 6, Lx=2.0, kind="channel", jitter=0.2, seed=34),
+                dict(group_u=[[0.04, 0], [0, 0], [0, 0]], group_rho=[1.0, 0.999, 1.0])),
+    "naca": (lambda: mg.naca_omesh(n_wall=48, n_normal=16, y1=2e-3, radius=6.0),
+             dict(group_u=[[0, 0], [0.05, 0]], theta=0.1)),
+}
+
+
+def _random_state(n, rng, amp=0.02):
+    rho = 1 + 0.01 * rng.standard_normal(n)
+    ux, uy = 0.05 * rng.standard_normal((2, n))
+    f = O.feq(rho, ux, uy) + amp * 1e-2 * O.WT[:, None] * rng.standard_normal((9, n))
+    return f
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_advection_operator_parity(F, name):
+    say("advection", name)
+    make, extra = MESHES[name]
+    m = make()
+    p = O.default_params(nu=1e-3, dt=1e-2, **extra)
+    orc = O.Oracle(m, p)
+    rng = np.random.default_rng(40)
+    g = _random_state(orc.g.n, rng)
+    ref = orc.advection(g)
+    st = F.State(F.Mesh(m), p, precision="fp64")
+    got = st.apply_advection(g)
+    assert rel(got, ref, np.abs(ref).max()) < 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_laminar_step_parity(F, name):
+    say("laminar step", name)
+    make, extra = MESHES[name]
+    m = make()
+    nu = 2e-4
+    p = O.default_params(nu=nu, dt=10 * 3 * nu, **extra)
+    orc = O.Oracle(m, p)
+    rng = np.random.default_rng(41)
+    f = _random_state(orc.g.n, rng)
+    st = F.State(F.Mesh(m), p, precision="fp64")
+    st.set_state(f)
+    fo = f
+    for k, tol in ((1, 1e-12), (4, 1e-11)):
+        for _ in range(k):
+            fo, _, _ = orc.step(fo)
+        st.step(k)
+        got = st.get_f()
+        assert rel(got, fo, dev_scale(fo)) < tol, (k, rel(got, fo, dev_scale(fo)))
+
+
+def _c1_params():
+    nu = 0.1 / 1000
+    return O.default_params(nu=nu, dt=10 * 3 * nu, group_u=[[0, 0], [0.1, 0]])
+
+
+def test_cavity_full_run_parity(F):
+    """Laminar lid-driven cavity, 48x48 jittered triangles (4608 cells), Re 1000, dt = 10 tau,
+    500 steps: f, macro fields, totals and residual against the oracle."""
+    say("cavity 4608 cells, 500 steps, fp64")
+    m = mg.cavity()
+    p = _c1_params()
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    f, _, _ = orc.init_state(np.ones(n), np.zeros(n), np.zeros(n))
+    st = F.State(F.Mesh(m), p, precision="fp64", rho=np.ones(n), u=np.zeros((n, 2)))
+    f_prev = f
+    for _ in range(500):
+        f_prev = f
+        f, _, _ = orc.step(f)
+    res = st.step(500, residual=True)
+    got = st.get_f()
+    assert rel(got, f, dev_scale(f)) < 1e-10
+    mo = st.moments()
+    rho, ux, uy, _ = orc.macro(f)
+    np.testing.assert_allclose(mo["rho"], rho, rtol=1e-12)
+    np.testing.assert_allclose(mo["u"][:, 0], ux, atol=1e-12 * 0.1)
+    np.testing.assert_allclose(mo["totals"], orc.totals(f), rtol=1e-12, atol=1e-15)
+    _, ux0, uy0, _ = orc.macro(f_prev)
+    np.testing.assert_allclose(res, orc.residual(ux0, uy0, ux, uy), rtol=1e-8)
+    # mass is conserved in the closed cavity
+    assert abs(mo["totals"][0] - 1.0) < 1e-13
+
+
+def test_cavity_fp32_deviation_error(F):
+    """FP32-deviation storage against the FP64 oracle on the cavity after 200 steps: the error in
+    velocity stays below 1e-4 of the lid speed (stated gate)."""
+    say("cavity fp32dev 200 steps")
+    m = mg.cavity()
+    p = _c1_params()
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    f, _, _ = orc.init_state(np.ones(n), np.zeros(n), np.zeros(n))
+    f, _, _ = orc.run(f, None, None, 200)
+    st = F.State(F.Mesh(m), p, precision="fp32dev", rho=np.ones(n), u=np.zeros((n, 2)))
+    st.step(200)
+    mo = st.moments()
+    _, ux, uy, _ = orc.macro(f)
+    err = max(np.abs(mo["u"][:, 0] - ux).max(), np.abs(mo["u"][:, 1] - uy).max()) / 0.1
+    print("fp32dev velocity error / U =", err)
+    assert err < 1e-4
+    assert abs(mo["totals"][0] - 1.0) < 1e-6
+
+
+def _sst_case(m, extra, seed):
+    nu = 1e-4
+    p = O.default_params(nu=nu, dt=20 * 3 * nu, sst=True, **extra)
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    rng = np.random.default_rng(seed)
+    x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+    ux = 0.05 * np.tanh(3 * (y - y.mean())) + 0.005 * rng.standard_normal(n)
+    uy = 0.01 * np.sin(2 * x) + 0.005 * rng.standard_normal(n)
+    rho = 1 + 0.002 * rng.standard_normal(n)
+    f = O.feq(rho, ux, uy) + 1e-5 * O.WT[:, None] * rng.standard_normal((9, n))
+    k = 1e-4 * (1 + 0.5 * rng.random(n))
+    w = 0.5 * (1 + 0.5 * rng.random(n))
+    return orc, p, f, k, w
+
+
+SST_MESHES = {
+    "backstep_coarse": (lambda: mg.backstep(core=0.25, dx_core=0.5, y1=1e-2, dx_corner=0.05, wall_layers=3),
+                        dict(group_u=[[0, 0], [0.05, 0], [0, 0]], group_k=[0, 1e-4, 0], group_w=[0, 0.5, 0])),
+    "naca": (lambda: mg.naca_omesh(n_wall=48, n_normal=16, y1=2e-3, radius=6.0),
+             dict(group_u=[[0, 0], [0.05, 0]], group_k=[0, 1e-4], group_w=[0, 0.5], theta=0.15)),
+    "duct": (lambda: mg.rectangle(10, 7, Lx=1.4, kind="duct", jitter=0.25, seed=33),
+             dict(group_u=[[0.05, 0.01], [0, 0], [0.05, 0.0]], group_k=[1e-4, 0, 1e-4], group_w=[0.5, 0, 0.5])),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SST_MESHES))
+def test_sst_step_parity(F, name):
+    say("sst step", name)
+    make, extra = SST_MESHES[name]
+    m = make()
+    orc, p, f, k, w = _sst_case(m, extra, 50)
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k, omega=w)
+    st.set_state(f, k, w)
+    fo, ko, wo = f, k, w
+    for nsteps, tol in ((1, 1e-12), (4, 1e-11)):
+        fo, ko, wo = orc.run(fo, ko, wo, nsteps)
+        st.step(nsteps)
+        got = st.get_f()
+        mo = st.moments()
+        assert rel(got, fo, dev_scale(fo)) < tol, ("f", nsteps, rel(got, fo, dev_scale(fo)))
+        assert rel(mo["k"], ko, np.abs(ko).max()) < tol * 10, ("k", nsteps, rel(mo["k"], ko, np.abs(ko).max()))
+        assert rel(mo["omega"], wo, np.abs(wo).max()) < tol * 10, ("w", nsteps)
+        assert rel(mo["nu_t"], orc.last_nut, np.abs(orc.last_nut).max()) < tol * 10, ("nu_t", nsteps)
+
+
+def test_forces_parity(F):
+    say("forces naca")
+    make, extra = SST_MESHES["naca"]
+    m = make()
+    orc, p, f, k, w = _sst_case(m, dict(extra, jr_group=0, jr_xmin=0.3, eps_tau=1e-6), 51)
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k, omega=w)
+    st.set_state(f, k, w)
+    Fo, JRo = orc.forces(f, 1)
+    Fg, JRg = st.forces(1)
+    np.testing.assert_allclose(Fg, Fo, rtol=1e-11, atol=1e-16)
+    assert abs(JRg - JRo) < 1e-12 * max(1.0, abs(JRo))
