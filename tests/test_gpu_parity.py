@@ -51,6 +51,15 @@ MESHES = {
 }
 
 
+def courant_dt(m, C=0.5):
+    """time step at advective Courant number C: max over cells and directions of
+    (dt / A) sum over edges of max(e.n, 0) dl equals C."""
+    G = O.Geometry(m)
+    en = np.maximum(O.EX[:, None] * G.nl[:, 0] + O.EY[:, None] * G.nl[:, 1], 0.0)
+    out = np.stack([np.bincount(G.cell, weights=en[a], minlength=G.n) for a in range(9)])
+    return C / (out / G.area).max()
+
+
 def _random_state(n, rng, amp=0.02):
     rho = 1 + 0.01 * rng.standard_normal(n)
     ux, uy = 0.05 * rng.standard_normal((2, n))
@@ -78,8 +87,9 @@ def test_laminar_step_parity(F, name):
     say("laminar step", name)
     make, extra = MESHES[name]
     m = make()
-    nu = 2e-4
-    p = O.default_params(nu=nu, dt=10 * 3 * nu, **extra)
+    dt = courant_dt(m)
+    nu = dt / 30
+    p = O.default_params(nu=nu, dt=dt, **extra)
     orc = O.Oracle(m, p)
     rng = np.random.default_rng(41)
     f = _random_state(orc.g.n, rng)
@@ -120,7 +130,7 @@ def test_cavity_full_run_parity(F):
     rho, ux, uy, _ = orc.macro(f)
     np.testing.assert_allclose(mo["rho"], rho, rtol=1e-12)
     np.testing.assert_allclose(mo["u"][:, 0], ux, atol=1e-12 * 0.1)
-    np.testing.assert_allclose(mo["totals"], orc.totals(f), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(mo["totals"], orc.totals(f), rtol=1e-12, atol=1e-13)
     _, ux0, uy0, _ = orc.macro(f_prev)
     np.testing.assert_allclose(res, orc.residual(ux0, uy0, ux, uy), rtol=1e-8)
     # mass is conserved in the closed cavity
@@ -148,8 +158,9 @@ def test_cavity_fp32_deviation_error(F):
 
 
 def _sst_case(m, extra, seed):
-    nu = 1e-4
-    p = O.default_params(nu=nu, dt=20 * 3 * nu, sst=True, **extra)
+    dt = courant_dt(m)
+    nu = dt / 60
+    p = O.default_params(nu=nu, dt=dt, sst=True, **extra)
     orc = O.Oracle(m, p)
     n = orc.g.n
     rng = np.random.default_rng(seed)
