@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Throughput of one IMEX Runge-Kutta step of the FVLBM D2Q9 + k-omega SST on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload delaunay4m]
+
+Workload (default): seeded Delaunay triangulation of a 4:1 rectangle, ~4.0M triangles, point
+density graded x3 toward the bottom wall; walls on the long sides, inlet left, outlet right;
+Re_H = 3.6e4, inlet u = 0.05, k = 1e-6, omega = 1e-2 (lattice units); dt = 0.9 x the advective
+Courant limit; FP32-deviation storage.  Synthetic data: the mesh and the uniform initial state
+come from the seeded generator (no datasets).  Prints one JSON line on stdout; progress on stderr.
+
+`value` = cells x steps / second / 1e6 (MLUPS) over the timed region, inputs resident in HBM.
+`roofline` = the dominant kernel's algorithmic bytes per launch / its mean HIP-event duration.
+`cpu_baseline` = the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# ----------------------------------------------------------------------------------------------
+# Workloads
+# ----------------------------------------------------------------------------------------------
+def workload(name):
+    from paper_1812_00394_amd import meshgen as mg
+    if name == "delaunay4m":
+        mesh = mg.delaunay_rect(n_points=2_000_000, seed=5)
+        U, H, Re = 0.05, 1.0, 3.6e4
+        flow = dict(nu=U * H / Re, sst=True, group_u=[[0, 0], [U, 0], [0, 0]], group_rho=[1, 1, 1],
+                    group_k=[0, 1e-6, 0], group_w=[0, 1e-2, 0])
+        init = dict(u=(U, 0.0), k=1e-6, w=1e-2)
+        return mesh, flow, init, 0.9
+    if name == "cavity":
+        mesh = mg.cavity()
+        nu = 0.1 / 1000
+        return mesh, dict(nu=nu, dt=30 * nu, group_u=[[0, 0], [0.1, 0]]), dict(u=(0.0, 0.0)), None
+    if name == "backstep":
+        mesh = mg.backstep()
+        U, Re = 0.05, 3.6e4
+        nu = U / Re
+        flow = dict(nu=nu, dt=60 * 3 * nu, sst=True, group_u=[[0, 0], [U, 0], [0, 0]], group_rho=[1, 1, 1],
+                    group_k=[0, 1e-6, 0], group_w=[0, 1e-2, 0])
+        return mesh, flow, dict(u=(0.0, 0.0), k=1e-6, w=1e-2), 0.9
+    raise SystemExit(f"unknown workload {name}")
+
+
+def make_state(F, M, flow, init, precision, dt_frac):
+    p = dict(flow)
+    if dt_frac is not None:
+        tau0 = 3 * p["nu"]
+        p["dt"] = min(p.get("dt", 1e30), dt_frac * M.max_dt())
+        p.setdefault("dt_over_tau0", p["dt"] / tau0)
+    n = M.n_cells
+    u = np.tile(np.asarray(init["u"], float), (n, 1))
+    kw = {}
+    if p.get("sst"):
+        kw = dict(k=np.full(n, init["k"]), omega=np.full(n, init["w"]))
+    p.pop("dt_over_tau0", None)
+    return F.State(M, p, precision=precision, rho=np.ones(n), u=u, **kw), p
+
+
+# Algorithmic (compulsory) bytes per cell of one launch of each kernel: every array the kernel
+# must read or write counted once (neighbour gathers counted once), T = bytes per stored value,
+# S = mean edges per cell; FP64 geometry: nl, rf, d = 48 B per edge, LSQ coefficients 16 B per
+# edge, neighbour ids 4 x 4 B, 1/A and wall distance 8 B each.
+def kernel_bytes(T, S):
+    geo_flux = 16 + 48 * S + 8
+    return {
+        "sst_a": 15 * T + 16 + 16 * S + 8,
+        "sst_b": 19 * T + geo_flux + 8,
+        "collide1": 19 * T,
+        "grad": 25 * T + 16 + 16 * S,
+        "sweep1": 53 * T + geo_flux,
+        "sweep2": 62 * T + geo_flux,
+        "sweep3": 46 * T + geo_flux,
+    }
+
+
+# Compulsory bytes per cell of a whole step for the method itself (independent of how it is split
+# into kernels): f-state traffic of the three stage sweeps (81 words), the SST coupling (14 words),
+# and the FP64 geometry of four sweeps (144 B each on triangles) plus the wall distance.
+def step_bytes(T, S):
+    geo = 8 + 16 + 4 * S + 16 * S + 4 * S + S / 2 * 32   # area, centroid, nbr, LSQ, face ids, shared faces
+    return (81 + 14) * T + 4 * geo + 8
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1812_00394_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as fh:
+            h.update(name.encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload_name, precision):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was taken on the
+    current kernel sources; else None."""
+    path = os.path.join(PROFILES, f"{kernel}_{workload_name}_{precision}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_steps(F, st, steps, warmup, stream, kernel_timing=True):
+    import torch
+    st.step(warmup)
+    torch.cuda.synchronize()
+    if kernel_timing:
+        st.timing(True)
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    t0 = time.perf_counter()
+    st.step(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    kt = st.timing_read() if kernel_timing else None
+    if kernel_timing:
+        st.timing(False)
+    return ms, wall, kt
+
+
+def cpu_baseline(mesh_sample_points, steps):
+    """The FP64 oracle (numpy) stepping a bounded sample of the workload on the host."""
+    from oracle import fvlbm_oracle as O
+    from paper_1812_00394_amd import meshgen as mg
+    m = mg.delaunay_rect(n_points=mesh_sample_points, seed=5)
+    U, H, Re = 0.05, 1.0, 3.6e4
+    nu = U * H / Re
+    orc = O.Oracle(m, O.default_params(nu=nu, dt=1.0, sst=True, group_u=[[0, 0], [U, 0], [0, 0]],
+                                       group_rho=[1, 1, 1], group_k=[0, 1e-6, 0], group_w=[0, 1e-2, 0]))
+    # same Courant fraction as the GPU run
+    G = orc.g
+    en = np.maximum(O.EX[:, None] * G.nl[:, 0] + O.EY[:, None] * G.nl[:, 1], 0.0)
+    out = np.stack([np.bincount(G.cell, weights=en[a], minlength=G.n) for a in range(9)])
+    orc.p["dt"] = 0.9 / (out / G.area).max()
+    n = G.n
+    f, k, w = orc.init_state(np.ones(n), np.full(n, U), np.zeros(n), np.full(n, 1e-6), np.full(n, 1e-2))
+    c0 = time.process_time()
+    t0 = time.perf_counter()
+    orc.run(f, k, w, steps)
+    dt = time.perf_counter() - t0
+    cores = max(1, round((time.process_time() - c0) / dt))
+    return n, steps, dt, cores
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="delaunay4m")
+    ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-points", type=int, default=40_000)
+    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference kernel for rocprof byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of this "
+              "path is a design note, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1812_00394_amd import fvlbm as F
+    F.lib()
+
+    t0 = time.perf_counter()
+    mesh, flow, init, dt_frac = workload(args.workload)
+    log(f"mesh {mesh['name']}: {len(mesh['cell_ptr']) - 1} cells generated in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    M = F.Mesh(mesh, order="morton")
+    log(f"library preprocessing {time.perf_counter() - t0:.1f}s")
+    n = M.n_cells
+    S = float(np.mean(np.diff(mesh["cell_ptr"])))
+    stream = torch.cuda.current_stream()
+
+    st, p = make_state(F, M, flow, init, args.precision, dt_frac)
+    log(f"{args.precision} state ready; dt = {p['dt']:.4g} = {p['dt'] / (3 * p['nu']):.1f} tau0")
+    ms, wall, kt = time_steps(F, st, args.steps, args.warmup, stream)
+    mlups = n * args.steps / (ms * 1e-3) / 1e6
+    log(f"{args.precision}: {ms / args.steps:.3f} ms/step, {mlups:.1f} MLUPS (wall {wall:.3f}s)")
+    mo = st.moments()
+    if not np.all(np.isfinite(mo["totals"])):
+        raise SystemExit("non-finite state after the timed steps")
+
+    T = 4 if args.precision == "fp32dev" else 8
+    kb = kernel_bytes(T, S)
+    per_kernel = {}
+    for name, (tms, cnt) in kt.items():
+        if cnt:
+            avg = tms / cnt
+            per_kernel[name] = dict(ms_avg=round(avg, 5), launches=cnt, share=round(tms / ms, 4),
+                                    gbs=round(kb[name] * n / (avg * 1e-3) / 1e9, 1))
+    dominant = max(per_kernel, key=lambda k: kt[k][0])
+    dk = per_kernel[dominant]
+    achieved = kb[dominant] * n / (dk["ms_avg"] * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, args.workload, args.precision)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": dominant, "algorithmic_bytes_per_launch": kb[dominant] * n}
+    sb = step_bytes(T, S)
+    step_gbs = sb * n * args.steps / (ms * 1e-3) / 1e9
+
+    extra = {}
+    if not args.no_fp64 and args.precision == "fp32dev":
+        st64, _ = make_state(F, M, flow, init, "fp64", dt_frac)
+        ms64, _, _ = time_steps(F, st64, max(10, args.steps // 2), args.warmup, stream, kernel_timing=False)
+        steps64 = max(10, args.steps // 2)
+        mlups64 = n * steps64 / (ms64 * 1e-3) / 1e6
+        log(f"fp64: {ms64 / steps64:.3f} ms/step, {mlups64:.1f} MLUPS")
+        # same number of steps from the same initial state: FP32-deviation error against FP64
+        st32, _ = make_state(F, M, flow, init, "fp32dev", dt_frac)
+        st32.step(args.warmup + steps64)
+        m32, m64 = st32.moments(), st64.moments()
+        U = float(np.abs(init["u"]).max()) or 0.1
+        err_u = float(np.abs(m32["u"] - m64["u"]).max() / U)
+        err_rho = float(np.abs(m32["rho"] - m64["rho"]).max())
+        extra = {"fp64_mlups": round(mlups64, 1), "fp64_ms_per_step": round(ms64 / steps64, 4),
+                 "fp32dev_vs_fp64": {"steps": args.warmup + steps64, "max_du_over_U": err_u,
+                                     "max_drho": err_rho}}
+        del st64, st32
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cn, csteps, cdt, ccores = cpu_baseline(args.cpu_sample_points, args.cpu_steps)
+        cpu = {"value": round(cn * csteps / cdt / 1e6, 4), "unit": "MLUPS", "cores": ccores, "kind": "oracle",
+               "sample": f"the same generator at {cn} cells (graded Delaunay rectangle, SST, FP64), "
+                         f"{csteps} IMEX steps in {cdt:.1f} s (numpy oracle, {os.cpu_count()} host cores visible)"}
+        log(f"cpu oracle: {cpu['value']} MLUPS on {cn} cells")
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    out = {
+        "metric": "MLUPS per IMEX step (FP64 vs FP32-dev) at stated err; adjoint/forward ratio",
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32dev" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {n} cells, D2Q9 + k-omega SST, {args.precision}, "
+                               f"dt {p['dt']:.3g} ({p['dt'] / (3 * p['nu']):.0f} tau0)",
+                   "cells": n, "precision": args.precision, "sst": bool(p.get("sst"))},
+        "roofline": roofline,
+        "step_roofline": {"bytes_per_cell": round(sb, 1), "achieved_gbs": round(step_gbs, 1),
+                          "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
+        "kernels": per_kernel,
+        "adjoint_forward_ratio": None,
+        "cpu_baseline": cpu,
+        "kernel_source_sha256": source_hash(),
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

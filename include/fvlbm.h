@@ -122,6 +122,10 @@ fvlbm_status fvlbm_mesh_geometry(const fvlbm_mesh *mesh, double *area, double *c
 /* Internal renumbering: perm[i] = user index of internal cell i. */
 fvlbm_status fvlbm_mesh_permutation(const fvlbm_mesh *mesh, int64_t *perm);
 
+/* Largest time step at advective Courant number 1 (the explicit convection limit of the IMEX
+ * stages): 1 / max over cells c and directions a of sum_edges max(e_a.n, 0) dl / A_c. */
+fvlbm_status fvlbm_mesh_max_dt(const fvlbm_mesh *mesh, double *dt);
+
 /* Device bytes fvlbm_init needs for this mesh, precision and SST switch. */
 fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *mesh, int32_t precision, int32_t sst, size_t *bytes);
 
@@ -174,6 +178,25 @@ fvlbm_status fvlbm_forces(fvlbm_state *st, uint64_t wall_group_mask, double forc
  * boundary treatment of fvlbm_step.  g_in, out: host [9][n] FP64 user order.  Synchronises.
  */
 fvlbm_status fvlbm_apply_advection(fvlbm_state *st, const double *g_in, double *out);
+
+/*
+ * Per-kernel timing with HIP events recorded on the state's stream around every launch of
+ * fvlbm_step.  enable = 1 clears the counters and starts recording, 0 stops.  fvlbm_timing_read
+ * synchronises and returns, per kernel id (FVLBM_K_*), the summed duration in ms and the number of
+ * launches since recording started.
+ */
+enum {
+    FVLBM_K_SST_A = 0,     /* SST gradients, blending, eddy viscosity, sources */
+    FVLBM_K_SST_B = 1,     /* SST fluxes and update, nu_t -> tau */
+    FVLBM_K_COLLIDE1 = 2,  /* stage-1 collision */
+    FVLBM_K_GRAD = 3,      /* least-squares gradient of a stage field */
+    FVLBM_K_SWEEP1 = 4,    /* stage-1 convection + stage-2 collision */
+    FVLBM_K_SWEEP2 = 5,    /* stage-2 convection + stage-3 collision */
+    FVLBM_K_SWEEP3 = 6,    /* stage-3 convection + combination + macro update */
+    FVLBM_K_COUNT = 7
+};
+fvlbm_status fvlbm_timing(fvlbm_state *st, int32_t enable);
+fvlbm_status fvlbm_timing_read(fvlbm_state *st, double ms[FVLBM_K_COUNT], int64_t launches[FVLBM_K_COUNT]);
 
 void fvlbm_state_destroy(fvlbm_state *st);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -67,6 +68,19 @@ struct fvlbm_state {
     double *partial = nullptr;   // kRedBlocks * 4
     double *result = nullptr;    // 4
     int64_t steps_done = 0;
+    // per-kernel event timing (fvlbm_timing)
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> event_pool;
+    size_t pool_used = 0;
+    double t_ms[FVLBM_K_COUNT] = {};
+    int64_t t_count[FVLBM_K_COUNT] = {};
+    ~fvlbm_state() {
+        for (auto &e : event_pool) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
 };
 
 namespace {
@@ -251,6 +265,43 @@ void upload_geometry(fvlbm_state *st) {
     check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+// Brackets a launch with events when timing is on.
+struct Timed {
+    fvlbm_state *st;
+    int id;
+    std::pair<hipEvent_t, hipEvent_t> ev{};
+    Timed(fvlbm_state *s, int k) : st(s), id(k) {
+        if (!st->timing) return;
+        if (st->pool_used == st->event_pool.size()) {
+            std::pair<hipEvent_t, hipEvent_t> e;
+            check(hipEventCreate(&e.first), "hipEventCreate");
+            check(hipEventCreate(&e.second), "hipEventCreate");
+            st->event_pool.push_back(e);
+        }
+        ev = st->event_pool[st->pool_used++];
+        check(hipEventRecord(ev.first, st->stream), "hipEventRecord");
+    }
+    ~Timed() {
+        if (!st->timing) return;
+        (void)hipEventRecord(ev.second, st->stream);
+        st->events.push_back({id, ev});
+    }
+};
+
+// Folds recorded events into the per-kernel sums (synchronises) and recycles them.
+void drain_events(fvlbm_state *st) {
+    if (st->events.empty()) return;
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+    for (auto &e : st->events) {
+        float ms = 0;
+        check(hipEventElapsedTime(&ms, e.second.first, e.second.second), "hipEventElapsedTime");
+        st->t_ms[e.first] += ms;
+        st->t_count[e.first] += 1;
+    }
+    st->events.clear();
+    st->pool_used = 0;
+}
+
 template <typename T>
 void launch_step(fvlbm_state *st) {
     const Geo &g = st->geo;
@@ -264,17 +315,17 @@ void launch_step(fvlbm_state *st) {
     if (st->sst) {
         T *K0 = (T *)st->K[st->cur_kw], *W0 = (T *)st->W[st->cur_kw];
         T *K1 = (T *)st->K[st->cur_kw ^ 1], *W1 = (T *)st->W[st->cur_kw ^ 1];
-        k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, p);
-        k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, K1, W1, tau, (T *)st->nut, p);
+        { Timed t(st, FVLBM_K_SST_A); k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, p); }
+        { Timed t(st, FVLBM_K_SST_B); k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, K1, W1, tau, (T *)st->nut, p); }
         st->cur_kw ^= 1;
     }
-    k_collide1<T><<<nbk, kBlock, 0, s>>>(n, F, tau, X, p);
-    k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0);
-    k_sweep1<T><<<nbk, kBlock, 0, s>>>(g, F, X, G, tau, Y, A, p);
-    k_grad<T><<<nbk, kBlock, 0, s>>>(g, Y, G, p.rho0);
-    k_sweep2<T><<<nbk, kBlock, 0, s>>>(g, F, Y, G, tau, X, A, p);
-    k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0);
-    k_sweep3<T><<<nbk, kBlock, 0, s>>>(g, X, G, A, F, Mnew, p);
+    { Timed t(st, FVLBM_K_COLLIDE1); k_collide1<T><<<nbk, kBlock, 0, s>>>(n, F, tau, X, p); }
+    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
+    { Timed t(st, FVLBM_K_SWEEP1); k_sweep1<T><<<nbk, kBlock, 0, s>>>(g, F, X, G, tau, Y, A, p); }
+    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, Y, G, p.rho0); }
+    { Timed t(st, FVLBM_K_SWEEP2); k_sweep2<T><<<nbk, kBlock, 0, s>>>(g, F, Y, G, tau, X, A, p); }
+    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
+    { Timed t(st, FVLBM_K_SWEEP3); k_sweep3<T><<<nbk, kBlock, 0, s>>>(g, X, G, A, F, Mnew, p); }
     st->cur_m ^= 1;
     check(hipGetLastError(), "kernel launch");
 }
@@ -523,6 +574,7 @@ fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *res) {
                 launch_step<double>(st);
             else
                 launch_step<float>(st);
+            if (st->timing && st->events.size() > 4096) drain_events(st);
         }
         st->steps_done += n_steps;
         if (res) {
@@ -594,6 +646,51 @@ fvlbm_status fvlbm_apply_advection(fvlbm_state *st, const double *g_in, double *
             apply_advection<double>(st, g_in, out);
         else
             apply_advection<float>(st, g_in, out);
+    });
+}
+
+fvlbm_status fvlbm_timing(fvlbm_state *st, int32_t enable) {
+    return guarded([&] {
+        if (!st) throw Error(FVLBM_EINVAL, "timing: NULL state");
+        drain_events(st);
+        if (enable) {
+            for (int i = 0; i < FVLBM_K_COUNT; ++i) {
+                st->t_ms[i] = 0;
+                st->t_count[i] = 0;
+            }
+        }
+        st->timing = enable != 0;
+    });
+}
+
+fvlbm_status fvlbm_timing_read(fvlbm_state *st, double ms[FVLBM_K_COUNT], int64_t launches[FVLBM_K_COUNT]) {
+    return guarded([&] {
+        if (!st || !ms || !launches) throw Error(FVLBM_EINVAL, "timing_read: NULL argument");
+        drain_events(st);
+        for (int i = 0; i < FVLBM_K_COUNT; ++i) {
+            ms[i] = st->t_ms[i];
+            launches[i] = st->t_count[i];
+        }
+    });
+}
+
+fvlbm_status fvlbm_mesh_max_dt(const fvlbm_mesh *m, double *dt) {
+    return guarded([&] {
+        if (!m || !dt) throw Error(FVLBM_EINVAL, "mesh_max_dt: NULL argument");
+        double worst = 0;
+        const int64_t n = m->n;
+        for (int64_t c = 0; c < n; ++c) {
+            for (int a = 1; a < 9; ++a) {
+                double out = 0;
+                for (int s = 0; s < kSlots; ++s) {
+                    const int64_t si = s * n + c;
+                    if (m->nbr[si] == -1) continue;
+                    out += std::max(0.0, ex(a) * m->nlx[si] + ey(a) * m->nly[si]);
+                }
+                worst = std::max(worst, out / m->area[c]);
+            }
+        }
+        *dt = 1.0 / worst;
     });
 }
 

@@ -53,7 +53,8 @@ _lib = None
 EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlbm_mesh_geometry",
            "fvlbm_mesh_permutation", "fvlbm_state_bytes", "fvlbm_init", "fvlbm_set_state", "fvlbm_step",
            "fvlbm_moments", "fvlbm_get_f", "fvlbm_forces", "fvlbm_apply_advection", "fvlbm_state_destroy",
-           "fvlbm_last_error"]
+           "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read"]
+KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3"]
 
 
 def lib():
@@ -79,6 +80,9 @@ def lib():
     L.fvlbm_get_f.argtypes = [P, I32, P]
     L.fvlbm_forces.argtypes = [P, C.c_uint64, P, P]
     L.fvlbm_apply_advection.argtypes = [P, P, P]
+    L.fvlbm_mesh_max_dt.argtypes = [P, P]
+    L.fvlbm_timing.argtypes = [P, I32]
+    L.fvlbm_timing_read.argtypes = [P, P, P]
     L.fvlbm_state_destroy.argtypes = [P]
     L.fvlbm_state_destroy.restype = None
     L.fvlbm_last_error.restype = C.c_char_p
@@ -141,6 +145,12 @@ class Mesh:
         p = np.zeros(self.n_cells, dtype=np.int64)
         _check(lib().fvlbm_mesh_permutation(self.handle, _ptr(p)))
         return p
+
+    def max_dt(self):
+        """time step at advective Courant number 1"""
+        d = np.zeros(1)
+        _check(lib().fvlbm_mesh_max_dt(self.handle, _ptr(d)))
+        return float(d[0])
 
     def state_bytes(self, precision="fp64", sst=False):
         b = C.c_size_t()
@@ -252,6 +262,16 @@ class State:
         out = np.zeros((9, n))
         _check(lib().fvlbm_apply_advection(self.handle, _ptr(g), _ptr(out)))
         return out
+
+    def timing(self, enable=True):
+        _check(lib().fvlbm_timing(self.handle, int(bool(enable))))
+
+    def timing_read(self):
+        """{kernel: (total ms, launches)} since timing was enabled"""
+        ms = np.zeros(len(KERNELS))
+        cnt = np.zeros(len(KERNELS), dtype=np.int64)
+        _check(lib().fvlbm_timing_read(self.handle, _ptr(ms), _ptr(cnt)))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNELS)}
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
