@@ -414,10 +414,14 @@ class Oracle:
         out = []
         for phi, gphi, ghost, Gcell in ((k, gkw[0], gk, Gk_cell), (w, gkw[1], gw, Gw_cell)):
             # convective: mdot * upwind reconstructed value
+            # reading r28: the reconstructed upwind value is kept in [0, 2 phi_up] (positivity;
+            # inactive where |grad phi . r| <= phi_up, i.e. in smooth regions)
             v_self = phi[hc] + gphi[0, hc] * rc[:, 0] + gphi[1, hc] * rc[:, 1]
+            v_self = rmin(rmax(v_self, 0.0), 2.0 * phi[hc])
             fv = v_self.copy()
             rn = G.xf[inner] - G.xs[inner]
             v_nbr = phi[nb] + gphi[0, nb] * rn[:, 0] + gphi[1, nb] * rn[:, 1]
+            v_nbr = rmin(rmax(v_nbr, 0.0), 2.0 * phi[nb])
             fv[inner] = np.where(np.real(mdot[inner]) >= 0, v_self[inner], v_nbr)
             fv[bh] = np.where(np.real(mdot[bh]) >= 0, v_self[bh], ghost)
             conv = mdot * fv
@@ -436,8 +440,14 @@ class Oracle:
             diff[bh] = np.where(dirichlet, Gcell[c] * (ghost - phi[c]) / dperp * G.l[bh], 0.0)
             out.append(self._cell_sum(-conv + diff))
         net_k, net_w = out
-        k1 = (k + dt / (rho * G.area) * net_k + dt / rho * P) / (1 + dt * bstar * w)
-        w1 = (w + dt / (rho * G.area) * net_w + dt / rho * (Pw + cross)) / (1 + dt * beta * w)
+        # reading r29: the negative part of each explicit source moves into the implicit
+        # denominator (divided by the old value), so a negative source cannot flip the sign
+        src_k = P
+        src_w = Pw + cross
+        pos_k, neg_k = rmax(src_k, 0.0), rmax(-src_k, 0.0)
+        pos_w, neg_w = rmax(src_w, 0.0), rmax(-src_w, 0.0)
+        k1 = (k + dt / (rho * G.area) * net_k + dt / rho * pos_k) / (1 + dt * bstar * w + dt / rho * neg_k / k)
+        w1 = (w + dt / (rho * G.area) * net_w + dt / rho * pos_w) / (1 + dt * beta * w + dt / rho * neg_w / w)
         k1 = rmax(k1, 1e-20)
         w1 = rmax(w1, 1e-20)
         # eddy viscosity from the updated k, omega (F2 re-evaluated), strain from level n

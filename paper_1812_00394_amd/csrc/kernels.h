@@ -257,6 +257,9 @@ template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a <= b ? a : b; }
 
 template <typename T>
+__device__ __forceinline__ T bound_face(T v, T up) { return tmin(tmax(v, T(0)), T(2) * up); }
+
+template <typename T>
 __global__ void __launch_bounds__(256) k_sst_a(Geo g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
                                                const T *__restrict__ K, const T *__restrict__ W,
                                                T *__restrict__ aux, StepPar<T> p) {
@@ -353,8 +356,10 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
         if (nb == -1) continue;
         const T nlx = T(g.nlx[si]), nly = T(g.nly[si]);
         const T rx = T(g.rfx[si]), ry = T(g.rfy[si]);
-        const T ks = kc + gkc[0] * rx + gkc[1] * ry;   // own value extrapolated to the edge
-        const T ws = wc + gwc[0] * rx + gwc[1] * ry;
+        // own value extrapolated to the edge, kept in [0, 2 phi_c] so the explicit outflow
+        // cannot drive k or omega negative (inactive where |grad phi . r| <= phi_c)
+        const T ks = bound_face(kc + gkc[0] * rx + gkc[1] * ry, kc);
+        const T ws = bound_face(wc + gwc[0] * rx + gwc[1] * ry, wc);
         if (nb >= 0) {
             const T rhoN = p.rho0 + M[nb], uxN = M[(size_t)n + nb], uyN = M[(size_t)2 * n + nb];
             const T mdot = T(0.5) * ((rho * ux + rhoN * uxN) * nlx + (rho * uy + rhoN * uyN) * nly);
@@ -367,8 +372,8 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
                 wf = ws;
             } else {
                 const T qx = T(g.rfx[si] - g.dx[si]), qy = T(g.rfy[si] - g.dy[si]);
-                kf = kN + gkN[0] * qx + gkN[1] * qy;
-                wf = wN + gwN[0] * qx + gwN[1] * qy;
+                kf = bound_face(kN + gkN[0] * qx + gkN[1] * qy, kN);
+                wf = bound_face(wN + gwN[0] * qx + gwN[1] * qy, wN);
             }
             const T ddx = T(g.dx[si]), ddy = T(g.dy[si]);
             const T dist = sqrt(ddx * ddx + ddy * ddy);
@@ -405,8 +410,10 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
         }
     }
     const T fac = p.dt * T(g.inv_area[c]) / rho;
-    T k1 = (kc + fac * net_k + aux[(size_t)6 * n + c]) / (T(1) + p.dt * p.bstar * wc);
-    T w1 = (wc + fac * net_w + aux[(size_t)7 * n + c]) / (T(1) + p.dt * aux[(size_t)8 * n + c] * wc);
+    // point-implicit update; the negative part of each explicit source joins the denominator
+    const T sk = aux[(size_t)6 * n + c], sw = aux[(size_t)7 * n + c];
+    T k1 = (kc + fac * net_k + tmax(sk, T(0))) / (T(1) + p.dt * p.bstar * wc + tmax(-sk, T(0)) / kc);
+    T w1 = (wc + fac * net_w + tmax(sw, T(0))) / (T(1) + p.dt * aux[(size_t)8 * n + c] * wc + tmax(-sw, T(0)) / wc);
     k1 = tmax(k1, T(1e-20));
     w1 = tmax(w1, T(1e-20));
     const T d = T(g.wdist[c]);

@@ -204,6 +204,29 @@ def test_sst_step_parity(F, name):
         assert rel(mo["nu_t"], orc.last_nut, np.abs(orc.last_nut).max()) < tol * 10, ("nu_t", nsteps)
 
 
+def test_sst_impulsive_start_parity(F):
+    """Uniform stream started impulsively between walls: the positivity bound of the k / omega
+    face values and the implicit negative sources are active on both sides."""
+    say("sst impulsive start, graded delaunay")
+    m = mg.delaunay_rect(n_points=1500, seed=5)
+    U, nu = 0.05, 0.05 / 3.6e4
+    p = O.default_params(nu=nu, dt=0.9 * courant_dt(m, 1.0), sst=True, group_u=[[0, 0], [U, 0], [0, 0]],
+                         group_rho=[1, 1, 1], group_k=[0, 1e-6, 0], group_w=[0, 1e-2, 0])
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    f, k, w = orc.init_state(np.ones(n), np.full(n, U), np.zeros(n), np.full(n, 1e-6), np.full(n, 1e-2))
+    st = F.State(F.Mesh(m), p, precision="fp64", rho=np.ones(n), u=np.tile([U, 0.0], (n, 1)),
+                 k=np.full(n, 1e-6), omega=np.full(n, 1e-2))
+    for nsteps in (1, 9, 20):
+        f, k, w = orc.run(f, k, w, nsteps)
+        st.step(nsteps)
+        got = st.get_f()
+        mo = st.moments()
+        assert rel(got, f, dev_scale(f)) < 1e-10, ("f", nsteps, rel(got, f, dev_scale(f)))
+        assert rel(mo["k"], k, np.abs(k).max()) < 1e-9, ("k", nsteps, rel(mo["k"], k, np.abs(k).max()))
+        assert rel(mo["omega"], w, np.abs(w).max()) < 1e-9, ("w", nsteps)
+
+
 def test_forces_parity(F):
     say("forces naca")
     make, extra = SST_MESHES["naca"]

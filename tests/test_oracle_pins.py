@@ -522,3 +522,54 @@ def test_sst_upwind_translation():
     exact = k0(x - U[0] * T, y - U[1] * T) * decay
     err = np.sqrt(np.sum(G.area * (k - exact) ** 2)) / np.sqrt(np.sum(G.area * exact ** 2))
     assert err < 0.03, err
+
+
+def test_sst_negative_sources_implicit():
+    """Reading r29.  Uniform k, omega and a linear velocity with positive divergence on a uniform
+    quad mesh: P = rho k ((S^2 - 2/3 div^2)/omega - 2/3 div) < 0 and likewise the omega source, so
+    interior cells obey exactly
+        k1 = (k - dt k div) / (1 + dt beta* w + dt |P| / (rho k))
+        w1 = (w - dt w div) / (1 + dt beta2 w + dt |P_w| / (rho w))."""
+    mesh = mg.rectangle(10, 10, kind="open", split="none")
+    nu, dt = 1e-5, 0.05
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True, group_u=[[0.0, 0.0]],
+                                          group_k=[1e-4], group_w=[10.0]))
+    G = orc.g
+    x, y = G.xc[:, 0], G.xc[:, 1]
+    n = G.n
+    a = 0.1
+    ux, uy = 0.02 + a * x, -0.01 + a * y
+    k, w = np.full(n, 1e-4), np.full(n, 10.0)
+    k1, w1, _, _ = orc.sst_update(np.ones(n), ux, uy, k, w)
+    cells = _two_ring_interior(G)
+    S2, div = 2 * (a * a + a * a), 2 * a
+    P = k[0] * ((S2 - 2 / 3 * div ** 2) / w[0] - 2 / 3 * div)
+    c = dict(O.SST_DEFAULTS)
+    cw2 = c["beta2"] / c["beta_star"] - c["sigma_w2"] * c["kappa"] ** 2 / np.sqrt(c["beta_star"])
+    Pw = cw2 * (S2 - 2 / 3 * div ** 2) - 2 / 3 * cw2 * w[0] * div
+    assert P < 0 and Pw < 0
+    ek = (k[0] - dt * k[0] * div) / (1 + dt * 0.09 * w[0] + dt * (-P) / k[0])
+    ew = (w[0] - dt * w[0] * div) / (1 + dt * 0.0828 * w[0] + dt * (-Pw) / w[0])
+    np.testing.assert_allclose(k1[cells], ek, rtol=1e-12)
+    np.testing.assert_allclose(w1[cells], ew, rtol=1e-12)
+
+
+def test_sst_stays_positive_from_impulsive_start():
+    """Readings r28-r29: a uniform stream started impulsively between walls (large near-wall
+    gradients, wall omega >> interior omega) keeps k and omega positive and the relaxation time
+    bounded, at dt = 0.9 of the advective Courant limit (hundreds of tau0 on this coarse mesh)."""
+    m = mg.delaunay_rect(n_points=1500, seed=5)
+    U, nu = 0.05, 0.05 / 3.6e4
+    orc = O.Oracle(m, O.default_params(nu=nu, dt=1.0, sst=True, group_u=[[0, 0], [U, 0], [0, 0]],
+                                       group_rho=[1, 1, 1], group_k=[0, 1e-6, 0], group_w=[0, 1e-2, 0]))
+    G = orc.g
+    en = np.maximum(O.EX[:, None] * G.nl[:, 0] + O.EY[:, None] * G.nl[:, 1], 0.0)
+    out = np.stack([np.bincount(G.cell, weights=en[a], minlength=G.n) for a in range(9)])
+    orc.p["dt"] = 0.9 / (out / G.area).max()
+    n = G.n
+    f, k, w = orc.init_state(np.ones(n), np.full(n, U), np.zeros(n), np.full(n, 1e-6), np.full(n, 1e-2))
+    for _ in range(60):
+        f, k, w = orc.step(f, k, w)
+        assert k.min() > 1e-12 and w.min() > 1e-8, (k.min(), w.min())
+        assert orc.last_tau.max() < 1e-2
+    assert np.isfinite(f).all()
