@@ -425,15 +425,15 @@ class Oracle:
             fv[inner] = np.where(np.real(mdot[inner]) >= 0, v_self[inner], v_nbr)
             fv[bh] = np.where(np.real(mdot[bh]) >= 0, v_self[bh], ghost)
             conv = mdot * fv
-            # diffusive: Gamma_f (grad phi_f . n) dl with the over-relaxed-free correction
+            # diffusive (reading r30): Gamma_f (grad phi_f . n) dl with the two-point central
+            # difference along the centroid line, grad phi_f = (phi_N - phi_c) / |d| d^
             diff = np.zeros(H, dtype=self.dtype)
             dvec = G.d[inner]
             dist = np.sqrt(dvec[:, 0] ** 2 + dvec[:, 1] ** 2)
             dh = dvec / dist[:, None]
-            ag = 0.5 * (gphi[:, hc[inner]] + gphi[:, nb])
-            corr = (phi[nb] - phi[hc[inner]]) / dist - (ag[0] * dh[:, 0] + ag[1] * dh[:, 1])
-            gfx = ag[0] + corr * dh[:, 0]
-            gfy = ag[1] + corr * dh[:, 1]
+            dq = (phi[nb] - phi[hc[inner]]) / dist
+            gfx = dq * dh[:, 0]
+            gfy = dq * dh[:, 1]
             Gf = 0.5 * (Gcell[hc[inner]] + Gcell[nb])
             diff[inner] = Gf * (gfx * G.nl[inner, 0] + gfy * G.nl[inner, 1])
             dirichlet = ~zg

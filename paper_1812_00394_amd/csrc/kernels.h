@@ -379,14 +379,10 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
             const T dist = sqrt(ddx * ddx + ddy * ddy);
             const T hx = ddx / dist, hy = ddy / dist;
             const T GkN = aux[(size_t)4 * n + nb], GwN = aux[(size_t)5 * n + nb];
-            // face gradient: average gradient with its component along d replaced by the difference quotient
-            T agx = T(0.5) * (gkc[0] + gkN[0]), agy = T(0.5) * (gkc[1] + gkN[1]);
-            T corr = (kN - kc) / dist - (agx * hx + agy * hy);
-            const T dk = T(0.5) * (Gkc + GkN) * ((agx + corr * hx) * nlx + (agy + corr * hy) * nly);
-            agx = T(0.5) * (gwc[0] + gwN[0]);
-            agy = T(0.5) * (gwc[1] + gwN[1]);
-            corr = (wN - wc) / dist - (agx * hx + agy * hy);
-            const T dw = T(0.5) * (Gwc + GwN) * ((agx + corr * hx) * nlx + (agy + corr * hy) * nly);
+            // central two-point face gradient along the centroid line: (phi_N - phi_c) / |d| d^
+            const T hn = (hx * nlx + hy * nly) / dist;
+            const T dk = T(0.5) * (Gkc + GkN) * (kN - kc) * hn;
+            const T dw = T(0.5) * (Gwc + GwN) * (wN - wc) * hn;
             net_k += -mdot * kf + dk;
             net_w += -mdot * wf + dw;
         } else {

@@ -450,8 +450,10 @@ def test_sst_manufactured_advection_and_cross_diffusion():
     """Uniform flow, linear k and omega = c k (so mu_t = rho/c is uniform and F1 = 0 without
     walls): on cells away from the boundary the update is exactly
       k1 = (k - dt u.grad k) / (1 + dt beta* omega)
-      w1 = (w - dt u.grad w + dt 2 sigma_w2 grad k.grad w / w) / (1 + dt beta2 w)."""
-    mesh = mg.rectangle(12, 12, kind="open", jitter=0.2, seed=24)
+      w1 = (w - dt u.grad w + dt 2 sigma_w2 grad k.grad w / w) / (1 + dt beta2 w).
+    The mesh is orthogonal (uniform quads), where the two-point diffusive flux of a linear field
+    with uniform coefficient vanishes exactly (reading r30)."""
+    mesh = mg.rectangle(12, 12, kind="open", split="none")
     nu, dt = 1e-4, 0.05
     orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True, group_u=[[0.04, -0.03]],
                                           group_k=[1e-3], group_w=[0.5]))
