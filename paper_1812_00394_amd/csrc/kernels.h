@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, 
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= g.n) return;
     const int n = g.n;
-    T gc[9], ga[9], fn[9], f1[9], fe1[9], rhs[9], f3[9], fe[9];
+    T gc[9], ga[9], fn[9], f1[9], fe1[9], rhs[9], f3[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) gc[a] = Y[(size_t)a * n + c];
     advect_cell(g, Y, G, c, p.rho0, gc, ga);
@@ -186,6 +186,8 @@ __global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, 
     T drho2, rho2, ux2, uy2;
     moments(gc, p.rho0, drho2, rho2, ux2, uy2);                  // stage-2 moments
     const T h2 = p.dt * T(0.5), h3 = p.dt / T(3);
+    // stage-3 moments from f^n and the convection terms (Eq. (sumimeximplicitnew))
+    T m0 = 0, mx = 0, my = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const T a1 = A[(size_t)a * n + c];
@@ -193,8 +195,13 @@ __global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, 
         const T gc2 = (dfeq(a, drho2, rho2, ux2, uy2) - gc[a]) * itau;
         rhs[a] = fn[a] + h2 * (a1 + ga[a]) + h3 * (gc1 + gc2);
         ga[a] += a1;                                               // Ga1 + Ga2
+        const T mv = fn[a] + h2 * ga[a];
+        m0 += mv;
+        mx += T(ex(a)) * mv;
+        my += T(ey(a)) * mv;
     }
-    stage_collide(rhs, p.dt / (T(3) * tc), p.rho0, f3, fe);
+    const T rho3 = p.rho0 + m0;
+    stage_collide_m(rhs, p.dt / (T(3) * tc), m0, rho3, mx / rho3, my / rho3, f3);
     const T h6 = p.dt / T(6);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {

@@ -73,6 +73,16 @@ __device__ __forceinline__ void stage_collide(const T rhs[9], T a, T rho0, T out
     }
 }
 
+// The same stage solve with the stage moments given (Eq. (sumimeximplicitnew): they follow from f^n
+// and the earlier convection terms alone, never from the collision terms, whose invariant moments
+// vanish only up to rounding and would be amplified by dt / tau).
+template <typename T>
+__device__ __forceinline__ void stage_collide_m(const T rhs[9], T a, T drho, T rho, T ux, T uy, T out[9]) {
+    T inv = T(1) / (T(1) + a);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] = (rhs[q] + a * dfeq(q, drho, rho, ux, uy)) * inv;
+}
+
 enum : int32_t { kWall = 1, kMovingWall = 2, kInlet = 3, kOutlet = 4, kFarfield = 5 };
 
 // Ghost deviation at the midpoint of boundary edge b of a cell whose state is gc (moments drho,

@@ -64,6 +64,9 @@ def lib():
         return _lib
     if not os.path.exists(LIB):
         raise RuntimeError(f"{LIB} is missing: build it with `python -m paper_1812_00394_amd.build`")
+    # torch first: its HIP runtime then satisfies the library's libamdhip64.so.7 dependency, so the
+    # workspace, the stream and the library's kernels share one runtime
+    import torch  # noqa: F401
     L = C.CDLL(LIB)
     P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int32, C.c_double
     L.fvlbm_mesh_create.argtypes = [I64, P, I64, P, P, I64, P, P, I32, P, P, I32, C.POINTER(C.c_void_p)]

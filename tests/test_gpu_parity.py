@@ -228,8 +228,9 @@ def test_sst_impulsive_start_parity(F):
 
 
 def test_sst_impulsive_start_fp32_deviation(F):
-    """The same impulsive start in FP32-deviation storage against the FP64 oracle after 30 steps:
-    velocity within 1e-4 U, k and omega within 1e-3 relative (stated gates)."""
+    """The same impulsive start in FP32-deviation storage against the FP64 oracle: velocity, k and
+    omega within 2e-6 after one step and within 1e-4 after 30 steps of this harsh transient
+    (relative to U and to their maxima; stated gates)."""
     say("sst impulsive start fp32dev")
     m = mg.delaunay_rect(n_points=1500, seed=5)
     U, nu = 0.05, 0.05 / 3.6e4
@@ -238,18 +239,19 @@ def test_sst_impulsive_start_fp32_deviation(F):
     orc = O.Oracle(m, p)
     n = orc.g.n
     f, k, w = orc.init_state(np.ones(n), np.full(n, U), np.zeros(n), np.full(n, 1e-6), np.full(n, 1e-2))
-    f, k, w = orc.run(f, k, w, 30)
     st = F.State(F.Mesh(m), p, precision="fp32dev", rho=np.ones(n), u=np.tile([U, 0.0], (n, 1)),
                  k=np.full(n, 1e-6), omega=np.full(n, 1e-2))
-    st.step(30)
-    mo = st.moments()
-    _, ux, uy, _ = orc.macro(f)
-    du = max(np.abs(mo["u"][:, 0] - ux).max(), np.abs(mo["u"][:, 1] - uy).max()) / U
-    dk = np.abs(mo["k"] - k).max() / np.abs(k).max()
-    dw = np.abs(mo["omega"] - w).max() / np.abs(w).max()
-    print("fp32dev sst errors: du/U", du, "dk", dk, "dw", dw)
-    assert np.isfinite(mo["totals"]).all()
-    assert du < 1e-4 and dk < 1e-3 and dw < 1e-3, (du, dk, dw)
+    for nsteps, gate_u, gate_kw in ((1, 2e-6, 2e-6), (29, 1e-4, 1e-4)):
+        f, k, w = orc.run(f, k, w, nsteps)
+        st.step(nsteps)
+        mo = st.moments()
+        _, ux, uy, _ = orc.macro(f)
+        du = max(np.abs(mo["u"][:, 0] - ux).max(), np.abs(mo["u"][:, 1] - uy).max()) / U
+        dk = np.abs(mo["k"] - k).max() / np.abs(k).max()
+        dw = np.abs(mo["omega"] - w).max() / np.abs(w).max()
+        print("fp32dev sst errors after", nsteps, "steps: du/U", du, "dk", dk, "dw", dw)
+        assert np.isfinite(mo["totals"]).all()
+        assert du < gate_u and dk < gate_kw and dw < gate_kw, (nsteps, du, dk, dw)
 
 
 def test_forces_parity(F):
