@@ -32,7 +32,7 @@ struct StepPar {
 // ----------------------------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T *__restrict__ G, T rho0) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     T gc[9];
@@ -132,7 +132,7 @@ __device__ __forceinline__ void advect_cell(const Geo &g, const T *__restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256) k_collide1(int n, const T *__restrict__ F, const T *__restrict__ tau,
                                                   T *__restrict__ X, StepPar<T> p) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= n) return;
     T fn[9], f1[9], fe[9];
 #pragma unroll
@@ -147,7 +147,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_sweep1(Geo g, const T *__restrict__ F, const T *__restrict__ X,
                                                 const T *__restrict__ G, const T *__restrict__ tau,
                                                 T *__restrict__ Y, T *__restrict__ A, StepPar<T> p) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     T gc[9], ga[9], rhs[9], f2[9], fe[9];
@@ -171,7 +171,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, const T *__restrict__ Y,
                                                 const T *__restrict__ G, const T *__restrict__ tau,
                                                 T *__restrict__ X, T *__restrict__ A, StepPar<T> p) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     T gc[9], ga[9], fn[9], f1[9], fe1[9], rhs[9], f3[9];
@@ -215,7 +215,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_sweep3(Geo g, const T *__restrict__ X, const T *__restrict__ G,
                                                 const T *__restrict__ A, T *__restrict__ F, T *__restrict__ M,
                                                 StepPar<T> p) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     T gc[9], ga[9], fnew[9];
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(256) k_sweep3(Geo g, const T *__restrict__ X, 
 template <typename T>
 __global__ void __launch_bounds__(256) k_advect(Geo g, const T *__restrict__ X, const T *__restrict__ G,
                                                 T *__restrict__ out, T rho0) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     T gc[9], ga[9];
@@ -270,7 +270,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_sst_a(Geo g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
                                                const T *__restrict__ K, const T *__restrict__ W,
                                                T *__restrict__ aux, StepPar<T> p) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     const T rho = p.rho0 + M[c], ux = M[(size_t)n + c], uy = M[(size_t)2 * n + c];
@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
                                                const T *__restrict__ K, const T *__restrict__ W,
                                                const T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
                                                T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     const T rho = p.rho0 + M[c], ux = M[(size_t)n + c], uy = M[(size_t)2 * n + c];
@@ -523,7 +523,7 @@ __global__ void __launch_bounds__(256) k_forces(Geo g, const T *__restrict__ M, 
 // ----------------------------------------------------------------------------------------------
 template <typename T>
 __global__ void k_import_f(Geo g, const double *__restrict__ fu, T *__restrict__ F, double rho0) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int u = g.perm[c];
 #pragma unroll
@@ -532,7 +532,7 @@ __global__ void k_import_f(Geo g, const double *__restrict__ fu, T *__restrict__
 
 template <typename T>
 __global__ void k_export_f(Geo g, const T *__restrict__ F, double *__restrict__ fu, double rho0) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int u = g.perm[c];
 #pragma unroll
@@ -543,7 +543,7 @@ __global__ void k_export_f(Geo g, const T *__restrict__ F, double *__restrict__ 
 template <typename T>
 __global__ void k_init_feq(Geo g, const double *__restrict__ rho_u, const double *__restrict__ vel_u,
                            T *__restrict__ F, double rho0) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int u = g.perm[c];
     const double rho = rho_u[u], ux = vel_u[2 * (size_t)u], uy = vel_u[2 * (size_t)u + 1];
@@ -553,21 +553,21 @@ __global__ void k_init_feq(Geo g, const double *__restrict__ rho_u, const double
 
 template <typename T>
 __global__ void k_import_scalar(Geo g, const double *__restrict__ su, T *__restrict__ S) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     S[c] = T(su[g.perm[c]]);
 }
 
 template <typename T>
 __global__ void k_export_scalar(Geo g, const T *__restrict__ S, double add, double *__restrict__ su) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     su[g.perm[c]] = (double)S[c] + add;
 }
 
 template <typename T>
 __global__ void k_export_vel(Geo g, const T *__restrict__ M, double *__restrict__ vu) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= g.n) return;
     const int u = g.perm[c];
     vu[2 * (size_t)u] = (double)M[(size_t)g.n + c];
@@ -577,7 +577,7 @@ __global__ void k_export_vel(Geo g, const T *__restrict__ M, double *__restrict_
 // macro variables of the current f (after import / init)
 template <typename T>
 __global__ void k_macro(int n, const T *__restrict__ F, T *__restrict__ M, T rho0) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c >= n) return;
     T d[9];
 #pragma unroll
@@ -591,7 +591,7 @@ __global__ void k_macro(int n, const T *__restrict__ F, T *__restrict__ M, T rho
 
 template <typename T>
 __global__ void k_fill(int n, T *__restrict__ x, T v) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = cell_index();
     if (c < n) x[c] = v;
 }
 

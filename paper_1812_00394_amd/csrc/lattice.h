@@ -20,6 +20,17 @@ __host__ __device__ constexpr T wt(int a) {
     return a == 0 ? T(4) / T(9) : (a < 5 ? T(1) / T(9) : T(1) / T(36));
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD b mod 8).  This maps
+// them so that each XCD processes one contiguous range of blocks; with cells in space-filling-curve
+// order its neighbour gathers then hit its own L2 instead of being fetched again by another XCD.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ int cell_index() { return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; }
+
 // Geometry and boundary data on the device (pointers into the caller's workspace).
 struct Geo {
     int32_t n;    // cells
