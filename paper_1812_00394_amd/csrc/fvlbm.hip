@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <string>
@@ -64,6 +65,12 @@ struct fvlbm_state {
     void *K[2] = {nullptr, nullptr}, *W[2] = {nullptr, nullptr};
     void *tau = nullptr, *nut = nullptr, *aux = nullptr;
     int cur_m = 0, cur_kw = 0;
+    // tiles of the fused stage kernels
+    bool tiled = true;
+    int32_t *hptr = nullptr, *hcell = nullptr;
+    int16_t *lnb = nullptr;
+    int tile_w = 0;
+    size_t lds_bytes = 0;
     double *scratch = nullptr;   // 9 n doubles (staging of user-order FP64 arrays)
     double *partial = nullptr;   // kRedBlocks * 4
     double *result = nullptr;    // 4
@@ -136,6 +143,9 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
         st->W[1] = cv.take<T>(n);
         st->aux = cv.take<T>(10 * n);
     }
+    st->lnb = cv.take<int16_t>(S);
+    st->hptr = cv.take<int32_t>((size_t)m->n_tiles + 1);
+    st->hcell = cv.take<int32_t>(std::max<size_t>(1, m->halo_cell.size()));
     st->scratch = cv.take<double>(9 * n);
     st->partial = cv.take<double>((size_t)kRedBlocks * 4);
     st->result = cv.take<double>(4);
@@ -251,6 +261,9 @@ void upload_geometry(fvlbm_state *st) {
     h2d(const_cast<double *>(g.b_l), m->b_l, s);
     h2d(const_cast<double *>(g.b_dperp), m->b_dperp, s);
     h2d(const_cast<double *>(g.b_xfx), m->b_xfx, s);
+    h2d(st->lnb, m->lnb, s);
+    h2d(st->hptr, m->halo_ptr, s);
+    h2d(st->hcell, m->halo_cell, s);
     std::vector<double> bv[6];
     std::vector<int32_t> zg;
     boundary_values(m, st->par, bv, zg);
@@ -320,12 +333,23 @@ void launch_step(fvlbm_state *st) {
         st->cur_kw ^= 1;
     }
     { Timed t(st, FVLBM_K_COLLIDE1); k_collide1<T><<<nbk, kBlock, 0, s>>>(n, F, tau, X, p); }
-    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
-    { Timed t(st, FVLBM_K_SWEEP1); k_sweep1<T><<<nbk, kBlock, 0, s>>>(g, F, X, G, tau, Y, A, p); }
-    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, Y, G, p.rho0); }
-    { Timed t(st, FVLBM_K_SWEEP2); k_sweep2<T><<<nbk, kBlock, 0, s>>>(g, F, Y, G, tau, X, A, p); }
-    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
-    { Timed t(st, FVLBM_K_SWEEP3); k_sweep3<T><<<nbk, kBlock, 0, s>>>(g, X, G, A, F, Mnew, p); }
+    const StageBufs<T> b1{X, F, tau, A, Y, nullptr, nullptr};
+    const StageBufs<T> b2{Y, F, tau, A, X, nullptr, nullptr};
+    const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, F, Mnew};
+    if (st->tiled) {
+        const int nt = st->mesh->n_tiles;
+        const size_t lds = st->lds_bytes;
+        { Timed t(st, FVLBM_K_SWEEP1); k_stage_tiled<T, 1><<<nt, kTileCells, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b1, p); }
+        { Timed t(st, FVLBM_K_SWEEP2); k_stage_tiled<T, 2><<<nt, kTileCells, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b2, p); }
+        { Timed t(st, FVLBM_K_SWEEP3); k_stage_tiled<T, 3><<<nt, kTileCells, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b3, p); }
+    } else {
+        { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
+        { Timed t(st, FVLBM_K_SWEEP1); k_sweep<T, 1><<<nbk, kBlock, 0, s>>>(g, G, b1, p); }
+        { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, Y, G, p.rho0); }
+        { Timed t(st, FVLBM_K_SWEEP2); k_sweep<T, 2><<<nbk, kBlock, 0, s>>>(g, G, b2, p); }
+        { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
+        { Timed t(st, FVLBM_K_SWEEP3); k_sweep<T, 3><<<nbk, kBlock, 0, s>>>(g, G, b3, p); }
+    }
     st->cur_m ^= 1;
     check(hipGetLastError(), "kernel launch");
 }
@@ -366,8 +390,23 @@ void import_state(fvlbm_state *st, const double *f, const double *k, const doubl
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
 }
 
+// Chooses the sweep variant: the tiled kernels unless their LDS would not fit (or the environment
+// variable FVLBM_SWEEP=split asks for the two-kernel path).
+template <typename T>
+void choose_sweep(fvlbm_state *st) {
+    static_assert(kTileCells == kTile, "tile size of the kernels and of the mesh preprocessing differ");
+    st->tile_w = kTile + st->mesh->halo_max;
+    st->lds_bytes = (size_t)16 * st->tile_w * sizeof(T);
+    int dev = 0, max_lds = 0;
+    check(hipGetDevice(&dev), "hipGetDevice");
+    check(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
+    const char *env = std::getenv("FVLBM_SWEEP");
+    st->tiled = st->lds_bytes <= (size_t)max_lds && !(env && std::string(env) == "split");
+}
+
 template <typename T>
 void do_init(fvlbm_state *st, const double *rho, const double *u, const double *k, const double *w) {
+    choose_sweep<T>(st);
     upload_geometry<T>(st);
     const Geo &g = st->geo;
     const int n = g.n, nbk = blocks_for(n);

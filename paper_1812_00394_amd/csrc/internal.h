@@ -19,6 +19,7 @@ struct Error : std::runtime_error {
 void set_last_error(const std::string &msg);
 
 constexpr int kSlots = 4;               // at most four edges per cell (triangles and quads)
+constexpr int kTile = 256;              // cells per tile of the fused stage kernels (one workgroup)
 constexpr double kNoWallDistance = 1e30;
 
 }  // namespace fvlbm
@@ -51,4 +52,11 @@ struct fvlbm_mesh {
     std::vector<int32_t> b_cell, b_group, b_kind;
     std::vector<int64_t> b_user;  // index into the caller's boundary-edge arrays
     std::vector<double> b_nx, b_ny, b_l, b_dperp, b_xfx, b_xfy;
+    // tiles of kTile consecutive internal cells: the halo of tile t (interior neighbours of its
+    // cells that lie outside it, ascending) is halo_cell[halo_ptr[t] .. halo_ptr[t+1]); lnb[s][c]
+    // is the tile-local index of slot s's neighbour: c' - tile start inside the tile, kTile + its
+    // position in the halo outside it (0 for boundary / unused slots)
+    int32_t n_tiles = 0, halo_max = 0;
+    std::vector<int32_t> halo_ptr, halo_cell;
+    std::vector<int16_t> lnb;
 };

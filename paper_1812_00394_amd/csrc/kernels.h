@@ -30,22 +30,22 @@ struct StepPar {
 // Least-squares gradient of the eight moving directions of a stage field.
 // G layout: plane 2(a-1) = d/dx, 2(a-1)+1 = d/dy of direction a, each [n].
 // ----------------------------------------------------------------------------------------------
+// LSQ gradient of the eight moving directions of one cell: gc receives the cell's own values,
+// gx / gy the gradients (index 1..8).  Boundary edges contribute their ghost state.
 template <typename T>
-__global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T *__restrict__ G, T rho0) {
-    const int c = cell_index();
-    if (c >= g.n) return;
+__device__ __forceinline__ void grad_cell(const Geo &g, const T *__restrict__ f, int cell, T rho0, T gc[9], T gx[9],
+                                          T gy[9]) {
     const int n = g.n;
-    T gc[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) gc[a] = f[(size_t)a * n + c];
-    T gx[9], gy[9];
+    for (int a = 0; a < 9; ++a) gc[a] = f[(size_t)a * n + cell];
 #pragma unroll
     for (int a = 0; a < 9; ++a) gx[a] = gy[a] = T(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        const int nb = g.nbr[(size_t)s * n + c];
+        const size_t si = (size_t)s * n + cell;
+        const int nb = g.nbr[si];
         if (nb == -1) continue;
-        const T cxs = T(g.cx[(size_t)s * n + c]), cys = T(g.cy[(size_t)s * n + c]);
+        const T cxs = T(g.cx[si]), cys = T(g.cy[si]);
         if (nb >= 0) {
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T 
         } else {
             T drho, rho, ux, uy, gb[9];
             moments(gc, rho0, drho, rho, ux, uy);
-            ghost(g, -2 - nb, g.nlx[(size_t)s * n + c], g.nly[(size_t)s * n + c], gc, drho, rho, ux, uy, gb);
+            ghost(g, -2 - nb, g.nlx[si], g.nly[si], gc, drho, rho, ux, uy, gb);
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const T d = gb[a] - gc[a];
@@ -65,6 +65,16 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T 
             }
         }
     }
+}
+
+// Gradient planes of a stage field: plane 2(a-1) = d/dx, 2(a-1)+1 = d/dy of direction a, each [n].
+template <typename T>
+__global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T *__restrict__ G, T rho0) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], gx[9], gy[9];
+    grad_cell(g, f, c, rho0, gc, gx, gy);
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
         G[(size_t)(2 * (a - 1)) * n + c] = gx[a];
@@ -72,21 +82,41 @@ __global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T 
     }
 }
 
+// Neighbour access of the convection term: the upwind neighbour's value extrapolated to the edge
+// midpoint, g_N + grad g_N . q.  From the global gradient planes, or from the tile's LDS copy.
+template <typename T>
+struct NbrGlobal {
+    const T *f, *G;
+    int n;
+    __device__ __forceinline__ void slot(int, int) {}
+    __device__ __forceinline__ T recon(int a, int nb, T qx, T qy) const {
+        return f[(size_t)a * n + nb] + G[(size_t)(2 * (a - 1)) * n + nb] * qx + G[(size_t)(2 * (a - 1) + 1) * n + nb] * qy;
+    }
+};
+
+template <typename T>
+struct NbrTile {
+    const T *f;
+    const T *L;            // LDS gradient planes [16][W]
+    const int16_t *lnb;    // tile-local neighbour index per slot
+    int n, W, loc;
+    __device__ __forceinline__ void slot(int s, int c) { loc = lnb[(size_t)s * n + c]; }
+    __device__ __forceinline__ T recon(int a, int nb, T qx, T qy) const {
+        return f[(size_t)a * n + nb] + L[(2 * (a - 1)) * W + loc] * qx + L[(2 * (a - 1) + 1) * W + loc] * qy;
+    }
+};
+
 // Convection term of cell c (Eq. (advection)): -(1/A) sum over edges of (e.n) dl times the face
 // value, the face value being the upwind cell's value extrapolated to the edge midpoint with its
 // LSQ gradient; on walls the ghost state, on open boundaries the ghost state for incoming
 // directions.  gc: the cell's own values; out[0] = 0 (the rest direction does not move).
-template <typename T>
-__device__ __forceinline__ void advect_cell(const Geo &g, const T *__restrict__ f, const T *__restrict__ G, int c,
-                                            T rho0, const T gc[9], T out[9]) {
+template <typename T, typename Nbr>
+__device__ __forceinline__ void advect_cell(const Geo &g, int c, T rho0, const T gc[9], const T gxc[9], const T gyc[9],
+                                            Nbr nbr_acc, T out[9]) {
     const int n = g.n;
-    T gxc[9], gyc[9], acc[9];
+    T acc[9];
 #pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        gxc[a] = G[(size_t)(2 * (a - 1)) * n + c];
-        gyc[a] = G[(size_t)(2 * (a - 1) + 1) * n + c];
-        acc[a] = T(0);
-    }
+    for (int a = 1; a < 9; ++a) acc[a] = T(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const size_t si = (size_t)s * n + c;
@@ -95,16 +125,12 @@ __device__ __forceinline__ void advect_cell(const Geo &g, const T *__restrict__ 
         const double nlx = g.nlx[si], nly = g.nly[si];
         const T rx = T(g.rfx[si]), ry = T(g.rfy[si]);
         if (nb >= 0) {
+            nbr_acc.slot(s, c);
             const T qx = T(g.rfx[si] - g.dx[si]), qy = T(g.rfy[si] - g.dy[si]);
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const double end = ex(a) * nlx + ey(a) * nly;
-                T val;
-                if (end >= 0)
-                    val = gc[a] + gxc[a] * rx + gyc[a] * ry;
-                else
-                    val = f[(size_t)a * n + nb] + G[(size_t)(2 * (a - 1)) * n + nb] * qx +
-                          G[(size_t)(2 * (a - 1) + 1) * n + nb] * qy;
+                const T val = end >= 0 ? gc[a] + gxc[a] * rx + gyc[a] * ry : nbr_acc.recon(a, nb, qx, qy);
                 acc[a] += T(end) * val;
             }
         } else {
@@ -128,6 +154,20 @@ __device__ __forceinline__ void advect_cell(const Geo &g, const T *__restrict__ 
     for (int a = 1; a < 9; ++a) out[a] = -acc[a] * ia;
 }
 
+// Convection term of cell c from the global gradient planes (gc = the cell's own values).
+template <typename T>
+__device__ __forceinline__ void advect_cell_global(const Geo &g, const T *__restrict__ f, const T *__restrict__ G,
+                                                   int c, T rho0, const T gc[9], T out[9]) {
+    const int n = g.n;
+    T gxc[9], gyc[9];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        gxc[a] = G[(size_t)(2 * (a - 1)) * n + c];
+        gyc[a] = G[(size_t)(2 * (a - 1) + 1) * n + c];
+    }
+    advect_cell(g, c, rho0, gc, gxc, gyc, NbrGlobal<T>{f, G, n}, out);
+}
+
 // f^(1) = stage solve of f^n with a = dt/(4 tau).
 template <typename T>
 __global__ void __launch_bounds__(256) k_collide1(int n, const T *__restrict__ F, const T *__restrict__ tau,
@@ -142,18 +182,13 @@ __global__ void __launch_bounds__(256) k_collide1(int n, const T *__restrict__ F
     for (int a = 0; a < 9; ++a) X[(size_t)a * n + c] = f1[a];
 }
 
-// Sweep 1: Ga1 = Gamma^a(f^(1)); f^(2) = solve(f^n + dt/2 Ga1, a = dt/(4 tau)).
+// ---- stage epilogues (cell-local), shared by the two-kernel and the tiled sweeps ----
+// Stage 1 -> 2: f^(2) = solve(f^n + dt/2 Ga1, a = dt/(4 tau)); stores f^(2) and Ga1.
 template <typename T>
-__global__ void __launch_bounds__(256) k_sweep1(Geo g, const T *__restrict__ F, const T *__restrict__ X,
-                                                const T *__restrict__ G, const T *__restrict__ tau,
-                                                T *__restrict__ Y, T *__restrict__ A, StepPar<T> p) {
-    const int c = cell_index();
-    if (c >= g.n) return;
-    const int n = g.n;
-    T gc[9], ga[9], rhs[9], f2[9], fe[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) gc[a] = X[(size_t)a * n + c];
-    advect_cell(g, X, G, c, p.rho0, gc, ga);
+__device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const T *__restrict__ F,
+                                          const T *__restrict__ tau, T *__restrict__ Y, T *__restrict__ A,
+                                          const StepPar<T> &p) {
+    T rhs[9], f2[9], fe[9];
     const T h = p.dt * T(0.5);
 #pragma unroll
     for (int a = 0; a < 9; ++a) rhs[a] = F[(size_t)a * n + c] + h * ga[a];
@@ -165,26 +200,20 @@ __global__ void __launch_bounds__(256) k_sweep1(Geo g, const T *__restrict__ F, 
     }
 }
 
-// Sweep 2: Ga2 = Gamma^a(f^(2)); Gc1, Gc2 recomputed cell-locally; f^(3) = solve(rhs3, dt/(3 tau));
-// A <- Q = f^(3) - dt/6 (Ga1 + Ga2).
+// Stage 2 -> 3: Gc1, Gc2 recomputed cell-locally; f^(3) = solve(rhs3, dt/(3 tau)) with the stage
+// moments of Eq. (sumimeximplicitnew); stores f^(3) and Q = f^(3) - dt/6 (Ga1 + Ga2) (over Ga1).
 template <typename T>
-__global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, const T *__restrict__ Y,
-                                                const T *__restrict__ G, const T *__restrict__ tau,
-                                                T *__restrict__ X, T *__restrict__ A, StepPar<T> p) {
-    const int c = cell_index();
-    if (c >= g.n) return;
-    const int n = g.n;
-    T gc[9], ga[9], fn[9], f1[9], fe1[9], rhs[9], f3[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) gc[a] = Y[(size_t)a * n + c];
-    advect_cell(g, Y, G, c, p.rho0, gc, ga);
+__device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T ga2[9], const T *__restrict__ F,
+                                          const T *__restrict__ tau, T *__restrict__ X, T *__restrict__ A,
+                                          const StepPar<T> &p) {
+    T fn[9], f1[9], fe1[9], rhs[9], f3[9], gsum[9];
     const T tc = tau[c];
     const T itau = T(1) / tc;
 #pragma unroll
     for (int a = 0; a < 9; ++a) fn[a] = F[(size_t)a * n + c];
     stage_collide(fn, p.dt / (T(4) * tc), p.rho0, f1, fe1);      // f^(1), f_eq^(1)
     T drho2, rho2, ux2, uy2;
-    moments(gc, p.rho0, drho2, rho2, ux2, uy2);                  // stage-2 moments
+    moments(f2, p.rho0, drho2, rho2, ux2, uy2);                  // stage-2 moments
     const T h2 = p.dt * T(0.5), h3 = p.dt / T(3);
     // stage-3 moments from f^n and the convection terms (Eq. (sumimeximplicitnew))
     T m0 = 0, mx = 0, my = 0;
@@ -192,10 +221,10 @@ __global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, 
     for (int a = 0; a < 9; ++a) {
         const T a1 = A[(size_t)a * n + c];
         const T gc1 = (fe1[a] - f1[a]) * itau;
-        const T gc2 = (dfeq(a, drho2, rho2, ux2, uy2) - gc[a]) * itau;
-        rhs[a] = fn[a] + h2 * (a1 + ga[a]) + h3 * (gc1 + gc2);
-        ga[a] += a1;                                               // Ga1 + Ga2
-        const T mv = fn[a] + h2 * ga[a];
+        const T gc2 = (dfeq(a, drho2, rho2, ux2, uy2) - f2[a]) * itau;
+        gsum[a] = a1 + ga2[a];                                     // Ga1 + Ga2
+        rhs[a] = fn[a] + h2 * gsum[a] + h3 * (gc1 + gc2);
+        const T mv = fn[a] + h2 * gsum[a];
         m0 += mv;
         mx += T(ex(a)) * mv;
         my += T(ey(a)) * mv;
@@ -206,26 +235,19 @@ __global__ void __launch_bounds__(256) k_sweep2(Geo g, const T *__restrict__ F, 
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         X[(size_t)a * n + c] = f3[a];
-        A[(size_t)a * n + c] = f3[a] - h6 * ga[a];
+        A[(size_t)a * n + c] = f3[a] - h6 * gsum[a];
     }
 }
 
-// Sweep 3: f^{n+1} = Q + dt/3 Gamma^a(f^(3)); macro variables (Step 7): rho - rho0, u.
+// Stage 3 -> n+1: f^{n+1} = Q + dt/3 Ga3; macro variables (Step 7): rho - rho0, u.
 template <typename T>
-__global__ void __launch_bounds__(256) k_sweep3(Geo g, const T *__restrict__ X, const T *__restrict__ G,
-                                                const T *__restrict__ A, T *__restrict__ F, T *__restrict__ M,
-                                                StepPar<T> p) {
-    const int c = cell_index();
-    if (c >= g.n) return;
-    const int n = g.n;
-    T gc[9], ga[9], fnew[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) gc[a] = X[(size_t)a * n + c];
-    advect_cell(g, X, G, c, p.rho0, gc, ga);
+__device__ __forceinline__ void epilogue3(int c, int n, const T ga3[9], const T *__restrict__ A, T *__restrict__ F,
+                                          T *__restrict__ M, const StepPar<T> &p) {
+    T fnew[9];
     const T h3 = p.dt / T(3);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        fnew[a] = A[(size_t)a * n + c] + h3 * ga[a];
+        fnew[a] = A[(size_t)a * n + c] + h3 * ga3[a];
         F[(size_t)a * n + c] = fnew[a];
     }
     T drho, rho, ux, uy;
@@ -233,6 +255,84 @@ __global__ void __launch_bounds__(256) k_sweep3(Geo g, const T *__restrict__ X, 
     M[c] = drho;
     M[(size_t)n + c] = ux;
     M[(size_t)2 * n + c] = uy;
+}
+
+// Buffers of one stage sweep: src = the stage field whose convection term is taken.
+template <typename T>
+struct StageBufs {
+    const T *src, *F_in, *tau;
+    T *A, *out, *F_out, *M;
+};
+
+template <typename T, int J>
+__device__ __forceinline__ void stage_epilogue(int c, int n, const T gc[9], const T ga[9], const StageBufs<T> &b,
+                                               const StepPar<T> &p) {
+    if constexpr (J == 1)
+        epilogue1(c, n, ga, b.F_in, b.tau, b.out, b.A, p);
+    else if constexpr (J == 2)
+        epilogue2(c, n, gc, ga, b.F_in, b.tau, b.out, b.A, p);
+    else
+        epilogue3(c, n, ga, b.A, b.F_out, b.M, p);
+}
+
+// Two-kernel sweep (after k_grad): the convection term of stage J from the global gradient planes.
+//   J=1: src = f^(1), out = f^(2), A = Ga1
+//   J=2: src = f^(2), out = f^(3), A: Ga1 -> Q
+//   J=3: src = f^(3), A = Q, F_out = f^{n+1}, M = macro variables
+template <typename T, int J>
+__global__ void __launch_bounds__(256) k_sweep(Geo g, const T *__restrict__ G, StageBufs<T> b, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], ga[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
+    advect_cell_global(g, b.src, G, c, p.rho0, gc, ga);
+    stage_epilogue<T, J>(c, n, gc, ga, b, p);
+}
+
+// Tiled sweep: one workgroup per tile of kTileCells consecutive cells.  Phase 1 computes the LSQ
+// gradients of the tile's cells (kept in registers and LDS) and of its halo (LDS); phase 2 takes
+// the convection term with every upwind neighbour's gradient from LDS and runs the epilogue.  The
+// gradient planes never travel through HBM.
+constexpr int kTileCells = 256;
+
+template <typename T, int J>
+__global__ void __launch_bounds__(kTileCells) k_stage_tiled(Geo g, const int32_t *__restrict__ hptr,
+                                                           const int32_t *__restrict__ hcell,
+                                                           const int16_t *__restrict__ lnb, int W, StageBufs<T> b,
+                                                           StepPar<T> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *L = reinterpret_cast<T *>(smem);
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int start = tile * kTileCells;
+    const int ncell = min(kTileCells, g.n - start);
+    const int h0 = hptr[tile], hcnt = hptr[tile + 1] - h0;
+    const int t = threadIdx.x;
+    T gc[9], gx[9], gy[9];
+    if (t < ncell) {
+        grad_cell(g, b.src, start + t, p.rho0, gc, gx, gy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            L[(2 * (a - 1)) * W + t] = gx[a];
+            L[(2 * (a - 1) + 1) * W + t] = gy[a];
+        }
+    }
+    for (int w = t; w < hcnt; w += kTileCells) {
+        T hc[9], hx[9], hy[9];
+        grad_cell(g, b.src, hcell[h0 + w], p.rho0, hc, hx, hy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            L[(2 * (a - 1)) * W + kTileCells + w] = hx[a];
+            L[(2 * (a - 1) + 1) * W + kTileCells + w] = hy[a];
+        }
+    }
+    __syncthreads();
+    if (t >= ncell) return;
+    const int c = start + t;
+    T ga[9];
+    advect_cell(g, c, p.rho0, gc, gx, gy, NbrTile<T>{b.src, L, lnb, g.n, W, 0}, ga);
+    stage_epilogue<T, J>(c, g.n, gc, ga, b, p);
 }
 
 // Convection term alone (diagnostic entry point).
@@ -245,7 +345,7 @@ __global__ void __launch_bounds__(256) k_advect(Geo g, const T *__restrict__ X, 
     T gc[9], ga[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) gc[a] = X[(size_t)a * n + c];
-    advect_cell(g, X, G, c, rho0, gc, ga);
+    advect_cell_global(g, X, G, c, rho0, gc, ga);
 #pragma unroll
     for (int a = 0; a < 9; ++a) out[(size_t)a * n + c] = ga[a];
 }

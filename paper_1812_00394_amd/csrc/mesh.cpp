@@ -419,6 +419,37 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
         }
     }
 
+    // ---- tiles and halos for the fused stage kernels ----
+    m->n_tiles = (int32_t)((N + kTile - 1) / kTile);
+    m->halo_ptr.assign(m->n_tiles + 1, 0);
+    m->lnb.assign(kSlots * N, 0);
+    for (int32_t t = 0; t < m->n_tiles; ++t) {
+        const int64_t lo = (int64_t)t * kTile, hi = std::min<int64_t>(N, lo + kTile);
+        std::vector<int32_t> halo;
+        for (int64_t c = lo; c < hi; ++c)
+            for (int s = 0; s < kSlots; ++s) {
+                const int32_t nb = m->nbr[s * N + c];
+                if (nb >= 0 && (nb < lo || nb >= hi)) halo.push_back(nb);
+            }
+        std::sort(halo.begin(), halo.end());
+        halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
+        for (int64_t c = lo; c < hi; ++c)
+            for (int s = 0; s < kSlots; ++s) {
+                const int32_t nb = m->nbr[s * N + c];
+                if (nb < 0) continue;
+                int64_t local;
+                if (nb >= lo && nb < hi)
+                    local = nb - lo;
+                else
+                    local = kTile + (std::lower_bound(halo.begin(), halo.end(), nb) - halo.begin());
+                if (local > 32767) throw Error(FVLBM_EMESH, "mesh_create: tile halo too large");
+                m->lnb[s * N + c] = (int16_t)local;
+            }
+        m->halo_ptr[t + 1] = m->halo_ptr[t] + (int32_t)halo.size();
+        m->halo_max = std::max<int32_t>(m->halo_max, (int32_t)halo.size());
+        m->halo_cell.insert(m->halo_cell.end(), halo.begin(), halo.end());
+    }
+
     // ---- wall distance: exact nearest point over WALL / MOVING_WALL edges ----
     m->wdist.assign(N, kNoWallDistance);
     Bvh bvh;

@@ -82,9 +82,12 @@ def test_advection_operator_parity(F, name):
     assert rel(got, ref, np.abs(ref).max()) < 1e-12
 
 
+@pytest.mark.parametrize("sweep", ["tiled", "split"])
 @pytest.mark.parametrize("name", sorted(MESHES))
-def test_laminar_step_parity(F, name):
-    say("laminar step", name)
+def test_laminar_step_parity(F, name, sweep, monkeypatch):
+    """Both sweep variants: the tiled kernels (gradients in LDS) and the two-kernel path."""
+    say("laminar step", name, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = MESHES[name]
     m = make()
     dt = courant_dt(m)
