@@ -91,27 +91,32 @@ def make_state(F, M, flow, init, precision, dt_frac):
 
 
 # Algorithmic (compulsory) bytes per cell of one launch of each kernel: every array the kernel
-# must read or write counted once (neighbour gathers counted once), T = bytes per stored value,
-# S = mean edges per cell; FP64 geometry: nl, rf, d = 48 B per edge, LSQ coefficients 16 B per
-# edge, neighbour ids 4 x 4 B, 1/A and wall distance 8 B each.
-def kernel_bytes(T, S):
-    geo_flux = 16 + 48 * S + 8
+# must read or write counted once (neighbour gathers counted once).  T = bytes per value of the
+# state's arithmetic type (4 FP32-deviation, 8 FP64), which is also the type of the per-edge
+# geometry the sweeps stream (nl, rf, q, c: 8 values per edge); S = mean edges per cell; neighbour
+# ids 4 x 4 B, tile-local ids 4 x 2 B, 1/A one value, wall distance 8 B (FP64).
+def kernel_bytes(T, S, tiled=True):
+    edge = 8 * T * S
+    geo = 16 + 8 + edge + T if tiled else 16 + edge + T
+    extra = 0 if tiled else 16 * T            # split path: the gradient planes are read back
     return {
-        "sst_a": 15 * T + 16 + 16 * S + 8,
-        "sst_b": 19 * T + geo_flux + 8,
+        "sst_a": 15 * T + 16 + 2 * T * S + 8,
+        "sst_b": 19 * T + 16 + 6 * T * S + T + 8,
         "collide1": 19 * T,
-        "grad": 25 * T + 16 + 16 * S,
-        "sweep1": 53 * T + geo_flux,
-        "sweep2": 62 * T + geo_flux,
-        "sweep3": 46 * T + geo_flux,
+        "grad": 25 * T + 16 + 2 * T * S,
+        "sweep1": 37 * T + geo + extra,
+        "sweep2": 46 * T + geo + extra,
+        "sweep3": 30 * T + geo + extra,
     }
 
 
 # Compulsory bytes per cell of a whole step for the method itself (independent of how it is split
-# into kernels): f-state traffic of the three stage sweeps (81 words), the SST coupling (14 words),
-# and the FP64 geometry of four sweeps (144 B each on triangles) plus the wall distance.
+# into kernels): f-state traffic of the three stage sweeps (81 values), the SST coupling (14
+# values), and the mesh data of four sweeps (3 LBM + 1 SST) held in the same type: area, centroid,
+# LSQ coefficients (2 per edge), shared edge normals and midpoints (S/2 edges x 4 values), neighbour
+# and edge ids (4 B each per edge); plus the FP64 wall distance.
 def step_bytes(T, S):
-    geo = 8 + 16 + 4 * S + 16 * S + 4 * S + S / 2 * 32   # area, centroid, nbr, LSQ, face ids, shared faces
+    geo = T * (1 + 2 + 2 * S + S / 2 * 4) + 4 * S + 4 * S
     return (81 + 14) * T + 4 * geo + 8
 
 
@@ -234,7 +239,7 @@ def main():
         raise SystemExit("non-finite state after the timed steps")
 
     T = 4 if args.precision == "fp32dev" else 8
-    kb = kernel_bytes(T, S)
+    kb = kernel_bytes(T, S, tiled=os.environ.get("FVLBM_SWEEP", "tiled") != "split")
     per_kernel = {}
     for name, (tms, cnt) in kt.items():
         if cnt:

@@ -58,7 +58,9 @@ struct fvlbm_state {
     int sst = 0;
     fvlbm_params par{};
     hipStream_t stream = nullptr;
-    Geo geo{};
+    Geo<double> geo64{};
+    Geo<float> geo32{};
+    int32_t n_cells = 0;
     int32_t *bzg = nullptr;
     void *F = nullptr, *X = nullptr, *Y = nullptr, *A = nullptr, *G = nullptr;
     void *M[2] = {nullptr, nullptr};
@@ -92,24 +94,32 @@ struct fvlbm_state {
 
 namespace {
 
+template <typename T>
+Geo<T> &geo_of(fvlbm_state *st);
+template <>
+Geo<double> &geo_of<double>(fvlbm_state *st) { return st->geo64; }
+template <>
+Geo<float> &geo_of<float>(fvlbm_state *st) { return st->geo32; }
+
 // Layout of the workspace.  Geometry arrays are written by fvlbm_init; the rest is state.
 template <typename T>
 void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
     const size_t n = (size_t)m->n, nb = m->b_cell.size(), S = kSlots * n;
-    Geo &g = st->geo;
+    Geo<T> &g = geo_of<T>(st);
+    st->n_cells = (int32_t)n;
     g.n = (int32_t)n;
     g.nb = (int32_t)nb;
     g.nbr = cv.take<int32_t>(S);
-    g.nlx = cv.take<double>(S);
-    g.nly = cv.take<double>(S);
-    g.rfx = cv.take<double>(S);
-    g.rfy = cv.take<double>(S);
-    g.dx = cv.take<double>(S);
-    g.dy = cv.take<double>(S);
-    g.cx = cv.take<double>(S);
-    g.cy = cv.take<double>(S);
+    g.nlx = cv.take<T>(S);
+    g.nly = cv.take<T>(S);
+    g.rfx = cv.take<T>(S);
+    g.rfy = cv.take<T>(S);
+    g.qx = cv.take<T>(S);
+    g.qy = cv.take<T>(S);
+    g.cx = cv.take<T>(S);
+    g.cy = cv.take<T>(S);
     g.area = cv.take<double>(n);
-    g.inv_area = cv.take<double>(n);
+    g.inv_area = cv.take<T>(n);
     g.wdist = cv.take<double>(n);
     g.perm = cv.take<int32_t>(n);
     g.b_kind = cv.take<int32_t>(nb);
@@ -235,20 +245,28 @@ template <typename T>
 void upload_geometry(fvlbm_state *st) {
     const fvlbm_mesh *m = st->mesh;
     hipStream_t s = st->stream;
-    Geo &g = st->geo;
-    h2d(const_cast<int32_t *>(g.nbr), m->nbr, s);
-    h2d(const_cast<double *>(g.nlx), m->nlx, s);
-    h2d(const_cast<double *>(g.nly), m->nly, s);
-    h2d(const_cast<double *>(g.rfx), m->rfx, s);
-    h2d(const_cast<double *>(g.rfy), m->rfy, s);
-    h2d(const_cast<double *>(g.dx), m->dx, s);
-    h2d(const_cast<double *>(g.dy), m->dy, s);
-    h2d(const_cast<double *>(g.cx), m->cx, s);
-    h2d(const_cast<double *>(g.cy), m->cy, s);
-    h2d(const_cast<double *>(g.area), m->area, s);
-    std::vector<double> ia(m->n);
+    Geo<T> &g = geo_of<T>(st);
+    // per-edge working copies in the state's arithmetic type, converted from the FP64 masters
+    auto as_t = [](const std::vector<double> &v) { return std::vector<T>(v.begin(), v.end()); };
+    std::vector<double> qx(m->rfx.size()), qy(m->rfy.size()), ia(m->n);
+    for (size_t i = 0; i < qx.size(); ++i) {
+        qx[i] = m->rfx[i] - m->dx[i];
+        qy[i] = m->rfy[i] - m->dy[i];
+    }
     for (int64_t i = 0; i < m->n; ++i) ia[i] = 1.0 / m->area[i];
-    h2d(const_cast<double *>(g.inv_area), ia, s);
+    std::vector<std::vector<T>> conv = {as_t(m->nlx), as_t(m->nly), as_t(m->rfx), as_t(m->rfy), as_t(qx),
+                                        as_t(qy),      as_t(m->cx),  as_t(m->cy),  as_t(ia)};
+    h2d(const_cast<int32_t *>(g.nbr), m->nbr, s);
+    h2d(const_cast<T *>(g.nlx), conv[0], s);
+    h2d(const_cast<T *>(g.nly), conv[1], s);
+    h2d(const_cast<T *>(g.rfx), conv[2], s);
+    h2d(const_cast<T *>(g.rfy), conv[3], s);
+    h2d(const_cast<T *>(g.qx), conv[4], s);
+    h2d(const_cast<T *>(g.qy), conv[5], s);
+    h2d(const_cast<T *>(g.cx), conv[6], s);
+    h2d(const_cast<T *>(g.cy), conv[7], s);
+    h2d(const_cast<T *>(g.inv_area), conv[8], s);
+    h2d(const_cast<double *>(g.area), m->area, s);
     h2d(const_cast<double *>(g.wdist), m->wdist, s);
     std::vector<int32_t> perm(m->n);
     for (int64_t i = 0; i < m->n; ++i) perm[i] = (int32_t)m->perm[i];
@@ -317,7 +335,7 @@ void drain_events(fvlbm_state *st) {
 
 template <typename T>
 void launch_step(fvlbm_state *st) {
-    const Geo &g = st->geo;
+    const Geo<T> &g = geo_of<T>(st);
     const int n = g.n;
     const int nbk = blocks_for(n);
     hipStream_t s = st->stream;
@@ -356,7 +374,7 @@ void launch_step(fvlbm_state *st) {
 
 template <typename T>
 double residual(fvlbm_state *st) {
-    const int n = st->geo.n;
+    const int n = st->n_cells;
     k_residual<T><<<kRedBlocks, kBlock, 0, st->stream>>>(n, (T *)st->M[st->cur_m], (T *)st->M[st->cur_m ^ 1], st->partial);
     k_finish<2><<<1, kBlock, 0, st->stream>>>(st->partial, kRedBlocks, st->result);
     double r[2];
@@ -367,7 +385,7 @@ double residual(fvlbm_state *st) {
 
 template <typename T>
 void import_state(fvlbm_state *st, const double *f, const double *k, const double *w) {
-    const Geo &g = st->geo;
+    const Geo<T> &g = geo_of<T>(st);
     const int nbk = blocks_for(g.n);
     if (f) {
         upload_scratch(st, f, 9 * (size_t)g.n);
@@ -408,7 +426,7 @@ template <typename T>
 void do_init(fvlbm_state *st, const double *rho, const double *u, const double *k, const double *w) {
     choose_sweep<T>(st);
     upload_geometry<T>(st);
-    const Geo &g = st->geo;
+    const Geo<T> &g = geo_of<T>(st);
     const int n = g.n, nbk = blocks_for(n);
     // rho and u staged in the scratch area: rho [n] then u [n][2]
     check(hipMemcpyAsync(st->scratch, rho, n * sizeof(double), hipMemcpyHostToDevice, st->stream), "hipMemcpyAsync H2D");
@@ -425,7 +443,7 @@ void do_init(fvlbm_state *st, const double *rho, const double *u, const double *
 
 template <typename T>
 void export_moments(fvlbm_state *st, int on_device, double *rho, double *u, double *k, double *w, double *nut) {
-    const Geo &g = st->geo;
+    const Geo<T> &g = geo_of<T>(st);
     const int n = g.n, nbk = blocks_for(n);
     hipStream_t s = st->stream;
     const T *M = (const T *)st->M[st->cur_m];
@@ -448,7 +466,7 @@ void export_moments(fvlbm_state *st, int on_device, double *rho, double *u, doub
 
 template <typename T>
 void totals(fvlbm_state *st, double out[3]) {
-    k_totals<T><<<kRedBlocks, kBlock, 0, st->stream>>>(st->geo, (const T *)st->M[st->cur_m], st->par.rho0, st->partial);
+    k_totals<T><<<kRedBlocks, kBlock, 0, st->stream>>>(geo_of<T>(st), (const T *)st->M[st->cur_m], st->par.rho0, st->partial);
     k_finish<3><<<1, kBlock, 0, st->stream>>>(st->partial, kRedBlocks, st->result);
     check(hipMemcpyAsync(out, st->result, 3 * sizeof(double), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
@@ -456,7 +474,7 @@ void totals(fvlbm_state *st, double out[3]) {
 
 template <typename T>
 void forces(fvlbm_state *st, uint64_t mask, double out[3]) {
-    k_forces<T><<<kRedBlocks, kBlock, 0, st->stream>>>(st->geo, (const T *)st->M[st->cur_m], st->par.rho0, st->par.nu,
+    k_forces<T><<<kRedBlocks, kBlock, 0, st->stream>>>(geo_of<T>(st), (const T *)st->M[st->cur_m], st->par.rho0, st->par.nu,
                                                          (unsigned long long)mask, st->par.jr_group, st->par.jr_xmin,
                                                          st->par.eps_tau, st->partial);
     k_finish<3><<<1, kBlock, 0, st->stream>>>(st->partial, kRedBlocks, st->result);
@@ -466,7 +484,7 @@ void forces(fvlbm_state *st, uint64_t mask, double out[3]) {
 
 template <typename T>
 void apply_advection(fvlbm_state *st, const double *gin, double *out) {
-    const Geo &g = st->geo;
+    const Geo<T> &g = geo_of<T>(st);
     const int n = g.n, nbk = blocks_for(n);
     hipStream_t s = st->stream;
     upload_scratch(st, gin, 9 * (size_t)n);
@@ -647,16 +665,15 @@ fvlbm_status fvlbm_moments(fvlbm_state *st, int32_t on_device, double *rho, doub
 fvlbm_status fvlbm_get_f(fvlbm_state *st, int32_t on_device, double *f) {
     return guarded([&] {
         if (!st || !f) throw Error(FVLBM_EINVAL, "get_f: NULL argument");
-        const Geo &g = st->geo;
-        const int nbk = blocks_for(g.n);
+        const int nbk = blocks_for(st->n_cells);
         double *target = on_device ? f : st->scratch;
         if (st->precision == FVLBM_FP64)
-            k_export_f<double><<<nbk, kBlock, 0, st->stream>>>(g, (const double *)st->F, target, st->par.rho0);
+            k_export_f<double><<<nbk, kBlock, 0, st->stream>>>(st->geo64, (const double *)st->F, target, st->par.rho0);
         else
-            k_export_f<float><<<nbk, kBlock, 0, st->stream>>>(g, (const float *)st->F, target, st->par.rho0);
+            k_export_f<float><<<nbk, kBlock, 0, st->stream>>>(st->geo32, (const float *)st->F, target, st->par.rho0);
         check(hipGetLastError(), "kernel launch");
         if (!on_device) {
-            check(hipMemcpyAsync(f, st->scratch, 9 * (size_t)g.n * sizeof(double), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
+            check(hipMemcpyAsync(f, st->scratch, 9 * (size_t)st->n_cells * sizeof(double), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
             check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
         }
     });

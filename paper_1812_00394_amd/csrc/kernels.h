@@ -33,7 +33,7 @@ struct StepPar {
 // LSQ gradient of the eight moving directions of one cell: gc receives the cell's own values,
 // gx / gy the gradients (index 1..8).  Boundary edges contribute their ghost state.
 template <typename T>
-__device__ __forceinline__ void grad_cell(const Geo &g, const T *__restrict__ f, int cell, T rho0, T gc[9], T gx[9],
+__device__ __forceinline__ void grad_cell(const Geo<T> &g, const T *__restrict__ f, int cell, T rho0, T gc[9], T gx[9],
                                           T gy[9]) {
     const int n = g.n;
 #pragma unroll
@@ -45,7 +45,7 @@ __device__ __forceinline__ void grad_cell(const Geo &g, const T *__restrict__ f,
         const size_t si = (size_t)s * n + cell;
         const int nb = g.nbr[si];
         if (nb == -1) continue;
-        const T cxs = T(g.cx[si]), cys = T(g.cy[si]);
+        const T cxs = g.cx[si], cys = g.cy[si];
         if (nb >= 0) {
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
@@ -69,7 +69,7 @@ __device__ __forceinline__ void grad_cell(const Geo &g, const T *__restrict__ f,
 
 // Gradient planes of a stage field: plane 2(a-1) = d/dx, 2(a-1)+1 = d/dy of direction a, each [n].
 template <typename T>
-__global__ void __launch_bounds__(256) k_grad(Geo g, const T *__restrict__ f, T *__restrict__ G, T rho0) {
+__global__ void __launch_bounds__(256) k_grad(Geo<T> g, const T *__restrict__ f, T *__restrict__ G, T rho0) {
     const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
@@ -111,7 +111,7 @@ struct NbrTile {
 // LSQ gradient; on walls the ghost state, on open boundaries the ghost state for incoming
 // directions.  gc: the cell's own values; out[0] = 0 (the rest direction does not move).
 template <typename T, typename Nbr>
-__device__ __forceinline__ void advect_cell(const Geo &g, int c, T rho0, const T gc[9], const T gxc[9], const T gyc[9],
+__device__ __forceinline__ void advect_cell(const Geo<T> &g, int c, T rho0, const T gc[9], const T gxc[9], const T gyc[9],
                                             Nbr nbr_acc, T out[9]) {
     const int n = g.n;
     T acc[9];
@@ -122,16 +122,16 @@ __device__ __forceinline__ void advect_cell(const Geo &g, int c, T rho0, const T
         const size_t si = (size_t)s * n + c;
         const int nb = g.nbr[si];
         if (nb == -1) continue;
-        const double nlx = g.nlx[si], nly = g.nly[si];
-        const T rx = T(g.rfx[si]), ry = T(g.rfy[si]);
+        const T nlx = g.nlx[si], nly = g.nly[si];
+        const T rx = g.rfx[si], ry = g.rfy[si];
         if (nb >= 0) {
             nbr_acc.slot(s, c);
-            const T qx = T(g.rfx[si] - g.dx[si]), qy = T(g.rfy[si] - g.dy[si]);
+            const T qx = g.qx[si], qy = g.qy[si];
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
-                const double end = ex(a) * nlx + ey(a) * nly;
-                const T val = end >= 0 ? gc[a] + gxc[a] * rx + gyc[a] * ry : nbr_acc.recon(a, nb, qx, qy);
-                acc[a] += T(end) * val;
+                const T end = T(ex(a)) * nlx + T(ey(a)) * nly;
+                const T val = end >= T(0) ? gc[a] + gxc[a] * rx + gyc[a] * ry : nbr_acc.recon(a, nb, qx, qy);
+                acc[a] += end * val;
             }
         } else {
             const int b = -2 - nb;
@@ -142,13 +142,13 @@ __device__ __forceinline__ void advect_cell(const Geo &g, int c, T rho0, const T
             const bool wall = (kind == kWall || kind == kMovingWall);
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
-                const double end = ex(a) * nlx + ey(a) * nly;
-                const T val = (wall || end < 0) ? gb[a] : gc[a] + gxc[a] * rx + gyc[a] * ry;
-                acc[a] += T(end) * val;
+                const T end = T(ex(a)) * nlx + T(ey(a)) * nly;
+                const T val = (wall || end < T(0)) ? gb[a] : gc[a] + gxc[a] * rx + gyc[a] * ry;
+                acc[a] += end * val;
             }
         }
     }
-    const T ia = T(g.inv_area[c]);
+    const T ia = g.inv_area[c];
     out[0] = T(0);
 #pragma unroll
     for (int a = 1; a < 9; ++a) out[a] = -acc[a] * ia;
@@ -156,7 +156,7 @@ __device__ __forceinline__ void advect_cell(const Geo &g, int c, T rho0, const T
 
 // Convection term of cell c from the global gradient planes (gc = the cell's own values).
 template <typename T>
-__device__ __forceinline__ void advect_cell_global(const Geo &g, const T *__restrict__ f, const T *__restrict__ G,
+__device__ __forceinline__ void advect_cell_global(const Geo<T> &g, const T *__restrict__ f, const T *__restrict__ G,
                                                    int c, T rho0, const T gc[9], T out[9]) {
     const int n = g.n;
     T gxc[9], gyc[9];
@@ -280,7 +280,7 @@ __device__ __forceinline__ void stage_epilogue(int c, int n, const T gc[9], cons
 //   J=2: src = f^(2), out = f^(3), A: Ga1 -> Q
 //   J=3: src = f^(3), A = Q, F_out = f^{n+1}, M = macro variables
 template <typename T, int J>
-__global__ void __launch_bounds__(256) k_sweep(Geo g, const T *__restrict__ G, StageBufs<T> b, StepPar<T> p) {
+__global__ void __launch_bounds__(256) k_sweep(Geo<T> g, const T *__restrict__ G, StageBufs<T> b, StepPar<T> p) {
     const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo g, const T *__restrict__ G, S
 constexpr int kTileCells = 256;
 
 template <typename T, int J>
-__global__ void __launch_bounds__(kTileCells) k_stage_tiled(Geo g, const int32_t *__restrict__ hptr,
+__global__ void __launch_bounds__(kTileCells) k_stage_tiled(Geo<T> g, const int32_t *__restrict__ hptr,
                                                            const int32_t *__restrict__ hcell,
                                                            const int16_t *__restrict__ lnb, int W, StageBufs<T> b,
                                                            StepPar<T> p) {
@@ -337,7 +337,7 @@ __global__ void __launch_bounds__(kTileCells) k_stage_tiled(Geo g, const int32_t
 
 // Convection term alone (diagnostic entry point).
 template <typename T>
-__global__ void __launch_bounds__(256) k_advect(Geo g, const T *__restrict__ X, const T *__restrict__ G,
+__global__ void __launch_bounds__(256) k_advect(Geo<T> g, const T *__restrict__ X, const T *__restrict__ G,
                                                 T *__restrict__ out, T rho0) {
     const int c = cell_index();
     if (c >= g.n) return;
@@ -367,7 +367,7 @@ template <typename T>
 __device__ __forceinline__ T bound_face(T v, T up) { return tmin(tmax(v, T(0)), T(2) * up); }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_sst_a(Geo g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
+__global__ void __launch_bounds__(256) k_sst_a(Geo<T> g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
                                                const T *__restrict__ K, const T *__restrict__ W,
                                                T *__restrict__ aux, StepPar<T> p) {
     const int c = cell_index();
@@ -381,7 +381,7 @@ __global__ void __launch_bounds__(256) k_sst_a(Geo g, const int32_t *__restrict_
         const size_t si = (size_t)s * n + c;
         const int nb = g.nbr[si];
         if (nb == -1) continue;
-        const T cxs = T(g.cx[si]), cys = T(g.cy[si]);
+        const T cxs = g.cx[si], cys = g.cy[si];
         T du, dv, dk, dw;
         if (nb >= 0) {
             du = M[(size_t)n + nb] - ux;
@@ -443,7 +443,7 @@ __global__ void __launch_bounds__(256) k_sst_a(Geo g, const int32_t *__restrict_
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
+__global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
                                                const T *__restrict__ K, const T *__restrict__ W,
                                                const T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
                                                T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
@@ -461,8 +461,8 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
         const size_t si = (size_t)s * n + c;
         const int nb = g.nbr[si];
         if (nb == -1) continue;
-        const T nlx = T(g.nlx[si]), nly = T(g.nly[si]);
-        const T rx = T(g.rfx[si]), ry = T(g.rfy[si]);
+        const T nlx = g.nlx[si], nly = g.nly[si];
+        const T rx = g.rfx[si], ry = g.rfy[si];
         // own value extrapolated to the edge, kept in [0, 2 phi_c] so the explicit outflow
         // cannot drive k or omega negative (inactive where |grad phi . r| <= phi_c)
         const T ks = bound_face(kc + gkc[0] * rx + gkc[1] * ry, kc);
@@ -478,11 +478,11 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
                 kf = ks;
                 wf = ws;
             } else {
-                const T qx = T(g.rfx[si] - g.dx[si]), qy = T(g.rfy[si] - g.dy[si]);
+                const T qx = g.qx[si], qy = g.qy[si];
                 kf = bound_face(kN + gkN[0] * qx + gkN[1] * qy, kN);
                 wf = bound_face(wN + gwN[0] * qx + gwN[1] * qy, wN);
             }
-            const T ddx = T(g.dx[si]), ddy = T(g.dy[si]);
+            const T ddx = rx - g.qx[si], ddy = ry - g.qy[si];   // x_N' - x_c
             const T dist = sqrt(ddx * ddx + ddy * ddy);
             const T hx = ddx / dist, hy = ddy / dist;
             const T GkN = aux[(size_t)4 * n + nb], GwN = aux[(size_t)5 * n + nb];
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo g, const int32_t *__restrict_
             net_w += -mdot * wf + dw;
         }
     }
-    const T fac = p.dt * T(g.inv_area[c]) / rho;
+    const T fac = p.dt * g.inv_area[c] / rho;
     // point-implicit update; the negative part of each explicit source joins the denominator
     const T sk = aux[(size_t)6 * n + c], sw = aux[(size_t)7 * n + c];
     T k1 = (kc + fac * net_k + tmax(sk, T(0))) / (T(1) + p.dt * p.bstar * wc + tmax(-sk, T(0)) / kc);
@@ -577,7 +577,7 @@ __global__ void __launch_bounds__(256) k_residual(int n, const T *__restrict__ M
 
 // sum A rho, sum A rho u
 template <typename T>
-__global__ void __launch_bounds__(256) k_totals(Geo g, const T *__restrict__ M, double rho0, double *__restrict__ partial) {
+__global__ void __launch_bounds__(256) k_totals(Geo<T> g, const T *__restrict__ M, double rho0, double *__restrict__ partial) {
     double v[3] = {0, 0, 0};
     const int n = g.n;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
@@ -592,7 +592,7 @@ __global__ void __launch_bounds__(256) k_totals(Geo g, const T *__restrict__ M, 
 
 // force on selected wall edges and the smooth reversed-flow length
 template <typename T>
-__global__ void __launch_bounds__(256) k_forces(Geo g, const T *__restrict__ M, double rho0, double nu,
+__global__ void __launch_bounds__(256) k_forces(Geo<T> g, const T *__restrict__ M, double rho0, double nu,
                                                 unsigned long long mask, int jr_group, double jr_xmin, double eps,
                                                 double *__restrict__ partial) {
     double v[3] = {0, 0, 0};
@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(256) k_forces(Geo g, const T *__restrict__ M, 
 // Import / export between the caller's FP64 user-order arrays and the internal state.
 // ----------------------------------------------------------------------------------------------
 template <typename T>
-__global__ void k_import_f(Geo g, const double *__restrict__ fu, T *__restrict__ F, double rho0) {
+__global__ void k_import_f(Geo<T> g, const double *__restrict__ fu, T *__restrict__ F, double rho0) {
     const int c = cell_index();
     if (c >= g.n) return;
     const int u = g.perm[c];
@@ -631,7 +631,7 @@ __global__ void k_import_f(Geo g, const double *__restrict__ fu, T *__restrict__
 }
 
 template <typename T>
-__global__ void k_export_f(Geo g, const T *__restrict__ F, double *__restrict__ fu, double rho0) {
+__global__ void k_export_f(Geo<T> g, const T *__restrict__ F, double *__restrict__ fu, double rho0) {
     const int c = cell_index();
     if (c >= g.n) return;
     const int u = g.perm[c];
@@ -641,7 +641,7 @@ __global__ void k_export_f(Geo g, const T *__restrict__ F, double *__restrict__ 
 
 // f = f_eq(rho, u) (Step 0), from user-order rho [n], u [n][2]
 template <typename T>
-__global__ void k_init_feq(Geo g, const double *__restrict__ rho_u, const double *__restrict__ vel_u,
+__global__ void k_init_feq(Geo<T> g, const double *__restrict__ rho_u, const double *__restrict__ vel_u,
                            T *__restrict__ F, double rho0) {
     const int c = cell_index();
     if (c >= g.n) return;
@@ -652,21 +652,21 @@ __global__ void k_init_feq(Geo g, const double *__restrict__ rho_u, const double
 }
 
 template <typename T>
-__global__ void k_import_scalar(Geo g, const double *__restrict__ su, T *__restrict__ S) {
+__global__ void k_import_scalar(Geo<T> g, const double *__restrict__ su, T *__restrict__ S) {
     const int c = cell_index();
     if (c >= g.n) return;
     S[c] = T(su[g.perm[c]]);
 }
 
 template <typename T>
-__global__ void k_export_scalar(Geo g, const T *__restrict__ S, double add, double *__restrict__ su) {
+__global__ void k_export_scalar(Geo<T> g, const T *__restrict__ S, double add, double *__restrict__ su) {
     const int c = cell_index();
     if (c >= g.n) return;
     su[g.perm[c]] = (double)S[c] + add;
 }
 
 template <typename T>
-__global__ void k_export_vel(Geo g, const T *__restrict__ M, double *__restrict__ vu) {
+__global__ void k_export_vel(Geo<T> g, const T *__restrict__ M, double *__restrict__ vu) {
     const int c = cell_index();
     if (c >= g.n) return;
     const int u = g.perm[c];

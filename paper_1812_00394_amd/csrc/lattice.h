@@ -31,13 +31,18 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
 
 __device__ __forceinline__ int cell_index() { return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; }
 
-// Geometry and boundary data on the device (pointers into the caller's workspace).
+// Geometry and boundary data on the device (pointers into the caller's workspace).  The per-edge
+// arrays a sweep streams are held in the arithmetic type T of the state (FP64 masters of every
+// quantity stay on the host and in the FP64 fields below): nl = outward normal x length,
+// rf = x_f - x_c, q = x_f - x_N' (from the neighbour's centroid image), c = LSQ coefficients.
+template <typename T>
 struct Geo {
     int32_t n;    // cells
     int32_t nb;   // boundary edges
     const int32_t *nbr;                                              // [4][n]
-    const double *nlx, *nly, *rfx, *rfy, *dx, *dy, *cx, *cy;         // [4][n]
-    const double *area, *inv_area, *wdist;                           // [n]
+    const T *nlx, *nly, *rfx, *rfy, *qx, *qy, *cx, *cy;              // [4][n]
+    const T *inv_area;                                               // [n]
+    const double *area, *wdist;                                      // [n]
     const int32_t *perm;                                             // [n] internal -> user
     const int32_t *b_kind, *b_cell;                                  // [nb]
     const double *b_nx, *b_ny, *b_l, *b_dperp, *b_xfx;               // [nb]
@@ -101,14 +106,14 @@ enum : int32_t { kWall = 1, kMovingWall = 2, kInlet = 3, kOutlet = 4, kFarfield 
 //   walls: f_eq(rho_c, u_w) + (g_c - f_eq(rho_c, u_c)) for every direction;
 //   inlet / outlet / far field: replaced for incoming directions (e.n < 0) only.
 template <typename T>
-__device__ __forceinline__ void ghost(const Geo &g, int b, double nlx, double nly, const T gc[9], T drho, T rho,
-                                      T ux, T uy, T gb[9]) {
+__device__ __forceinline__ void ghost(const Geo<T> &g, int b, T nlx, T nly, const T gc[9], T drho, T rho, T ux,
+                                      T uy, T gb[9]) {
     const int kind = g.b_kind[b];
     const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]);
     const T rb = T(g.b_rho[b]), drb = T(g.b_drho[b]);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const double en = ex(a) * nlx + ey(a) * nly;
+        const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
         const T neq = gc[a] - dfeq(a, drho, rho, ux, uy);
         T v;
         if (kind == kWall || kind == kMovingWall) {
