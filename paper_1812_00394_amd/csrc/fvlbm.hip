@@ -68,7 +68,7 @@ struct fvlbm_state {
     void *tau = nullptr, *nut = nullptr, *aux = nullptr;
     int cur_m = 0, cur_kw = 0;
     // tiles of the fused stage kernels
-    bool tiled = true;
+    bool tiled = true, tile_vals = true;
     int32_t *hptr = nullptr, *hcell = nullptr;
     int16_t *lnb = nullptr;
     int tile_w = 0;
@@ -357,9 +357,16 @@ void launch_step(fvlbm_state *st) {
     if (st->tiled) {
         const int nt = st->mesh->n_tiles;
         const size_t lds = st->lds_bytes;
-        { Timed t(st, FVLBM_K_SWEEP1); k_stage_tiled<T, 1><<<nt, kTileCells, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b1, p); }
-        { Timed t(st, FVLBM_K_SWEEP2); k_stage_tiled<T, 2><<<nt, kTileCells, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b2, p); }
-        { Timed t(st, FVLBM_K_SWEEP3); k_stage_tiled<T, 3><<<nt, kTileCells, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b3, p); }
+        const int nth = kTileCells + kHaloThreads;
+        if (st->tile_vals) {
+            { Timed t(st, FVLBM_K_SWEEP1); k_stage_tiled<T, 1, true><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b1, p); }
+            { Timed t(st, FVLBM_K_SWEEP2); k_stage_tiled<T, 2, true><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b2, p); }
+            { Timed t(st, FVLBM_K_SWEEP3); k_stage_tiled<T, 3, true><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b3, p); }
+        } else {
+            { Timed t(st, FVLBM_K_SWEEP1); k_stage_tiled<T, 1, false><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b1, p); }
+            { Timed t(st, FVLBM_K_SWEEP2); k_stage_tiled<T, 2, false><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b2, p); }
+            { Timed t(st, FVLBM_K_SWEEP3); k_stage_tiled<T, 3, false><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b3, p); }
+        }
     } else {
         { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
         { Timed t(st, FVLBM_K_SWEEP1); k_sweep<T, 1><<<nbk, kBlock, 0, s>>>(g, G, b1, p); }
@@ -414,12 +421,17 @@ template <typename T>
 void choose_sweep(fvlbm_state *st) {
     static_assert(kTileCells == kTile, "tile size of the kernels and of the mesh preprocessing differ");
     st->tile_w = kTile + st->mesh->halo_max;
-    st->lds_bytes = (size_t)16 * st->tile_w * sizeof(T);
     int dev = 0, max_lds = 0;
     check(hipGetDevice(&dev), "hipGetDevice");
     check(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
     const char *env = std::getenv("FVLBM_SWEEP");
-    st->tiled = st->lds_bytes <= (size_t)max_lds && !(env && std::string(env) == "split");
+    const std::string mode = env ? env : "";
+    // values staged in LDS as well when 24 planes fit in a third of a CU's LDS (occupancy), else
+    // gradients only; the two-kernel path when not even those fit
+    const size_t with_vals = (size_t)24 * st->tile_w * sizeof(T), grads = (size_t)16 * st->tile_w * sizeof(T);
+    st->tile_vals = mode != "tiled-grads" && with_vals <= (size_t)std::min(max_lds, 160 * 1024 / 3);
+    st->lds_bytes = st->tile_vals ? with_vals : grads;
+    st->tiled = st->lds_bytes <= (size_t)max_lds && mode != "split";
 }
 
 template <typename T>

@@ -291,17 +291,70 @@ __global__ void __launch_bounds__(256) k_sweep(Geo<T> g, const T *__restrict__ G
     stage_epilogue<T, J>(c, n, gc, ga, b, p);
 }
 
-// Tiled sweep: one workgroup per tile of kTileCells consecutive cells.  Phase 1 computes the LSQ
-// gradients of the tile's cells (kept in registers and LDS) and of its halo (LDS); phase 2 takes
-// the convection term with every upwind neighbour's gradient from LDS and runs the epilogue.  The
-// gradient planes never travel through HBM.
+// Tiled sweep: one workgroup per tile of kTileCells consecutive cells plus kHaloThreads extra
+// threads for the tile's halo (the interior neighbours outside the tile).
+//   VALS = true : phase 0 stages the stage field of the tile and its halo in LDS (directions 1..8);
+//                 phase 1 computes the LSQ gradients of the tile cells from LDS and those of the
+//                 halo cells from global memory (their own neighbours lie further out);
+//   VALS = false: phase 1 reads every neighbour value from global memory.
+// Phase 2 takes the convection term with each upwind neighbour's value and gradient from LDS and
+// runs the stage epilogue.  LDS planes (W = kTileCells + halo_max columns): 16 gradient planes
+// (d/dx, d/dy of directions 1..8) then, with VALS, 8 value planes.  Tile cell t is column t, halo
+// cell j column kTileCells + j; lnb gives the column of each slot's neighbour.
 constexpr int kTileCells = 256;
+constexpr int kHaloThreads = 64;
 
-template <typename T, int J>
-__global__ void __launch_bounds__(kTileCells) k_stage_tiled(Geo<T> g, const int32_t *__restrict__ hptr,
-                                                           const int32_t *__restrict__ hcell,
-                                                           const int16_t *__restrict__ lnb, int W, StageBufs<T> b,
-                                                           StepPar<T> p) {
+template <typename T>
+struct NbrTileVals {
+    const T *L;            // LDS planes [24][W]
+    const int16_t *lnb;
+    int n, W, loc;
+    __device__ __forceinline__ void slot(int s, int c) { loc = lnb[(size_t)s * n + c]; }
+    __device__ __forceinline__ T recon(int a, int, T qx, T qy) const {
+        return L[(15 + a) * W + loc] + L[(2 * (a - 1)) * W + loc] * qx + L[(2 * (a - 1) + 1) * W + loc] * qy;
+    }
+};
+
+// LSQ gradient of a tile cell whose neighbours' values are all in LDS (value plane of direction a
+// is 15 + a); boundary edges use the ghost state of the cell's own values gc.
+template <typename T>
+__device__ __forceinline__ void grad_cell_lds(const Geo<T> &g, int cell, const int16_t *__restrict__ lnb,
+                                              const T *L, int W, T rho0, const T gc[9], T gx[9], T gy[9]) {
+    const int n = g.n;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gx[a] = gy[a] = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + cell;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        const T cxs = g.cx[si], cys = g.cy[si];
+        if (nb >= 0) {
+            const int loc = lnb[si];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T d = L[(15 + a) * W + loc] - gc[a];
+                gx[a] += cxs * d;
+                gy[a] += cys * d;
+            }
+        } else {
+            T drho, rho, ux, uy, gb[9];
+            moments(gc, rho0, drho, rho, ux, uy);
+            ghost(g, -2 - nb, g.nlx[si], g.nly[si], gc, drho, rho, ux, uy, gb);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T d = gb[a] - gc[a];
+                gx[a] += cxs * d;
+                gy[a] += cys * d;
+            }
+        }
+    }
+}
+
+template <typename T, int J, bool VALS>
+__global__ void __launch_bounds__(kTileCells + kHaloThreads)
+    k_stage_tiled(Geo<T> g, const int32_t *__restrict__ hptr, const int32_t *__restrict__ hcell,
+                  const int16_t *__restrict__ lnb, int W, StageBufs<T> b, StepPar<T> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *L = reinterpret_cast<T *>(smem);
     const int tile = xcd_block(blockIdx.x, gridDim.x);
@@ -309,30 +362,57 @@ __global__ void __launch_bounds__(kTileCells) k_stage_tiled(Geo<T> g, const int3
     const int ncell = min(kTileCells, g.n - start);
     const int h0 = hptr[tile], hcnt = hptr[tile + 1] - h0;
     const int t = threadIdx.x;
+    const int n = g.n;
     T gc[9], gx[9], gy[9];
+    if constexpr (VALS) {
+        // phase 0: stage values of the tile (coalesced) and of its halo (gathered)
+        if (t < ncell) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + start + t];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) L[(15 + a) * W + t] = gc[a];
+        }
+        for (int j = t; j < hcnt; j += kTileCells + kHaloThreads) {
+            const int hc = hcell[h0 + j];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) L[(15 + a) * W + kTileCells + j] = b.src[(size_t)a * n + hc];
+        }
+        __syncthreads();
+    }
+    // phase 1: gradients of the tile cells (threads < kTileCells) and of the halo (the rest first)
     if (t < ncell) {
-        grad_cell(g, b.src, start + t, p.rho0, gc, gx, gy);
+        if constexpr (VALS)
+            grad_cell_lds(g, start + t, lnb, L, W, p.rho0, gc, gx, gy);
+        else
+            grad_cell(g, b.src, start + t, p.rho0, gc, gx, gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             L[(2 * (a - 1)) * W + t] = gx[a];
             L[(2 * (a - 1) + 1) * W + t] = gy[a];
         }
     }
-    for (int w = t; w < hcnt; w += kTileCells) {
-        T hc[9], hx[9], hy[9];
-        grad_cell(g, b.src, hcell[h0 + w], p.rho0, hc, hx, hy);
+    {
+        // halo cell j is taken by thread kTileCells + j, then (beyond kHaloThreads) by thread j - kHaloThreads
+        const int first = t >= kTileCells ? t - kTileCells : t + kHaloThreads;
+        for (int j = first; j < hcnt; j += kTileCells + kHaloThreads) {
+            T hc[9], hx[9], hy[9];
+            grad_cell(g, b.src, hcell[h0 + j], p.rho0, hc, hx, hy);
 #pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            L[(2 * (a - 1)) * W + kTileCells + w] = hx[a];
-            L[(2 * (a - 1) + 1) * W + kTileCells + w] = hy[a];
+            for (int a = 1; a < 9; ++a) {
+                L[(2 * (a - 1)) * W + kTileCells + j] = hx[a];
+                L[(2 * (a - 1) + 1) * W + kTileCells + j] = hy[a];
+            }
         }
     }
     __syncthreads();
     if (t >= ncell) return;
     const int c = start + t;
     T ga[9];
-    advect_cell(g, c, p.rho0, gc, gx, gy, NbrTile<T>{b.src, L, lnb, g.n, W, 0}, ga);
-    stage_epilogue<T, J>(c, g.n, gc, ga, b, p);
+    if constexpr (VALS)
+        advect_cell(g, c, p.rho0, gc, gx, gy, NbrTileVals<T>{L, lnb, n, W, 0}, ga);
+    else
+        advect_cell(g, c, p.rho0, gc, gx, gy, NbrTile<T>{b.src, L, lnb, n, W, 0}, ga);
+    stage_epilogue<T, J>(c, n, gc, ga, b, p);
 }
 
 // Convection term alone (diagnostic entry point).

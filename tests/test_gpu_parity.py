@@ -82,10 +82,11 @@ def test_advection_operator_parity(F, name):
     assert rel(got, ref, np.abs(ref).max()) < 1e-12
 
 
-@pytest.mark.parametrize("sweep", ["tiled", "split"])
+@pytest.mark.parametrize("sweep", ["tiled", "tiled-grads", "split"])
 @pytest.mark.parametrize("name", sorted(MESHES))
 def test_laminar_step_parity(F, name, sweep, monkeypatch):
-    """Both sweep variants: the tiled kernels (gradients in LDS) and the two-kernel path."""
+    """Every sweep variant: tiled with values and gradients in LDS, tiled with gradients only, and
+    the two-kernel path."""
     say("laminar step", name, sweep)
     monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = MESHES[name]
