@@ -198,6 +198,41 @@ enum {
 fvlbm_status fvlbm_timing(fvlbm_state *st, int32_t enable);
 fvlbm_status fvlbm_timing_read(fvlbm_state *st, double ms[FVLBM_K_COUNT], int64_t launches[FVLBM_K_COUNT]);
 
+/*
+ * Diagnostic: the transpose of the convection operator at g, g_bar = (d Gamma^a(g) / d g)^T lam,
+ * and d_theta = d(lam . Gamma^a(g)) / d theta (theta enters through the inlet / far-field ghost
+ * states).  g_in, lam, g_bar: host [9][n] FP64 user order; d_theta: one double.  Synchronises.
+ */
+fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, const double *lam, double *g_bar,
+                                           double *d_theta);
+
+/*
+ * Discrete adjoint (reverse mode) of a recorded run, with checkpointing and recomputation.
+ *
+ * fvlbm_adjoint_bytes: device bytes of the adjoint workspace for n_steps recorded steps with a
+ *   checkpoint every ckpt_every steps (checkpoints, one segment of states, adjoint fields).
+ * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
+ *   (f, k, omega) every ckpt_every steps and at the end in `workspace` (device memory owned by the
+ *   caller, 256-byte aligned, kept alive until the adjoint has run).
+ * fvlbm_adjoint_step: for J = seed[0] F_x + seed[1] F_y + seed[2] J_R of the final state (forces of
+ *   the walls in wall_group_mask and the reversed-flow length, as fvlbm_forces), returns
+ *   dparams = dJ/d(theta, sigma_k1, sigma_omega1, beta*, a1) in FP64, differentiating the discrete
+ *   step exactly (branches of max / min / upwind choices as taken).  Each segment of ckpt_every
+ *   steps is recomputed from its checkpoint; every step is reversed after recomputing it: the
+ *   combination and stage collisions in closed form, the convection term by its transpose, the SST
+ *   update, fluxes, closure and LSQ gradients by their transposes.  The state is restored to the
+ *   final recorded state afterwards.  Errors: FVLBM_ESTATE without a recording, FVLBM_EDIVERGED.
+ * fvlbm_adjoint_state: the same reverse run seeded with the adjoint of the final state (host [9][n],
+ *   [n], [n] FP64 user order; lam_k / lam_w may be NULL), returning the adjoint of the recorded
+ *   initial state and dparams (for dot-product checks).
+ */
+fvlbm_status fvlbm_adjoint_bytes(const fvlbm_mesh *mesh, int32_t precision, int32_t n_steps, int32_t ckpt_every,
+                                 size_t *bytes);
+fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, void *workspace, size_t ws_bytes);
+fvlbm_status fvlbm_adjoint_step(fvlbm_state *st, uint64_t wall_group_mask, const double seed[3], double dparams[5]);
+fvlbm_status fvlbm_adjoint_state(fvlbm_state *st, const double *lam_f, const double *lam_k, const double *lam_w,
+                                 double *lam_f0, double *lam_k0, double *lam_w0, double dparams[5]);
+
 void fvlbm_state_destroy(fvlbm_state *st);
 
 const char *fvlbm_last_error(void);

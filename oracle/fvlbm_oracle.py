@@ -403,7 +403,9 @@ class Oracle:
         inner = np.nonzero(G.interior)[0]
         nb = G.nbr[inner]
         H = len(hc)
-        mdot = np.zeros(H, dtype=self.dtype)
+        # complex when the parameters or the state carry a complex-step perturbation
+        cdt = np.result_type(self.dtype, rho, ux, uy, k, w)
+        mdot = np.zeros(H, dtype=cdt)
         mdot[inner] = 0.5 * ((rho[hc[inner]] * ux[hc[inner]] + rho[nb] * ux[nb]) * G.nl[inner, 0]
                              + (rho[hc[inner]] * uy[hc[inner]] + rho[nb] * uy[nb]) * G.nl[inner, 1])
         bh = G.bidx
@@ -427,7 +429,7 @@ class Oracle:
             conv = mdot * fv
             # diffusive (reading r30): Gamma_f (grad phi_f . n) dl with the two-point central
             # difference along the centroid line, grad phi_f = (phi_N - phi_c) / |d| d^
-            diff = np.zeros(H, dtype=self.dtype)
+            diff = np.zeros(H, dtype=cdt)
             dvec = G.d[inner]
             dist = np.sqrt(dvec[:, 0] ** 2 + dvec[:, 1] ** 2)
             dh = dvec / dist[:, None]

@@ -1,0 +1,668 @@
+// Discrete adjoint of the IMEX step: transposed operators.
+//
+// The convection term Gamma^a of Eq. (advection) is linear in the stage field g except through the
+// boundary ghost states (which depend on the moments of the boundary cell).  Its transpose applied
+// to an adjoint field L (one value per cell and direction) is taken in two gathers:
+//   adv_T1 (per cell j): with mu_c = -L_c / A_c, every edge whose face value j reconstructs
+//           (outgoing directions, e.n > 0) carries weight en (mu_j - mu_N) to g_j and, through the
+//           extrapolation g_j + grad g_j . r_f, en (mu_j - mu_N) r_f to the adjoint of grad g_j
+//           (Gbar_j).  Boundary edges route their weight through the ghost state's Jacobian (dual
+//           numbers), together with the ghost's use in j's own LSQ gradient (c_b . Gbar_j); the
+//           inflow angle theta enters through the rotated inlet / far-field velocities.
+//   adv_T2 (per cell s): the transposed LSQ gradient, gbar_s += sum_j c_(j->s) . Gbar_j over the
+//           neighbours j of s, minus (sum_k c_sk) . Gbar_s.
+// The same slot data serves both sides of an edge: seen from the neighbour N, e.n changes sign and
+// its reconstruction vector x_f - x_N is the slot's q.
+#pragma once
+
+#include "kernels.h"
+
+namespace fvlbm {
+
+// d(ghost state)/d(cell state, theta) contracted with gbar (directions 1..8): adds to gout[0..8]
+// and returns the theta part.  Theta rotates the velocity of inlet and far-field edges.
+template <typename T>
+__device__ __forceinline__ T ghost_vjp(const Geo<T> &g, int b, T nlx, T nly, const T gc[9], T rho0, const T gbar[9],
+                                       T gout[9]) {
+    using D = Dual<T, 10>;
+    const int kind = g.b_kind[b];
+    D gcd[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gcd[a] = D::var(gc[a], a);
+    const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]);
+    const bool rot = (kind == kInlet || kind == kFarfield);
+    D dubx(ubx), duby(uby);
+    if (rot) {   // d(R(theta) u)/d theta = (-u_y, u_x) of the rotated velocity
+        dubx.d[9] = -uby;
+        duby.d[9] = ubx;
+    }
+    D drho, rho, ux, uy, gb[9];
+    moments(gcd, D(rho0), drho, rho, ux, uy);
+    ghost_state<D, T>(kind, dubx, duby, D(T(g.b_rho[b])), D(T(g.b_drho[b])), nlx, nly, gcd, drho, rho, ux, uy, gb);
+    T dth = 0;
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) gout[i] += gbar[a] * gb[a].d[i];
+        dth += gbar[a] * gb[a].d[9];
+    }
+    return dth;
+}
+
+// L, gbar: [9][n] (direction 0 of L unused); Gbar: [16][n]; dth: [n] per-cell theta contributions (FP64).
+template <typename T>
+__global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ f, const T *__restrict__ L,
+                                                T *__restrict__ gbar, T *__restrict__ Gbar, double *__restrict__ dth,
+                                                T rho0) {
+    const int j = cell_index();
+    if (j >= g.n) return;
+    const int n = g.n;
+    T mu[9], gj[9], gd[9], Gx[9], Gy[9];
+    const T ia = g.inv_area[j];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        mu[a] = -L[(size_t)a * n + j] * ia;
+        gj[a] = f[(size_t)a * n + j];
+        gd[a] = Gx[a] = Gy[a] = T(0);
+    }
+    // pass 1: interior edges and open-boundary outgoing directions
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + j;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        const T nlx = g.nlx[si], nly = g.nly[si], rx = g.rfx[si], ry = g.rfy[si];
+        if (nb >= 0) {
+            const T ian = g.inv_area[nb];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+                if (en > T(0)) {
+                    const T w = en * (mu[a] + L[(size_t)a * n + nb] * ian);
+                    gd[a] += w;
+                    Gx[a] += w * rx;
+                    Gy[a] += w * ry;
+                }
+            }
+        } else {
+            const int kind = g.b_kind[-2 - nb];
+            if (kind == kWall || kind == kMovingWall) continue;
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+                if (en >= T(0)) {
+                    const T w = en * mu[a];
+                    gd[a] += w;
+                    Gx[a] += w * rx;
+                    Gy[a] += w * ry;
+                }
+            }
+        }
+    }
+    // pass 2: ghost states (face values on walls / incoming directions, and the LSQ gradient)
+    T th = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + j;
+        const int nb = g.nbr[si];
+        if (nb >= -1) continue;
+        const int b = -2 - nb;
+        const int kind = g.b_kind[b];
+        const bool wall = (kind == kWall || kind == kMovingWall);
+        const T nlx = g.nlx[si], nly = g.nly[si], cxs = g.cx[si], cys = g.cy[si];
+        T gb_bar[9];
+        gb_bar[0] = T(0);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+            gb_bar[a] = cxs * Gx[a] + cys * Gy[a] + ((wall || en < T(0)) ? en * mu[a] : T(0));
+        }
+        th += ghost_vjp(g, b, nlx, nly, gj, rho0, gb_bar, gd);
+    }
+    // own part of the transposed LSQ gradient: grad g_j = sum_k c_jk (v_k - g_j)
+    T sx = 0, sy = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + j;
+        if (g.nbr[si] == -1) continue;
+        sx += g.cx[si];
+        sy += g.cy[si];
+    }
+#pragma unroll
+    for (int a = 1; a < 9; ++a) gd[a] -= sx * Gx[a] + sy * Gy[a];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gbar[(size_t)a * n + j] += gd[a];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        Gbar[(size_t)(2 * (a - 1)) * n + j] = Gx[a];
+        Gbar[(size_t)(2 * (a - 1) + 1) * n + j] = Gy[a];
+    }
+    dth[j] += (double)th;
+}
+
+// Interior neighbours' part of the transposed LSQ gradient.  rev[k][s]: the slot of neighbour
+// nbr[k][s] that points back to s.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adv_T2(Geo<T> g, const int8_t *__restrict__ rev, const T *__restrict__ Gbar,
+                                                T *__restrict__ gbar) {
+    const int s0 = cell_index();
+    if (s0 >= g.n) return;
+    const int n = g.n;
+    T acc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t si = (size_t)k * n + s0;
+        const int j = g.nbr[si];
+        if (j < 0) continue;
+        const size_t sj = (size_t)rev[si] * n + j;
+        const T cx = g.cx[sj], cy = g.cy[sj];
+#pragma unroll
+        for (int a = 1; a < 9; ++a)
+            acc[a] += cx * Gbar[(size_t)(2 * (a - 1)) * n + j] + cy * Gbar[(size_t)(2 * (a - 1) + 1) * n + j];
+    }
+#pragma unroll
+    for (int a = 1; a < 9; ++a) gbar[(size_t)a * n + s0] += acc[a];
+}
+
+}  // namespace fvlbm
+
+namespace fvlbm {
+
+// ----------------------------------------------------------------------------------------------
+// Stage collisions, reversed.  With m = (rho - rho0, j_x, j_y), the equilibrium f_eq(m) and
+// M^T lam = lam_0 + e_x lam_x + e_y lam_y:
+//   f = (rhs + a f_eq(m)) / (1 + a)  gives  rhs_bar = f_bar / (1 + a),
+//   m_bar = (d f_eq / d m)^T (a / (1 + a) f_bar),  a_bar = sum f_bar (f_eq - f) / (1 + a),
+// and a = dt m_JJ / tau gives tau_bar = -a_bar a / tau.
+// ----------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void feq_vjp(T drho, T jx, T jy, T rho0, const T lam[9], T mbar[3]) {
+    using D = Dual<T, 3>;
+    const D dr = D::var(drho, 0), dx = D::var(jx, 1), dy = D::var(jy, 2);
+    const D rho = D(rho0) + dr;
+    const D ux = dx / rho, uy = dy / rho;
+    mbar[0] = mbar[1] = mbar[2] = T(0);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const D fe = dfeq(a, dr, rho, ux, uy);
+        mbar[0] += lam[a] * fe.d[0];
+        mbar[1] += lam[a] * fe.d[1];
+        mbar[2] += lam[a] * fe.d[2];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void raw_moments(const T d[9], T &m0, T &mx, T &my) {
+    m0 = mx = my = T(0);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        m0 += d[a];
+        mx += T(ex(a)) * d[a];
+        my += T(ey(a)) * d[a];
+    }
+}
+
+// Reverse of the stage solve with the moments taken from rhs itself; adds rhs_bar to out and
+// returns a_bar.  f: the stage result, mom: the moments of rhs (= those of f).
+template <typename T>
+__device__ __forceinline__ T collide_vjp(const T f[9], T m0, T mx, T my, T a, T rho0, const T fbar[9], T out[9]) {
+    const T inv = T(1) / (T(1) + a);
+    const T rho = rho0 + m0, ux = mx / rho, uy = my / rho;
+    T lam[9], mb[3], abar = 0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        lam[q] = a * inv * fbar[q];
+        abar += fbar[q] * (dfeq(q, m0, rho, ux, uy) - f[q]) * inv;
+    }
+    feq_vjp(m0, mx, my, rho0, lam, mb);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) out[q] += fbar[q] * inv + mb[0] + T(ex(q)) * mb[1] + T(ey(q)) * mb[2];
+    return abar;
+}
+
+// Buffers of the step reverse.
+template <typename T>
+struct AdjBufs {
+    const T *fn, *f1, *f2, *f3, *Q, *tau;   // forward data of the step (f1 recomputed)
+    T *lfn;    // adjoint of f^n (accumulated)
+    T *lf1, *lf2, *lf3;                     // adjoints of the stage fields
+    T *lam;    // input of the transposed convection (adjoint of a convection term)
+    T *lg1;    // adjoint of Ga1
+    T *ltau;   // adjoint of tau
+};
+
+// Reverse of the third stage and of the combination f^{n+1} = Q + dt/3 Ga3, given f3_bar (already
+// holding Ga3's transpose applied to dt/3 lam_{n+1}) and lam_{n+1} = lfn on entry (the adjoint of
+// f^{n+1}).  Produces: lfn <- adjoint of f^n (partial), lf2 (Gc2 part), lf1 (Gc1 part), lam = Ga2
+// adjoint, lg1 = Ga1 adjoint (partial), ltau.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_stage3(int n, AdjBufs<T> b, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= n) return;
+    T fn[9], f1[9], f2[9], f3[9], Q[9], lq[9], l3[9];
+    const T tc = b.tau[c];
+    const T dt = p.dt;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const size_t i = (size_t)a * n + c;
+        fn[a] = b.fn[i]; f1[a] = b.f1[i]; f2[a] = b.f2[i]; f3[a] = b.f3[i]; Q[a] = b.Q[i];
+        lq[a] = b.lfn[i];                 // lam_{n+1} = adjoint of Q
+        l3[a] = b.lf3[i] + lq[a];         // f3 enters Q with weight 1
+    }
+    // Q = f3 - dt/6 (Ga1 + Ga2)
+    T lg12[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) lg12[a] = -dt / T(6) * lq[a];
+    // f3 = (rhs3 + a3 f_eq(m3)) / (1 + a3), m3 = m(f^n) + dt/2 m(Ga1 + Ga2), Ga1 + Ga2 = 6 (f3 - Q) / dt
+    const T a3 = dt / (T(3) * tc);
+    const T inv3 = T(1) / (T(1) + a3);
+    T m0 = 0, mx = 0, my = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const T mv = fn[a] + T(3) * (f3[a] - Q[a]);
+        m0 += mv;
+        mx += T(ex(a)) * mv;
+        my += T(ey(a)) * mv;
+    }
+    const T rho3 = p.rho0 + m0, ux3 = mx / rho3, uy3 = my / rho3;
+    T lrhs[9], lfe[9], mb[3], abar = 0;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        lrhs[a] = l3[a] * inv3;
+        lfe[a] = a3 * inv3 * l3[a];
+        abar += l3[a] * (dfeq(a, m0, rho3, ux3, uy3) - f3[a]) * inv3;
+    }
+    T ltau = -abar * a3 / tc;
+    feq_vjp(m0, mx, my, p.rho0, lfe, mb);
+    T lfn[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const T mt = mb[0] + T(ex(a)) * mb[1] + T(ey(a)) * mb[2];   // M^T m3_bar
+        lfn[a] = mt + lrhs[a];                                      // through m3 and rhs3
+        lg12[a] += dt * T(0.5) * (mt + lrhs[a]);
+    }
+    // rhs3 = f^n + dt/2 (Ga1 + Ga2) + dt/3 (Gc1 + Gc2)
+    const T itau = T(1) / tc;
+    T lgc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) lgc[a] = dt / T(3) * lrhs[a];
+    // Gc2 = (f_eq(m(f2)) - f2) / tau
+    {
+        T q0, qx, qy;
+        raw_moments(f2, q0, qx, qy);
+        const T r = p.rho0 + q0, vx = qx / r, vy = qy / r;
+        T l[9], mb2[3];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            l[a] = lgc[a] * itau;
+            ltau -= lgc[a] * (dfeq(a, q0, r, vx, vy) - f2[a]) * itau * itau;
+        }
+        feq_vjp(q0, qx, qy, p.rho0, l, mb2);
+#pragma unroll
+        for (int a = 0; a < 9; ++a)
+            b.lf2[(size_t)a * n + c] = mb2[0] + T(ex(a)) * mb2[1] + T(ey(a)) * mb2[2] - l[a];
+    }
+    // Gc1 = (f_eq(m(f^n)) - f1) / tau
+    {
+        T q0, qx, qy;
+        raw_moments(fn, q0, qx, qy);
+        const T r = p.rho0 + q0, vx = qx / r, vy = qy / r;
+        T l[9], mb1[3];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            l[a] = lgc[a] * itau;
+            ltau -= lgc[a] * (dfeq(a, q0, r, vx, vy) - f1[a]) * itau * itau;
+        }
+        feq_vjp(q0, qx, qy, p.rho0, l, mb1);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            lfn[a] += mb1[0] + T(ex(a)) * mb1[1] + T(ey(a)) * mb1[2];
+            b.lf1[(size_t)a * n + c] = -l[a];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const size_t i = (size_t)a * n + c;
+        b.lfn[i] = lfn[a];
+        b.lam[i] = lg12[a];     // Ga2 adjoint
+        b.lg1[i] = lg12[a];     // Ga1 adjoint so far
+    }
+    b.ltau[c] = ltau;
+}
+
+// Reverse of the second stage f2 = solve(f^n + dt/2 Ga1, a2 = dt/(4 tau)) given the complete f2
+// adjoint: lfn += rhs2_bar; lam <- Ga1 adjoint = lg1 + dt/2 rhs2_bar; ltau += ...
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_stage2(int n, AdjBufs<T> b, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= n) return;
+    T f2[9], lf2[9], lr[9];
+    const T tc = b.tau[c];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        f2[a] = b.f2[(size_t)a * n + c];
+        lf2[a] = b.lf2[(size_t)a * n + c];
+        lr[a] = T(0);
+    }
+    T m0, mx, my;
+    raw_moments(f2, m0, mx, my);
+    const T a2 = p.dt / (T(4) * tc);
+    const T abar = collide_vjp(f2, m0, mx, my, a2, p.rho0, lf2, lr);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const size_t i = (size_t)a * n + c;
+        b.lfn[i] += lr[a];
+        b.lam[i] = b.lg1[i] + p.dt * T(0.5) * lr[a];
+    }
+    b.ltau[c] += -abar * a2 / tc;
+}
+
+// Reverse of the first stage f1 = solve(f^n, a1 = dt/(4 tau)) given the complete f1 adjoint.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_stage1(int n, AdjBufs<T> b, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= n) return;
+    T f1[9], fn[9], lf1[9], lr[9];
+    const T tc = b.tau[c];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        f1[a] = b.f1[(size_t)a * n + c];
+        fn[a] = b.fn[(size_t)a * n + c];
+        lf1[a] = b.lf1[(size_t)a * n + c];
+        lr[a] = T(0);
+    }
+    T m0, mx, my;
+    raw_moments(fn, m0, mx, my);
+    const T a1 = p.dt / (T(4) * tc);
+    const T abar = collide_vjp(f1, m0, mx, my, a1, p.rho0, lf1, lr);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) b.lfn[(size_t)a * n + c] += lr[a];
+    b.ltau[c] += -abar * a1 / tc;
+}
+
+// ----------------------------------------------------------------------------------------------
+// SST, reversed.  Cell data x = (rho, u, v, k, omega, dk/dx, dk/dy, domega/dx, domega/dy, Gamma_k,
+// Gamma_omega); lx its adjoint [11][n]; lnet [2][n] the adjoint of the net k / omega inflow; lown
+// [4][n] the adjoint of (dt P / rho, dt (P_w + cross) / rho, beta, S); lgrad [8][n] the adjoint of
+// the LSQ gradients of u, v, k, omega; pbar [5][n] (FP64) per-cell parameter adjoints in the order
+// (theta, sigma_k1, sigma_w1, beta*, a1).
+// ----------------------------------------------------------------------------------------------
+struct SstAdj {
+    const int32_t *bzg;
+    double *pbar;
+};
+
+template <typename T>
+__device__ __forceinline__ void sst_net(const Geo<T> &g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
+                                        const T *__restrict__ K, const T *__restrict__ W, const T *__restrict__ aux,
+                                        int c, T rho0, const T xc[11], T &net_k, T &net_w) {
+    const int n = g.n;
+    net_k = net_w = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        T tk, tw;
+        if (nb >= 0) {
+            T xn[11];
+            sst_cell_x(n, nb, rho0, M, K, W, aux, xn);
+            sst_face<T, T>(xc, xn, g.nlx[si], g.nly[si], g.rfx[si], g.rfy[si], g.qx[si], g.qy[si], tk, tw);
+        } else {
+            const int b = -2 - nb;
+            sst_bface<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), g.nlx[si], g.nly[si],
+                            g.rfx[si], g.rfy[si], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
+        }
+        net_k += tk;
+        net_w += tw;
+    }
+}
+
+// SB1: reverse of the point-implicit update and of tau = 3 (nu + nu_t).
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_sst_update(Geo<T> g, SstAdj sa, const T *__restrict__ M,
+                                                        const T *__restrict__ K, const T *__restrict__ W,
+                                                        const T *__restrict__ aux, const T *__restrict__ lk1,
+                                                        const T *__restrict__ lw1, const T *__restrict__ ltau,
+                                                        T *__restrict__ lx, T *__restrict__ lnet, T *__restrict__ lown,
+                                                        StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T xc[11];
+    sst_cell_x(n, c, p.rho0, M, K, W, aux, xc);
+    T nk, nw;
+    sst_net(g, sa.bzg, M, K, W, aux, c, p.rho0, xc, nk, nw);
+    using D = Dual<T, 11>;
+    // inputs: rho, k, omega, net_k, net_w, sk, sw, beta, S, a1, beta*
+    const D rho = D::var(xc[0], 0), k = D::var(xc[3], 1), w = D::var(xc[4], 2);
+    const D netk = D::var(nk, 3), netw = D::var(nw, 4);
+    const D sk = D::var(aux[(size_t)6 * n + c], 5), sw = D::var(aux[(size_t)7 * n + c], 6);
+    const D beta = D::var(aux[(size_t)8 * n + c], 7), Sr = D::var(aux[(size_t)9 * n + c], 8);
+    SstParams<D> q{D::var(p.a1, 9), D::var(p.bstar, 10), D(p.sk1), D(p.sw1)};
+    D k1, w1, nut;
+    sst_update<D, T>(rho, k, w, netk, netw, sk, sw, beta, Sr, T(g.wdist[c]), g.inv_area[c], p, q, k1, w1, nut);
+    const T a_k = lk1[c], a_w = lw1[c], a_t = T(3) * ltau[c];
+    T l[11];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) l[i] = a_k * k1.d[i] + a_w * w1.d[i] + a_t * nut.d[i];
+    lx[c] += l[0];
+    lx[(size_t)3 * n + c] += l[1];
+    lx[(size_t)4 * n + c] += l[2];
+    lnet[c] = l[3];
+    lnet[(size_t)n + c] = l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lown[(size_t)i * n + c] = l[5 + i];
+    sa.pbar[(size_t)4 * n + c] += (double)l[9];
+    sa.pbar[(size_t)3 * n + c] += (double)l[10];
+}
+
+// SB2: reverse of the face fluxes, gathered per cell j from its own edges and, through the same
+// edges seen from the neighbour, from the neighbours' net inflows.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_sst_faces(Geo<T> g, SstAdj sa, const T *__restrict__ M,
+                                                       const T *__restrict__ K, const T *__restrict__ W,
+                                                       const T *__restrict__ aux, const T *__restrict__ lnet,
+                                                       T *__restrict__ lx, StepPar<T> p) {
+    const int j = cell_index();
+    if (j >= g.n) return;
+    const int n = g.n;
+    using D = Dual<T, 12>;   // 11 cell values + theta
+    T xj[11];
+    sst_cell_x(n, j, p.rho0, M, K, W, aux, xj);
+    D xd[11];
+#pragma unroll
+    for (int i = 0; i < 11; ++i) xd[i] = D::var(xj[i], i);
+    const T lk = lnet[j], lw = lnet[(size_t)n + j];
+    T acc[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) acc[i] = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + j;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        const T nlx = g.nlx[si], nly = g.nly[si], rx = g.rfx[si], ry = g.rfy[si], qx = g.qx[si], qy = g.qy[si];
+        if (nb >= 0) {
+            T xn[11];
+            sst_cell_x(n, nb, p.rho0, M, K, W, aux, xn);
+            D xnd[11];
+#pragma unroll
+            for (int i = 0; i < 11; ++i) xnd[i] = D(xn[i]);
+            D tk, tw;
+            sst_face<D, T>(xd, xnd, nlx, nly, rx, ry, qx, qy, tk, tw);      // in j's net inflow
+            const T lkn = lnet[nb], lwn = lnet[(size_t)n + nb];
+            D uk, uw;
+            sst_face<D, T>(xnd, xd, -nlx, -nly, qx, qy, rx, ry, uk, uw);    // in the neighbour's
+#pragma unroll
+            for (int i = 0; i < 11; ++i) acc[i] += lk * tk.d[i] + lw * tw.d[i] + lkn * uk.d[i] + lwn * uw.d[i];
+        } else {
+            const int b = -2 - nb;
+            const int kind = g.b_kind[b];
+            const bool zg = sa.bzg[b] != 0;
+            const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]);
+            D dubx(ubx), duby(uby);
+            if (!zg && (kind == kInlet || kind == kFarfield)) {
+                dubx.d[11] = -uby;
+                duby.d[11] = ubx;
+            }
+            D tk, tw;
+            sst_bface<D, T>(xd, zg, dubx, duby, T(g.b_k[b]), T(g.b_w[b]), nlx, nly, rx, ry, T(g.b_l[b] / g.b_dperp[b]), tk, tw);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) acc[i] += lk * tk.d[i] + lw * tw.d[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 11; ++i) lx[(size_t)i * n + j] += acc[i];
+    sa.pbar[j] += (double)acc[11];
+}
+
+// SA1: reverse of the cell-local closure (dual numbers over its 11 inputs and 4 constants).
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_sst_local(Geo<T> g, SstAdj sa, const T *__restrict__ M,
+                                                       const T *__restrict__ K, const T *__restrict__ W,
+                                                       const T *__restrict__ lown, T *__restrict__ lx,
+                                                       T *__restrict__ lgrad, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gu[2], gv[2], gk[2], gw[2];
+    sst_gradients(g, sa.bzg, M, K, W, c, gu, gv, gk, gw);
+    using D = Dual<T, 15>;
+    const D rho = D::var(p.rho0 + M[c], 0), k = D::var(K[c], 1), w = D::var(W[c], 2);
+    const SstParams<D> q{D::var(p.a1, 11), D::var(p.bstar, 12), D::var(p.sk1, 13), D::var(p.sw1, 14)};
+    const SstLocal<D> o = sst_local<D, T>(rho, k, w, D::var(gu[0], 3), D::var(gu[1], 4), D::var(gv[0], 5), D::var(gv[1], 6),
+                                          D::var(gk[0], 7), D::var(gk[1], 8), D::var(gw[0], 9), D::var(gw[1], 10),
+                                          T(g.wdist[c]), p, q);
+    const T lGk = lx[(size_t)9 * n + c], lGw = lx[(size_t)10 * n + c];
+    const T lsk = lown[c], lsw = lown[(size_t)n + c], lb = lown[(size_t)2 * n + c], lS = lown[(size_t)3 * n + c];
+    T l[15];
+#pragma unroll
+    for (int i = 0; i < 15; ++i)
+        l[i] = lGk * o.Gk.d[i] + lGw * o.Gw.d[i] + lsk * o.sk.d[i] + lsw * o.sw.d[i] + lb * o.beta.d[i] + lS * o.Sr.d[i];
+    lx[c] += l[0];
+    lx[(size_t)3 * n + c] += l[1];
+    lx[(size_t)4 * n + c] += l[2];
+    // gradients of u, v (closure only), of k, omega (closure + the face reconstructions)
+    lgrad[c] = l[3];
+    lgrad[(size_t)1 * n + c] = l[4];
+    lgrad[(size_t)2 * n + c] = l[5];
+    lgrad[(size_t)3 * n + c] = l[6];
+    lgrad[(size_t)4 * n + c] = l[7] + lx[(size_t)5 * n + c];
+    lgrad[(size_t)5 * n + c] = l[8] + lx[(size_t)6 * n + c];
+    lgrad[(size_t)6 * n + c] = l[9] + lx[(size_t)7 * n + c];
+    lgrad[(size_t)7 * n + c] = l[10] + lx[(size_t)8 * n + c];
+    sa.pbar[(size_t)4 * n + c] += (double)l[11];
+    sa.pbar[(size_t)3 * n + c] += (double)l[12];
+    sa.pbar[(size_t)1 * n + c] += (double)l[13];
+    sa.pbar[(size_t)2 * n + c] += (double)l[14];
+}
+
+// SA2: transposed LSQ gradients of u, v, k, omega, then the macro transpose onto f^n:
+// u = j_x / rho gives d u / d f_a = (e_x,a - u) / rho; rho - rho0 = sum f.  Writes the adjoints of
+// k^n, omega^n and adds to lfn.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_sst_grad(Geo<T> g, SstAdj sa, const int8_t *__restrict__ rev,
+                                                      const T *__restrict__ M, const T *__restrict__ lgrad,
+                                                      const T *__restrict__ lx, T *__restrict__ lfn,
+                                                      T *__restrict__ lk, T *__restrict__ lw, T rho0) {
+    const int s0 = cell_index();
+    if (s0 >= g.n) return;
+    const int n = g.n;
+    T acc[4] = {0, 0, 0, 0};      // u, v, k, omega
+    T own[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) own[i] = lgrad[(size_t)i * n + s0];
+    T th = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const size_t si = (size_t)k * n + s0;
+        const int j = g.nbr[si];
+        if (j == -1) continue;
+        const T cx = g.cx[si], cy = g.cy[si];
+        if (j >= 0) {
+            const size_t sj = (size_t)rev[si] * n + j;
+            const T cjx = g.cx[sj], cjy = g.cy[sj];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                acc[v] += cjx * lgrad[(size_t)(2 * v) * n + j] + cjy * lgrad[(size_t)(2 * v + 1) * n + j];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] -= cx * own[2 * v] + cy * own[2 * v + 1];
+        } else {
+            const int b = -2 - j;
+            if (sa.bzg[b]) continue;      // zero-gradient ghost: no contribution
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] -= cx * own[2 * v] + cy * own[2 * v + 1];
+            const int kind = g.b_kind[b];
+            if (kind == kInlet || kind == kFarfield) {
+                const T lu = cx * own[0] + cy * own[1], lv = cx * own[2] + cy * own[3];
+                th += lu * (-T(g.b_uy[b])) + lv * T(g.b_ux[b]);
+            }
+        }
+    }
+    sa.pbar[s0] += (double)th;
+    const T lrho = lx[s0], lu = lx[(size_t)n + s0] + acc[0], lv = lx[(size_t)2 * n + s0] + acc[1];
+    lk[s0] = lx[(size_t)3 * n + s0] + acc[2];
+    lw[s0] = lx[(size_t)4 * n + s0] + acc[3];
+    const T rho = rho0 + M[s0], ux = M[(size_t)n + s0], uy = M[(size_t)2 * n + s0];
+    const T ir = T(1) / rho;
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        lfn[(size_t)a * n + s0] += lrho + (T(ex(a)) - ux) * ir * lu + (T(ey(a)) - uy) * ir * lv;
+}
+
+// Forces and the reversed-flow length at the final state, reversed onto f (through rho, u of the
+// wall cells): seed = (dJ/dF_x, dJ/dF_y, dJ/dJ_R).
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_forces(Geo<T> g, const T *__restrict__ F, unsigned long long mask,
+                                                    int jr_group, double jr_xmin, double eps, double nu, double sx,
+                                                    double sy, double sj, T rho0, T *__restrict__ lfn) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T d[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) d[a] = F[(size_t)a * n + c];
+    using D = Dual<double, 3>;
+    D acc[3];
+    bool any = false;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int nb = g.nbr[(size_t)s * n + c];
+        if (nb >= -1) continue;
+        const int b = -2 - nb;
+        const int kind = g.b_kind[b];
+        if (kind != kWall && kind != kMovingWall) continue;
+        const int grp = g.b_group[b];
+        const bool inF = (mask >> grp) & 1ull, inJ = (grp == jr_group && g.b_xfx[b] > jr_xmin);
+        if (!inF && !inJ) continue;
+        if (!any) {
+            T m0, mx, my;
+            raw_moments(d, m0, mx, my);
+            const D dr = D::var((double)m0, 0), jx = D::var((double)mx, 1), jy = D::var((double)my, 2);
+            const D rho = D((double)rho0) + dr;
+            acc[0] = rho;
+            acc[1] = jx / rho;
+            acc[2] = jy / rho;
+            any = true;
+        }
+        const D rho = acc[0], ux = acc[1], uy = acc[2];
+        const double nx = g.b_nx[b], ny = g.b_ny[b], l = g.b_l[b], dp = g.b_dperp[b];
+        const D rux = ux - g.b_ux[b], ruy = uy - g.b_uy[b];
+        const D un = rux * nx + ruy * ny;
+        const D mu = rho * nu;
+        const D tx = mu * (rux - un * nx) / dp, ty = mu * (ruy - un * ny) / dp;
+        const D dpres = (rho - (double)rho0) / 3.0;
+        D J(0.0);
+        if (inF) J = J + (sx * l) * (dpres * nx + tx) + (sy * l) * (dpres * ny + ty);
+        if (inJ) J = J + (sj * l * 0.5) * (1.0 - dtanh(tx / eps));
+        // accumulate dJ/d(m) into lfn below
+        const double j0 = J.d[0], j1 = J.d[1], j2 = J.d[2];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) lfn[(size_t)a * n + c] += T(j0 + ex(a) * j1 + ey(a) * j2);
+    }
+}
+
+}  // namespace fvlbm

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "adjoint.h"
 #include "kernels.h"
 
 namespace fvlbm {
@@ -71,12 +72,18 @@ struct fvlbm_state {
     bool tiled = true, tile_vals = true;
     int32_t *hptr = nullptr, *hcell = nullptr;
     int16_t *lnb = nullptr;
+    int8_t *rev = nullptr;
+    void *scr1 = nullptr;        // one n-array of T for diagnostics
     int tile_w = 0;
     size_t lds_bytes = 0;
     double *scratch = nullptr;   // 9 n doubles (staging of user-order FP64 arrays)
     double *partial = nullptr;   // kRedBlocks * 4
     double *result = nullptr;    // 4
     int64_t steps_done = 0;
+    // record / adjoint (fvlbm_record, fvlbm_adjoint_step)
+    char *adj_ws = nullptr;
+    size_t adj_bytes = 0;
+    int32_t rec_steps = 0, rec_ckpt = 0;
     // per-kernel event timing (fvlbm_timing)
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
@@ -154,6 +161,8 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
         st->aux = cv.take<T>(10 * n);
     }
     st->lnb = cv.take<int16_t>(S);
+    st->rev = cv.take<int8_t>(S);
+    st->scr1 = cv.take<T>(n);
     st->hptr = cv.take<int32_t>((size_t)m->n_tiles + 1);
     st->hcell = cv.take<int32_t>(std::max<size_t>(1, m->halo_cell.size()));
     st->scratch = cv.take<double>(9 * n);
@@ -185,9 +194,7 @@ StepPar<T> step_par(const fvlbm_params &p) {
     s.sw2 = T(p.sigma_w2);
     s.b1 = T(p.beta1);
     s.b2 = T(p.beta2);
-    // C_omega_i = beta_i / beta* - sigma_omega_i kappa^2 / sqrt(beta*)
-    s.cw1 = T(p.beta1 / p.beta_star - p.sigma_w1 * p.kappa * p.kappa / std::sqrt(p.beta_star));
-    s.cw2 = T(p.beta2 / p.beta_star - p.sigma_w2 * p.kappa * p.kappa / std::sqrt(p.beta_star));
+    s.kappa = T(p.kappa);
     return s;
 }
 
@@ -280,6 +287,7 @@ void upload_geometry(fvlbm_state *st) {
     h2d(const_cast<double *>(g.b_dperp), m->b_dperp, s);
     h2d(const_cast<double *>(g.b_xfx), m->b_xfx, s);
     h2d(st->lnb, m->lnb, s);
+    h2d(st->rev, m->rev, s);
     h2d(st->hptr, m->halo_ptr, s);
     h2d(st->hcell, m->halo_cell, s);
     std::vector<double> bv[6];
@@ -508,6 +516,256 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
     check(hipGetLastError(), "kernel launch");
     check(hipMemcpyAsync(out, st->scratch, 9 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
     check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+// Diagnostic: gbar = Gamma^a(g)^T lam and d(lam . Gamma^a(g))/d theta.
+template <typename T>
+void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *lam, double *out, double *dtheta) {
+    const Geo<T> &g = geo_of<T>(st);
+    const int n = g.n, nbk = blocks_for(n);
+    hipStream_t s = st->stream;
+    upload_scratch(st, gin, 9 * (size_t)n);
+    k_import_f<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, (T *)st->X, st->par.rho0);
+    check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    upload_scratch(st, lam, 9 * (size_t)n);
+    k_import_f<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, (T *)st->Y, 0.0);
+    k_fill<T><<<blocks_for(9 * (size_t)n), kBlock, 0, s>>>(9 * n, (T *)st->A, T(0));
+    double *dth = st->scratch + 8 * (size_t)n;   // last plane of the staging area (free after import)
+    k_fill<double><<<nbk, kBlock, 0, s>>>(n, dth, 0.0);
+    k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->Y, (T *)st->A, (T *)st->G, dth, T(st->par.rho0));
+    k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, (T *)st->A);
+    k_sum<double><<<kRedBlocks, kBlock, 0, s>>>(n, dth, st->partial);
+    k_export_f<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->A, st->scratch, 0.0);
+    k_finish<1><<<1, kBlock, 0, s>>>(st->partial, kRedBlocks, st->result);
+    check(hipGetLastError(), "kernel launch");
+    check(hipMemcpyAsync(out, st->scratch, 9 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+    check(hipMemcpyAsync(dtheta, st->result, sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+// ---------------------------------------------------------------------------------------------
+// Record and adjoint.  Layout of the caller's adjoint workspace (all T unless noted):
+//   checkpoints: (ceil(N/C) + 1) states of f [9n], k [n], omega [n] (the last one: the final state)
+//   segment:     C states of the same form
+//   adjoint:     lF [9n], lK [n], lW [n], lf1, lf2, lf3, lam, lg1, F1 [9n each], ltau [n],
+//                lx [11n], lnet [2n], lown [4n], lgrad [8n], pbar [5n] (FP64)
+// ---------------------------------------------------------------------------------------------
+template <typename T>
+struct AdjLayout {
+    T *ckpt, *seg, *lF, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *F1, *ltau, *lx, *lnet, *lown, *lgrad;
+    double *pbar;
+    size_t state_len;
+};
+
+template <typename T>
+size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout<T> &L) {
+    const size_t sl = 11 * (size_t)n;
+    const size_t nck = (size_t)((n_steps + ckpt - 1) / ckpt) + 1;
+    L.state_len = sl;
+    L.ckpt = cv.take<T>(nck * sl);
+    L.seg = cv.take<T>((size_t)ckpt * sl);
+    L.lF = cv.take<T>(9 * (size_t)n);
+    L.lK = cv.take<T>(n);
+    L.lW = cv.take<T>(n);
+    L.lf1 = cv.take<T>(9 * (size_t)n);
+    L.lf2 = cv.take<T>(9 * (size_t)n);
+    L.lf3 = cv.take<T>(9 * (size_t)n);
+    L.lam = cv.take<T>(9 * (size_t)n);
+    L.lg1 = cv.take<T>(9 * (size_t)n);
+    L.F1 = cv.take<T>(9 * (size_t)n);
+    L.ltau = cv.take<T>(n);
+    L.lx = cv.take<T>(11 * (size_t)n);
+    L.lnet = cv.take<T>(2 * (size_t)n);
+    L.lown = cv.take<T>(4 * (size_t)n);
+    L.lgrad = cv.take<T>(8 * (size_t)n);
+    L.pbar = cv.take<double>(5 * (size_t)n);
+    return cv.off + 256;
+}
+
+template <typename T>
+AdjLayout<T> adj_layout(fvlbm_state *st) {
+    Carver cv;
+    cv.base = st->adj_ws;
+    AdjLayout<T> L;
+    adj_carve<T>(cv, st->n_cells, st->rec_steps, st->rec_ckpt, L);
+    return L;
+}
+
+// copy the current state (f, k, omega) into / out of a slot of 11 n values
+template <typename T>
+void save_state(fvlbm_state *st, T *slot) {
+    const size_t n = st->n_cells;
+    check(hipMemcpyAsync(slot, st->F, 9 * n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    if (st->sst) {
+        check(hipMemcpyAsync(slot + 9 * n, st->K[st->cur_kw], n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+        check(hipMemcpyAsync(slot + 10 * n, st->W[st->cur_kw], n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    }
+}
+
+template <typename T>
+void load_state(fvlbm_state *st, const T *slot) {
+    const size_t n = st->n_cells;
+    check(hipMemcpyAsync(st->F, slot, 9 * n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    if (st->sst) {
+        check(hipMemcpyAsync(st->K[st->cur_kw], slot + 9 * n, n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+        check(hipMemcpyAsync(st->W[st->cur_kw], slot + 10 * n, n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    }
+    k_macro<T><<<blocks_for(n), kBlock, 0, st->stream>>>((int)n, (const T *)st->F, (T *)st->M[st->cur_m], T(st->par.rho0));
+}
+
+template <typename T>
+void record(fvlbm_state *st) {
+    AdjLayout<T> L = adj_layout<T>(st);
+    const int C = st->rec_ckpt;
+    for (int32_t i = 0; i < st->rec_steps; ++i) {
+        if (i % C == 0) save_state<T>(st, L.ckpt + (size_t)(i / C) * L.state_len);
+        launch_step<T>(st);
+    }
+    const size_t nck = (size_t)((st->rec_steps + C - 1) / C);
+    save_state<T>(st, L.ckpt + nck * L.state_len);
+    st->steps_done += st->rec_steps;
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+}
+
+// Transposed convection at field f applied to L.lam, accumulated into out (theta into pbar[0]).
+template <typename T>
+void adv_transpose(fvlbm_state *st, const AdjLayout<T> &L, const T *f, T *out) {
+    const Geo<T> &g = geo_of<T>(st);
+    const int nbk = blocks_for(g.n);
+    k_adv_T1<T><<<nbk, kBlock, 0, st->stream>>>(g, f, L.lam, out, (T *)st->G, L.pbar, T(st->par.rho0));
+    k_adv_T2<T><<<nbk, kBlock, 0, st->stream>>>(g, st->rev, (const T *)st->G, out);
+}
+
+template <typename T>
+__global__ void k_scale(size_t n, const T *__restrict__ x, T a, T *__restrict__ y) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
+// Reverse of one step whose input state is in `slot` (on entry L.lF, L.lK, L.lW hold the adjoint
+// of the step's output; on exit that of its input).
+template <typename T>
+void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot) {
+    const Geo<T> &g = geo_of<T>(st);
+    const int n = g.n, nbk = blocks_for(n);
+    const size_t n9 = 9 * (size_t)n;
+    hipStream_t s = st->stream;
+    StepPar<T> p = step_par<T>(st->par);
+    // recompute the step: X = f3, Y = f2, A = Q, tau, aux; keep the input macro / k / omega buffers
+    load_state<T>(st, slot);
+    T *Mn = (T *)st->M[st->cur_m];
+    T *Kn = st->sst ? (T *)st->K[st->cur_kw] : nullptr, *Wn = st->sst ? (T *)st->W[st->cur_kw] : nullptr;
+    launch_step<T>(st);
+    const T *fn = slot;
+    k_collide1<T><<<nbk, kBlock, 0, s>>>(n, fn, (const T *)st->tau, L.F1, p);
+    AdjBufs<T> b{fn, L.F1, (const T *)st->Y, (const T *)st->X, (const T *)st->A, (const T *)st->tau,
+                 L.lF, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
+    // Ga3 with weight dt/3 in f^{n+1}
+    k_scale<T><<<blocks_for(n9), kBlock, 0, s>>>(n9, L.lF, p.dt / T(3), L.lam);
+    k_fill<T><<<blocks_for(n9), kBlock, 0, s>>>((int)n9, L.lf3, T(0));
+    adv_transpose<T>(st, L, (const T *)st->X, L.lf3);
+    k_adj_stage3<T><<<nbk, kBlock, 0, s>>>(n, b, p);
+    adv_transpose<T>(st, L, (const T *)st->Y, L.lf2);
+    k_adj_stage2<T><<<nbk, kBlock, 0, s>>>(n, b, p);
+    adv_transpose<T>(st, L, L.F1, L.lf1);
+    k_adj_stage1<T><<<nbk, kBlock, 0, s>>>(n, b, p);
+    if (st->sst) {
+        SstAdj sa{st->bzg, L.pbar};
+        k_fill<T><<<blocks_for(11 * (size_t)n), kBlock, 0, s>>>(11 * n, L.lx, T(0));
+        k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, (const T *)st->aux, L.lK, L.lW, L.ltau, L.lx, L.lnet, L.lown, p);
+        k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, (const T *)st->aux, L.lnet, L.lx, p);
+        k_adj_sst_local<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, L.lown, L.lx, L.lgrad, p);
+        k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, Mn, L.lgrad, L.lx, L.lF, L.lK, L.lW, p.rho0);
+    }
+    check(hipGetLastError(), "kernel launch");
+}
+
+// Reverse of the whole recorded run (L.lF / lK / lW seeded with the adjoint of the final state).
+template <typename T>
+void reverse_run(fvlbm_state *st, const AdjLayout<T> &L) {
+    const int N = st->rec_steps, C = st->rec_ckpt;
+    const int nseg = (N + C - 1) / C;
+    for (int sg = nseg - 1; sg >= 0; --sg) {
+        const int first = sg * C, last = std::min(N, first + C);
+        load_state<T>(st, L.ckpt + (size_t)sg * L.state_len);
+        for (int i = first; i < last; ++i) {
+            save_state<T>(st, L.seg + (size_t)(i - first) * L.state_len);
+            if (i + 1 < last) launch_step<T>(st);
+        }
+        for (int i = last - 1; i >= first; --i) reverse_step<T>(st, L, L.seg + (size_t)(i - first) * L.state_len);
+    }
+    // restore the final state
+    load_state<T>(st, L.ckpt + (size_t)nseg * L.state_len);
+    // macro buffers for a residual of a later step: both hold the final macro variables
+    check(hipMemcpyAsync(st->M[st->cur_m ^ 1], st->M[st->cur_m], 3 * (size_t)st->n_cells * sizeof(T),
+                         hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+}
+
+template <typename T>
+void reduce_pbar(fvlbm_state *st, const AdjLayout<T> &L, double out[5]) {
+    const int n = st->n_cells;
+    for (int i = 0; i < 5; ++i) {
+        k_sum<double><<<kRedBlocks, kBlock, 0, st->stream>>>(n, L.pbar + (size_t)i * n, st->partial);
+        k_finish<1><<<1, kBlock, 0, st->stream>>>(st->partial, kRedBlocks, st->result + i % 4);
+        check(hipMemcpyAsync(out + i, st->result + i % 4, sizeof(double), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
+        check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
+    }
+}
+
+template <typename T>
+void adjoint_forces(fvlbm_state *st, uint64_t mask, const double seed[3], double dparams[5]) {
+    AdjLayout<T> L = adj_layout<T>(st);
+    const Geo<T> &g = geo_of<T>(st);
+    const int n = g.n, nbk = blocks_for(n);
+    hipStream_t s = st->stream;
+    k_fill<T><<<blocks_for(9 * (size_t)n), kBlock, 0, s>>>(9 * n, L.lF, T(0));
+    k_fill<T><<<nbk, kBlock, 0, s>>>(n, L.lK, T(0));
+    k_fill<T><<<nbk, kBlock, 0, s>>>(n, L.lW, T(0));
+    k_fill<double><<<blocks_for(5 * (size_t)n), kBlock, 0, s>>>(5 * n, L.pbar, 0.0);
+    k_adj_forces<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->F, (unsigned long long)mask, st->par.jr_group, st->par.jr_xmin,
+                                          st->par.eps_tau, st->par.nu, seed[0], seed[1], seed[2], T(st->par.rho0), L.lF);
+    reverse_run<T>(st, L);
+    reduce_pbar<T>(st, L, dparams);
+}
+
+template <typename T>
+void adjoint_state(fvlbm_state *st, const double *lf, const double *lk, const double *lw, double *lf0, double *lk0,
+                   double *lw0, double dparams[5]) {
+    AdjLayout<T> L = adj_layout<T>(st);
+    const Geo<T> &g = geo_of<T>(st);
+    const int n = g.n, nbk = blocks_for(n);
+    hipStream_t s = st->stream;
+    upload_scratch(st, lf, 9 * (size_t)n);
+    k_import_f<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, L.lF, 0.0);
+    k_fill<T><<<nbk, kBlock, 0, s>>>(n, L.lK, T(0));
+    k_fill<T><<<nbk, kBlock, 0, s>>>(n, L.lW, T(0));
+    check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st->sst && lk) {
+        upload_scratch(st, lk, n);
+        k_import_scalar<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, L.lK);
+        check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    if (st->sst && lw) {
+        upload_scratch(st, lw, n);
+        k_import_scalar<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, L.lW);
+        check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    k_fill<double><<<blocks_for(5 * (size_t)n), kBlock, 0, s>>>(5 * n, L.pbar, 0.0);
+    reverse_run<T>(st, L);
+    k_export_f<T><<<nbk, kBlock, 0, s>>>(g, L.lF, st->scratch, 0.0);
+    check(hipMemcpyAsync(lf0, st->scratch, 9 * (size_t)n * sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+    check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st->sst && lk0) {
+        k_export_scalar<T><<<nbk, kBlock, 0, s>>>(g, L.lK, 0.0, st->scratch);
+        check(hipMemcpyAsync(lk0, st->scratch, n * sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+        check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    if (st->sst && lw0) {
+        k_export_scalar<T><<<nbk, kBlock, 0, s>>>(g, L.lW, 0.0, st->scratch);
+        check(hipMemcpyAsync(lw0, st->scratch, n * sizeof(double), hipMemcpyDeviceToHost, s), "hipMemcpyAsync D2H");
+        check(hipStreamSynchronize(s), "hipStreamSynchronize");
+    }
+    reduce_pbar<T>(st, L, dparams);
 }
 
 template <typename F>
@@ -759,6 +1017,78 @@ fvlbm_status fvlbm_mesh_max_dt(const fvlbm_mesh *m, double *dt) {
             }
         }
         *dt = 1.0 / worst;
+    });
+}
+
+fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, const double *lam, double *g_bar,
+                                           double *d_theta) {
+    return guarded([&] {
+        if (!st || !g_in || !lam || !g_bar || !d_theta) throw Error(FVLBM_EINVAL, "apply_advection_adjoint: NULL argument");
+        if (st->precision == FVLBM_FP64)
+            apply_advection_adjoint<double>(st, g_in, lam, g_bar, d_theta);
+        else
+            apply_advection_adjoint<float>(st, g_in, lam, g_bar, d_theta);
+    });
+}
+
+fvlbm_status fvlbm_adjoint_bytes(const fvlbm_mesh *m, int32_t precision, int32_t n_steps, int32_t ckpt_every,
+                                 size_t *bytes) {
+    return guarded([&] {
+        if (!m || !bytes) throw Error(FVLBM_EINVAL, "adjoint_bytes: NULL argument");
+        if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "adjoint_bytes: n_steps and ckpt_every must be >= 1");
+        Carver cv;
+        if (precision == FVLBM_FP64) {
+            AdjLayout<double> L;
+            *bytes = adj_carve<double>(cv, m->n, n_steps, std::min(ckpt_every, n_steps), L);
+        } else {
+            AdjLayout<float> L;
+            *bytes = adj_carve<float>(cv, m->n, n_steps, std::min(ckpt_every, n_steps), L);
+        }
+    });
+}
+
+fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, void *workspace, size_t ws_bytes) {
+    return guarded([&] {
+        if (!st || !workspace) throw Error(FVLBM_EINVAL, "record: NULL argument");
+        if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
+        if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");
+        size_t need = 0;
+        fvlbm_status e = fvlbm_adjoint_bytes(st->mesh, st->precision, n_steps, ckpt_every, &need);
+        if (e != FVLBM_OK) throw Error(e, fvlbm_last_error());
+        if (ws_bytes < need) throw Error(FVLBM_EINVAL, "record: workspace too small (" + std::to_string(ws_bytes) + " < " + std::to_string(need) + ")");
+        st->adj_ws = reinterpret_cast<char *>(workspace);
+        st->adj_bytes = ws_bytes;
+        st->rec_steps = n_steps;
+        st->rec_ckpt = std::min(ckpt_every, n_steps);
+        if (st->precision == FVLBM_FP64)
+            record<double>(st);
+        else
+            record<float>(st);
+    });
+}
+
+fvlbm_status fvlbm_adjoint_step(fvlbm_state *st, uint64_t wall_group_mask, const double seed[3], double dparams[5]) {
+    return guarded([&] {
+        if (!st || !seed || !dparams) throw Error(FVLBM_EINVAL, "adjoint_step: NULL argument");
+        if (!st->adj_ws) throw Error(FVLBM_ESTATE, "adjoint_step: no recorded run (call fvlbm_record first)");
+        if (st->precision == FVLBM_FP64)
+            adjoint_forces<double>(st, wall_group_mask, seed, dparams);
+        else
+            adjoint_forces<float>(st, wall_group_mask, seed, dparams);
+        for (int i = 0; i < 5; ++i)
+            if (!std::isfinite(dparams[i])) throw Error(FVLBM_EDIVERGED, "adjoint_step: non-finite gradient");
+    });
+}
+
+fvlbm_status fvlbm_adjoint_state(fvlbm_state *st, const double *lam_f, const double *lam_k, const double *lam_w,
+                                 double *lam_f0, double *lam_k0, double *lam_w0, double dparams[5]) {
+    return guarded([&] {
+        if (!st || !lam_f || !lam_f0 || !dparams) throw Error(FVLBM_EINVAL, "adjoint_state: NULL argument");
+        if (!st->adj_ws) throw Error(FVLBM_ESTATE, "adjoint_state: no recorded run (call fvlbm_record first)");
+        if (st->precision == FVLBM_FP64)
+            adjoint_state<double>(st, lam_f, lam_k, lam_w, lam_f0, lam_k0, lam_w0, dparams);
+        else
+            adjoint_state<float>(st, lam_f, lam_k, lam_w, lam_f0, lam_k0, lam_w0, dparams);
     });
 }
 

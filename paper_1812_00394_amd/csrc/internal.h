@@ -47,6 +47,7 @@ struct fvlbm_mesh {
     std::vector<int64_t> iperm;  // user -> internal
     std::vector<double> area, xc, yc, wdist;
     std::vector<int32_t> nbr;
+    std::vector<int8_t> rev;     // [kSlots][n]: slot of the neighbour that points back (interior slots)
     std::vector<double> nlx, nly, rfx, rfy, dx, dy, cx, cy;
     // boundary edges (periodic ones excluded), ordered by internal owner cell then slot
     std::vector<int32_t> b_cell, b_group, b_kind;

@@ -23,7 +23,7 @@ namespace fvlbm {
 template <typename T>
 struct StepPar {
     T rho0, dt, nu;
-    T a1, bstar, sk1, sk2, sw1, sw2, b1, b2, cw1, cw2;
+    T a1, bstar, sk1, sk2, sw1, sw2, b1, b2, kappa;
 };
 
 // ----------------------------------------------------------------------------------------------
@@ -442,20 +442,174 @@ template <typename T>
 __device__ __forceinline__ T tmax(T a, T b) { return a >= b ? a : b; }
 template <typename T>
 __device__ __forceinline__ T tmin(T a, T b) { return a <= b ? a : b; }
+template <typename T, int K>
+__device__ __forceinline__ Dual<T, K> tmax(const Dual<T, K> &a, const Dual<T, K> &b) { return dmax(a, b); }
+template <typename T, int K>
+__device__ __forceinline__ Dual<T, K> tmin(const Dual<T, K> &a, const Dual<T, K> &b) { return dmin(a, b); }
+template <typename T>
+__device__ __forceinline__ T ssqrt(T a) { return sqrt(a); }
+template <typename T>
+__device__ __forceinline__ T stanh(T a) { return tanh(a); }
+template <typename T, int K>
+__device__ __forceinline__ Dual<T, K> ssqrt(const Dual<T, K> &a) { return dsqrt(a); }
+template <typename T, int K>
+__device__ __forceinline__ Dual<T, K> stanh(const Dual<T, K> &a) { return dtanh(a); }
+template <typename S>
+__device__ __forceinline__ S sval(const S &a) { return a; }
+template <typename T, int K>
+__device__ __forceinline__ T sval(const Dual<T, K> &a) { return a.v; }
+
+// The four SST constants the adjoint differentiates (a1, beta*, sigma_k1, sigma_omega1), in the
+// scalar type S; the others come from StepPar.
+template <typename S>
+struct SstParams {
+    S a1, bstar, sk1, sw1;
+};
+
+// Cell-local closure of the SST model (Section 2): from rho, k, omega, the wall distance d and the
+// gradients of u, v, k, omega, the diffusion coefficients Gamma_k, Gamma_omega, the explicit
+// sources dt P / rho and dt (P_omega + cross diffusion) / rho, the blended beta and the strain S.
+template <typename S>
+struct SstLocal {
+    S Gk, Gw, sk, sw, beta, Sr;
+};
+
+template <typename S, typename T>
+__device__ __forceinline__ SstLocal<S> sst_local(S rho, S k, S w, S dux, S duy, S dvx, S dvy, S dkx, S dky, S dwx,
+                                                 S dwy, T d, const StepPar<T> &p, const SstParams<S> &q) {
+    // C_omega_i = beta_i / beta* - sigma_omega_i kappa^2 / sqrt(beta*)
+    const S sb = ssqrt(q.bstar);
+    const S cw1 = cst<S>(p.b1) / q.bstar - q.sw1 * cst<S>(p.kappa * p.kappa) / sb;
+    const S cw2 = cst<S>(p.b2) / q.bstar - cst<S>(p.sw2 * p.kappa * p.kappa) / sb;
+    const S s11 = dux, s22 = dvy, s12 = cst<S>(0.5) * (duy + dvx);
+    const S S2 = cst<S>(2) * (s11 * s11 + s22 * s22 + cst<S>(2) * s12 * s12);
+    const S Sr = ssqrt(S2);
+    const S div = dux + dvy;
+    const S gkgw = dkx * dwx + dky * dwy;
+    const S CD = tmax(cst<S>(2) * rho * cst<S>(p.sw2) / w * gkgw, cst<S>(1e-20));
+    const S sk = ssqrt(k);
+    const S dd = cst<S>(d);
+    const S visc = cst<S>(500) * cst<S>(p.nu) / (w * dd * dd);
+    const S arg1 = tmin(tmax(sk / (cst<S>(0.09) * w * dd), visc), cst<S>(4) * rho * cst<S>(p.sw2) * k / (CD * dd * dd));
+    const S a2 = arg1 * arg1;
+    const S F1 = stanh(a2 * a2);
+    const S arg2 = tmax(cst<S>(2) * sk / (cst<S>(0.09) * w * dd), visc);
+    const S F2 = stanh(arg2 * arg2);
+    const S den = tmax(q.a1 * w, Sr * F2);
+    const S mu = rho * cst<S>(p.nu);
+    const S mut = q.a1 * rho * k / den;
+    const S one = cst<S>(1);
+    const S sig_k = F1 * q.sk1 + (one - F1) * cst<S>(p.sk2);
+    const S sig_w = F1 * q.sw1 + (one - F1) * cst<S>(p.sw2);
+    const S beta = F1 * cst<S>(p.b1) + (one - F1) * cst<S>(p.b2);
+    const S gam = F1 * cw1 + (one - F1) * cw2;
+    const S tt = cst<S>(2.0 / 3.0);
+    const S P = mut * (S2 - tt * div * div) - tt * rho * k * div;
+    // gamma rho P / mu_t without the 0/0 at k = 0: rho k / mu_t = den / a1
+    const S Pw = gam * rho * (S2 - tt * div * div) - tt * gam * rho * (den / q.a1) * div;
+    const S cross = cst<S>(2) * (one - F1) * rho * cst<S>(p.sw2) * gkgw / w;
+    SstLocal<S> o;
+    o.Gk = mu + sig_k * mut;
+    o.Gw = mu + sig_w * mut;
+    o.sk = cst<S>(p.dt) / rho * P;
+    o.sw = cst<S>(p.dt) / rho * (Pw + cross);
+    o.beta = beta;
+    o.Sr = Sr;
+    return o;
+}
+
+// Upwind k / omega face value, kept in [0, 2 phi_up] so the explicit outflow cannot drive k or
+// omega negative (inactive where |grad phi . r| <= phi_up).
+template <typename S>
+__device__ __forceinline__ S bound_face(S v, S up) { return tmin(tmax(v, cst<S>(0)), cst<S>(2) * up); }
+
+// Convective and diffusive flux of k and omega through an interior edge, seen from cell c (the
+// contribution to c's net inflow): -mdot phi_f + Gamma_f (phi_N - phi_c) (d^ . n l) / |d|, with
+// mdot = ((rho u)_c + (rho u)_N) / 2 . n l and phi_f the bounded upwind extrapolation.
+// Cell data x = (rho, u, v, k, omega, dk/dx, dk/dy, domega/dx, domega/dy, Gamma_k, Gamma_omega).
+template <typename S, typename T>
+__device__ __forceinline__ void sst_face(const S xc[11], const S xn[11], T nlx, T nly, T rx, T ry, T qx, T qy, S &Tk,
+                                         S &Tw) {
+    const S mdot = cst<S>(0.5) * ((xc[0] * xc[1] + xn[0] * xn[1]) * cst<S>(nlx) + (xc[0] * xc[2] + xn[0] * xn[2]) * cst<S>(nly));
+    S kf, wf;
+    if (sval(mdot) >= 0) {
+        kf = bound_face(xc[3] + xc[5] * cst<S>(rx) + xc[6] * cst<S>(ry), xc[3]);
+        wf = bound_face(xc[4] + xc[7] * cst<S>(rx) + xc[8] * cst<S>(ry), xc[4]);
+    } else {
+        kf = bound_face(xn[3] + xn[5] * cst<S>(qx) + xn[6] * cst<S>(qy), xn[3]);
+        wf = bound_face(xn[4] + xn[7] * cst<S>(qx) + xn[8] * cst<S>(qy), xn[4]);
+    }
+    // central two-point face gradient along the centroid line: (phi_N - phi_c) / |d| d^
+    const T ddx = rx - qx, ddy = ry - qy;
+    const T dist = sqrt(ddx * ddx + ddy * ddy);
+    const T hn = (ddx * nlx + ddy * nly) / (dist * dist);
+    Tk = -(mdot * kf) + cst<S>(0.5) * (xc[9] + xn[9]) * (xn[3] - xc[3]) * cst<S>(hn);
+    Tw = -(mdot * wf) + cst<S>(0.5) * (xc[10] + xn[10]) * (xn[4] - xc[4]) * cst<S>(hn);
+}
+
+// The same through a boundary edge: ghost values are the cell's own where zero-gradient (zg),
+// else the boundary data (ub velocity, kb, wb); Dirichlet diffusion (phi_b - phi_c) l / d_perp.
+template <typename S, typename T>
+__device__ __forceinline__ void sst_bface(const S xc[11], bool zg, S ubx, S uby, T kb, T wb, T nlx, T nly, T rx, T ry,
+                                          T l_over_dp, S &Tk, S &Tw) {
+    const S bux = zg ? xc[1] : ubx, buy = zg ? xc[2] : uby;
+    const S bk = zg ? xc[3] : cst<S>(kb), bw = zg ? xc[4] : cst<S>(wb);
+    const S mdot = xc[0] * (bux * cst<S>(nlx) + buy * cst<S>(nly));
+    S kf, wf;
+    if (sval(mdot) >= 0) {
+        kf = bound_face(xc[3] + xc[5] * cst<S>(rx) + xc[6] * cst<S>(ry), xc[3]);
+        wf = bound_face(xc[4] + xc[7] * cst<S>(rx) + xc[8] * cst<S>(ry), xc[4]);
+    } else {
+        kf = bk;
+        wf = bw;
+    }
+    Tk = -(mdot * kf);
+    Tw = -(mdot * wf);
+    if (!zg) {
+        Tk = Tk + xc[9] * (bk - xc[3]) * cst<S>(l_over_dp);
+        Tw = Tw + xc[10] * (bw - xc[4]) * cst<S>(l_over_dp);
+    }
+}
+
+// Point-implicit update (negative parts of the explicit sources join the denominator), floor,
+// and the eddy viscosity from the updated k, omega with the level-n strain rate.
+template <typename S, typename T>
+__device__ __forceinline__ void sst_update(S rho, S k, S w, S net_k, S net_w, S sk, S sw, S beta, S Sr, T d,
+                                           T inv_area, const StepPar<T> &p, const SstParams<S> &q, S &k1, S &w1,
+                                           S &nut) {
+    const S fac = cst<S>(p.dt * inv_area) / rho;
+    const S zero = cst<S>(0), one = cst<S>(1), dt = cst<S>(p.dt);
+    k1 = (k + fac * net_k + tmax(sk, zero)) / (one + dt * q.bstar * w + tmax(-sk, zero) / k);
+    w1 = (w + fac * net_w + tmax(sw, zero)) / (one + dt * beta * w + tmax(-sw, zero) / w);
+    k1 = tmax(k1, cst<S>(1e-20));
+    w1 = tmax(w1, cst<S>(1e-20));
+    const S dd = cst<S>(d);
+    const S arg2 = tmax(cst<S>(2) * ssqrt(k1) / (cst<S>(0.09) * w1 * dd), cst<S>(500) * cst<S>(p.nu) / (w1 * dd * dd));
+    const S F2 = stanh(arg2 * arg2);
+    nut = q.a1 * k1 / tmax(q.a1 * w1, Sr * F2);
+}
 
 template <typename T>
-__device__ __forceinline__ T bound_face(T v, T up) { return tmin(tmax(v, T(0)), T(2) * up); }
+__device__ __forceinline__ SstParams<T> sst_params(const StepPar<T> &p) {
+    return SstParams<T>{p.a1, p.bstar, p.sk1, p.sw1};
+}
 
+// ----------------------------------------------------------------------------------------------
+// k-omega SST kernels (Section 2 model; finite-volume form Eq. (SSTequint)).
+// aux planes: 0,1 grad k; 2,3 grad omega; 4 Gamma_k; 5 Gamma_omega; 6 dt P / rho;
+//             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S.
+// Boundary data per edge (set at init): b_ux, b_uy velocity (0 on resting walls), b_k (0 on walls),
+// b_w (60 nu / (beta1 d_perp^2) on walls), and b_zg = 1 where k, omega, u are zero-gradient
+// (outlets, far-field outflow edges).
+// ----------------------------------------------------------------------------------------------
+// LSQ gradients of u, v, k, omega of cell c (ghost values at boundary edges as above).
 template <typename T>
-__global__ void __launch_bounds__(256) k_sst_a(Geo<T> g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
-                                               const T *__restrict__ K, const T *__restrict__ W,
-                                               T *__restrict__ aux, StepPar<T> p) {
-    const int c = cell_index();
-    if (c >= g.n) return;
+__device__ __forceinline__ void sst_gradients(const Geo<T> &g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
+                                              const T *__restrict__ K, const T *__restrict__ W, int c, T gu[2], T gv[2],
+                                              T gk[2], T gw[2]) {
     const int n = g.n;
-    const T rho = p.rho0 + M[c], ux = M[(size_t)n + c], uy = M[(size_t)2 * n + c];
-    const T kc = K[c], wc = W[c];
-    T gu[2] = {0, 0}, gv[2] = {0, 0}, gk[2] = {0, 0}, gw[2] = {0, 0};
+    const T ux = M[(size_t)n + c], uy = M[(size_t)2 * n + c], kc = K[c], wc = W[c];
+    gu[0] = gu[1] = gv[0] = gv[1] = gk[0] = gk[1] = gw[0] = gw[1] = T(0);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const size_t si = (size_t)s * n + c;
@@ -484,42 +638,43 @@ __global__ void __launch_bounds__(256) k_sst_a(Geo<T> g, const int32_t *__restri
         gk[0] += cxs * dk; gk[1] += cys * dk;
         gw[0] += cxs * dw; gw[1] += cys * dw;
     }
-    const T d = T(g.wdist[c]);
-    const T s11 = gu[0], s22 = gv[1], s12 = T(0.5) * (gu[1] + gv[0]);
-    const T S2 = T(2) * (s11 * s11 + s22 * s22 + T(2) * s12 * s12);
-    const T S = sqrt(S2);
-    const T div = gu[0] + gv[1];
-    const T gkgw = gk[0] * gw[0] + gk[1] * gw[1];
-    const T CD = tmax(T(2) * rho * p.sw2 / wc * gkgw, T(1e-20));
-    const T sk = sqrt(kc);
-    const T visc = T(500) * p.nu / (wc * d * d);
-    const T arg1 = tmin(tmax(sk / (T(0.09) * wc * d), visc), T(4) * rho * p.sw2 * kc / (CD * d * d));
-    const T a4 = arg1 * arg1 * arg1 * arg1;
-    const T F1 = tanh(a4);
-    const T arg2 = tmax(T(2) * sk / (T(0.09) * wc * d), visc);
-    const T F2 = tanh(arg2 * arg2);
-    const T den = tmax(p.a1 * wc, S * F2);
-    const T mu = rho * p.nu;
-    const T mut = p.a1 * rho * kc / den;
-    const T sig_k = F1 * p.sk1 + (T(1) - F1) * p.sk2;
-    const T sig_w = F1 * p.sw1 + (T(1) - F1) * p.sw2;
-    const T beta = F1 * p.b1 + (T(1) - F1) * p.b2;
-    const T gam = F1 * p.cw1 + (T(1) - F1) * p.cw2;
-    const T twothird = T(2) / T(3);
-    const T P = mut * (S2 - twothird * div * div) - twothird * rho * kc * div;
-    // gamma rho P / mu_t without the 0/0 at k = 0: rho k / mu_t = den / a1
-    const T Pw = gam * rho * (S2 - twothird * div * div) - twothird * gam * rho * (den / p.a1) * div;
-    const T cross = T(2) * (T(1) - F1) * rho * p.sw2 * gkgw / wc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_sst_a(Geo<T> g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
+                                               const T *__restrict__ K, const T *__restrict__ W,
+                                               T *__restrict__ aux, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gu[2], gv[2], gk[2], gw[2];
+    sst_gradients(g, bzg, M, K, W, c, gu, gv, gk, gw);
+    const T rho = p.rho0 + M[c];
+    const SstLocal<T> o = sst_local<T, T>(rho, K[c], W[c], gu[0], gu[1], gv[0], gv[1], gk[0], gk[1], gw[0], gw[1],
+                                          T(g.wdist[c]), p, sst_params(p));
     aux[c] = gk[0];
     aux[(size_t)1 * n + c] = gk[1];
     aux[(size_t)2 * n + c] = gw[0];
     aux[(size_t)3 * n + c] = gw[1];
-    aux[(size_t)4 * n + c] = mu + sig_k * mut;
-    aux[(size_t)5 * n + c] = mu + sig_w * mut;
-    aux[(size_t)6 * n + c] = p.dt / rho * P;
-    aux[(size_t)7 * n + c] = p.dt / rho * (Pw + cross);
-    aux[(size_t)8 * n + c] = beta;
-    aux[(size_t)9 * n + c] = S;
+    aux[(size_t)4 * n + c] = o.Gk;
+    aux[(size_t)5 * n + c] = o.Gw;
+    aux[(size_t)6 * n + c] = o.sk;
+    aux[(size_t)7 * n + c] = o.sw;
+    aux[(size_t)8 * n + c] = o.beta;
+    aux[(size_t)9 * n + c] = o.Sr;
+}
+
+// The 11 cell values the SST face flux uses (see sst_face).
+template <typename T>
+__device__ __forceinline__ void sst_cell_x(int n, int c, T rho0, const T *__restrict__ M, const T *__restrict__ K,
+                                           const T *__restrict__ W, const T *__restrict__ aux, T x[11]) {
+    x[0] = rho0 + M[c];
+    x[1] = M[(size_t)n + c];
+    x[2] = M[(size_t)2 * n + c];
+    x[3] = K[c];
+    x[4] = W[c];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) x[5 + i] = aux[(size_t)i * n + c];
 }
 
 template <typename T>
@@ -530,80 +685,31 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
     const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
-    const T rho = p.rho0 + M[c], ux = M[(size_t)n + c], uy = M[(size_t)2 * n + c];
-    const T kc = K[c], wc = W[c];
-    const T gkc[2] = {aux[c], aux[(size_t)n + c]};
-    const T gwc[2] = {aux[(size_t)2 * n + c], aux[(size_t)3 * n + c]};
-    const T Gkc = aux[(size_t)4 * n + c], Gwc = aux[(size_t)5 * n + c];
+    T xc[11];
+    sst_cell_x(n, c, p.rho0, M, K, W, aux, xc);
     T net_k = 0, net_w = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const size_t si = (size_t)s * n + c;
         const int nb = g.nbr[si];
         if (nb == -1) continue;
-        const T nlx = g.nlx[si], nly = g.nly[si];
-        const T rx = g.rfx[si], ry = g.rfy[si];
-        // own value extrapolated to the edge, kept in [0, 2 phi_c] so the explicit outflow
-        // cannot drive k or omega negative (inactive where |grad phi . r| <= phi_c)
-        const T ks = bound_face(kc + gkc[0] * rx + gkc[1] * ry, kc);
-        const T ws = bound_face(wc + gwc[0] * rx + gwc[1] * ry, wc);
+        T tk, tw;
         if (nb >= 0) {
-            const T rhoN = p.rho0 + M[nb], uxN = M[(size_t)n + nb], uyN = M[(size_t)2 * n + nb];
-            const T mdot = T(0.5) * ((rho * ux + rhoN * uxN) * nlx + (rho * uy + rhoN * uyN) * nly);
-            const T kN = K[nb], wN = W[nb];
-            const T gkN[2] = {aux[nb], aux[(size_t)n + nb]};
-            const T gwN[2] = {aux[(size_t)2 * n + nb], aux[(size_t)3 * n + nb]};
-            T kf, wf;
-            if (mdot >= T(0)) {
-                kf = ks;
-                wf = ws;
-            } else {
-                const T qx = g.qx[si], qy = g.qy[si];
-                kf = bound_face(kN + gkN[0] * qx + gkN[1] * qy, kN);
-                wf = bound_face(wN + gwN[0] * qx + gwN[1] * qy, wN);
-            }
-            const T ddx = rx - g.qx[si], ddy = ry - g.qy[si];   // x_N' - x_c
-            const T dist = sqrt(ddx * ddx + ddy * ddy);
-            const T hx = ddx / dist, hy = ddy / dist;
-            const T GkN = aux[(size_t)4 * n + nb], GwN = aux[(size_t)5 * n + nb];
-            // central two-point face gradient along the centroid line: (phi_N - phi_c) / |d| d^
-            const T hn = (hx * nlx + hy * nly) / dist;
-            const T dk = T(0.5) * (Gkc + GkN) * (kN - kc) * hn;
-            const T dw = T(0.5) * (Gwc + GwN) * (wN - wc) * hn;
-            net_k += -mdot * kf + dk;
-            net_w += -mdot * wf + dw;
+            T xn[11];
+            sst_cell_x(n, nb, p.rho0, M, K, W, aux, xn);
+            sst_face<T, T>(xc, xn, g.nlx[si], g.nly[si], g.rfx[si], g.rfy[si], g.qx[si], g.qy[si], tk, tw);
         } else {
             const int b = -2 - nb;
-            const bool zg = bzg[b] != 0;
-            const T ubx = zg ? ux : T(g.b_ux[b]);
-            const T uby = zg ? uy : T(g.b_uy[b]);
-            const T kb = zg ? kc : T(g.b_k[b]);
-            const T wb = zg ? wc : T(g.b_w[b]);
-            const T mdot = rho * (ubx * nlx + uby * nly);
-            const T kf = mdot >= T(0) ? ks : kb;
-            const T wf = mdot >= T(0) ? ws : wb;
-            T dk = 0, dw = 0;
-            if (!zg) {
-                const T f = T(g.b_l[b]) / T(g.b_dperp[b]);
-                dk = Gkc * (kb - kc) * f;
-                dw = Gwc * (wb - wc) * f;
-            }
-            net_k += -mdot * kf + dk;
-            net_w += -mdot * wf + dw;
+            sst_bface<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), g.nlx[si], g.nly[si],
+                            g.rfx[si], g.rfy[si], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
         }
+        net_k += tk;
+        net_w += tw;
     }
-    const T fac = p.dt * g.inv_area[c] / rho;
-    // point-implicit update; the negative part of each explicit source joins the denominator
-    const T sk = aux[(size_t)6 * n + c], sw = aux[(size_t)7 * n + c];
-    T k1 = (kc + fac * net_k + tmax(sk, T(0))) / (T(1) + p.dt * p.bstar * wc + tmax(-sk, T(0)) / kc);
-    T w1 = (wc + fac * net_w + tmax(sw, T(0))) / (T(1) + p.dt * aux[(size_t)8 * n + c] * wc + tmax(-sw, T(0)) / wc);
-    k1 = tmax(k1, T(1e-20));
-    w1 = tmax(w1, T(1e-20));
-    const T d = T(g.wdist[c]);
-    const T S = aux[(size_t)9 * n + c];
-    const T arg2 = tmax(T(2) * sqrt(k1) / (T(0.09) * w1 * d), T(500) * p.nu / (w1 * d * d));
-    const T F2 = tanh(arg2 * arg2);
-    const T nt = p.a1 * k1 / tmax(p.a1 * w1, S * F2);
+    T k1, w1, nt;
+    sst_update<T, T>(xc[0], xc[3], xc[4], net_k, net_w, aux[(size_t)6 * n + c], aux[(size_t)7 * n + c],
+                     aux[(size_t)8 * n + c], aux[(size_t)9 * n + c], T(g.wdist[c]), g.inv_area[c], p, sst_params(p),
+                     k1, w1, nt);
     K1[c] = k1;
     W1[c] = w1;
     nut[c] = nt;
@@ -639,6 +745,14 @@ __global__ void __launch_bounds__(256) k_finish(const double *__restrict__ parti
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] += partial[(size_t)b * NV + k];
     block_store<NV>(v, out);
+}
+
+// sum of an n-array
+template <typename T>
+__global__ void __launch_bounds__(256) k_sum(int n, const T *__restrict__ x, double *__restrict__ partial) {
+    double v[1] = {0};
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) v[0] += (double)x[c];
+    block_store<1>(v, partial);
 }
 
 // sum |u_new - u_old|^2, sum |u_new|^2

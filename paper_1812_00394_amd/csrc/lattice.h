@@ -10,7 +10,23 @@
 
 #include <cstdint>
 
+#include "dual.h"
+
 namespace fvlbm {
+
+enum : int32_t { kWall = 1, kMovingWall = 2, kInlet = 3, kOutlet = 4, kFarfield = 5 };
+
+// Scalar constants for generic code: S is float, double or a dual number over one of them.
+template <class S>
+struct ScalarBase {
+    using type = S;
+};
+template <class T, int K>
+struct ScalarBase<Dual<T, K>> {
+    using type = T;
+};
+template <class S>
+__device__ __forceinline__ S cst(double x) { return S(typename ScalarBase<S>::type(x)); }
 
 // Lattice velocities of Qian's D2Q9 model and their weights (a = 0 rest, 1-4 axes, 5-8 diagonals).
 __host__ __device__ constexpr int ex(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0); }
@@ -52,21 +68,22 @@ struct Geo {
 
 // Equilibrium deviation f_eq,a(rho, u) - w_a rho0, with drho = rho - rho0 (second-order D2Q9
 // equilibrium w_a rho (1 + 3 e.u + 4.5 (e.u)^2 - 1.5 u^2)).
-template <typename T>
-__device__ __forceinline__ T dfeq(int a, T drho, T rho, T ux, T uy) {
-    T eu = T(ex(a)) * ux + T(ey(a)) * uy;
-    return wt<T>(a) * (drho + rho * (T(3) * eu + T(4.5) * eu * eu - T(1.5) * (ux * ux + uy * uy)));
+template <typename S>
+__device__ __forceinline__ S dfeq(int a, S drho, S rho, S ux, S uy) {
+    S eu = cst<S>(ex(a)) * ux + cst<S>(ey(a)) * uy;
+    return cst<S>(a == 0 ? 4.0 / 9.0 : (a < 5 ? 1.0 / 9.0 : 1.0 / 36.0)) *
+           (drho + rho * (cst<S>(3) * eu + cst<S>(4.5) * eu * eu - cst<S>(1.5) * (ux * ux + uy * uy)));
 }
 
 // Density deviation and velocity of a deviation vector (the collision invariants 1, e_x, e_y).
-template <typename T>
-__device__ __forceinline__ void moments(const T d[9], T rho0, T &drho, T &rho, T &ux, T &uy) {
-    T s = 0, jx = 0, jy = 0;
+template <typename S>
+__device__ __forceinline__ void moments(const S d[9], S rho0, S &drho, S &rho, S &ux, S &uy) {
+    S s = cst<S>(0), jx = cst<S>(0), jy = cst<S>(0);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        s += d[a];
-        jx += T(ex(a)) * d[a];
-        jy += T(ey(a)) * d[a];
+        s = s + d[a];
+        jx = jx + cst<S>(ex(a)) * d[a];
+        jy = jy + cst<S>(ey(a)) * d[a];
     }
     drho = s;
     rho = rho0 + s;
@@ -99,26 +116,23 @@ __device__ __forceinline__ void stage_collide_m(const T rhs[9], T a, T drho, T r
     for (int q = 0; q < 9; ++q) out[q] = (rhs[q] + a * dfeq(q, drho, rho, ux, uy)) * inv;
 }
 
-enum : int32_t { kWall = 1, kMovingWall = 2, kInlet = 3, kOutlet = 4, kFarfield = 5 };
-
 // Ghost deviation at the midpoint of boundary edge b of a cell whose state is gc (moments drho,
 // rho, ux, uy), non-equilibrium extrapolation from the cell:
 //   walls: f_eq(rho_c, u_w) + (g_c - f_eq(rho_c, u_c)) for every direction;
 //   inlet / outlet / far field: replaced for incoming directions (e.n < 0) only.
-template <typename T>
-__device__ __forceinline__ void ghost(const Geo<T> &g, int b, T nlx, T nly, const T gc[9], T drho, T rho, T ux,
-                                      T uy, T gb[9]) {
-    const int kind = g.b_kind[b];
-    const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]);
-    const T rb = T(g.b_rho[b]), drb = T(g.b_drho[b]);
+// The ghost state for a boundary edge of the given kind, boundary velocity ub and density rb
+// (drb = rb - rho0); generic in the scalar type S (the adjoint evaluates it on dual numbers).
+template <typename S, typename T>
+__device__ __forceinline__ void ghost_state(int kind, S ubx, S uby, S rb, S drb, T nlx, T nly, const S gc[9], S drho,
+                                            S rho, S ux, S uy, S gb[9]) {
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
-        const T neq = gc[a] - dfeq(a, drho, rho, ux, uy);
-        T v;
+        const S neq = gc[a] - dfeq(a, drho, rho, ux, uy);
+        S v;
         if (kind == kWall || kind == kMovingWall) {
             v = dfeq(a, drho, rho, ubx, uby) + neq;
-        } else if (en < 0) {
+        } else if (en < T(0)) {
             if (kind == kInlet)
                 v = dfeq(a, drho, rho, ubx, uby) + neq;
             else if (kind == kOutlet)
@@ -130,6 +144,13 @@ __device__ __forceinline__ void ghost(const Geo<T> &g, int b, T nlx, T nly, cons
         }
         gb[a] = v;
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void ghost(const Geo<T> &g, int b, T nlx, T nly, const T gc[9], T drho, T rho, T ux,
+                                      T uy, T gb[9]) {
+    ghost_state<T, T>(g.b_kind[b], T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_rho[b]), T(g.b_drho[b]), nlx, nly, gc, drho, rho,
+                      ux, uy, gb);
 }
 
 }  // namespace fvlbm

@@ -365,6 +365,7 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
         m->yc[i] = cyu[perm[i]];
     }
     m->nbr.assign(kSlots * N, -1);
+    m->rev.assign(kSlots * N, 0);
     for (auto *v : {&m->nlx, &m->nly, &m->rfx, &m->rfy, &m->dx, &m->dy, &m->cx, &m->cy}) v->assign(kSlots * N, 0.0);
     for (int64_t i = 0; i < N; ++i) {
         int64_t u = perm[i], p0 = cell_ptr[u], nv = cell_ptr[u + 1] - p0;
@@ -382,6 +383,7 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
             if (partner[h] >= 0) {
                 int64_t nb = hcell[partner[h]];
                 m->nbr[s] = (int32_t)m->iperm[nb];
+                m->rev[s] = (int8_t)(partner[h] - cell_ptr[nb]);
                 m->dx[s] = cxu[nb] + pshift_x[h] - cxu[u];
                 m->dy[s] = cyu[nb] + pshift_y[h] - cyu[u];
             } else {

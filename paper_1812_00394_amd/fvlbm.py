@@ -53,7 +53,9 @@ _lib = None
 EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlbm_mesh_geometry",
            "fvlbm_mesh_permutation", "fvlbm_state_bytes", "fvlbm_init", "fvlbm_set_state", "fvlbm_step",
            "fvlbm_moments", "fvlbm_get_f", "fvlbm_forces", "fvlbm_apply_advection", "fvlbm_state_destroy",
-           "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read"]
+           "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read",
+           "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
+           "fvlbm_adjoint_state"]
 KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3"]
 
 
@@ -86,6 +88,11 @@ def lib():
     L.fvlbm_mesh_max_dt.argtypes = [P, P]
     L.fvlbm_timing.argtypes = [P, I32]
     L.fvlbm_timing_read.argtypes = [P, P, P]
+    L.fvlbm_apply_advection_adjoint.argtypes = [P, P, P, P, P]
+    L.fvlbm_adjoint_bytes.argtypes = [P, I32, I32, I32, C.POINTER(C.c_size_t)]
+    L.fvlbm_record.argtypes = [P, I32, I32, P, C.c_size_t]
+    L.fvlbm_adjoint_step.argtypes = [P, C.c_uint64, P, P]
+    L.fvlbm_adjoint_state.argtypes = [P, P, P, P, P, P, P, P]
     L.fvlbm_state_destroy.argtypes = [P]
     L.fvlbm_state_destroy.restype = None
     L.fvlbm_last_error.restype = C.c_char_p
@@ -265,6 +272,45 @@ class State:
         out = np.zeros((9, n))
         _check(lib().fvlbm_apply_advection(self.handle, _ptr(g), _ptr(out)))
         return out
+
+    def apply_advection_adjoint(self, g, lam):
+        """(d Gamma^a(g)/dg)^T lam and d(lam . Gamma^a(g))/d theta"""
+        n = self.mesh.n_cells
+        g = _f64(g, (9, n))
+        lam = _f64(lam, (9, n))
+        out = np.zeros((9, n))
+        dth = np.zeros(1)
+        _check(lib().fvlbm_apply_advection_adjoint(self.handle, _ptr(g), _ptr(lam), _ptr(out), _ptr(dth)))
+        return out, float(dth[0])
+
+    # ---- adjoint ----
+    def record(self, n_steps, ckpt_every=20):
+        """advance n_steps steps, storing checkpoints for the adjoint"""
+        import torch
+        b = C.c_size_t()
+        prec = FP64 if self.precision == "fp64" else FP32_DEV
+        _check(lib().fvlbm_adjoint_bytes(self.mesh.handle, prec, int(n_steps), int(ckpt_every), C.byref(b)))
+        self.adj_workspace = torch.empty(b.value, dtype=torch.uint8, device=self.workspace.device)
+        _check(lib().fvlbm_record(self.handle, int(n_steps), int(ckpt_every),
+                                  C.c_void_p(self.adj_workspace.data_ptr()), b.value))
+
+    def adjoint(self, group_mask, seed):
+        """dJ/d(theta, sigma_k1, sigma_w1, beta*, a1) for J = seed . (F_x, F_y, J_R) of the final state"""
+        sd = _f64(seed, (3,))
+        out = np.zeros(5)
+        _check(lib().fvlbm_adjoint_step(self.handle, C.c_uint64(group_mask), _ptr(sd), _ptr(out)))
+        return out
+
+    def adjoint_state(self, lam_f, lam_k=None, lam_w=None):
+        n = self.mesh.n_cells
+        lf = _f64(lam_f, (9, n))
+        lk = _f64(lam_k, (n,)) if lam_k is not None else None
+        lw = _f64(lam_w, (n,)) if lam_w is not None else None
+        of, ok, ow = np.zeros((9, n)), np.zeros(n), np.zeros(n)
+        dp = np.zeros(5)
+        _check(lib().fvlbm_adjoint_state(self.handle, _ptr(lf), _ptr(lk), _ptr(lw), _ptr(of),
+                                         _ptr(ok) if self.sst else None, _ptr(ow) if self.sst else None, _ptr(dp)))
+        return of, ok, ow, dp
 
     def timing(self, enable=True):
         _check(lib().fvlbm_timing(self.handle, int(bool(enable))))

@@ -1,0 +1,209 @@
+"""GPU adjoint: transposed operators and the full discrete adjoint against complex-step derivatives
+of the FP64 oracle (h = 1e-30, exact to rounding) and centred finite differences.
+
+Dot-product tests: for the transpose A^T of an operator's Jacobian A at a state, <A^T lam, v> must
+equal <lam, A v>, where A v is the oracle's complex-step directional derivative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fvlbm_oracle as O
+from paper_1812_00394_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+H = 1e-30
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1812_00394_amd import fvlbm
+    fvlbm.lib()
+    return fvlbm
+
+
+MESHES = {
+    "cavity": (lambda: mg.cavity(n=10, jitter=0.2, seed=61), dict(group_u=[[0, 0], [0.1, 0]])),
+    "periodic": (lambda: mg.rectangle(7, 6, kind="periodic", jitter=0.25, seed=62), dict()),
+    "duct": (lambda: mg.rectangle(9, 6, Lx=1.4, kind="duct", jitter=0.25, seed=63),
+             dict(group_u=[[0.05, 0.01], [0, 0], [0.05, 0.0]], group_rho=[1.0, 1.002, 1.0], theta=0.2)),
+    "naca": (lambda: mg.naca_omesh(n_wall=32, n_normal=10, y1=2e-3, radius=6.0),
+             dict(group_u=[[0, 0], [0.05, 0]], theta=0.1)),
+}
+
+
+def _state(n, rng):
+    rho = 1 + 0.01 * rng.standard_normal(n)
+    ux, uy = 0.05 * rng.standard_normal((2, n))
+    return O.feq(rho, ux, uy) + 2e-4 * O.WT[:, None] * rng.standard_normal((9, n))
+
+
+@pytest.mark.parametrize("name", sorted(MESHES))
+def test_advection_transpose_dot_product(F, name):
+    say("advection transpose", name)
+    make, extra = MESHES[name]
+    m = make()
+    p = O.default_params(nu=1e-3, dt=1e-2, **extra)
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    rng = np.random.default_rng(70)
+    g = _state(n, rng)
+    v = rng.standard_normal((9, n)) * O.WT[:, None]
+    lam = rng.standard_normal((9, n))
+    lam[0] = 0.0                      # the rest direction has no convection term
+    Jv = np.imag(orc.advection(g + 1j * H * v)) / H
+    st = F.State(F.Mesh(m), p, precision="fp64")
+    gbar, dth = st.apply_advection_adjoint(g, lam)
+    lhs, rhs = np.sum(gbar * v), np.sum(lam * Jv)
+    assert abs(lhs - rhs) <= 1e-11 * max(abs(rhs), np.abs(lam * Jv).sum() * 1e-3), (lhs, rhs)
+    # theta
+    pc = dict(p, theta=p.get("theta", 0.0) + 1j * H)
+    dGa = np.imag(O.Oracle(m, pc).advection(g.astype(complex))) / H
+    ref = np.sum(lam * dGa)
+    assert abs(dth - ref) <= 1e-10 * max(abs(ref), 1e-12), (dth, ref)
+
+
+# ------------------------------------------------------------------------------------------------
+# Whole-run adjoint (checkpointed reverse of several IMEX steps)
+# ------------------------------------------------------------------------------------------------
+def _courant_dt(m, C):
+    G = O.Geometry(m)
+    en = np.maximum(O.EX[:, None] * G.nl[:, 0] + O.EY[:, None] * G.nl[:, 1], 0.0)
+    out = np.stack([np.bincount(G.cell, weights=en[a], minlength=G.n) for a in range(9)])
+    return C / (out / G.area).max()
+
+
+RUNS = {
+    # name: (mesh, flow extras, sst)
+    "duct_laminar": (lambda: mg.rectangle(9, 6, Lx=1.4, kind="duct", jitter=0.25, seed=63),
+                     dict(group_u=[[0.05, 0.01], [0, 0], [0.05, 0.0]], group_rho=[1.0, 1.002, 1.0], theta=0.2), False),
+    "backstep_sst": (lambda: mg.backstep(core=0.35, dx_core=0.7, y1=1.5e-2, dx_corner=0.08, wall_layers=2),
+                     dict(group_u=[[0, 0], [0.05, 0.004], [0, 0]], group_k=[0, 2e-4, 0], group_w=[0, 0.4, 0],
+                          theta=0.05, jr_group=0, jr_xmin=0.0, eps_tau=1e-7), True),
+    "naca_sst": (lambda: mg.naca_omesh(n_wall=32, n_normal=10, y1=4e-3, radius=5.0),
+                 dict(group_u=[[0, 0], [0.05, 0]], group_k=[0, 2e-4], group_w=[0, 0.4], theta=0.12), True),
+}
+
+
+def _run_case(name, seed=80):
+    make, extra, sst = RUNS[name]
+    m = make()
+    dt = _courant_dt(m, 0.5)
+    p = O.default_params(nu=dt / 40, dt=dt, sst=sst, **extra)
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    rng = np.random.default_rng(seed)
+    x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+    ux = 0.04 * np.tanh(2 * (y - y.mean())) + 0.004 * rng.standard_normal(n)
+    uy = 0.006 * np.sin(2 * x) + 0.004 * rng.standard_normal(n)
+    rho = 1 + 0.002 * rng.standard_normal(n)
+    f0 = O.feq(rho, ux, uy) + 2e-5 * O.WT[:, None] * rng.standard_normal((9, n))
+    k0 = 2e-4 * (1 + 0.5 * rng.random(n)) if sst else None
+    w0 = 0.4 * (1 + 0.5 * rng.random(n)) if sst else None
+    return m, p, orc, f0, k0, w0, sst
+
+
+def _oracle_final(m, p, f0, k0, w0, N):
+    orc = O.Oracle(m, p)
+    return orc.run(f0, k0, w0, N)
+
+
+PARAMS = ["theta", "sigma_k1", "sigma_w1", "beta_star", "a1"]
+
+
+@pytest.mark.parametrize("name", sorted(RUNS))
+def test_run_adjoint_dot_product_and_params(F, name):
+    say("run adjoint", name)
+    m, p, orc, f0, k0, w0, sst = _run_case(name)
+    n = orc.g.n
+    N = 3
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k0, omega=w0)
+    st.set_state(f0, k0, w0)
+    st.record(N, ckpt_every=2)
+    rng = np.random.default_rng(81)
+    lf = rng.standard_normal((9, n))
+    lk = rng.standard_normal(n) * 1e3 if sst else None
+    lw = rng.standard_normal(n) if sst else None
+    lf0, lk0, lw0, dp = st.adjoint_state(lf, lk, lw)
+    # directional derivative of the final state along a random initial perturbation
+    vf = rng.standard_normal((9, n)) * O.WT[:, None] * 1e-3
+    vk = rng.standard_normal(n) * 1e-5 if sst else None
+    vw = rng.standard_normal(n) * 1e-2 if sst else None
+    fN, kN, wN = _oracle_final(m, p, f0 + 1j * H * vf, None if not sst else k0 + 1j * H * vk,
+                               None if not sst else w0 + 1j * H * vw, N)
+    rhs = np.sum(lf * np.imag(fN)) / H
+    lhs = np.sum(lf0 * vf)
+    if sst:
+        rhs += (np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))) / H
+        lhs += np.sum(lk0 * vk) + np.sum(lw0 * vw)
+    assert abs(lhs - rhs) <= 1e-9 * abs(rhs), (lhs, rhs)
+    # parameter derivatives of lam . final state
+    for i, key in enumerate(PARAMS):
+        if not sst and key != "theta":
+            assert dp[i] == 0.0
+            continue
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        fN, kN, wN = _oracle_final(m, pc, f0.astype(complex), None if not sst else k0.astype(complex),
+                                   None if not sst else w0.astype(complex), N)
+        ref = np.sum(lf * np.imag(fN)) / H
+        if sst:
+            ref += (np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))) / H
+        assert abs(dp[i] - ref) <= 1e-8 * max(abs(ref), 1e-30), (key, dp[i], ref)
+
+
+def test_adjoint_forces_complex_step_fd_and_checkpoints(F):
+    """d(F_x, F_y, J_R)/d params over 4 recorded steps: against complex step on the oracle (1e-8),
+    against centred differences of the GPU forward (eps = 1e-6 max(|p|, 1); 1e-3 plus the rounding
+    floor), and independent of the checkpoint interval (1, 3, 4)."""
+    say("adjoint of forces, backstep sst")
+    m, p, orc, f0, k0, w0, sst = _run_case("backstep_sst", seed=90)
+    N = 4
+    seed = np.array([0.7, -1.3, 2.0])
+
+    def J_of(orc_like, f, k, w):
+        Fv, JR = orc_like.forces(f, 1)
+        return seed[0] * Fv[0] + seed[1] * Fv[1] + seed[2] * JR
+
+    results = []
+    for ck in (1, 3, 4):
+        st = F.State(F.Mesh(m), p, precision="fp64", k=k0, omega=w0)
+        st.set_state(f0, k0, w0)
+        st.record(N, ckpt_every=ck)
+        results.append(st.adjoint(1, seed))
+    for r in results[1:]:
+        np.testing.assert_allclose(r, results[0], rtol=1e-12, atol=1e-300)
+    dp = results[0]
+    for i, key in enumerate(PARAMS):
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        o = O.Oracle(m, pc)
+        fN, kN, wN = o.run(f0.astype(complex), k0.astype(complex), w0.astype(complex), N)
+        ref = np.imag(J_of(o, fN, kN, wN)) / H
+        assert abs(dp[i] - ref) <= 1e-8 * max(abs(ref), 1e-30), (key, dp[i], ref)
+        # centred differences of the GPU forward
+        eps = 1e-6 * max(abs(p[key]), 1.0)
+        Jpm = []
+        for sgn in (1, -1):
+            pp = dict(p)
+            pp[key] = p[key] + sgn * eps
+            s2 = F.State(F.Mesh(m), pp, precision="fp64", k=k0, omega=w0)
+            s2.set_state(f0, k0, w0)
+            s2.step(N)
+            Fv, JR = s2.forces(1)
+            Jpm.append(seed[0] * Fv[0] + seed[1] * Fv[1] + seed[2] * JR)
+        fd = (Jpm[0] - Jpm[1]) / (2 * eps)
+        # central differences straddle the kinks of the scheme (bounds, upwind and max / min
+        # switches) and lose digits to rounding when the derivative is small: the exact reference
+        # is the complex step, the difference quotient a sanity check at 1e-3 plus its rounding floor
+        floor = 1e-13 * (abs(Jpm[0]) + abs(Jpm[1])) / eps
+        assert abs(dp[i] - fd) <= 1e-3 * abs(ref) + floor, (key, dp[i], fd, floor)

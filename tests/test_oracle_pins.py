@@ -575,3 +575,28 @@ def test_sst_stays_positive_from_impulsive_start():
         assert k.min() > 1e-12 and w.min() > 1e-8, (k.min(), w.min())
         assert orc.last_tau.max() < 1e-2
     assert np.isfinite(f).all()
+
+
+def test_complex_step_of_state_matches_central_differences():
+    """The oracle is the reference for the adjoint: its complex-step derivative with respect to the
+    state (f, k, omega) must carry through every array of the step (no silent cast to real) and
+    agree with central differences."""
+    import warnings
+    m = mg.backstep(core=0.35, dx_core=0.7, y1=1.5e-2, dx_corner=0.08, wall_layers=2)
+    p = O.default_params(nu=1e-4, dt=2e-3, sst=True, group_u=[[0, 0], [0.05, 0.004], [0, 0]],
+                         group_k=[0, 2e-4, 0], group_w=[0, 0.4, 0])
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    rng = np.random.default_rng(3)
+    f0 = O.feq(1 + 0.002 * rng.standard_normal(n), 0.04 + 0.004 * rng.standard_normal(n), 0.004 * rng.standard_normal(n))
+    k0, w0 = 2e-4 * (1 + 0.5 * rng.random(n)), 0.4 * (1 + 0.5 * rng.random(n))
+    vf, vk, vw = 1e-3 * O.WT[:, None] * rng.standard_normal((9, n)), rng.standard_normal(n), rng.standard_normal(n)
+    with warnings.catch_warnings():
+        warnings.simplefilter("error")
+        fc, kc, wc = orc.run(f0 + 1e-30j * vf, k0 + 1e-30j * 1e-4 * vk, w0 + 1e-30j * vw, 1)
+    eps = 1e-7
+    fp, kp, wp = orc.run(f0 + eps * vf, k0 + eps * 1e-4 * vk, w0 + eps * vw, 1)
+    fm, km, wm = orc.run(f0 - eps * vf, k0 - eps * 1e-4 * vk, w0 - eps * vw, 1)
+    for c, pl, mi in ((fc, fp, fm), (kc, kp, km), (wc, wp, wm)):
+        fd = (pl - mi) / (2 * eps)
+        assert np.abs(np.imag(c) / 1e-30 - fd).max() <= 1e-4 * np.abs(fd).max()
