@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-points", type=int, default=40_000)
     ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--adjoint-steps", type=int, default=50, help="recorded steps of the adjoint timing (0: skip)")
+    ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the adjoint")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for rocprof byte counters)")
     args = ap.parse_args()
@@ -275,6 +277,29 @@ def main():
                                      "max_drho": err_rho}}
         del st64, st32
 
+    adjoint = None
+    if args.adjoint_steps > 0 and p.get("sst"):
+        import torch
+        # forward with checkpoints, then the reverse run (recompute + transposed kernels), timed apart
+        sta, _ = make_state(F, M, flow, init, args.precision, dt_frac)
+        sta.step(args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sta.record(args.adjoint_steps, ckpt_every=args.ckpt)
+        torch.cuda.synchronize()
+        t_rec = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        grad = sta.adjoint(1, [1.0, 0.0, 0.0])
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        t_fwd = ms / args.steps * 1e-3 * args.adjoint_steps
+        adjoint = {"steps": args.adjoint_steps, "ckpt_every": args.ckpt, "record_s": round(t_rec, 4),
+                   "adjoint_s": round(t_adj, 4), "forward_s": round(t_fwd, 4),
+                   "ratio": round(t_adj / t_fwd, 3), "functional": "x-force on the walls",
+                   "gradient": [float(x) for x in grad]}
+        log(f"adjoint of {args.adjoint_steps} steps: {t_adj:.3f}s vs forward {t_fwd:.3f}s (ratio {t_adj / t_fwd:.2f})")
+        del sta
+
     cpu = None
     if not args.no_cpu_baseline:
         cn, csteps, cdt, ccores = cpu_baseline(args.cpu_sample_points, args.cpu_steps)
@@ -310,7 +335,8 @@ def main():
         "step_roofline": {"bytes_per_cell": round(sb, 1), "achieved_gbs": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4)},
         "kernels": per_kernel,
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
+        "adjoint": adjoint,
         "cpu_baseline": cpu,
         "kernel_source_sha256": source_hash(),
     }

@@ -207,3 +207,35 @@ def test_adjoint_forces_complex_step_fd_and_checkpoints(F):
         # is the complex step, the difference quotient a sanity check at 1e-3 plus its rounding floor
         floor = 1e-13 * (abs(Jpm[0]) + abs(Jpm[1])) / eps
         assert abs(dp[i] - fd) <= 1e-3 * abs(ref) + floor, (key, dp[i], fd, floor)
+
+
+def test_autograd_function_and_fp32(F):
+    """torch.autograd through FVLBMObjective equals the oracle's complex-step gradient (FP64 to
+    1e-8); the FP32-deviation adjoint is within 1e-3 relative of it (stated gate)."""
+    say("autograd objective, backstep sst")
+    import torch
+    from paper_1812_00394_amd.autograd import FVLBMObjective, Problem, PARAM_NAMES
+    m, p, orc, f0, k0, w0, sst = _run_case("backstep_sst", seed=91)
+    n = orc.g.n
+    N = 3
+    w = torch.tensor([0.3, -0.8, 1.5], dtype=torch.float64)
+    ref = []
+    for key in PARAM_NAMES:
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        o = O.Oracle(m, pc)
+        fN, _, _ = o.run(f0.astype(complex), k0.astype(complex), w0.astype(complex), N)
+        Fv, JR = o.forces(fN, 1)
+        ref.append(np.imag(w[0].item() * Fv[0] + w[1].item() * Fv[1] + w[2].item() * JR) / H)
+    ref = np.array(ref)
+    for precision, tol in (("fp64", 1e-8), ("fp32dev", 1e-3)):
+        prob = Problem(F.Mesh(m), p, rho=np.ones(n), u=np.zeros((n, 2)), k=k0, omega=w0, n_steps=N,
+                       ckpt_every=2, wall_mask=1, precision=precision, f0=f0)
+        params = torch.tensor([p[k] for k in PARAM_NAMES], dtype=torch.float64, requires_grad=True)
+        J = FVLBMObjective.apply(params, prob)
+        (J @ w).backward()
+        g = params.grad.numpy()
+        rel = np.abs(g - ref) / np.maximum(np.abs(ref), 1e-30)
+        print(precision, "adjoint gradient", g, "relative error", rel)
+        scale = np.abs(ref).max()
+        assert np.all(np.abs(g - ref) <= tol * np.maximum(np.abs(ref), 1e-6 * scale)), (precision, g, ref)
