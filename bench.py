@@ -93,18 +93,25 @@ def make_state(F, M, flow, init, precision, dt_frac):
 # Algorithmic (compulsory) bytes per cell of one launch of each kernel: every array the kernel
 # must read or write counted once (neighbour gathers counted once).  T = bytes per value of the
 # state's arithmetic type (4 FP32-deviation, 8 FP64), which is also the type of the per-edge
-# geometry the sweeps stream (nl, rf, q, c: 8 values per edge); S = mean edges per cell; neighbour
-# ids 4 x 4 B, tile-local ids 4 x 2 B, 1/A one value, wall distance 8 B (FP64).
-def kernel_bytes(T, S, tiled=True):
+# geometry the sweeps stream (nl, rf, q, c: 8 values per edge); S = mean edges per cell; 1/A one
+# value, wall distance 8 B (FP64).  Neighbour ids (4 B) and tile-local ids (2 B) per slot: the
+# ring sweep reads the S slots of the mesh, the older tiled sweeps all four.
+#   ring : sweep 1 takes f^(1) from f^n and tau on the fly (no collide1 launch): reads f^n, tau,
+#          writes f^(2), Ga1 (28 values); sweep 2 reads f^(2), f^n, tau, Ga1, writes f^(3), Q (46);
+#          sweep 3 reads f^(3), Q, writes f^{n+1} and rho, u (30)
+#   tiled: collide1 writes f^(1) (19 values with f^n and tau); sweep 1 reads f^(1) as well (37)
+#   split: as tiled, plus the 16 gradient planes each sweep reads back (grad writes them)
+def kernel_bytes(T, S, variant="ring"):
     edge = 8 * T * S
-    geo = 16 + 8 + edge + T if tiled else 16 + edge + T
-    extra = 0 if tiled else 16 * T            # split path: the gradient planes are read back
+    ids = 6 * S if variant == "ring" else 24
+    geo = ids + edge + T
+    extra = 16 * T if variant == "split" else 0
     return {
         "sst_a": 15 * T + 16 + 2 * T * S + 8,
         "sst_b": 19 * T + 16 + 6 * T * S + T + 8,
         "collide1": 19 * T,
         "grad": 25 * T + 16 + 2 * T * S,
-        "sweep1": 37 * T + geo + extra,
+        "sweep1": (28 if variant == "ring" else 37) * T + geo + extra,
         "sweep2": 46 * T + geo + extra,
         "sweep3": 30 * T + geo + extra,
     }
@@ -241,7 +248,9 @@ def main():
         raise SystemExit("non-finite state after the timed steps")
 
     T = 4 if args.precision == "fp32dev" else 8
-    kb = kernel_bytes(T, S, tiled=os.environ.get("FVLBM_SWEEP", "tiled") != "split")
+    # the variant the library chose: the ring sweep launches no collide1, the split path its grad
+    variant = "split" if kt["grad"][1] else ("tiled" if kt["collide1"][1] else "ring")
+    kb = kernel_bytes(T, S, variant)
     per_kernel = {}
     for name, (tms, cnt) in kt.items():
         if cnt:

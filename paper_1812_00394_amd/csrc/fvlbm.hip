@@ -68,9 +68,13 @@ struct fvlbm_state {
     void *K[2] = {nullptr, nullptr}, *W[2] = {nullptr, nullptr};
     void *tau = nullptr, *nut = nullptr, *aux = nullptr;
     int cur_m = 0, cur_kw = 0;
-    // tiles of the fused stage kernels
-    bool tiled = true, tile_vals = true;
+    // tiles of the fused stage kernels: ring (extended halo lists), tiled (ring 1 only, with or
+    // without the stage values in LDS) or the two-kernel split path
+    bool ring = true, tiled = true, tile_vals = true;
+    int ring_s = 4, ring_wv = 0, ring_wg = 0;
     int32_t *hptr = nullptr, *hcell = nullptr;
+    int32_t *xptr = nullptr, *xn1 = nullptr, *xcell = nullptr;
+    int16_t *xlnb = nullptr;
     int16_t *lnb = nullptr;
     int8_t *rev = nullptr;
     void *scr1 = nullptr;        // one n-array of T for diagnostics
@@ -165,6 +169,10 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
     st->scr1 = cv.take<T>(n);
     st->hptr = cv.take<int32_t>((size_t)m->n_tiles + 1);
     st->hcell = cv.take<int32_t>(std::max<size_t>(1, m->halo_cell.size()));
+    st->xptr = cv.take<int32_t>((size_t)m->n_tiles + 1);
+    st->xn1 = cv.take<int32_t>((size_t)m->n_tiles);
+    st->xcell = cv.take<int32_t>(std::max<size_t>(1, m->ext_cell.size()));
+    st->xlnb = cv.take<int16_t>(kSlots * std::max<size_t>(1, m->ext_cell.size()));
     st->scratch = cv.take<double>(9 * n);
     st->partial = cv.take<double>((size_t)kRedBlocks * 4);
     st->result = cv.take<double>(4);
@@ -290,6 +298,10 @@ void upload_geometry(fvlbm_state *st) {
     h2d(st->rev, m->rev, s);
     h2d(st->hptr, m->halo_ptr, s);
     h2d(st->hcell, m->halo_cell, s);
+    h2d(st->xptr, m->ext_ptr, s);
+    h2d(st->xn1, m->ext_n1, s);
+    h2d(st->xcell, m->ext_cell, s);
+    h2d(st->xlnb, m->ext_lnb, s);
     std::vector<double> bv[6];
     std::vector<int32_t> zg;
     boundary_values(m, st->par, bv, zg);
@@ -358,10 +370,29 @@ void launch_step(fvlbm_state *st) {
         { Timed t(st, FVLBM_K_SST_B); k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, K1, W1, tau, (T *)st->nut, p); }
         st->cur_kw ^= 1;
     }
-    { Timed t(st, FVLBM_K_COLLIDE1); k_collide1<T><<<nbk, kBlock, 0, s>>>(n, F, tau, X, p); }
     const StageBufs<T> b1{X, F, tau, A, Y, nullptr, nullptr};
     const StageBufs<T> b2{Y, F, tau, A, X, nullptr, nullptr};
     const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, F, Mnew};
+    if (st->ring) {
+        // stage 1 takes f^(1) from f^n on the fly: no separate collision launch
+        const int nt = st->mesh->n_tiles;
+        const size_t lds = st->lds_bytes;
+        const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+        const int wv = st->ring_wv, wg = st->ring_wg;
+        if (st->ring_s == 3) {
+            { Timed t(st, FVLBM_K_SWEEP1); k_stage_ring<T, 1, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b1, p); }
+            { Timed t(st, FVLBM_K_SWEEP2); k_stage_ring<T, 2, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b2, p); }
+            { Timed t(st, FVLBM_K_SWEEP3); k_stage_ring<T, 3, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b3, p); }
+        } else {
+            { Timed t(st, FVLBM_K_SWEEP1); k_stage_ring<T, 1, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b1, p); }
+            { Timed t(st, FVLBM_K_SWEEP2); k_stage_ring<T, 2, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b2, p); }
+            { Timed t(st, FVLBM_K_SWEEP3); k_stage_ring<T, 3, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b3, p); }
+        }
+        st->cur_m ^= 1;
+        check(hipGetLastError(), "kernel launch");
+        return;
+    }
+    { Timed t(st, FVLBM_K_COLLIDE1); k_collide1<T><<<nbk, kBlock, 0, s>>>(n, F, tau, X, p); }
     if (st->tiled) {
         const int nt = st->mesh->n_tiles;
         const size_t lds = st->lds_bytes;
@@ -423,8 +454,10 @@ void import_state(fvlbm_state *st, const double *f, const double *k, const doubl
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
 }
 
-// Chooses the sweep variant: the tiled kernels unless their LDS would not fit (or the environment
-// variable FVLBM_SWEEP=split asks for the two-kernel path).
+// Chooses the sweep variant: the ring-tiled kernels when every tile's extended halo fits one
+// thread per ext cell and their LDS fits; else the ring-1 tiled kernels unless their LDS would not
+// fit; else the two-kernel path.  The environment variable FVLBM_SWEEP (ring, tiled, tiled-grads,
+// split) restricts the choice.
 template <typename T>
 void choose_sweep(fvlbm_state *st) {
     static_assert(kTileCells == kTile, "tile size of the kernels and of the mesh preprocessing differ");
@@ -434,6 +467,16 @@ void choose_sweep(fvlbm_state *st) {
     check(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute");
     const char *env = std::getenv("FVLBM_SWEEP");
     const std::string mode = env ? env : "";
+    st->ring_s = st->mesh->max_faces <= 3 ? 3 : 4;
+    st->ring_wv = kTile + st->mesh->ext_max;
+    st->ring_wg = kTile + st->mesh->halo_max;
+    const size_t ring_lds = ((size_t)8 * st->ring_wv + (size_t)16 * st->ring_wg) * sizeof(T);
+    st->ring = (mode.empty() || mode == "ring") && st->mesh->ext_max <= kTileCells && ring_lds <= (size_t)max_lds;
+    if (st->ring) {
+        st->lds_bytes = ring_lds;
+        st->tiled = false;
+        return;
+    }
     // values staged in LDS as well when 24 planes fit in a third of a CU's LDS (occupancy), else
     // gradients only; the two-kernel path when not even those fit
     const size_t with_vals = (size_t)24 * st->tile_w * sizeof(T), grads = (size_t)16 * st->tile_w * sizeof(T);

@@ -60,4 +60,11 @@ struct fvlbm_mesh {
     int32_t n_tiles = 0, halo_max = 0;
     std::vector<int32_t> halo_ptr, halo_cell;
     std::vector<int16_t> lnb;
+    // extended halo of tile t: ext_cell[ext_ptr[t] .. ext_ptr[t+1]) lists ring 1 (the halo above,
+    // ext_n1[t] cells) then ring 2 (interior neighbours of ring-1 cells outside the tile and ring 1,
+    // ascending); ext_lnb[s][e] is the tile-local column of slot s's neighbour of ring-1 entry e
+    // (tile cells c - tile start, ext entry j kTile + j; 0 for boundary / unused slots)
+    int32_t ext_max = 0;
+    std::vector<int32_t> ext_ptr, ext_n1, ext_cell;
+    std::vector<int16_t> ext_lnb;
 };

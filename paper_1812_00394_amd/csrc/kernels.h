@@ -182,17 +182,44 @@ __global__ void __launch_bounds__(256) k_collide1(int n, const T *__restrict__ F
     for (int a = 0; a < 9; ++a) X[(size_t)a * n + c] = f1[a];
 }
 
-// ---- stage epilogues (cell-local), shared by the two-kernel and the tiled sweeps ----
+// ---- stage epilogues (cell-local), shared by every sweep variant ----
+// Operands an epilogue reads besides the stage field: f^n and tau (stages 1, 2), the stored
+// convection term Ga1 (stage 2) or Q (stage 3).  Loaded by the caller so that a kernel can issue
+// the loads early; members a stage does not use are dead code.
+template <typename T>
+struct EpiOps {
+    T fn[9], a[9], tc;
+};
+
+// Buffers of one stage sweep: src = the stage field whose convection term is taken.
+template <typename T>
+struct StageBufs {
+    const T *src, *F_in, *tau;
+    T *A, *out, *F_out, *M;
+};
+
+template <typename T, int J>
+__device__ __forceinline__ void load_ops(const StageBufs<T> &b, int c, int n, EpiOps<T> &o) {
+    if constexpr (J <= 2) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) o.fn[a] = b.F_in[(size_t)a * n + c];
+        o.tc = b.tau[c];
+    }
+    if constexpr (J >= 2) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) o.a[a] = b.A[(size_t)a * n + c];
+    }
+}
+
 // Stage 1 -> 2: f^(2) = solve(f^n + dt/2 Ga1, a = dt/(4 tau)); stores f^(2) and Ga1.
 template <typename T>
-__device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const T *__restrict__ F,
-                                          const T *__restrict__ tau, T *__restrict__ Y, T *__restrict__ A,
-                                          const StepPar<T> &p) {
+__device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const EpiOps<T> &o, T *__restrict__ Y,
+                                          T *__restrict__ A, const StepPar<T> &p) {
     T rhs[9], f2[9], fe[9];
     const T h = p.dt * T(0.5);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) rhs[a] = F[(size_t)a * n + c] + h * ga[a];
-    stage_collide(rhs, p.dt / (T(4) * tau[c]), p.rho0, f2, fe);
+    for (int a = 0; a < 9; ++a) rhs[a] = o.fn[a] + h * ga[a];
+    stage_collide(rhs, p.dt / (T(4) * o.tc), p.rho0, f2, fe);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         Y[(size_t)a * n + c] = f2[a];
@@ -203,15 +230,12 @@ __device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const T *
 // Stage 2 -> 3: Gc1, Gc2 recomputed cell-locally; f^(3) = solve(rhs3, dt/(3 tau)) with the stage
 // moments of Eq. (sumimeximplicitnew); stores f^(3) and Q = f^(3) - dt/6 (Ga1 + Ga2) (over Ga1).
 template <typename T>
-__device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T ga2[9], const T *__restrict__ F,
-                                          const T *__restrict__ tau, T *__restrict__ X, T *__restrict__ A,
-                                          const StepPar<T> &p) {
-    T fn[9], f1[9], fe1[9], rhs[9], f3[9], gsum[9];
-    const T tc = tau[c];
+__device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T ga2[9], const EpiOps<T> &o,
+                                          T *__restrict__ X, T *__restrict__ A, const StepPar<T> &p) {
+    T f1[9], fe1[9], rhs[9], f3[9], gsum[9];
+    const T tc = o.tc;
     const T itau = T(1) / tc;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) fn[a] = F[(size_t)a * n + c];
-    stage_collide(fn, p.dt / (T(4) * tc), p.rho0, f1, fe1);      // f^(1), f_eq^(1)
+    stage_collide(o.fn, p.dt / (T(4) * tc), p.rho0, f1, fe1);    // f^(1), f_eq^(1)
     T drho2, rho2, ux2, uy2;
     moments(f2, p.rho0, drho2, rho2, ux2, uy2);                  // stage-2 moments
     const T h2 = p.dt * T(0.5), h3 = p.dt / T(3);
@@ -219,12 +243,11 @@ __device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T g
     T m0 = 0, mx = 0, my = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        const T a1 = A[(size_t)a * n + c];
         const T gc1 = (fe1[a] - f1[a]) * itau;
         const T gc2 = (dfeq(a, drho2, rho2, ux2, uy2) - f2[a]) * itau;
-        gsum[a] = a1 + ga2[a];                                     // Ga1 + Ga2
-        rhs[a] = fn[a] + h2 * gsum[a] + h3 * (gc1 + gc2);
-        const T mv = fn[a] + h2 * gsum[a];
+        gsum[a] = o.a[a] + ga2[a];                                 // Ga1 + Ga2
+        rhs[a] = o.fn[a] + h2 * gsum[a] + h3 * (gc1 + gc2);
+        const T mv = o.fn[a] + h2 * gsum[a];
         m0 += mv;
         mx += T(ex(a)) * mv;
         my += T(ey(a)) * mv;
@@ -241,13 +264,13 @@ __device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T g
 
 // Stage 3 -> n+1: f^{n+1} = Q + dt/3 Ga3; macro variables (Step 7): rho - rho0, u.
 template <typename T>
-__device__ __forceinline__ void epilogue3(int c, int n, const T ga3[9], const T *__restrict__ A, T *__restrict__ F,
+__device__ __forceinline__ void epilogue3(int c, int n, const T ga3[9], const EpiOps<T> &o, T *__restrict__ F,
                                           T *__restrict__ M, const StepPar<T> &p) {
     T fnew[9];
     const T h3 = p.dt / T(3);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        fnew[a] = A[(size_t)a * n + c] + h3 * ga3[a];
+        fnew[a] = o.a[a] + h3 * ga3[a];
         F[(size_t)a * n + c] = fnew[a];
     }
     T drho, rho, ux, uy;
@@ -257,22 +280,23 @@ __device__ __forceinline__ void epilogue3(int c, int n, const T ga3[9], const T 
     M[(size_t)2 * n + c] = uy;
 }
 
-// Buffers of one stage sweep: src = the stage field whose convection term is taken.
-template <typename T>
-struct StageBufs {
-    const T *src, *F_in, *tau;
-    T *A, *out, *F_out, *M;
-};
+template <typename T, int J>
+__device__ __forceinline__ void stage_epilogue_ops(int c, int n, const T gc[9], const T ga[9], const EpiOps<T> &o,
+                                                   const StageBufs<T> &b, const StepPar<T> &p) {
+    if constexpr (J == 1)
+        epilogue1(c, n, ga, o, b.out, b.A, p);
+    else if constexpr (J == 2)
+        epilogue2(c, n, gc, ga, o, b.out, b.A, p);
+    else
+        epilogue3(c, n, ga, o, b.F_out, b.M, p);
+}
 
 template <typename T, int J>
 __device__ __forceinline__ void stage_epilogue(int c, int n, const T gc[9], const T ga[9], const StageBufs<T> &b,
                                                const StepPar<T> &p) {
-    if constexpr (J == 1)
-        epilogue1(c, n, ga, b.F_in, b.tau, b.out, b.A, p);
-    else if constexpr (J == 2)
-        epilogue2(c, n, gc, ga, b.F_in, b.tau, b.out, b.A, p);
-    else
-        epilogue3(c, n, ga, b.A, b.F_out, b.M, p);
+    EpiOps<T> o;
+    load_ops<T, J>(b, c, n, o);
+    stage_epilogue_ops<T, J>(c, n, gc, ga, o, b, p);
 }
 
 // Two-kernel sweep (after k_grad): the convection term of stage J from the global gradient planes.
@@ -413,6 +437,201 @@ __global__ void __launch_bounds__(kTileCells + kHaloThreads)
     else
         advect_cell(g, c, p.rho0, gc, gx, gy, NbrTile<T>{b.src, L, lnb, n, W, 0}, ga);
     stage_epilogue<T, J>(c, n, gc, ga, b, p);
+}
+
+// ---- ring-tiled sweep ----
+// One workgroup of kTileCells threads per tile of kTileCells consecutive cells.  The tile's
+// extended halo (ring 1: the interior neighbours of its cells outside it; ring 2: the interior
+// neighbours of ring-1 cells outside tile and ring 1) is listed per tile, so every global load a
+// workgroup needs is issued in phase 0, at most one dependent step behind the tile's own loads:
+//   phase 0: thread t loads tile cell t (stage values, the epilogue operands, its edge geometry)
+//            and ext cell t (stage values; for a ring-1 cell also its LSQ coefficients and
+//            neighbour columns); the stage values of directions 1..8 go to LDS;
+//   phase 1: LSQ gradients of tile cell t and ring-1 cell t from the LDS values, into LDS;
+//   phase 2: the convection term of tile cell t (Eq. (advection)) with each upwind neighbour's
+//            value and gradient from LDS, then the stage epilogue.
+// Stage 1 takes f^(1) = stage solve of f^n (a = dt/(4 tau)) on the fly, for tile and ext cells.
+// LDS: V [8][Wv] values (Wv = kTileCells + largest extended halo), Gl [16][Wg] gradients
+// (Wg = kTileCells + largest ring 1); tile cell t is column t, ext entry j column kTileCells + j.
+// S = edges per cell of the mesh (3: triangles only; 4 otherwise).
+struct RingTiles {
+    const int32_t *ptr;    // [n_tiles + 1] offsets into cell
+    const int32_t *n1;     // [n_tiles] ring-1 count
+    const int32_t *cell;   // [n_ext] internal cell ids: ring 1 then ring 2 of each tile
+    const int16_t *lnb;    // [4][n_ext] columns of the neighbours of ring-1 entries
+    int32_t n_ext;
+};
+
+// LSQ gradient from LDS values of a cell with edge data held in registers (nb, col, cx, cy per
+// slot; the normal of a boundary edge is read when needed).  Same summation order as grad_cell.
+template <typename T, int S>
+__device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int nb[S], const int col[S], const T cxs[S],
+                                          const T cys[S], const T *V, int Wv, T rho0, const T gc[9], T gx[9], T gy[9]) {
+    const int n = g.n;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gx[a] = gy[a] = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] == -1) continue;
+        if (nb[s] >= 0) {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T d = V[(a - 1) * Wv + col[s]] - gc[a];
+                gx[a] += cxs[s] * d;
+                gy[a] += cys[s] * d;
+            }
+        } else {
+            const size_t si = (size_t)s * n + cell;
+            T drho, rho, ux, uy, gb[9];
+            moments(gc, rho0, drho, rho, ux, uy);
+            ghost(g, -2 - nb[s], g.nlx[si], g.nly[si], gc, drho, rho, ux, uy, gb);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T d = gb[a] - gc[a];
+                gx[a] += cxs[s] * d;
+                gy[a] += cys[s] * d;
+            }
+        }
+    }
+}
+
+template <typename T, int J, int S>
+__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
+    k_stage_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg, StageBufs<T> b,
+                 StepPar<T> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *V = reinterpret_cast<T *>(smem);
+    T *Gl = V + 8 * Wv;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int start = tile * kTileCells;
+    const int ncell = min(kTileCells, g.n - start);
+    const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
+    const int t = threadIdx.x;
+    const int n = g.n;
+    const bool own = t < ncell, ext = t < nx, ring1 = t < n1;
+    const int c = start + t;
+
+    // ---- phase 0 ----
+    T gc[9];
+    EpiOps<T> ops;
+    int nb[S], col[S];
+    T cxs[S], cys[S], nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], ia = T(0);
+    if (own) {
+        if constexpr (J == 1) {
+            load_ops<T, 1>(b, c, n, ops);
+            T fe[9];
+            stage_collide(ops.fn, p.dt / (T(4) * ops.tc), p.rho0, gc, fe);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
+            load_ops<T, J>(b, c, n, ops);
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const size_t si = (size_t)s * n + c;
+            nb[s] = g.nbr[si];
+            col[s] = lnb[si];
+            cxs[s] = g.cx[si];
+            cys[s] = g.cy[si];
+            nlx[s] = g.nlx[si];
+            nly[s] = g.nly[si];
+            rx[s] = g.rfx[si];
+            ry[s] = g.rfy[si];
+            qx[s] = g.qx[si];
+            qy[s] = g.qy[si];
+        }
+        ia = g.inv_area[c];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) V[(a - 1) * Wv + t] = gc[a];
+    }
+    T hv[9];
+    int hc = 0, hnb[S], hcol[S];
+    T hcx[S], hcy[S];
+    if (ext) {
+        hc = rt.cell[x0 + t];
+        if constexpr (J == 1) {
+            T hf[9], fe[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) hf[a] = b.F_in[(size_t)a * n + hc];
+            stage_collide(hf, p.dt / (T(4) * b.tau[hc]), p.rho0, hv, fe);
+        } else {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) hv[a] = b.src[(size_t)a * n + hc];
+        }
+#pragma unroll
+        for (int a = 1; a < 9; ++a) V[(a - 1) * Wv + kTileCells + t] = hv[a];
+        if (ring1) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const size_t si = (size_t)s * n + hc;
+                hnb[s] = g.nbr[si];
+                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
+                hcx[s] = g.cx[si];
+                hcy[s] = g.cy[si];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 1 ----
+    if (ring1) {
+        T hx[9], hy[9];
+        grad_ring<T, S>(g, hc, hnb, hcol, hcx, hcy, V, Wv, p.rho0, hv, hx, hy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gl[(2 * (a - 1)) * Wg + kTileCells + t] = hx[a];
+            Gl[(2 * (a - 1) + 1) * Wg + kTileCells + t] = hy[a];
+        }
+    }
+    T gx[9], gy[9];
+    if (own) {
+        grad_ring<T, S>(g, c, nb, col, cxs, cys, V, Wv, p.rho0, gc, gx, gy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gl[(2 * (a - 1)) * Wg + t] = gx[a];
+            Gl[(2 * (a - 1) + 1) * Wg + t] = gy[a];
+        }
+    }
+    __syncthreads();
+    if (!own) return;
+
+    // ---- phase 2: convection term, same summation order as advect_cell ----
+    T acc[9];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] == -1) continue;
+        if (nb[s] >= 0) {
+            const int loc = col[s];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T end = T(ex(a)) * nlx[s] + T(ey(a)) * nly[s];
+                const T val = end >= T(0) ? gc[a] + gx[a] * rx[s] + gy[a] * ry[s]
+                                          : V[(a - 1) * Wv + loc] + Gl[(2 * (a - 1)) * Wg + loc] * qx[s] +
+                                                Gl[(2 * (a - 1) + 1) * Wg + loc] * qy[s];
+                acc[a] += end * val;
+            }
+        } else {
+            const int bi = -2 - nb[s];
+            T drho, rho, ux, uy, gb[9];
+            moments(gc, p.rho0, drho, rho, ux, uy);
+            ghost(g, bi, nlx[s], nly[s], gc, drho, rho, ux, uy, gb);
+            const int kind = g.b_kind[bi];
+            const bool wall = (kind == kWall || kind == kMovingWall);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T end = T(ex(a)) * nlx[s] + T(ey(a)) * nly[s];
+                const T val = (wall || end < T(0)) ? gb[a] : gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
+                acc[a] += end * val;
+            }
+        }
+    }
+    T ga[9];
+    ga[0] = T(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) ga[a] = -acc[a] * ia;
+    stage_epilogue_ops<T, J>(c, n, gc, ga, ops, b, p);
 }
 
 // Convection term alone (diagnostic entry point).

@@ -424,7 +424,10 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
     // ---- tiles and halos for the fused stage kernels ----
     m->n_tiles = (int32_t)((N + kTile - 1) / kTile);
     m->halo_ptr.assign(m->n_tiles + 1, 0);
+    m->ext_ptr.assign(m->n_tiles + 1, 0);
+    m->ext_n1.assign(m->n_tiles, 0);
     m->lnb.assign(kSlots * N, 0);
+    std::vector<int16_t> ext_lnb_rows;
     for (int32_t t = 0; t < m->n_tiles; ++t) {
         const int64_t lo = (int64_t)t * kTile, hi = std::min<int64_t>(N, lo + kTile);
         std::vector<int32_t> halo;
@@ -450,6 +453,45 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
         m->halo_ptr[t + 1] = m->halo_ptr[t] + (int32_t)halo.size();
         m->halo_max = std::max<int32_t>(m->halo_max, (int32_t)halo.size());
         m->halo_cell.insert(m->halo_cell.end(), halo.begin(), halo.end());
+        // second ring: interior neighbours of ring-1 cells outside the tile and ring 1
+        std::vector<int32_t> ring2;
+        for (int32_t h : halo)
+            for (int s = 0; s < kSlots; ++s) {
+                const int32_t nb = m->nbr[s * N + h];
+                if (nb < 0 || (nb >= lo && nb < hi) || std::binary_search(halo.begin(), halo.end(), nb)) continue;
+                ring2.push_back(nb);
+            }
+        std::sort(ring2.begin(), ring2.end());
+        ring2.erase(std::unique(ring2.begin(), ring2.end()), ring2.end());
+        const size_t e0 = m->ext_cell.size();
+        m->ext_cell.insert(m->ext_cell.end(), halo.begin(), halo.end());
+        m->ext_cell.insert(m->ext_cell.end(), ring2.begin(), ring2.end());
+        m->ext_ptr[t + 1] = (int32_t)m->ext_cell.size();
+        m->ext_n1[t] = (int32_t)halo.size();
+        m->ext_max = std::max<int32_t>(m->ext_max, (int32_t)(halo.size() + ring2.size()));
+        // tile-local column of each ring-1 cell's neighbours: tile cells c - lo, ext entry j kTile + j
+        ext_lnb_rows.resize(m->ext_cell.size() * kSlots, 0);
+        for (size_t j = 0; j < halo.size(); ++j)
+            for (int s = 0; s < kSlots; ++s) {
+                const int32_t nb = m->nbr[s * N + halo[j]];
+                if (nb < 0) continue;
+                int64_t local;
+                if (nb >= lo && nb < hi)
+                    local = nb - lo;
+                else if (std::binary_search(halo.begin(), halo.end(), nb))
+                    local = kTile + (std::lower_bound(halo.begin(), halo.end(), nb) - halo.begin());
+                else
+                    local = kTile + (int64_t)halo.size() + (std::lower_bound(ring2.begin(), ring2.end(), nb) - ring2.begin());
+                if (local > 32767) throw Error(FVLBM_EMESH, "mesh_create: tile halo too large");
+                ext_lnb_rows[(e0 + j) * kSlots + s] = (int16_t)local;
+            }
+    }
+    // ring-1 neighbour columns as [kSlots][n_ext]
+    {
+        const size_t ne = m->ext_cell.size();
+        m->ext_lnb.assign(kSlots * std::max<size_t>(ne, 1), 0);
+        for (size_t e = 0; e < ne; ++e)
+            for (int s = 0; s < kSlots; ++s) m->ext_lnb[s * ne + e] = ext_lnb_rows[e * kSlots + s];
     }
 
     // ---- wall distance: exact nearest point over WALL / MOVING_WALL edges ----

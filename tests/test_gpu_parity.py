@@ -82,11 +82,11 @@ def test_advection_operator_parity(F, name):
     assert rel(got, ref, np.abs(ref).max()) < 1e-12
 
 
-@pytest.mark.parametrize("sweep", ["tiled", "tiled-grads", "split"])
+@pytest.mark.parametrize("sweep", ["ring", "tiled", "tiled-grads", "split"])
 @pytest.mark.parametrize("name", sorted(MESHES))
 def test_laminar_step_parity(F, name, sweep, monkeypatch):
-    """Every sweep variant: tiled with values and gradients in LDS, tiled with gradients only, and
-    the two-kernel path."""
+    """Every sweep variant: ring-tiled (both halo rings staged in LDS, stage 1 collision fused),
+    tiled with values and gradients in LDS, tiled with gradients only, and the two-kernel path."""
     say("laminar step", name, sweep)
     monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = MESHES[name]
