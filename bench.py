@@ -107,6 +107,8 @@ def kernel_bytes(T, S, variant="ring"):
     geo = ids + edge + T
     extra = 16 * T if variant == "split" else 0
     return {
+        # ring SST (one launch): reads rho, u, v, k, omega, writes k, omega, nu_t, tau (9 values)
+        "sst": 9 * T + 6 * S + 8 * T * S + T + 8,
         "sst_a": 15 * T + 16 + 2 * T * S + 8,
         "sst_b": 19 * T + 16 + 6 * T * S + T + 8,
         "collide1": 19 * T,

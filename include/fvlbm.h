@@ -193,7 +193,8 @@ enum {
     FVLBM_K_SWEEP1 = 4,    /* stage-1 convection + stage-2 collision */
     FVLBM_K_SWEEP2 = 5,    /* stage-2 convection + stage-3 collision */
     FVLBM_K_SWEEP3 = 6,    /* stage-3 convection + combination + macro update */
-    FVLBM_K_COUNT = 7
+    FVLBM_K_SST = 7,       /* SST in one ring-tiled launch (replaces SST_A + SST_B) */
+    FVLBM_K_COUNT = 8
 };
 fvlbm_status fvlbm_timing(fvlbm_state *st, int32_t enable);
 fvlbm_status fvlbm_timing_read(fvlbm_state *st, double ms[FVLBM_K_COUNT], int64_t launches[FVLBM_K_COUNT]);

@@ -72,6 +72,8 @@ struct fvlbm_state {
     // without the stage values in LDS) or the two-kernel split path
     bool ring = true, tiled = true, tile_vals = true;
     int ring_s = 4, ring_wv = 0, ring_wg = 0;
+    size_t sst_lds_bytes = 0;
+    bool want_aux = false;       // the SST launch also stores the aux planes (adjoint recompute)
     int32_t *hptr = nullptr, *hcell = nullptr;
     int32_t *xptr = nullptr, *xn1 = nullptr, *xcell = nullptr;
     int16_t *xlnb = nullptr;
@@ -363,11 +365,30 @@ void launch_step(fvlbm_state *st) {
     T *F = (T *)st->F, *X = (T *)st->X, *Y = (T *)st->Y, *A = (T *)st->A, *G = (T *)st->G;
     T *Mcur = (T *)st->M[st->cur_m], *Mnew = (T *)st->M[st->cur_m ^ 1];
     T *tau = (T *)st->tau;
+    const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
     if (st->sst) {
         T *K0 = (T *)st->K[st->cur_kw], *W0 = (T *)st->W[st->cur_kw];
         T *K1 = (T *)st->K[st->cur_kw ^ 1], *W1 = (T *)st->W[st->cur_kw ^ 1];
-        { Timed t(st, FVLBM_K_SST_A); k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, p); }
-        { Timed t(st, FVLBM_K_SST_B); k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, (T *)st->aux, K1, W1, tau, (T *)st->nut, p); }
+        T *aux = (T *)st->aux, *nut = (T *)st->nut;
+        if (st->ring) {
+            const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+            const size_t lds = st->sst_lds_bytes;
+            Timed t(st, FVLBM_K_SST);
+            if (st->ring_s == 3) {
+                if (st->want_aux)
+                    k_sst_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
+                else
+                    k_sst_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
+            } else {
+                if (st->want_aux)
+                    k_sst_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
+                else
+                    k_sst_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
+            }
+        } else {
+            { Timed t(st, FVLBM_K_SST_A); k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, aux, p); }
+            { Timed t(st, FVLBM_K_SST_B); k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p); }
+        }
         st->cur_kw ^= 1;
     }
     const StageBufs<T> b1{X, F, tau, A, Y, nullptr, nullptr};
@@ -377,7 +398,6 @@ void launch_step(fvlbm_state *st) {
         // stage 1 takes f^(1) from f^n on the fly: no separate collision launch
         const int nt = st->mesh->n_tiles;
         const size_t lds = st->lds_bytes;
-        const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
         const int wv = st->ring_wv, wg = st->ring_wg;
         if (st->ring_s == 3) {
             { Timed t(st, FVLBM_K_SWEEP1); k_stage_ring<T, 1, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b1, p); }
@@ -474,6 +494,7 @@ void choose_sweep(fvlbm_state *st) {
     st->ring = (mode.empty() || mode == "ring") && st->mesh->ext_max <= kTileCells && ring_lds <= (size_t)max_lds;
     if (st->ring) {
         st->lds_bytes = ring_lds;
+        st->sst_lds_bytes = ((size_t)5 * st->ring_wv + (size_t)6 * st->ring_wg) * sizeof(T);
         st->tiled = false;
         return;
     }
@@ -698,7 +719,9 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot) {
     load_state<T>(st, slot);
     T *Mn = (T *)st->M[st->cur_m];
     T *Kn = st->sst ? (T *)st->K[st->cur_kw] : nullptr, *Wn = st->sst ? (T *)st->W[st->cur_kw] : nullptr;
+    st->want_aux = true;
     launch_step<T>(st);
+    st->want_aux = false;
     const T *fn = slot;
     k_collide1<T><<<nbk, kBlock, 0, s>>>(n, fn, (const T *)st->tau, L.F1, p);
     AdjBufs<T> b{fn, L.F1, (const T *)st->Y, (const T *)st->X, (const T *)st->A, (const T *)st->tau,

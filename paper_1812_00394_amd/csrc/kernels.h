@@ -935,6 +935,197 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
     tau[c] = T(3) * (p.nu + nt);
 }
 
+// ---- ring-tiled SST: gradients, closure, face fluxes and update in one launch ----
+// The layout of the ring-tiled stage sweeps (one workgroup per tile, extended halo lists):
+//   phase 0: rho, u, v, k, omega of tile cell t and ext cell t into LDS; the edge data of tile
+//            cell t and of ring-1 cell t into registers;
+//   phase 1: LSQ gradients of u, v, k, omega and the cell-local closure (sst_local) of tile cell t
+//            and ring-1 cell t; grad k, grad omega, Gamma_k, Gamma_omega into LDS;
+//   phase 2: face fluxes of tile cell t with its neighbours' data from LDS, point-implicit update,
+//            nu_t and tau.  AUX: also store the aux planes of k_sst_a (the adjoint reads them).
+// LDS: Vv [5][Wv] (rho, u, v, k, omega), Vx [6][Wg] (dk/dx, dk/dy, dw/dx, dw/dy, Gamma_k, Gamma_w).
+template <typename T, int S>
+__device__ __forceinline__ void sst_grad_ring(const Geo<T> &g, const int32_t *__restrict__ bzg, const int nb[S],
+                                              const int col[S], const T cxs[S], const T cys[S], const T *Vv, int Wv,
+                                              T ux, T uy, T kc, T wc, T gu[2], T gv[2], T gk[2], T gw[2]) {
+    gu[0] = gu[1] = gv[0] = gv[1] = gk[0] = gk[1] = gw[0] = gw[1] = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] == -1) continue;
+        T du, dv, dk, dw;
+        if (nb[s] >= 0) {
+            du = Vv[1 * Wv + col[s]] - ux;
+            dv = Vv[2 * Wv + col[s]] - uy;
+            dk = Vv[3 * Wv + col[s]] - kc;
+            dw = Vv[4 * Wv + col[s]] - wc;
+        } else {
+            const int b = -2 - nb[s];
+            if (bzg[b]) {
+                du = dv = dk = dw = T(0);
+            } else {
+                du = T(g.b_ux[b]) - ux;
+                dv = T(g.b_uy[b]) - uy;
+                dk = T(g.b_k[b]) - kc;
+                dw = T(g.b_w[b]) - wc;
+            }
+        }
+        gu[0] += cxs[s] * du; gu[1] += cys[s] * du;
+        gv[0] += cxs[s] * dv; gv[1] += cys[s] * dv;
+        gk[0] += cxs[s] * dk; gk[1] += cys[s] * dk;
+        gw[0] += cxs[s] * dw; gw[1] += cys[s] * dw;
+    }
+}
+
+template <typename T, int S, bool AUX>
+__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
+    k_sst_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg,
+               const int32_t *__restrict__ bzg, const T *__restrict__ M, const T *__restrict__ K,
+               const T *__restrict__ W, T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
+               T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *Vv = reinterpret_cast<T *>(smem);
+    T *Vx = Vv + 5 * Wv;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int start = tile * kTileCells;
+    const int ncell = min(kTileCells, g.n - start);
+    const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
+    const int t = threadIdx.x;
+    const int n = g.n;
+    const bool own = t < ncell, ext = t < nx, ring1 = t < n1;
+    const int c = start + t;
+    const SstParams<T> q = sst_params(p);
+
+    // ---- phase 0 ----
+    T rho = T(0), ux = T(0), uy = T(0), kc = T(0), wc = T(0), dc = T(0), ia = T(0);
+    int nb[S], col[S];
+    T cxs[S], cys[S], nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S];
+    if (own) {
+        rho = p.rho0 + M[c];
+        ux = M[(size_t)n + c];
+        uy = M[(size_t)2 * n + c];
+        kc = K[c];
+        wc = W[c];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const size_t si = (size_t)s * n + c;
+            nb[s] = g.nbr[si];
+            col[s] = lnb[si];
+            cxs[s] = g.cx[si];
+            cys[s] = g.cy[si];
+            nlx[s] = g.nlx[si];
+            nly[s] = g.nly[si];
+            rx[s] = g.rfx[si];
+            ry[s] = g.rfy[si];
+            qx[s] = g.qx[si];
+            qy[s] = g.qy[si];
+        }
+        dc = T(g.wdist[c]);
+        ia = g.inv_area[c];
+        Vv[t] = rho;
+        Vv[1 * Wv + t] = ux;
+        Vv[2 * Wv + t] = uy;
+        Vv[3 * Wv + t] = kc;
+        Vv[4 * Wv + t] = wc;
+    }
+    T hr = T(0), hu = T(0), hvv = T(0), hk = T(0), hw = T(0), hd = T(0);
+    int hnb[S], hcol[S];
+    T hcx[S], hcy[S];
+    if (ext) {
+        const int hc = rt.cell[x0 + t];
+        hr = p.rho0 + M[hc];
+        hu = M[(size_t)n + hc];
+        hvv = M[(size_t)2 * n + hc];
+        hk = K[hc];
+        hw = W[hc];
+        const int j = kTileCells + t;
+        Vv[j] = hr;
+        Vv[1 * Wv + j] = hu;
+        Vv[2 * Wv + j] = hvv;
+        Vv[3 * Wv + j] = hk;
+        Vv[4 * Wv + j] = hw;
+        if (ring1) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const size_t si = (size_t)s * n + hc;
+                hnb[s] = g.nbr[si];
+                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
+                hcx[s] = g.cx[si];
+                hcy[s] = g.cy[si];
+            }
+            hd = T(g.wdist[hc]);
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 1 ----
+    if (ring1) {
+        T gu[2], gv[2], gk[2], gw[2];
+        sst_grad_ring<T, S>(g, bzg, hnb, hcol, hcx, hcy, Vv, Wv, hu, hvv, hk, hw, gu, gv, gk, gw);
+        const SstLocal<T> o = sst_local<T, T>(hr, hk, hw, gu[0], gu[1], gv[0], gv[1], gk[0], gk[1], gw[0], gw[1], hd, p, q);
+        const int j = kTileCells + t;
+        Vx[j] = gk[0];
+        Vx[1 * Wg + j] = gk[1];
+        Vx[2 * Wg + j] = gw[0];
+        Vx[3 * Wg + j] = gw[1];
+        Vx[4 * Wg + j] = o.Gk;
+        Vx[5 * Wg + j] = o.Gw;
+    }
+    SstLocal<T> oc{};
+    T xc[11];
+    if (own) {
+        T gu[2], gv[2], gk[2], gw[2];
+        sst_grad_ring<T, S>(g, bzg, nb, col, cxs, cys, Vv, Wv, ux, uy, kc, wc, gu, gv, gk, gw);
+        oc = sst_local<T, T>(rho, kc, wc, gu[0], gu[1], gv[0], gv[1], gk[0], gk[1], gw[0], gw[1], dc, p, q);
+        Vx[t] = gk[0];
+        Vx[1 * Wg + t] = gk[1];
+        Vx[2 * Wg + t] = gw[0];
+        Vx[3 * Wg + t] = gw[1];
+        Vx[4 * Wg + t] = oc.Gk;
+        Vx[5 * Wg + t] = oc.Gw;
+        xc[0] = rho; xc[1] = ux; xc[2] = uy; xc[3] = kc; xc[4] = wc;
+        xc[5] = gk[0]; xc[6] = gk[1]; xc[7] = gw[0]; xc[8] = gw[1]; xc[9] = oc.Gk; xc[10] = oc.Gw;
+        if constexpr (AUX) {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) aux[(size_t)i * n + c] = xc[5 + i];
+            aux[(size_t)6 * n + c] = oc.sk;
+            aux[(size_t)7 * n + c] = oc.sw;
+            aux[(size_t)8 * n + c] = oc.beta;
+            aux[(size_t)9 * n + c] = oc.Sr;
+        }
+    }
+    __syncthreads();
+    if (!own) return;
+
+    // ---- phase 2: fluxes (same summation order as k_sst_b) and the update ----
+    T net_k = 0, net_w = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] == -1) continue;
+        T tk, tw;
+        if (nb[s] >= 0) {
+            const int l = col[s];
+            T xn[11];
+#pragma unroll
+            for (int i = 0; i < 5; ++i) xn[i] = Vv[i * Wv + l];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) xn[5 + i] = Vx[i * Wg + l];
+            sst_face<T, T>(xc, xn, nlx[s], nly[s], rx[s], ry[s], qx[s], qy[s], tk, tw);
+        } else {
+            const int b = -2 - nb[s];
+            sst_bface<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), nlx[s], nly[s],
+                            rx[s], ry[s], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
+        }
+        net_k += tk;
+        net_w += tw;
+    }
+    T k1, w1, nt;
+    sst_update<T, T>(rho, kc, wc, net_k, net_w, oc.sk, oc.sw, oc.beta, oc.Sr, dc, ia, p, q, k1, w1, nt);
+    K1[c] = k1;
+    W1[c] = w1;
+    nut[c] = nt;
+    tau[c] = T(3) * (p.nu + nt);
+}
+
 // ----------------------------------------------------------------------------------------------
 // Reductions (FP64, deterministic two-pass: per-block partials in a fixed grid, then one block).
 // ----------------------------------------------------------------------------------------------

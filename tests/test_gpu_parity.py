@@ -188,9 +188,12 @@ SST_MESHES = {
 }
 
 
+@pytest.mark.parametrize("sweep", ["ring", "split"])
 @pytest.mark.parametrize("name", sorted(SST_MESHES))
-def test_sst_step_parity(F, name):
-    say("sst step", name)
+def test_sst_step_parity(F, name, sweep, monkeypatch):
+    """The SST in one ring-tiled launch and as the two-kernel pair."""
+    say("sst step", name, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = SST_MESHES[name]
     m = make()
     orc, p, f, k, w = _sst_case(m, extra, 50)
