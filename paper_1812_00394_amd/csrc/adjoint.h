@@ -6,9 +6,11 @@
 //   adv_T1 (per cell j): with mu_c = -L_c / A_c, every edge whose face value j reconstructs
 //           (outgoing directions, e.n > 0) carries weight en (mu_j - mu_N) to g_j and, through the
 //           extrapolation g_j + grad g_j . r_f, en (mu_j - mu_N) r_f to the adjoint of grad g_j
-//           (Gbar_j).  Boundary edges route their weight through the ghost state's Jacobian (dual
-//           numbers), together with the ghost's use in j's own LSQ gradient (c_b . Gbar_j); the
-//           inflow angle theta enters through the rotated inlet / far-field velocities.
+//           (Gbar_j).
+//   adv_T1b (per cell with boundary edges): boundary edges route their weight through the ghost
+//           state's Jacobian (dual numbers), together with the ghost's use in j's own LSQ gradient
+//           (c_b . Gbar_j); the inflow angle theta enters through the rotated inlet / far-field
+//           velocities.
 //   adv_T2 (per cell s): the transposed LSQ gradient, gbar_s += sum_j c_(j->s) . Gbar_j over the
 //           neighbours j of s, minus (sum_k c_sk) . Gbar_s.
 // The same slot data serves both sides of an edge: seen from the neighbour N, e.n changes sign and
@@ -49,23 +51,22 @@ __device__ __forceinline__ T ghost_vjp(const Geo<T> &g, int b, T nlx, T nly, con
     return dth;
 }
 
-// L, gbar: [9][n] (direction 0 of L unused); Gbar: [16][n]; dth: [n] per-cell theta contributions (FP64).
+// L, gbar: [9][n] (direction 0 of L unused); Gbar: [16][n].  Every edge except the ghost-state
+// parts, which k_adv_T1b adds.
 template <typename T>
-__global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ f, const T *__restrict__ L,
-                                                T *__restrict__ gbar, T *__restrict__ Gbar, double *__restrict__ dth,
-                                                T rho0) {
+__global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ L, T *__restrict__ gbar,
+                                                T *__restrict__ Gbar) {
     const int j = cell_index();
     if (j >= g.n) return;
     const int n = g.n;
-    T mu[9], gj[9], gd[9], Gx[9], Gy[9];
+    T mu[9], gd[9], Gx[9], Gy[9];
     const T ia = g.inv_area[j];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         mu[a] = -L[(size_t)a * n + j] * ia;
-        gj[a] = f[(size_t)a * n + j];
         gd[a] = Gx[a] = Gy[a] = T(0);
     }
-    // pass 1: interior edges and open-boundary outgoing directions
+    // interior edges: interior edges and open-boundary outgoing directions
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const size_t si = (size_t)s * n + j;
@@ -99,26 +100,6 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
             }
         }
     }
-    // pass 2: ghost states (face values on walls / incoming directions, and the LSQ gradient)
-    T th = 0;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const size_t si = (size_t)s * n + j;
-        const int nb = g.nbr[si];
-        if (nb >= -1) continue;
-        const int b = -2 - nb;
-        const int kind = g.b_kind[b];
-        const bool wall = (kind == kWall || kind == kMovingWall);
-        const T nlx = g.nlx[si], nly = g.nly[si], cxs = g.cx[si], cys = g.cy[si];
-        T gb_bar[9];
-        gb_bar[0] = T(0);
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
-            gb_bar[a] = cxs * Gx[a] + cys * Gy[a] + ((wall || en < T(0)) ? en * mu[a] : T(0));
-        }
-        th += ghost_vjp(g, b, nlx, nly, gj, rho0, gb_bar, gd);
-    }
     // own part of the transposed LSQ gradient: grad g_j = sum_k c_jk (v_k - g_j)
     T sx = 0, sy = 0;
 #pragma unroll
@@ -137,6 +118,56 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
         Gbar[(size_t)(2 * (a - 1)) * n + j] = Gx[a];
         Gbar[(size_t)(2 * (a - 1) + 1) * n + j] = Gy[a];
     }
+}
+
+// Ghost-state part of adv_T1 for cells with boundary edges (after k_adv_T1): the face values on
+// walls and incoming directions, and the ghosts' use in the cell's own LSQ gradient, through the
+// ghost state's Jacobian.  One thread per cell: boundary edges are ordered by owner cell, and the
+// thread of a cell's first boundary edge takes all of them in slot order.  Kept out of k_adv_T1 so
+// that its dual-number registers do not limit the occupancy of the all-cell kernel.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__ f, const T *__restrict__ L,
+                                                 T *__restrict__ gbar, const T *__restrict__ Gbar,
+                                                 double *__restrict__ dth, T rho0) {
+    const int b0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b0 >= g.nb) return;
+    const int j = g.b_cell[b0];
+    if (b0 > 0 && g.b_cell[b0 - 1] == j) return;
+    const int n = g.n;
+    T mu[9], gj[9], gd[9], Gx[9], Gy[9];
+    const T ia = g.inv_area[j];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        mu[a] = -L[(size_t)a * n + j] * ia;
+        gj[a] = f[(size_t)a * n + j];
+        gd[a] = T(0);
+    }
+    Gx[0] = Gy[0] = T(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        Gx[a] = Gbar[(size_t)(2 * (a - 1)) * n + j];
+        Gy[a] = Gbar[(size_t)(2 * (a - 1) + 1) * n + j];
+    }
+    T th = 0;
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + j;
+        const int nb = g.nbr[si];
+        if (nb >= -1) continue;
+        const int b = -2 - nb;
+        const int kind = g.b_kind[b];
+        const bool wall = (kind == kWall || kind == kMovingWall);
+        const T nlx = g.nlx[si], nly = g.nly[si], cxs = g.cx[si], cys = g.cy[si];
+        T gb_bar[9];
+        gb_bar[0] = T(0);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+            gb_bar[a] = cxs * Gx[a] + cys * Gy[a] + ((wall || en < T(0)) ? en * mu[a] : T(0));
+        }
+        th += ghost_vjp(g, b, nlx, nly, gj, rho0, gb_bar, gd);
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gbar[(size_t)a * n + j] += gd[a];
     dth[j] += (double)th;
 }
 

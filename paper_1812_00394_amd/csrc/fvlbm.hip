@@ -596,7 +596,9 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
     k_fill<T><<<blocks_for(9 * (size_t)n), kBlock, 0, s>>>(9 * n, (T *)st->A, T(0));
     double *dth = st->scratch + 8 * (size_t)n;   // last plane of the staging area (free after import)
     k_fill<double><<<nbk, kBlock, 0, s>>>(n, dth, 0.0);
-    k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->Y, (T *)st->A, (T *)st->G, dth, T(st->par.rho0));
+    k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->Y, (T *)st->A, (T *)st->G);
+    if (g.nb > 0)
+        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->Y, (T *)st->A, (const T *)st->G, dth, T(st->par.rho0));
     k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, (T *)st->A);
     k_sum<double><<<kRedBlocks, kBlock, 0, s>>>(n, dth, st->partial);
     k_export_f<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->A, st->scratch, 0.0);
@@ -616,9 +618,10 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct AdjLayout {
-    T *ckpt, *seg, *lF, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *F1, *ltau, *lx, *lnet, *lown, *lgrad;
+    T *ckpt, *seg, *stg, *lF, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *F1, *ltau, *lx, *lnet, *lown, *lgrad;
     double *pbar;
     size_t state_len;
+    size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [10][n]
 };
 
 template <typename T>
@@ -628,6 +631,8 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     L.state_len = sl;
     L.ckpt = cv.take<T>(nck * sl);
     L.seg = cv.take<T>((size_t)ckpt * sl);
+    L.stage_len = 38 * (size_t)n;
+    L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
     L.lF = cv.take<T>(9 * (size_t)n);
     L.lK = cv.take<T>(n);
     L.lW = cv.take<T>(n);
@@ -696,7 +701,9 @@ template <typename T>
 void adv_transpose(fvlbm_state *st, const AdjLayout<T> &L, const T *f, T *out) {
     const Geo<T> &g = geo_of<T>(st);
     const int nbk = blocks_for(g.n);
-    k_adv_T1<T><<<nbk, kBlock, 0, st->stream>>>(g, f, L.lam, out, (T *)st->G, L.pbar, T(st->par.rho0));
+    k_adv_T1<T><<<nbk, kBlock, 0, st->stream>>>(g, L.lam, out, (T *)st->G);
+    if (g.nb > 0)
+        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, st->stream>>>(g, f, L.lam, out, (const T *)st->G, L.pbar, T(st->par.rho0));
     k_adv_T2<T><<<nbk, kBlock, 0, st->stream>>>(g, st->rev, (const T *)st->G, out);
 }
 
@@ -706,40 +713,71 @@ __global__ void k_scale(size_t n, const T *__restrict__ x, T a, T *__restrict__ 
     if (i < n) y[i] = a * x[i];
 }
 
-// Reverse of one step whose input state is in `slot` (on entry L.lF, L.lK, L.lW hold the adjoint
-// of the step's output; on exit that of its input).
+// Stage data of one step of a segment, kept from the segment's forward pass for its reverse.
 template <typename T>
-void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot) {
+struct StageSlot {
+    T *Y, *X, *A, *tau, *aux;
+};
+
+template <typename T>
+StageSlot<T> stage_slot(const fvlbm_state *st, const AdjLayout<T> &L, int i) {
+    const size_t n = st->n_cells;
+    T *b = L.stg + (size_t)i * L.stage_len;
+    return StageSlot<T>{b, b + 9 * n, b + 18 * n, st->sst ? b + 27 * n : (T *)st->tau, b + 28 * n};
+}
+
+// Runs one step with its stage buffers (f^(2), f^(3), Q, and with the SST tau and aux) pointed at
+// a stage slot, so that the reverse of the step needs no recomputation.
+template <typename T>
+void step_into(fvlbm_state *st, const StageSlot<T> &ss) {
+    void *X = st->X, *Y = st->Y, *A = st->A, *tau = st->tau, *aux = st->aux;
+    st->X = ss.X;
+    st->Y = ss.Y;
+    st->A = ss.A;
+    if (st->sst) {
+        st->tau = ss.tau;
+        st->aux = ss.aux;
+        st->want_aux = true;
+    }
+    launch_step<T>(st);
+    st->X = X;
+    st->Y = Y;
+    st->A = A;
+    st->tau = tau;
+    st->aux = aux;
+    st->want_aux = false;
+}
+
+// Reverse of one step whose input state is in `slot` and whose stage data is in `ss` (on entry
+// L.lF, L.lK, L.lW hold the adjoint of the step's output; on exit that of its input).
+template <typename T>
+void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const StageSlot<T> &ss) {
     const Geo<T> &g = geo_of<T>(st);
     const int n = g.n, nbk = blocks_for(n);
     const size_t n9 = 9 * (size_t)n;
     hipStream_t s = st->stream;
     StepPar<T> p = step_par<T>(st->par);
-    // recompute the step: X = f3, Y = f2, A = Q, tau, aux; keep the input macro / k / omega buffers
-    load_state<T>(st, slot);
-    T *Mn = (T *)st->M[st->cur_m];
-    T *Kn = st->sst ? (T *)st->K[st->cur_kw] : nullptr, *Wn = st->sst ? (T *)st->W[st->cur_kw] : nullptr;
-    st->want_aux = true;
-    launch_step<T>(st);
-    st->want_aux = false;
+    // the step's input: f and its macro variables, k, omega
     const T *fn = slot;
-    k_collide1<T><<<nbk, kBlock, 0, s>>>(n, fn, (const T *)st->tau, L.F1, p);
-    AdjBufs<T> b{fn, L.F1, (const T *)st->Y, (const T *)st->X, (const T *)st->A, (const T *)st->tau,
-                 L.lF, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
+    T *Mn = (T *)st->M[st->cur_m];
+    k_macro<T><<<nbk, kBlock, 0, s>>>(n, fn, Mn, T(st->par.rho0));
+    const T *Kn = st->sst ? slot + 9 * (size_t)n : nullptr, *Wn = st->sst ? slot + 10 * (size_t)n : nullptr;
+    k_collide1<T><<<nbk, kBlock, 0, s>>>(n, fn, ss.tau, L.F1, p);
+    AdjBufs<T> b{fn, L.F1, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
     // Ga3 with weight dt/3 in f^{n+1}
     k_scale<T><<<blocks_for(n9), kBlock, 0, s>>>(n9, L.lF, p.dt / T(3), L.lam);
     k_fill<T><<<blocks_for(n9), kBlock, 0, s>>>((int)n9, L.lf3, T(0));
-    adv_transpose<T>(st, L, (const T *)st->X, L.lf3);
+    adv_transpose<T>(st, L, ss.X, L.lf3);
     k_adj_stage3<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    adv_transpose<T>(st, L, (const T *)st->Y, L.lf2);
+    adv_transpose<T>(st, L, ss.Y, L.lf2);
     k_adj_stage2<T><<<nbk, kBlock, 0, s>>>(n, b, p);
     adv_transpose<T>(st, L, L.F1, L.lf1);
     k_adj_stage1<T><<<nbk, kBlock, 0, s>>>(n, b, p);
     if (st->sst) {
         SstAdj sa{st->bzg, L.pbar};
         k_fill<T><<<blocks_for(11 * (size_t)n), kBlock, 0, s>>>(11 * n, L.lx, T(0));
-        k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, (const T *)st->aux, L.lK, L.lW, L.ltau, L.lx, L.lnet, L.lown, p);
-        k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, (const T *)st->aux, L.lnet, L.lx, p);
+        k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW, L.ltau, L.lx, L.lnet, L.lown, p);
+        k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lnet, L.lx, p);
         k_adj_sst_local<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, L.lown, L.lx, L.lgrad, p);
         k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, Mn, L.lgrad, L.lx, L.lF, L.lK, L.lW, p.rho0);
     }
@@ -747,6 +785,8 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot) {
 }
 
 // Reverse of the whole recorded run (L.lF / lK / lW seeded with the adjoint of the final state).
+// Each segment is recomputed once from its checkpoint, keeping every step's input state and stage
+// data; then its steps are reversed from the last.
 template <typename T>
 void reverse_run(fvlbm_state *st, const AdjLayout<T> &L) {
     const int N = st->rec_steps, C = st->rec_ckpt;
@@ -756,9 +796,10 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L) {
         load_state<T>(st, L.ckpt + (size_t)sg * L.state_len);
         for (int i = first; i < last; ++i) {
             save_state<T>(st, L.seg + (size_t)(i - first) * L.state_len);
-            if (i + 1 < last) launch_step<T>(st);
+            step_into<T>(st, stage_slot<T>(st, L, i - first));
         }
-        for (int i = last - 1; i >= first; --i) reverse_step<T>(st, L, L.seg + (size_t)(i - first) * L.state_len);
+        for (int i = last - 1; i >= first; --i)
+            reverse_step<T>(st, L, L.seg + (size_t)(i - first) * L.state_len, stage_slot<T>(st, L, i - first));
     }
     // restore the final state
     load_state<T>(st, L.ckpt + (size_t)nseg * L.state_len);
