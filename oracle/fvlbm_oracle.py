@@ -69,7 +69,10 @@ def default_params(**kw):
 # Geometry (computed once, float64).  Readings: r1 (A, n, dl), G1-G4 of the design notes.
 # =============================================================================================
 class Geometry:
-    def __init__(self, mesh):
+    def __init__(self, mesh, wall_segments=None):
+        """wall_segments: optional [m, 2, 2] end points of the wall edges the wall distance is
+        measured to (default: the WALL / MOVING_WALL edges of this mesh); a piece cut out of a
+        larger mesh passes the walls of the whole mesh."""
         nodes = np.asarray(mesh["nodes"], dtype=np.float64)
         ptr = np.asarray(mesh["cell_ptr"], dtype=np.int64)
         cn = np.asarray(mesh["cell_nodes"], dtype=np.int64)
@@ -161,9 +164,13 @@ class Geometry:
         # ---- G4: wall distance, brute force point-to-segment over all wall edges ----
         wall_b = np.nonzero(np.isin(self.kinds[bgrp], [WALL, MOVING_WALL]))[0]
         self.wall_dist = np.full(n, NO_WALL_DISTANCE)
-        if len(wall_b):
+        if wall_segments is not None:
+            P = np.asarray(wall_segments, dtype=np.float64)[:, 0]
+            Q = np.asarray(wall_segments, dtype=np.float64)[:, 1]
+        else:
             P = nodes[bfn[wall_b, 0]]
             Q = nodes[bfn[wall_b, 1]]
+        if len(P):
             for s in range(0, n, 4096):
                 x = self.xc[s:s + 4096, None, :]
                 seg = Q - P
@@ -202,9 +209,9 @@ def stage_solve(rhs, rho, jx, jy, a):
 
 
 class Oracle:
-    def __init__(self, mesh, params):
+    def __init__(self, mesh, params, wall_segments=None):
         self.m = mesh
-        self.g = Geometry(mesh)
+        self.g = Geometry(mesh, wall_segments)
         self.p = dict(params)
         p = self.p
         ng = len(self.g.kinds)

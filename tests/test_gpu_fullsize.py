@@ -1,0 +1,101 @@
+"""Parity at the benchmark's full size and launch configuration: the 4.0M-cell graded Delaunay
+rectangle with SST, the developed-stream initial state and the sweep variant the benchmark times
+(ring-tiled), one step in FP64 and in FP32-deviation storage, against the oracle on sampled cells.
+
+The oracle cannot step four million cells, but one step reaches only six edge rings (measured in
+test_submesh_oracle.py, which also checks the method against full oracle runs): for sample cells
+in the interior, next to each wall, the inlet, the outlet and in the corners, the oracle steps the
+piece of the mesh within 10 rings of them, with the wall distance measured to the whole mesh's
+walls, and gives their exact new values.  Gates: FP64 1e-12 of max |f - w rho0| for f, 1e-11 for
+k, omega, nu_t (the small-mesh SST gates); FP32-deviation 2e-6 of U for u and 2e-6 relative for
+k and omega (the FP32 SST gate after one step)."""
+import sys
+
+import numpy as np
+import pytest
+
+import bench
+from oracle import fvlbm_oracle as O
+from paper_1812_00394_amd import meshgen as mg
+from tests import submesh as sm
+
+pytestmark = pytest.mark.gpu
+
+U, H, RE = 0.05, 1.0, 3.6e4
+NU = U * H / RE
+DT = 6.0e-5      # about 0.9 x the advective Courant limit of this mesh (14 tau0)
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1812_00394_amd import fvlbm
+    fvlbm.lib()
+    return fvlbm
+
+
+def _params(extra_group=False):
+    gu, gr, gk, gw = [[0, 0], [U, 0], [0, 0]], [1, 1, 1], [0, 1e-6, 0], [0, 1e-2, 0]
+    if extra_group:
+        gu, gr, gk, gw = gu + [[0, 0]], gr + [1], gk + [1e-6], gw + [1e-2]
+    return O.default_params(nu=NU, dt=DT, sst=True, group_u=gu, group_rho=gr, group_k=gk, group_w=gw)
+
+
+@pytest.mark.timeout(900)
+def test_fullsize_sampled_parity(F):
+    say("full size: delaunay 2M points, mesh generation")
+    m = mg.delaunay_rect(n_points=2_000_000, seed=5)
+    n = len(m["cell_ptr"]) - 1
+    assert n > 3_900_000
+    xc = sm.centroids(m)
+    u, k, w = bench.initial_fields(dict(profile="channel", U=U, H=H, k=1e-6, w=1e-2), xc, NU)
+    rng = np.random.default_rng(11)
+    bottom, inlet, outlet = sm.boundary_cells(m, 0), sm.boundary_cells(m, 1), sm.boundary_cells(m, 2)
+    top = bottom[xc[bottom, 1] > 0.5 * H]
+    bottom = bottom[xc[bottom, 1] <= 0.5 * H]
+    corners = np.intersect1d(np.r_[inlet, outlet], np.r_[bottom, top])
+    seeds = np.unique(np.r_[rng.choice(n, 6, replace=False), rng.choice(bottom, 3), rng.choice(top, 2),
+                            rng.choice(inlet, 2), rng.choice(outlet, 2), corners[:4]])
+    say("oracle on the piece within 10 rings of", len(seeds), "sample cells")
+    piece, cells = sm.cut(m, sm.rings(m, seeds, 10))
+    po = O.Oracle(piece, _params(True), wall_segments=sm.wall_segments(m))
+    g0, k0, w0 = po.init_state(np.ones(len(cells)), u[cells, 0], u[cells, 1], k[cells], w[cells])
+    g1, k1, w1 = po.step(g0, k0, w0)
+    nut1 = po.last_nut
+    at = np.searchsorted(cells, seeds)
+    ref_f, ref_k, ref_w, ref_nut = g1[:, at], k1[at], w1[at], nut1[at]
+    _, ref_ux, ref_uy, _ = po.macro(g1[:, at])
+
+    say("library mesh preprocessing")
+    M = F.Mesh(m)
+    for precision in ("fp64", "fp32dev"):
+        say("one step on the GPU,", precision)
+        st = F.State(M, _params(), precision=precision, rho=np.ones(n), u=u, k=k, omega=w)
+        st.timing(True)
+        st.step(1)
+        kt = st.timing_read()
+        # the benchmark's launch configuration: ring-tiled SST and sweeps
+        assert kt["sst"][1] == 1 and kt["sweep2"][1] == 1 and kt["collide1"][1] == 0, kt
+        mo = st.moments()
+        if precision == "fp64":
+            f = st.get_f()[:, seeds]
+            scale = np.abs(ref_f - O.WT[:, None]).max()
+            err = np.abs(f - ref_f).max() / scale
+            assert err < 1e-12, err
+            for name, got, ref in (("k", mo["k"][seeds], ref_k), ("omega", mo["omega"][seeds], ref_w),
+                                   ("nu_t", mo["nu_t"][seeds], ref_nut)):
+                e = np.abs(got - ref).max() / np.abs(ref).max()
+                assert e < 1e-11, (name, e)
+        else:
+            du = max(np.abs(mo["u"][seeds, 0] - ref_ux).max(), np.abs(mo["u"][seeds, 1] - ref_uy).max()) / U
+            dk = np.abs(mo["k"][seeds] - ref_k).max() / np.abs(ref_k).max()
+            dw = np.abs(mo["omega"][seeds] - ref_w).max() / np.abs(ref_w).max()
+            say("fp32dev errors at the samples: du/U", du, "dk", dk, "dw", dw)
+            assert du < 2e-6 and dk < 2e-6 and dw < 2e-6, (du, dk, dw)
+        del st

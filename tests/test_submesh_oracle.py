@@ -1,0 +1,71 @@
+"""The sampled full-size parity check rests on one property of the scheme: after one step, a cell
+holds what the oracle computes on any piece of the mesh containing every cell within R rings of
+it, for R at least the step's reach (two rings for the SST update, two per stage sweep), when the
+wall distance is measured to the whole mesh's walls.  Checked here against full oracle runs on a
+mesh small enough to step whole, with the workload of the benchmark (graded Delaunay rectangle,
+SST, developed stream)."""
+import numpy as np
+import pytest
+
+import bench
+from oracle import fvlbm_oracle as O
+from paper_1812_00394_amd import meshgen as mg
+from tests import submesh as sm
+
+
+def _case(n_points=1500):
+    m = mg.delaunay_rect(n_points=n_points, seed=5)
+    U, H, Re = 0.05, 1.0, 3.6e4
+    nu = U * H / Re
+    p = O.default_params(nu=nu, dt=4e-4, sst=True, group_u=[[0, 0], [U, 0], [0, 0]], group_rho=[1, 1, 1],
+                         group_k=[0, 1e-6, 0], group_w=[0, 1e-2, 0])
+    xc = sm.centroids(m)
+    u, k, w = bench.initial_fields(dict(profile="channel", U=U, H=H, k=1e-6, w=1e-2), xc, nu)
+    return m, p, u, k, w
+
+
+def _piece_params(p):
+    q = dict(p)
+    q["group_u"] = list(p["group_u"]) + [[0, 0]]
+    q["group_rho"] = list(p["group_rho"]) + [1]
+    q["group_k"] = list(p["group_k"]) + [1e-6]
+    q["group_w"] = list(p["group_w"]) + [1e-2]
+    return q
+
+
+def test_centroids_match_oracle():
+    m, _, _, _, _ = _case(400)
+    np.testing.assert_allclose(sm.centroids(m), O.Geometry(m).xc, rtol=0, atol=1e-15)
+
+
+def test_wall_segments_reproduce_own_walls():
+    m, _, _, _, _ = _case(400)
+    a = O.Geometry(m).wall_dist
+    b = O.Geometry(m, wall_segments=sm.wall_segments(m)).wall_dist
+    np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("R,exact", [(10, True), (2, False)])
+def test_piece_reproduces_full_step(R, exact):
+    """R = 10 rings: the sample cells match the full run to rounding; R = 2 (less than the reach)
+    must not, which shows the check can fail."""
+    m, p, u, k, w = _case()
+    n = len(m["cell_ptr"]) - 1
+    full = O.Oracle(m, p)
+    f0, k0, w0 = full.init_state(np.ones(n), u[:, 0], u[:, 1], k, w)
+    f1, k1, w1 = full.step(f0, k0, w0)
+    rng = np.random.default_rng(7)
+    seeds = np.unique(np.r_[rng.choice(n, 4, replace=False), sm.boundary_cells(m, 0)[:2],
+                            sm.boundary_cells(m, 1)[:1], sm.boundary_cells(m, 2)[:1]])
+    piece, cells = sm.cut(m, sm.rings(m, seeds, R))
+    po = O.Oracle(piece, _piece_params(p), wall_segments=sm.wall_segments(m))
+    g0, kk0, ww0 = po.init_state(np.ones(len(cells)), u[cells, 0], u[cells, 1], k[cells], w[cells])
+    g1, kk1, ww1 = po.step(g0, kk0, ww0)
+    where = np.searchsorted(cells, seeds)
+    scale = np.abs(f1 - O.WT[:, None]).max()
+    err_f = np.abs(g1[:, where] - f1[:, seeds]).max() / scale
+    err_k = np.abs(kk1[where] - k1[seeds]).max() / np.abs(k1).max()
+    if exact:
+        assert err_f < 1e-13 and err_k < 1e-13, (err_f, err_k)
+    else:
+        assert err_f > 1e-10, err_f
