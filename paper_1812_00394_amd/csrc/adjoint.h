@@ -197,6 +197,186 @@ __global__ void __launch_bounds__(256) k_adv_T2(Geo<T> g, const int8_t *__restri
     for (int a = 1; a < 9; ++a) gbar[(size_t)a * n + s0] += acc[a];
 }
 
+// Ring-tiled transposed convection (adv_T1 and adv_T2 in one launch, ghost parts excepted), in the
+// layout of the ring-tiled forward sweeps:
+//   phase 0: mu = -L / A of tile cell t and ext cell t into LDS; the edge data of tile cell t (with
+//            the LSQ coefficient of each interior neighbour's slot that points back, c_(j->t))
+//            and of ring-1 cell t into registers;
+//   phase 1: adv_T1 of tile cell t and ring-1 cell t: Gbar (the adjoint of the LSQ gradient) into
+//            LDS, and the own part of tile cell t;
+//   phase 2: adv_T2 of tile cell t from its neighbours' Gbar in LDS; out += (ACC) or = the sum.
+// Gbar goes to global memory only for cells with boundary edges, where k_adv_T1b reads it.
+template <typename T, int S, bool ACC>
+__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
+    k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
+                 int Wg, const T *__restrict__ L, T *__restrict__ out, T *__restrict__ Gbar) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *V = reinterpret_cast<T *>(smem);   // [8][Wv]: mu of directions 1..8
+    T *Gl = V + 8 * Wv;                   // [16][Wg]
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int start = tile * kTileCells;
+    const int ncell = min(kTileCells, g.n - start);
+    const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
+    const int t = threadIdx.x;
+    const int n = g.n;
+    const bool own = t < ncell, ext = t < nx, ring1 = t < n1;
+    const int c = start + t;
+
+    // ---- phase 0 ----
+    T mu[9];
+    int nb[S], col[S];
+    T nlx[S], nly[S], rx[S], ry[S], cxs[S], cys[S], cbx[S], cby[S];
+    if (own) {
+        const T ia = g.inv_area[c];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            mu[a] = -L[(size_t)a * n + c] * ia;
+            V[(a - 1) * Wv + t] = mu[a];
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const size_t si = (size_t)s * n + c;
+            nb[s] = g.nbr[si];
+            col[s] = lnb[si];
+            nlx[s] = g.nlx[si];
+            nly[s] = g.nly[si];
+            rx[s] = g.rfx[si];
+            ry[s] = g.rfy[si];
+            cxs[s] = g.cx[si];
+            cys[s] = g.cy[si];
+            cbx[s] = cby[s] = T(0);
+            if (nb[s] >= 0) {
+                const size_t sj = (size_t)rev[si] * n + nb[s];
+                cbx[s] = g.cx[sj];
+                cby[s] = g.cy[sj];
+            }
+        }
+    }
+    T hmu[9];
+    int hnb[S], hcol[S];
+    T hnlx[S], hnly[S], hrx[S], hry[S], hcx[S], hcy[S];
+    if (ext) {
+        const int hc = rt.cell[x0 + t];
+        const T ia = g.inv_area[hc];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            hmu[a] = -L[(size_t)a * n + hc] * ia;
+            V[(a - 1) * Wv + kTileCells + t] = hmu[a];
+        }
+        if (ring1) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const size_t si = (size_t)s * n + hc;
+                hnb[s] = g.nbr[si];
+                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
+                hnlx[s] = g.nlx[si];
+                hnly[s] = g.nly[si];
+                hrx[s] = g.rfx[si];
+                hry[s] = g.rfy[si];
+                hcx[s] = g.cx[si];
+                hcy[s] = g.cy[si];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 1: adv_T1 (same summation order as k_adv_T1) ----
+    // weights of the edges whose face value cell x reconstructs: interior edges (mu_x - mu_N) and
+    // outgoing directions of open boundaries (mu_x); gd: the part on g_x itself
+    auto t1 = [&](const T m[9], const int *nbs, const int *cols, const T *nx_, const T *ny_, const T *rx_,
+                  const T *ry_, T gd[9], T Gx[9], T Gy[9]) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gd[a] = Gx[a] = Gy[a] = T(0);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nbs[s] == -1) continue;
+            if (nbs[s] >= 0) {
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const T en = T(ex(a)) * nx_[s] + T(ey(a)) * ny_[s];
+                    if (en > T(0)) {
+                        const T w = en * (m[a] - V[(a - 1) * Wv + cols[s]]);
+                        gd[a] += w;
+                        Gx[a] += w * rx_[s];
+                        Gy[a] += w * ry_[s];
+                    }
+                }
+            } else {
+                const int kind = g.b_kind[-2 - nbs[s]];
+                if (kind == kWall || kind == kMovingWall) continue;
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const T en = T(ex(a)) * nx_[s] + T(ey(a)) * ny_[s];
+                    if (en >= T(0)) {
+                        const T w = en * m[a];
+                        gd[a] += w;
+                        Gx[a] += w * rx_[s];
+                        Gy[a] += w * ry_[s];
+                    }
+                }
+            }
+        }
+    };
+    if (ring1) {
+        T gd[9], Gx[9], Gy[9];
+        t1(hmu, hnb, hcol, hnlx, hnly, hrx, hry, gd, Gx, Gy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gl[(2 * (a - 1)) * Wg + kTileCells + t] = Gx[a];
+            Gl[(2 * (a - 1) + 1) * Wg + kTileCells + t] = Gy[a];
+        }
+    }
+    T gd[9], Gx[9], Gy[9];
+    if (own) {
+        t1(mu, nb, col, nlx, nly, rx, ry, gd, Gx, Gy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gl[(2 * (a - 1)) * Wg + t] = Gx[a];
+            Gl[(2 * (a - 1) + 1) * Wg + t] = Gy[a];
+        }
+    }
+    __syncthreads();
+    if (!own) return;
+
+    // ---- phase 2: own LSQ part, then adv_T2 (same order as k_adv_T1 + k_adv_T2) ----
+    T sx = 0, sy = 0;
+    bool bnd = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] == -1) continue;
+        sx += cxs[s];
+        sy += cys[s];
+        bnd = bnd || nb[s] <= -2;
+    }
+#pragma unroll
+    for (int a = 1; a < 9; ++a) gd[a] -= sx * Gx[a] + sy * Gy[a];
+    T acc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] < 0) continue;
+#pragma unroll
+        for (int a = 1; a < 9; ++a)
+            acc[a] += cbx[s] * Gl[(2 * (a - 1)) * Wg + col[s]] + cby[s] * Gl[(2 * (a - 1) + 1) * Wg + col[s]];
+    }
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        const size_t i = (size_t)a * n + c;
+        if constexpr (ACC)
+            out[i] = (out[i] + gd[a]) + acc[a];
+        else
+            out[i] = gd[a] + acc[a];
+    }
+    if (bnd) {
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gbar[(size_t)(2 * (a - 1)) * n + c] = Gx[a];
+            Gbar[(size_t)(2 * (a - 1) + 1) * n + c] = Gy[a];
+        }
+    }
+}
+
 }  // namespace fvlbm
 
 namespace fvlbm {

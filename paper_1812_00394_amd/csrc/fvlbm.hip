@@ -582,6 +582,40 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
     check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+// Transposed convection at field f applied to lam, accumulated into out (acc) or stored there;
+// the theta part per cell is added to dth.  Uses st->G for the gradient adjoints.
+template <typename T>
+void adv_transpose(fvlbm_state *st, const T *f, const T *lam, T *out, double *dth, bool acc) {
+    const Geo<T> &g = geo_of<T>(st);
+    const int nbk = blocks_for(g.n);
+    hipStream_t s = st->stream;
+    if (st->ring) {
+        const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+        const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+        const size_t lds = st->lds_bytes;
+        T *Gb = (T *)st->G;
+        if (st->ring_s == 3) {
+            if (acc)
+                k_adv_T_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+            else
+                k_adv_T_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+        } else {
+            if (acc)
+                k_adv_T_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+            else
+                k_adv_T_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+        }
+        if (g.nb > 0)
+            k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, lam, out, (const T *)st->G, dth, T(st->par.rho0));
+        return;
+    }
+    if (!acc) k_fill<T><<<blocks_for(9 * (size_t)g.n), kBlock, 0, s>>>(9 * g.n, out, T(0));
+    k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, out, (T *)st->G);
+    if (g.nb > 0)
+        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, lam, out, (const T *)st->G, dth, T(st->par.rho0));
+    k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, out);
+}
+
 // Diagnostic: gbar = Gamma^a(g)^T lam and d(lam . Gamma^a(g))/d theta.
 template <typename T>
 void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *lam, double *out, double *dtheta) {
@@ -596,10 +630,7 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
     k_fill<T><<<blocks_for(9 * (size_t)n), kBlock, 0, s>>>(9 * n, (T *)st->A, T(0));
     double *dth = st->scratch + 8 * (size_t)n;   // last plane of the staging area (free after import)
     k_fill<double><<<nbk, kBlock, 0, s>>>(n, dth, 0.0);
-    k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->Y, (T *)st->A, (T *)st->G);
-    if (g.nb > 0)
-        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->Y, (T *)st->A, (const T *)st->G, dth, T(st->par.rho0));
-    k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, (T *)st->A);
+    adv_transpose<T>(st, (const T *)st->X, (const T *)st->Y, (T *)st->A, dth, true);
     k_sum<double><<<kRedBlocks, kBlock, 0, s>>>(n, dth, st->partial);
     k_export_f<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->A, st->scratch, 0.0);
     k_finish<1><<<1, kBlock, 0, s>>>(st->partial, kRedBlocks, st->result);
@@ -696,17 +727,6 @@ void record(fvlbm_state *st) {
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
 }
 
-// Transposed convection at field f applied to L.lam, accumulated into out (theta into pbar[0]).
-template <typename T>
-void adv_transpose(fvlbm_state *st, const AdjLayout<T> &L, const T *f, T *out) {
-    const Geo<T> &g = geo_of<T>(st);
-    const int nbk = blocks_for(g.n);
-    k_adv_T1<T><<<nbk, kBlock, 0, st->stream>>>(g, L.lam, out, (T *)st->G);
-    if (g.nb > 0)
-        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, st->stream>>>(g, f, L.lam, out, (const T *)st->G, L.pbar, T(st->par.rho0));
-    k_adv_T2<T><<<nbk, kBlock, 0, st->stream>>>(g, st->rev, (const T *)st->G, out);
-}
-
 template <typename T>
 __global__ void k_scale(size_t n, const T *__restrict__ x, T a, T *__restrict__ y) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -766,12 +786,11 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     AdjBufs<T> b{fn, L.F1, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
     // Ga3 with weight dt/3 in f^{n+1}
     k_scale<T><<<blocks_for(n9), kBlock, 0, s>>>(n9, L.lF, p.dt / T(3), L.lam);
-    k_fill<T><<<blocks_for(n9), kBlock, 0, s>>>((int)n9, L.lf3, T(0));
-    adv_transpose<T>(st, L, ss.X, L.lf3);
+    adv_transpose<T>(st, ss.X, L.lam, L.lf3, L.pbar, false);
     k_adj_stage3<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    adv_transpose<T>(st, L, ss.Y, L.lf2);
+    adv_transpose<T>(st, ss.Y, L.lam, L.lf2, L.pbar, true);
     k_adj_stage2<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    adv_transpose<T>(st, L, L.F1, L.lf1);
+    adv_transpose<T>(st, L.F1, L.lam, L.lf1, L.pbar, true);
     k_adj_stage1<T><<<nbk, kBlock, 0, s>>>(n, b, p);
     if (st->sst) {
         SstAdj sa{st->bzg, L.pbar};

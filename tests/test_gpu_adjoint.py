@@ -47,9 +47,12 @@ def _state(n, rng):
     return O.feq(rho, ux, uy) + 2e-4 * O.WT[:, None] * rng.standard_normal((9, n))
 
 
+@pytest.mark.parametrize("sweep", ["ring", "split"])
 @pytest.mark.parametrize("name", sorted(MESHES))
-def test_advection_transpose_dot_product(F, name):
-    say("advection transpose", name)
+def test_advection_transpose_dot_product(F, name, sweep, monkeypatch):
+    """The ring-tiled transposed convection and the three-kernel one (split path)."""
+    say("advection transpose", name, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = MESHES[name]
     m = make()
     p = O.default_params(nu=1e-3, dt=1e-2, **extra)
@@ -120,9 +123,11 @@ def _oracle_final(m, p, f0, k0, w0, N):
 PARAMS = ["theta", "sigma_k1", "sigma_w1", "beta_star", "a1"]
 
 
+@pytest.mark.parametrize("sweep", ["ring", "split"])
 @pytest.mark.parametrize("name", sorted(RUNS))
-def test_run_adjoint_dot_product_and_params(F, name):
-    say("run adjoint", name)
+def test_run_adjoint_dot_product_and_params(F, name, sweep, monkeypatch):
+    say("run adjoint", name, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     m, p, orc, f0, k0, w0, sst = _run_case(name)
     n = orc.g.n
     N = 3
