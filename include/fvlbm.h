@@ -212,7 +212,7 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *
  * fvlbm_adjoint_bytes: device bytes of the adjoint workspace for n_steps recorded steps with a
  *   checkpoint every ckpt_every steps: checkpoints (11 n values each), one segment of input states
- *   and stage data (49 n values per step), adjoint fields.
+ *   and stage data (51 n values per step), adjoint fields.
  * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
  *   (f, k, omega) every ckpt_every steps and at the end in `workspace` (device memory owned by the
  *   caller, 256-byte aligned, kept alive until the adjoint has run).

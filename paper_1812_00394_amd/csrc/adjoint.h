@@ -18,6 +18,7 @@
 #pragma once
 
 #include "kernels.h"
+#include "sst_reverse.h"
 
 namespace fvlbm {
 
@@ -605,33 +606,8 @@ struct SstAdj {
     double *pbar;
 };
 
-template <typename T>
-__device__ __forceinline__ void sst_net(const Geo<T> &g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
-                                        const T *__restrict__ K, const T *__restrict__ W, const T *__restrict__ aux,
-                                        int c, T rho0, const T xc[11], T &net_k, T &net_w) {
-    const int n = g.n;
-    net_k = net_w = T(0);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const size_t si = (size_t)s * n + c;
-        const int nb = g.nbr[si];
-        if (nb == -1) continue;
-        T tk, tw;
-        if (nb >= 0) {
-            T xn[11];
-            sst_cell_x(n, nb, rho0, M, K, W, aux, xn);
-            sst_face<T, T>(xc, xn, g.nlx[si], g.nly[si], g.rfx[si], g.rfy[si], g.qx[si], g.qy[si], tk, tw);
-        } else {
-            const int b = -2 - nb;
-            sst_bface<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), g.nlx[si], g.nly[si],
-                            g.rfx[si], g.rfy[si], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
-        }
-        net_k += tk;
-        net_w += tw;
-    }
-}
-
-// SB1: reverse of the point-implicit update and of tau = 3 (nu + nu_t).
+// SB1: reverse of the point-implicit update and of tau = 3 (nu + nu_t) (cell-local: the net
+// inflows are aux planes 10, 11 of the forward).
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_sst_update(Geo<T> g, SstAdj sa, const T *__restrict__ M,
                                                         const T *__restrict__ K, const T *__restrict__ W,
@@ -642,32 +618,20 @@ __global__ void __launch_bounds__(256) k_adj_sst_update(Geo<T> g, SstAdj sa, con
     const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
-    T xc[11];
-    sst_cell_x(n, c, p.rho0, M, K, W, aux, xc);
-    T nk, nw;
-    sst_net(g, sa.bzg, M, K, W, aux, c, p.rho0, xc, nk, nw);
-    using D = Dual<T, 11>;
-    // inputs: rho, k, omega, net_k, net_w, sk, sw, beta, S, a1, beta*
-    const D rho = D::var(xc[0], 0), k = D::var(xc[3], 1), w = D::var(xc[4], 2);
-    const D netk = D::var(nk, 3), netw = D::var(nw, 4);
-    const D sk = D::var(aux[(size_t)6 * n + c], 5), sw = D::var(aux[(size_t)7 * n + c], 6);
-    const D beta = D::var(aux[(size_t)8 * n + c], 7), Sr = D::var(aux[(size_t)9 * n + c], 8);
-    SstParams<D> q{D::var(p.a1, 9), D::var(p.bstar, 10), D(p.sk1), D(p.sw1)};
-    D k1, w1, nut;
-    sst_update<D, T>(rho, k, w, netk, netw, sk, sw, beta, Sr, T(g.wdist[c]), g.inv_area[c], p, q, k1, w1, nut);
-    const T a_k = lk1[c], a_w = lw1[c], a_t = T(3) * ltau[c];
-    T l[11];
+    T xb[3] = {0, 0, 0}, ob[6];
+    SstParBar<T> pb;
+    sst_update_rev<T>(p.rho0 + M[c], K[c], W[c], aux[(size_t)10 * n + c], aux[(size_t)11 * n + c], aux[(size_t)6 * n + c],
+                      aux[(size_t)7 * n + c], aux[(size_t)8 * n + c], aux[(size_t)9 * n + c], T(g.wdist[c]), g.inv_area[c],
+                      p, sst_params(p), lk1[c], lw1[c], T(3) * ltau[c], xb, ob, pb);
+    lx[c] += xb[0];
+    lx[(size_t)3 * n + c] += xb[1];
+    lx[(size_t)4 * n + c] += xb[2];
+    lnet[c] = ob[0];
+    lnet[(size_t)n + c] = ob[1];
 #pragma unroll
-    for (int i = 0; i < 11; ++i) l[i] = a_k * k1.d[i] + a_w * w1.d[i] + a_t * nut.d[i];
-    lx[c] += l[0];
-    lx[(size_t)3 * n + c] += l[1];
-    lx[(size_t)4 * n + c] += l[2];
-    lnet[c] = l[3];
-    lnet[(size_t)n + c] = l[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) lown[(size_t)i * n + c] = l[5 + i];
-    sa.pbar[(size_t)4 * n + c] += (double)l[9];
-    sa.pbar[(size_t)3 * n + c] += (double)l[10];
+    for (int i = 0; i < 4; ++i) lown[(size_t)i * n + c] = ob[2 + i];
+    sa.pbar[(size_t)4 * n + c] += (double)pb.a1;
+    sa.pbar[(size_t)3 * n + c] += (double)pb.bstar;
 }
 
 // SB2: reverse of the face fluxes, gathered per cell j from its own edges and, through the same
@@ -680,16 +644,12 @@ __global__ void __launch_bounds__(256) k_adj_sst_faces(Geo<T> g, SstAdj sa, cons
     const int j = cell_index();
     if (j >= g.n) return;
     const int n = g.n;
-    using D = Dual<T, 12>;   // 11 cell values + theta
-    T xj[11];
+    T xj[11], acc[11];
     sst_cell_x(n, j, p.rho0, M, K, W, aux, xj);
-    D xd[11];
 #pragma unroll
-    for (int i = 0; i < 11; ++i) xd[i] = D::var(xj[i], i);
+    for (int i = 0; i < 11; ++i) acc[i] = T(0);
     const T lk = lnet[j], lw = lnet[(size_t)n + j];
-    T acc[12];
-#pragma unroll
-    for (int i = 0; i < 12; ++i) acc[i] = T(0);
+    T th = 0;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const size_t si = (size_t)s * n + j;
@@ -697,40 +657,25 @@ __global__ void __launch_bounds__(256) k_adj_sst_faces(Geo<T> g, SstAdj sa, cons
         if (nb == -1) continue;
         const T nlx = g.nlx[si], nly = g.nly[si], rx = g.rfx[si], ry = g.rfy[si], qx = g.qx[si], qy = g.qy[si];
         if (nb >= 0) {
-            T xn[11];
+            T xn[11], unused[11];
             sst_cell_x(n, nb, p.rho0, M, K, W, aux, xn);
-            D xnd[11];
 #pragma unroll
-            for (int i = 0; i < 11; ++i) xnd[i] = D(xn[i]);
-            D tk, tw;
-            sst_face<D, T>(xd, xnd, nlx, nly, rx, ry, qx, qy, tk, tw);      // in j's net inflow
-            const T lkn = lnet[nb], lwn = lnet[(size_t)n + nb];
-            D uk, uw;
-            sst_face<D, T>(xnd, xd, -nlx, -nly, qx, qy, rx, ry, uk, uw);    // in the neighbour's
-#pragma unroll
-            for (int i = 0; i < 11; ++i) acc[i] += lk * tk.d[i] + lw * tw.d[i] + lkn * uk.d[i] + lwn * uw.d[i];
+            for (int i = 0; i < 11; ++i) unused[i] = T(0);
+            sst_face_rev<T>(xj, xn, nlx, nly, rx, ry, qx, qy, lk, lw, acc, unused);               // j's net inflow
+            sst_face_rev<T>(xn, xj, -nlx, -nly, qx, qy, rx, ry, lnet[nb], lnet[(size_t)n + nb], unused, acc);  // N's
         } else {
             const int b = -2 - nb;
             const int kind = g.b_kind[b];
-            const bool zg = sa.bzg[b] != 0;
-            const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]);
-            D dubx(ubx), duby(uby);
-            if (!zg && (kind == kInlet || kind == kFarfield)) {
-                dubx.d[11] = -uby;
-                duby.d[11] = ubx;
-            }
-            D tk, tw;
-            sst_bface<D, T>(xd, zg, dubx, duby, T(g.b_k[b]), T(g.b_w[b]), nlx, nly, rx, ry, T(g.b_l[b] / g.b_dperp[b]), tk, tw);
-#pragma unroll
-            for (int i = 0; i < 12; ++i) acc[i] += lk * tk.d[i] + lw * tw.d[i];
+            th += sst_bface_rev<T>(xj, sa.bzg[b] != 0, kind == kInlet || kind == kFarfield, T(g.b_ux[b]), T(g.b_uy[b]),
+                                   T(g.b_k[b]), T(g.b_w[b]), nlx, nly, rx, ry, T(g.b_l[b] / g.b_dperp[b]), lk, lw, acc);
         }
     }
 #pragma unroll
     for (int i = 0; i < 11; ++i) lx[(size_t)i * n + j] += acc[i];
-    sa.pbar[j] += (double)acc[11];
+    sa.pbar[j] += (double)th;
 }
 
-// SA1: reverse of the cell-local closure (dual numbers over its 11 inputs and 4 constants).
+// SA1: reverse of the cell-local closure.
 template <typename T>
 __global__ void __launch_bounds__(256) k_adj_sst_local(Geo<T> g, SstAdj sa, const T *__restrict__ M,
                                                        const T *__restrict__ K, const T *__restrict__ W,
@@ -741,18 +686,13 @@ __global__ void __launch_bounds__(256) k_adj_sst_local(Geo<T> g, SstAdj sa, cons
     const int n = g.n;
     T gu[2], gv[2], gk[2], gw[2];
     sst_gradients(g, sa.bzg, M, K, W, c, gu, gv, gk, gw);
-    using D = Dual<T, 15>;
-    const D rho = D::var(p.rho0 + M[c], 0), k = D::var(K[c], 1), w = D::var(W[c], 2);
-    const SstParams<D> q{D::var(p.a1, 11), D::var(p.bstar, 12), D::var(p.sk1, 13), D::var(p.sw1, 14)};
-    const SstLocal<D> o = sst_local<D, T>(rho, k, w, D::var(gu[0], 3), D::var(gu[1], 4), D::var(gv[0], 5), D::var(gv[1], 6),
-                                          D::var(gk[0], 7), D::var(gk[1], 8), D::var(gw[0], 9), D::var(gw[1], 10),
-                                          T(g.wdist[c]), p, q);
-    const T lGk = lx[(size_t)9 * n + c], lGw = lx[(size_t)10 * n + c];
-    const T lsk = lown[c], lsw = lown[(size_t)n + c], lb = lown[(size_t)2 * n + c], lS = lown[(size_t)3 * n + c];
-    T l[15];
+    T l[11];
 #pragma unroll
-    for (int i = 0; i < 15; ++i)
-        l[i] = lGk * o.Gk.d[i] + lGw * o.Gw.d[i] + lsk * o.sk.d[i] + lsw * o.sw.d[i] + lb * o.beta.d[i] + lS * o.Sr.d[i];
+    for (int i = 0; i < 11; ++i) l[i] = T(0);
+    SstParBar<T> pb;
+    sst_local_rev<T>(p.rho0 + M[c], K[c], W[c], gu[0], gu[1], gv[0], gv[1], gk[0], gk[1], gw[0], gw[1], T(g.wdist[c]), p,
+                     sst_params(p), lx[(size_t)9 * n + c], lx[(size_t)10 * n + c], lown[c], lown[(size_t)n + c],
+                     lown[(size_t)2 * n + c], lown[(size_t)3 * n + c], l, pb);
     lx[c] += l[0];
     lx[(size_t)3 * n + c] += l[1];
     lx[(size_t)4 * n + c] += l[2];
@@ -765,10 +705,10 @@ __global__ void __launch_bounds__(256) k_adj_sst_local(Geo<T> g, SstAdj sa, cons
     lgrad[(size_t)5 * n + c] = l[8] + lx[(size_t)6 * n + c];
     lgrad[(size_t)6 * n + c] = l[9] + lx[(size_t)7 * n + c];
     lgrad[(size_t)7 * n + c] = l[10] + lx[(size_t)8 * n + c];
-    sa.pbar[(size_t)4 * n + c] += (double)l[11];
-    sa.pbar[(size_t)3 * n + c] += (double)l[12];
-    sa.pbar[(size_t)1 * n + c] += (double)l[13];
-    sa.pbar[(size_t)2 * n + c] += (double)l[14];
+    sa.pbar[(size_t)4 * n + c] += (double)pb.a1;
+    sa.pbar[(size_t)3 * n + c] += (double)pb.bstar;
+    sa.pbar[(size_t)1 * n + c] += (double)pb.sk1;
+    sa.pbar[(size_t)2 * n + c] += (double)pb.sw1;
 }
 
 // SA2: transposed LSQ gradients of u, v, k, omega, then the macro transpose onto f^n:

@@ -164,7 +164,7 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
         st->K[1] = cv.take<T>(n);
         st->W[0] = cv.take<T>(n);
         st->W[1] = cv.take<T>(n);
-        st->aux = cv.take<T>(10 * n);
+        st->aux = cv.take<T>(12 * n);
     }
     st->lnb = cv.take<int16_t>(S);
     st->rev = cv.take<int8_t>(S);
@@ -652,7 +652,7 @@ struct AdjLayout {
     T *ckpt, *seg, *stg, *lF, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *F1, *ltau, *lx, *lnet, *lown, *lgrad;
     double *pbar;
     size_t state_len;
-    size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [10][n]
+    size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [12][n]
 };
 
 template <typename T>
@@ -662,7 +662,7 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     L.state_len = sl;
     L.ckpt = cv.take<T>(nck * sl);
     L.seg = cv.take<T>((size_t)ckpt * sl);
-    L.stage_len = 38 * (size_t)n;
+    L.stage_len = 40 * (size_t)n;
     L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
     L.lF = cv.take<T>(9 * (size_t)n);
     L.lK = cv.take<T>(n);

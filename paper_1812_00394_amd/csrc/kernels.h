@@ -652,7 +652,8 @@ __global__ void __launch_bounds__(256) k_advect(Geo<T> g, const T *__restrict__ 
 // ----------------------------------------------------------------------------------------------
 // k-omega SST (Section 2 model; finite-volume form Eq. (SSTequint)).
 // aux planes: 0,1 grad k; 2,3 grad omega; 4 Gamma_k; 5 Gamma_omega; 6 dt P / rho;
-//             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S.
+//             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S;
+//             10, 11 net inflows of k, omega (written by the flux / update stage).
 // Boundary data per edge (set at init): b_ux, b_uy velocity (0 on resting walls), b_k (0 on walls),
 // b_w (60 nu / (beta1 d_perp^2) on walls), and b_zg = 1 where k, omega, u are zero-gradient
 // (outlets, far-field outflow edges).
@@ -816,7 +817,8 @@ __device__ __forceinline__ SstParams<T> sst_params(const StepPar<T> &p) {
 // ----------------------------------------------------------------------------------------------
 // k-omega SST kernels (Section 2 model; finite-volume form Eq. (SSTequint)).
 // aux planes: 0,1 grad k; 2,3 grad omega; 4 Gamma_k; 5 Gamma_omega; 6 dt P / rho;
-//             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S.
+//             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S;
+//             10, 11 net inflows of k, omega (written by the flux / update stage).
 // Boundary data per edge (set at init): b_ux, b_uy velocity (0 on resting walls), b_k (0 on walls),
 // b_w (60 nu / (beta1 d_perp^2) on walls), and b_zg = 1 where k, omega, u are zero-gradient
 // (outlets, far-field outflow edges).
@@ -899,7 +901,7 @@ __device__ __forceinline__ void sst_cell_x(int n, int c, T rho0, const T *__rest
 template <typename T>
 __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
                                                const T *__restrict__ K, const T *__restrict__ W,
-                                               const T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
+                                               T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
                                                T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
     const int c = cell_index();
     if (c >= g.n) return;
@@ -925,6 +927,8 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
         net_k += tk;
         net_w += tw;
     }
+    aux[(size_t)10 * n + c] = net_k;
+    aux[(size_t)11 * n + c] = net_w;
     T k1, w1, nt;
     sst_update<T, T>(xc[0], xc[3], xc[4], net_k, net_w, aux[(size_t)6 * n + c], aux[(size_t)7 * n + c],
                      aux[(size_t)8 * n + c], aux[(size_t)9 * n + c], T(g.wdist[c]), g.inv_area[c], p, sst_params(p),
@@ -942,7 +946,7 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
 //   phase 1: LSQ gradients of u, v, k, omega and the cell-local closure (sst_local) of tile cell t
 //            and ring-1 cell t; grad k, grad omega, Gamma_k, Gamma_omega into LDS;
 //   phase 2: face fluxes of tile cell t with its neighbours' data from LDS, point-implicit update,
-//            nu_t and tau.  AUX: also store the aux planes of k_sst_a (the adjoint reads them).
+//            nu_t and tau.  AUX: also store the aux planes (the adjoint reads them).
 // LDS: Vv [5][Wv] (rho, u, v, k, omega), Vx [6][Wg] (dk/dx, dk/dy, dw/dx, dw/dy, Gamma_k, Gamma_w).
 template <typename T, int S>
 __device__ __forceinline__ void sst_grad_ring(const Geo<T> &g, const int32_t *__restrict__ bzg, const int nb[S],
@@ -1117,6 +1121,10 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         }
         net_k += tk;
         net_w += tw;
+    }
+    if constexpr (AUX) {
+        aux[(size_t)10 * n + c] = net_k;
+        aux[(size_t)11 * n + c] = net_w;
     }
     T k1, w1, nt;
     sst_update<T, T>(rho, kc, wc, net_k, net_w, oc.sk, oc.sw, oc.beta, oc.Sr, dc, ia, p, q, k1, w1, nt);
