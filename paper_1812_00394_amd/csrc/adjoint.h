@@ -764,6 +764,210 @@ __global__ void __launch_bounds__(256) k_adj_sst_grad(Geo<T> g, SstAdj sa, const
         lfn[(size_t)a * n + s0] += lrho + (T(ex(a)) - ux) * ir * lu + (T(ey(a)) - uy) * ir * lv;
 }
 
+// ---- ring-tiled SST reverse: update, faces, closure and LSQ gradients in one launch ----
+// The layout of the ring-tiled forward kernels.  x = the 11 cell values of the face fluxes
+// (rho, u, v, k, omega, grad k, grad omega, Gamma_k, Gamma_omega).
+//   phase 0: tile cell t and ext cell t: x and the reverse of the cell-local update (the adjoints
+//            of the net inflows into LDS, those of rho, k, omega and of the closure outputs kept);
+//   phase 1: tile cell t and ring-1 cell t: reverse of its face fluxes (both edge perspectives,
+//            neighbours from LDS) and of its closure (gradients recomputed from LDS): the adjoints
+//            of its LSQ gradients into LDS;
+//   phase 2: tile cell t: transposed LSQ gradients from its neighbours' gradient adjoints in LDS,
+//            the macro transpose onto f^n; the adjoints of k^n, omega^n go to lk_out, lw_out
+//            (the adjoints of k, omega of the step's output are read from lk1, lw1).
+// LDS: X [11][Wv], Ln [2][Wv] (net-inflow adjoints), Lg [8][Wg] (gradient adjoints).
+template <typename T, int S>
+__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
+    k_adj_sst_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
+                   int Wg, SstAdj sa, const T *__restrict__ M, const T *__restrict__ K, const T *__restrict__ W,
+                   const T *__restrict__ aux, const T *__restrict__ lk1, const T *__restrict__ lw1,
+                   const T *__restrict__ ltau, T *__restrict__ lfn, T *__restrict__ lk_out, T *__restrict__ lw_out,
+                   StepPar<T> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *X = reinterpret_cast<T *>(smem);
+    T *Ln = X + 11 * Wv;
+    T *Lg = Ln + 2 * Wv;
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int start = tile * kTileCells;
+    const int ncell = min(kTileCells, g.n - start);
+    const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
+    const int t = threadIdx.x;
+    const int n = g.n;
+    const bool own = t < ncell, ext = t < nx, ring1 = t < n1;
+    const int c = start + t;
+    const SstParams<T> q = sst_params(p);
+
+    // phase 0: cell values and the update's reverse of cell `cell`, stored at LDS column `col`
+    auto load_update = [&](int cell, int col, T x[11], T lxu[3], T lown[4], SstParBar<T> &pb) {
+        x[0] = p.rho0 + M[cell];
+        x[1] = M[(size_t)n + cell];
+        x[2] = M[(size_t)2 * n + cell];
+        x[3] = K[cell];
+        x[4] = W[cell];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) x[5 + i] = aux[(size_t)i * n + cell];
+#pragma unroll
+        for (int i = 0; i < 11; ++i) X[i * Wv + col] = x[i];
+        T ob[6];
+        lxu[0] = lxu[1] = lxu[2] = T(0);
+        sst_update_rev<T>(x[0], x[3], x[4], aux[(size_t)10 * n + cell], aux[(size_t)11 * n + cell],
+                          aux[(size_t)6 * n + cell], aux[(size_t)7 * n + cell], aux[(size_t)8 * n + cell],
+                          aux[(size_t)9 * n + cell], T(g.wdist[cell]), g.inv_area[cell], p, q, lk1[cell], lw1[cell],
+                          T(3) * ltau[cell], lxu, ob, pb);
+        Ln[col] = ob[0];
+        Ln[Wv + col] = ob[1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lown[i] = ob[2 + i];
+    };
+    T xc[11], lxc[3], lownc[4];
+    SstParBar<T> pbc;
+    int nb[S], col[S];
+    T nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], cxs[S], cys[S];
+    if (own) {
+        load_update(c, t, xc, lxc, lownc, pbc);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const size_t si = (size_t)s * n + c;
+            nb[s] = g.nbr[si];
+            col[s] = lnb[si];
+            nlx[s] = g.nlx[si];
+            nly[s] = g.nly[si];
+            rx[s] = g.rfx[si];
+            ry[s] = g.rfy[si];
+            qx[s] = g.qx[si];
+            qy[s] = g.qy[si];
+            cxs[s] = g.cx[si];
+            cys[s] = g.cy[si];
+        }
+    }
+    T xh[11], lxh[3], lownh[4];
+    SstParBar<T> pbh;    // ring-1 cells: their constants' adjoints are their own tile's
+    int hc = 0;
+    if (ext) {
+        hc = rt.cell[x0 + t];
+        load_update(hc, kTileCells + t, xh, lxh, lownh, pbh);
+    }
+    __syncthreads();
+
+    // phase 1: faces and closure of a cell with edge data e*, LDS column cl; returns the 11 x
+    // adjoints (lx) and the theta part, adds the constants' adjoints to pb
+    auto faces_closure = [&](int cell, int cl, const T x[11], const T lxu[3], const T lown[4], const int *enb,
+                             const int *ecol, const T *enx, const T *eny, const T *erx, const T *ery, const T *eqx,
+                             const T *eqy, const T *ecx, const T *ecy, T lg[8], T lx[11], SstParBar<T> &pb) {
+        T th = 0;
+#pragma unroll
+        for (int i = 0; i < 11; ++i) lx[i] = T(0);
+        const T lk = Ln[cl], lw = Ln[Wv + cl];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (enb[s] == -1) continue;
+            if (enb[s] >= 0) {
+                T xn[11], unused[11];
+#pragma unroll
+                for (int i = 0; i < 11; ++i) {
+                    xn[i] = X[i * Wv + ecol[s]];
+                    unused[i] = T(0);
+                }
+                sst_face_rev<T>(x, xn, enx[s], eny[s], erx[s], ery[s], eqx[s], eqy[s], lk, lw, lx, unused);
+                sst_face_rev<T>(xn, x, -enx[s], -eny[s], eqx[s], eqy[s], erx[s], ery[s], Ln[ecol[s]],
+                                Ln[Wv + ecol[s]], unused, lx);
+            } else {
+                const int b = -2 - enb[s];
+                const int kind = g.b_kind[b];
+                th += sst_bface_rev<T>(x, sa.bzg[b] != 0, kind == kInlet || kind == kFarfield, T(g.b_ux[b]),
+                                       T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), enx[s], eny[s], erx[s], ery[s],
+                                       T(g.b_l[b] / g.b_dperp[b]), lk, lw, lx);
+            }
+        }
+        lx[0] += lxu[0];
+        lx[3] += lxu[1];
+        lx[4] += lxu[2];
+        T gu[2], gv[2], gk[2], gw[2];
+        sst_grad_ring<T, S>(g, sa.bzg, enb, ecol, ecx, ecy, X, Wv, x[1], x[2], x[3], x[4], gu, gv, gk, gw);
+        T l[11];
+#pragma unroll
+        for (int i = 0; i < 11; ++i) l[i] = T(0);
+        sst_local_rev<T>(x[0], x[3], x[4], gu[0], gu[1], gv[0], gv[1], gk[0], gk[1], gw[0], gw[1], T(g.wdist[cell]), p, q,
+                         lx[9], lx[10], lown[0], lown[1], lown[2], lown[3], l, pb);
+        lx[0] += l[0];
+        lx[3] += l[1];
+        lx[4] += l[2];
+        lg[0] = l[3];
+        lg[1] = l[4];
+        lg[2] = l[5];
+        lg[3] = l[6];
+        lg[4] = l[7] + lx[5];
+        lg[5] = l[8] + lx[6];
+        lg[6] = l[9] + lx[7];
+        lg[7] = l[10] + lx[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Lg[i * Wg + cl] = lg[i];
+        return th;
+    };
+    if (ring1) {
+        int hnb[S], hcol[S];
+        T hnx[S], hny[S], hrx[S], hry[S], hqx[S], hqy[S], hcx[S], hcy[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const size_t si = (size_t)s * n + hc;
+            hnb[s] = g.nbr[si];
+            hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
+            hnx[s] = g.nlx[si];
+            hny[s] = g.nly[si];
+            hrx[s] = g.rfx[si];
+            hry[s] = g.rfy[si];
+            hqx[s] = g.qx[si];
+            hqy[s] = g.qy[si];
+            hcx[s] = g.cx[si];
+            hcy[s] = g.cy[si];
+        }
+        T lg[8], lx[11];
+        faces_closure(hc, kTileCells + t, xh, lxh, lownh, hnb, hcol, hnx, hny, hrx, hry, hqx, hqy, hcx, hcy, lg, lx, pbh);
+    }
+    T lgc[8], lx[11], th = 0;
+    if (own)
+        th = faces_closure(c, t, xc, lxc, lownc, nb, col, nlx, nly, rx, ry, qx, qy, cxs, cys, lgc, lx, pbc);
+    __syncthreads();
+    if (!own) return;
+
+    // phase 2: transposed LSQ gradients (same order as k_adj_sst_grad) and the macro transpose
+    T acc[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] == -1) continue;
+        if (nb[s] >= 0) {
+            const size_t sj = (size_t)rev[(size_t)s * n + c] * n + nb[s];
+            const T cjx = g.cx[sj], cjy = g.cy[sj];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] += cjx * Lg[(2 * v) * Wg + col[s]] + cjy * Lg[(2 * v + 1) * Wg + col[s]];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] -= cxs[s] * lgc[2 * v] + cys[s] * lgc[2 * v + 1];
+        } else {
+            const int b = -2 - nb[s];
+            if (sa.bzg[b]) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] -= cxs[s] * lgc[2 * v] + cys[s] * lgc[2 * v + 1];
+            const int kind = g.b_kind[b];
+            if (kind == kInlet || kind == kFarfield) {
+                const T lu = cxs[s] * lgc[0] + cys[s] * lgc[1], lv = cxs[s] * lgc[2] + cys[s] * lgc[3];
+                th += lu * (-T(g.b_uy[b])) + lv * T(g.b_ux[b]);
+            }
+        }
+    }
+    sa.pbar[c] += (double)th;
+    sa.pbar[(size_t)1 * n + c] += (double)pbc.sk1;
+    sa.pbar[(size_t)2 * n + c] += (double)pbc.sw1;
+    sa.pbar[(size_t)3 * n + c] += (double)pbc.bstar;
+    sa.pbar[(size_t)4 * n + c] += (double)pbc.a1;
+    const T lrho = lx[0], lu = lx[1] + acc[0], lv = lx[2] + acc[1];
+    lk_out[c] = lx[3] + acc[2];
+    lw_out[c] = lx[4] + acc[3];
+    const T ir = T(1) / xc[0], ux = xc[1], uy = xc[2];
+#pragma unroll
+    for (int a = 0; a < 9; ++a)
+        lfn[(size_t)a * n + c] += lrho + (T(ex(a)) - ux) * ir * lu + (T(ey(a)) - uy) * ir * lv;
+}
+
 // Forces and the reversed-flow length at the final state, reversed onto f (through rho, u of the
 // wall cells): seed = (dJ/dF_x, dJ/dF_y, dJ/dJ_R).
 template <typename T>

@@ -792,7 +792,22 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     k_adj_stage2<T><<<nbk, kBlock, 0, s>>>(n, b, p);
     adv_transpose<T>(st, L.F1, L.lam, L.lf1, L.pbar, true);
     k_adj_stage1<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    if (st->sst) {
+    if (st->sst && st->ring) {
+        // one ring-tiled launch; the new k / omega adjoints go through L.lnet (other workgroups
+        // still read the old ones as halo data)
+        SstAdj sa{st->bzg, L.pbar};
+        const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+        const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+        const size_t lds = ((size_t)13 * wv + (size_t)8 * wg) * sizeof(T);
+        if (st->ring_s == 3)
+            k_adj_sst_ring<T, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
+                                                          L.ltau, L.lF, L.lnet, L.lnet + n, p);
+        else
+            k_adj_sst_ring<T, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
+                                                          L.ltau, L.lF, L.lnet, L.lnet + n, p);
+        check(hipMemcpyAsync(L.lK, L.lnet, n * sizeof(T), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync D2D");
+        check(hipMemcpyAsync(L.lW, L.lnet + n, n * sizeof(T), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync D2D");
+    } else if (st->sst) {
         SstAdj sa{st->bzg, L.pbar};
         k_fill<T><<<blocks_for(11 * (size_t)n), kBlock, 0, s>>>(11 * n, L.lx, T(0));
         k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW, L.ltau, L.lx, L.lnet, L.lown, p);
