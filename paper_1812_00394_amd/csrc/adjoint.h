@@ -55,7 +55,7 @@ __device__ __forceinline__ T ghost_vjp(const Geo<T> &g, int b, T nlx, T nly, con
 // L, gbar: [9][n] (direction 0 of L unused); Gbar: [16][n].  Every edge except the ghost-state
 // parts, which k_adv_T1b adds.
 template <typename T>
-__global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ L, T *__restrict__ gbar,
+__global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ L, T lscale, T *__restrict__ gbar,
                                                 T *__restrict__ Gbar) {
     const int j = cell_index();
     if (j >= g.n) return;
@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
     const T ia = g.inv_area[j];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        mu[a] = -L[(size_t)a * n + j] * ia;
+        mu[a] = -(lscale * L[(size_t)a * n + j]) * ia;
         gd[a] = Gx[a] = Gy[a] = T(0);
     }
     // interior edges: interior edges and open-boundary outgoing directions
@@ -80,7 +80,7 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
             for (int a = 1; a < 9; ++a) {
                 const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
                 if (en > T(0)) {
-                    const T w = en * (mu[a] + L[(size_t)a * n + nb] * ian);
+                    const T w = en * (mu[a] + (lscale * L[(size_t)a * n + nb]) * ian);
                     gd[a] += w;
                     Gx[a] += w * rx;
                     Gy[a] += w * ry;
@@ -125,11 +125,12 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
 // walls and incoming directions, and the ghosts' use in the cell's own LSQ gradient, through the
 // ghost state's Jacobian.  One thread per cell: boundary edges are ordered by owner cell, and the
 // thread of a cell's first boundary edge takes all of them in slot order.  Kept out of k_adv_T1 so
-// that its dual-number registers do not limit the occupancy of the all-cell kernel.
+// that its dual-number registers do not limit the occupancy of the all-cell kernel.  With tau1
+// given, the field is the stage solve of f with a = a_dt / tau1 (f^(1) from f^n).
 template <typename T>
-__global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__ f, const T *__restrict__ L,
-                                                 T *__restrict__ gbar, const T *__restrict__ Gbar,
-                                                 double *__restrict__ dth, T rho0) {
+__global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__ f, const T *__restrict__ tau1, T a_dt,
+                                                 const T *__restrict__ L, T lscale, T *__restrict__ gbar,
+                                                 const T *__restrict__ Gbar, double *__restrict__ dth, T rho0) {
     const int b0 = blockIdx.x * blockDim.x + threadIdx.x;
     if (b0 >= g.nb) return;
     const int j = g.b_cell[b0];
@@ -139,9 +140,15 @@ __global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__
     const T ia = g.inv_area[j];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        mu[a] = -L[(size_t)a * n + j] * ia;
+        mu[a] = -(lscale * L[(size_t)a * n + j]) * ia;
         gj[a] = f[(size_t)a * n + j];
         gd[a] = T(0);
+    }
+    if (tau1) {
+        T f1[9], fe[9];
+        stage_collide(gj, a_dt / tau1[j], rho0, f1, fe);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gj[a] = f1[a];
     }
     Gx[0] = Gy[0] = T(0);
 #pragma unroll
@@ -210,7 +217,7 @@ __global__ void __launch_bounds__(256) k_adv_T2(Geo<T> g, const int8_t *__restri
 template <typename T, int S, bool ACC>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
-                 int Wg, const T *__restrict__ L, T *__restrict__ out, T *__restrict__ Gbar) {
+                 int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, T *__restrict__ Gbar) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *V = reinterpret_cast<T *>(smem);   // [8][Wv]: mu of directions 1..8
     T *Gl = V + 8 * Wv;                   // [16][Wg]
@@ -231,7 +238,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         const T ia = g.inv_area[c];
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            mu[a] = -L[(size_t)a * n + c] * ia;
+            mu[a] = -(lscale * L[(size_t)a * n + c]) * ia;
             V[(a - 1) * Wv + t] = mu[a];
         }
 #pragma unroll
@@ -261,7 +268,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         const T ia = g.inv_area[hc];
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            hmu[a] = -L[(size_t)a * n + hc] * ia;
+            hmu[a] = -(lscale * L[(size_t)a * n + hc]) * ia;
             V[(a - 1) * Wv + kTileCells + t] = hmu[a];
         }
         if (ring1) {
@@ -437,7 +444,7 @@ __device__ __forceinline__ T collide_vjp(const T f[9], T m0, T mx, T my, T a, T 
 // Buffers of the step reverse.
 template <typename T>
 struct AdjBufs {
-    const T *fn, *f1, *f2, *f3, *Q, *tau;   // forward data of the step (f1 recomputed)
+    const T *fn, *f2, *f3, *Q, *tau;        // forward data of the step (f^(1) is formed from f^n)
     T *lfn;    // adjoint of f^n (accumulated)
     T *lf1, *lf2, *lf3;                     // adjoints of the stage fields
     T *lam;    // input of the transposed convection (adjoint of a convection term)
@@ -459,9 +466,13 @@ __global__ void __launch_bounds__(256) k_adj_stage3(int n, AdjBufs<T> b, StepPar
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
-        fn[a] = b.fn[i]; f1[a] = b.f1[i]; f2[a] = b.f2[i]; f3[a] = b.f3[i]; Q[a] = b.Q[i];
+        fn[a] = b.fn[i]; f2[a] = b.f2[i]; f3[a] = b.f3[i]; Q[a] = b.Q[i];
         lq[a] = b.lfn[i];                 // lam_{n+1} = adjoint of Q
         l3[a] = b.lf3[i] + lq[a];         // f3 enters Q with weight 1
+    }
+    {
+        T fe[9];
+        stage_collide(fn, dt / (T(4) * tc), p.rho0, f1, fe);   // f^(1)
     }
     // Q = f3 - dt/6 (Ga1 + Ga2)
     T lg12[9];
@@ -576,15 +587,15 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_adj_stage1(int n, AdjBufs<T> b, StepPar<T> p) {
     const int c = cell_index();
     if (c >= n) return;
-    T f1[9], fn[9], lf1[9], lr[9];
+    T f1[9], fe[9], fn[9], lf1[9], lr[9];
     const T tc = b.tau[c];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
-        f1[a] = b.f1[(size_t)a * n + c];
         fn[a] = b.fn[(size_t)a * n + c];
         lf1[a] = b.lf1[(size_t)a * n + c];
         lr[a] = T(0);
     }
+    stage_collide(fn, p.dt / (T(4) * tc), p.rho0, f1, fe);   // f^(1)
     T m0, mx, my;
     raw_moments(fn, m0, mx, my);
     const T a1 = p.dt / (T(4) * tc);

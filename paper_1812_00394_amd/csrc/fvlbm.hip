@@ -74,6 +74,8 @@ struct fvlbm_state {
     int ring_s = 4, ring_wv = 0, ring_wg = 0;
     size_t sst_lds_bytes = 0;
     bool want_aux = false;       // the SST launch also stores the aux planes (adjoint recompute)
+    void *F_out = nullptr;       // where a step writes f^{n+1} (nullptr: over f^n)
+    bool last_seg_valid = false; // the segment buffers hold the recorded run's last segment
     int32_t *hptr = nullptr, *hcell = nullptr;
     int32_t *xptr = nullptr, *xn1 = nullptr, *xcell = nullptr;
     int16_t *xlnb = nullptr;
@@ -164,7 +166,7 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
         st->K[1] = cv.take<T>(n);
         st->W[0] = cv.take<T>(n);
         st->W[1] = cv.take<T>(n);
-        st->aux = cv.take<T>(12 * n);
+        st->aux = cv.take<T>(15 * n);
     }
     st->lnb = cv.take<int16_t>(S);
     st->rev = cv.take<int8_t>(S);
@@ -393,7 +395,7 @@ void launch_step(fvlbm_state *st) {
     }
     const StageBufs<T> b1{X, F, tau, A, Y, nullptr, nullptr};
     const StageBufs<T> b2{Y, F, tau, A, X, nullptr, nullptr};
-    const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, F, Mnew};
+    const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, st->F_out ? (T *)st->F_out : F, Mnew};
     if (st->ring) {
         // stage 1 takes f^(1) from f^n on the fly: no separate collision launch
         const int nt = st->mesh->n_tiles;
@@ -582,10 +584,12 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
     check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
-// Transposed convection at field f applied to lam, accumulated into out (acc) or stored there;
-// the theta part per cell is added to dth.  Uses st->G for the gradient adjoints.
+// Transposed convection at field f (with tau1: at the stage solve of f with a = dt / (4 tau1))
+// applied to lscale lam, accumulated into out (acc) or stored there; the theta part per cell is
+// added to dth.  Uses st->G for the gradient adjoints.
 template <typename T>
-void adv_transpose(fvlbm_state *st, const T *f, const T *lam, T *out, double *dth, bool acc) {
+void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T lscale, T *out, double *dth, bool acc) {
+    const T a_dt = T(st->par.dt / 4.0);
     const Geo<T> &g = geo_of<T>(st);
     const int nbk = blocks_for(g.n);
     hipStream_t s = st->stream;
@@ -596,23 +600,23 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *lam, T *out, double *dt
         T *Gb = (T *)st->G;
         if (st->ring_s == 3) {
             if (acc)
-                k_adv_T_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+                k_adv_T_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
             else
-                k_adv_T_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+                k_adv_T_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
         } else {
             if (acc)
-                k_adv_T_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+                k_adv_T_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
             else
-                k_adv_T_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, out, Gb);
+                k_adv_T_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
         }
         if (g.nb > 0)
-            k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, lam, out, (const T *)st->G, dth, T(st->par.rho0));
+            k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, T(st->par.rho0));
         return;
     }
     if (!acc) k_fill<T><<<blocks_for(9 * (size_t)g.n), kBlock, 0, s>>>(9 * g.n, out, T(0));
-    k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, out, (T *)st->G);
+    k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, (T *)st->G);
     if (g.nb > 0)
-        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, lam, out, (const T *)st->G, dth, T(st->par.rho0));
+        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, T(st->par.rho0));
     k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, out);
 }
 
@@ -630,7 +634,7 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
     k_fill<T><<<blocks_for(9 * (size_t)n), kBlock, 0, s>>>(9 * n, (T *)st->A, T(0));
     double *dth = st->scratch + 8 * (size_t)n;   // last plane of the staging area (free after import)
     k_fill<double><<<nbk, kBlock, 0, s>>>(n, dth, 0.0);
-    adv_transpose<T>(st, (const T *)st->X, (const T *)st->Y, (T *)st->A, dth, true);
+    adv_transpose<T>(st, (const T *)st->X, (const T *)nullptr, (const T *)st->Y, T(1), (T *)st->A, dth, true);
     k_sum<double><<<kRedBlocks, kBlock, 0, s>>>(n, dth, st->partial);
     k_export_f<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->A, st->scratch, 0.0);
     k_finish<1><<<1, kBlock, 0, s>>>(st->partial, kRedBlocks, st->result);
@@ -643,16 +647,17 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
 // ---------------------------------------------------------------------------------------------
 // Record and adjoint.  Layout of the caller's adjoint workspace (all T unless noted):
 //   checkpoints: (ceil(N/C) + 1) states of f [9n], k [n], omega [n] (the last one: the final state)
-//   segment:     C states of the same form
-//   adjoint:     lF [9n], lK [n], lW [n], lf1, lf2, lf3, lam, lg1, F1 [9n each], ltau [n],
+//   segment:     C + 1 states of the same form (the inputs of a segment's steps and its output)
+//   stage data:  C slots of f^(2), f^(3), Q [9n each], tau [n], aux [15n]
+//   adjoint:     lF [9n], lK [n], lW [n], lf1, lf2, lf3, lam, lg1 [9n each], ltau [n],
 //                lx [11n], lnet [2n], lown [4n], lgrad [8n], pbar [5n] (FP64)
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct AdjLayout {
-    T *ckpt, *seg, *stg, *lF, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *F1, *ltau, *lx, *lnet, *lown, *lgrad;
+    T *ckpt, *seg, *stg, *lF, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
     double *pbar;
     size_t state_len;
-    size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [12][n]
+    size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [15][n]
 };
 
 template <typename T>
@@ -661,8 +666,8 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     const size_t nck = (size_t)((n_steps + ckpt - 1) / ckpt) + 1;
     L.state_len = sl;
     L.ckpt = cv.take<T>(nck * sl);
-    L.seg = cv.take<T>((size_t)ckpt * sl);
-    L.stage_len = 40 * (size_t)n;
+    L.seg = cv.take<T>((size_t)(ckpt + 1) * sl);
+    L.stage_len = 43 * (size_t)n;
     L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
     L.lF = cv.take<T>(9 * (size_t)n);
     L.lK = cv.take<T>(n);
@@ -672,7 +677,6 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     L.lf3 = cv.take<T>(9 * (size_t)n);
     L.lam = cv.take<T>(9 * (size_t)n);
     L.lg1 = cv.take<T>(9 * (size_t)n);
-    L.F1 = cv.take<T>(9 * (size_t)n);
     L.ltau = cv.take<T>(n);
     L.lx = cv.take<T>(11 * (size_t)n);
     L.lnet = cv.take<T>(2 * (size_t)n);
@@ -713,26 +717,6 @@ void load_state(fvlbm_state *st, const T *slot) {
     k_macro<T><<<blocks_for(n), kBlock, 0, st->stream>>>((int)n, (const T *)st->F, (T *)st->M[st->cur_m], T(st->par.rho0));
 }
 
-template <typename T>
-void record(fvlbm_state *st) {
-    AdjLayout<T> L = adj_layout<T>(st);
-    const int C = st->rec_ckpt;
-    for (int32_t i = 0; i < st->rec_steps; ++i) {
-        if (i % C == 0) save_state<T>(st, L.ckpt + (size_t)(i / C) * L.state_len);
-        launch_step<T>(st);
-    }
-    const size_t nck = (size_t)((st->rec_steps + C - 1) / C);
-    save_state<T>(st, L.ckpt + nck * L.state_len);
-    st->steps_done += st->rec_steps;
-    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
-}
-
-template <typename T>
-__global__ void k_scale(size_t n, const T *__restrict__ x, T a, T *__restrict__ y) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = a * x[i];
-}
-
 // Stage data of one step of a segment, kept from the segment's forward pass for its reverse.
 template <typename T>
 struct StageSlot {
@@ -746,26 +730,65 @@ StageSlot<T> stage_slot(const fvlbm_state *st, const AdjLayout<T> &L, int i) {
     return StageSlot<T>{b, b + 9 * n, b + 18 * n, st->sst ? b + 27 * n : (T *)st->tau, b + 28 * n};
 }
 
-// Runs one step with its stage buffers (f^(2), f^(3), Q, and with the SST tau and aux) pointed at
-// a stage slot, so that the reverse of the step needs no recomputation.
+// Step j of a segment, in place in the segment buffers: reads the state in segment slot j, writes
+// the next one into slot j + 1, and its stage data (f^(2), f^(3), Q and with the SST tau and the
+// aux planes) into stage slot j, so that its reverse needs no recomputation.
 template <typename T>
-void step_into(fvlbm_state *st, const StageSlot<T> &ss) {
-    void *X = st->X, *Y = st->Y, *A = st->A, *tau = st->tau, *aux = st->aux;
+void step_seg(fvlbm_state *st, const AdjLayout<T> &L, int j) {
+    const size_t n = st->n_cells;
+    T *in = L.seg + (size_t)j * L.state_len, *out = in + L.state_len;
+    const StageSlot<T> ss = stage_slot<T>(st, L, j);
+    void *F = st->F, *X = st->X, *Y = st->Y, *A = st->A, *tau = st->tau, *aux = st->aux;
+    void *K0 = st->K[0], *K1 = st->K[1], *W0 = st->W[0], *W1 = st->W[1];
+    st->F = in;
+    st->F_out = out;
     st->X = ss.X;
     st->Y = ss.Y;
     st->A = ss.A;
     if (st->sst) {
+        st->K[st->cur_kw] = in + 9 * n;
+        st->K[st->cur_kw ^ 1] = out + 9 * n;
+        st->W[st->cur_kw] = in + 10 * n;
+        st->W[st->cur_kw ^ 1] = out + 10 * n;
         st->tau = ss.tau;
         st->aux = ss.aux;
         st->want_aux = true;
     }
     launch_step<T>(st);
+    st->F = F;
+    st->F_out = nullptr;
     st->X = X;
     st->Y = Y;
     st->A = A;
     st->tau = tau;
     st->aux = aux;
+    st->K[0] = K0;
+    st->K[1] = K1;
+    st->W[0] = W0;
+    st->W[1] = W1;
     st->want_aux = false;
+}
+
+// Advances the recorded run, storing a checkpoint every C steps and the final state.  The last
+// segment is run through the segment buffers, so that the reverse starts without recomputing it.
+template <typename T>
+void record(fvlbm_state *st) {
+    AdjLayout<T> L = adj_layout<T>(st);
+    const int N = st->rec_steps, C = st->rec_ckpt;
+    const int first_last = ((N - 1) / C) * C;
+    for (int32_t i = 0; i < first_last; ++i) {
+        if (i % C == 0) save_state<T>(st, L.ckpt + (size_t)(i / C) * L.state_len);
+        launch_step<T>(st);
+    }
+    save_state<T>(st, L.ckpt + (size_t)(first_last / C) * L.state_len);
+    save_state<T>(st, L.seg);
+    for (int32_t i = first_last; i < N; ++i) step_seg<T>(st, L, i - first_last);
+    load_state<T>(st, L.seg + (size_t)(N - first_last) * L.state_len);
+    const size_t nck = (size_t)((N + C - 1) / C);
+    save_state<T>(st, L.ckpt + nck * L.state_len);
+    st->last_seg_valid = true;
+    st->steps_done += N;
+    check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
 }
 
 // Reverse of one step whose input state is in `slot` and whose stage data is in `ss` (on entry
@@ -774,23 +797,19 @@ template <typename T>
 void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const StageSlot<T> &ss) {
     const Geo<T> &g = geo_of<T>(st);
     const int n = g.n, nbk = blocks_for(n);
-    const size_t n9 = 9 * (size_t)n;
     hipStream_t s = st->stream;
     StepPar<T> p = step_par<T>(st->par);
-    // the step's input: f and its macro variables, k, omega
+    // the step's input: f, its macro variables (kept by the SST), k, omega
     const T *fn = slot;
-    T *Mn = (T *)st->M[st->cur_m];
-    k_macro<T><<<nbk, kBlock, 0, s>>>(n, fn, Mn, T(st->par.rho0));
+    const T *Mn = st->sst ? ss.aux + 12 * (size_t)n : nullptr;
     const T *Kn = st->sst ? slot + 9 * (size_t)n : nullptr, *Wn = st->sst ? slot + 10 * (size_t)n : nullptr;
-    k_collide1<T><<<nbk, kBlock, 0, s>>>(n, fn, ss.tau, L.F1, p);
-    AdjBufs<T> b{fn, L.F1, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
-    // Ga3 with weight dt/3 in f^{n+1}
-    k_scale<T><<<blocks_for(n9), kBlock, 0, s>>>(n9, L.lF, p.dt / T(3), L.lam);
-    adv_transpose<T>(st, ss.X, L.lam, L.lf3, L.pbar, false);
+    AdjBufs<T> b{fn, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
+    // Ga3 enters f^{n+1} with weight dt/3: its transpose is applied to dt/3 lF
+    adv_transpose<T>(st, ss.X, nullptr, L.lF, p.dt / T(3), L.lf3, L.pbar, false);
     k_adj_stage3<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    adv_transpose<T>(st, ss.Y, L.lam, L.lf2, L.pbar, true);
+    adv_transpose<T>(st, ss.Y, nullptr, L.lam, T(1), L.lf2, L.pbar, true);
     k_adj_stage2<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    adv_transpose<T>(st, L.F1, L.lam, L.lf1, L.pbar, true);
+    adv_transpose<T>(st, fn, ss.tau, L.lam, T(1), L.lf1, L.pbar, true);   // at f^(1), formed from f^n
     k_adj_stage1<T><<<nbk, kBlock, 0, s>>>(n, b, p);
     if (st->sst && st->ring) {
         // one ring-tiled launch; the new k / omega adjoints go through L.lnet (other workgroups
@@ -819,27 +838,32 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
 }
 
 // Reverse of the whole recorded run (L.lF / lK / lW seeded with the adjoint of the final state).
-// Each segment is recomputed once from its checkpoint, keeping every step's input state and stage
-// data; then its steps are reversed from the last.
+// Each segment is recomputed once from its checkpoint in the segment buffers, keeping every step's
+// input state and stage data (the last segment comes from the record pass while those buffers
+// still hold it); then its steps are reversed from the last.
 template <typename T>
 void reverse_run(fvlbm_state *st, const AdjLayout<T> &L) {
     const int N = st->rec_steps, C = st->rec_ckpt;
     const int nseg = (N + C - 1) / C;
+    const size_t n = st->n_cells;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         const int first = sg * C, last = std::min(N, first + C);
-        load_state<T>(st, L.ckpt + (size_t)sg * L.state_len);
-        for (int i = first; i < last; ++i) {
-            save_state<T>(st, L.seg + (size_t)(i - first) * L.state_len);
-            step_into<T>(st, stage_slot<T>(st, L, i - first));
+        if (!(sg == nseg - 1 && st->last_seg_valid)) {
+            st->last_seg_valid = false;
+            check(hipMemcpyAsync(L.seg, L.ckpt + (size_t)sg * L.state_len, L.state_len * sizeof(T), hipMemcpyDeviceToDevice,
+                                 st->stream), "hipMemcpyAsync D2D");
+            k_macro<T><<<blocks_for(n), kBlock, 0, st->stream>>>((int)n, L.seg, (T *)st->M[st->cur_m], T(st->par.rho0));
+            for (int i = first; i < last; ++i) step_seg<T>(st, L, i - first);
         }
         for (int i = last - 1; i >= first; --i)
             reverse_step<T>(st, L, L.seg + (size_t)(i - first) * L.state_len, stage_slot<T>(st, L, i - first));
     }
+    st->last_seg_valid = false;
     // restore the final state
     load_state<T>(st, L.ckpt + (size_t)nseg * L.state_len);
     // macro buffers for a residual of a later step: both hold the final macro variables
-    check(hipMemcpyAsync(st->M[st->cur_m ^ 1], st->M[st->cur_m], 3 * (size_t)st->n_cells * sizeof(T),
-                         hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    check(hipMemcpyAsync(st->M[st->cur_m ^ 1], st->M[st->cur_m], 3 * n * sizeof(T), hipMemcpyDeviceToDevice, st->stream),
+          "hipMemcpyAsync D2D");
 }
 
 template <typename T>

@@ -653,7 +653,8 @@ __global__ void __launch_bounds__(256) k_advect(Geo<T> g, const T *__restrict__ 
 // k-omega SST (Section 2 model; finite-volume form Eq. (SSTequint)).
 // aux planes: 0,1 grad k; 2,3 grad omega; 4 Gamma_k; 5 Gamma_omega; 6 dt P / rho;
 //             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S;
-//             10, 11 net inflows of k, omega (written by the flux / update stage).
+//             10, 11 net inflows of k, omega (written by the flux / update stage);
+//             12..14 the input macro variables rho - rho0, u, v (kept for the adjoint).
 // Boundary data per edge (set at init): b_ux, b_uy velocity (0 on resting walls), b_k (0 on walls),
 // b_w (60 nu / (beta1 d_perp^2) on walls), and b_zg = 1 where k, omega, u are zero-gradient
 // (outlets, far-field outflow edges).
@@ -818,7 +819,8 @@ __device__ __forceinline__ SstParams<T> sst_params(const StepPar<T> &p) {
 // k-omega SST kernels (Section 2 model; finite-volume form Eq. (SSTequint)).
 // aux planes: 0,1 grad k; 2,3 grad omega; 4 Gamma_k; 5 Gamma_omega; 6 dt P / rho;
 //             7 dt (P_omega + cross diffusion) / rho; 8 blended beta; 9 strain rate S;
-//             10, 11 net inflows of k, omega (written by the flux / update stage).
+//             10, 11 net inflows of k, omega (written by the flux / update stage);
+//             12..14 the input macro variables rho - rho0, u, v (kept for the adjoint).
 // Boundary data per edge (set at init): b_ux, b_uy velocity (0 on resting walls), b_k (0 on walls),
 // b_w (60 nu / (beta1 d_perp^2) on walls), and b_zg = 1 where k, omega, u are zero-gradient
 // (outlets, far-field outflow edges).
@@ -929,6 +931,9 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
     }
     aux[(size_t)10 * n + c] = net_k;
     aux[(size_t)11 * n + c] = net_w;
+    aux[(size_t)12 * n + c] = M[c];
+    aux[(size_t)13 * n + c] = M[(size_t)n + c];
+    aux[(size_t)14 * n + c] = M[(size_t)2 * n + c];
     T k1, w1, nt;
     sst_update<T, T>(xc[0], xc[3], xc[4], net_k, net_w, aux[(size_t)6 * n + c], aux[(size_t)7 * n + c],
                      aux[(size_t)8 * n + c], aux[(size_t)9 * n + c], T(g.wdist[c]), g.inv_area[c], p, sst_params(p),
@@ -1004,11 +1009,17 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     int nb[S], col[S];
     T cxs[S], cys[S], nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S];
     if (own) {
-        rho = p.rho0 + M[c];
+        const T drho = M[c];
+        rho = p.rho0 + drho;
         ux = M[(size_t)n + c];
         uy = M[(size_t)2 * n + c];
         kc = K[c];
         wc = W[c];
+        if constexpr (AUX) {
+            aux[(size_t)12 * n + c] = drho;
+            aux[(size_t)13 * n + c] = ux;
+            aux[(size_t)14 * n + c] = uy;
+        }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const size_t si = (size_t)s * n + c;
