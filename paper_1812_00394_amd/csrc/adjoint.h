@@ -121,64 +121,6 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
     }
 }
 
-// Ghost-state part of adv_T1 for cells with boundary edges (after k_adv_T1): the face values on
-// walls and incoming directions, and the ghosts' use in the cell's own LSQ gradient, through the
-// ghost state's Jacobian.  One thread per cell: boundary edges are ordered by owner cell, and the
-// thread of a cell's first boundary edge takes all of them in slot order.  Kept out of k_adv_T1 so
-// that its dual-number registers do not limit the occupancy of the all-cell kernel.  With tau1
-// given, the field is the stage solve of f with a = a_dt / tau1 (f^(1) from f^n).
-template <typename T>
-__global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__ f, const T *__restrict__ tau1, T a_dt,
-                                                 const T *__restrict__ L, T lscale, T *__restrict__ gbar,
-                                                 const T *__restrict__ Gbar, double *__restrict__ dth, T rho0) {
-    const int b0 = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b0 >= g.nb) return;
-    const int j = g.b_cell[b0];
-    if (b0 > 0 && g.b_cell[b0 - 1] == j) return;
-    const int n = g.n;
-    T mu[9], gj[9], gd[9], Gx[9], Gy[9];
-    const T ia = g.inv_area[j];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        mu[a] = -(lscale * L[(size_t)a * n + j]) * ia;
-        gj[a] = f[(size_t)a * n + j];
-        gd[a] = T(0);
-    }
-    if (tau1) {
-        T f1[9], fe[9];
-        stage_collide(gj, a_dt / tau1[j], rho0, f1, fe);
-#pragma unroll
-        for (int a = 0; a < 9; ++a) gj[a] = f1[a];
-    }
-    Gx[0] = Gy[0] = T(0);
-#pragma unroll
-    for (int a = 1; a < 9; ++a) {
-        Gx[a] = Gbar[(size_t)(2 * (a - 1)) * n + j];
-        Gy[a] = Gbar[(size_t)(2 * (a - 1) + 1) * n + j];
-    }
-    T th = 0;
-    for (int s = 0; s < 4; ++s) {
-        const size_t si = (size_t)s * n + j;
-        const int nb = g.nbr[si];
-        if (nb >= -1) continue;
-        const int b = -2 - nb;
-        const int kind = g.b_kind[b];
-        const bool wall = (kind == kWall || kind == kMovingWall);
-        const T nlx = g.nlx[si], nly = g.nly[si], cxs = g.cx[si], cys = g.cy[si];
-        T gb_bar[9];
-        gb_bar[0] = T(0);
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
-            gb_bar[a] = cxs * Gx[a] + cys * Gy[a] + ((wall || en < T(0)) ? en * mu[a] : T(0));
-        }
-        th += ghost_vjp(g, b, nlx, nly, gj, rho0, gb_bar, gd);
-    }
-#pragma unroll
-    for (int a = 0; a < 9; ++a) gbar[(size_t)a * n + j] += gd[a];
-    dth[j] += (double)th;
-}
-
 // Interior neighbours' part of the transposed LSQ gradient.  rev[k][s]: the slot of neighbour
 // nbr[k][s] that points back to s.
 template <typename T>
@@ -203,186 +145,6 @@ __global__ void __launch_bounds__(256) k_adv_T2(Geo<T> g, const int8_t *__restri
     }
 #pragma unroll
     for (int a = 1; a < 9; ++a) gbar[(size_t)a * n + s0] += acc[a];
-}
-
-// Ring-tiled transposed convection (adv_T1 and adv_T2 in one launch, ghost parts excepted), in the
-// layout of the ring-tiled forward sweeps:
-//   phase 0: mu = -L / A of tile cell t and ext cell t into LDS; the edge data of tile cell t (with
-//            the LSQ coefficient of each interior neighbour's slot that points back, c_(j->t))
-//            and of ring-1 cell t into registers;
-//   phase 1: adv_T1 of tile cell t and ring-1 cell t: Gbar (the adjoint of the LSQ gradient) into
-//            LDS, and the own part of tile cell t;
-//   phase 2: adv_T2 of tile cell t from its neighbours' Gbar in LDS; out += (ACC) or = the sum.
-// Gbar goes to global memory only for cells with boundary edges, where k_adv_T1b reads it.
-template <typename T, int S, bool ACC>
-__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
-    k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
-                 int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, T *__restrict__ Gbar) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    T *V = reinterpret_cast<T *>(smem);   // [8][Wv]: mu of directions 1..8
-    T *Gl = V + 8 * Wv;                   // [16][Wg]
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
-    const int start = tile * kTileCells;
-    const int ncell = min(kTileCells, g.n - start);
-    const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
-    const int t = threadIdx.x;
-    const int n = g.n;
-    const bool own = t < ncell, ext = t < nx, ring1 = t < n1;
-    const int c = start + t;
-
-    // ---- phase 0 ----
-    T mu[9];
-    int nb[S], col[S];
-    T nlx[S], nly[S], rx[S], ry[S], cxs[S], cys[S], cbx[S], cby[S];
-    if (own) {
-        const T ia = g.inv_area[c];
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            mu[a] = -(lscale * L[(size_t)a * n + c]) * ia;
-            V[(a - 1) * Wv + t] = mu[a];
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const size_t si = (size_t)s * n + c;
-            nb[s] = g.nbr[si];
-            col[s] = lnb[si];
-            nlx[s] = g.nlx[si];
-            nly[s] = g.nly[si];
-            rx[s] = g.rfx[si];
-            ry[s] = g.rfy[si];
-            cxs[s] = g.cx[si];
-            cys[s] = g.cy[si];
-            cbx[s] = cby[s] = T(0);
-            if (nb[s] >= 0) {
-                const size_t sj = (size_t)rev[si] * n + nb[s];
-                cbx[s] = g.cx[sj];
-                cby[s] = g.cy[sj];
-            }
-        }
-    }
-    T hmu[9];
-    int hnb[S], hcol[S];
-    T hnlx[S], hnly[S], hrx[S], hry[S], hcx[S], hcy[S];
-    if (ext) {
-        const int hc = rt.cell[x0 + t];
-        const T ia = g.inv_area[hc];
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            hmu[a] = -(lscale * L[(size_t)a * n + hc]) * ia;
-            V[(a - 1) * Wv + kTileCells + t] = hmu[a];
-        }
-        if (ring1) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const size_t si = (size_t)s * n + hc;
-                hnb[s] = g.nbr[si];
-                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
-                hnlx[s] = g.nlx[si];
-                hnly[s] = g.nly[si];
-                hrx[s] = g.rfx[si];
-                hry[s] = g.rfy[si];
-                hcx[s] = g.cx[si];
-                hcy[s] = g.cy[si];
-            }
-        }
-    }
-    __syncthreads();
-
-    // ---- phase 1: adv_T1 (same summation order as k_adv_T1) ----
-    // weights of the edges whose face value cell x reconstructs: interior edges (mu_x - mu_N) and
-    // outgoing directions of open boundaries (mu_x); gd: the part on g_x itself
-    auto t1 = [&](const T m[9], const int *nbs, const int *cols, const T *nx_, const T *ny_, const T *rx_,
-                  const T *ry_, T gd[9], T Gx[9], T Gy[9]) {
-#pragma unroll
-        for (int a = 0; a < 9; ++a) gd[a] = Gx[a] = Gy[a] = T(0);
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            if (nbs[s] == -1) continue;
-            if (nbs[s] >= 0) {
-#pragma unroll
-                for (int a = 1; a < 9; ++a) {
-                    const T en = T(ex(a)) * nx_[s] + T(ey(a)) * ny_[s];
-                    if (en > T(0)) {
-                        const T w = en * (m[a] - V[(a - 1) * Wv + cols[s]]);
-                        gd[a] += w;
-                        Gx[a] += w * rx_[s];
-                        Gy[a] += w * ry_[s];
-                    }
-                }
-            } else {
-                const int kind = g.b_kind[-2 - nbs[s]];
-                if (kind == kWall || kind == kMovingWall) continue;
-#pragma unroll
-                for (int a = 1; a < 9; ++a) {
-                    const T en = T(ex(a)) * nx_[s] + T(ey(a)) * ny_[s];
-                    if (en >= T(0)) {
-                        const T w = en * m[a];
-                        gd[a] += w;
-                        Gx[a] += w * rx_[s];
-                        Gy[a] += w * ry_[s];
-                    }
-                }
-            }
-        }
-    };
-    if (ring1) {
-        T gd[9], Gx[9], Gy[9];
-        t1(hmu, hnb, hcol, hnlx, hnly, hrx, hry, gd, Gx, Gy);
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            Gl[(2 * (a - 1)) * Wg + kTileCells + t] = Gx[a];
-            Gl[(2 * (a - 1) + 1) * Wg + kTileCells + t] = Gy[a];
-        }
-    }
-    T gd[9], Gx[9], Gy[9];
-    if (own) {
-        t1(mu, nb, col, nlx, nly, rx, ry, gd, Gx, Gy);
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            Gl[(2 * (a - 1)) * Wg + t] = Gx[a];
-            Gl[(2 * (a - 1) + 1) * Wg + t] = Gy[a];
-        }
-    }
-    __syncthreads();
-    if (!own) return;
-
-    // ---- phase 2: own LSQ part, then adv_T2 (same order as k_adv_T1 + k_adv_T2) ----
-    T sx = 0, sy = 0;
-    bool bnd = false;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        if (nb[s] == -1) continue;
-        sx += cxs[s];
-        sy += cys[s];
-        bnd = bnd || nb[s] <= -2;
-    }
-#pragma unroll
-    for (int a = 1; a < 9; ++a) gd[a] -= sx * Gx[a] + sy * Gy[a];
-    T acc[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) acc[a] = T(0);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        if (nb[s] < 0) continue;
-#pragma unroll
-        for (int a = 1; a < 9; ++a)
-            acc[a] += cbx[s] * Gl[(2 * (a - 1)) * Wg + col[s]] + cby[s] * Gl[(2 * (a - 1) + 1) * Wg + col[s]];
-    }
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const size_t i = (size_t)a * n + c;
-        if constexpr (ACC)
-            out[i] = (out[i] + gd[a]) + acc[a];
-        else
-            out[i] = gd[a] + acc[a];
-    }
-    if (bnd) {
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            Gbar[(size_t)(2 * (a - 1)) * n + c] = Gx[a];
-            Gbar[(size_t)(2 * (a - 1) + 1) * n + c] = Gy[a];
-        }
-    }
 }
 
 }  // namespace fvlbm
@@ -556,17 +318,16 @@ __global__ void __launch_bounds__(256) k_adj_stage3(int n, AdjBufs<T> b, StepPar
 }
 
 // Reverse of the second stage f2 = solve(f^n + dt/2 Ga1, a2 = dt/(4 tau)) given the complete f2
-// adjoint: lfn += rhs2_bar; lam <- Ga1 adjoint = lg1 + dt/2 rhs2_bar; ltau += ...
+// adjoint lf2 of cell c: lfn += rhs2_bar; lam_out <- Ga1 adjoint = lg1 + dt/2 rhs2_bar (lam_out may
+// be lg1 itself); ltau += ...
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_stage2(int n, AdjBufs<T> b, StepPar<T> p) {
-    const int c = cell_index();
-    if (c >= n) return;
-    T f2[9], lf2[9], lr[9];
+__device__ __forceinline__ void adj_stage2_cell(int c, int n, const T lf2[9], const AdjBufs<T> &b, T *lam_out,
+                                                const StepPar<T> &p) {
+    T f2[9], lr[9];
     const T tc = b.tau[c];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         f2[a] = b.f2[(size_t)a * n + c];
-        lf2[a] = b.lf2[(size_t)a * n + c];
         lr[a] = T(0);
     }
     T m0, mx, my;
@@ -577,22 +338,19 @@ __global__ void __launch_bounds__(256) k_adj_stage2(int n, AdjBufs<T> b, StepPar
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
         b.lfn[i] += lr[a];
-        b.lam[i] = b.lg1[i] + p.dt * T(0.5) * lr[a];
+        lam_out[i] = b.lg1[i] + p.dt * T(0.5) * lr[a];
     }
     b.ltau[c] += -abar * a2 / tc;
 }
 
-// Reverse of the first stage f1 = solve(f^n, a1 = dt/(4 tau)) given the complete f1 adjoint.
+// Reverse of the first stage f1 = solve(f^n, a1 = dt/(4 tau)) given the complete f1 adjoint lf1.
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_stage1(int n, AdjBufs<T> b, StepPar<T> p) {
-    const int c = cell_index();
-    if (c >= n) return;
-    T f1[9], fe[9], fn[9], lf1[9], lr[9];
+__device__ __forceinline__ void adj_stage1_cell(int c, int n, const T lf1[9], const AdjBufs<T> &b, const StepPar<T> &p) {
+    T f1[9], fe[9], fn[9], lr[9];
     const T tc = b.tau[c];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         fn[a] = b.fn[(size_t)a * n + c];
-        lf1[a] = b.lf1[(size_t)a * n + c];
         lr[a] = T(0);
     }
     stage_collide(fn, p.dt / (T(4) * tc), p.rho0, f1, fe);   // f^(1)
@@ -603,6 +361,283 @@ __global__ void __launch_bounds__(256) k_adj_stage1(int n, AdjBufs<T> b, StepPar
 #pragma unroll
     for (int a = 0; a < 9; ++a) b.lfn[(size_t)a * n + c] += lr[a];
     b.ltau[c] += -abar * a1 / tc;
+}
+
+// The stage reverse that follows the transposed convection of stage J (EPI = J, 0: none), for cell
+// c with the complete adjoint lf of its stage field: stage 2 leaves the Ga1 adjoint in lg1.
+template <typename T, int EPI>
+__device__ __forceinline__ void adj_stage_epilogue(int c, int n, const T lf[9], const AdjBufs<T> &b, const StepPar<T> &p) {
+    if constexpr (EPI == 2)
+        adj_stage2_cell(c, n, lf, b, b.lg1, p);
+    else if constexpr (EPI == 1)
+        adj_stage1_cell(c, n, lf, b, p);
+}
+
+template <typename T, int EPI>
+__global__ void __launch_bounds__(256) k_adj_stage(int n, AdjBufs<T> b, StepPar<T> p, const T *__restrict__ lf_in) {
+    const int c = cell_index();
+    if (c >= n) return;
+    T lf[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) lf[a] = lf_in[(size_t)a * n + c];
+    adj_stage_epilogue<T, EPI>(c, n, lf, b, p);
+}
+
+// Ghost-state part of adv_T1 for cells with boundary edges (after k_adv_T1): the face values on
+// walls and incoming directions, and the ghosts' use in the cell's own LSQ gradient, through the
+// ghost state's Jacobian.  One thread per cell: boundary edges are ordered by owner cell, and the
+// thread of a cell's first boundary edge takes all of them in slot order.  Kept out of k_adv_T1 so
+// that its dual-number registers do not limit the occupancy of the all-cell kernel.  With tau1
+// given, the field is the stage solve of f with a = a_dt / tau1 (f^(1) from f^n).  EPI = J: the
+// cell's stage-J reverse follows (k_adv_T_ring left the cell's adjoint in gbar without it).
+template <typename T, int EPI>
+__global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__ f, const T *__restrict__ tau1, T a_dt,
+                                                 const T *__restrict__ L, T lscale, T *__restrict__ gbar,
+                                                 const T *__restrict__ Gbar, double *__restrict__ dth, T rho0,
+                                                 AdjBufs<T> ab, StepPar<T> p) {
+    const int b0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b0 >= g.nb) return;
+    const int j = g.b_cell[b0];
+    if (b0 > 0 && g.b_cell[b0 - 1] == j) return;
+    const int n = g.n;
+    T mu[9], gj[9], gd[9], Gx[9], Gy[9];
+    const T ia = g.inv_area[j];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        mu[a] = -(lscale * L[(size_t)a * n + j]) * ia;
+        gj[a] = f[(size_t)a * n + j];
+        gd[a] = T(0);
+    }
+    if (tau1) {
+        T f1[9], fe[9];
+        stage_collide(gj, a_dt / tau1[j], rho0, f1, fe);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gj[a] = f1[a];
+    }
+    Gx[0] = Gy[0] = T(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        Gx[a] = Gbar[(size_t)(2 * (a - 1)) * n + j];
+        Gy[a] = Gbar[(size_t)(2 * (a - 1) + 1) * n + j];
+    }
+    T th = 0;
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + j;
+        const int nb = g.nbr[si];
+        if (nb >= -1) continue;
+        const int b = -2 - nb;
+        const int kind = g.b_kind[b];
+        const bool wall = (kind == kWall || kind == kMovingWall);
+        const T nlx = g.nlx[si], nly = g.nly[si], cxs = g.cx[si], cys = g.cy[si];
+        T gb_bar[9];
+        gb_bar[0] = T(0);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+            gb_bar[a] = cxs * Gx[a] + cys * Gy[a] + ((wall || en < T(0)) ? en * mu[a] : T(0));
+        }
+        th += ghost_vjp(g, b, nlx, nly, gj, rho0, gb_bar, gd);
+    }
+    dth[j] += (double)th;
+    if constexpr (EPI == 0) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gbar[(size_t)a * n + j] += gd[a];
+    } else {
+        T lf[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) lf[a] = gbar[(size_t)a * n + j] + gd[a];
+        adj_stage_epilogue<T, EPI>(j, n, lf, ab, p);
+    }
+}
+
+// Ring-tiled transposed convection (adv_T1 and adv_T2 in one launch, ghost parts excepted), in the
+// layout of the ring-tiled forward sweeps:
+//   phase 0: mu = -L / A of tile cell t and ext cell t into LDS; the edge data of tile cell t (with
+//            the LSQ coefficient of each interior neighbour's slot that points back, c_(j->t))
+//            and of ring-1 cell t into registers;
+//   phase 1: adv_T1 of tile cell t and ring-1 cell t: Gbar (the adjoint of the LSQ gradient) into
+//            LDS, and the own part of tile cell t;
+//   phase 2: adv_T2 of tile cell t from its neighbours' Gbar in LDS; out += (ACC) or = the sum;
+//            EPI = J: for a cell without boundary edges its stage-J reverse follows at once
+//            (nothing stored in out); a cell with boundary edges stores the sum, k_adv_T1b adds
+//            the ghost part and runs the stage reverse.
+// Gbar goes to global memory only for cells with boundary edges, where k_adv_T1b reads it.
+template <typename T, int S, bool ACC, int EPI>
+__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
+    k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
+                 int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, T *__restrict__ Gbar, AdjBufs<T> ab,
+                 StepPar<T> p) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *V = reinterpret_cast<T *>(smem);   // [8][Wv]: mu of directions 1..8
+    T *Gl = V + 8 * Wv;                   // [16][Wg]
+    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int start = tile * kTileCells;
+    const int ncell = min(kTileCells, g.n - start);
+    const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
+    const int t = threadIdx.x;
+    const int n = g.n;
+    const bool own = t < ncell, ext = t < nx, ring1 = t < n1;
+    const int c = start + t;
+
+    // ---- phase 0 ----
+    T mu[9];
+    int nb[S], col[S];
+    T nlx[S], nly[S], rx[S], ry[S], cxs[S], cys[S], cbx[S], cby[S];
+    if (own) {
+        const T ia = g.inv_area[c];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            mu[a] = -(lscale * L[(size_t)a * n + c]) * ia;
+            V[(a - 1) * Wv + t] = mu[a];
+        }
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const size_t si = (size_t)s * n + c;
+            nb[s] = g.nbr[si];
+            col[s] = lnb[si];
+            nlx[s] = g.nlx[si];
+            nly[s] = g.nly[si];
+            rx[s] = g.rfx[si];
+            ry[s] = g.rfy[si];
+            cxs[s] = g.cx[si];
+            cys[s] = g.cy[si];
+            cbx[s] = cby[s] = T(0);
+            if (nb[s] >= 0) {
+                const size_t sj = (size_t)rev[si] * n + nb[s];
+                cbx[s] = g.cx[sj];
+                cby[s] = g.cy[sj];
+            }
+        }
+    }
+    T hmu[9];
+    int hnb[S], hcol[S];
+    T hnlx[S], hnly[S], hrx[S], hry[S], hcx[S], hcy[S];
+    if (ext) {
+        const int hc = rt.cell[x0 + t];
+        const T ia = g.inv_area[hc];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            hmu[a] = -(lscale * L[(size_t)a * n + hc]) * ia;
+            V[(a - 1) * Wv + kTileCells + t] = hmu[a];
+        }
+        if (ring1) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const size_t si = (size_t)s * n + hc;
+                hnb[s] = g.nbr[si];
+                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
+                hnlx[s] = g.nlx[si];
+                hnly[s] = g.nly[si];
+                hrx[s] = g.rfx[si];
+                hry[s] = g.rfy[si];
+                hcx[s] = g.cx[si];
+                hcy[s] = g.cy[si];
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- phase 1: adv_T1 (same summation order as k_adv_T1) ----
+    // weights of the edges whose face value cell x reconstructs: interior edges (mu_x - mu_N) and
+    // outgoing directions of open boundaries (mu_x); gd: the part on g_x itself
+    auto t1 = [&](const T m[9], const int *nbs, const int *cols, const T *nx_, const T *ny_, const T *rx_,
+                  const T *ry_, T gd[9], T Gx[9], T Gy[9]) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gd[a] = Gx[a] = Gy[a] = T(0);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nbs[s] == -1) continue;
+            if (nbs[s] >= 0) {
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const T en = T(ex(a)) * nx_[s] + T(ey(a)) * ny_[s];
+                    if (en > T(0)) {
+                        const T w = en * (m[a] - V[(a - 1) * Wv + cols[s]]);
+                        gd[a] += w;
+                        Gx[a] += w * rx_[s];
+                        Gy[a] += w * ry_[s];
+                    }
+                }
+            } else {
+                const int kind = g.b_kind[-2 - nbs[s]];
+                if (kind == kWall || kind == kMovingWall) continue;
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const T en = T(ex(a)) * nx_[s] + T(ey(a)) * ny_[s];
+                    if (en >= T(0)) {
+                        const T w = en * m[a];
+                        gd[a] += w;
+                        Gx[a] += w * rx_[s];
+                        Gy[a] += w * ry_[s];
+                    }
+                }
+            }
+        }
+    };
+    if (ring1) {
+        T gd[9], Gx[9], Gy[9];
+        t1(hmu, hnb, hcol, hnlx, hnly, hrx, hry, gd, Gx, Gy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gl[(2 * (a - 1)) * Wg + kTileCells + t] = Gx[a];
+            Gl[(2 * (a - 1) + 1) * Wg + kTileCells + t] = Gy[a];
+        }
+    }
+    T gd[9], Gx[9], Gy[9];
+    if (own) {
+        t1(mu, nb, col, nlx, nly, rx, ry, gd, Gx, Gy);
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gl[(2 * (a - 1)) * Wg + t] = Gx[a];
+            Gl[(2 * (a - 1) + 1) * Wg + t] = Gy[a];
+        }
+    }
+    __syncthreads();
+    if (!own) return;
+
+    // ---- phase 2: own LSQ part, then adv_T2 (same order as k_adv_T1 + k_adv_T2) ----
+    T sx = 0, sy = 0;
+    bool bnd = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] == -1) continue;
+        sx += cxs[s];
+        sy += cys[s];
+        bnd = bnd || nb[s] <= -2;
+    }
+#pragma unroll
+    for (int a = 1; a < 9; ++a) gd[a] -= sx * Gx[a] + sy * Gy[a];
+    T acc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) acc[a] = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        if (nb[s] < 0) continue;
+#pragma unroll
+        for (int a = 1; a < 9; ++a)
+            acc[a] += cbx[s] * Gl[(2 * (a - 1)) * Wg + col[s]] + cby[s] * Gl[(2 * (a - 1) + 1) * Wg + col[s]];
+    }
+    T lf[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        if constexpr (ACC)
+            lf[a] = (out[(size_t)a * n + c] + gd[a]) + acc[a];
+        else
+            lf[a] = gd[a] + acc[a];
+    }
+    if (EPI == 0 || bnd) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) out[(size_t)a * n + c] = lf[a];
+    } else {
+        adj_stage_epilogue<T, EPI>(c, n, lf, ab, p);
+    }
+    if (bnd) {
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            Gbar[(size_t)(2 * (a - 1)) * n + c] = Gx[a];
+            Gbar[(size_t)(2 * (a - 1) + 1) * n + c] = Gy[a];
+        }
+    }
 }
 
 // ----------------------------------------------------------------------------------------------

@@ -584,40 +584,59 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
     check(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
 
+template <typename T, int S, bool ACC, int EPI>
+void launch_T_ring(fvlbm_state *st, const T *lam, T lscale, T *out, const AdjBufs<T> &ab, const StepPar<T> &p) {
+    const Geo<T> &g = geo_of<T>(st);
+    const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+    k_adv_T_ring<T, S, ACC, EPI><<<st->mesh->n_tiles, kTileCells, st->lds_bytes, st->stream>>>(
+        g, rt, st->lnb, st->rev, st->ring_wv, st->ring_wg, lam, lscale, out, (T *)st->G, ab, p);
+}
+
 // Transposed convection at field f (with tau1: at the stage solve of f with a = dt / (4 tau1))
 // applied to lscale lam, accumulated into out (acc) or stored there; the theta part per cell is
-// added to dth.  Uses st->G for the gradient adjoints.
+// added to dth.  epi = J (acc only): the stage-J reverse follows, taking the complete adjoint of
+// the stage field (the ring path then leaves out undefined for cells without boundary edges).
+// Uses st->G for the gradient adjoints.
 template <typename T>
-void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T lscale, T *out, double *dth, bool acc) {
+void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T lscale, T *out, double *dth, bool acc,
+                   int epi = 0, const AdjBufs<T> &ab = AdjBufs<T>{}, const StepPar<T> &p = StepPar<T>{}) {
     const T a_dt = T(st->par.dt / 4.0);
     const Geo<T> &g = geo_of<T>(st);
     const int nbk = blocks_for(g.n);
     hipStream_t s = st->stream;
+    if (epi != 0 && !acc) throw Error(FVLBM_EINVAL, "adv_transpose: a stage epilogue needs accumulation");
     if (st->ring) {
-        const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
-        const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
-        const size_t lds = st->lds_bytes;
-        T *Gb = (T *)st->G;
-        if (st->ring_s == 3) {
-            if (acc)
-                k_adv_T_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
+        const bool s3 = st->ring_s == 3;
+        if (!acc)
+            s3 ? launch_T_ring<T, 3, false, 0>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, false, 0>(st, lam, lscale, out, ab, p);
+        else if (epi == 0)
+            s3 ? launch_T_ring<T, 3, true, 0>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, true, 0>(st, lam, lscale, out, ab, p);
+        else if (epi == 2)
+            s3 ? launch_T_ring<T, 3, true, 2>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, true, 2>(st, lam, lscale, out, ab, p);
+        else
+            s3 ? launch_T_ring<T, 3, true, 1>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, true, 1>(st, lam, lscale, out, ab, p);
+        if (g.nb > 0) {
+            const int nbb = blocks_for(g.nb);
+            const T rho0 = T(st->par.rho0);
+            if (epi == 2)
+                k_adv_T1b<T, 2><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
+            else if (epi == 1)
+                k_adv_T1b<T, 1><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
             else
-                k_adv_T_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
-        } else {
-            if (acc)
-                k_adv_T_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
-            else
-                k_adv_T_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, lam, lscale, out, Gb);
+                k_adv_T1b<T, 0><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
         }
-        if (g.nb > 0)
-            k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, T(st->par.rho0));
         return;
     }
     if (!acc) k_fill<T><<<blocks_for(9 * (size_t)g.n), kBlock, 0, s>>>(9 * g.n, out, T(0));
     k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, (T *)st->G);
     if (g.nb > 0)
-        k_adv_T1b<T><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, T(st->par.rho0));
+        k_adv_T1b<T, 0><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth,
+                                                            T(st->par.rho0), ab, p);
     k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, out);
+    if (epi == 2)
+        k_adj_stage<T, 2><<<nbk, kBlock, 0, s>>>(g.n, ab, p, out);
+    else if (epi == 1)
+        k_adj_stage<T, 1><<<nbk, kBlock, 0, s>>>(g.n, ab, p, out);
 }
 
 // Diagnostic: gbar = Gamma^a(g)^T lam and d(lam . Gamma^a(g))/d theta.
@@ -807,10 +826,10 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     // Ga3 enters f^{n+1} with weight dt/3: its transpose is applied to dt/3 lF
     adv_transpose<T>(st, ss.X, nullptr, L.lF, p.dt / T(3), L.lf3, L.pbar, false);
     k_adj_stage3<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    adv_transpose<T>(st, ss.Y, nullptr, L.lam, T(1), L.lf2, L.pbar, true);
-    k_adj_stage2<T><<<nbk, kBlock, 0, s>>>(n, b, p);
-    adv_transpose<T>(st, fn, ss.tau, L.lam, T(1), L.lf1, L.pbar, true);   // at f^(1), formed from f^n
-    k_adj_stage1<T><<<nbk, kBlock, 0, s>>>(n, b, p);
+    // stage 2: transpose at f^(2), then its stage reverse (the Ga1 adjoint goes to lg1)
+    adv_transpose<T>(st, ss.Y, nullptr, L.lam, T(1), L.lf2, L.pbar, true, 2, b, p);
+    // stage 1: transpose at f^(1), formed from f^n, then its stage reverse
+    adv_transpose<T>(st, fn, ss.tau, L.lg1, T(1), L.lf1, L.pbar, true, 1, b, p);
     if (st->sst && st->ring) {
         // one ring-tiled launch; the new k / omega adjoints go through L.lnet (other workgroups
         // still read the old ones as halo data)
