@@ -207,21 +207,20 @@ __device__ __forceinline__ T collide_vjp(const T f[9], T m0, T mx, T my, T a, T 
 template <typename T>
 struct AdjBufs {
     const T *fn, *f2, *f3, *Q, *tau;        // forward data of the step (f^(1) is formed from f^n)
-    T *lfn;    // adjoint of f^n (accumulated)
+    const T *lnext;   // adjoint of f^{n+1} (the step's output)
+    T *lfn;    // adjoint of f^n (written by the third stage's reverse, then accumulated)
     T *lf1, *lf2, *lf3;                     // adjoints of the stage fields
     T *lam;    // input of the transposed convection (adjoint of a convection term)
     T *lg1;    // adjoint of Ga1
     T *ltau;   // adjoint of tau
 };
 
-// Reverse of the third stage and of the combination f^{n+1} = Q + dt/3 Ga3, given f3_bar (already
-// holding Ga3's transpose applied to dt/3 lam_{n+1}) and lam_{n+1} = lfn on entry (the adjoint of
-// f^{n+1}).  Produces: lfn <- adjoint of f^n (partial), lf2 (Gc2 part), lf1 (Gc1 part), lam = Ga2
-// adjoint, lg1 = Ga1 adjoint (partial), ltau.
+// Reverse of the third stage and of the combination f^{n+1} = Q + dt/3 Ga3, given lf3 (the
+// transpose of Ga3 applied to dt/3 lam_{n+1}) and lam_{n+1} = lnext (the adjoint of f^{n+1}).
+// Writes lfn (the adjoint of f^n so far), lf2 (Gc2 part), lf1 (Gc1 part), lam (the Ga2 adjoint and
+// the Ga1 adjoint so far), ltau.
 template <typename T>
-__global__ void __launch_bounds__(256) k_adj_stage3(int n, AdjBufs<T> b, StepPar<T> p) {
-    const int c = cell_index();
-    if (c >= n) return;
+__device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], const AdjBufs<T> &b, const StepPar<T> &p) {
     T fn[9], f1[9], f2[9], f3[9], Q[9], lq[9], l3[9];
     const T tc = b.tau[c];
     const T dt = p.dt;
@@ -229,8 +228,8 @@ __global__ void __launch_bounds__(256) k_adj_stage3(int n, AdjBufs<T> b, StepPar
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
         fn[a] = b.fn[i]; f2[a] = b.f2[i]; f3[a] = b.f3[i]; Q[a] = b.Q[i];
-        lq[a] = b.lfn[i];                 // lam_{n+1} = adjoint of Q
-        l3[a] = b.lf3[i] + lq[a];         // f3 enters Q with weight 1
+        lq[a] = b.lnext[i];               // lam_{n+1} = adjoint of Q
+        l3[a] = lf3[a] + lq[a];           // f3 enters Q with weight 1
     }
     {
         T fe[9];
@@ -311,15 +310,14 @@ __global__ void __launch_bounds__(256) k_adj_stage3(int n, AdjBufs<T> b, StepPar
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
         b.lfn[i] = lfn[a];
-        b.lam[i] = lg12[a];     // Ga2 adjoint
-        b.lg1[i] = lg12[a];     // Ga1 adjoint so far
+        b.lam[i] = lg12[a];     // Ga2 adjoint, and the Ga1 adjoint so far
     }
     b.ltau[c] = ltau;
 }
 
 // Reverse of the second stage f2 = solve(f^n + dt/2 Ga1, a2 = dt/(4 tau)) given the complete f2
-// adjoint lf2 of cell c: lfn += rhs2_bar; lam_out <- Ga1 adjoint = lg1 + dt/2 rhs2_bar (lam_out may
-// be lg1 itself); ltau += ...
+// adjoint lf2 of cell c: lfn += rhs2_bar; lam_out <- Ga1 adjoint = (its part from the third stage,
+// in lam) + dt/2 rhs2_bar; ltau += ...
 template <typename T>
 __device__ __forceinline__ void adj_stage2_cell(int c, int n, const T lf2[9], const AdjBufs<T> &b, T *lam_out,
                                                 const StepPar<T> &p) {
@@ -338,7 +336,7 @@ __device__ __forceinline__ void adj_stage2_cell(int c, int n, const T lf2[9], co
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
         b.lfn[i] += lr[a];
-        lam_out[i] = b.lg1[i] + p.dt * T(0.5) * lr[a];
+        lam_out[i] = b.lam[i] + p.dt * T(0.5) * lr[a];
     }
     b.ltau[c] += -abar * a2 / tc;
 }
@@ -364,10 +362,13 @@ __device__ __forceinline__ void adj_stage1_cell(int c, int n, const T lf1[9], co
 }
 
 // The stage reverse that follows the transposed convection of stage J (EPI = J, 0: none), for cell
-// c with the complete adjoint lf of its stage field: stage 2 leaves the Ga1 adjoint in lg1.
+// c with the complete adjoint lf of its stage field: stage 3 (with the combination) leaves the Ga2
+// adjoint in lam, stage 2 the Ga1 adjoint in lg1.
 template <typename T, int EPI>
 __device__ __forceinline__ void adj_stage_epilogue(int c, int n, const T lf[9], const AdjBufs<T> &b, const StepPar<T> &p) {
-    if constexpr (EPI == 2)
+    if constexpr (EPI == 3)
+        adj_stage3_cell(c, n, lf, b, p);
+    else if constexpr (EPI == 2)
         adj_stage2_cell(c, n, lf, b, b.lg1, p);
     else if constexpr (EPI == 1)
         adj_stage1_cell(c, n, lf, b, p);

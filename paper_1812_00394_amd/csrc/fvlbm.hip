@@ -594,8 +594,8 @@ void launch_T_ring(fvlbm_state *st, const T *lam, T lscale, T *out, const AdjBuf
 
 // Transposed convection at field f (with tau1: at the stage solve of f with a = dt / (4 tau1))
 // applied to lscale lam, accumulated into out (acc) or stored there; the theta part per cell is
-// added to dth.  epi = J (acc only): the stage-J reverse follows, taking the complete adjoint of
-// the stage field (the ring path then leaves out undefined for cells without boundary edges).
+// added to dth.  epi = J: the stage-J reverse follows, taking the complete adjoint of the stage
+// field (the ring path then leaves out undefined for cells without boundary edges).
 // Uses st->G for the gradient adjoints.
 template <typename T>
 void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T lscale, T *out, double *dth, bool acc,
@@ -604,10 +604,14 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
     const Geo<T> &g = geo_of<T>(st);
     const int nbk = blocks_for(g.n);
     hipStream_t s = st->stream;
-    if (epi != 0 && !acc) throw Error(FVLBM_EINVAL, "adv_transpose: a stage epilogue needs accumulation");
+    // stage 3 stores the transpose (its f^(3) adjoint starts from it), stages 2 and 1 add to theirs
+    if ((acc && epi == 3) || (!acc && (epi == 1 || epi == 2)))
+        throw Error(FVLBM_EINVAL, "adv_transpose: stage epilogue and accumulation do not match");
     if (st->ring) {
         const bool s3 = st->ring_s == 3;
-        if (!acc)
+        if (!acc && epi == 3)
+            s3 ? launch_T_ring<T, 3, false, 3>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, false, 3>(st, lam, lscale, out, ab, p);
+        else if (!acc)
             s3 ? launch_T_ring<T, 3, false, 0>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, false, 0>(st, lam, lscale, out, ab, p);
         else if (epi == 0)
             s3 ? launch_T_ring<T, 3, true, 0>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, true, 0>(st, lam, lscale, out, ab, p);
@@ -618,7 +622,9 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
         if (g.nb > 0) {
             const int nbb = blocks_for(g.nb);
             const T rho0 = T(st->par.rho0);
-            if (epi == 2)
+            if (epi == 3)
+                k_adv_T1b<T, 3><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
+            else if (epi == 2)
                 k_adv_T1b<T, 2><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
             else if (epi == 1)
                 k_adv_T1b<T, 1><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
@@ -633,7 +639,9 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
         k_adv_T1b<T, 0><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth,
                                                             T(st->par.rho0), ab, p);
     k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, out);
-    if (epi == 2)
+    if (epi == 3)
+        k_adj_stage<T, 3><<<nbk, kBlock, 0, s>>>(g.n, ab, p, out);
+    else if (epi == 2)
         k_adj_stage<T, 2><<<nbk, kBlock, 0, s>>>(g.n, ab, p, out);
     else if (epi == 1)
         k_adj_stage<T, 1><<<nbk, kBlock, 0, s>>>(g.n, ab, p, out);
@@ -668,12 +676,12 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
 //   checkpoints: (ceil(N/C) + 1) states of f [9n], k [n], omega [n] (the last one: the final state)
 //   segment:     C + 1 states of the same form (the inputs of a segment's steps and its output)
 //   stage data:  C slots of f^(2), f^(3), Q [9n each], tau [n], aux [15n]
-//   adjoint:     lF [9n], lK [n], lW [n], lf1, lf2, lf3, lam, lg1 [9n each], ltau [n],
+//   adjoint:     lF, lF2 [9n], lK [n], lW [n], lf1, lf2, lf3, lam, lg1 [9n each], ltau [n],
 //                lx [11n], lnet [2n], lown [4n], lgrad [8n], pbar [5n] (FP64)
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct AdjLayout {
-    T *ckpt, *seg, *stg, *lF, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
+    T *ckpt, *seg, *stg, *lF, *lF2, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
     double *pbar;
     size_t state_len;
     size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [15][n]
@@ -689,6 +697,7 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     L.stage_len = 43 * (size_t)n;
     L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
     L.lF = cv.take<T>(9 * (size_t)n);
+    L.lF2 = cv.take<T>(9 * (size_t)n);
     L.lK = cv.take<T>(n);
     L.lW = cv.take<T>(n);
     L.lf1 = cv.take<T>(9 * (size_t)n);
@@ -810,8 +819,9 @@ void record(fvlbm_state *st) {
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
 }
 
-// Reverse of one step whose input state is in `slot` and whose stage data is in `ss` (on entry
-// L.lF, L.lK, L.lW hold the adjoint of the step's output; on exit that of its input).
+// Reverse of one step whose input state is in `slot` and whose stage data is in `ss`: from the
+// adjoint of the step's output (f: L.lF; k, omega: L.lK, L.lW) to that of its input (f: L.lF2;
+// k, omega: L.lK, L.lW).
 template <typename T>
 void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const StageSlot<T> &ss) {
     const Geo<T> &g = geo_of<T>(st);
@@ -822,10 +832,10 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     const T *fn = slot;
     const T *Mn = st->sst ? ss.aux + 12 * (size_t)n : nullptr;
     const T *Kn = st->sst ? slot + 9 * (size_t)n : nullptr, *Wn = st->sst ? slot + 10 * (size_t)n : nullptr;
-    AdjBufs<T> b{fn, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
-    // Ga3 enters f^{n+1} with weight dt/3: its transpose is applied to dt/3 lF
-    adv_transpose<T>(st, ss.X, nullptr, L.lF, p.dt / T(3), L.lf3, L.pbar, false);
-    k_adj_stage3<T><<<nbk, kBlock, 0, s>>>(n, b, p);
+    AdjBufs<T> b{fn, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lF2, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
+    // stage 3: Ga3 enters f^{n+1} with weight dt/3, its transpose is applied to dt/3 lF; then the
+    // reverse of the combination and of the third stage
+    adv_transpose<T>(st, ss.X, nullptr, L.lF, p.dt / T(3), L.lf3, L.pbar, false, 3, b, p);
     // stage 2: transpose at f^(2), then its stage reverse (the Ga1 adjoint goes to lg1)
     adv_transpose<T>(st, ss.Y, nullptr, L.lam, T(1), L.lf2, L.pbar, true, 2, b, p);
     // stage 1: transpose at f^(1), formed from f^n, then its stage reverse
@@ -839,10 +849,10 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
         const size_t lds = ((size_t)13 * wv + (size_t)8 * wg) * sizeof(T);
         if (st->ring_s == 3)
             k_adj_sst_ring<T, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
-                                                          L.ltau, L.lF, L.lnet, L.lnet + n, p);
+                                                          L.ltau, L.lF2, L.lnet, L.lnet + n, p);
         else
             k_adj_sst_ring<T, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
-                                                          L.ltau, L.lF, L.lnet, L.lnet + n, p);
+                                                          L.ltau, L.lF2, L.lnet, L.lnet + n, p);
         check(hipMemcpyAsync(L.lK, L.lnet, n * sizeof(T), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync D2D");
         check(hipMemcpyAsync(L.lW, L.lnet + n, n * sizeof(T), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync D2D");
     } else if (st->sst) {
@@ -851,7 +861,7 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
         k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW, L.ltau, L.lx, L.lnet, L.lown, p);
         k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lnet, L.lx, p);
         k_adj_sst_local<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, L.lown, L.lx, L.lgrad, p);
-        k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, Mn, L.lgrad, L.lx, L.lF, L.lK, L.lW, p.rho0);
+        k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, Mn, L.lgrad, L.lx, L.lF2, L.lK, L.lW, p.rho0);
     }
     check(hipGetLastError(), "kernel launch");
 }
@@ -861,7 +871,8 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
 // input state and stage data (the last segment comes from the record pass while those buffers
 // still hold it); then its steps are reversed from the last.
 template <typename T>
-void reverse_run(fvlbm_state *st, const AdjLayout<T> &L) {
+void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
+    AdjLayout<T> L = L0;         // lF / lF2 alternate between steps
     const int N = st->rec_steps, C = st->rec_ckpt;
     const int nseg = (N + C - 1) / C;
     const size_t n = st->n_cells;
@@ -874,9 +885,13 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L) {
             k_macro<T><<<blocks_for(n), kBlock, 0, st->stream>>>((int)n, L.seg, (T *)st->M[st->cur_m], T(st->par.rho0));
             for (int i = first; i < last; ++i) step_seg<T>(st, L, i - first);
         }
-        for (int i = last - 1; i >= first; --i)
+        for (int i = last - 1; i >= first; --i) {
             reverse_step<T>(st, L, L.seg + (size_t)(i - first) * L.state_len, stage_slot<T>(st, L, i - first));
+            std::swap(L.lF, L.lF2);
+        }
     }
+    if (L.lF != L0.lF)
+        check(hipMemcpyAsync(L0.lF, L.lF, 9 * n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
     st->last_seg_valid = false;
     // restore the final state
     load_state<T>(st, L.ckpt + (size_t)nseg * L.state_len);
