@@ -22,34 +22,76 @@
 
 namespace fvlbm {
 
-// d(ghost state)/d(cell state, theta) contracted with gbar (directions 1..8): adds to gout[0..8]
-// and returns the theta part.  Theta rotates the velocity of inlet and far-field edges.
+// Value and partial derivatives of the equilibrium deviation dfeq(a, drho, rho0 + drho, ux, uy)
+// with respect to drho (through rho as well), ux and uy.
+template <typename T>
+struct FeqPartials {
+    T dr, dux, duy;
+};
+
+template <typename T>
+__device__ __forceinline__ FeqPartials<T> dfeq_partials(int a, T rho, T ux, T uy) {
+    const T w = wt<T>(a);
+    const T eu = T(ex(a)) * ux + T(ey(a)) * uy;
+    const T poly = T(3) * eu + T(4.5) * eu * eu - T(1.5) * (ux * ux + uy * uy);
+    return FeqPartials<T>{w * (T(1) + poly), w * rho * (T(3) * T(ex(a)) + T(9) * eu * T(ex(a)) - T(3) * ux),
+                          w * rho * (T(3) * T(ey(a)) + T(9) * eu * T(ey(a)) - T(3) * uy)};
+}
+
+// d(ghost state)/d(cell state, theta) contracted with gbar (directions 1..8), in reverse mode:
+// adds to gout[0..8] and returns the theta part.  The ghost state (ghost_state in lattice.h) of
+// direction a replaced by the boundary is f_eq(rho_g, u_g) + c (g_a - f_eq(rho, u)), with (rho, u)
+// the cell's moments and (rho_g, u_g, c) set by the edge kind; theta rotates the velocity of inlet
+// and far-field edges (d u_b / d theta = (-u_b,y, u_b,x)).
 template <typename T>
 __device__ __forceinline__ T ghost_vjp(const Geo<T> &g, int b, T nlx, T nly, const T gc[9], T rho0, const T gbar[9],
                                        T gout[9]) {
-    using D = Dual<T, 10>;
     const int kind = g.b_kind[b];
-    D gcd[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) gcd[a] = D::var(gc[a], a);
-    const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]);
-    const bool rot = (kind == kInlet || kind == kFarfield);
-    D dubx(ubx), duby(uby);
-    if (rot) {   // d(R(theta) u)/d theta = (-u_y, u_x) of the rotated velocity
-        dubx.d[9] = -uby;
-        duby.d[9] = ubx;
-    }
-    D drho, rho, ux, uy, gb[9];
-    moments(gcd, D(rho0), drho, rho, ux, uy);
-    ghost_state<D, T>(kind, dubx, duby, D(T(g.b_rho[b])), D(T(g.b_drho[b])), nlx, nly, gcd, drho, rho, ux, uy, gb);
-    T dth = 0;
+    const T ubx = T(g.b_ux[b]), uby = T(g.b_uy[b]), rb = T(g.b_rho[b]);
+    const bool wall = kind == kWall || kind == kMovingWall;
+    const bool rot = kind == kInlet || kind == kFarfield;
+    T drho, rho, ux, uy;
+    moments(gc, rho0, drho, rho, ux, uy);
+    T r_b = 0, ux_b = 0, uy_b = 0, ubx_b = 0, uby_b = 0;   // adjoints of drho, ux, uy, u_b
 #pragma unroll
     for (int a = 1; a < 9; ++a) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) gout[i] += gbar[a] * gb[a].d[i];
-        dth += gbar[a] * gb[a].d[9];
+        const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+        const T gb = gbar[a];
+        if (!(wall || en < T(0))) {
+            gout[a] += gb;           // the cell's own value
+            continue;
+        }
+        if (kind != kFarfield) {
+            // + (g_a - f_eq(rho, u)): the non-equilibrium part of the cell
+            gout[a] += gb;
+            const FeqPartials<T> d = dfeq_partials<T>(a, rho, ux, uy);
+            r_b -= gb * d.dr;
+            ux_b -= gb * d.dux;
+            uy_b -= gb * d.duy;
+        }
+        if (wall || kind == kInlet) {
+            // f_eq(rho, u_b)
+            const FeqPartials<T> d = dfeq_partials<T>(a, rho, ubx, uby);
+            r_b += gb * d.dr;
+            ubx_b += gb * d.dux;
+            uby_b += gb * d.duy;
+        } else if (kind == kOutlet) {
+            // f_eq(rho_b, u)
+            const FeqPartials<T> d = dfeq_partials<T>(a, rb, ux, uy);
+            ux_b += gb * d.dux;
+            uy_b += gb * d.duy;
+        } else {
+            // far field: f_eq(rho_b, u_b)
+            const FeqPartials<T> d = dfeq_partials<T>(a, rb, ubx, uby);
+            ubx_b += gb * d.dux;
+            uby_b += gb * d.duy;
+        }
     }
-    return dth;
+    // moments: drho = sum g, u = (sum e g) / rho
+    const T ir = T(1) / rho;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) gout[i] += r_b + (T(ex(i)) - ux) * ir * ux_b + (T(ey(i)) - uy) * ir * uy_b;
+    return rot ? ubx_b * (-uby) + uby_b * ubx : T(0);
 }
 
 // L, gbar: [9][n] (direction 0 of L unused); Gbar: [16][n].  Every edge except the ghost-state
