@@ -464,6 +464,7 @@ __global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__
         Gy[a] = Gbar[(size_t)(2 * (a - 1) + 1) * n + j];
     }
     T th = 0;
+#pragma unroll
     for (int s = 0; s < 4; ++s) {
         const size_t si = (size_t)s * n + j;
         const int nb = g.nbr[si];
@@ -911,7 +912,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     T xc[11], lxc[3], lownc[4];
     SstParBar<T> pbc;
     int nb[S], col[S];
-    T nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], cxs[S], cys[S];
+    T nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], cxs[S], cys[S], cbx[S], cby[S];
     if (own) {
         load_update(c, t, xc, lxc, lownc, pbc);
 #pragma unroll
@@ -927,6 +928,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             qy[s] = g.qy[si];
             cxs[s] = g.cx[si];
             cys[s] = g.cy[si];
+            // the LSQ coefficient of the neighbour's slot that points back
+            cbx[s] = cby[s] = T(0);
+            if (nb[s] >= 0) {
+                const size_t sj = (size_t)rev[si] * n + nb[s];
+                cbx[s] = g.cx[sj];
+                cby[s] = g.cy[sj];
+            }
         }
     }
     T xh[11], lxh[3], lownh[4];
@@ -1025,10 +1033,9 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     for (int s = 0; s < S; ++s) {
         if (nb[s] == -1) continue;
         if (nb[s] >= 0) {
-            const size_t sj = (size_t)rev[(size_t)s * n + c] * n + nb[s];
-            const T cjx = g.cx[sj], cjy = g.cy[sj];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] += cjx * Lg[(2 * v) * Wg + col[s]] + cjy * Lg[(2 * v + 1) * Wg + col[s]];
+            for (int v = 0; v < 4; ++v)
+                acc[v] += cbx[s] * Lg[(2 * v) * Wg + col[s]] + cby[s] * Lg[(2 * v + 1) * Wg + col[s]];
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[v] -= cxs[s] * lgc[2 * v] + cys[s] * lgc[2 * v + 1];
         } else {

@@ -676,12 +676,12 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
 //   checkpoints: (ceil(N/C) + 1) states of f [9n], k [n], omega [n] (the last one: the final state)
 //   segment:     C + 1 states of the same form (the inputs of a segment's steps and its output)
 //   stage data:  C slots of f^(2), f^(3), Q [9n each], tau [n], aux [15n]
-//   adjoint:     lF, lF2 [9n], lK [n], lW [n], lf1, lf2, lf3, lam, lg1 [9n each], ltau [n],
+//   adjoint:     lF, lF2 [9n], lK, lW, lK2, lW2 [n], lf1, lf2, lf3, lam, lg1 [9n each], ltau [n],
 //                lx [11n], lnet [2n], lown [4n], lgrad [8n], pbar [5n] (FP64)
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 struct AdjLayout {
-    T *ckpt, *seg, *stg, *lF, *lF2, *lK, *lW, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
+    T *ckpt, *seg, *stg, *lF, *lF2, *lK, *lW, *lK2, *lW2, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
     double *pbar;
     size_t state_len;
     size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [15][n]
@@ -700,6 +700,8 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     L.lF2 = cv.take<T>(9 * (size_t)n);
     L.lK = cv.take<T>(n);
     L.lW = cv.take<T>(n);
+    L.lK2 = cv.take<T>(n);
+    L.lW2 = cv.take<T>(n);
     L.lf1 = cv.take<T>(9 * (size_t)n);
     L.lf2 = cv.take<T>(9 * (size_t)n);
     L.lf3 = cv.take<T>(9 * (size_t)n);
@@ -821,7 +823,7 @@ void record(fvlbm_state *st) {
 
 // Reverse of one step whose input state is in `slot` and whose stage data is in `ss`: from the
 // adjoint of the step's output (f: L.lF; k, omega: L.lK, L.lW) to that of its input (f: L.lF2;
-// k, omega: L.lK, L.lW).
+// k, omega: L.lK2, L.lW2).
 template <typename T>
 void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const StageSlot<T> &ss) {
     const Geo<T> &g = geo_of<T>(st);
@@ -841,27 +843,24 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     // stage 1: transpose at f^(1), formed from f^n, then its stage reverse
     adv_transpose<T>(st, fn, ss.tau, L.lg1, T(1), L.lf1, L.pbar, true, 1, b, p);
     if (st->sst && st->ring) {
-        // one ring-tiled launch; the new k / omega adjoints go through L.lnet (other workgroups
-        // still read the old ones as halo data)
+        // one ring-tiled launch
         SstAdj sa{st->bzg, L.pbar};
         const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
         const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
         const size_t lds = ((size_t)13 * wv + (size_t)8 * wg) * sizeof(T);
         if (st->ring_s == 3)
             k_adj_sst_ring<T, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
-                                                          L.ltau, L.lF2, L.lnet, L.lnet + n, p);
+                                                          L.ltau, L.lF2, L.lK2, L.lW2, p);
         else
             k_adj_sst_ring<T, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
-                                                          L.ltau, L.lF2, L.lnet, L.lnet + n, p);
-        check(hipMemcpyAsync(L.lK, L.lnet, n * sizeof(T), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync D2D");
-        check(hipMemcpyAsync(L.lW, L.lnet + n, n * sizeof(T), hipMemcpyDeviceToDevice, s), "hipMemcpyAsync D2D");
+                                                          L.ltau, L.lF2, L.lK2, L.lW2, p);
     } else if (st->sst) {
         SstAdj sa{st->bzg, L.pbar};
         k_fill<T><<<blocks_for(11 * (size_t)n), kBlock, 0, s>>>(11 * n, L.lx, T(0));
         k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW, L.ltau, L.lx, L.lnet, L.lown, p);
         k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lnet, L.lx, p);
         k_adj_sst_local<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, L.lown, L.lx, L.lgrad, p);
-        k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, Mn, L.lgrad, L.lx, L.lF2, L.lK, L.lW, p.rho0);
+        k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, Mn, L.lgrad, L.lx, L.lF2, L.lK2, L.lW2, p.rho0);
     }
     check(hipGetLastError(), "kernel launch");
 }
@@ -872,7 +871,7 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
 // still hold it); then its steps are reversed from the last.
 template <typename T>
 void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
-    AdjLayout<T> L = L0;         // lF / lF2 alternate between steps
+    AdjLayout<T> L = L0;         // lF / lF2 (and lK, lW / lK2, lW2) alternate between steps
     const int N = st->rec_steps, C = st->rec_ckpt;
     const int nseg = (N + C - 1) / C;
     const size_t n = st->n_cells;
@@ -888,10 +887,18 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
         for (int i = last - 1; i >= first; --i) {
             reverse_step<T>(st, L, L.seg + (size_t)(i - first) * L.state_len, stage_slot<T>(st, L, i - first));
             std::swap(L.lF, L.lF2);
+            if (st->sst) {
+                std::swap(L.lK, L.lK2);
+                std::swap(L.lW, L.lW2);
+            }
         }
     }
     if (L.lF != L0.lF)
         check(hipMemcpyAsync(L0.lF, L.lF, 9 * n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    if (L.lK != L0.lK) {
+        check(hipMemcpyAsync(L0.lK, L.lK, n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+        check(hipMemcpyAsync(L0.lW, L.lW, n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
+    }
     st->last_seg_valid = false;
     // restore the final state
     load_state<T>(st, L.ckpt + (size_t)nseg * L.state_len);
