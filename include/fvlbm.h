@@ -74,6 +74,10 @@ typedef struct fvlbm_state fvlbm_state;
  *   bface_vals NULL, or [n_bfaces][5] = (u, v, rho, k, omega) per boundary edge in the order
  *              given to fvlbm_mesh_create, replacing the group values (inflow profiles)
  *   jr_group, jr_xmin, eps_tau   the reattachment proxy J_R of fvlbm_forces
+ *   limiter    0: the upwind face value of f is the linear reconstruction (Eq. (advection) with
+ *              the cell gradient); 1: it is also kept between the values of the two cells that
+ *              share the edge (first order at local extrema; for flows around sharp edges).  The
+ *              adjoint entry points reject a limited state (FVLBM_ESTATE).
  */
 typedef struct {
     double nu, dt, rho0;
@@ -85,7 +89,7 @@ typedef struct {
     double group_k[FVLBM_MAX_GROUPS];
     double group_w[FVLBM_MAX_GROUPS];
     const double *bface_vals;
-    int32_t jr_group, reserved;
+    int32_t jr_group, limiter;
     double jr_xmin, eps_tau;
 } fvlbm_params;
 
@@ -172,6 +176,14 @@ fvlbm_status fvlbm_get_f(fvlbm_state *st, int32_t on_device, double *f);
  * l (1 - tanh(tau_x / eps_tau)) / 2 (smooth reversed-flow length).
  */
 fvlbm_status fvlbm_forces(fvlbm_state *st, uint64_t wall_group_mask, double force[2], double *j_r);
+
+/*
+ * Lift and drag coefficients of the walls in wall_group_mask (the force of fvlbm_forces, on the
+ * airfoil of the paper's Section 4 test): drag along the free-stream direction (cos theta,
+ * sin theta), lift along (-sin theta, cos theta), both divided by rho0 u_ref^2 chord / 2.
+ * coeffs[2] = (C_l, C_d).  Errors: FVLBM_EINVAL (NULL, u_ref or chord <= 0), FVLBM_EDIVERGED.
+ */
+fvlbm_status fvlbm_lift_drag(fvlbm_state *st, uint64_t wall_group_mask, double u_ref, double chord, double coeffs[2]);
 
 /*
  * Diagnostic: the convection term Gamma^a of Eq. (advection) of an arbitrary field g, with the

@@ -56,10 +56,15 @@ def rmin(a, b):
     return np.where(np.real(a) <= np.real(b), a, b)
 
 
+def rmin_mask(a, b):
+    """a <= b by real parts (the branch selection of reading r25)."""
+    return np.real(a) <= np.real(b)
+
+
 def default_params(**kw):
     p = dict(nu=1e-3, dt=1e-2, rho0=1.0, sst=False, theta=0.0,
              group_u=None, group_rho=None, group_k=None, group_w=None, bface_vals=None,
-             jr_group=-1, jr_xmin=0.0, eps_tau=1.0)
+             jr_group=-1, jr_xmin=0.0, eps_tau=1.0, limiter=0)
     p.update(SST_DEFAULTS)
     p.update(kw)
     return p
@@ -331,6 +336,12 @@ class Oracle:
     # every a; at open boundaries for incoming a only.
     # ---------------------------------------------------------------------------------------
     def advection(self, g_arr):
+        """Convection term of Eq. (advection) for every cell and direction."""
+        en, face = self.face_values(g_arr)
+        return -self._cell_sum(en * face) / self.g.area
+
+    def face_values(self, g_arr):
+        """(e.n) dl and the upwind face value of every half-face and direction [9, H]."""
         G = self.g
         rho, jx, jy = moments(g_arr)
         ux, uy = jx / rho, jy / rho
@@ -346,10 +357,18 @@ class Oracle:
         rn = G.xf[inner] - G.xs[inner]                            # from the (shifted) neighbour centroid
         v_nbr = g_arr[:, nb] + grad[:, 0, nb] * rn[:, 0] + grad[:, 1, nb] * rn[:, 1]
         face[:, inner] = np.where(en[:, inner] >= 0, v_self[:, inner], v_nbr)
+        if self.p.get("limiter", 0):
+            # optional limiter (a reading; Part I's reconstruction is not in this paper): an
+            # interior face value stays between the values of the two cells that share the edge
+            a_, b_ = g_arr[:, c[inner]], g_arr[:, nb]
+            lo = np.where(rmin_mask(a_, b_), a_, b_)
+            hi = np.where(rmin_mask(a_, b_), b_, a_)
+            v = face[:, inner]
+            face[:, inner] = np.where(np.real(v) < np.real(lo), lo, np.where(np.real(v) > np.real(hi), hi, v))
         bh = G.bidx
         wall = (self.b_kind == WALL) | (self.b_kind == MOVING_WALL)
         face[:, bh] = np.where(wall | (en[:, bh] < 0), gb, v_self[:, bh])
-        return -self._cell_sum(en * face) / G.area
+        return en, face
 
     # ---------------------------------------------------------------------------------------
     # k-omega SST update (Section 2 equations; Section 3.2 coupling; readings r5-r13).

@@ -207,6 +207,7 @@ StepPar<T> step_par(const fvlbm_params &p) {
     s.b1 = T(p.beta1);
     s.b2 = T(p.beta2);
     s.kappa = T(p.kappa);
+    s.limiter = p.limiter;
     return s;
 }
 
@@ -576,7 +577,7 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
     upload_scratch(st, gin, 9 * (size_t)n);
     k_import_f<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, (T *)st->X, st->par.rho0);
     k_grad<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (T *)st->G, T(st->par.rho0));
-    k_advect<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->G, (T *)st->Y, T(st->par.rho0));
+    k_advect<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->G, (T *)st->Y, T(st->par.rho0), st->par.limiter);
     // Gamma^a is exported without the w_a rho0 shift
     k_export_f<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->Y, st->scratch, 0.0);
     check(hipGetLastError(), "kernel launch");
@@ -1060,6 +1061,7 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         if (p->n_groups != m->n_groups) throw Error(FVLBM_EINVAL, "init: params.n_groups differs from the mesh");
         if (!(p->nu > 0) || !(p->dt > 0) || !(p->rho0 > 0)) throw Error(FVLBM_EINVAL, "init: nu, dt and rho0 must be > 0 (tau = 3 nu)");
         if (p->sst && (!k || !omega)) throw Error(FVLBM_EINVAL, "init: SST needs k and omega");
+        if (p->limiter != 0 && p->limiter != 1) throw Error(FVLBM_EINVAL, "init: limiter must be 0 or 1");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "init: workspace must be 256-byte aligned");
         const size_t need = layout_bytes(m, precision, p->sst ? 1 : 0);
         if (ws_bytes < need) throw Error(FVLBM_EINVAL, "init: workspace too small (" + std::to_string(ws_bytes) + " < " + std::to_string(need) + ")");
@@ -1171,6 +1173,23 @@ fvlbm_status fvlbm_forces(fvlbm_state *st, uint64_t mask, double force[2], doubl
     });
 }
 
+fvlbm_status fvlbm_lift_drag(fvlbm_state *st, uint64_t mask, double u_ref, double chord, double coeffs[2]) {
+    return guarded([&] {
+        if (!st || !coeffs) throw Error(FVLBM_EINVAL, "lift_drag: NULL argument");
+        if (!(u_ref > 0) || !(chord > 0)) throw Error(FVLBM_EINVAL, "lift_drag: u_ref and chord must be positive");
+        double r[3];
+        if (st->precision == FVLBM_FP64)
+            forces<double>(st, mask, r);
+        else
+            forces<float>(st, mask, r);
+        if (!std::isfinite(r[0]) || !std::isfinite(r[1])) throw Error(FVLBM_EDIVERGED, "lift_drag: non-finite force");
+        const double c = std::cos(st->par.theta), s = std::sin(st->par.theta);
+        const double q = 0.5 * st->par.rho0 * u_ref * u_ref * chord;
+        coeffs[0] = (-s * r[0] + c * r[1]) / q;
+        coeffs[1] = (c * r[0] + s * r[1]) / q;
+    });
+}
+
 fvlbm_status fvlbm_apply_advection(fvlbm_state *st, const double *g_in, double *out) {
     return guarded([&] {
         if (!st || !g_in || !out) throw Error(FVLBM_EINVAL, "apply_advection: NULL argument");
@@ -1230,6 +1249,7 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
                                            double *d_theta) {
     return guarded([&] {
         if (!st || !g_in || !lam || !g_bar || !d_theta) throw Error(FVLBM_EINVAL, "apply_advection_adjoint: NULL argument");
+        if (st->par.limiter) throw Error(FVLBM_ESTATE, "apply_advection_adjoint: the limited convection has no adjoint here");
         if (st->precision == FVLBM_FP64)
             apply_advection_adjoint<double>(st, g_in, lam, g_bar, d_theta);
         else
@@ -1257,6 +1277,7 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
     return guarded([&] {
         if (!st || !workspace) throw Error(FVLBM_EINVAL, "record: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
+        if (st->par.limiter) throw Error(FVLBM_ESTATE, "record: the limited convection has no adjoint here");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");
         size_t need = 0;
         fvlbm_status e = fvlbm_adjoint_bytes(st->mesh, st->precision, n_steps, ckpt_every, &need);

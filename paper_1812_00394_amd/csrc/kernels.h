@@ -24,6 +24,7 @@ template <typename T>
 struct StepPar {
     T rho0, dt, nu;
     T a1, bstar, sk1, sk2, sw1, sw2, b1, b2, kappa;
+    int limiter;   // keep interior face values of f between the two cells' values
 };
 
 // ----------------------------------------------------------------------------------------------
@@ -92,6 +93,7 @@ struct NbrGlobal {
     __device__ __forceinline__ T recon(int a, int nb, T qx, T qy) const {
         return f[(size_t)a * n + nb] + G[(size_t)(2 * (a - 1)) * n + nb] * qx + G[(size_t)(2 * (a - 1) + 1) * n + nb] * qy;
     }
+    __device__ __forceinline__ T value(int a, int nb) const { return f[(size_t)a * n + nb]; }
 };
 
 template <typename T>
@@ -104,15 +106,23 @@ struct NbrTile {
     __device__ __forceinline__ T recon(int a, int nb, T qx, T qy) const {
         return f[(size_t)a * n + nb] + L[(2 * (a - 1)) * W + loc] * qx + L[(2 * (a - 1) + 1) * W + loc] * qy;
     }
+    __device__ __forceinline__ T value(int a, int nb) const { return f[(size_t)a * n + nb]; }
 };
 
 // Convection term of cell c (Eq. (advection)): -(1/A) sum over edges of (e.n) dl times the face
 // value, the face value being the upwind cell's value extrapolated to the edge midpoint with its
 // LSQ gradient; on walls the ghost state, on open boundaries the ghost state for incoming
 // directions.  gc: the cell's own values; out[0] = 0 (the rest direction does not move).
+// The limited face value: v kept between the values of the two cells sharing the edge.
+template <typename T>
+__device__ __forceinline__ T clip_between(T v, T a, T b) {
+    const T lo = a <= b ? a : b, hi = a <= b ? b : a;
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
 template <typename T, typename Nbr>
 __device__ __forceinline__ void advect_cell(const Geo<T> &g, int c, T rho0, const T gc[9], const T gxc[9], const T gyc[9],
-                                            Nbr nbr_acc, T out[9]) {
+                                            Nbr nbr_acc, T out[9], int limiter = 0) {
     const int n = g.n;
     T acc[9];
 #pragma unroll
@@ -130,7 +140,8 @@ __device__ __forceinline__ void advect_cell(const Geo<T> &g, int c, T rho0, cons
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const T end = T(ex(a)) * nlx + T(ey(a)) * nly;
-                const T val = end >= T(0) ? gc[a] + gxc[a] * rx + gyc[a] * ry : nbr_acc.recon(a, nb, qx, qy);
+                T val = end >= T(0) ? gc[a] + gxc[a] * rx + gyc[a] * ry : nbr_acc.recon(a, nb, qx, qy);
+                if (limiter) val = clip_between(val, gc[a], nbr_acc.value(a, nb));
                 acc[a] += end * val;
             }
         } else {
@@ -157,7 +168,7 @@ __device__ __forceinline__ void advect_cell(const Geo<T> &g, int c, T rho0, cons
 // Convection term of cell c from the global gradient planes (gc = the cell's own values).
 template <typename T>
 __device__ __forceinline__ void advect_cell_global(const Geo<T> &g, const T *__restrict__ f, const T *__restrict__ G,
-                                                   int c, T rho0, const T gc[9], T out[9]) {
+                                                   int c, T rho0, const T gc[9], T out[9], int limiter) {
     const int n = g.n;
     T gxc[9], gyc[9];
 #pragma unroll
@@ -165,7 +176,7 @@ __device__ __forceinline__ void advect_cell_global(const Geo<T> &g, const T *__r
         gxc[a] = G[(size_t)(2 * (a - 1)) * n + c];
         gyc[a] = G[(size_t)(2 * (a - 1) + 1) * n + c];
     }
-    advect_cell(g, c, rho0, gc, gxc, gyc, NbrGlobal<T>{f, G, n}, out);
+    advect_cell(g, c, rho0, gc, gxc, gyc, NbrGlobal<T>{f, G, n}, out, limiter);
 }
 
 // f^(1) = stage solve of f^n with a = dt/(4 tau).
@@ -311,7 +322,7 @@ __global__ void __launch_bounds__(256) k_sweep(Geo<T> g, const T *__restrict__ G
     T gc[9], ga[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
-    advect_cell_global(g, b.src, G, c, p.rho0, gc, ga);
+    advect_cell_global(g, b.src, G, c, p.rho0, gc, ga, p.limiter);
     stage_epilogue<T, J>(c, n, gc, ga, b, p);
 }
 
@@ -337,6 +348,7 @@ struct NbrTileVals {
     __device__ __forceinline__ T recon(int a, int, T qx, T qy) const {
         return L[(15 + a) * W + loc] + L[(2 * (a - 1)) * W + loc] * qx + L[(2 * (a - 1) + 1) * W + loc] * qy;
     }
+    __device__ __forceinline__ T value(int a, int) const { return L[(15 + a) * W + loc]; }
 };
 
 // LSQ gradient of a tile cell whose neighbours' values are all in LDS (value plane of direction a
@@ -433,9 +445,9 @@ __global__ void __launch_bounds__(kTileCells + kHaloThreads)
     const int c = start + t;
     T ga[9];
     if constexpr (VALS)
-        advect_cell(g, c, p.rho0, gc, gx, gy, NbrTileVals<T>{L, lnb, n, W, 0}, ga);
+        advect_cell(g, c, p.rho0, gc, gx, gy, NbrTileVals<T>{L, lnb, n, W, 0}, ga, p.limiter);
     else
-        advect_cell(g, c, p.rho0, gc, gx, gy, NbrTile<T>{b.src, L, lnb, n, W, 0}, ga);
+        advect_cell(g, c, p.rho0, gc, gx, gy, NbrTile<T>{b.src, L, lnb, n, W, 0}, ga, p.limiter);
     stage_epilogue<T, J>(c, n, gc, ga, b, p);
 }
 
@@ -607,9 +619,10 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const T end = T(ex(a)) * nlx[s] + T(ey(a)) * nly[s];
-                const T val = end >= T(0) ? gc[a] + gx[a] * rx[s] + gy[a] * ry[s]
-                                          : V[(a - 1) * Wv + loc] + Gl[(2 * (a - 1)) * Wg + loc] * qx[s] +
-                                                Gl[(2 * (a - 1) + 1) * Wg + loc] * qy[s];
+                T val = end >= T(0) ? gc[a] + gx[a] * rx[s] + gy[a] * ry[s]
+                                    : V[(a - 1) * Wv + loc] + Gl[(2 * (a - 1)) * Wg + loc] * qx[s] +
+                                          Gl[(2 * (a - 1) + 1) * Wg + loc] * qy[s];
+                if (p.limiter) val = clip_between(val, gc[a], V[(a - 1) * Wv + loc]);
                 acc[a] += end * val;
             }
         } else {
@@ -637,14 +650,14 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 // Convection term alone (diagnostic entry point).
 template <typename T>
 __global__ void __launch_bounds__(256) k_advect(Geo<T> g, const T *__restrict__ X, const T *__restrict__ G,
-                                                T *__restrict__ out, T rho0) {
+                                                T *__restrict__ out, T rho0, int limiter) {
     const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     T gc[9], ga[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) gc[a] = X[(size_t)a * n + c];
-    advect_cell_global(g, X, G, c, rho0, gc, ga);
+    advect_cell_global(g, X, G, c, rho0, gc, ga, limiter);
 #pragma unroll
     for (int a = 0; a < 9; ++a) out[(size_t)a * n + c] = ga[a];
 }

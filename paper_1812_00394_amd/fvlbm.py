@@ -44,7 +44,7 @@ class Params(C.Structure):
                 ("group_k", C.c_double * FVLBM_MAX_GROUPS),
                 ("group_w", C.c_double * FVLBM_MAX_GROUPS),
                 ("bface_vals", C.POINTER(C.c_double)),
-                ("jr_group", C.c_int32), ("reserved", C.c_int32),
+                ("jr_group", C.c_int32), ("limiter", C.c_int32),
                 ("jr_xmin", C.c_double), ("eps_tau", C.c_double)]
 
 
@@ -55,7 +55,7 @@ EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlb
            "fvlbm_moments", "fvlbm_get_f", "fvlbm_forces", "fvlbm_apply_advection", "fvlbm_state_destroy",
            "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read",
            "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
-           "fvlbm_adjoint_state"]
+           "fvlbm_adjoint_state", "fvlbm_lift_drag"]
 KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst"]
 
 
@@ -84,6 +84,7 @@ def lib():
     L.fvlbm_moments.argtypes = [P, I32, P, P, P, P, P, P]
     L.fvlbm_get_f.argtypes = [P, I32, P]
     L.fvlbm_forces.argtypes = [P, C.c_uint64, P, P]
+    L.fvlbm_lift_drag.argtypes = [P, C.c_uint64, C.c_double, C.c_double, P]
     L.fvlbm_apply_advection.argtypes = [P, P, P]
     L.fvlbm_mesh_max_dt.argtypes = [P, P]
     L.fvlbm_timing.argtypes = [P, I32]
@@ -200,6 +201,7 @@ def make_params(p, n_groups, n_bfaces=None):
         keep = _f64(bv, (n_bfaces, 5))
         s.bface_vals = keep.ctypes.data_as(C.POINTER(C.c_double))
     s.jr_group = int(p.get("jr_group", -1))
+    s.limiter = int(p.get("limiter", 0))
     s.jr_xmin = float(p.get("jr_xmin", 0.0))
     s.eps_tau = float(p.get("eps_tau", 1.0))
     return s, keep
@@ -265,6 +267,12 @@ class State:
         jr = C.c_double()
         _check(lib().fvlbm_forces(self.handle, C.c_uint64(group_mask), _ptr(F), C.byref(jr)))
         return F, jr.value
+
+    def lift_drag(self, group_mask, u_ref, chord=1.0):
+        """(C_l, C_d) of the walls in group_mask: drag along the free stream (theta), lift normal to it."""
+        c = np.zeros(2)
+        _check(lib().fvlbm_lift_drag(self.handle, C.c_uint64(group_mask), float(u_ref), float(chord), _ptr(c)))
+        return float(c[0]), float(c[1])
 
     def apply_advection(self, g):
         n = self.mesh.n_cells

@@ -600,3 +600,72 @@ def test_complex_step_of_state_matches_central_differences():
     for c, pl, mi in ((fc, fp, fm), (kc, kp, km), (wc, wp, wm)):
         fd = (pl - mi) / (2 * eps)
         assert np.abs(np.imag(c) / 1e-30 - fd).max() <= 1e-4 * np.abs(fd).max()
+
+
+# ------------------------------------------------------------------------------------------------
+# Optional face-value limiter (a reading: the paper leaves the reconstruction to Part I).  An
+# interior face value is kept between the values of the two cells that share the edge.
+# ------------------------------------------------------------------------------------------------
+def test_limiter_inactive_for_linear_field_on_orthogonal_mesh():
+    """On a uniform orthogonal mesh the face midpoint value of a linear field is the mean of the two
+    cell values, strictly inside their range: between cells whose LSQ gradients are exact (no
+    boundary edge, whose ghost state does not follow the field) the limited and unlimited face
+    values coincide."""
+    m = mg.rectangle(8, 6, Lx=1.3, kind="duct", jitter=0.0, split="none")
+    p = O.default_params(nu=1e-3, dt=1e-2, group_u=[[0.03, 0.0], [0, 0], [0.03, 0.0]])
+    o0 = O.Oracle(m, p)
+    o1 = O.Oracle(m, dict(p, limiter=1))
+    G = o0.g
+    x, y = G.xc[:, 0], G.xc[:, 1]
+    g = O.feq(1.0, 0.02, 0.01)[:, None] + (0.3 + 0.1 * np.arange(9))[:, None] * 1e-3 * (x - 0.4 * y)[None, :]
+    _, f0 = o0.face_values(g)
+    _, f1 = o1.face_values(g)
+    has_bnd = np.zeros(G.n, bool)
+    has_bnd[G.cell[~G.interior]] = True
+    inner = np.nonzero(G.interior & ~has_bnd[G.cell] & ~has_bnd[np.maximum(G.nbr, 0)])[0]
+    assert len(inner) > 40
+    np.testing.assert_allclose(f1[:, inner], f0[:, inner], rtol=0, atol=1e-16)
+    # the mean of the two cell values, as a linear profile gives at the shared edge's midpoint
+    np.testing.assert_allclose(f0[1:, inner], 0.5 * (g[1:, G.cell[inner]] + g[1:, G.nbr[inner]]), rtol=0, atol=1e-15)
+
+
+def test_limiter_keeps_face_values_between_the_two_cells():
+    m = mg.cavity(n=12, jitter=0.2, seed=71)
+    p = O.default_params(nu=1e-3, dt=1e-2, group_u=[[0, 0], [0.1, 0]])
+    rng = np.random.default_rng(72)
+    g = O.feq(1.0, 0.0, 0.0)[:, None] * (1 + 0.05 * rng.standard_normal((9, len(m["cell_ptr"]) - 1)))
+    for lim in (0, 1):
+        orc = O.Oracle(m, dict(p, limiter=lim))
+        G = orc.g
+        _, face = orc.face_values(g)
+        inner = np.nonzero(G.interior)[0]
+        a, b = g[:, G.cell[inner]], g[:, G.nbr[inner]]
+        v = face[:, inner]
+        outside = (v < np.minimum(a, b) - 1e-15) | (v > np.maximum(a, b) + 1e-15)
+        if lim:
+            assert not outside.any()
+        else:
+            assert outside.mean() > 0.05     # the random field makes the plain reconstruction overshoot
+
+
+def test_limiter_removes_the_overshoot_next_to_a_step():
+    """Next to a step profile the cells' LSQ gradients point across the step, so the linear
+    reconstruction overshoots on the faces between two equal cells; the limited value there is
+    exactly the two cells' common value."""
+    m = mg.rectangle(10, 4, Lx=1.0, kind="duct", jitter=0.0, split="none")
+    p = O.default_params(nu=1e-3, dt=1e-2, group_u=[[0.0, 0.0], [0, 0], [0.0, 0.0]])
+    g = None
+    for lim in (0, 1):
+        orc = O.Oracle(m, dict(p, limiter=lim))
+        G = orc.g
+        if g is None:
+            g = np.tile(O.WT[:, None], (1, G.n)) * np.where(G.xc[:, 0] < 0.5, 1.02, 1.0)[None, :]
+        _, face = orc.face_values(g)
+        inner = np.nonzero(G.interior)[0]
+        a, b = g[:, G.cell[inner]], g[:, G.nbr[inner]]
+        equal = np.abs(a - b) < 1e-15
+        dev = np.abs(face[:, inner] - a)[equal]
+        if lim:
+            assert dev.max() == 0.0
+        else:
+            assert dev.max() > 1e-5
