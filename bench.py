@@ -204,10 +204,46 @@ def cpu_baseline(mesh_sample_points, steps):
     return n, steps, dt, cores
 
 
+def airfoil_run(F, steps):
+    """The airfoil workload: 512 x 384 O-mesh (196,608 quads) around the sharp-trailing-edge 12 %
+    section, Re 6e6 on the chord, 10 degrees incidence, u_inf = 0.05, dt = 0.9 of the advective
+    Courant limit, developed near-wall start, face-value limiter on; lift and drag after `steps`
+    steps in FP32-dev and FP64, and the throughput of both."""
+    import torch
+    from paper_1812_00394_amd import meshgen as mg
+    M = F.Mesh(mg.naca_omesh())
+    n = M.n_cells
+    _, _, wd = M.geometry()
+    U, c, Re, alpha = 0.05, 1.0, 6e6, np.deg2rad(10.0)
+    nu = U * c / Re
+    kinf, winf = 1e-3 * U * U / Re, 5 * U / c
+    p = dict(nu=nu, dt=min(180 * 3 * nu, 0.9 * M.max_dt()), sst=True, theta=alpha, limiter=1,
+             group_u=[[0, 0], [U, 0]], group_rho=[1, 1], group_k=[0, kinf], group_w=[0, winf])
+    fac = np.minimum(1.0, (wd / 0.01) ** (1 / 7))
+    u0 = np.stack([U * np.cos(alpha) * fac, U * np.sin(alpha) * fac], axis=1)
+    w0 = np.maximum(winf, 6 * nu / (0.075 * wd ** 2))
+    out = {"cells": n, "steps": steps, "dt_over_tau0": round(p["dt"] / (3 * nu), 2), "limiter": 1}
+    for prec in ("fp32dev", "fp64"):
+        st = F.State(M, p, precision=prec, rho=np.ones(n), u=u0, k=np.full(n, kinf), omega=w0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st.step(steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        cl, cd = st.lift_drag(1, U, c)
+        out[prec] = {"cl": cl, "cd": cd, "mlups": round(n * steps / dt / 1e6, 1)}
+        del st
+    out["rel_diff_cl"] = abs(out["fp32dev"]["cl"] - out["fp64"]["cl"]) / abs(out["fp64"]["cl"])
+    out["rel_diff_cd"] = abs(out["fp32dev"]["cd"] - out["fp64"]["cd"]) / abs(out["fp64"]["cd"])
+    log(f"airfoil {steps} steps: Cl {out['fp64']['cl']:.6g} / {out['fp32dev']['cl']:.6g}, "
+        f"Cd {out['fp64']['cd']:.6g} / {out['fp32dev']['cd']:.6g} (FP64 / FP32-dev)")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="delaunay4m")
     ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
@@ -217,6 +253,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--adjoint-steps", type=int, default=50, help="recorded steps of the adjoint timing (0: skip)")
     ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the adjoint")
+    ap.add_argument("--airfoil-steps", type=int, default=3000,
+                    help="steps of the airfoil run (lift and drag in FP32-dev and FP64; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for rocprof byte counters)")
     args = ap.parse_args()
@@ -311,6 +349,8 @@ def main():
         log(f"adjoint of {args.adjoint_steps} steps: {t_adj:.3f}s vs forward {t_fwd:.3f}s (ratio {t_adj / t_fwd:.2f})")
         del sta
 
+    airfoil = airfoil_run(F, args.airfoil_steps) if args.airfoil_steps > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         cn, csteps, cdt, ccores = cpu_baseline(args.cpu_sample_points, args.cpu_steps)
@@ -348,6 +388,7 @@ def main():
         "kernels": per_kernel,
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
+        "airfoil_lift_drag": airfoil,
         "cpu_baseline": cpu,
         "kernel_source_sha256": source_hash(),
     }
