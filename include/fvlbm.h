@@ -226,8 +226,10 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   checkpoint every ckpt_every steps: checkpoints (11 n values each), one segment of states
  *   (ckpt_every + 1 of 11 n values) and of stage data (43 n values per step), adjoint fields.
  * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
- *   (f, k, omega) every ckpt_every steps and at the end in `workspace` (device memory owned by the
- *   caller, 256-byte aligned, kept alive until the adjoint has run).
+ *   (f, k, omega) at the start of every segment and at the end in `workspace` (device memory owned
+ *   by the caller, 256-byte aligned, kept alive until the adjoint has run).  Segments have at most
+ *   ckpt_every steps and are counted from the end of the run (only the first may be shorter); the
+ *   last one is kept whole, with its stage data, so that the reverse starts without recomputing it.
  * fvlbm_adjoint_step: for J = seed[0] F_x + seed[1] F_y + seed[2] J_R of the final state (forces of
  *   the walls in wall_group_mask and the reversed-flow length, as fvlbm_forces), returns
  *   dparams = dJ/d(theta, sigma_k1, sigma_omega1, beta*, a1) in FP64, differentiating the discrete

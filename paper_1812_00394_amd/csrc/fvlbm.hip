@@ -800,22 +800,35 @@ void step_seg(fvlbm_state *st, const AdjLayout<T> &L, int j) {
     st->want_aux = false;
 }
 
-// Advances the recorded run, storing a checkpoint every C steps and the final state.  The last
-// segment is run through the segment buffers, so that the reverse starts without recomputing it.
+// Segments of a recorded run of N steps with at most C steps each, placed from the end: segment sg
+// (of nseg = ceil(N / C)) covers steps [first, last); only the first may be shorter than C.
+inline void segment_bounds(int N, int C, int sg, int &first, int &last) {
+    const int nseg = (N + C - 1) / C;
+    last = N - (nseg - 1 - sg) * C;
+    first = std::max(0, last - C);
+}
+
+// Advances the recorded run, storing a checkpoint at the start of every segment and the final
+// state.  The last segment is run through the segment buffers, so that the reverse starts without
+// recomputing it.
 template <typename T>
 void record(fvlbm_state *st) {
     AdjLayout<T> L = adj_layout<T>(st);
     const int N = st->rec_steps, C = st->rec_ckpt;
-    const int first_last = ((N - 1) / C) * C;
-    for (int32_t i = 0; i < first_last; ++i) {
-        if (i % C == 0) save_state<T>(st, L.ckpt + (size_t)(i / C) * L.state_len);
-        launch_step<T>(st);
+    const int nseg = (N + C - 1) / C;
+    for (int sg = 0; sg < nseg - 1; ++sg) {
+        int first, last;
+        segment_bounds(N, C, sg, first, last);
+        save_state<T>(st, L.ckpt + (size_t)sg * L.state_len);
+        for (int i = first; i < last; ++i) launch_step<T>(st);
     }
-    save_state<T>(st, L.ckpt + (size_t)(first_last / C) * L.state_len);
+    int first_last, last_last;
+    segment_bounds(N, C, nseg - 1, first_last, last_last);
+    save_state<T>(st, L.ckpt + (size_t)(nseg - 1) * L.state_len);
     save_state<T>(st, L.seg);
     for (int32_t i = first_last; i < N; ++i) step_seg<T>(st, L, i - first_last);
     load_state<T>(st, L.seg + (size_t)(N - first_last) * L.state_len);
-    const size_t nck = (size_t)((N + C - 1) / C);
+    const size_t nck = (size_t)nseg;
     save_state<T>(st, L.ckpt + nck * L.state_len);
     st->last_seg_valid = true;
     st->steps_done += N;
@@ -877,7 +890,8 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
     const int nseg = (N + C - 1) / C;
     const size_t n = st->n_cells;
     for (int sg = nseg - 1; sg >= 0; --sg) {
-        const int first = sg * C, last = std::min(N, first + C);
+        int first, last;
+        segment_bounds(N, C, sg, first, last);
         if (!(sg == nseg - 1 && st->last_seg_valid)) {
             st->last_seg_valid = false;
             check(hipMemcpyAsync(L.seg, L.ckpt + (size_t)sg * L.state_len, L.state_len * sizeof(T), hipMemcpyDeviceToDevice,
