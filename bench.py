@@ -204,6 +204,44 @@ def cpu_baseline(mesh_sample_points, steps):
     return n, steps, dt, cores
 
 
+def imex_vs_explicit(F, M_big, flow_big, init_big, dt_frac_big):
+    """Per-step cost of the IMEX scheme against the explicit scheme it is compared with (forward
+    Euler, dt < 2 tau; per-step cost does not depend on dt): on the 4,608-cell cavity (laminar,
+    FP64, launch-bound) and on the benchmark mesh (SST, FP32-dev)."""
+    import torch
+    from paper_1812_00394_amd import meshgen as mg
+
+    def timed(fn, steps):
+        fn(3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(steps)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps * 1e3
+
+    out = {}
+    cav = F.Mesh(mg.cavity())
+    nu = 0.1 / 1000
+    n = cav.n_cells
+    for name, dt in (("imex", 10 * 3 * nu), ("explicit", 3 * nu)):
+        st = F.State(cav, dict(nu=nu, dt=dt, group_u=[[0, 0], [0.1, 0]]), precision="fp64", rho=np.ones(n),
+                     u=np.zeros((n, 2)))
+        out.setdefault("cavity_4608_fp64", {})[name + "_ms"] = round(timed(st.step if name == "imex" else st.step_explicit, 300), 4)
+        del st
+    for name in ("imex", "explicit"):
+        if name == "imex":
+            st, p = make_state(F, M_big, flow_big, init_big, "fp32dev", dt_frac_big)
+        else:   # a stable step for the explicit scheme: dt = tau0
+            st, p = make_state(F, M_big, dict(flow_big, dt=3 * flow_big["nu"]), init_big, "fp32dev", None)
+        fn = st.step if name == "imex" else st.step_explicit
+        out.setdefault("delaunay4m_fp32dev", {})[name + "_ms"] = round(timed(fn, 50), 4)
+        del st
+    for v in out.values():
+        v["ratio"] = round(v["imex_ms"] / v["explicit_ms"], 3)
+    log(f"IMEX / explicit per step: {out}")
+    return out
+
+
 def airfoil_run(F, steps):
     """The airfoil workload: 512 x 384 O-mesh (196,608 quads) around the sharp-trailing-edge 12 %
     section, Re 6e6 on the chord, 10 degrees incidence, u_inf = 0.05, dt = 0.9 of the advective
@@ -253,6 +291,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--adjoint-steps", type=int, default=50, help="recorded steps of the adjoint timing (0: skip)")
     ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the adjoint")
+    ap.add_argument("--no-explicit", action="store_true", help="skip the IMEX / explicit cost comparison")
     ap.add_argument("--airfoil-steps", type=int, default=3000,
                     help="steps of the airfoil run (lift and drag in FP32-dev and FP64; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -350,6 +389,7 @@ def main():
         del sta
 
     airfoil = airfoil_run(F, args.airfoil_steps) if args.airfoil_steps > 0 else None
+    cost_ratio = None if args.no_explicit else imex_vs_explicit(F, M, flow, init, dt_frac)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -389,6 +429,7 @@ def main():
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
         "airfoil_lift_drag": airfoil,
+        "imex_over_explicit_per_step": cost_ratio,
         "cpu_baseline": cpu,
         "kernel_source_sha256": source_hash(),
     }

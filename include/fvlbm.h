@@ -157,6 +157,15 @@ fvlbm_status fvlbm_set_state(fvlbm_state *st, const double *f, const double *k, 
 fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *residual);
 
 /*
+ * Advance n_steps steps of the explicit scheme the paper compares the IMEX scheme with (Section
+ * 3.1): forward Euler of the semi-discrete equation, Eq. (semibgk), f^{n+1} = f^n + dt (Ga(f^n) +
+ * (f_eq(f^n) - f^n) / tau), with the SST update first as in fvlbm_step.  Stable for dt < 2 tau
+ * only (the caller's choice).  Needs the ring-tiled sweep (FVLBM_ESTATE otherwise); residual as
+ * fvlbm_step.
+ */
+fvlbm_status fvlbm_step_explicit(fvlbm_state *st, int32_t n_steps, double *residual);
+
+/*
  * Macro fields (Step 7) in FP64, user order.  on_device = 0: host pointers (synchronises);
  * 1: device pointers (asynchronous).  Any field pointer may be NULL.  rho [n], u [n][2],
  * k, omega, nu_t [n] (FVLBM_ESTATE if asked of a laminar state).  totals (host, may be NULL):
@@ -206,7 +215,8 @@ enum {
     FVLBM_K_SWEEP2 = 5,    /* stage-2 convection + stage-3 collision */
     FVLBM_K_SWEEP3 = 6,    /* stage-3 convection + combination + macro update */
     FVLBM_K_SST = 7,       /* SST in one ring-tiled launch (replaces SST_A + SST_B) */
-    FVLBM_K_COUNT = 8
+    FVLBM_K_EXPLICIT = 8,  /* convection + collision of the explicit scheme */
+    FVLBM_K_COUNT = 9
 };
 fvlbm_status fvlbm_timing(fvlbm_state *st, int32_t enable);
 fvlbm_status fvlbm_timing_read(fvlbm_state *st, double ms[FVLBM_K_COUNT], int64_t launches[FVLBM_K_COUNT]);

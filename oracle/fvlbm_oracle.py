@@ -516,6 +516,28 @@ class Oracle:
         return fn1
 
     # ---------------------------------------------------------------------------------------
+    # The explicit scheme the paper compares the IMEX scheme with (Section 3.1): forward Euler of
+    # the semi-discrete equation (Eq. (semibgk)), f^{n+1} = f^n + dt (Ga(f^n) + Gc(f^n)), stable
+    # for dt < 2 tau only.
+    # ---------------------------------------------------------------------------------------
+    def explicit_step(self, f, tau):
+        dt = self.p["dt"]
+        rho, jx, jy = moments(f)
+        Gc = (feq(rho, jx / rho, jy / rho) - f) / tau           # Eq. (collision)
+        return f + dt * (self.advection(f) + Gc)                # Eq. (advection)
+
+    def step_explicit(self, f, k=None, w=None):
+        """One explicit step, with the SST update first as in the IMEX step."""
+        rho, jx, jy = moments(f)
+        if self.p["sst"]:
+            k, w, nut, tau = self.sst_update(rho, jx / rho, jy / rho, k, w)
+        else:
+            tau = self.tau_laminar()
+            nut = np.zeros(self.g.n)
+        self.last_tau, self.last_nut = tau, nut
+        return self.explicit_step(f, tau), k, w
+
+    # ---------------------------------------------------------------------------------------
     # Step 0 .. Step 7 of the algorithm at the end of Section 3.2 (SST once per step, r12).
     # ---------------------------------------------------------------------------------------
     def init_state(self, rho, ux, uy, k=None, w=None):

@@ -441,6 +441,43 @@ void launch_step(fvlbm_state *st) {
     check(hipGetLastError(), "kernel launch");
 }
 
+// One step of the explicit scheme (the SST first, as in launch_step), ring path only: f^{n+1} goes
+// to the X buffer, which then becomes F.
+template <typename T>
+void launch_explicit(fvlbm_state *st) {
+    if (!st->ring) throw Error(FVLBM_ESTATE, "explicit step: needs the ring-tiled sweep (FVLBM_SWEEP unset or ring)");
+    const Geo<T> &g = geo_of<T>(st);
+    hipStream_t s = st->stream;
+    StepPar<T> p = step_par<T>(st->par);
+    T *F = (T *)st->F, *X = (T *)st->X, *tau = (T *)st->tau;
+    T *Mcur = (T *)st->M[st->cur_m], *Mnew = (T *)st->M[st->cur_m ^ 1];
+    const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+    if (st->sst) {
+        T *K0 = (T *)st->K[st->cur_kw], *W0 = (T *)st->W[st->cur_kw];
+        T *K1 = (T *)st->K[st->cur_kw ^ 1], *W1 = (T *)st->W[st->cur_kw ^ 1];
+        const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+        Timed t(st, FVLBM_K_SST);
+        if (st->ring_s == 3)
+            k_sst_ring<T, 3, false><<<nt, kTileCells, st->sst_lds_bytes, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0,
+                                                                          (T *)st->aux, K1, W1, tau, (T *)st->nut, p);
+        else
+            k_sst_ring<T, 4, false><<<nt, kTileCells, st->sst_lds_bytes, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0,
+                                                                          (T *)st->aux, K1, W1, tau, (T *)st->nut, p);
+        st->cur_kw ^= 1;
+    }
+    const StageBufs<T> b0{F, nullptr, tau, nullptr, nullptr, X, Mnew};
+    {
+        Timed t(st, FVLBM_K_EXPLICIT);
+        if (st->ring_s == 3)
+            k_stage_ring<T, 0, 3><<<st->mesh->n_tiles, kTileCells, st->lds_bytes, s>>>(g, rt, st->lnb, st->ring_wv, st->ring_wg, b0, p);
+        else
+            k_stage_ring<T, 0, 4><<<st->mesh->n_tiles, kTileCells, st->lds_bytes, s>>>(g, rt, st->lnb, st->ring_wv, st->ring_wg, b0, p);
+    }
+    std::swap(st->F, st->X);
+    st->cur_m ^= 1;
+    check(hipGetLastError(), "kernel launch");
+}
+
 template <typename T>
 double residual(fvlbm_state *st) {
     const int n = st->n_cells;
@@ -1130,6 +1167,26 @@ fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *res) {
             const double r = st->precision == FVLBM_FP64 ? residual<double>(st) : residual<float>(st);
             *res = r;
             if (!std::isfinite(r)) throw Error(FVLBM_EDIVERGED, "step: non-finite velocity residual");
+        }
+    });
+}
+
+fvlbm_status fvlbm_step_explicit(fvlbm_state *st, int32_t n_steps, double *res) {
+    return guarded([&] {
+        if (!st) throw Error(FVLBM_EINVAL, "step_explicit: NULL state");
+        if (n_steps < 0) throw Error(FVLBM_EINVAL, "step_explicit: n_steps < 0");
+        for (int32_t i = 0; i < n_steps; ++i) {
+            if (st->precision == FVLBM_FP64)
+                launch_explicit<double>(st);
+            else
+                launch_explicit<float>(st);
+            if (st->timing && st->events.size() > 4096) drain_events(st);
+        }
+        st->steps_done += n_steps;
+        if (res) {
+            const double r = st->precision == FVLBM_FP64 ? residual<double>(st) : residual<float>(st);
+            *res = r;
+            if (!std::isfinite(r)) throw Error(FVLBM_EDIVERGED, "step_explicit: non-finite velocity residual");
         }
     });
 }

@@ -211,7 +211,8 @@ struct StageBufs {
 
 template <typename T, int J>
 __device__ __forceinline__ void load_ops(const StageBufs<T> &b, int c, int n, EpiOps<T> &o) {
-    if constexpr (J <= 2) {
+    if constexpr (J == 0) o.tc = b.tau[c];
+    if constexpr (J == 1 || J == 2) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) o.fn[a] = b.F_in[(size_t)a * n + c];
         o.tc = b.tau[c];
@@ -291,10 +292,31 @@ __device__ __forceinline__ void epilogue3(int c, int n, const T ga3[9], const Ep
     M[(size_t)2 * n + c] = uy;
 }
 
+// The explicit scheme (forward Euler of Eq. (semibgk)): f^{n+1} = f^n + dt (Ga + (f_eq - f^n) / tau)
+// from the convection term Ga of f^n = gc; stores f^{n+1} and its macro variables.
+template <typename T>
+__device__ __forceinline__ void epilogue_explicit(int c, int n, const T gc[9], const T ga[9], const EpiOps<T> &o,
+                                                  T *__restrict__ F, T *__restrict__ M, const StepPar<T> &p) {
+    T drho, rho, ux, uy, fnew[9];
+    moments(gc, p.rho0, drho, rho, ux, uy);
+    const T itau = T(1) / o.tc;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        fnew[a] = gc[a] + p.dt * (ga[a] + (dfeq(a, drho, rho, ux, uy) - gc[a]) * itau);
+        F[(size_t)a * n + c] = fnew[a];
+    }
+    moments(fnew, p.rho0, drho, rho, ux, uy);
+    M[c] = drho;
+    M[(size_t)n + c] = ux;
+    M[(size_t)2 * n + c] = uy;
+}
+
 template <typename T, int J>
 __device__ __forceinline__ void stage_epilogue_ops(int c, int n, const T gc[9], const T ga[9], const EpiOps<T> &o,
                                                    const StageBufs<T> &b, const StepPar<T> &p) {
-    if constexpr (J == 1)
+    if constexpr (J == 0)
+        epilogue_explicit(c, n, gc, ga, o, b.F_out, b.M, p);
+    else if constexpr (J == 1)
         epilogue1(c, n, ga, o, b.out, b.A, p);
     else if constexpr (J == 2)
         epilogue2(c, n, gc, ga, o, b.out, b.A, p);
@@ -463,6 +485,7 @@ __global__ void __launch_bounds__(kTileCells + kHaloThreads)
 //   phase 2: the convection term of tile cell t (Eq. (advection)) with each upwind neighbour's
 //            value and gradient from LDS, then the stage epilogue.
 // Stage 1 takes f^(1) = stage solve of f^n (a = dt/(4 tau)) on the fly, for tile and ext cells.
+// J = 0 is the explicit scheme: src = f^n, forward-Euler epilogue.
 // LDS: V [8][Wv] values (Wv = kTileCells + largest extended halo), Gl [16][Wg] gradients
 // (Wg = kTileCells + largest ring 1); tile cell t is column t, ext entry j column kTileCells + j.
 // S = edges per cell of the mesh (3: triangles only; 4 otherwise).

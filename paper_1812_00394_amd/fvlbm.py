@@ -55,8 +55,8 @@ EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlb
            "fvlbm_moments", "fvlbm_get_f", "fvlbm_forces", "fvlbm_apply_advection", "fvlbm_state_destroy",
            "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read",
            "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
-           "fvlbm_adjoint_state", "fvlbm_lift_drag"]
-KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst"]
+           "fvlbm_adjoint_state", "fvlbm_lift_drag", "fvlbm_step_explicit"]
+KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit"]
 
 
 def lib():
@@ -81,6 +81,7 @@ def lib():
     L.fvlbm_init.argtypes = [P, C.POINTER(Params), I32, P, P, P, P, P, C.c_size_t, P, C.POINTER(C.c_void_p)]
     L.fvlbm_set_state.argtypes = [P, P, P, P]
     L.fvlbm_step.argtypes = [P, I32, P]
+    L.fvlbm_step_explicit.argtypes = [P, I32, P]
     L.fvlbm_moments.argtypes = [P, I32, P, P, P, P, P, P]
     L.fvlbm_get_f.argtypes = [P, I32, P]
     L.fvlbm_forces.argtypes = [P, C.c_uint64, P, P]
@@ -237,6 +238,12 @@ class State:
     def step(self, n_steps=1, residual=False):
         r = C.c_double()
         _check(lib().fvlbm_step(self.handle, int(n_steps), C.byref(r) if residual else None))
+        return r.value if residual else None
+
+    def step_explicit(self, n_steps=1, residual=False):
+        """n_steps of the explicit (forward Euler) scheme; stable for dt < 2 tau only."""
+        r = C.c_double()
+        _check(lib().fvlbm_step_explicit(self.handle, int(n_steps), C.byref(r) if residual else None))
         return r.value if residual else None
 
     def set_state(self, f=None, k=None, omega=None):

@@ -361,3 +361,42 @@ def test_airfoil_full_size_lift_drag_fp32_vs_fp64(F):
     print("lift, drag after 3000 steps:", out)
     (l64, d64), (l32, d32) = out["fp64"], out["fp32dev"]
     assert abs(l32 - l64) <= 1e-4 * abs(l64) and abs(d32 - d64) <= 1e-4 * abs(d64), out
+
+
+# ------------------------------------------------------------------------------------------------
+# The explicit scheme the IMEX scheme is compared with (forward Euler, dt < 2 tau).
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["cavity", "periodic", "naca"])
+def test_explicit_step_parity(F, name):
+    say("explicit step", name)
+    make, extra = MESHES[name]
+    m = make()
+    dt = courant_dt(m)
+    p = O.default_params(nu=dt / 3, dt=dt, **extra)      # dt = tau
+    orc = O.Oracle(m, p)
+    f = _random_state(orc.g.n, np.random.default_rng(45))
+    st = F.State(F.Mesh(m), p, precision="fp64")
+    st.set_state(f)
+    fo = f
+    for k, tol in ((1, 1e-12), (4, 1e-11)):
+        for _ in range(k):
+            fo, _, _ = orc.step_explicit(fo)
+        st.step_explicit(k)
+        assert rel(st.get_f(), fo, dev_scale(fo)) < tol
+
+
+def test_explicit_sst_step_parity(F):
+    say("explicit sst step, duct")
+    make, extra = SST_MESHES["duct"]
+    m = make()
+    orc, p, f, k, w = _sst_case(m, extra, 53)
+    p = dict(p, nu=p["dt"] / 3)
+    orc = O.Oracle(m, p)
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k, omega=w)
+    st.set_state(f, k, w)
+    fo, ko, wo = f, k, w
+    for _ in range(2):
+        fo, ko, wo = orc.step_explicit(fo, ko, wo)
+    st.step_explicit(2)
+    assert rel(st.get_f(), fo, dev_scale(fo)) < 1e-11
+    assert rel(st.moments()["omega"], wo, np.abs(wo).max()) < 1e-10

@@ -669,3 +669,45 @@ def test_limiter_removes_the_overshoot_next_to_a_step():
             assert dev.max() == 0.0
         else:
             assert dev.max() > 1e-5
+
+
+# ------------------------------------------------------------------------------------------------
+# The explicit (forward Euler) scheme the IMEX scheme is compared with.
+# ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("ratio", [0.5, 1.0, 1.9])
+def test_explicit_uniform_relaxation_factor(ratio):
+    """A uniform non-equilibrium perturbation on a periodic mesh (no convection) relaxes by the
+    forward-Euler factor 1 - dt / tau per step; moments are conserved exactly."""
+    m = mg.rectangle(6, 5, kind="periodic", jitter=0.2, seed=81)
+    nu = 1e-3
+    tau = 3 * nu
+    orc = O.Oracle(m, O.default_params(nu=nu, dt=ratio * tau))
+    n = orc.g.n
+    fe = O.feq(1.01, 0.03, -0.02)
+    pert = 1e-4 * np.array([0.0, 1, -1, 1, -1, 0.5, -0.5, 0.5, -0.5])   # moments 0 (1, e_x, e_y)
+    f = np.tile((fe + pert)[:, None], (1, n))
+    f1 = orc.explicit_step(f, orc.tau_laminar())
+    np.testing.assert_allclose(f1 - fe[:, None], np.broadcast_to((1 - ratio) * pert[:, None], f1.shape), rtol=0, atol=1e-16)
+
+
+def test_explicit_step_first_order_in_time():
+    """Taylor-Green decay with the explicit scheme at dt < 2 tau: the velocity decays at the
+    viscous rate; halving dt halves the deviation from the exact decay (first order)."""
+    errs = []
+    for dt_ratio in (0.4, 0.2):
+        m = mg.rectangle(24, 24, Lx=2 * np.pi, Ly=2 * np.pi, kind="periodic", jitter=0.0, split="none")
+        nu = 0.05
+        tau = 3 * nu
+        orc = O.Oracle(m, O.default_params(nu=nu, dt=dt_ratio * tau))
+        x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+        U = 0.01
+        f, _, _ = orc.init_state(np.ones(orc.g.n), U * np.sin(x) * np.cos(y), -U * np.cos(x) * np.sin(y))
+        T = 1.2
+        nsteps = int(round(T / orc.p["dt"]))
+        for _ in range(nsteps):
+            f = orc.explicit_step(f, orc.tau_laminar())
+        _, ux, _, _ = orc.macro(f)
+        amp = np.max(np.abs(ux)) / U
+        errs.append(abs(amp - np.exp(-2 * nu * nsteps * orc.p["dt"])))
+    # both schemes are within a few percent; the time error shrinks with dt
+    assert errs[0] < 0.05 and errs[1] < errs[0]
