@@ -102,13 +102,17 @@ def make_state(F, M, flow, init, precision, dt_frac):
 #   tiled: collide1 writes f^(1) (19 values with f^n and tau); sweep 1 reads f^(1) as well (37)
 #   split: as tiled, plus the 16 gradient planes each sweep reads back (grad writes them)
 def kernel_bytes(T, S, variant="ring"):
-    edge = 8 * T * S
-    ids = 6 * S if variant == "ring" else 24
-    geo = ids + edge + T
+    # ring kernels: per edge the int16 slot code and normal, midpoint offset and neighbour offset
+    # (6 values), per cell 1/area and the inverse LSQ matrix (3 values); the first-boundary-edge
+    # index is read by boundary cells only.  Split kernels: int32 ids, both ids and 8 edge values.
+    if variant == "ring":
+        geo = 2 * S + 6 * T * S + 4 * T
+    else:
+        geo = 24 + 8 * T * S + T
     extra = 16 * T if variant == "split" else 0
     return {
         # ring SST (one launch): reads rho, u, v, k, omega, writes k, omega, nu_t, tau (9 values)
-        "sst": 9 * T + 6 * S + 8 * T * S + T + 8,
+        "sst": 9 * T + 2 * S + 6 * T * S + 4 * T + 8,
         "sst_a": 15 * T + 16 + 2 * T * S + 8,
         "sst_b": 19 * T + 16 + 6 * T * S + T + 8,
         "collide1": 19 * T,

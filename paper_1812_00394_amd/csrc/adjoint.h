@@ -88,7 +88,7 @@ __device__ __forceinline__ T ghost_vjp(const Geo<T> &g, int b, T nlx, T nly, con
         }
     }
     // moments: drho = sum g, u = (sum e g) / rho
-    const T ir = T(1) / rho;
+    const T ir = recip(rho);
 #pragma unroll
     for (int i = 0; i < 9; ++i) gout[i] += r_b + (T(ex(i)) - ux) * ir * ux_b + (T(ey(i)) - uy) * ir * uy_b;
     return rot ? ubx_b * (-uby) + uby_b * ubx : T(0);
@@ -231,8 +231,8 @@ __device__ __forceinline__ void raw_moments(const T d[9], T &m0, T &mx, T &my) {
 // returns a_bar.  f: the stage result, mom: the moments of rhs (= those of f).
 template <typename T>
 __device__ __forceinline__ T collide_vjp(const T f[9], T m0, T mx, T my, T a, T rho0, const T fbar[9], T out[9]) {
-    const T inv = T(1) / (T(1) + a);
-    const T rho = rho0 + m0, ux = mx / rho, uy = my / rho;
+    const T inv = recip(T(1) + a);
+    const T rho = rho0 + m0, irho = recip(rho), ux = mx * irho, uy = my * irho;
     T lam[9], mb[3], abar = 0;
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
@@ -275,15 +275,15 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
     }
     {
         T fe[9];
-        stage_collide(fn, dt / (T(4) * tc), p.rho0, f1, fe);   // f^(1)
+        stage_collide(fn, dt * T(0.25) * recip(tc), p.rho0, f1, fe);   // f^(1)
     }
     // Q = f3 - dt/6 (Ga1 + Ga2)
     T lg12[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) lg12[a] = -dt / T(6) * lq[a];
+    for (int a = 0; a < 9; ++a) lg12[a] = -dt * T(1.0 / 6.0) * lq[a];
     // f3 = (rhs3 + a3 f_eq(m3)) / (1 + a3), m3 = m(f^n) + dt/2 m(Ga1 + Ga2), Ga1 + Ga2 = 6 (f3 - Q) / dt
-    const T a3 = dt / (T(3) * tc);
-    const T inv3 = T(1) / (T(1) + a3);
+    const T a3 = dt * T(1.0 / 3.0) * recip(tc);
+    const T inv3 = recip(T(1) + a3);
     T m0 = 0, mx = 0, my = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -292,7 +292,7 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
         mx += T(ex(a)) * mv;
         my += T(ey(a)) * mv;
     }
-    const T rho3 = p.rho0 + m0, ux3 = mx / rho3, uy3 = my / rho3;
+    const T rho3 = p.rho0 + m0, ir3 = recip(rho3), ux3 = mx * ir3, uy3 = my * ir3;
     T lrhs[9], lfe[9], mb[3], abar = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -300,7 +300,7 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
         lfe[a] = a3 * inv3 * l3[a];
         abar += l3[a] * (dfeq(a, m0, rho3, ux3, uy3) - f3[a]) * inv3;
     }
-    T ltau = -abar * a3 / tc;
+    T ltau = -abar * a3 * recip(tc);
     feq_vjp(m0, mx, my, p.rho0, lfe, mb);
     T lfn[9];
 #pragma unroll
@@ -310,15 +310,15 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
         lg12[a] += dt * T(0.5) * (mt + lrhs[a]);
     }
     // rhs3 = f^n + dt/2 (Ga1 + Ga2) + dt/3 (Gc1 + Gc2)
-    const T itau = T(1) / tc;
+    const T itau = recip(tc);
     T lgc[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) lgc[a] = dt / T(3) * lrhs[a];
+    for (int a = 0; a < 9; ++a) lgc[a] = dt * T(1.0 / 3.0) * lrhs[a];
     // Gc2 = (f_eq(m(f2)) - f2) / tau
     {
         T q0, qx, qy;
         raw_moments(f2, q0, qx, qy);
-        const T r = p.rho0 + q0, vx = qx / r, vy = qy / r;
+        const T r = p.rho0 + q0, ir = recip(r), vx = qx * ir, vy = qy * ir;
         T l[9], mb2[3];
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
@@ -334,7 +334,7 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
     {
         T q0, qx, qy;
         raw_moments(fn, q0, qx, qy);
-        const T r = p.rho0 + q0, vx = qx / r, vy = qy / r;
+        const T r = p.rho0 + q0, ir = recip(r), vx = qx * ir, vy = qy * ir;
         T l[9], mb1[3];
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
@@ -372,7 +372,7 @@ __device__ __forceinline__ void adj_stage2_cell(int c, int n, const T lf2[9], co
     }
     T m0, mx, my;
     raw_moments(f2, m0, mx, my);
-    const T a2 = p.dt / (T(4) * tc);
+    const T a2 = p.dt * T(0.25) * recip(tc);
     const T abar = collide_vjp(f2, m0, mx, my, a2, p.rho0, lf2, lr);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -380,7 +380,7 @@ __device__ __forceinline__ void adj_stage2_cell(int c, int n, const T lf2[9], co
         b.lfn[i] += lr[a];
         lam_out[i] = b.lam[i] + p.dt * T(0.5) * lr[a];
     }
-    b.ltau[c] += -abar * a2 / tc;
+    b.ltau[c] += -abar * a2 * recip(tc);
 }
 
 // Reverse of the first stage f1 = solve(f^n, a1 = dt/(4 tau)) given the complete f1 adjoint lf1.
@@ -393,14 +393,14 @@ __device__ __forceinline__ void adj_stage1_cell(int c, int n, const T lf1[9], co
         fn[a] = b.fn[(size_t)a * n + c];
         lr[a] = T(0);
     }
-    stage_collide(fn, p.dt / (T(4) * tc), p.rho0, f1, fe);   // f^(1)
+    stage_collide(fn, p.dt * T(0.25) * recip(tc), p.rho0, f1, fe);   // f^(1)
     T m0, mx, my;
     raw_moments(fn, m0, mx, my);
-    const T a1 = p.dt / (T(4) * tc);
+    const T a1 = p.dt * T(0.25) * recip(tc);
     const T abar = collide_vjp(f1, m0, mx, my, a1, p.rho0, lf1, lr);
 #pragma unroll
     for (int a = 0; a < 9; ++a) b.lfn[(size_t)a * n + c] += lr[a];
-    b.ltau[c] += -abar * a1 / tc;
+    b.ltau[c] += -abar * a1 * recip(tc);
 }
 
 // The stage reverse that follows the transposed convection of stage J (EPI = J, 0: none), for cell
@@ -453,7 +453,7 @@ __global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__
     }
     if (tau1) {
         T f1[9], fe[9];
-        stage_collide(gj, a_dt / tau1[j], rho0, f1, fe);
+        stage_collide(gj, a_dt * recip(tau1[j]), rho0, f1, fe);
 #pragma unroll
         for (int a = 0; a < 9; ++a) gj[a] = f1[a];
     }
@@ -848,7 +848,7 @@ __global__ void __launch_bounds__(256) k_adj_sst_grad(Geo<T> g, SstAdj sa, const
     lk[s0] = lx[(size_t)3 * n + s0] + acc[2];
     lw[s0] = lx[(size_t)4 * n + s0] + acc[3];
     const T rho = rho0 + M[s0], ux = M[(size_t)n + s0], uy = M[(size_t)2 * n + s0];
-    const T ir = T(1) / rho;
+    const T ir = recip(rho);
 #pragma unroll
     for (int a = 0; a < 9; ++a)
         lfn[(size_t)a * n + s0] += lrho + (T(ex(a)) - ux) * ir * lu + (T(ey(a)) - uy) * ir * lv;
@@ -1058,7 +1058,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     const T lrho = lx[0], lu = lx[1] + acc[0], lv = lx[2] + acc[1];
     lk_out[c] = lx[3] + acc[2];
     lw_out[c] = lx[4] + acc[3];
-    const T ir = T(1) / xc[0], ux = xc[1], uy = xc[2];
+    const T ir = recip(xc[0]), ux = xc[1], uy = xc[2];
 #pragma unroll
     for (int a = 0; a < 9; ++a)
         lfn[(size_t)a * n + c] += lrho + (T(ex(a)) - ux) * ir * lu + (T(ey(a)) - uy) * ir * lv;

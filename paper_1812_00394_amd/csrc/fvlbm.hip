@@ -135,6 +135,8 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
     g.cy = cv.take<T>(S);
     g.area = cv.take<double>(n);
     g.inv_area = cv.take<T>(n);
+    g.mi = cv.take<T>(3 * n);
+    g.bfirst = cv.take<int32_t>(n);
     g.wdist = cv.take<double>(n);
     g.perm = cv.take<int32_t>(n);
     g.b_kind = cv.take<int32_t>(nb);
@@ -274,6 +276,12 @@ void upload_geometry(fvlbm_state *st) {
         qy[i] = m->rfy[i] - m->dy[i];
     }
     for (int64_t i = 0; i < m->n; ++i) ia[i] = 1.0 / m->area[i];
+    std::vector<T> mi(3 * (size_t)m->n);
+    for (int64_t i = 0; i < m->n; ++i) {
+        mi[i] = (T)m->mi00[i];
+        mi[m->n + i] = (T)m->mi01[i];
+        mi[2 * m->n + i] = (T)m->mi11[i];
+    }
     std::vector<std::vector<T>> conv = {as_t(m->nlx), as_t(m->nly), as_t(m->rfx), as_t(m->rfy), as_t(qx),
                                         as_t(qy),      as_t(m->cx),  as_t(m->cy),  as_t(ia)};
     h2d(const_cast<int32_t *>(g.nbr), m->nbr, s);
@@ -286,6 +294,8 @@ void upload_geometry(fvlbm_state *st) {
     h2d(const_cast<T *>(g.cx), conv[6], s);
     h2d(const_cast<T *>(g.cy), conv[7], s);
     h2d(const_cast<T *>(g.inv_area), conv[8], s);
+    h2d(const_cast<T *>(g.mi), mi, s);
+    h2d(const_cast<int32_t *>(g.bfirst), m->bfirst, s);
     h2d(const_cast<double *>(g.area), m->area, s);
     h2d(const_cast<double *>(g.wdist), m->wdist, s);
     std::vector<int32_t> perm(m->n);

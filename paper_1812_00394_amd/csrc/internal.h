@@ -49,6 +49,8 @@ struct fvlbm_mesh {
     std::vector<int32_t> nbr;
     std::vector<int8_t> rev;     // [kSlots][n]: slot of the neighbour that points back (interior slots)
     std::vector<double> nlx, nly, rfx, rfy, dx, dy, cx, cy;
+    std::vector<double> mi00, mi01, mi11;   // [n] inverse of the weighted least-squares matrix
+    std::vector<int32_t> bfirst;            // [n] first boundary edge of the cell, -1 if none
     // boundary edges (periodic ones excluded), ordered by internal owner cell then slot
     std::vector<int32_t> b_cell, b_group, b_kind;
     std::vector<int64_t> b_user;  // index into the caller's boundary-edge arrays
@@ -56,14 +58,15 @@ struct fvlbm_mesh {
     // tiles of kTile consecutive internal cells: the halo of tile t (interior neighbours of its
     // cells that lie outside it, ascending) is halo_cell[halo_ptr[t] .. halo_ptr[t+1]); lnb[s][c]
     // is the tile-local index of slot s's neighbour: c' - tile start inside the tile, kTile + its
-    // position in the halo outside it (0 for boundary / unused slots)
+    // position in the halo outside it; -1 for an unused slot, -2 - k for the cell's k-th boundary
+    // edge (edge number bfirst[c] + k)
     int32_t n_tiles = 0, halo_max = 0;
     std::vector<int32_t> halo_ptr, halo_cell;
     std::vector<int16_t> lnb;
     // extended halo of tile t: ext_cell[ext_ptr[t] .. ext_ptr[t+1]) lists ring 1 (the halo above,
     // ext_n1[t] cells) then ring 2 (interior neighbours of ring-1 cells outside the tile and ring 1,
     // ascending); ext_lnb[s][e] is the tile-local column of slot s's neighbour of ring-1 entry e
-    // (tile cells c - tile start, ext entry j kTile + j; 0 for boundary / unused slots)
+    // (tile cells c - tile start, ext entry j kTile + j; -1 unused, -2 - k the k-th boundary edge)
     int32_t ext_max = 0;
     std::vector<int32_t> ext_ptr, ext_n1, ext_cell;
     std::vector<int16_t> ext_lnb;

@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) k_collide1(int n, const T *__restrict__ F
     T fn[9], f1[9], fe[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) fn[a] = F[(size_t)a * n + c];
-    stage_collide(fn, p.dt / (T(4) * tau[c]), p.rho0, f1, fe);
+    stage_collide(fn, p.dt * T(0.25) * recip(tau[c]), p.rho0, f1, fe);
 #pragma unroll
     for (int a = 0; a < 9; ++a) X[(size_t)a * n + c] = f1[a];
 }
@@ -231,7 +231,7 @@ __device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const Epi
     const T h = p.dt * T(0.5);
 #pragma unroll
     for (int a = 0; a < 9; ++a) rhs[a] = o.fn[a] + h * ga[a];
-    stage_collide(rhs, p.dt / (T(4) * o.tc), p.rho0, f2, fe);
+    stage_collide(rhs, p.dt * T(0.25) * recip(o.tc), p.rho0, f2, fe);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         Y[(size_t)a * n + c] = f2[a];
@@ -246,11 +246,11 @@ __device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T g
                                           T *__restrict__ X, T *__restrict__ A, const StepPar<T> &p) {
     T f1[9], fe1[9], rhs[9], f3[9], gsum[9];
     const T tc = o.tc;
-    const T itau = T(1) / tc;
-    stage_collide(o.fn, p.dt / (T(4) * tc), p.rho0, f1, fe1);    // f^(1), f_eq^(1)
+    const T itau = recip(tc);
+    stage_collide(o.fn, p.dt * T(0.25) * itau, p.rho0, f1, fe1);   // f^(1), f_eq^(1)
     T drho2, rho2, ux2, uy2;
     moments(f2, p.rho0, drho2, rho2, ux2, uy2);                  // stage-2 moments
-    const T h2 = p.dt * T(0.5), h3 = p.dt / T(3);
+    const T h2 = p.dt * T(0.5), h3 = p.dt * T(1.0 / 3.0);
     // stage-3 moments from f^n and the convection terms (Eq. (sumimeximplicitnew))
     T m0 = 0, mx = 0, my = 0;
 #pragma unroll
@@ -265,8 +265,9 @@ __device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T g
         my += T(ey(a)) * mv;
     }
     const T rho3 = p.rho0 + m0;
-    stage_collide_m(rhs, p.dt / (T(3) * tc), m0, rho3, mx / rho3, my / rho3, f3);
-    const T h6 = p.dt / T(6);
+    const T ir3 = recip(rho3);
+    stage_collide_m(rhs, h3 * itau, m0, rho3, mx * ir3, my * ir3, f3);
+    const T h6 = p.dt * T(1.0 / 6.0);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         X[(size_t)a * n + c] = f3[a];
@@ -279,7 +280,7 @@ template <typename T>
 __device__ __forceinline__ void epilogue3(int c, int n, const T ga3[9], const EpiOps<T> &o, T *__restrict__ F,
                                           T *__restrict__ M, const StepPar<T> &p) {
     T fnew[9];
-    const T h3 = p.dt / T(3);
+    const T h3 = p.dt * T(1.0 / 3.0);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         fnew[a] = o.a[a] + h3 * ga3[a];
@@ -299,7 +300,7 @@ __device__ __forceinline__ void epilogue_explicit(int c, int n, const T gc[9], c
                                                   T *__restrict__ F, T *__restrict__ M, const StepPar<T> &p) {
     T drho, rho, ux, uy, fnew[9];
     moments(gc, p.rho0, drho, rho, ux, uy);
-    const T itau = T(1) / o.tc;
+    const T itau = recip(o.tc);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         fnew[a] = gc[a] + p.dt * (ga[a] + (dfeq(a, drho, rho, ux, uy) - gc[a]) * itau);
@@ -530,6 +531,31 @@ __device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int n
     }
 }
 
+// Slot codes of a cell (tile-local int16 columns: >= 0 an interior neighbour's LDS column, -1 an
+// unused slot, -2 - k the cell's k-th boundary edge) decoded into the classification the sweeps
+// use: nb >= 0 interior, -1 unused, -2 - b boundary edge b = bfirst[cell] + k.  Only cells with a
+// boundary edge read bfirst.
+template <int S>
+__device__ __forceinline__ void decode_slots(const int32_t *__restrict__ bfirst, int cell, const int col[S], int nb[S]) {
+    bool bnd = false;
+#pragma unroll
+    for (int s = 0; s < S; ++s) bnd = bnd || col[s] <= -2;
+    const int bf = bnd ? bfirst[cell] : 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) nb[s] = col[s] >= -1 ? col[s] : col[s] - bf;
+}
+
+// LSQ coefficients of one slot, (cx, cy) = w M^-1 d with d = r_f - q the centroid offset to the
+// neighbour (to the edge midpoint on a boundary edge, where q = 0), w = 1 / |d|^2 and M^-1 the
+// cell's inverse least-squares matrix (m00, m01, m11).  Zero on an unused slot.
+template <typename T>
+__device__ __forceinline__ void lsq_coef(T m00, T m01, T m11, T rx, T ry, T qx, T qy, bool used, T &cx, T &cy) {
+    const T dx = rx - qx, dy = ry - qy;
+    const T w = used ? recip(dx * dx + dy * dy) : T(0);
+    cx = w * (m00 * dx + m01 * dy);
+    cy = w * (m01 * dx + m11 * dy);
+}
+
 template <typename T, int J, int S>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_stage_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg, StageBufs<T> b,
@@ -555,7 +581,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         if constexpr (J == 1) {
             load_ops<T, 1>(b, c, n, ops);
             T fe[9];
-            stage_collide(ops.fn, p.dt / (T(4) * ops.tc), p.rho0, gc, fe);
+            stage_collide(ops.fn, p.dt * T(0.25) * recip(ops.tc), p.rho0, gc, fe);
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
@@ -564,10 +590,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const size_t si = (size_t)s * n + c;
-            nb[s] = g.nbr[si];
             col[s] = lnb[si];
-            cxs[s] = g.cx[si];
-            cys[s] = g.cy[si];
             nlx[s] = g.nlx[si];
             nly[s] = g.nly[si];
             rx[s] = g.rfx[si];
@@ -575,6 +598,10 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             qx[s] = g.qx[si];
             qy[s] = g.qy[si];
         }
+        decode_slots<S>(g.bfirst, c, col, nb);
+        const T m00 = g.mi[c], m01 = g.mi[(size_t)n + c], m11 = g.mi[(size_t)2 * n + c];
+#pragma unroll
+        for (int s = 0; s < S; ++s) lsq_coef(m00, m01, m11, rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
         ia = g.inv_area[c];
 #pragma unroll
         for (int a = 1; a < 9; ++a) V[(a - 1) * Wv + t] = gc[a];
@@ -588,7 +615,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             T hf[9], fe[9];
 #pragma unroll
             for (int a = 0; a < 9; ++a) hf[a] = b.F_in[(size_t)a * n + hc];
-            stage_collide(hf, p.dt / (T(4) * b.tau[hc]), p.rho0, hv, fe);
+            stage_collide(hf, p.dt * T(0.25) * recip(b.tau[hc]), p.rho0, hv, fe);
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a) hv[a] = b.src[(size_t)a * n + hc];
@@ -599,11 +626,11 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const size_t si = (size_t)s * n + hc;
-                hnb[s] = g.nbr[si];
                 hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
                 hcx[s] = g.cx[si];
                 hcy[s] = g.cy[si];
             }
+            decode_slots<S>(g.bfirst, hc, hcol, hnb);
         }
     }
     __syncthreads();
@@ -639,13 +666,16 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         if (nb[s] == -1) continue;
         if (nb[s] >= 0) {
             const int loc = col[s];
+            // both reconstructions, then a select: the upwind side differs from lane to lane, so
+            // a branch would run both sides anyway
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const T end = T(ex(a)) * nlx[s] + T(ey(a)) * nly[s];
-                T val = end >= T(0) ? gc[a] + gx[a] * rx[s] + gy[a] * ry[s]
-                                    : V[(a - 1) * Wv + loc] + Gl[(2 * (a - 1)) * Wg + loc] * qx[s] +
-                                          Gl[(2 * (a - 1) + 1) * Wg + loc] * qy[s];
-                if (p.limiter) val = clip_between(val, gc[a], V[(a - 1) * Wv + loc]);
+                const T vn = V[(a - 1) * Wv + loc];
+                const T up_n = vn + Gl[(2 * (a - 1)) * Wg + loc] * qx[s] + Gl[(2 * (a - 1) + 1) * Wg + loc] * qy[s];
+                const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
+                T val = end >= T(0) ? up_c : up_n;
+                if (p.limiter) val = clip_between(val, gc[a], vn);
                 acc[a] += end * val;
             }
         } else {
@@ -735,26 +765,28 @@ template <typename S, typename T>
 __device__ __forceinline__ SstLocal<S> sst_local(S rho, S k, S w, S dux, S duy, S dvx, S dvy, S dkx, S dky, S dwx,
                                                  S dwy, T d, const StepPar<T> &p, const SstParams<S> &q) {
     // C_omega_i = beta_i / beta* - sigma_omega_i kappa^2 / sqrt(beta*)
-    const S sb = ssqrt(q.bstar);
-    const S cw1 = cst<S>(p.b1) / q.bstar - q.sw1 * cst<S>(p.kappa * p.kappa) / sb;
-    const S cw2 = cst<S>(p.b2) / q.bstar - cst<S>(p.sw2 * p.kappa * p.kappa) / sb;
+    const S ib = recip(q.bstar), isb = recip(ssqrt(q.bstar));
+    const S cw1 = cst<S>(p.b1) * ib - q.sw1 * cst<S>(p.kappa * p.kappa) * isb;
+    const S cw2 = cst<S>(p.b2) * ib - cst<S>(p.sw2 * p.kappa * p.kappa) * isb;
     const S s11 = dux, s22 = dvy, s12 = cst<S>(0.5) * (duy + dvx);
     const S S2 = cst<S>(2) * (s11 * s11 + s22 * s22 + cst<S>(2) * s12 * s12);
     const S Sr = ssqrt(S2);
     const S div = dux + dvy;
     const S gkgw = dkx * dwx + dky * dwy;
-    const S CD = tmax(cst<S>(2) * rho * cst<S>(p.sw2) / w * gkgw, cst<S>(1e-20));
+    const S iw = recip(w);
+    const S CD = tmax(cst<S>(2) * rho * cst<S>(p.sw2) * iw * gkgw, cst<S>(1e-20));
     const S sk = ssqrt(k);
-    const S dd = cst<S>(d);
-    const S visc = cst<S>(500) * cst<S>(p.nu) / (w * dd * dd);
-    const S arg1 = tmin(tmax(sk / (cst<S>(0.09) * w * dd), visc), cst<S>(4) * rho * cst<S>(p.sw2) * k / (CD * dd * dd));
+    const S idd = cst<S>(recip(d)), idd2 = idd * idd;
+    const S visc = cst<S>(500) * cst<S>(p.nu) * iw * idd2;
+    const S t1 = sk * iw * idd * cst<S>(1.0 / 0.09);   // sqrt(k) / (0.09 omega d)
+    const S arg1 = tmin(tmax(t1, visc), cst<S>(4) * rho * cst<S>(p.sw2) * k * recip(CD) * idd2);
     const S a2 = arg1 * arg1;
     const S F1 = stanh(a2 * a2);
-    const S arg2 = tmax(cst<S>(2) * sk / (cst<S>(0.09) * w * dd), visc);
+    const S arg2 = tmax(cst<S>(2) * t1, visc);
     const S F2 = stanh(arg2 * arg2);
     const S den = tmax(q.a1 * w, Sr * F2);
     const S mu = rho * cst<S>(p.nu);
-    const S mut = q.a1 * rho * k / den;
+    const S mut = q.a1 * rho * k * recip(den);
     const S one = cst<S>(1);
     const S sig_k = F1 * q.sk1 + (one - F1) * cst<S>(p.sk2);
     const S sig_w = F1 * q.sw1 + (one - F1) * cst<S>(p.sw2);
@@ -763,13 +795,14 @@ __device__ __forceinline__ SstLocal<S> sst_local(S rho, S k, S w, S dux, S duy, 
     const S tt = cst<S>(2.0 / 3.0);
     const S P = mut * (S2 - tt * div * div) - tt * rho * k * div;
     // gamma rho P / mu_t without the 0/0 at k = 0: rho k / mu_t = den / a1
-    const S Pw = gam * rho * (S2 - tt * div * div) - tt * gam * rho * (den / q.a1) * div;
-    const S cross = cst<S>(2) * (one - F1) * rho * cst<S>(p.sw2) * gkgw / w;
+    const S Pw = gam * rho * (S2 - tt * div * div) - tt * gam * rho * (den * recip(q.a1)) * div;
+    const S cross = cst<S>(2) * (one - F1) * rho * cst<S>(p.sw2) * gkgw * iw;
+    const S dtr = cst<S>(p.dt) * recip(rho);
     SstLocal<S> o;
     o.Gk = mu + sig_k * mut;
     o.Gw = mu + sig_w * mut;
-    o.sk = cst<S>(p.dt) / rho * P;
-    o.sw = cst<S>(p.dt) / rho * (Pw + cross);
+    o.sk = dtr * P;
+    o.sw = dtr * (Pw + cross);
     o.beta = beta;
     o.Sr = Sr;
     return o;
@@ -788,18 +821,16 @@ template <typename S, typename T>
 __device__ __forceinline__ void sst_face(const S xc[11], const S xn[11], T nlx, T nly, T rx, T ry, T qx, T qy, S &Tk,
                                          S &Tw) {
     const S mdot = cst<S>(0.5) * ((xc[0] * xc[1] + xn[0] * xn[1]) * cst<S>(nlx) + (xc[0] * xc[2] + xn[0] * xn[2]) * cst<S>(nly));
-    S kf, wf;
-    if (sval(mdot) >= 0) {
-        kf = bound_face(xc[3] + xc[5] * cst<S>(rx) + xc[6] * cst<S>(ry), xc[3]);
-        wf = bound_face(xc[4] + xc[7] * cst<S>(rx) + xc[8] * cst<S>(ry), xc[4]);
-    } else {
-        kf = bound_face(xn[3] + xn[5] * cst<S>(qx) + xn[6] * cst<S>(qy), xn[3]);
-        wf = bound_face(xn[4] + xn[7] * cst<S>(qx) + xn[8] * cst<S>(qy), xn[4]);
-    }
+    // both upwind candidates, then a select (the upwind side differs from lane to lane)
+    const S kc = bound_face(xc[3] + xc[5] * cst<S>(rx) + xc[6] * cst<S>(ry), xc[3]);
+    const S wc = bound_face(xc[4] + xc[7] * cst<S>(rx) + xc[8] * cst<S>(ry), xc[4]);
+    const S kn = bound_face(xn[3] + xn[5] * cst<S>(qx) + xn[6] * cst<S>(qy), xn[3]);
+    const S wn = bound_face(xn[4] + xn[7] * cst<S>(qx) + xn[8] * cst<S>(qy), xn[4]);
+    const bool up_c = sval(mdot) >= 0;
+    const S kf = up_c ? kc : kn, wf = up_c ? wc : wn;
     // central two-point face gradient along the centroid line: (phi_N - phi_c) / |d| d^
     const T ddx = rx - qx, ddy = ry - qy;
-    const T dist = sqrt(ddx * ddx + ddy * ddy);
-    const T hn = (ddx * nlx + ddy * nly) / (dist * dist);
+    const T hn = (ddx * nlx + ddy * nly) * recip(ddx * ddx + ddy * ddy);
     Tk = -(mdot * kf) + cst<S>(0.5) * (xc[9] + xn[9]) * (xn[3] - xc[3]) * cst<S>(hn);
     Tw = -(mdot * wf) + cst<S>(0.5) * (xc[10] + xn[10]) * (xn[4] - xc[4]) * cst<S>(hn);
 }
@@ -834,16 +865,16 @@ template <typename S, typename T>
 __device__ __forceinline__ void sst_update(S rho, S k, S w, S net_k, S net_w, S sk, S sw, S beta, S Sr, T d,
                                            T inv_area, const StepPar<T> &p, const SstParams<S> &q, S &k1, S &w1,
                                            S &nut) {
-    const S fac = cst<S>(p.dt * inv_area) / rho;
+    const S fac = cst<S>(p.dt * inv_area) * recip(rho);
     const S zero = cst<S>(0), one = cst<S>(1), dt = cst<S>(p.dt);
-    k1 = (k + fac * net_k + tmax(sk, zero)) / (one + dt * q.bstar * w + tmax(-sk, zero) / k);
-    w1 = (w + fac * net_w + tmax(sw, zero)) / (one + dt * beta * w + tmax(-sw, zero) / w);
+    k1 = (k + fac * net_k + tmax(sk, zero)) * recip(one + dt * q.bstar * w + tmax(-sk, zero) * recip(k));
+    w1 = (w + fac * net_w + tmax(sw, zero)) * recip(one + dt * beta * w + tmax(-sw, zero) * recip(w));
     k1 = tmax(k1, cst<S>(1e-20));
     w1 = tmax(w1, cst<S>(1e-20));
-    const S dd = cst<S>(d);
-    const S arg2 = tmax(cst<S>(2) * ssqrt(k1) / (cst<S>(0.09) * w1 * dd), cst<S>(500) * cst<S>(p.nu) / (w1 * dd * dd));
+    const S iw1 = recip(w1), idd = cst<S>(recip(d));
+    const S arg2 = tmax(cst<S>(2.0 / 0.09) * ssqrt(k1) * iw1 * idd, cst<S>(500) * cst<S>(p.nu) * iw1 * idd * idd);
     const S F2 = stanh(arg2 * arg2);
-    nut = q.a1 * k1 / tmax(q.a1 * w1, Sr * F2);
+    nut = q.a1 * k1 * recip(tmax(q.a1 * w1, Sr * F2));
 }
 
 template <typename T>
@@ -1059,10 +1090,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const size_t si = (size_t)s * n + c;
-            nb[s] = g.nbr[si];
             col[s] = lnb[si];
-            cxs[s] = g.cx[si];
-            cys[s] = g.cy[si];
             nlx[s] = g.nlx[si];
             nly[s] = g.nly[si];
             rx[s] = g.rfx[si];
@@ -1070,6 +1098,10 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             qx[s] = g.qx[si];
             qy[s] = g.qy[si];
         }
+        decode_slots<S>(g.bfirst, c, col, nb);
+        const T m00 = g.mi[c], m01 = g.mi[(size_t)n + c], m11 = g.mi[(size_t)2 * n + c];
+#pragma unroll
+        for (int s = 0; s < S; ++s) lsq_coef(m00, m01, m11, rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
         dc = T(g.wdist[c]);
         ia = g.inv_area[c];
         Vv[t] = rho;
@@ -1098,11 +1130,11 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 const size_t si = (size_t)s * n + hc;
-                hnb[s] = g.nbr[si];
                 hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
                 hcx[s] = g.cx[si];
                 hcy[s] = g.cy[si];
             }
+            decode_slots<S>(g.bfirst, hc, hcol, hnb);
             hd = T(g.wdist[hc]);
         }
     }

@@ -28,6 +28,14 @@ struct ScalarBase<Dual<T, K>> {
 template <class S>
 __device__ __forceinline__ S cst(double x) { return S(typename ScalarBase<S>::type(x)); }
 
+// 1 / x.  FP32: the hardware reciprocal (v_rcp_f32, within 1 ulp), one instruction instead of the
+// correctly rounded division sequence; its error is below the FP32 rounding of the quantities it
+// scales.  FP64 and dual numbers: the division.
+template <class S>
+__device__ __forceinline__ S recip(S x) { return cst<S>(1) / x; }
+template <>
+__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Lattice velocities of Qian's D2Q9 model and their weights (a = 0 rest, 1-4 axes, 5-8 diagonals).
 __host__ __device__ constexpr int ex(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0); }
 __host__ __device__ constexpr int ey(int a) { return (a == 2 || a == 5 || a == 6) ? 1 : ((a == 4 || a == 7 || a == 8) ? -1 : 0); }
@@ -58,6 +66,8 @@ struct Geo {
     const int32_t *nbr;                                              // [4][n]
     const T *nlx, *nly, *rfx, *rfy, *qx, *qy, *cx, *cy;              // [4][n]
     const T *inv_area;                                               // [n]
+    const T *mi;                                                     // [3][n] inverse LSQ matrix: 00, 01, 11
+    const int32_t *bfirst;                                           // [n] first boundary edge, -1 if none
     const double *area, *wdist;                                      // [n]
     const int32_t *perm;                                             // [n] internal -> user
     const int32_t *b_kind, *b_cell;                                  // [nb]
@@ -87,8 +97,9 @@ __device__ __forceinline__ void moments(const S d[9], S rho0, S &drho, S &rho, S
     }
     drho = s;
     rho = rho0 + s;
-    ux = jx / rho;
-    uy = jy / rho;
+    const S r = recip(rho);
+    ux = jx * r;
+    uy = jy * r;
 }
 
 // Implicit stage of the IMEX scheme, solved explicitly: the stage moments equal those of rhs
@@ -98,7 +109,7 @@ template <typename T>
 __device__ __forceinline__ void stage_collide(const T rhs[9], T a, T rho0, T out[9], T fe[9]) {
     T drho, rho, ux, uy;
     moments(rhs, rho0, drho, rho, ux, uy);
-    T inv = T(1) / (T(1) + a);
+    const T inv = recip(T(1) + a);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         fe[q] = dfeq(q, drho, rho, ux, uy);
@@ -111,7 +122,7 @@ __device__ __forceinline__ void stage_collide(const T rhs[9], T a, T rho0, T out
 // vanish only up to rounding and would be amplified by dt / tau).
 template <typename T>
 __device__ __forceinline__ void stage_collide_m(const T rhs[9], T a, T drho, T rho, T ux, T uy, T out[9]) {
-    T inv = T(1) / (T(1) + a);
+    const T inv = recip(T(1) + a);
 #pragma unroll
     for (int q = 0; q < 9; ++q) out[q] = (rhs[q] + a * dfeq(q, drho, rho, ux, uy)) * inv;
 }

@@ -138,6 +138,13 @@ uint64_t spread_bits(uint64_t v) {  // 21 bits -> every other bit of 42
 }  // namespace
 
 // Builds the mesh; throws fvlbm::Error on invalid input.
+// Tile-local slot code of a slot with no interior neighbour: -1 unused; the k-th boundary edge of
+// the cell (in slot order) -2 - k, counting k in nbnd.
+inline int16_t slot_code(int32_t nb, int &nbnd) {
+    if (nb == -1) return -1;
+    return (int16_t)(-2 - nbnd++);
+}
+
 fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const int64_t *cell_ptr,
                        const int64_t *cell_nodes, int64_t n_bf, const int64_t *bf_nodes, const int32_t *bf_group,
                        int32_t n_groups, const int32_t *group_kind, const double *pshift, int32_t order) {
@@ -367,6 +374,7 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
     m->nbr.assign(kSlots * N, -1);
     m->rev.assign(kSlots * N, 0);
     for (auto *v : {&m->nlx, &m->nly, &m->rfx, &m->rfy, &m->dx, &m->dy, &m->cx, &m->cy}) v->assign(kSlots * N, 0.0);
+    for (auto *v : {&m->mi00, &m->mi01, &m->mi11}) v->assign(N, 0.0);
     for (int64_t i = 0; i < N; ++i) {
         int64_t u = perm[i], p0 = cell_ptr[u], nv = cell_ptr[u + 1] - p0;
         double M00 = 0, M01 = 0, M11 = 0;
@@ -413,6 +421,9 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
         double det = M00 * M11 - M01 * M01;
         if (!(det > 1e-14 * (M00 * M11))) throw Error(FVLBM_EMESH, "mesh_create: degenerate least-squares stencil");
         double i00 = M11 / det, i01 = -M01 / det, i11 = M00 / det;
+        m->mi00[i] = i00;
+        m->mi01[i] = i01;
+        m->mi11[i] = i11;
         for (int64_t k = 0; k < nv; ++k) {
             int64_t s = k * N + i;
             double w = 1.0 / (m->dx[s] * m->dx[s] + m->dy[s] * m->dy[s]);
@@ -420,6 +431,10 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
             m->cy[s] = w * (i01 * m->dx[s] + i11 * m->dy[s]);
         }
     }
+
+    // first boundary edge of each cell (its boundary edges are consecutive, in slot order)
+    m->bfirst.assign(N, -1);
+    for (size_t b = m->b_cell.size(); b-- > 0;) m->bfirst[m->b_cell[b]] = (int32_t)b;
 
     // ---- tiles and halos for the fused stage kernels ----
     m->n_tiles = (int32_t)((N + kTile - 1) / kTile);
@@ -438,10 +453,14 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
             }
         std::sort(halo.begin(), halo.end());
         halo.erase(std::unique(halo.begin(), halo.end()), halo.end());
-        for (int64_t c = lo; c < hi; ++c)
+        for (int64_t c = lo; c < hi; ++c) {
+            int nbnd = 0;
             for (int s = 0; s < kSlots; ++s) {
                 const int32_t nb = m->nbr[s * N + c];
-                if (nb < 0) continue;
+                if (nb < 0) {
+                    m->lnb[s * N + c] = slot_code(nb, nbnd);
+                    continue;
+                }
                 int64_t local;
                 if (nb >= lo && nb < hi)
                     local = nb - lo;
@@ -450,6 +469,7 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
                 if (local > 32767) throw Error(FVLBM_EMESH, "mesh_create: tile halo too large");
                 m->lnb[s * N + c] = (int16_t)local;
             }
+        }
         m->halo_ptr[t + 1] = m->halo_ptr[t] + (int32_t)halo.size();
         m->halo_max = std::max<int32_t>(m->halo_max, (int32_t)halo.size());
         m->halo_cell.insert(m->halo_cell.end(), halo.begin(), halo.end());
@@ -471,10 +491,14 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
         m->ext_max = std::max<int32_t>(m->ext_max, (int32_t)(halo.size() + ring2.size()));
         // tile-local column of each ring-1 cell's neighbours: tile cells c - lo, ext entry j kTile + j
         ext_lnb_rows.resize(m->ext_cell.size() * kSlots, 0);
-        for (size_t j = 0; j < halo.size(); ++j)
+        for (size_t j = 0; j < halo.size(); ++j) {
+            int nbnd = 0;
             for (int s = 0; s < kSlots; ++s) {
                 const int32_t nb = m->nbr[s * N + halo[j]];
-                if (nb < 0) continue;
+                if (nb < 0) {
+                    ext_lnb_rows[(e0 + j) * kSlots + s] = slot_code(nb, nbnd);
+                    continue;
+                }
                 int64_t local;
                 if (nb >= lo && nb < hi)
                     local = nb - lo;
@@ -485,6 +509,7 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
                 if (local > 32767) throw Error(FVLBM_EMESH, "mesh_create: tile halo too large");
                 ext_lnb_rows[(e0 + j) * kSlots + s] = (int16_t)local;
             }
+        }
     }
     // ring-1 neighbour columns as [kSlots][n_ext]
     {

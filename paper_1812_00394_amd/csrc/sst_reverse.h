@@ -220,8 +220,7 @@ __device__ __forceinline__ void sst_face_rev(const T xc[11], const T xn[11], T n
     const T kf = bound_face(vk, up_c ? xc[3] : xn[3]);
     const T wf = bound_face(vw, up_c ? xc[4] : xn[4]);
     const T ddx = rx - qx, ddy = ry - qy;
-    const T dist = sqrt(ddx * ddx + ddy * ddy);
-    const T hn = (ddx * nlx + ddy * nly) / (dist * dist);
+    const T hn = (ddx * nlx + ddy * nly) * recip(ddx * ddx + ddy * ddy);
     // Tk = -mdot kf + 0.5 (Gk_c + Gk_N) (k_N - k_c) hn, likewise Tw
     const T mdot_b = -lk * kf - lw * wf;
     const T kf_b = -lk * mdot, wf_b = -lw * mdot;
