@@ -368,6 +368,26 @@ void drain_events(fvlbm_state *st) {
     st->pool_used = 0;
 }
 
+// One ring-tiled stage sweep (stage J; J = 0 the explicit scheme) over all tiles; edges per cell
+// and the face-value limiter are template switches of the kernel.
+template <typename T, int J>
+void stage_ring(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, const StageBufs<T> &b, const StepPar<T> &p,
+                hipStream_t s) {
+    const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+    const size_t lds = st->lds_bytes;
+    if (st->ring_s == 3) {
+        if (p.limiter)
+            k_stage_ring<T, J, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+        else
+            k_stage_ring<T, J, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+    } else {
+        if (p.limiter)
+            k_stage_ring<T, J, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+        else
+            k_stage_ring<T, J, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+    }
+}
+
 template <typename T>
 void launch_step(fvlbm_state *st) {
     const Geo<T> &g = geo_of<T>(st);
@@ -409,18 +429,9 @@ void launch_step(fvlbm_state *st) {
     const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, st->F_out ? (T *)st->F_out : F, Mnew};
     if (st->ring) {
         // stage 1 takes f^(1) from f^n on the fly: no separate collision launch
-        const int nt = st->mesh->n_tiles;
-        const size_t lds = st->lds_bytes;
-        const int wv = st->ring_wv, wg = st->ring_wg;
-        if (st->ring_s == 3) {
-            { Timed t(st, FVLBM_K_SWEEP1); k_stage_ring<T, 1, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b1, p); }
-            { Timed t(st, FVLBM_K_SWEEP2); k_stage_ring<T, 2, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b2, p); }
-            { Timed t(st, FVLBM_K_SWEEP3); k_stage_ring<T, 3, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b3, p); }
-        } else {
-            { Timed t(st, FVLBM_K_SWEEP1); k_stage_ring<T, 1, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b1, p); }
-            { Timed t(st, FVLBM_K_SWEEP2); k_stage_ring<T, 2, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b2, p); }
-            { Timed t(st, FVLBM_K_SWEEP3); k_stage_ring<T, 3, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b3, p); }
-        }
+        { Timed t(st, FVLBM_K_SWEEP1); stage_ring<T, 1>(st, g, rt, b1, p, s); }
+        { Timed t(st, FVLBM_K_SWEEP2); stage_ring<T, 2>(st, g, rt, b2, p, s); }
+        { Timed t(st, FVLBM_K_SWEEP3); stage_ring<T, 3>(st, g, rt, b3, p, s); }
         st->cur_m ^= 1;
         check(hipGetLastError(), "kernel launch");
         return;
@@ -478,10 +489,7 @@ void launch_explicit(fvlbm_state *st) {
     const StageBufs<T> b0{F, nullptr, tau, nullptr, nullptr, X, Mnew};
     {
         Timed t(st, FVLBM_K_EXPLICIT);
-        if (st->ring_s == 3)
-            k_stage_ring<T, 0, 3><<<st->mesh->n_tiles, kTileCells, st->lds_bytes, s>>>(g, rt, st->lnb, st->ring_wv, st->ring_wg, b0, p);
-        else
-            k_stage_ring<T, 0, 4><<<st->mesh->n_tiles, kTileCells, st->lds_bytes, s>>>(g, rt, st->lnb, st->ring_wv, st->ring_wg, b0, p);
+        stage_ring<T, 0>(st, g, rt, b0, p, s);
     }
     std::swap(st->F, st->X);
     st->cur_m ^= 1;

@@ -119,6 +119,9 @@ __device__ __forceinline__ T clip_between(T v, T a, T b) {
     const T lo = a <= b ? a : b, hi = a <= b ? b : a;
     return v < lo ? lo : (v > hi ? hi : v);
 }
+// FP32: the clip is the median of the three values (one v_med3_f32)
+template <>
+__device__ __forceinline__ float clip_between<float>(float v, float a, float b) { return __builtin_amdgcn_fmed3f(v, a, b); }
 
 template <typename T, typename Nbr>
 __device__ __forceinline__ void advect_cell(const Geo<T> &g, int c, T rho0, const T gc[9], const T gxc[9], const T gyc[9],
@@ -478,17 +481,21 @@ __global__ void __launch_bounds__(kTileCells + kHaloThreads)
 // One workgroup of kTileCells threads per tile of kTileCells consecutive cells.  The tile's
 // extended halo (ring 1: the interior neighbours of its cells outside it; ring 2: the interior
 // neighbours of ring-1 cells outside tile and ring 1) is listed per tile, so every global load a
-// workgroup needs is issued in phase 0, at most one dependent step behind the tile's own loads:
-//   phase 0: thread t loads tile cell t (stage values, the epilogue operands, its edge geometry)
-//            and ext cell t (stage values; for a ring-1 cell also its LSQ coefficients and
+// workgroup needs is issued early, at most one dependent step behind the tile's own loads:
+//   phase 0: thread t loads tile cell t (stage values, its edge geometry; stage 1 also f^n and
+//            tau) and ext cell t (stage values; for a ring-1 cell also its LSQ coefficients and
 //            neighbour columns); the stage values of directions 1..8 go to LDS;
-//   phase 1: LSQ gradients of tile cell t and ring-1 cell t from the LDS values, into LDS;
+//   phase 1: LSQ gradients of ring-1 cell t and tile cell t from the LDS values, into LDS; the
+//            epilogue operands of stages 2, 3 (and of the explicit scheme) are loaded between the
+//            two, so that they are not live during phase 0 and the ring-1 gradient;
 //   phase 2: the convection term of tile cell t (Eq. (advection)) with each upwind neighbour's
 //            value and gradient from LDS, then the stage epilogue.
 // Stage 1 takes f^(1) = stage solve of f^n (a = dt/(4 tau)) on the fly, for tile and ext cells.
 // J = 0 is the explicit scheme: src = f^n, forward-Euler epilogue.
-// LDS: V [8][Wv] values (Wv = kTileCells + largest extended halo), Gl [16][Wg] gradients
-// (Wg = kTileCells + largest ring 1); tile cell t is column t, ext entry j column kTileCells + j.
+// LDS, cell-major so that a neighbour's data is a few 16-byte reads at one address: V [Wv][8]
+// values of directions 1..8 (Wv = kTileCells + largest extended halo), Gl [Wg][16] their x / y
+// gradients interleaved (Wg = kTileCells + largest ring 1); tile cell t is row t, ext entry j row
+// kTileCells + j.
 // S = edges per cell of the mesh (3: triangles only; 4 otherwise).
 struct RingTiles {
     const int32_t *ptr;    // [n_tiles + 1] offsets into cell
@@ -499,27 +506,37 @@ struct RingTiles {
 };
 
 // LSQ gradient from LDS values of a cell with edge data held in registers (nb, col, cx, cy per
-// slot; the normal of a boundary edge is read when needed).  Same summation order as grad_cell.
+// slot; the normal of a boundary edge is read when needed).  The interior edges are summed in
+// straight-line code (an edge without an interior neighbour reads row 0 with weight 0), the
+// boundary edges' ghost states after them, in a branch that only boundary cells take.
 template <typename T, int S>
 __device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int nb[S], const int col[S], const T cxs[S],
-                                          const T cys[S], const T *V, int Wv, T rho0, const T gc[9], T gx[9], T gy[9]) {
+                                          const T cys[S], const T *V, T rho0, const T gc[9], T gx[9], T gy[9]) {
     const int n = g.n;
 #pragma unroll
     for (int a = 0; a < 9; ++a) gx[a] = gy[a] = T(0);
+    bool bnd = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (nb[s] == -1) continue;
-        if (nb[s] >= 0) {
+        const bool in = nb[s] >= 0;
+        bnd = bnd || nb[s] <= -2;
+        const int r = in ? col[s] : 0;
+        const T wx = in ? cxs[s] : T(0), wy = in ? cys[s] : T(0);
 #pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                const T d = V[(a - 1) * Wv + col[s]] - gc[a];
-                gx[a] += cxs[s] * d;
-                gy[a] += cys[s] * d;
-            }
-        } else {
+        for (int a = 1; a < 9; ++a) {
+            const T d = V[r * 8 + (a - 1)] - gc[a];
+            gx[a] += wx * d;
+            gy[a] += wy * d;
+        }
+    }
+    if (bnd) {
+        T drho, rho, ux, uy;
+        moments(gc, rho0, drho, rho, ux, uy);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nb[s] > -2) continue;
             const size_t si = (size_t)s * n + cell;
-            T drho, rho, ux, uy, gb[9];
-            moments(gc, rho0, drho, rho, ux, uy);
+            T gb[9];
             ghost(g, -2 - nb[s], g.nlx[si], g.nly[si], gc, drho, rho, ux, uy, gb);
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
@@ -556,7 +573,7 @@ __device__ __forceinline__ void lsq_coef(T m00, T m01, T m11, T rx, T ry, T qx, 
     cy = w * (m01 * dx + m11 * dy);
 }
 
-template <typename T, int J, int S>
+template <typename T, int J, int S, bool LIM>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_stage_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg, StageBufs<T> b,
                  StepPar<T> p) {
@@ -585,7 +602,6 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         } else {
 #pragma unroll
             for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
-            load_ops<T, J>(b, c, n, ops);
         }
 #pragma unroll
         for (int s = 0; s < S; ++s) {
@@ -604,7 +620,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         for (int s = 0; s < S; ++s) lsq_coef(m00, m01, m11, rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
         ia = g.inv_area[c];
 #pragma unroll
-        for (int a = 1; a < 9; ++a) V[(a - 1) * Wv + t] = gc[a];
+        for (int a = 1; a < 9; ++a) V[t * 8 + (a - 1)] = gc[a];
     }
     T hv[9];
     int hc = 0, hnb[S], hcol[S];
@@ -621,7 +637,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             for (int a = 0; a < 9; ++a) hv[a] = b.src[(size_t)a * n + hc];
         }
 #pragma unroll
-        for (int a = 1; a < 9; ++a) V[(a - 1) * Wv + kTileCells + t] = hv[a];
+        for (int a = 1; a < 9; ++a) V[(kTileCells + t) * 8 + (a - 1)] = hv[a];
         if (ring1) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -638,57 +654,74 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     // ---- phase 1 ----
     if (ring1) {
         T hx[9], hy[9];
-        grad_ring<T, S>(g, hc, hnb, hcol, hcx, hcy, V, Wv, p.rho0, hv, hx, hy);
+        grad_ring<T, S>(g, hc, hnb, hcol, hcx, hcy, V, p.rho0, hv, hx, hy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[(2 * (a - 1)) * Wg + kTileCells + t] = hx[a];
-            Gl[(2 * (a - 1) + 1) * Wg + kTileCells + t] = hy[a];
+            Gl[(kTileCells + t) * 16 + 2 * (a - 1)] = hx[a];
+            Gl[(kTileCells + t) * 16 + 2 * (a - 1) + 1] = hy[a];
         }
     }
     T gx[9], gy[9];
     if (own) {
-        grad_ring<T, S>(g, c, nb, col, cxs, cys, V, Wv, p.rho0, gc, gx, gy);
+        // the epilogue operands of stages other than 1 are loaded here, after the ring-1 work:
+        // they are in flight during the gradient and the barrier without being live in phase 0
+        if constexpr (J != 1) load_ops<T, J>(b, c, n, ops);
+        grad_ring<T, S>(g, c, nb, col, cxs, cys, V, p.rho0, gc, gx, gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[(2 * (a - 1)) * Wg + t] = gx[a];
-            Gl[(2 * (a - 1) + 1) * Wg + t] = gy[a];
+            Gl[t * 16 + 2 * (a - 1)] = gx[a];
+            Gl[t * 16 + 2 * (a - 1) + 1] = gy[a];
         }
     }
     __syncthreads();
     if (!own) return;
 
-    // ---- phase 2: convection term, same summation order as advect_cell ----
+    // ---- phase 2: convection term; interior edges in straight-line code (an edge without an
+    // interior neighbour reads row 0 with a zero normal), boundary edges after them ----
     T acc[9];
 #pragma unroll
     for (int a = 1; a < 9; ++a) acc[a] = T(0);
+    bool bnd = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (nb[s] == -1) continue;
-        if (nb[s] >= 0) {
-            const int loc = col[s];
-            // both reconstructions, then a select: the upwind side differs from lane to lane, so
-            // a branch would run both sides anyway
+        const bool in = nb[s] >= 0;
+        bnd = bnd || nb[s] <= -2;
+        const int loc = in ? col[s] : 0;
+        const T mx = in ? nlx[s] : T(0), my = in ? nly[s] : T(0);
+        // both reconstructions, then a select: the upwind side differs from lane to lane
 #pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                const T end = T(ex(a)) * nlx[s] + T(ey(a)) * nly[s];
-                const T vn = V[(a - 1) * Wv + loc];
-                const T up_n = vn + Gl[(2 * (a - 1)) * Wg + loc] * qx[s] + Gl[(2 * (a - 1) + 1) * Wg + loc] * qy[s];
-                const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
-                T val = end >= T(0) ? up_c : up_n;
-                if (p.limiter) val = clip_between(val, gc[a], vn);
-                acc[a] += end * val;
-            }
-        } else {
+        for (int a = 1; a < 9; ++a) {
+            const T end = T(ex(a)) * mx + T(ey(a)) * my;
+            const T vn = V[loc * 8 + (a - 1)];
+            const T up_n = vn + Gl[loc * 16 + 2 * (a - 1)] * qx[s] + Gl[loc * 16 + 2 * (a - 1) + 1] * qy[s];
+            const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
+            T val = end >= T(0) ? up_c : up_n;
+            if constexpr (LIM) val = clip_between(val, gc[a], vn);
+            acc[a] += end * val;
+        }
+        // one edge's LDS reads in flight at a time (bounds the registers they occupy)
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (bnd) {
+        // rare: the edge data is read again and the cell's gradient taken from LDS, so that
+        // neither stays live in registers through the interior loop
+        T drho, rho, ux, uy;
+        moments(gc, p.rho0, drho, rho, ux, uy);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nb[s] > -2) continue;
             const int bi = -2 - nb[s];
-            T drho, rho, ux, uy, gb[9];
-            moments(gc, p.rho0, drho, rho, ux, uy);
-            ghost(g, bi, nlx[s], nly[s], gc, drho, rho, ux, uy, gb);
+            const size_t si = (size_t)s * n + c;
+            const T bnx = g.nlx[si], bny = g.nly[si], brx = g.rfx[si], bry = g.rfy[si];
+            T gb[9];
+            ghost(g, bi, bnx, bny, gc, drho, rho, ux, uy, gb);
             const int kind = g.b_kind[bi];
             const bool wall = (kind == kWall || kind == kMovingWall);
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
-                const T end = T(ex(a)) * nlx[s] + T(ey(a)) * nly[s];
-                const T val = (wall || end < T(0)) ? gb[a] : gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
+                const T end = T(ex(a)) * bnx + T(ey(a)) * bny;
+                const T own_f = gc[a] + Gl[t * 16 + 2 * (a - 1)] * brx + Gl[t * 16 + 2 * (a - 1) + 1] * bry;
+                const T val = (wall || end < T(0)) ? gb[a] : own_f;
                 acc[a] += end * val;
             }
         }
