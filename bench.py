@@ -92,27 +92,30 @@ def make_state(F, M, flow, init, precision, dt_frac):
 
 # Algorithmic (compulsory) bytes per cell of one launch of each kernel: every array the kernel
 # must read or write counted once (neighbour gathers counted once).  T = bytes per value of the
-# state's arithmetic type (4 FP32-deviation, 8 FP64), which is also the type of the per-edge
-# geometry the sweeps stream (nl, rf, q, c: 8 values per edge); S = mean edges per cell; 1/A one
-# value, wall distance 8 B (FP64).  Neighbour ids (4 B) and tile-local ids (2 B) per slot: the
-# ring sweep reads the S slots of the mesh, the older tiled sweeps all four.
+# state's arithmetic type (4 FP32-deviation, 8 FP64), which is also the type of the geometry the
+# sweeps stream; S = edges per cell; wall distance 8 B (FP64).
 #   ring : sweep 1 takes f^(1) from f^n and tau on the fly (no collide1 launch): reads f^n, tau,
 #          writes f^(2), Ga1 (28 values); sweep 2 reads f^(2), f^n, tau, Ga1, writes f^(3), Q (46);
 #          sweep 3 reads f^(3), Q, writes f^{n+1} and rho, u (30)
 #   tiled: collide1 writes f^(1) (19 values with f^n and tau); sweep 1 reads f^(1) as well (37)
 #   split: as tiled, plus the 16 gradient planes each sweep reads back (grad writes them)
 def kernel_bytes(T, S, variant="ring"):
-    # ring kernels: per edge the int16 slot code and normal, midpoint offset and neighbour offset
-    # (6 values), per cell 1/area and the inverse LSQ matrix (3 values); the first-boundary-edge
-    # index is read by boundary cells only.  Split kernels: int32 ids, both ids and 8 edge values.
-    if variant == "ring":
+    # ring kernels, triangles: per edge the int16 slot code and the neighbour-centroid offset q
+    # (2 values), per cell the vertex offsets from the centroid (2 vertices in FP32, 3 in FP64);
+    # normals, midpoints, area and LSQ coefficients are formed from them.  Other meshes: per edge
+    # the slot code and normal, midpoint and neighbour offsets (6 values), per cell 1/area and the
+    # inverse LSQ matrix.  The first-boundary-edge index is read by boundary cells only.  Split
+    # kernels: both int32 ids and 8 edge values per edge.
+    if variant == "ring" and S == 3:
+        geo = 2 * S + 2 * T * S + (4 if T == 4 else 6) * T
+    elif variant == "ring":
         geo = 2 * S + 6 * T * S + 4 * T
     else:
         geo = 24 + 8 * T * S + T
     extra = 16 * T if variant == "split" else 0
     return {
         # ring SST (one launch): reads rho, u, v, k, omega, writes k, omega, nu_t, tau (9 values)
-        "sst": 9 * T + 2 * S + 6 * T * S + 4 * T + 8,
+        "sst": 9 * T + geo + 8,
         "sst_a": 15 * T + 16 + 2 * T * S + 8,
         "sst_b": 19 * T + 16 + 6 * T * S + T + 8,
         "collide1": 19 * T,

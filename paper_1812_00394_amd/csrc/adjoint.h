@@ -865,7 +865,8 @@ __global__ void __launch_bounds__(256) k_adj_sst_grad(Geo<T> g, SstAdj sa, const
 //   phase 2: tile cell t: transposed LSQ gradients from its neighbours' gradient adjoints in LDS,
 //            the macro transpose onto f^n; the adjoints of k^n, omega^n go to lk_out, lw_out
 //            (the adjoints of k, omega of the step's output are read from lk1, lw1).
-// LDS: X [11][Wv], Ln [2][Wv] (net-inflow adjoints), Lg [8][Wg] (gradient adjoints).
+// LDS, cell-major: X [Wv][12] (the 11 cell values at row positions xpos), Ln [Wv][2] (net-inflow
+// adjoints), Lg [Wg][8] (gradient adjoints).
 template <typename T, int S>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_adj_sst_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
@@ -875,7 +876,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
                    StepPar<T> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *X = reinterpret_cast<T *>(smem);
-    T *Ln = X + 11 * Wv;
+    T *Ln = X + 12 * Wv;
     T *Lg = Ln + 2 * Wv;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int start = tile * kTileCells;
@@ -887,7 +888,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     const int c = start + t;
     const SstParams<T> q = sst_params(p);
 
-    // phase 0: cell values and the update's reverse of cell `cell`, stored at LDS column `col`
+    // phase 0: cell values and the update's reverse of cell `cell`, stored at LDS row `col`
     auto load_update = [&](int cell, int col, T x[11], T lxu[3], T lown[4], SstParBar<T> &pb) {
         x[0] = p.rho0 + M[cell];
         x[1] = M[(size_t)n + cell];
@@ -897,15 +898,15 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int i = 0; i < 6; ++i) x[5 + i] = aux[(size_t)i * n + cell];
 #pragma unroll
-        for (int i = 0; i < 11; ++i) X[i * Wv + col] = x[i];
+        for (int i = 0; i < 11; ++i) X[col * 12 + xpos(i)] = x[i];
         T ob[6];
         lxu[0] = lxu[1] = lxu[2] = T(0);
         sst_update_rev<T>(x[0], x[3], x[4], aux[(size_t)10 * n + cell], aux[(size_t)11 * n + cell],
                           aux[(size_t)6 * n + cell], aux[(size_t)7 * n + cell], aux[(size_t)8 * n + cell],
                           aux[(size_t)9 * n + cell], T(g.wdist[cell]), g.inv_area[cell], p, q, lk1[cell], lw1[cell],
                           T(3) * ltau[cell], lxu, ob, pb);
-        Ln[col] = ob[0];
-        Ln[Wv + col] = ob[1];
+        Ln[col * 2] = ob[0];
+        Ln[col * 2 + 1] = ob[1];
 #pragma unroll
         for (int i = 0; i < 4; ++i) lown[i] = ob[2 + i];
     };
@@ -954,7 +955,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         T th = 0;
 #pragma unroll
         for (int i = 0; i < 11; ++i) lx[i] = T(0);
-        const T lk = Ln[cl], lw = Ln[Wv + cl];
+        const T lk = Ln[cl * 2], lw = Ln[cl * 2 + 1];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             if (enb[s] == -1) continue;
@@ -962,12 +963,12 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
                 T xn[11], unused[11];
 #pragma unroll
                 for (int i = 0; i < 11; ++i) {
-                    xn[i] = X[i * Wv + ecol[s]];
+                    xn[i] = X[ecol[s] * 12 + xpos(i)];
                     unused[i] = T(0);
                 }
                 sst_face_rev<T>(x, xn, enx[s], eny[s], erx[s], ery[s], eqx[s], eqy[s], lk, lw, lx, unused);
-                sst_face_rev<T>(xn, x, -enx[s], -eny[s], eqx[s], eqy[s], erx[s], ery[s], Ln[ecol[s]],
-                                Ln[Wv + ecol[s]], unused, lx);
+                sst_face_rev<T>(xn, x, -enx[s], -eny[s], eqx[s], eqy[s], erx[s], ery[s], Ln[ecol[s] * 2],
+                                Ln[ecol[s] * 2 + 1], unused, lx);
             } else {
                 const int b = -2 - enb[s];
                 const int kind = g.b_kind[b];
@@ -980,7 +981,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         lx[3] += lxu[1];
         lx[4] += lxu[2];
         T gu[2], gv[2], gk[2], gw[2];
-        sst_grad_ring<T, S>(g, sa.bzg, enb, ecol, ecx, ecy, X, Wv, x[1], x[2], x[3], x[4], gu, gv, gk, gw);
+        sst_grad_ring<T, S, 12>(g, sa.bzg, enb, ecol, ecx, ecy, X, x[1], x[2], x[3], x[4], gu, gv, gk, gw);
         T l[11];
 #pragma unroll
         for (int i = 0; i < 11; ++i) l[i] = T(0);
@@ -998,7 +999,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         lg[6] = l[9] + lx[7];
         lg[7] = l[10] + lx[8];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) Lg[i * Wg + cl] = lg[i];
+        for (int i = 0; i < 8; ++i) Lg[cl * 8 + i] = lg[i];
         return th;
     };
     if (ring1) {
@@ -1035,7 +1036,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         if (nb[s] >= 0) {
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-                acc[v] += cbx[s] * Lg[(2 * v) * Wg + col[s]] + cby[s] * Lg[(2 * v + 1) * Wg + col[s]];
+                acc[v] += cbx[s] * Lg[col[s] * 8 + 2 * v] + cby[s] * Lg[col[s] * 8 + 2 * v + 1];
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[v] -= cxs[s] * lgc[2 * v] + cys[s] * lgc[2 * v + 1];
         } else {

@@ -136,6 +136,7 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
     g.area = cv.take<double>(n);
     g.inv_area = cv.take<T>(n);
     g.mi = cv.take<T>(3 * n);
+    g.tp = cv.take<T>(6 * n);
     g.bfirst = cv.take<int32_t>(n);
     g.wdist = cv.take<double>(n);
     g.perm = cv.take<int32_t>(n);
@@ -295,6 +296,8 @@ void upload_geometry(fvlbm_state *st) {
     h2d(const_cast<T *>(g.cy), conv[7], s);
     h2d(const_cast<T *>(g.inv_area), conv[8], s);
     h2d(const_cast<T *>(g.mi), mi, s);
+    const std::vector<T> tp = as_t(m->tri_p);
+    h2d(const_cast<T *>(g.tp), tp, s);
     h2d(const_cast<int32_t *>(g.bfirst), m->bfirst, s);
     h2d(const_cast<double *>(g.area), m->area, s);
     h2d(const_cast<double *>(g.wdist), m->wdist, s);
@@ -552,7 +555,7 @@ void choose_sweep(fvlbm_state *st) {
     st->ring = (mode.empty() || mode == "ring") && st->mesh->ext_max <= kTileCells && ring_lds <= (size_t)max_lds;
     if (st->ring) {
         st->lds_bytes = ring_lds;
-        st->sst_lds_bytes = ((size_t)5 * st->ring_wv + (size_t)6 * st->ring_wg) * sizeof(T);
+        st->sst_lds_bytes = ((size_t)8 * st->ring_wv + (size_t)6 * st->ring_wg) * sizeof(T);
         st->tiled = false;
         return;
     }
@@ -916,7 +919,7 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
         SstAdj sa{st->bzg, L.pbar};
         const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
         const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
-        const size_t lds = ((size_t)13 * wv + (size_t)8 * wg) * sizeof(T);
+        const size_t lds = ((size_t)14 * wv + (size_t)8 * wg) * sizeof(T);
         if (st->ring_s == 3)
             k_adj_sst_ring<T, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
                                                           L.ltau, L.lF2, L.lK2, L.lW2, p);

@@ -50,6 +50,7 @@ struct fvlbm_mesh {
     std::vector<int8_t> rev;     // [kSlots][n]: slot of the neighbour that points back (interior slots)
     std::vector<double> nlx, nly, rfx, rfy, dx, dy, cx, cy;
     std::vector<double> mi00, mi01, mi11;   // [n] inverse of the weighted least-squares matrix
+    std::vector<double> tri_p;              // [6][n] triangle vertices minus the centroid (x0, y0, x1, y1, x2, y2)
     std::vector<int32_t> bfirst;            // [n] first boundary edge of the cell, -1 if none
     // boundary edges (periodic ones excluded), ordered by internal owner cell then slot
     std::vector<int32_t> b_cell, b_group, b_kind;

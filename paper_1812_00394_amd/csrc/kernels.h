@@ -562,6 +562,60 @@ __device__ __forceinline__ void decode_slots(const int32_t *__restrict__ bfirst,
     for (int s = 0; s < S; ++s) nb[s] = col[s] >= -1 ? col[s] : col[s] - bf;
 }
 
+// Edge geometry of a triangle cell from its vertex offsets p_k (vertex k minus the centroid; edge k
+// runs from vertex k to vertex k+1, counter-clockwise): outward normal x length, midpoint minus
+// centroid, and the inverse area.  FP32 reads p0, p1 and takes p2 = -p0 - p1 (the centroid of a
+// triangle is its vertex mean; the difference is far below FP32 resolution); FP64 reads all three.
+template <typename T>
+__device__ __forceinline__ void tri_edges(const Geo<T> &g, int c, T nlx[3], T nly[3], T rx[3], T ry[3], T &ia) {
+    const size_t n = g.n;
+    T px[3], py[3];
+    px[0] = g.tp[c];
+    py[0] = g.tp[n + c];
+    px[1] = g.tp[2 * n + c];
+    py[1] = g.tp[3 * n + c];
+    if constexpr (sizeof(T) == 4) {
+        px[2] = -px[0] - px[1];
+        py[2] = -py[0] - py[1];
+    } else {
+        px[2] = g.tp[4 * n + c];
+        py[2] = g.tp[5 * n + c];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = k, b = (k + 1) % 3;
+        nlx[k] = py[b] - py[a];
+        nly[k] = px[a] - px[b];
+        rx[k] = T(0.5) * (px[a] + px[b]);
+        ry[k] = T(0.5) * (py[a] + py[b]);
+    }
+    ia = T(2) * recip((px[1] - px[0]) * (py[2] - py[0]) - (px[2] - px[0]) * (py[1] - py[0]));
+}
+
+// LSQ coefficients of all slots of a cell from its centroid offsets d = r_f - q (Section 3 LSQ
+// gradient with weights 1 / |d|^2): M = sum w d d^T, (cx, cy) = w M^-1 d; zero on unused slots.
+template <typename T, int S>
+__device__ __forceinline__ void lsq_cell(const T rx[S], const T ry[S], const T qx[S], const T qy[S], const int nb[S],
+                                         T cx[S], T cy[S]) {
+    T dx[S], dy[S], w[S], m00 = T(0), m01 = T(0), m11 = T(0);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        dx[s] = rx[s] - qx[s];
+        dy[s] = ry[s] - qy[s];
+        w[s] = nb[s] != -1 ? recip(dx[s] * dx[s] + dy[s] * dy[s]) : T(0);
+        m00 += w[s] * dx[s] * dx[s];
+        m01 += w[s] * dx[s] * dy[s];
+        m11 += w[s] * dy[s] * dy[s];
+    }
+    const T idet = recip(m00 * m11 - m01 * m01);
+    const T i00 = m11 * idet, i01 = -m01 * idet, i11 = m00 * idet;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        cx[s] = w[s] * (i00 * dx[s] + i01 * dy[s]);
+        cy[s] = w[s] * (i01 * dx[s] + i11 * dy[s]);
+    }
+}
+
 // LSQ coefficients of one slot, (cx, cy) = w M^-1 d with d = r_f - q the centroid offset to the
 // neighbour (to the edge midpoint on a boundary edge, where q = 0), w = 1 / |d|^2 and M^-1 the
 // cell's inverse least-squares matrix (m00, m01, m11).  Zero on an unused slot.
@@ -571,6 +625,40 @@ __device__ __forceinline__ void lsq_coef(T m00, T m01, T m11, T rx, T ry, T qx, 
     const T w = used ? recip(dx * dx + dy * dy) : T(0);
     cx = w * (m00 * dx + m01 * dy);
     cy = w * (m01 * dx + m11 * dy);
+}
+
+// Edge data of tile cell c in registers: slot codes, classification, normal x length, midpoint
+// and neighbour-centroid offsets, LSQ coefficients, inverse area.  Triangle meshes (S = 3) form
+// normals, midpoints, area and LSQ coefficients from the vertex offsets and q; other meshes read
+// them, with the LSQ coefficients from the stored inverse LSQ matrix.
+template <typename T, int S>
+__device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__restrict__ lnb, int c, int col[S],
+                                           int nb[S], T nlx[S], T nly[S], T rx[S], T ry[S], T qx[S], T qy[S],
+                                           T cxs[S], T cys[S], T &ia) {
+    const int n = g.n;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const size_t si = (size_t)s * n + c;
+        col[s] = lnb[si];
+        qx[s] = g.qx[si];
+        qy[s] = g.qy[si];
+        if constexpr (S != 3) {
+            nlx[s] = g.nlx[si];
+            nly[s] = g.nly[si];
+            rx[s] = g.rfx[si];
+            ry[s] = g.rfy[si];
+        }
+    }
+    decode_slots<S>(g.bfirst, c, col, nb);
+    if constexpr (S == 3) {
+        tri_edges(g, c, nlx, nly, rx, ry, ia);
+        lsq_cell<T, S>(rx, ry, qx, qy, nb, cxs, cys);
+    } else {
+        const T m00 = g.mi[c], m01 = g.mi[(size_t)n + c], m11 = g.mi[(size_t)2 * n + c];
+#pragma unroll
+        for (int s = 0; s < S; ++s) lsq_coef(m00, m01, m11, rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
+        ia = g.inv_area[c];
+    }
 }
 
 template <typename T, int J, int S, bool LIM>
@@ -603,22 +691,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
             for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const size_t si = (size_t)s * n + c;
-            col[s] = lnb[si];
-            nlx[s] = g.nlx[si];
-            nly[s] = g.nly[si];
-            rx[s] = g.rfx[si];
-            ry[s] = g.rfy[si];
-            qx[s] = g.qx[si];
-            qy[s] = g.qy[si];
-        }
-        decode_slots<S>(g.bfirst, c, col, nb);
-        const T m00 = g.mi[c], m01 = g.mi[(size_t)n + c], m11 = g.mi[(size_t)2 * n + c];
-#pragma unroll
-        for (int s = 0; s < S; ++s) lsq_coef(m00, m01, m11, rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
-        ia = g.inv_area[c];
+        cell_edges<T, S>(g, lnb, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, ia);
 #pragma unroll
         for (int a = 1; a < 9; ++a) V[t * 8 + (a - 1)] = gc[a];
     }
@@ -1052,36 +1125,44 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
 //            and ring-1 cell t; grad k, grad omega, Gamma_k, Gamma_omega into LDS;
 //   phase 2: face fluxes of tile cell t with its neighbours' data from LDS, point-implicit update,
 //            nu_t and tau.  AUX: also store the aux planes (the adjoint reads them).
-// LDS: Vv [5][Wv] (rho, u, v, k, omega), Vx [6][Wg] (dk/dx, dk/dy, dw/dx, dw/dy, Gamma_k, Gamma_w).
-template <typename T, int S>
+// LDS, cell-major: Vv [Wv][8] (u, v, k, omega, rho, 3 unused), Vx [Wg][6] (dk/dx, dk/dy, dw/dx,
+// dw/dy, Gamma_k, Gamma_w).  Interior edges are summed in straight-line code (an edge without an
+// interior neighbour reads row 0 with weight 0), boundary edges after them in a branch.
+// Row position of the SST cell data x = (rho, u, v, k, omega, dk/dx, dk/dy, dw/dx, dw/dy, Gamma_k,
+// Gamma_w) in a cell-major LDS row: u, v, k, omega first (one 16-byte read for the gradients).
+__host__ __device__ constexpr int xpos(int i) { return i == 0 ? 4 : (i <= 4 ? i - 1 : i); }
+
+// RS: LDS row stride; u, v, k, omega at row offsets 0..3.
+template <typename T, int S, int RS = 8>
 __device__ __forceinline__ void sst_grad_ring(const Geo<T> &g, const int32_t *__restrict__ bzg, const int nb[S],
-                                              const int col[S], const T cxs[S], const T cys[S], const T *Vv, int Wv,
+                                              const int col[S], const T cxs[S], const T cys[S], const T *Vv,
                                               T ux, T uy, T kc, T wc, T gu[2], T gv[2], T gk[2], T gw[2]) {
     gu[0] = gu[1] = gv[0] = gv[1] = gk[0] = gk[1] = gw[0] = gw[1] = T(0);
+    bool bnd = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (nb[s] == -1) continue;
-        T du, dv, dk, dw;
-        if (nb[s] >= 0) {
-            du = Vv[1 * Wv + col[s]] - ux;
-            dv = Vv[2 * Wv + col[s]] - uy;
-            dk = Vv[3 * Wv + col[s]] - kc;
-            dw = Vv[4 * Wv + col[s]] - wc;
-        } else {
+        const bool in = nb[s] >= 0;
+        bnd = bnd || nb[s] <= -2;
+        const int r = in ? col[s] : 0;
+        const T wx = in ? cxs[s] : T(0), wy = in ? cys[s] : T(0);
+        const T du = Vv[r * RS + 0] - ux, dv = Vv[r * RS + 1] - uy, dk = Vv[r * RS + 2] - kc, dw = Vv[r * RS + 3] - wc;
+        gu[0] += wx * du; gu[1] += wy * du;
+        gv[0] += wx * dv; gv[1] += wy * dv;
+        gk[0] += wx * dk; gk[1] += wy * dk;
+        gw[0] += wx * dw; gw[1] += wy * dw;
+    }
+    if (bnd) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nb[s] > -2) continue;
             const int b = -2 - nb[s];
-            if (bzg[b]) {
-                du = dv = dk = dw = T(0);
-            } else {
-                du = T(g.b_ux[b]) - ux;
-                dv = T(g.b_uy[b]) - uy;
-                dk = T(g.b_k[b]) - kc;
-                dw = T(g.b_w[b]) - wc;
-            }
+            if (bzg[b]) continue;   // zero-gradient edge: the ghost equals the cell
+            const T du = T(g.b_ux[b]) - ux, dv = T(g.b_uy[b]) - uy, dk = T(g.b_k[b]) - kc, dw = T(g.b_w[b]) - wc;
+            gu[0] += cxs[s] * du; gu[1] += cys[s] * du;
+            gv[0] += cxs[s] * dv; gv[1] += cys[s] * dv;
+            gk[0] += cxs[s] * dk; gk[1] += cys[s] * dk;
+            gw[0] += cxs[s] * dw; gw[1] += cys[s] * dw;
         }
-        gu[0] += cxs[s] * du; gu[1] += cys[s] * du;
-        gv[0] += cxs[s] * dv; gv[1] += cys[s] * dv;
-        gk[0] += cxs[s] * dk; gk[1] += cys[s] * dk;
-        gw[0] += cxs[s] * dw; gw[1] += cys[s] * dw;
     }
 }
 
@@ -1093,7 +1174,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
                T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *Vv = reinterpret_cast<T *>(smem);
-    T *Vx = Vv + 5 * Wv;
+    T *Vx = Vv + 8 * Wv;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
@@ -1120,28 +1201,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             aux[(size_t)13 * n + c] = ux;
             aux[(size_t)14 * n + c] = uy;
         }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const size_t si = (size_t)s * n + c;
-            col[s] = lnb[si];
-            nlx[s] = g.nlx[si];
-            nly[s] = g.nly[si];
-            rx[s] = g.rfx[si];
-            ry[s] = g.rfy[si];
-            qx[s] = g.qx[si];
-            qy[s] = g.qy[si];
-        }
-        decode_slots<S>(g.bfirst, c, col, nb);
-        const T m00 = g.mi[c], m01 = g.mi[(size_t)n + c], m11 = g.mi[(size_t)2 * n + c];
-#pragma unroll
-        for (int s = 0; s < S; ++s) lsq_coef(m00, m01, m11, rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
+        cell_edges<T, S>(g, lnb, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, ia);
         dc = T(g.wdist[c]);
-        ia = g.inv_area[c];
-        Vv[t] = rho;
-        Vv[1 * Wv + t] = ux;
-        Vv[2 * Wv + t] = uy;
-        Vv[3 * Wv + t] = kc;
-        Vv[4 * Wv + t] = wc;
+        Vv[t * 8 + 0] = ux;
+        Vv[t * 8 + 1] = uy;
+        Vv[t * 8 + 2] = kc;
+        Vv[t * 8 + 3] = wc;
+        Vv[t * 8 + 4] = rho;
     }
     T hr = T(0), hu = T(0), hvv = T(0), hk = T(0), hw = T(0), hd = T(0);
     int hnb[S], hcol[S];
@@ -1154,11 +1220,11 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         hk = K[hc];
         hw = W[hc];
         const int j = kTileCells + t;
-        Vv[j] = hr;
-        Vv[1 * Wv + j] = hu;
-        Vv[2 * Wv + j] = hvv;
-        Vv[3 * Wv + j] = hk;
-        Vv[4 * Wv + j] = hw;
+        Vv[j * 8 + 0] = hu;
+        Vv[j * 8 + 1] = hvv;
+        Vv[j * 8 + 2] = hk;
+        Vv[j * 8 + 3] = hw;
+        Vv[j * 8 + 4] = hr;
         if (ring1) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -1176,28 +1242,28 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     // ---- phase 1 ----
     if (ring1) {
         T gu[2], gv[2], gk[2], gw[2];
-        sst_grad_ring<T, S>(g, bzg, hnb, hcol, hcx, hcy, Vv, Wv, hu, hvv, hk, hw, gu, gv, gk, gw);
+        sst_grad_ring<T, S>(g, bzg, hnb, hcol, hcx, hcy, Vv, hu, hvv, hk, hw, gu, gv, gk, gw);
         const SstLocal<T> o = sst_local<T, T>(hr, hk, hw, gu[0], gu[1], gv[0], gv[1], gk[0], gk[1], gw[0], gw[1], hd, p, q);
         const int j = kTileCells + t;
-        Vx[j] = gk[0];
-        Vx[1 * Wg + j] = gk[1];
-        Vx[2 * Wg + j] = gw[0];
-        Vx[3 * Wg + j] = gw[1];
-        Vx[4 * Wg + j] = o.Gk;
-        Vx[5 * Wg + j] = o.Gw;
+        Vx[j * 6 + 0] = gk[0];
+        Vx[j * 6 + 1] = gk[1];
+        Vx[j * 6 + 2] = gw[0];
+        Vx[j * 6 + 3] = gw[1];
+        Vx[j * 6 + 4] = o.Gk;
+        Vx[j * 6 + 5] = o.Gw;
     }
     SstLocal<T> oc{};
     T xc[11];
     if (own) {
         T gu[2], gv[2], gk[2], gw[2];
-        sst_grad_ring<T, S>(g, bzg, nb, col, cxs, cys, Vv, Wv, ux, uy, kc, wc, gu, gv, gk, gw);
+        sst_grad_ring<T, S>(g, bzg, nb, col, cxs, cys, Vv, ux, uy, kc, wc, gu, gv, gk, gw);
         oc = sst_local<T, T>(rho, kc, wc, gu[0], gu[1], gv[0], gv[1], gk[0], gk[1], gw[0], gw[1], dc, p, q);
-        Vx[t] = gk[0];
-        Vx[1 * Wg + t] = gk[1];
-        Vx[2 * Wg + t] = gw[0];
-        Vx[3 * Wg + t] = gw[1];
-        Vx[4 * Wg + t] = oc.Gk;
-        Vx[5 * Wg + t] = oc.Gw;
+        Vx[t * 6 + 0] = gk[0];
+        Vx[t * 6 + 1] = gk[1];
+        Vx[t * 6 + 2] = gw[0];
+        Vx[t * 6 + 3] = gw[1];
+        Vx[t * 6 + 4] = oc.Gk;
+        Vx[t * 6 + 5] = oc.Gw;
         xc[0] = rho; xc[1] = ux; xc[2] = uy; xc[3] = kc; xc[4] = wc;
         xc[5] = gk[0]; xc[6] = gk[1]; xc[7] = gw[0]; xc[8] = gw[1]; xc[9] = oc.Gk; xc[10] = oc.Gw;
         if constexpr (AUX) {
@@ -1212,27 +1278,37 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     __syncthreads();
     if (!own) return;
 
-    // ---- phase 2: fluxes (same summation order as k_sst_b) and the update ----
+    // ---- phase 2: fluxes (interior edges straight-line, boundary edges after) and the update ----
     T net_k = 0, net_w = 0;
+    bool bnd = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (nb[s] == -1) continue;
+        const bool in = nb[s] >= 0;
+        bnd = bnd || nb[s] <= -2;
+        const int l = in ? col[s] : 0;
+        T xn[11];
+        xn[0] = Vv[l * 8 + 4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xn[1 + i] = Vv[l * 8 + i];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) xn[5 + i] = Vx[l * 6 + i];
         T tk, tw;
-        if (nb[s] >= 0) {
-            const int l = col[s];
-            T xn[11];
+        sst_face<T, T>(xc, xn, nlx[s], nly[s], rx[s], ry[s], qx[s], qy[s], tk, tw);
+        net_k += in ? tk : T(0);
+        net_w += in ? tw : T(0);
+    }
+    if (bnd) {
 #pragma unroll
-            for (int i = 0; i < 5; ++i) xn[i] = Vv[i * Wv + l];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) xn[5 + i] = Vx[i * Wg + l];
-            sst_face<T, T>(xc, xn, nlx[s], nly[s], rx[s], ry[s], qx[s], qy[s], tk, tw);
-        } else {
+        for (int s = 0; s < S; ++s) {
+            if (nb[s] > -2) continue;
             const int b = -2 - nb[s];
-            sst_bface<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), nlx[s], nly[s],
-                            rx[s], ry[s], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
+            const size_t si = (size_t)s * n + c;
+            T tk, tw;
+            sst_bface<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), g.nlx[si], g.nly[si],
+                            g.rfx[si], g.rfy[si], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
+            net_k += tk;
+            net_w += tw;
         }
-        net_k += tk;
-        net_w += tw;
     }
     if constexpr (AUX) {
         aux[(size_t)10 * n + c] = net_k;

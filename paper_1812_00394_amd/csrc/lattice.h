@@ -67,6 +67,7 @@ struct Geo {
     const T *nlx, *nly, *rfx, *rfy, *qx, *qy, *cx, *cy;              // [4][n]
     const T *inv_area;                                               // [n]
     const T *mi;                                                     // [3][n] inverse LSQ matrix: 00, 01, 11
+    const T *tp;                                                     // [6][n] triangle vertices - centroid
     const int32_t *bfirst;                                           // [n] first boundary edge, -1 if none
     const double *area, *wdist;                                      // [n]
     const int32_t *perm;                                             // [n] internal -> user

@@ -371,6 +371,17 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
         m->xc[i] = cxu[perm[i]];
         m->yc[i] = cyu[perm[i]];
     }
+    // vertex offsets from the centroid of triangle cells (exact differences of nearby values)
+    m->tri_p.assign(6 * N, 0.0);
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t u = perm[i], p0 = cell_ptr[u];
+        if (cell_ptr[u + 1] - p0 != 3) continue;
+        for (int k = 0; k < 3; ++k) {
+            const int64_t v = cell_nodes[p0 + k];
+            m->tri_p[(2 * k) * N + i] = xy[2 * v] - cxu[u];
+            m->tri_p[(2 * k + 1) * N + i] = xy[2 * v + 1] - cyu[u];
+        }
+    }
     m->nbr.assign(kSlots * N, -1);
     m->rev.assign(kSlots * N, 0);
     for (auto *v : {&m->nlx, &m->nly, &m->rfx, &m->rfy, &m->dx, &m->dy, &m->cx, &m->cy}) v->assign(kSlots * N, 0.0);
