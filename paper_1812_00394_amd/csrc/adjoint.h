@@ -496,24 +496,30 @@ __global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__
 
 // Ring-tiled transposed convection (adv_T1 and adv_T2 in one launch, ghost parts excepted), in the
 // layout of the ring-tiled forward sweeps:
-//   phase 0: mu = -L / A of tile cell t and ext cell t into LDS; the edge data of tile cell t (with
-//            the LSQ coefficient of each interior neighbour's slot that points back, c_(j->t))
-//            and of ring-1 cell t into registers;
-//   phase 1: adv_T1 of tile cell t and ring-1 cell t: Gbar (the adjoint of the LSQ gradient) into
+//   phase 0: mu = -L / A of tile cell t and ext cell t into LDS; the edge data of tile cell t and
+//            of ring-1 cell t into registers (triangle meshes: their inverse LSQ matrices into
+//            LDS; other meshes: the LSQ coefficient of each interior neighbour's slot that points
+//            back, c_(j->t), gathered);
+//   phase 1: adv_T1 of ring-1 cell t and tile cell t: Gbar (the adjoint of the LSQ gradient) into
 //            LDS, and the own part of tile cell t;
-//   phase 2: adv_T2 of tile cell t from its neighbours' Gbar in LDS; out += (ACC) or = the sum;
+//   phase 2: adv_T2 of tile cell t from its neighbours' Gbar in LDS (triangle meshes: c_(j->t) =
+//            w M_j^-1 (-d) from neighbour j's inverse LSQ matrix); out += (ACC) or = the sum;
 //            EPI = J: for a cell without boundary edges its stage-J reverse follows at once
 //            (nothing stored in out); a cell with boundary edges stores the sum, k_adv_T1b adds
 //            the ghost part and runs the stage reverse.
 // Gbar goes to global memory only for cells with boundary edges, where k_adv_T1b reads it.
+// LDS, cell-major: V [Wv][8] mu, Gl [Wg][16] Gbar (x, y interleaved), Mi [Wg][3] (S = 3).
+// Interior edges are summed in straight-line code (an edge without an interior neighbour reads
+// row 0 with weight 0), open-boundary edges after them.
 template <typename T, int S, bool ACC, int EPI>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
                  int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, T *__restrict__ Gbar, AdjBufs<T> ab,
                  StepPar<T> p) {
     extern __shared__ __align__(16) unsigned char smem[];
-    T *V = reinterpret_cast<T *>(smem);   // [8][Wv]: mu of directions 1..8
-    T *Gl = V + 8 * Wv;                   // [16][Wg]
+    T *V = reinterpret_cast<T *>(smem);
+    T *Gl = V + 8 * Wv;
+    T *Mi = Gl + 16 * Wg;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
@@ -526,83 +532,82 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     // ---- phase 0 ----
     T mu[9];
     int nb[S], col[S];
-    T nlx[S], nly[S], rx[S], ry[S], cxs[S], cys[S], cbx[S], cby[S];
+    T nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], cxs[S], cys[S], cbx[S], cby[S];
     if (own) {
-        const T ia = g.inv_area[c];
+        T mi[3], ia;
+        cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             mu[a] = -(lscale * L[(size_t)a * n + c]) * ia;
-            V[(a - 1) * Wv + t] = mu[a];
+            V[t * 8 + (a - 1)] = mu[a];
         }
+        if constexpr (S == 3) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const size_t si = (size_t)s * n + c;
-            nb[s] = g.nbr[si];
-            col[s] = lnb[si];
-            nlx[s] = g.nlx[si];
-            nly[s] = g.nly[si];
-            rx[s] = g.rfx[si];
-            ry[s] = g.rfy[si];
-            cxs[s] = g.cx[si];
-            cys[s] = g.cy[si];
-            cbx[s] = cby[s] = T(0);
-            if (nb[s] >= 0) {
-                const size_t sj = (size_t)rev[si] * n + nb[s];
-                cbx[s] = g.cx[sj];
-                cby[s] = g.cy[sj];
+            for (int k = 0; k < 3; ++k) Mi[t * 3 + k] = mi[k];
+        } else {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const size_t si = (size_t)s * n + c;
+                cbx[s] = cby[s] = T(0);
+                if (nb[s] >= 0) {
+                    const size_t sj = (size_t)rev[si] * n + g.nbr[si];
+                    cbx[s] = g.cx[sj];
+                    cby[s] = g.cy[sj];
+                }
             }
         }
     }
     T hmu[9];
     int hnb[S], hcol[S];
-    T hnlx[S], hnly[S], hrx[S], hry[S], hcx[S], hcy[S];
+    T hnlx[S], hnly[S], hrx[S], hry[S];
     if (ext) {
         const int hc = rt.cell[x0 + t];
-        const T ia = g.inv_area[hc];
+        T hqx[S], hqy[S], hcx[S], hcy[S], hmi[3], hia;
+        if (ring1) {
+            cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy, hmi,
+                             hia);
+            if constexpr (S == 3) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Mi[(kTileCells + t) * 3 + k] = hmi[k];
+            }
+        } else {
+            hia = g.inv_area[hc];
+        }
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            hmu[a] = -(lscale * L[(size_t)a * n + hc]) * ia;
-            V[(a - 1) * Wv + kTileCells + t] = hmu[a];
-        }
-        if (ring1) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const size_t si = (size_t)s * n + hc;
-                hnb[s] = g.nbr[si];
-                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
-                hnlx[s] = g.nlx[si];
-                hnly[s] = g.nly[si];
-                hrx[s] = g.rfx[si];
-                hry[s] = g.rfy[si];
-                hcx[s] = g.cx[si];
-                hcy[s] = g.cy[si];
-            }
+            hmu[a] = -(lscale * L[(size_t)a * n + hc]) * hia;
+            V[(kTileCells + t) * 8 + (a - 1)] = hmu[a];
         }
     }
     __syncthreads();
 
-    // ---- phase 1: adv_T1 (same summation order as k_adv_T1) ----
+    // ---- phase 1: adv_T1 ----
     // weights of the edges whose face value cell x reconstructs: interior edges (mu_x - mu_N) and
     // outgoing directions of open boundaries (mu_x); gd: the part on g_x itself
     auto t1 = [&](const T m[9], const int *nbs, const int *cols, const T *nx_, const T *ny_, const T *rx_,
                   const T *ry_, T gd[9], T Gx[9], T Gy[9]) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) gd[a] = Gx[a] = Gy[a] = T(0);
+        bool bnd = false;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            if (nbs[s] == -1) continue;
-            if (nbs[s] >= 0) {
+            const bool in = nbs[s] >= 0;
+            bnd = bnd || nbs[s] <= -2;
+            const int r = in ? cols[s] : 0;
+            const T mx = in ? nx_[s] : T(0), my = in ? ny_[s] : T(0);
 #pragma unroll
-                for (int a = 1; a < 9; ++a) {
-                    const T en = T(ex(a)) * nx_[s] + T(ey(a)) * ny_[s];
-                    if (en > T(0)) {
-                        const T w = en * (m[a] - V[(a - 1) * Wv + cols[s]]);
-                        gd[a] += w;
-                        Gx[a] += w * rx_[s];
-                        Gy[a] += w * ry_[s];
-                    }
-                }
-            } else {
+            for (int a = 1; a < 9; ++a) {
+                const T en = T(ex(a)) * mx + T(ey(a)) * my;
+                const T w = en > T(0) ? en * (m[a] - V[r * 8 + (a - 1)]) : T(0);
+                gd[a] += w;
+                Gx[a] += w * rx_[s];
+                Gy[a] += w * ry_[s];
+            }
+        }
+        if (bnd) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                if (nbs[s] > -2) continue;
                 const int kind = g.b_kind[-2 - nbs[s]];
                 if (kind == kWall || kind == kMovingWall) continue;
 #pragma unroll
@@ -623,8 +628,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         t1(hmu, hnb, hcol, hnlx, hnly, hrx, hry, gd, Gx, Gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[(2 * (a - 1)) * Wg + kTileCells + t] = Gx[a];
-            Gl[(2 * (a - 1) + 1) * Wg + kTileCells + t] = Gy[a];
+            Gl[(kTileCells + t) * 16 + 2 * (a - 1)] = Gx[a];
+            Gl[(kTileCells + t) * 16 + 2 * (a - 1) + 1] = Gy[a];
         }
     }
     T gd[9], Gx[9], Gy[9];
@@ -632,20 +637,19 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         t1(mu, nb, col, nlx, nly, rx, ry, gd, Gx, Gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[(2 * (a - 1)) * Wg + t] = Gx[a];
-            Gl[(2 * (a - 1) + 1) * Wg + t] = Gy[a];
+            Gl[t * 16 + 2 * (a - 1)] = Gx[a];
+            Gl[t * 16 + 2 * (a - 1) + 1] = Gy[a];
         }
     }
     __syncthreads();
     if (!own) return;
 
-    // ---- phase 2: own LSQ part, then adv_T2 (same order as k_adv_T1 + k_adv_T2) ----
+    // ---- phase 2: own LSQ part, then adv_T2 ----
     T sx = 0, sy = 0;
     bool bnd = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (nb[s] == -1) continue;
-        sx += cxs[s];
+        sx += cxs[s];   // zero on unused slots
         sy += cys[s];
         bnd = bnd || nb[s] <= -2;
     }
@@ -656,10 +660,21 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     for (int a = 0; a < 9; ++a) acc[a] = T(0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (nb[s] < 0) continue;
+        const bool in = nb[s] >= 0;
+        const int r = in ? col[s] : 0;
+        T bx, by;
+        if constexpr (S == 3) {
+            // neighbour r's LSQ coefficient of its edge back to this cell: w M_r^-1 (-d)
+            const T dx = rx[s] - qx[s], dy = ry[s] - qy[s];
+            const T w = in ? recip(dx * dx + dy * dy) : T(0);
+            bx = -w * (Mi[r * 3] * dx + Mi[r * 3 + 1] * dy);
+            by = -w * (Mi[r * 3 + 1] * dx + Mi[r * 3 + 2] * dy);
+        } else {
+            bx = in ? cbx[s] : T(0);
+            by = in ? cby[s] : T(0);
+        }
 #pragma unroll
-        for (int a = 1; a < 9; ++a)
-            acc[a] += cbx[s] * Gl[(2 * (a - 1)) * Wg + col[s]] + cby[s] * Gl[(2 * (a - 1) + 1) * Wg + col[s]];
+        for (int a = 1; a < 9; ++a) acc[a] += bx * Gl[r * 16 + 2 * (a - 1)] + by * Gl[r * 16 + 2 * (a - 1) + 1];
     }
     T lf[9];
 #pragma unroll
@@ -866,7 +881,8 @@ __global__ void __launch_bounds__(256) k_adj_sst_grad(Geo<T> g, SstAdj sa, const
 //            the macro transpose onto f^n; the adjoints of k^n, omega^n go to lk_out, lw_out
 //            (the adjoints of k, omega of the step's output are read from lk1, lw1).
 // LDS, cell-major: X [Wv][12] (the 11 cell values at row positions xpos), Ln [Wv][2] (net-inflow
-// adjoints), Lg [Wg][8] (gradient adjoints).
+// adjoints), Lg [Wg][8] (gradient adjoints), Mi [Wg][3] (triangle meshes: inverse LSQ matrices,
+// from which the neighbours' LSQ coefficients pointing back are formed; other meshes gather them).
 template <typename T, int S>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_adj_sst_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
@@ -878,6 +894,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     T *X = reinterpret_cast<T *>(smem);
     T *Ln = X + 12 * Wv;
     T *Lg = Ln + 2 * Wv;
+    T *Mi = Lg + 8 * Wg;   // [Wg][3] inverse LSQ matrices (S = 3)
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
@@ -916,34 +933,42 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     T nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], cxs[S], cys[S], cbx[S], cby[S];
     if (own) {
         load_update(c, t, xc, lxc, lownc, pbc);
+        T mi[3], ia;
+        cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
+        if constexpr (S == 3) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const size_t si = (size_t)s * n + c;
-            nb[s] = g.nbr[si];
-            col[s] = lnb[si];
-            nlx[s] = g.nlx[si];
-            nly[s] = g.nly[si];
-            rx[s] = g.rfx[si];
-            ry[s] = g.rfy[si];
-            qx[s] = g.qx[si];
-            qy[s] = g.qy[si];
-            cxs[s] = g.cx[si];
-            cys[s] = g.cy[si];
-            // the LSQ coefficient of the neighbour's slot that points back
-            cbx[s] = cby[s] = T(0);
-            if (nb[s] >= 0) {
-                const size_t sj = (size_t)rev[si] * n + nb[s];
-                cbx[s] = g.cx[sj];
-                cby[s] = g.cy[sj];
+            for (int k = 0; k < 3; ++k) Mi[t * 3 + k] = mi[k];
+        } else {
+            // the LSQ coefficient of the neighbour's slot that points back, gathered
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const size_t si = (size_t)s * n + c;
+                cbx[s] = cby[s] = T(0);
+                if (nb[s] >= 0) {
+                    const size_t sj = (size_t)rev[si] * n + g.nbr[si];
+                    cbx[s] = g.cx[sj];
+                    cby[s] = g.cy[sj];
+                }
             }
         }
     }
     T xh[11], lxh[3], lownh[4];
     SstParBar<T> pbh;    // ring-1 cells: their constants' adjoints are their own tile's
     int hc = 0;
+    int hnb[S], hcol[S];
+    T hnx[S], hny[S], hrx[S], hry[S], hqx[S], hqy[S], hcx[S], hcy[S];
     if (ext) {
         hc = rt.cell[x0 + t];
         load_update(hc, kTileCells + t, xh, lxh, lownh, pbh);
+        if (ring1) {
+            T hmi[3], hia;
+            cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnx, hny, hrx, hry, hqx, hqy, hcx, hcy, hmi,
+                             hia);
+            if constexpr (S == 3) {
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Mi[(kTileCells + t) * 3 + k] = hmi[k];
+            }
+        }
     }
     __syncthreads();
 
@@ -1003,22 +1028,6 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         return th;
     };
     if (ring1) {
-        int hnb[S], hcol[S];
-        T hnx[S], hny[S], hrx[S], hry[S], hqx[S], hqy[S], hcx[S], hcy[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const size_t si = (size_t)s * n + hc;
-            hnb[s] = g.nbr[si];
-            hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
-            hnx[s] = g.nlx[si];
-            hny[s] = g.nly[si];
-            hrx[s] = g.rfx[si];
-            hry[s] = g.rfy[si];
-            hqx[s] = g.qx[si];
-            hqy[s] = g.qy[si];
-            hcx[s] = g.cx[si];
-            hcy[s] = g.cy[si];
-        }
         T lg[8], lx[11];
         faces_closure(hc, kTileCells + t, xh, lxh, lownh, hnb, hcol, hnx, hny, hrx, hry, hqx, hqy, hcx, hcy, lg, lx, pbh);
     }
@@ -1028,18 +1037,36 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     __syncthreads();
     if (!own) return;
 
-    // phase 2: transposed LSQ gradients (same order as k_adj_sst_grad) and the macro transpose
+    // phase 2: transposed LSQ gradients (interior edges straight-line, boundary edges after) and
+    // the macro transpose
     T acc[4] = {0, 0, 0, 0};
+    bool bnd = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        if (nb[s] == -1) continue;
-        if (nb[s] >= 0) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-                acc[v] += cbx[s] * Lg[col[s] * 8 + 2 * v] + cby[s] * Lg[col[s] * 8 + 2 * v + 1];
-#pragma unroll
-            for (int v = 0; v < 4; ++v) acc[v] -= cxs[s] * lgc[2 * v] + cys[s] * lgc[2 * v + 1];
+        const bool in = nb[s] >= 0;
+        bnd = bnd || nb[s] <= -2;
+        const int r = in ? col[s] : 0;
+        T bx, by;
+        if constexpr (S == 3) {
+            // neighbour r's LSQ coefficient of its edge back to this cell: w M_r^-1 (-d)
+            const T dx = rx[s] - qx[s], dy = ry[s] - qy[s];
+            const T w = in ? recip(dx * dx + dy * dy) : T(0);
+            bx = -w * (Mi[r * 3] * dx + Mi[r * 3 + 1] * dy);
+            by = -w * (Mi[r * 3 + 1] * dx + Mi[r * 3 + 2] * dy);
         } else {
+            bx = in ? cbx[s] : T(0);
+            by = in ? cby[s] : T(0);
+        }
+        const T wx = in ? cxs[s] : T(0), wy = in ? cys[s] : T(0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] += bx * Lg[r * 8 + 2 * v] + by * Lg[r * 8 + 2 * v + 1];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] -= wx * lgc[2 * v] + wy * lgc[2 * v + 1];
+    }
+    if (bnd) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nb[s] > -2) continue;
             const int b = -2 - nb[s];
             if (sa.bzg[b]) continue;
 #pragma unroll

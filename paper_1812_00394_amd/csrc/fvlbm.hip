@@ -539,6 +539,19 @@ void import_state(fvlbm_state *st, const double *f, const double *k, const doubl
 // thread per ext cell and their LDS fits; else the ring-1 tiled kernels unless their LDS would not
 // fit; else the two-kernel path.  The environment variable FVLBM_SWEEP (ring, tiled, tiled-grads,
 // split) restricts the choice.
+// LDS of the ring-tiled transposed convection: values, gradient adjoints and, on triangle meshes,
+// the inverse LSQ matrices of tile and ring-1 cells.
+template <typename T>
+size_t adj_t_lds(const fvlbm_state *st) {
+    return ((size_t)8 * st->ring_wv + (size_t)(st->ring_s == 3 ? 19 : 16) * st->ring_wg) * sizeof(T);
+}
+// LDS of the ring-tiled SST reverse: cell values, net-inflow and gradient adjoints, and on
+// triangle meshes the inverse LSQ matrices.
+template <typename T>
+size_t adj_sst_lds(const fvlbm_state *st) {
+    return ((size_t)14 * st->ring_wv + (size_t)(st->ring_s == 3 ? 11 : 8) * st->ring_wg) * sizeof(T);
+}
+
 template <typename T>
 void choose_sweep(fvlbm_state *st) {
     static_assert(kTileCells == kTile, "tile size of the kernels and of the mesh preprocessing differ");
@@ -552,7 +565,10 @@ void choose_sweep(fvlbm_state *st) {
     st->ring_wv = kTile + st->mesh->ext_max;
     st->ring_wg = kTile + st->mesh->halo_max;
     const size_t ring_lds = ((size_t)8 * st->ring_wv + (size_t)16 * st->ring_wg) * sizeof(T);
-    st->ring = (mode.empty() || mode == "ring") && st->mesh->ext_max <= kTileCells && ring_lds <= (size_t)max_lds;
+    // the adjoint's ring kernels must fit as well: transposed convection and the SST reverse
+    const size_t adj_lds = std::max(adj_t_lds<T>(st), adj_sst_lds<T>(st));
+    st->ring = (mode.empty() || mode == "ring") && st->mesh->ext_max <= kTileCells &&
+               std::max(ring_lds, adj_lds) <= (size_t)max_lds;
     if (st->ring) {
         st->lds_bytes = ring_lds;
         st->sst_lds_bytes = ((size_t)8 * st->ring_wv + (size_t)6 * st->ring_wg) * sizeof(T);
@@ -647,7 +663,7 @@ template <typename T, int S, bool ACC, int EPI>
 void launch_T_ring(fvlbm_state *st, const T *lam, T lscale, T *out, const AdjBufs<T> &ab, const StepPar<T> &p) {
     const Geo<T> &g = geo_of<T>(st);
     const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
-    k_adv_T_ring<T, S, ACC, EPI><<<st->mesh->n_tiles, kTileCells, st->lds_bytes, st->stream>>>(
+    k_adv_T_ring<T, S, ACC, EPI><<<st->mesh->n_tiles, kTileCells, adj_t_lds<T>(st), st->stream>>>(
         g, rt, st->lnb, st->rev, st->ring_wv, st->ring_wg, lam, lscale, out, (T *)st->G, ab, p);
 }
 
@@ -919,7 +935,7 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
         SstAdj sa{st->bzg, L.pbar};
         const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
         const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
-        const size_t lds = ((size_t)14 * wv + (size_t)8 * wg) * sizeof(T);
+        const size_t lds = adj_sst_lds<T>(st);
         if (st->ring_s == 3)
             k_adj_sst_ring<T, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
                                                           L.ltau, L.lF2, L.lK2, L.lW2, p);

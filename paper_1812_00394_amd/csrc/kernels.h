@@ -596,7 +596,7 @@ __device__ __forceinline__ void tri_edges(const Geo<T> &g, int c, T nlx[3], T nl
 // gradient with weights 1 / |d|^2): M = sum w d d^T, (cx, cy) = w M^-1 d; zero on unused slots.
 template <typename T, int S>
 __device__ __forceinline__ void lsq_cell(const T rx[S], const T ry[S], const T qx[S], const T qy[S], const int nb[S],
-                                         T cx[S], T cy[S]) {
+                                         T cx[S], T cy[S], T mi[3]) {
     T dx[S], dy[S], w[S], m00 = T(0), m01 = T(0), m11 = T(0);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -609,6 +609,9 @@ __device__ __forceinline__ void lsq_cell(const T rx[S], const T ry[S], const T q
     }
     const T idet = recip(m00 * m11 - m01 * m01);
     const T i00 = m11 * idet, i01 = -m01 * idet, i11 = m00 * idet;
+    mi[0] = i00;
+    mi[1] = i01;
+    mi[2] = i11;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         cx[s] = w[s] * (i00 * dx[s] + i01 * dy[s]);
@@ -627,19 +630,19 @@ __device__ __forceinline__ void lsq_coef(T m00, T m01, T m11, T rx, T ry, T qx, 
     cy = w * (m01 * dx + m11 * dy);
 }
 
-// Edge data of tile cell c in registers: slot codes, classification, normal x length, midpoint
-// and neighbour-centroid offsets, LSQ coefficients, inverse area.  Triangle meshes (S = 3) form
-// normals, midpoints, area and LSQ coefficients from the vertex offsets and q; other meshes read
-// them, with the LSQ coefficients from the stored inverse LSQ matrix.
+// Edge data of cell c in registers: slot codes (from lnb, row stride ls), classification, normal
+// x length, midpoint and neighbour-centroid offsets, LSQ coefficients, inverse LSQ matrix, inverse
+// area.  Triangle meshes (S = 3) form normals, midpoints, area and LSQ data from the vertex
+// offsets and q; other meshes read them, with the LSQ coefficients from the stored inverse matrix.
 template <typename T, int S>
-__device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__restrict__ lnb, int c, int col[S],
-                                           int nb[S], T nlx[S], T nly[S], T rx[S], T ry[S], T qx[S], T qy[S],
-                                           T cxs[S], T cys[S], T &ia) {
+__device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__restrict__ lnb, size_t ls, size_t li,
+                                           int c, int col[S], int nb[S], T nlx[S], T nly[S], T rx[S], T ry[S],
+                                           T qx[S], T qy[S], T cxs[S], T cys[S], T mi[3], T &ia) {
     const int n = g.n;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const size_t si = (size_t)s * n + c;
-        col[s] = lnb[si];
+        col[s] = lnb[(size_t)s * ls + li];
         qx[s] = g.qx[si];
         qy[s] = g.qy[si];
         if constexpr (S != 3) {
@@ -652,11 +655,13 @@ __device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__res
     decode_slots<S>(g.bfirst, c, col, nb);
     if constexpr (S == 3) {
         tri_edges(g, c, nlx, nly, rx, ry, ia);
-        lsq_cell<T, S>(rx, ry, qx, qy, nb, cxs, cys);
+        lsq_cell<T, S>(rx, ry, qx, qy, nb, cxs, cys, mi);
     } else {
-        const T m00 = g.mi[c], m01 = g.mi[(size_t)n + c], m11 = g.mi[(size_t)2 * n + c];
+        mi[0] = g.mi[c];
+        mi[1] = g.mi[(size_t)n + c];
+        mi[2] = g.mi[(size_t)2 * n + c];
 #pragma unroll
-        for (int s = 0; s < S; ++s) lsq_coef(m00, m01, m11, rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
+        for (int s = 0; s < S; ++s) lsq_coef(mi[0], mi[1], mi[2], rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
         ia = g.inv_area[c];
     }
 }
@@ -691,7 +696,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
             for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
         }
-        cell_edges<T, S>(g, lnb, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, ia);
+        T mi[3];
+        cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
 #pragma unroll
         for (int a = 1; a < 9; ++a) V[t * 8 + (a - 1)] = gc[a];
     }
@@ -1201,7 +1207,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             aux[(size_t)13 * n + c] = ux;
             aux[(size_t)14 * n + c] = uy;
         }
-        cell_edges<T, S>(g, lnb, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, ia);
+        T mi[3];
+        cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
         dc = T(g.wdist[c]);
         Vv[t * 8 + 0] = ux;
         Vv[t * 8 + 1] = uy;

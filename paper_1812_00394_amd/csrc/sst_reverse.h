@@ -15,10 +15,12 @@ struct SstParBar {
     T a1 = T(0), bstar = T(0), sk1 = T(0), sw1 = T(0);
 };
 
+// 1 / cosh^2 x = 4 e / (1 + e)^2 with e = exp(-2 |x|) (no overflow, no cancellation).
 template <typename T>
 __device__ __forceinline__ T sech2(T x) {
-    const T ch = cosh(x);
-    return T(1) / (ch * ch);
+    const T e = exp(T(-2) * fabs(x));
+    const T s = T(1) + e;
+    return T(4) * e * recip(s * s);
 }
 
 // Reverse of sst_local.  In: the cell values and gradients of the forward call; out-adjoints
@@ -28,49 +30,54 @@ template <typename T>
 __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T dvx, T dvy, T dkx, T dky, T dwx, T dwy,
                                               T d, const StepPar<T> &p, const SstParams<T> &q, T lGk, T lGw, T lsk,
                                               T lsw, T lbeta, T lSr, T xb[11], SstParBar<T> &pb) {
-    // ---- forward, keeping the intermediates ----
+    // ---- forward, keeping the intermediates (the expressions of sst_local) ----
     const T kap2 = p.kappa * p.kappa;
-    const T sb = sqrt(q.bstar);
-    const T cw1 = p.b1 / q.bstar - q.sw1 * kap2 / sb;
-    const T cw2 = p.b2 / q.bstar - p.sw2 * kap2 / sb;
+    const T sb = sqrt(q.bstar), ib = recip(q.bstar), isb = recip(sb);
+    const T cw1 = p.b1 * ib - q.sw1 * kap2 * isb;
+    const T cw2 = p.b2 * ib - p.sw2 * p.kappa * p.kappa * isb;
     const T s11 = dux, s22 = dvy, s12 = T(0.5) * (duy + dvx);
     const T S2 = T(2) * (s11 * s11 + s22 * s22 + T(2) * s12 * s12);
     const T Sr = sqrt(S2);
     const T div = dux + dvy;
     const T gkgw = dkx * dwx + dky * dwy;
-    const T CDa = T(2) * rho * p.sw2 / w * gkgw;
+    const T iw = recip(w);
+    const T CDa = T(2) * rho * p.sw2 * iw * gkgw;
     const bool cd_pass = CDa >= T(1e-20);
     const T CD = cd_pass ? CDa : T(1e-20);
     const T sk = sqrt(k);
-    const T dd = d;
-    const T visc = T(500) * p.nu / (w * dd * dd);
-    const T t1 = sk / (T(0.09) * w * dd);
+    const T idd = recip(d), idd2 = idd * idd;
+    const T visc = T(500) * p.nu * iw * idd2;
+    const T t1 = sk * iw * idd * T(1.0 / 0.09);
     const bool m1_first = t1 >= visc;
     const T m1 = m1_first ? t1 : visc;
-    const T t2 = T(4) * rho * p.sw2 * k / (CD * dd * dd);
+    const T iCD = recip(CD);
+    const T t2 = T(4) * rho * p.sw2 * k * iCD * idd2;
     const bool a1_first = m1 <= t2;
     const T arg1 = a1_first ? m1 : t2;
     const T a2 = arg1 * arg1;
     const T F1 = tanh(a2 * a2);
-    const T t3 = T(2) * sk / (T(0.09) * w * dd);
+    const T t3 = T(2) * t1;
     const bool arg2_first = t3 >= visc;
     const T arg2 = arg2_first ? t3 : visc;
     const T F2 = tanh(arg2 * arg2);
     const bool den_first = q.a1 * w >= Sr * F2;
     const T den = den_first ? q.a1 * w : Sr * F2;
-    const T mut = q.a1 * rho * k / den;
+    const T iden = recip(den);
+    const T mut = q.a1 * rho * k * iden;
     const T one = T(1);
     const T sig_k = F1 * q.sk1 + (one - F1) * p.sk2;
     const T sig_w = F1 * q.sw1 + (one - F1) * p.sw2;
     const T gam = F1 * cw1 + (one - F1) * cw2;
     const T tt = T(2.0 / 3.0);
     const T E = S2 - tt * div * div;
-    const T Hh = den / q.a1;
+    const T ia1 = recip(q.a1);
+    const T Hh = den * ia1;
     const T P = mut * E - tt * rho * k * div;
     const T Pw = gam * rho * E - tt * gam * rho * Hh * div;
-    const T cross = T(2) * (one - F1) * rho * p.sw2 * gkgw / w;
-    const T sko = p.dt / rho * P;
-    const T swo = p.dt / rho * (Pw + cross);
+    const T cross = T(2) * (one - F1) * rho * p.sw2 * gkgw * iw;
+    const T irho = recip(rho), dtr = p.dt * irho;
+    const T sko = dtr * P;
+    const T swo = dtr * (Pw + cross);
     // ---- reverse ----
     T rho_b = 0, k_b = 0, w_b = 0, div_b = 0, S2_b = 0, gkgw_b = 0, F1_b = 0, den_b = 0, mut_b = 0, Sr_b = lSr;
     T a1_b = 0, cw1_b = 0, cw2_b = 0, sk1_b = 0, sw1_b = 0;
@@ -79,24 +86,24 @@ __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T d
     const T sigk_b = lGk * mut, sigw_b = lGw * mut;
     mut_b += lGk * sig_k + lGw * sig_w;
     // sk = dt / rho P, sw = dt / rho (Pw + cross)
-    const T P_b = lsk * p.dt / rho;
-    const T Pwc_b = lsw * p.dt / rho;
-    rho_b -= lsk * sko / rho + lsw * swo / rho;
+    const T P_b = lsk * dtr;
+    const T Pwc_b = lsw * dtr;
+    rho_b -= (lsk * sko + lsw * swo) * irho;
     // beta = F1 b1 + (1 - F1) b2
     F1_b += lbeta * (p.b1 - p.b2);
     // cross = 2 (1 - F1) rho sw2 gkgw / w
-    F1_b -= Pwc_b * T(2) * rho * p.sw2 * gkgw / w;
-    rho_b += Pwc_b * T(2) * (one - F1) * p.sw2 * gkgw / w;
-    gkgw_b += Pwc_b * T(2) * (one - F1) * rho * p.sw2 / w;
-    w_b -= Pwc_b * cross / w;
+    F1_b -= Pwc_b * T(2) * rho * p.sw2 * gkgw * iw;
+    rho_b += Pwc_b * T(2) * (one - F1) * p.sw2 * gkgw * iw;
+    gkgw_b += Pwc_b * T(2) * (one - F1) * rho * p.sw2 * iw;
+    w_b -= Pwc_b * cross * iw;
     // Pw = gam rho E - tt gam rho H div
     const T gam_b = Pwc_b * (rho * E - tt * rho * Hh * div);
     rho_b += Pwc_b * (gam * E - tt * gam * Hh * div);
     T E_b = Pwc_b * gam * rho;
     const T H_b = -Pwc_b * tt * gam * rho * div;
     div_b -= Pwc_b * tt * gam * rho * Hh;
-    den_b += H_b / q.a1;
-    a1_b -= H_b * den / (q.a1 * q.a1);
+    den_b += H_b * ia1;
+    a1_b -= H_b * den * ia1 * ia1;
     // P = mut E - tt rho k div
     mut_b += P_b * E;
     E_b += P_b * mut;
@@ -113,10 +120,10 @@ __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T d
     sw1_b += sigw_b * F1;
     sk1_b += sigk_b * F1;
     // mut = a1 rho k / den
-    a1_b += mut_b * rho * k / den;
-    rho_b += mut_b * q.a1 * k / den;
-    k_b += mut_b * q.a1 * rho / den;
-    den_b -= mut_b * mut / den;
+    a1_b += mut_b * rho * k * iden;
+    rho_b += mut_b * q.a1 * k * iden;
+    k_b += mut_b * q.a1 * rho * iden;
+    den_b -= mut_b * mut * iden;
     // den = max(a1 w, Sr F2)
     T F2_b = 0;
     if (den_first) {
@@ -130,8 +137,8 @@ __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T d
     const T arg2_b = F2_b * sech2(arg2 * arg2) * T(2) * arg2;
     T visc_b = 0, sk_b = 0;
     if (arg2_first) {
-        sk_b += arg2_b * T(2) / (T(0.09) * w * dd);
-        w_b -= arg2_b * t3 / w;
+        sk_b += arg2_b * T(2.0 / 0.09) * iw * idd;
+        w_b -= arg2_b * t3 * iw;
     } else {
         visc_b += arg2_b;
     }
@@ -141,29 +148,29 @@ __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T d
     if (a1_first) {
         // m1 = max(t1, visc)
         if (m1_first) {
-            sk_b += arg1_b / (T(0.09) * w * dd);
-            w_b -= arg1_b * t1 / w;
+            sk_b += arg1_b * T(1.0 / 0.09) * iw * idd;
+            w_b -= arg1_b * t1 * iw;
         } else {
             visc_b += arg1_b;
         }
     } else {
         // t2 = 4 rho sw2 k / (CD d^2)
-        rho_b += arg1_b * T(4) * p.sw2 * k / (CD * dd * dd);
-        k_b += arg1_b * T(4) * rho * p.sw2 / (CD * dd * dd);
-        const T CD_b = -arg1_b * t2 / CD;
+        rho_b += arg1_b * T(4) * p.sw2 * k * iCD * idd2;
+        k_b += arg1_b * T(4) * rho * p.sw2 * iCD * idd2;
+        const T CD_b = -arg1_b * t2 * iCD;
         if (cd_pass) {
             // CDa = 2 rho sw2 / w gkgw
-            rho_b += CD_b * T(2) * p.sw2 / w * gkgw;
-            w_b -= CD_b * CDa / w;
-            gkgw_b += CD_b * T(2) * rho * p.sw2 / w;
+            rho_b += CD_b * T(2) * p.sw2 * iw * gkgw;
+            w_b -= CD_b * CDa * iw;
+            gkgw_b += CD_b * T(2) * rho * p.sw2 * iw;
         }
     }
     // visc = 500 nu / (w d^2)
-    w_b -= visc_b * visc / w;
+    w_b -= visc_b * visc * iw;
     // sk = sqrt(k)
-    k_b += sk > T(0) ? sk_b * T(0.5) / sk : T(0);
+    k_b += sk > T(0) ? sk_b * T(0.5) * recip(sk) : T(0);
     // Sr = sqrt(S2), S2 = 2 (s11^2 + s22^2 + 2 s12^2)
-    S2_b += Sr > T(0) ? Sr_b * T(0.5) / Sr : T(0);
+    S2_b += Sr > T(0) ? Sr_b * T(0.5) * recip(Sr) : T(0);
     const T s12_b = S2_b * T(8) * s12;
     // gradients
     xb[0] += rho_b;
@@ -178,9 +185,9 @@ __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T d
     xb[9] += gkgw_b * dkx;                        // dwx
     xb[10] += gkgw_b * dky;                       // dwy
     // constants: cw1 = b1 / b* - sw1 kap^2 / sqrt(b*), cw2 = b2 / b* - sw2 kap^2 / sqrt(b*)
-    const T sb_b = (cw1_b * q.sw1 + cw2_b * p.sw2) * kap2 / (sb * sb);
-    pb.bstar += -(cw1_b * p.b1 + cw2_b * p.b2) / (q.bstar * q.bstar) + (sb > T(0) ? sb_b * T(0.5) / sb : T(0));
-    pb.sw1 += sw1_b - cw1_b * kap2 / sb;
+    const T sb_b = (cw1_b * q.sw1 + cw2_b * p.sw2) * kap2 * isb * isb;
+    pb.bstar += -(cw1_b * p.b1 + cw2_b * p.b2) * ib * ib + (sb > T(0) ? sb_b * T(0.5) * isb : T(0));
+    pb.sw1 += sw1_b - cw1_b * kap2 * isb;
     pb.sk1 += sk1_b;
     pb.a1 += a1_b;
 }
@@ -294,30 +301,36 @@ template <typename T>
 __device__ __forceinline__ void sst_update_rev(T rho, T k, T w, T net_k, T net_w, T sk, T sw, T beta, T Sr, T d, T inv_area,
                                                const StepPar<T> &p, const SstParams<T> &q, T k1_bar, T w1_bar, T nut_bar,
                                                T xb[3], T ob[6], SstParBar<T> &pb) {
+    // forward, in the expressions of sst_update
     const T dt = p.dt;
-    const T fac = dt * inv_area / rho;
+    const T irho = recip(rho);
+    const T fac = dt * inv_area * irho;
     const T skp = sk >= T(0) ? sk : T(0), skm = -sk >= T(0) ? -sk : T(0);
     const T swp = sw >= T(0) ? sw : T(0), swm = -sw >= T(0) ? -sw : T(0);
-    const T kn = k + fac * net_k + skp, kd = T(1) + dt * q.bstar * w + skm / k;
-    const T wn = w + fac * net_w + swp, wd = T(1) + dt * beta * w + swm / w;
-    const T kr = kn / kd, wr = wn / wd;
+    const T ik = recip(k), iw = recip(w);
+    const T kn = k + fac * net_k + skp, kd = T(1) + dt * q.bstar * w + skm * ik;
+    const T wn = w + fac * net_w + swp, wd = T(1) + dt * beta * w + swm * iw;
+    const T ikd = recip(kd), iwd = recip(wd);
+    const T kr = kn * ikd, wr = wn * iwd;
     const bool kpass = kr >= T(1e-20), wpass = wr >= T(1e-20);
     const T k1 = kpass ? kr : T(1e-20), w1 = wpass ? wr : T(1e-20);
-    const T dd = d;
+    const T idd = recip(d);
     const T sk1 = sqrt(k1);
-    const T A = T(2) * sk1 / (T(0.09) * w1 * dd);
-    const T B = T(500) * p.nu / (w1 * dd * dd);
+    const T iw1 = recip(w1);
+    const T A = T(2.0 / 0.09) * sk1 * iw1 * idd;
+    const T B = T(500) * p.nu * iw1 * idd * idd;
     const bool a_first = A >= B;
     const T arg2 = a_first ? A : B;
     const T F2 = tanh(arg2 * arg2);
     const bool den_first = q.a1 * w1 >= Sr * F2;
     const T den = den_first ? q.a1 * w1 : Sr * F2;
-    const T nut = q.a1 * k1 / den;
+    const T iden = recip(den);
+    const T nut = q.a1 * k1 * iden;
     // reverse
-    T kb = k1_bar + nut_bar * q.a1 / den;
+    T kb = k1_bar + nut_bar * q.a1 * iden;
     T wb = w1_bar;
-    pb.a1 += nut_bar * k1 / den;
-    const T den_b = -nut_bar * nut / den;
+    pb.a1 += nut_bar * k1 * iden;
+    const T den_b = -nut_bar * nut * iden;
     T Sr_b = 0, F2_b = 0;
     if (den_first) {
         pb.a1 += den_b * w1;
@@ -328,15 +341,15 @@ __device__ __forceinline__ void sst_update_rev(T rho, T k, T w, T net_k, T net_w
     }
     const T arg2_b = F2_b * sech2(arg2 * arg2) * T(2) * arg2;
     if (a_first) {
-        const T sk1_b = arg2_b * T(2) / (T(0.09) * w1 * dd);
-        wb -= arg2_b * A / w1;
-        kb += sk1 > T(0) ? sk1_b * T(0.5) / sk1 : T(0);
+        const T sk1_b = arg2_b * T(2.0 / 0.09) * iw1 * idd;
+        wb -= arg2_b * A * iw1;
+        kb += sk1 > T(0) ? sk1_b * T(0.5) * recip(sk1) : T(0);
     } else {
-        wb -= arg2_b * B / w1;
+        wb -= arg2_b * B * iw1;
     }
     const T kr_b = kpass ? kb : T(0), wr_b = wpass ? wb : T(0);
-    const T kn_b = kr_b / kd, kd_b = -kr_b * kr / kd;
-    const T wn_b = wr_b / wd, wd_b = -wr_b * wr / wd;
+    const T kn_b = kr_b * ikd, kd_b = -kr_b * kr * ikd;
+    const T wn_b = wr_b * iwd, wd_b = -wr_b * wr * iwd;
     T rho_b = 0, k_b = kn_b, w_b = wn_b, fac_b = kn_b * net_k + wn_b * net_w;
     ob[0] = kn_b * fac;
     ob[1] = wn_b * fac;
@@ -345,15 +358,15 @@ __device__ __forceinline__ void sst_update_rev(T rho, T k, T w, T net_k, T net_w
     // kd = 1 + dt b* w + max(-sk, 0) / k
     pb.bstar += kd_b * dt * w;
     w_b += kd_b * dt * q.bstar;
-    if (-sk >= T(0)) sk_b -= kd_b / k;
-    k_b -= kd_b * skm / (k * k);
+    if (-sk >= T(0)) sk_b -= kd_b * ik;
+    k_b -= kd_b * skm * ik * ik;
     // wd = 1 + dt beta w + max(-sw, 0) / w
     const T beta_b = wd_b * dt * w;
     w_b += wd_b * dt * beta;
-    if (-sw >= T(0)) sw_b -= wd_b / w;
-    w_b -= wd_b * swm / (w * w);
+    if (-sw >= T(0)) sw_b -= wd_b * iw;
+    w_b -= wd_b * swm * iw * iw;
     // fac = dt ia / rho
-    rho_b -= fac_b * fac / rho;
+    rho_b -= fac_b * fac * irho;
     xb[0] += rho_b;
     xb[1] += k_b;
     xb[2] += w_b;
