@@ -492,10 +492,10 @@ __global__ void __launch_bounds__(kTileCells + kHaloThreads)
 //            value and gradient from LDS, then the stage epilogue.
 // Stage 1 takes f^(1) = stage solve of f^n (a = dt/(4 tau)) on the fly, for tile and ext cells.
 // J = 0 is the explicit scheme: src = f^n, forward-Euler epilogue.
-// LDS, cell-major so that a neighbour's data is a few 16-byte reads at one address: V [Wv][8]
-// values of directions 1..8 (Wv = kTileCells + largest extended halo), Gl [Wg][16] their x / y
-// gradients interleaved (Wg = kTileCells + largest ring 1); tile cell t is row t, ext entry j row
-// kTileCells + j.
+// LDS, cell-major so that a neighbour's data is a few 16-byte reads: V [Wv][8] values of
+// directions 1..8 (Wv = kTileCells + largest extended halo), Gl [Wg][16] their x / y gradients
+// interleaved (Wg = kTileCells + largest ring 1), both with chunks permuted by row (vrow, grow);
+// tile cell t is row t, ext entry j row kTileCells + j.
 // S = edges per cell of the mesh (3: triangles only; 4 otherwise).
 struct RingTiles {
     const int32_t *ptr;    // [n_tiles + 1] offsets into cell
@@ -504,6 +504,13 @@ struct RingTiles {
     const int16_t *lnb;    // [4][n_ext] columns of the neighbours of ring-1 entries
     int32_t n_ext;
 };
+
+// Cell-major LDS rows with their 16-byte chunks permuted by row: chunk j of row r is stored at
+// chunk position j ^ (bits of r), so that the rows a wave reads (random within the tile) spread
+// over all LDS banks instead of the few that the row stride alone would reach.
+// vrow: 8 values per row (2 chunks); grow: 16 values per row (4 chunks).
+__device__ __forceinline__ int vrow(int r, int k) { return r * 8 + ((((k >> 2) ^ (r >> 3)) & 1) << 2) + (k & 3); }
+__device__ __forceinline__ int grow(int r, int k) { return r * 16 + ((((k >> 2) ^ (r >> 2)) & 3) << 2) + (k & 3); }
 
 // LSQ gradient from LDS values of a cell with edge data held in registers (nb, col, cx, cy per
 // slot; the normal of a boundary edge is read when needed).  The interior edges are summed in
@@ -524,7 +531,7 @@ __device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int n
         const T wx = in ? cxs[s] : T(0), wy = in ? cys[s] : T(0);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            const T d = V[r * 8 + (a - 1)] - gc[a];
+            const T d = V[vrow(r, a - 1)] - gc[a];
             gx[a] += wx * d;
             gy[a] += wy * d;
         }
@@ -699,7 +706,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         T mi[3];
         cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
 #pragma unroll
-        for (int a = 1; a < 9; ++a) V[t * 8 + (a - 1)] = gc[a];
+        for (int a = 1; a < 9; ++a) V[vrow(t, a - 1)] = gc[a];
     }
     T hv[9];
     int hc = 0, hnb[S], hcol[S];
@@ -716,7 +723,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             for (int a = 0; a < 9; ++a) hv[a] = b.src[(size_t)a * n + hc];
         }
 #pragma unroll
-        for (int a = 1; a < 9; ++a) V[(kTileCells + t) * 8 + (a - 1)] = hv[a];
+        for (int a = 1; a < 9; ++a) V[vrow(kTileCells + t, a - 1)] = hv[a];
         if (ring1) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -736,8 +743,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         grad_ring<T, S>(g, hc, hnb, hcol, hcx, hcy, V, p.rho0, hv, hx, hy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[(kTileCells + t) * 16 + 2 * (a - 1)] = hx[a];
-            Gl[(kTileCells + t) * 16 + 2 * (a - 1) + 1] = hy[a];
+            Gl[grow(kTileCells + t, 2 * (a - 1))] = hx[a];
+            Gl[grow(kTileCells + t, 2 * (a - 1) + 1)] = hy[a];
         }
     }
     T gx[9], gy[9];
@@ -748,8 +755,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         grad_ring<T, S>(g, c, nb, col, cxs, cys, V, p.rho0, gc, gx, gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[t * 16 + 2 * (a - 1)] = gx[a];
-            Gl[t * 16 + 2 * (a - 1) + 1] = gy[a];
+            Gl[grow(t, 2 * (a - 1))] = gx[a];
+            Gl[grow(t, 2 * (a - 1) + 1)] = gy[a];
         }
     }
     __syncthreads();
@@ -771,8 +778,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             const T end = T(ex(a)) * mx + T(ey(a)) * my;
-            const T vn = V[loc * 8 + (a - 1)];
-            const T up_n = vn + Gl[loc * 16 + 2 * (a - 1)] * qx[s] + Gl[loc * 16 + 2 * (a - 1) + 1] * qy[s];
+            const T vn = V[vrow(loc, a - 1)];
+            const T up_n = vn + Gl[grow(loc, 2 * (a - 1))] * qx[s] + Gl[grow(loc, 2 * (a - 1) + 1)] * qy[s];
             const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
             T val = end >= T(0) ? up_c : up_n;
             if constexpr (LIM) val = clip_between(val, gc[a], vn);
@@ -799,7 +806,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const T end = T(ex(a)) * bnx + T(ey(a)) * bny;
-                const T own_f = gc[a] + Gl[t * 16 + 2 * (a - 1)] * brx + Gl[t * 16 + 2 * (a - 1) + 1] * bry;
+                const T own_f = gc[a] + Gl[grow(t, 2 * (a - 1))] * brx + Gl[grow(t, 2 * (a - 1) + 1)] * bry;
                 const T val = (wall || end < T(0)) ? gb[a] : own_f;
                 acc[a] += end * val;
             }
