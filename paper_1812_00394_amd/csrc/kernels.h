@@ -509,8 +509,18 @@ struct RingTiles {
 // chunk position j ^ (bits of r), so that the rows a wave reads (random within the tile) spread
 // over all LDS banks instead of the few that the row stride alone would reach.
 // vrow: 8 values per row (2 chunks); grow: 16 values per row (4 chunks).
-__device__ __forceinline__ int vrow(int r, int k) { return r * 8 + ((((k >> 2) ^ (r >> 3)) & 1) << 2) + (k & 3); }
-__device__ __forceinline__ int grow(int r, int k) { return r * 16 + ((((k >> 2) ^ (r >> 2)) & 3) << 2) + (k & 3); }
+// The permutation pays off for 8-byte values; FP32 rows keep the plain order (the index arithmetic
+// costs more issue slots than the bank conflicts it removes there).
+template <typename T>
+__device__ __forceinline__ int vrow(int r, int k) {
+    if constexpr (sizeof(T) == 4) return r * 8 + k;
+    return r * 8 + ((((k >> 2) ^ (r >> 3)) & 1) << 2) + (k & 3);
+}
+template <typename T>
+__device__ __forceinline__ int grow(int r, int k) {
+    if constexpr (sizeof(T) == 4) return r * 16 + k;
+    return r * 16 + ((((k >> 2) ^ (r >> 2)) & 3) << 2) + (k & 3);
+}
 
 // LSQ gradient from LDS values of a cell with edge data held in registers (nb, col, cx, cy per
 // slot; the normal of a boundary edge is read when needed).  The interior edges are summed in
@@ -531,7 +541,7 @@ __device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int n
         const T wx = in ? cxs[s] : T(0), wy = in ? cys[s] : T(0);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            const T d = V[vrow(r, a - 1)] - gc[a];
+            const T d = V[vrow<T>(r, a - 1)] - gc[a];
             gx[a] += wx * d;
             gy[a] += wy * d;
         }
@@ -706,7 +716,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         T mi[3];
         cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
 #pragma unroll
-        for (int a = 1; a < 9; ++a) V[vrow(t, a - 1)] = gc[a];
+        for (int a = 1; a < 9; ++a) V[vrow<T>(t, a - 1)] = gc[a];
     }
     T hv[9];
     int hc = 0, hnb[S], hcol[S];
@@ -723,7 +733,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             for (int a = 0; a < 9; ++a) hv[a] = b.src[(size_t)a * n + hc];
         }
 #pragma unroll
-        for (int a = 1; a < 9; ++a) V[vrow(kTileCells + t, a - 1)] = hv[a];
+        for (int a = 1; a < 9; ++a) V[vrow<T>(kTileCells + t, a - 1)] = hv[a];
         if (ring1) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
@@ -743,8 +753,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         grad_ring<T, S>(g, hc, hnb, hcol, hcx, hcy, V, p.rho0, hv, hx, hy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[grow(kTileCells + t, 2 * (a - 1))] = hx[a];
-            Gl[grow(kTileCells + t, 2 * (a - 1) + 1)] = hy[a];
+            Gl[grow<T>(kTileCells + t, 2 * (a - 1))] = hx[a];
+            Gl[grow<T>(kTileCells + t, 2 * (a - 1) + 1)] = hy[a];
         }
     }
     T gx[9], gy[9];
@@ -755,8 +765,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         grad_ring<T, S>(g, c, nb, col, cxs, cys, V, p.rho0, gc, gx, gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            Gl[grow(t, 2 * (a - 1))] = gx[a];
-            Gl[grow(t, 2 * (a - 1) + 1)] = gy[a];
+            Gl[grow<T>(t, 2 * (a - 1))] = gx[a];
+            Gl[grow<T>(t, 2 * (a - 1) + 1)] = gy[a];
         }
     }
     __syncthreads();
@@ -778,8 +788,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             const T end = T(ex(a)) * mx + T(ey(a)) * my;
-            const T vn = V[vrow(loc, a - 1)];
-            const T up_n = vn + Gl[grow(loc, 2 * (a - 1))] * qx[s] + Gl[grow(loc, 2 * (a - 1) + 1)] * qy[s];
+            const T vn = V[vrow<T>(loc, a - 1)];
+            const T up_n = vn + Gl[grow<T>(loc, 2 * (a - 1))] * qx[s] + Gl[grow<T>(loc, 2 * (a - 1) + 1)] * qy[s];
             const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
             T val = end >= T(0) ? up_c : up_n;
             if constexpr (LIM) val = clip_between(val, gc[a], vn);
@@ -806,7 +816,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const T end = T(ex(a)) * bnx + T(ey(a)) * bny;
-                const T own_f = gc[a] + Gl[grow(t, 2 * (a - 1))] * brx + Gl[grow(t, 2 * (a - 1) + 1)] * bry;
+                const T own_f = gc[a] + Gl[grow<T>(t, 2 * (a - 1))] * brx + Gl[grow<T>(t, 2 * (a - 1) + 1)] * bry;
                 const T val = (wall || end < T(0)) ? gb[a] : own_f;
                 acc[a] += end * val;
             }
@@ -854,8 +864,23 @@ template <typename T, int K>
 __device__ __forceinline__ Dual<T, K> tmin(const Dual<T, K> &a, const Dual<T, K> &b) { return dmin(a, b); }
 template <typename T>
 __device__ __forceinline__ T ssqrt(T a) { return sqrt(a); }
+// FP32: the hardware square root (v_sqrt_f32, within 1 ulp)
+template <>
+__device__ __forceinline__ float ssqrt<float>(float a) { return __builtin_amdgcn_sqrtf(a); }
 template <typename T>
 __device__ __forceinline__ T stanh(T a) { return tanh(a); }
+// FP32: tanh x = 1 - 2 / (exp(2x) + 1) with the hardware exponential and reciprocal (the SST
+// evaluates it at squares, x >= 0; large x gives exp = inf and the result 1; near 0 the absolute
+// error is a few FP32 ulps of 1, far below what the blending functions resolve)
+template <>
+__device__ __forceinline__ float stanh<float>(float a) {
+    return 1.0f - 2.0f * __builtin_amdgcn_rcpf(__expf(2.0f * a) + 1.0f);
+}
+// exp: FP32 with the hardware exponential
+template <typename T>
+__device__ __forceinline__ T sexp(T a) { return exp(a); }
+template <>
+__device__ __forceinline__ float sexp<float>(float a) { return __expf(a); }
 template <typename T, int K>
 __device__ __forceinline__ Dual<T, K> ssqrt(const Dual<T, K> &a) { return dsqrt(a); }
 template <typename T, int K>

@@ -18,7 +18,7 @@ struct SstParBar {
 // 1 / cosh^2 x = 4 e / (1 + e)^2 with e = exp(-2 |x|) (no overflow, no cancellation).
 template <typename T>
 __device__ __forceinline__ T sech2(T x) {
-    const T e = exp(T(-2) * fabs(x));
+    const T e = sexp(T(-2) * fabs(x));
     const T s = T(1) + e;
     return T(4) * e * recip(s * s);
 }
@@ -32,19 +32,19 @@ __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T d
                                               T lsw, T lbeta, T lSr, T xb[11], SstParBar<T> &pb) {
     // ---- forward, keeping the intermediates (the expressions of sst_local) ----
     const T kap2 = p.kappa * p.kappa;
-    const T sb = sqrt(q.bstar), ib = recip(q.bstar), isb = recip(sb);
+    const T sb = ssqrt(q.bstar), ib = recip(q.bstar), isb = recip(sb);
     const T cw1 = p.b1 * ib - q.sw1 * kap2 * isb;
     const T cw2 = p.b2 * ib - p.sw2 * p.kappa * p.kappa * isb;
     const T s11 = dux, s22 = dvy, s12 = T(0.5) * (duy + dvx);
     const T S2 = T(2) * (s11 * s11 + s22 * s22 + T(2) * s12 * s12);
-    const T Sr = sqrt(S2);
+    const T Sr = ssqrt(S2);
     const T div = dux + dvy;
     const T gkgw = dkx * dwx + dky * dwy;
     const T iw = recip(w);
     const T CDa = T(2) * rho * p.sw2 * iw * gkgw;
     const bool cd_pass = CDa >= T(1e-20);
     const T CD = cd_pass ? CDa : T(1e-20);
-    const T sk = sqrt(k);
+    const T sk = ssqrt(k);
     const T idd = recip(d), idd2 = idd * idd;
     const T visc = T(500) * p.nu * iw * idd2;
     const T t1 = sk * iw * idd * T(1.0 / 0.09);
@@ -55,11 +55,11 @@ __device__ __forceinline__ void sst_local_rev(T rho, T k, T w, T dux, T duy, T d
     const bool a1_first = m1 <= t2;
     const T arg1 = a1_first ? m1 : t2;
     const T a2 = arg1 * arg1;
-    const T F1 = tanh(a2 * a2);
+    const T F1 = stanh(a2 * a2);
     const T t3 = T(2) * t1;
     const bool arg2_first = t3 >= visc;
     const T arg2 = arg2_first ? t3 : visc;
-    const T F2 = tanh(arg2 * arg2);
+    const T F2 = stanh(arg2 * arg2);
     const bool den_first = q.a1 * w >= Sr * F2;
     const T den = den_first ? q.a1 * w : Sr * F2;
     const T iden = recip(den);
@@ -315,13 +315,13 @@ __device__ __forceinline__ void sst_update_rev(T rho, T k, T w, T net_k, T net_w
     const bool kpass = kr >= T(1e-20), wpass = wr >= T(1e-20);
     const T k1 = kpass ? kr : T(1e-20), w1 = wpass ? wr : T(1e-20);
     const T idd = recip(d);
-    const T sk1 = sqrt(k1);
+    const T sk1 = ssqrt(k1);
     const T iw1 = recip(w1);
     const T A = T(2.0 / 0.09) * sk1 * iw1 * idd;
     const T B = T(500) * p.nu * iw1 * idd * idd;
     const bool a_first = A >= B;
     const T arg2 = a_first ? A : B;
-    const T F2 = tanh(arg2 * arg2);
+    const T F2 = stanh(arg2 * arg2);
     const bool den_first = q.a1 * w1 >= Sr * F2;
     const T den = den_first ? q.a1 * w1 : Sr * F2;
     const T iden = recip(den);
