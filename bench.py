@@ -96,10 +96,11 @@ def make_state(F, M, flow, init, precision, dt_frac):
 # sweeps stream; S = edges per cell; wall distance 8 B (FP64).
 #   ring : sweep 1 takes f^(1) from f^n and tau on the fly (no collide1 launch): reads f^n, tau,
 #          writes f^(2), Ga1 (28 values); sweep 2 reads f^(2), f^n, tau, Ga1, writes f^(3), Q (46);
-#          sweep 3 reads f^(3), Q, writes f^{n+1} and rho, u (30)
+#          sweep 3 reads f^(3), Q, writes f^{n+1} and rho, u (30).  With dt <= 16 tau0 stage 2
+#          recovers Ga1 from f^(2), f^n and tau: 9 values fewer in sweeps 1 and 2
 #   tiled: collide1 writes f^(1) (19 values with f^n and tau); sweep 1 reads f^(1) as well (37)
 #   split: as tiled, plus the 16 gradient planes each sweep reads back (grad writes them)
-def kernel_bytes(T, S, variant="ring"):
+def kernel_bytes(T, S, variant="ring", recover=False):
     # ring kernels, triangles: per edge the int16 slot code and the neighbour-centroid offset q
     # (2 values), per cell the vertex offsets from the centroid (2 vertices in FP32, 3 in FP64);
     # normals, midpoints, area and LSQ coefficients are formed from them.  Other meshes: per edge
@@ -120,8 +121,9 @@ def kernel_bytes(T, S, variant="ring"):
         "sst_b": 19 * T + 16 + 6 * T * S + T + 8,
         "collide1": 19 * T,
         "grad": 25 * T + 16 + 2 * T * S,
-        "sweep1": (28 if variant == "ring" else 37) * T + geo + extra,
-        "sweep2": 46 * T + geo + extra,
+        # recover: stage 2 recovers Ga1 from f^(2) (dt <= 16 tau0), stage 1 does not store it
+        "sweep1": ((28 if variant == "ring" else 37) - (9 if recover else 0)) * T + geo + extra,
+        "sweep2": (46 - (9 if recover else 0)) * T + geo + extra,
         "sweep3": 30 * T + geo + extra,
     }
 
@@ -343,7 +345,7 @@ def main():
     T = 4 if args.precision == "fp32dev" else 8
     # the variant the library chose: the ring sweep launches no collide1, the split path its grad
     variant = "split" if kt["grad"][1] else ("tiled" if kt["collide1"][1] else "ring")
-    kb = kernel_bytes(T, S, variant)
+    kb = kernel_bytes(T, S, variant, recover=p["dt"] <= 16 * 3 * p["nu"])
     per_kernel = {}
     for name, (tms, cnt) in kt.items():
         if cnt:

@@ -211,6 +211,9 @@ StepPar<T> step_par(const fvlbm_params &p) {
     s.b2 = T(p.beta2);
     s.kappa = T(p.kappa);
     s.limiter = p.limiter;
+    // Ga1 recovered from f^(2) when the stage solve's a = dt / (4 tau) stays <= 4 for every cell
+    // (tau >= tau0 = 3 nu): its rounding amplification 1 + a is then at most 5
+    s.recover = p.dt <= 16.0 * 3.0 * p.nu ? 1 : 0;
     return s;
 }
 

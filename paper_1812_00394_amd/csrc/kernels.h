@@ -25,6 +25,7 @@ struct StepPar {
     T rho0, dt, nu;
     T a1, bstar, sk1, sk2, sw1, sw2, b1, b2, kappa;
     int limiter;   // keep interior face values of f between the two cells' values
+    int recover;   // stage 2 recovers Ga1 from f^(2) instead of reading it (stage 1 does not store it)
 };
 
 // ----------------------------------------------------------------------------------------------
@@ -213,20 +214,27 @@ struct StageBufs {
 };
 
 template <typename T, int J>
-__device__ __forceinline__ void load_ops(const StageBufs<T> &b, int c, int n, EpiOps<T> &o) {
+__device__ __forceinline__ void load_ops(const StageBufs<T> &b, int c, int n, EpiOps<T> &o, int recover) {
     if constexpr (J == 0) o.tc = b.tau[c];
     if constexpr (J == 1 || J == 2) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) o.fn[a] = b.F_in[(size_t)a * n + c];
         o.tc = b.tau[c];
     }
-    if constexpr (J >= 2) {
+    if constexpr (J == 3) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) o.a[a] = b.A[(size_t)a * n + c];
     }
+    if constexpr (J == 2) {
+        if (!recover) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) o.a[a] = b.A[(size_t)a * n + c];
+        }
+    }
 }
 
-// Stage 1 -> 2: f^(2) = solve(f^n + dt/2 Ga1, a = dt/(4 tau)); stores f^(2) and Ga1.
+// Stage 1 -> 2: f^(2) = solve(f^n + dt/2 Ga1, a = dt/(4 tau)); stores f^(2), and Ga1 unless stage 2
+// recovers it.
 template <typename T>
 __device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const EpiOps<T> &o, T *__restrict__ Y,
                                           T *__restrict__ A, const StepPar<T> &p) {
@@ -236,31 +244,39 @@ __device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const Epi
     for (int a = 0; a < 9; ++a) rhs[a] = o.fn[a] + h * ga[a];
     stage_collide(rhs, p.dt * T(0.25) * recip(o.tc), p.rho0, f2, fe);
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        Y[(size_t)a * n + c] = f2[a];
-        A[(size_t)a * n + c] = ga[a];
+    for (int a = 0; a < 9; ++a) Y[(size_t)a * n + c] = f2[a];
+    if (!p.recover) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) A[(size_t)a * n + c] = ga[a];
     }
 }
 
 // Stage 2 -> 3: Gc1, Gc2 recomputed cell-locally; f^(3) = solve(rhs3, dt/(3 tau)) with the stage
 // moments of Eq. (sumimeximplicitnew); stores f^(3) and Q = f^(3) - dt/6 (Ga1 + Ga2) (over Ga1).
+// Ga1 is read, or recovered from the stage-2 solve: f^(2) = (rhs2 + a f_eq(f^(2))) / (1 + a) with
+// rhs2 = f^n + dt/2 Ga1 and a = dt/(4 tau), so Ga1 = (2/dt) (f^(2) + a (f^(2) - f_eq(f^(2))) - f^n).
+// The recovery amplifies the rounding of f^(2) by 1 + a; the host enables it for a <= 4 only.
 template <typename T>
 __device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T ga2[9], const EpiOps<T> &o,
                                           T *__restrict__ X, T *__restrict__ A, const StepPar<T> &p) {
     T f1[9], fe1[9], rhs[9], f3[9], gsum[9];
     const T tc = o.tc;
     const T itau = recip(tc);
-    stage_collide(o.fn, p.dt * T(0.25) * itau, p.rho0, f1, fe1);   // f^(1), f_eq^(1)
+    const T a12 = p.dt * T(0.25) * itau;                         // a of stages 1 and 2
+    stage_collide(o.fn, a12, p.rho0, f1, fe1);                   // f^(1), f_eq^(1)
     T drho2, rho2, ux2, uy2;
     moments(f2, p.rho0, drho2, rho2, ux2, uy2);                  // stage-2 moments
     const T h2 = p.dt * T(0.5), h3 = p.dt * T(1.0 / 3.0);
+    const T i_h2 = T(2) * recip(p.dt);
     // stage-3 moments from f^n and the convection terms (Eq. (sumimeximplicitnew))
     T m0 = 0, mx = 0, my = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
+        const T fe2 = dfeq(a, drho2, rho2, ux2, uy2);
         const T gc1 = (fe1[a] - f1[a]) * itau;
-        const T gc2 = (dfeq(a, drho2, rho2, ux2, uy2) - f2[a]) * itau;
-        gsum[a] = o.a[a] + ga2[a];                                 // Ga1 + Ga2
+        const T gc2 = (fe2 - f2[a]) * itau;
+        const T ga1 = p.recover ? (f2[a] + a12 * (f2[a] - fe2) - o.fn[a]) * i_h2 : o.a[a];
+        gsum[a] = ga1 + ga2[a];                                    // Ga1 + Ga2
         rhs[a] = o.fn[a] + h2 * gsum[a] + h3 * (gc1 + gc2);
         const T mv = o.fn[a] + h2 * gsum[a];
         m0 += mv;
@@ -332,7 +348,7 @@ template <typename T, int J>
 __device__ __forceinline__ void stage_epilogue(int c, int n, const T gc[9], const T ga[9], const StageBufs<T> &b,
                                                const StepPar<T> &p) {
     EpiOps<T> o;
-    load_ops<T, J>(b, c, n, o);
+    load_ops<T, J>(b, c, n, o, p.recover);
     stage_epilogue_ops<T, J>(c, n, gc, ga, o, b, p);
 }
 
@@ -706,7 +722,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     T cxs[S], cys[S], nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], ia = T(0);
     if (own) {
         if constexpr (J == 1) {
-            load_ops<T, 1>(b, c, n, ops);
+            load_ops<T, 1>(b, c, n, ops, p.recover);
             T fe[9];
             stage_collide(ops.fn, p.dt * T(0.25) * recip(ops.tc), p.rho0, gc, fe);
         } else {
@@ -761,7 +777,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     if (own) {
         // the epilogue operands of stages other than 1 are loaded here, after the ring-1 work:
         // they are in flight during the gradient and the barrier without being live in phase 0
-        if constexpr (J != 1) load_ops<T, J>(b, c, n, ops);
+        if constexpr (J != 1) load_ops<T, J>(b, c, n, ops, p.recover);
         grad_ring<T, S>(g, c, nb, col, cxs, cys, V, p.rho0, gc, gx, gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
