@@ -503,18 +503,17 @@ __global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__
 //   phase 1: adv_T1 of ring-1 cell t and tile cell t: Gbar (the adjoint of the LSQ gradient) into
 //            LDS, and the own part of tile cell t;
 //   phase 2: adv_T2 of tile cell t from its neighbours' Gbar in LDS (triangle meshes: c_(j->t) =
-//            w M_j^-1 (-d) from neighbour j's inverse LSQ matrix); out += (ACC) or = the sum;
-//            EPI = J: for a cell without boundary edges its stage-J reverse follows at once
-//            (nothing stored in out); a cell with boundary edges stores the sum, k_adv_T1b adds
-//            the ghost part and runs the stage reverse.
-// Gbar goes to global memory only for cells with boundary edges, where k_adv_T1b reads it.
+//            w M_j^-1 (-d) from neighbour j's inverse LSQ matrix); a cell with boundary edges adds
+//            the ghost part (as k_adv_T1b does for the other paths); out += (ACC) or = the sum, or
+//            with EPI = J the cell's stage-J reverse follows at once (nothing stored in out).
 // LDS, cell-major: V [Wv][8] mu, Gl [Wg][16] Gbar (x, y interleaved), Mi [Wg][3] (S = 3).
 // Interior edges are summed in straight-line code (an edge without an interior neighbour reads
 // row 0 with weight 0), open-boundary edges after them.
 template <typename T, int S, bool ACC, int EPI>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
-                 int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, T *__restrict__ Gbar, AdjBufs<T> ab,
+                 int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, const T *__restrict__ f,
+                 const T *__restrict__ tau1, T a_dt, double *__restrict__ dth, T rho0, AdjBufs<T> ab,
                  StepPar<T> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *V = reinterpret_cast<T *>(smem);
@@ -684,18 +683,51 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         else
             lf[a] = gd[a] + acc[a];
     }
-    if (EPI == 0 || bnd) {
+    if (bnd) {
+        // ghost part of a cell with boundary edges: the face values on walls and incoming
+        // directions and the ghosts' use in the cell's own LSQ gradient, through the closed-form
+        // Jacobian of the ghost states (the field is f, or its stage solve with a = a_dt / tau1);
+        // mu and the cell's gradient adjoint are read back from LDS
+        T gj[9], gdb[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+            gj[a] = f[(size_t)a * n + c];
+            gdb[a] = T(0);
+        }
+        if (tau1) {
+            T f1[9], fe[9];
+            stage_collide(gj, a_dt * recip(tau1[c]), rho0, f1, fe);
+#pragma unroll
+            for (int a = 0; a < 9; ++a) gj[a] = f1[a];
+        }
+        T th = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nb[s] > -2) continue;
+            const int b = -2 - nb[s];
+            const int kind = g.b_kind[b];
+            const bool wall = (kind == kWall || kind == kMovingWall);
+            const size_t si = (size_t)s * n + c;
+            const T bnx = g.nlx[si], bny = g.nly[si];
+            T gb_bar[9];
+            gb_bar[0] = T(0);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T en = T(ex(a)) * bnx + T(ey(a)) * bny;
+                gb_bar[a] = cxs[s] * Gl[t * 16 + 2 * (a - 1)] + cys[s] * Gl[t * 16 + 2 * (a - 1) + 1] +
+                            ((wall || en < T(0)) ? en * V[t * 8 + (a - 1)] : T(0));
+            }
+            th += ghost_vjp(g, b, bnx, bny, gj, rho0, gb_bar, gdb);
+        }
+        dth[c] += (double)th;
+#pragma unroll
+        for (int a = 0; a < 9; ++a) lf[a] += gdb[a];
+    }
+    if constexpr (EPI == 0) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) out[(size_t)a * n + c] = lf[a];
     } else {
         adj_stage_epilogue<T, EPI>(c, n, lf, ab, p);
-    }
-    if (bnd) {
-#pragma unroll
-        for (int a = 1; a < 9; ++a) {
-            Gbar[(size_t)(2 * (a - 1)) * n + c] = Gx[a];
-            Gbar[(size_t)(2 * (a - 1) + 1) * n + c] = Gy[a];
-        }
     }
 }
 

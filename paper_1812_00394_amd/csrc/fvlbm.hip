@@ -663,11 +663,12 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
 }
 
 template <typename T, int S, bool ACC, int EPI>
-void launch_T_ring(fvlbm_state *st, const T *lam, T lscale, T *out, const AdjBufs<T> &ab, const StepPar<T> &p) {
+void launch_T_ring(fvlbm_state *st, const T *f, const T *tau1, T a_dt, const T *lam, T lscale, T *out, double *dth,
+                   const AdjBufs<T> &ab, const StepPar<T> &p) {
     const Geo<T> &g = geo_of<T>(st);
     const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
     k_adv_T_ring<T, S, ACC, EPI><<<st->mesh->n_tiles, kTileCells, adj_t_lds<T>(st), st->stream>>>(
-        g, rt, st->lnb, st->rev, st->ring_wv, st->ring_wg, lam, lscale, out, (T *)st->G, ab, p);
+        g, rt, st->lnb, st->rev, st->ring_wv, st->ring_wg, lam, lscale, out, f, tau1, a_dt, dth, T(st->par.rho0), ab, p);
 }
 
 // Transposed convection at field f (with tau1: at the stage solve of f with a = dt / (4 tau1))
@@ -686,29 +687,20 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
     if ((acc && epi == 3) || (!acc && (epi == 1 || epi == 2)))
         throw Error(FVLBM_EINVAL, "adv_transpose: stage epilogue and accumulation do not match");
     if (st->ring) {
+        // one launch: the boundary cells' ghost parts are fused into the ring kernel
         const bool s3 = st->ring_s == 3;
+#define FVLBM_T_RING(S_, ACC_, EPI_) launch_T_ring<T, S_, ACC_, EPI_>(st, f, tau1, a_dt, lam, lscale, out, dth, ab, p)
         if (!acc && epi == 3)
-            s3 ? launch_T_ring<T, 3, false, 3>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, false, 3>(st, lam, lscale, out, ab, p);
+            s3 ? FVLBM_T_RING(3, false, 3) : FVLBM_T_RING(4, false, 3);
         else if (!acc)
-            s3 ? launch_T_ring<T, 3, false, 0>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, false, 0>(st, lam, lscale, out, ab, p);
+            s3 ? FVLBM_T_RING(3, false, 0) : FVLBM_T_RING(4, false, 0);
         else if (epi == 0)
-            s3 ? launch_T_ring<T, 3, true, 0>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, true, 0>(st, lam, lscale, out, ab, p);
+            s3 ? FVLBM_T_RING(3, true, 0) : FVLBM_T_RING(4, true, 0);
         else if (epi == 2)
-            s3 ? launch_T_ring<T, 3, true, 2>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, true, 2>(st, lam, lscale, out, ab, p);
+            s3 ? FVLBM_T_RING(3, true, 2) : FVLBM_T_RING(4, true, 2);
         else
-            s3 ? launch_T_ring<T, 3, true, 1>(st, lam, lscale, out, ab, p) : launch_T_ring<T, 4, true, 1>(st, lam, lscale, out, ab, p);
-        if (g.nb > 0) {
-            const int nbb = blocks_for(g.nb);
-            const T rho0 = T(st->par.rho0);
-            if (epi == 3)
-                k_adv_T1b<T, 3><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
-            else if (epi == 2)
-                k_adv_T1b<T, 2><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
-            else if (epi == 1)
-                k_adv_T1b<T, 1><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
-            else
-                k_adv_T1b<T, 0><<<nbb, kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth, rho0, ab, p);
-        }
+            s3 ? FVLBM_T_RING(3, true, 1) : FVLBM_T_RING(4, true, 1);
+#undef FVLBM_T_RING
         return;
     }
     if (!acc) k_fill<T><<<blocks_for(9 * (size_t)g.n), kBlock, 0, s>>>(9 * g.n, out, T(0));
