@@ -262,7 +262,9 @@ struct AdjBufs {
 // Writes lfn (the adjoint of f^n so far), lf2 (Gc2 part), lf1 (Gc1 part), lam (the Ga2 adjoint and
 // the Ga1 adjoint so far), ltau.
 template <typename T>
-__device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], const AdjBufs<T> &b, const StepPar<T> &p) {
+// lnext_c: the cell's lam_{n+1} when the caller holds it already (nullptr: read here).
+__device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], const AdjBufs<T> &b, const StepPar<T> &p,
+                                                const T *lnext_c = nullptr) {
     T fn[9], f1[9], f2[9], f3[9], Q[9], lq[9], l3[9];
     const T tc = b.tau[c];
     const T dt = p.dt;
@@ -270,8 +272,8 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
         fn[a] = b.fn[i]; f2[a] = b.f2[i]; f3[a] = b.f3[i]; Q[a] = b.Q[i];
-        lq[a] = b.lnext[i];               // lam_{n+1} = adjoint of Q
-        l3[a] = lf3[a] + lq[a];           // f3 enters Q with weight 1
+        lq[a] = lnext_c ? lnext_c[a] : b.lnext[i];   // lam_{n+1} = adjoint of Q
+        l3[a] = lf3[a] + lq[a];                      // f3 enters Q with weight 1
     }
     {
         T fe[9];
@@ -361,8 +363,9 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
 // adjoint lf2 of cell c: lfn += rhs2_bar; lam_out <- Ga1 adjoint = (its part from the third stage,
 // in lam) + dt/2 rhs2_bar; ltau += ...
 template <typename T>
+// lam_c: the cell's values of lam when the caller holds them already (nullptr: read here).
 __device__ __forceinline__ void adj_stage2_cell(int c, int n, const T lf2[9], const AdjBufs<T> &b, T *lam_out,
-                                                const StepPar<T> &p) {
+                                                const StepPar<T> &p, const T *lam_c = nullptr) {
     T f2[9], lr[9];
     const T tc = b.tau[c];
 #pragma unroll
@@ -378,7 +381,7 @@ __device__ __forceinline__ void adj_stage2_cell(int c, int n, const T lf2[9], co
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
         b.lfn[i] += lr[a];
-        lam_out[i] = b.lam[i] + p.dt * T(0.5) * lr[a];
+        lam_out[i] = (lam_c ? lam_c[a] : b.lam[i]) + p.dt * T(0.5) * lr[a];
     }
     b.ltau[c] += -abar * a2 * recip(tc);
 }
@@ -406,12 +409,15 @@ __device__ __forceinline__ void adj_stage1_cell(int c, int n, const T lf1[9], co
 // The stage reverse that follows the transposed convection of stage J (EPI = J, 0: none), for cell
 // c with the complete adjoint lf of its stage field: stage 3 (with the combination) leaves the Ga2
 // adjoint in lam, stage 2 the Ga1 adjoint in lg1.
+// lin_c: the cell's values of the transposed convection's input (lam_{n+1} for stage 3, lam for
+// stage 2) when the caller holds them already (nullptr: read here).
 template <typename T, int EPI>
-__device__ __forceinline__ void adj_stage_epilogue(int c, int n, const T lf[9], const AdjBufs<T> &b, const StepPar<T> &p) {
+__device__ __forceinline__ void adj_stage_epilogue(int c, int n, const T lf[9], const AdjBufs<T> &b, const StepPar<T> &p,
+                                                   const T *lin_c = nullptr) {
     if constexpr (EPI == 3)
-        adj_stage3_cell(c, n, lf, b, p);
+        adj_stage3_cell(c, n, lf, b, p, lin_c);
     else if constexpr (EPI == 2)
-        adj_stage2_cell(c, n, lf, b, b.lg1, p);
+        adj_stage2_cell(c, n, lf, b, b.lg1, p, lin_c);
     else if constexpr (EPI == 1)
         adj_stage1_cell(c, n, lf, b, p);
 }
@@ -529,15 +535,17 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     const int c = start + t;
 
     // ---- phase 0 ----
-    T mu[9];
+    T mu[9], Lc[9];   // Lc: the cell's input values, kept for the stage-2 / 3 reverse (same arrays)
     int nb[S], col[S];
     T nlx[S], nly[S], rx[S], ry[S], qx[S], qy[S], cxs[S], cys[S], cbx[S], cby[S];
     if (own) {
         T mi[3], ia;
         cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
+        if constexpr (EPI == 2 || EPI == 3) Lc[0] = L[c];
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
-            mu[a] = -(lscale * L[(size_t)a * n + c]) * ia;
+            Lc[a] = L[(size_t)a * n + c];
+            mu[a] = -(lscale * Lc[a]) * ia;
             V[t * 8 + (a - 1)] = mu[a];
         }
         if constexpr (S == 3) {
@@ -727,7 +735,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int a = 0; a < 9; ++a) out[(size_t)a * n + c] = lf[a];
     } else {
-        adj_stage_epilogue<T, EPI>(c, n, lf, ab, p);
+        adj_stage_epilogue<T, EPI>(c, n, lf, ab, p, Lc);
     }
 }
 

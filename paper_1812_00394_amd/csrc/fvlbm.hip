@@ -686,6 +686,9 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
     // stage 3 stores the transpose (its f^(3) adjoint starts from it), stages 2 and 1 add to theirs
     if ((acc && epi == 3) || (!acc && (epi == 1 || epi == 2)))
         throw Error(FVLBM_EINVAL, "adv_transpose: stage epilogue and accumulation do not match");
+    // the ring kernel hands its input values to the stage-3 / 2 reverse, which read the same arrays
+    if ((epi == 3 && lam != ab.lnext) || (epi == 2 && lam != ab.lam))
+        throw Error(FVLBM_EINVAL, "adv_transpose: the transposed input is not the stage reverse's");
     if (st->ring) {
         // one launch: the boundary cells' ghost parts are fused into the ring kernel
         const bool s3 = st->ring_s == 3;
