@@ -745,8 +745,10 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             for (int a = 0; a < 9; ++a) hf[a] = b.F_in[(size_t)a * n + hc];
             stage_collide(hf, p.dt * T(0.25) * recip(b.tau[hc]), p.rho0, hv, fe);
         } else {
+            // the rest direction only where a ring-1 cell's ghost states need the moments
+            hv[0] = ring1 ? b.src[hc] : T(0);
 #pragma unroll
-            for (int a = 0; a < 9; ++a) hv[a] = b.src[(size_t)a * n + hc];
+            for (int a = 1; a < 9; ++a) hv[a] = b.src[(size_t)a * n + hc];
         }
 #pragma unroll
         for (int a = 1; a < 9; ++a) V[vrow<T>(kTileCells + t, a - 1)] = hv[a];
