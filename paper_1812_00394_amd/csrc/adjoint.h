@@ -261,48 +261,47 @@ struct AdjBufs {
 // transpose of Ga3 applied to dt/3 lam_{n+1}) and lam_{n+1} = lnext (the adjoint of f^{n+1}).
 // Writes lfn (the adjoint of f^n so far), lf2 (Gc2 part), lf1 (Gc1 part), lam (the Ga2 adjoint and
 // the Ga1 adjoint so far), ltau.
-template <typename T>
 // lnext_c: the cell's lam_{n+1} when the caller holds it already (nullptr: read here).
+// Written in three sections that the scheduler keeps apart (f^(2) and f^(1) are needed only by the
+// later ones), which bounds the values live at once.
+template <typename T>
 __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], const AdjBufs<T> &b, const StepPar<T> &p,
                                                 const T *lnext_c = nullptr) {
-    T fn[9], f1[9], f2[9], f3[9], Q[9], lq[9], l3[9];
     const T tc = b.tau[c];
     const T dt = p.dt;
+    const T itau = recip(tc);
+    // ---- the combination and the third stage: needs f^n, f3, Q ----
+    T fn[9], lq[9], l3[9];
+    T m0 = 0, mx = 0, my = 0, f3d[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         const size_t i = (size_t)a * n + c;
-        fn[a] = b.fn[i]; f2[a] = b.f2[i]; f3[a] = b.f3[i]; Q[a] = b.Q[i];
+        fn[a] = b.fn[i];
+        const T f3a = b.f3[i];
         lq[a] = lnext_c ? lnext_c[a] : b.lnext[i];   // lam_{n+1} = adjoint of Q
         l3[a] = lf3[a] + lq[a];                      // f3 enters Q with weight 1
-    }
-    {
-        T fe[9];
-        stage_collide(fn, dt * T(0.25) * recip(tc), p.rho0, f1, fe);   // f^(1)
+        // f3 = (rhs3 + a3 f_eq(m3)) / (1 + a3), m3 = m(f^n) + dt/2 m(Ga1 + Ga2), Ga1 + Ga2 = 6 (f3 - Q) / dt
+        const T mv = fn[a] + T(3) * (f3a - b.Q[i]);
+        m0 += mv;
+        mx += T(ex(a)) * mv;
+        my += T(ey(a)) * mv;
+        f3d[a] = f3a;
     }
     // Q = f3 - dt/6 (Ga1 + Ga2)
     T lg12[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) lg12[a] = -dt * T(1.0 / 6.0) * lq[a];
-    // f3 = (rhs3 + a3 f_eq(m3)) / (1 + a3), m3 = m(f^n) + dt/2 m(Ga1 + Ga2), Ga1 + Ga2 = 6 (f3 - Q) / dt
-    const T a3 = dt * T(1.0 / 3.0) * recip(tc);
+    const T a3 = dt * T(1.0 / 3.0) * itau;
     const T inv3 = recip(T(1) + a3);
-    T m0 = 0, mx = 0, my = 0;
-#pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const T mv = fn[a] + T(3) * (f3[a] - Q[a]);
-        m0 += mv;
-        mx += T(ex(a)) * mv;
-        my += T(ey(a)) * mv;
-    }
     const T rho3 = p.rho0 + m0, ir3 = recip(rho3), ux3 = mx * ir3, uy3 = my * ir3;
     T lrhs[9], lfe[9], mb[3], abar = 0;
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
         lrhs[a] = l3[a] * inv3;
         lfe[a] = a3 * inv3 * l3[a];
-        abar += l3[a] * (dfeq(a, m0, rho3, ux3, uy3) - f3[a]) * inv3;
+        abar += l3[a] * (dfeq(a, m0, rho3, ux3, uy3) - f3d[a]) * inv3;
     }
-    T ltau = -abar * a3 * recip(tc);
+    T ltau = -abar * a3 * itau;
     feq_vjp(m0, mx, my, p.rho0, lfe, mb);
     T lfn[9];
 #pragma unroll
@@ -312,12 +311,17 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
         lg12[a] += dt * T(0.5) * (mt + lrhs[a]);
     }
     // rhs3 = f^n + dt/2 (Ga1 + Ga2) + dt/3 (Gc1 + Gc2)
-    const T itau = recip(tc);
     T lgc[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) lgc[a] = dt * T(1.0 / 3.0) * lrhs[a];
-    // Gc2 = (f_eq(m(f2)) - f2) / tau
+#pragma unroll
+    for (int a = 0; a < 9; ++a) b.lam[(size_t)a * n + c] = lg12[a];   // Ga2 adjoint, and the Ga1 adjoint so far
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- Gc2 = (f_eq(m(f2)) - f2) / tau: needs f2 ----
     {
+        T f2[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) f2[a] = b.f2[(size_t)a * n + c];
         T q0, qx, qy;
         raw_moments(f2, q0, qx, qy);
         const T r = p.rho0 + q0, ir = recip(r), vx = qx * ir, vy = qy * ir;
@@ -332,8 +336,14 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
         for (int a = 0; a < 9; ++a)
             b.lf2[(size_t)a * n + c] = mb2[0] + T(ex(a)) * mb2[1] + T(ey(a)) * mb2[2] - l[a];
     }
-    // Gc1 = (f_eq(m(f^n)) - f1) / tau
+    __builtin_amdgcn_sched_barrier(0);
+    // ---- Gc1 = (f_eq(m(f^n)) - f1) / tau, f1 = the first stage's solve of f^n ----
     {
+        T f1[9];
+        {
+            T fe[9];
+            stage_collide(fn, dt * T(0.25) * itau, p.rho0, f1, fe);   // f^(1)
+        }
         T q0, qx, qy;
         raw_moments(fn, q0, qx, qy);
         const T r = p.rho0 + q0, ir = recip(r), vx = qx * ir, vy = qy * ir;
@@ -351,11 +361,7 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
         }
     }
 #pragma unroll
-    for (int a = 0; a < 9; ++a) {
-        const size_t i = (size_t)a * n + c;
-        b.lfn[i] = lfn[a];
-        b.lam[i] = lg12[a];     // Ga2 adjoint, and the Ga1 adjoint so far
-    }
+    for (int a = 0; a < 9; ++a) b.lfn[(size_t)a * n + c] = lfn[a];
     b.ltau[c] = ltau;
 }
 
