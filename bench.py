@@ -425,6 +425,16 @@ def main():
             f"(ratio {t_res / t_fwd:.2f})")
         del sta
 
+    per_stage = None
+    if p.get("sst") and not args.no_explicit:
+        # the per-stage SST coupling (params.sst = 2): one more SST launch per step
+        stp, _ = make_state(F, M, dict(flow, sst_stages=1), init, args.precision, dt_frac)
+        ms_p, _, _ = time_steps(F, stp, max(20, args.steps // 4), args.warmup, stream, kernel_timing=False)
+        ms_p /= max(20, args.steps // 4)
+        per_stage = {"ms_per_step": round(ms_p, 4), "over_once_per_step": round(ms_p / (ms / args.steps), 3)}
+        log(f"per-stage SST: {ms_p:.3f} ms/step")
+        del stp
+
     airfoil = airfoil_run(F, args.airfoil_steps) if args.airfoil_steps > 0 else None
     cost_ratio = None if args.no_explicit else imex_vs_explicit(F, M, flow, init, dt_frac)
 
@@ -471,6 +481,7 @@ def main():
         "adjoint": adjoint,
         "airfoil_lift_drag": airfoil,
         "imex_over_explicit_per_step": cost_ratio,
+        "sst_per_stage": per_stage,
         "cpu_baseline": cpu,
         "kernel_source_sha256": source_hash(),
     }

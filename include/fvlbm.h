@@ -67,7 +67,12 @@ typedef struct fvlbm_state fvlbm_state;
  *              (Eq. (turbtau) with nu_t = 0)
  *   dt         time step
  *   rho0       reference density (outlet default; the FP32 mode stores f - w_a rho0)
- *   sst        0: laminar, 1: k-omega SST once per step before the three stages
+ *   sst        0: laminar; 1: k-omega SST once per step before the three stages (Section 3.2,
+ *              Step 1); 2: the SST solved again before the third stage, from k^n, omega^n with the
+ *              second stage's macro variables, for that stage's relaxation time, the step keeping
+ *              this solve's k, omega, nu_t (Step 5 read literally; the second stage's SST inputs
+ *              equal the first's, whose stage solve keeps rho and u).  The adjoint entry points
+ *              reject sst = 2 (FVLBM_ESTATE).
  *   a1 ... beta2  the SST constants listed in Section 2 (C_omega1/2 are derived from them)
  *   theta      inflow angle [rad]: rotates every INLET and FARFIELD velocity
  *   group_*    per boundary group: velocity (u, v), density, k, omega

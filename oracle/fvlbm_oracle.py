@@ -64,7 +64,7 @@ def rmin_mask(a, b):
 def default_params(**kw):
     p = dict(nu=1e-3, dt=1e-2, rho0=1.0, sst=False, theta=0.0,
              group_u=None, group_rho=None, group_k=None, group_w=None, bface_vals=None,
-             jr_group=-1, jr_xmin=0.0, eps_tau=1.0, limiter=0)
+             jr_group=-1, jr_xmin=0.0, eps_tau=1.0, limiter=0, sst_stages=0)
     p.update(SST_DEFAULTS)
     p.update(kw)
     return p
@@ -491,11 +491,15 @@ class Oracle:
     # One IMEX step, Section 3.1: Eqs. (imexone), (sumimeximplicitnew), (fnewstage),
     # (collision), (advection), (imextwo).  tau is frozen over the three stages (reading r12).
     # ---------------------------------------------------------------------------------------
-    def imex_step(self, f, tau):
+    def imex_step(self, f, tau, tau3=None):
+        """tau3: a callable giving the third stage's relaxation time from the second stage's f
+        (the per-stage SST, reading r33); None: tau throughout."""
         dt = self.p["dt"]
         rho_n, jx_n, jy_n = moments(f)
         Ga, Gc = [], []
+        fJ = f
         for J in range(3):
+            tJ = tau3(fJ) if (tau3 is not None and J == 2) else tau
             # Eq. (sumimeximplicitnew): the stage moments need only f^n and earlier convection
             rho, jx, jy = rho_n.copy(), jx_n.copy(), jy_n.copy()
             for kk in range(J):
@@ -506,8 +510,8 @@ class Oracle:
             rhs = f.copy()
             for kk in range(J):
                 rhs = rhs + dt * (MT[J, kk] * Ga[kk] + MI[J, kk] * Gc[kk])
-            fJ, fe = stage_solve(rhs, rho, jx, jy, dt * MI[J, J] / tau)
-            Gc.append(-(fJ - fe) / tau)                       # Eq. (collision)
+            fJ, fe = stage_solve(rhs, rho, jx, jy, dt * MI[J, J] / tJ)
+            Gc.append(-(fJ - fe) / tJ)                        # Eq. (collision)
             Ga.append(self.advection(fJ))                     # Eq. (advection)
         fn1 = f.copy()
         for J in range(3):                                    # Eq. (imextwo)
@@ -552,12 +556,26 @@ class Oracle:
     def step(self, f, k=None, w=None):
         rho, jx, jy = moments(f)
         ux, uy = jx / rho, jy / rho
+        tau3, last = None, {}
         if self.p["sst"]:
-            k, w, nut, tau = self.sst_update(rho, ux, uy, k, w)     # Step 1
+            k0, w0 = k, w
+            k, w, nut, tau = self.sst_update(rho, ux, uy, k0, w0)   # Step 1
+            if self.p.get("sst_stages"):
+                # reading r33: Step 5 repeats Step 1 before every stage, from k^n, omega^n with the
+                # macro variables of the previous stage's f.  The first stage's solve keeps the
+                # collision invariants, so the second stage's SST inputs are the first's and only
+                # the third stage's differ; the step keeps the last solve's k, omega, nu_t.
+                def tau3(f2):
+                    r2, jx2, jy2 = moments(f2)
+                    k3, w3, nut3, t3 = self.sst_update(r2, jx2 / r2, jy2 / r2, k0, w0)
+                    last.update(k=k3, w=w3, nut=nut3, tau=t3)
+                    return t3
         else:
             tau = self.tau_laminar()
             nut = np.zeros(self.g.n)
-        f = self.imex_step(f, tau)                                  # Steps 2-6
+        f = self.imex_step(f, tau, tau3)                            # Steps 2-6
+        if last:
+            k, w, nut = last["k"], last["w"], last["nut"]
         self.last_tau, self.last_nut = tau, nut
         return f, k, w
 

@@ -67,6 +67,8 @@ struct fvlbm_state {
     void *M[2] = {nullptr, nullptr};
     void *K[2] = {nullptr, nullptr}, *W[2] = {nullptr, nullptr};
     void *tau = nullptr, *nut = nullptr, *aux = nullptr;
+    void *tau3 = nullptr;        // the third stage's relaxation time (per-stage SST)
+    int sst_stages = 0;          // the SST is solved before every stage (params.sst = 2)
     int cur_m = 0, cur_kw = 0;
     // tiles of the fused stage kernels: ring (extended halo lists), tiled (ring 1 only, with or
     // without the stage values in LDS) or the two-kernel split path
@@ -170,6 +172,7 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
         st->W[0] = cv.take<T>(n);
         st->W[1] = cv.take<T>(n);
         st->aux = cv.take<T>(15 * n);
+        st->tau3 = cv.take<T>(n);
     }
     st->lnb = cv.take<int16_t>(S);
     st->rev = cv.take<int8_t>(S);
@@ -394,6 +397,36 @@ void stage_ring(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, const Sta
     }
 }
 
+// The SST update (Step 1) from the macro variables M and k, omega = K0, W0 into K1, W1, the
+// relaxation time tau_out and nu_t: one ring launch, or the two split kernels.
+template <typename T>
+void launch_sst(fvlbm_state *st, const T *M, const T *K0, const T *W0, T *K1, T *W1, T *tau_out, const StepPar<T> &p) {
+    const Geo<T> &g = geo_of<T>(st);
+    hipStream_t s = st->stream;
+    T *aux = (T *)st->aux, *nut = (T *)st->nut;
+    if (st->ring) {
+        const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+        const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+        const size_t lds = st->sst_lds_bytes;
+        Timed t(st, FVLBM_K_SST);
+        if (st->ring_s == 3) {
+            if (st->want_aux)
+                k_sst_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+            else
+                k_sst_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+        } else {
+            if (st->want_aux)
+                k_sst_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+            else
+                k_sst_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+        }
+    } else {
+        const int nbk = blocks_for(g.n);
+        { Timed t(st, FVLBM_K_SST_A); k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, M, K0, W0, aux, p); }
+        { Timed t(st, FVLBM_K_SST_B); k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p); }
+    }
+}
+
 template <typename T>
 void launch_step(fvlbm_state *st) {
     const Geo<T> &g = geo_of<T>(st);
@@ -405,37 +438,31 @@ void launch_step(fvlbm_state *st) {
     T *Mcur = (T *)st->M[st->cur_m], *Mnew = (T *)st->M[st->cur_m ^ 1];
     T *tau = (T *)st->tau;
     const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+    T *K0 = nullptr, *W0 = nullptr, *K1 = nullptr, *W1 = nullptr;
     if (st->sst) {
-        T *K0 = (T *)st->K[st->cur_kw], *W0 = (T *)st->W[st->cur_kw];
-        T *K1 = (T *)st->K[st->cur_kw ^ 1], *W1 = (T *)st->W[st->cur_kw ^ 1];
-        T *aux = (T *)st->aux, *nut = (T *)st->nut;
-        if (st->ring) {
-            const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
-            const size_t lds = st->sst_lds_bytes;
-            Timed t(st, FVLBM_K_SST);
-            if (st->ring_s == 3) {
-                if (st->want_aux)
-                    k_sst_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
-                else
-                    k_sst_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
-            } else {
-                if (st->want_aux)
-                    k_sst_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
-                else
-                    k_sst_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p);
-            }
-        } else {
-            { Timed t(st, FVLBM_K_SST_A); k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, aux, p); }
-            { Timed t(st, FVLBM_K_SST_B); k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, Mcur, K0, W0, aux, K1, W1, tau, nut, p); }
-        }
+        K0 = (T *)st->K[st->cur_kw];
+        W0 = (T *)st->W[st->cur_kw];
+        K1 = (T *)st->K[st->cur_kw ^ 1];
+        W1 = (T *)st->W[st->cur_kw ^ 1];
+        launch_sst<T>(st, Mcur, K0, W0, K1, W1, tau, p);
         st->cur_kw ^= 1;
     }
-    const StageBufs<T> b1{X, F, tau, A, Y, nullptr, nullptr};
-    const StageBufs<T> b2{Y, F, tau, A, X, nullptr, nullptr};
+    // per-stage SST (reading of Step 5): stage 1 also writes the stage-2 macro variables (into the
+    // buffer stage 3 fills at the end), from which the SST is solved again, from k^n, omega^n, for
+    // the third stage's relaxation time; the step keeps that solve's k, omega, nu_t.  The second
+    // stage's SST inputs are the first's (the first stage's solve keeps rho and u).
+    const bool per_stage = st->sst && st->sst_stages;
+    T *tau3 = (T *)st->tau3;
+    const StageBufs<T> b1{X, F, tau, A, Y, nullptr, per_stage ? Mnew : nullptr};
+    const StageBufs<T> b2{Y, F, tau, A, X, nullptr, nullptr, per_stage ? tau3 : nullptr};
     const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, st->F_out ? (T *)st->F_out : F, Mnew};
+    auto sst_stage3 = [&] {
+        if (per_stage) launch_sst<T>(st, Mnew, K0, W0, K1, W1, tau3, p);
+    };
     if (st->ring) {
         // stage 1 takes f^(1) from f^n on the fly: no separate collision launch
         { Timed t(st, FVLBM_K_SWEEP1); stage_ring<T, 1>(st, g, rt, b1, p, s); }
+        sst_stage3();
         { Timed t(st, FVLBM_K_SWEEP2); stage_ring<T, 2>(st, g, rt, b2, p, s); }
         { Timed t(st, FVLBM_K_SWEEP3); stage_ring<T, 3>(st, g, rt, b3, p, s); }
         st->cur_m ^= 1;
@@ -449,16 +476,19 @@ void launch_step(fvlbm_state *st) {
         const int nth = kTileCells + kHaloThreads;
         if (st->tile_vals) {
             { Timed t(st, FVLBM_K_SWEEP1); k_stage_tiled<T, 1, true><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b1, p); }
+            sst_stage3();
             { Timed t(st, FVLBM_K_SWEEP2); k_stage_tiled<T, 2, true><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b2, p); }
             { Timed t(st, FVLBM_K_SWEEP3); k_stage_tiled<T, 3, true><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b3, p); }
         } else {
             { Timed t(st, FVLBM_K_SWEEP1); k_stage_tiled<T, 1, false><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b1, p); }
+            sst_stage3();
             { Timed t(st, FVLBM_K_SWEEP2); k_stage_tiled<T, 2, false><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b2, p); }
             { Timed t(st, FVLBM_K_SWEEP3); k_stage_tiled<T, 3, false><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b3, p); }
         }
     } else {
         { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
         { Timed t(st, FVLBM_K_SWEEP1); k_sweep<T, 1><<<nbk, kBlock, 0, s>>>(g, G, b1, p); }
+        sst_stage3();
         { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, Y, G, p.rho0); }
         { Timed t(st, FVLBM_K_SWEEP2); k_sweep<T, 2><<<nbk, kBlock, 0, s>>>(g, G, b2, p); }
         { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
@@ -480,16 +510,8 @@ void launch_explicit(fvlbm_state *st) {
     T *Mcur = (T *)st->M[st->cur_m], *Mnew = (T *)st->M[st->cur_m ^ 1];
     const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
     if (st->sst) {
-        T *K0 = (T *)st->K[st->cur_kw], *W0 = (T *)st->W[st->cur_kw];
-        T *K1 = (T *)st->K[st->cur_kw ^ 1], *W1 = (T *)st->W[st->cur_kw ^ 1];
-        const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
-        Timed t(st, FVLBM_K_SST);
-        if (st->ring_s == 3)
-            k_sst_ring<T, 3, false><<<nt, kTileCells, st->sst_lds_bytes, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0,
-                                                                          (T *)st->aux, K1, W1, tau, (T *)st->nut, p);
-        else
-            k_sst_ring<T, 4, false><<<nt, kTileCells, st->sst_lds_bytes, s>>>(g, rt, st->lnb, wv, wg, st->bzg, Mcur, K0, W0,
-                                                                          (T *)st->aux, K1, W1, tau, (T *)st->nut, p);
+        launch_sst<T>(st, Mcur, (const T *)st->K[st->cur_kw], (const T *)st->W[st->cur_kw], (T *)st->K[st->cur_kw ^ 1],
+                      (T *)st->W[st->cur_kw ^ 1], tau, p);
         st->cur_kw ^= 1;
     }
     const StageBufs<T> b0{F, nullptr, tau, nullptr, nullptr, X, Mnew};
@@ -1146,6 +1168,7 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV) throw Error(FVLBM_EINVAL, "init: bad precision");
         if (p->n_groups != m->n_groups) throw Error(FVLBM_EINVAL, "init: params.n_groups differs from the mesh");
         if (!(p->nu > 0) || !(p->dt > 0) || !(p->rho0 > 0)) throw Error(FVLBM_EINVAL, "init: nu, dt and rho0 must be > 0 (tau = 3 nu)");
+        if (p->sst < 0 || p->sst > 2) throw Error(FVLBM_EINVAL, "init: sst must be 0, 1 or 2");
         if (p->sst && (!k || !omega)) throw Error(FVLBM_EINVAL, "init: SST needs k and omega");
         if (p->limiter != 0 && p->limiter != 1) throw Error(FVLBM_EINVAL, "init: limiter must be 0 or 1");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "init: workspace must be 256-byte aligned");
@@ -1155,6 +1178,7 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         st->mesh = m;
         st->precision = precision;
         st->sst = p->sst ? 1 : 0;
+        st->sst_stages = p->sst == 2 ? 1 : 0;
         st->par = *p;
         st->par.bface_vals = nullptr;   // only used here, the caller's array is not kept
         st->stream = reinterpret_cast<hipStream_t>(hip_stream);
@@ -1384,6 +1408,7 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
         if (!st || !workspace) throw Error(FVLBM_EINVAL, "record: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
         if (st->par.limiter) throw Error(FVLBM_ESTATE, "record: the limited convection has no adjoint here");
+        if (st->sst_stages) throw Error(FVLBM_ESTATE, "record: the per-stage SST coupling has no adjoint here");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");
         size_t need = 0;
         fvlbm_status e = fvlbm_adjoint_bytes(st->mesh, st->precision, n_steps, ckpt_every, &need);

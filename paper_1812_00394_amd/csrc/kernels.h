@@ -203,14 +203,17 @@ __global__ void __launch_bounds__(256) k_collide1(int n, const T *__restrict__ F
 // the loads early; members a stage does not use are dead code.
 template <typename T>
 struct EpiOps {
-    T fn[9], a[9], tc;
+    T fn[9], a[9], tc, tc3;
 };
 
-// Buffers of one stage sweep: src = the stage field whose convection term is taken.
+// Buffers of one stage sweep: src = the stage field whose convection term is taken.  M: stage 3
+// writes rho - rho0, u there; stage 1 writes the moments of f^(2) there when given (the per-stage
+// SST reads them).  tau3: the third stage's relaxation time when it differs (per-stage SST).
 template <typename T>
 struct StageBufs {
     const T *src, *F_in, *tau;
     T *A, *out, *F_out, *M;
+    const T *tau3;
 };
 
 template <typename T, int J>
@@ -230,6 +233,7 @@ __device__ __forceinline__ void load_ops(const StageBufs<T> &b, int c, int n, Ep
 #pragma unroll
             for (int a = 0; a < 9; ++a) o.a[a] = b.A[(size_t)a * n + c];
         }
+        o.tc3 = b.tau3 ? b.tau3[c] : o.tc;
     }
 }
 
@@ -237,7 +241,7 @@ __device__ __forceinline__ void load_ops(const StageBufs<T> &b, int c, int n, Ep
 // recovers it.
 template <typename T>
 __device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const EpiOps<T> &o, T *__restrict__ Y,
-                                          T *__restrict__ A, const StepPar<T> &p) {
+                                          T *__restrict__ A, T *__restrict__ M2, const StepPar<T> &p) {
     T rhs[9], f2[9], fe[9];
     const T h = p.dt * T(0.5);
 #pragma unroll
@@ -248,6 +252,14 @@ __device__ __forceinline__ void epilogue1(int c, int n, const T ga[9], const Epi
     if (!p.recover) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) A[(size_t)a * n + c] = ga[a];
+    }
+    if (M2) {
+        // the stage-2 macro variables, for the third stage's SST
+        T drho, rho, ux, uy;
+        moments(f2, p.rho0, drho, rho, ux, uy);
+        M2[c] = drho;
+        M2[(size_t)n + c] = ux;
+        M2[(size_t)2 * n + c] = uy;
     }
 }
 
@@ -285,7 +297,7 @@ __device__ __forceinline__ void epilogue2(int c, int n, const T f2[9], const T g
     }
     const T rho3 = p.rho0 + m0;
     const T ir3 = recip(rho3);
-    stage_collide_m(rhs, h3 * itau, m0, rho3, mx * ir3, my * ir3, f3);
+    stage_collide_m(rhs, h3 * recip(o.tc3), m0, rho3, mx * ir3, my * ir3, f3);
     const T h6 = p.dt * T(1.0 / 6.0);
 #pragma unroll
     for (int a = 0; a < 9; ++a) {
@@ -337,7 +349,7 @@ __device__ __forceinline__ void stage_epilogue_ops(int c, int n, const T gc[9], 
     if constexpr (J == 0)
         epilogue_explicit(c, n, gc, ga, o, b.F_out, b.M, p);
     else if constexpr (J == 1)
-        epilogue1(c, n, ga, o, b.out, b.A, p);
+        epilogue1(c, n, ga, o, b.out, b.A, b.M, p);
     else if constexpr (J == 2)
         epilogue2(c, n, gc, ga, o, b.out, b.A, p);
     else

@@ -179,7 +179,7 @@ def make_params(p, n_groups, n_bfaces=None):
     """Builds the C parameter struct from a dictionary (keys as in the header)."""
     s = Params()
     s.nu, s.dt, s.rho0 = float(p["nu"]), float(p["dt"]), float(p.get("rho0", 1.0))
-    s.sst = int(bool(p.get("sst", False)))
+    s.sst = (2 if p.get("sst_stages") else 1) if p.get("sst", False) else 0
     s.n_groups = n_groups
     c = dict(SST_CONSTANTS)
     c.update({k: p[k] for k in SST_CONSTANTS if k in p})

@@ -211,6 +211,48 @@ def test_sst_step_parity(F, name, sweep, monkeypatch):
         assert rel(mo["nu_t"], orc.last_nut, np.abs(orc.last_nut).max()) < tol * 10, ("nu_t", nsteps)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("name", ["backstep_coarse", "naca"])
+def test_sst_per_stage_step_parity(F, name, sweep, precision, monkeypatch):
+    """The SST solved again before the third stage (params.sst = 2, reading r33): the second SST
+    launch from k^n, omega^n with the stage-2 macro variables that stage 1 writes, the third stage's
+    relaxation time, the step keeping that solve's k, omega, nu_t.  FP64 to the SST gates; FP32-dev
+    to 2e-6 of U for u and 2e-6 relative for k, omega after one step."""
+    say("sst per-stage step", name, sweep, precision)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
+    make, extra = SST_MESHES[name]
+    m = make()
+    orc, p, f, k, w = _sst_case(m, extra, 52)
+    p = dict(p, sst_stages=1)
+    orc = O.Oracle(m, p)
+    st = F.State(F.Mesh(m), p, precision=precision, k=k, omega=w)
+    st.set_state(f, k, w)
+    once = O.Oracle(m, dict(p, sst_stages=0))
+    f1o, k1o, _ = once.step(f, k, w)
+    fo, ko, wo = f, k, w
+    for nsteps, tol in ((1, 1e-12), (3, 1e-11)):
+        fo, ko, wo = orc.run(fo, ko, wo, nsteps)
+        st.step(nsteps)
+        mo = st.moments()
+        if precision == "fp64":
+            got = st.get_f()
+            assert rel(got, fo, dev_scale(fo)) < tol, ("f", nsteps, rel(got, fo, dev_scale(fo)))
+            assert rel(mo["k"], ko, np.abs(ko).max()) < tol * 10, ("k", nsteps)
+            assert rel(mo["omega"], wo, np.abs(wo).max()) < tol * 10, ("w", nsteps)
+            assert rel(mo["nu_t"], orc.last_nut, np.abs(orc.last_nut).max()) < tol * 10, ("nu_t", nsteps)
+        elif nsteps == 1:
+            _, ux, uy, _ = orc.macro(fo)
+            du = max(np.abs(mo["u"][:, 0] - ux).max(), np.abs(mo["u"][:, 1] - uy).max()) / 0.05
+            assert du < 2e-6, du
+            assert rel(mo["k"], ko, np.abs(ko).max()) < 2e-6 and rel(mo["omega"], wo, np.abs(wo).max()) < 2e-6
+        if nsteps == 1:
+            # the variant is active: its k differs from the once-per-step coupling's
+            assert rel(ko, k1o, np.abs(k1o).max()) > 1e-9
+    with pytest.raises(F.FvlbmError):
+        st.record(2, ckpt_every=1)
+
+
 def test_sst_impulsive_start_parity(F):
     """Uniform stream started impulsively between walls: the positivity bound of the k / omega
     face values and the implicit negative sources are active on both sides."""

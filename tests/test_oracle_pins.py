@@ -711,3 +711,60 @@ def test_explicit_step_first_order_in_time():
         errs.append(abs(amp - np.exp(-2 * nu * nsteps * orc.p["dt"])))
     # both schemes are within a few percent; the time error shrinks with dt
     assert errs[0] < 0.05 and errs[1] < errs[0]
+
+
+# ------------------------------------------------------------------------------------------------
+# Reading r33, the per-stage SST coupling (Step 5 read literally): the third stage's relaxation
+# time comes from an SST solve from k^n, omega^n with the second stage's macro variables.
+# ------------------------------------------------------------------------------------------------
+def _r33_case(uniform):
+    m = mg.rectangle(10, 8, kind="periodic", jitter=0.0 if uniform else 0.25, seed=71)
+    nu = 1e-4
+    p = O.default_params(nu=nu, dt=40 * 3 * nu, sst=True)
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    rng = np.random.default_rng(72)
+    x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+    if uniform:
+        ux, uy = np.full(n, 0.03), np.full(n, -0.01)
+        k, w = np.full(n, 1e-4), np.full(n, 0.5)
+    else:
+        ux = 0.04 * np.sin(2 * np.pi * y) + 0.003 * rng.standard_normal(n)
+        uy = 0.02 * np.cos(2 * np.pi * x) + 0.003 * rng.standard_normal(n)
+        k = 1e-4 * (1 + 0.5 * rng.random(n))
+        w = 0.5 * (1 + 0.5 * rng.random(n))
+    f, k, w = orc.init_state(np.ones(n), ux, uy, k, w)
+    return m, p, f, k, w
+
+
+def test_sst_per_stage_reduces_to_once_per_step_for_uniform_flow():
+    """A uniform stream on a periodic mesh has no convection, so every stage has the macro
+    variables of f^n and the per-stage coupling is the once-per-step one."""
+    m, p, f, k, w = _r33_case(True)
+    a = O.Oracle(m, dict(p, sst_stages=0)).step(f, k, w)
+    b = O.Oracle(m, dict(p, sst_stages=1)).step(f, k, w)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(y, x, rtol=0, atol=1e-15 * np.abs(x).max())
+
+
+def test_sst_per_stage_uses_the_second_stage_moments():
+    """k^{n+1}, omega^{n+1} of the per-stage step equal an SST solve from k^n, omega^n with the
+    second stage's macro variables, formed here from Eq. (sumimeximplicitnew): the moments of
+    f^n plus dt/2 those of the convection term of f^(1) = the first stage's solve of f^n."""
+    m, p, f, k, w = _r33_case(False)
+    orc = O.Oracle(m, dict(p, sst_stages=1))
+    _, k1, w1 = orc.step(f, k, w)
+    ref = O.Oracle(m, dict(p, sst_stages=0))
+    rho, jx, jy = O.moments(f)
+    tau = ref.sst_update(rho, jx / rho, jy / rho, k, w)[3]
+    dt = p["dt"]
+    f1, _ = O.stage_solve(f, rho, jx, jy, dt / 4 / tau)
+    r_a, jx_a, jy_a = O.moments(ref.advection(f1))
+    rho2, jx2, jy2 = rho + dt / 2 * r_a, jx + dt / 2 * jx_a, jy + dt / 2 * jy_a
+    k2, w2, _, _ = ref.sst_update(rho2, jx2 / rho2, jy2 / rho2, k, w)
+    np.testing.assert_allclose(k1, k2, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(w1, w2, rtol=1e-13, atol=0)
+    # and the coupling changes the result against the once-per-step one
+    k_once = ref.step(f, k, w)[1]
+    assert np.abs(k1 - k_once).max() > 1e-6 * np.abs(k_once).max()
+
