@@ -1,16 +1,18 @@
-// HIP kernels of one IMEX step (gfx950).  One thread per cell; cells are renumbered along a
-// space-filling curve so that neighbour gathers of a wavefront hit a few cache lines.
+// HIP kernels of one IMEX step (gfx950).  Cells are renumbered along a space-filling curve so that
+// neighbour gathers of a wavefront hit a few cache lines.  The ring-tiled kernels (k_sst_ring,
+// k_stage_ring) are the main path; the one-thread-per-cell kernels below them are its fallbacks.
 //
 // Per step (Section 3.2 algorithm, SST once per step before the stages):
-//   sst_a    LSQ gradients of u, v, k, omega; S, div u, CD, F1, F2, mu_t, blending, sources
-//   sst_b    k / omega face fluxes (2nd-order upwind convection, central diffusion), point-implicit
+//   sst      LSQ gradients of u, v, k, omega; S, div u, CD, F1, F2, mu_t, blending, sources; k /
+//            omega face fluxes (2nd-order upwind convection, central diffusion), point-implicit
 //            update, nu_t from the updated k, omega, tau = 3 (nu + nu_t)        [Eq. (turbtau)]
-//   collide1 f^(1) from f^n (stage 1 has no earlier convection term)          [Eq. (fnewstage)]
-//   grad     LSQ gradient of the stage field (16 planes: directions 1..8)
+//            (fallback: sst_a, sst_b)
 //   sweep<J> convection term of stage J [Eq. (advection)] fused with the cell-local epilogue:
-//            J=1: f^(2) = solve(f^n + dt/2 Ga1)          (stores Ga1)
+//            J=1: f^(1) = solve(f^n) on the fly [Eq. (fnewstage)], its convection term Ga1,
+//                 f^(2) = solve(f^n + dt/2 Ga1)          (stores Ga1 unless stage 2 recovers it)
 //            J=2: f^(3) = solve(f^n + dt/2 (Ga1+Ga2) + dt/3 (Gc1+Gc2));  Q = f^(3) - dt/6 (Ga1+Ga2)
 //            J=3: f^{n+1} = Q + dt/3 Ga3                    (= Eq. (imextwo), see below)
+//            (fallback: collide1 writes f^(1), grad writes the 16 gradient planes, sweep reads them)
 // Eq. (imextwo) with n~ = n = 1/3: f^{n+1} = f^n + dt/3 sum Ga + dt/3 sum Gc.  Since the third
 // stage satisfies f^(3) = rhs3 + dt/3 Gc3 and rhs3 = f^n + dt/2 (Ga1+Ga2) + dt/3 (Gc1+Gc2), this is
 // f^{n+1} = f^(3) + dt/3 Ga3 - dt/6 (Ga1 + Ga2): no stored collision terms are needed.
