@@ -212,12 +212,17 @@ def cpu_baseline(mesh_sample_points, steps):
     n = G.n
     u, k0, w0 = initial_fields(dict(profile="channel", U=U, H=H, k=1e-6, w=1e-2), G.xc, nu)
     f, k, w = orc.init_state(np.ones(n), u[:, 0], u[:, 1], k0, w0)
-    c0 = time.process_time()
-    t0 = time.perf_counter()
-    orc.run(f, k, w, steps)
-    dt = time.perf_counter() - t0
-    cores = max(1, round((time.process_time() - c0) / dt))
-    return n, steps, dt, cores
+    from threadpoolctl import threadpool_limits
+    out = {}
+    for label, limit in (("one_thread", 1), ("all_threads", None)):
+        # the BLAS / OpenMP pools numpy may use: one thread, then the host's default
+        with threadpool_limits(limits=limit):
+            c0 = time.process_time()
+            t0 = time.perf_counter()
+            orc.run(f, k, w, steps)
+            dt = time.perf_counter() - t0
+            out[label] = (dt, max(1, round((time.process_time() - c0) / dt)))
+    return n, steps, out
 
 
 def imex_vs_explicit(F, M_big, flow_big, init_big, dt_frac_big):
@@ -362,7 +367,9 @@ def main():
     traffic = measured_traffic(dominant, args.workload, args.precision)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": dominant, "algorithmic_bytes_per_launch": kb[dominant] * n}
+                "kernel": dominant, "algorithmic_bytes_per_launch": kb[dominant] * n,
+                # the counters' HBM bytes over the same duration (the rate the memory delivered)
+                "traffic_gbs": round(traffic / (dk["ms_avg"] * 1e-3) / 1e9, 1) if traffic else None}
     sb = step_bytes(T, S)
     step_gbs = sb * n * args.steps / (ms * 1e-3) / 1e9
 
@@ -440,11 +447,16 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cn, csteps, cdt, ccores = cpu_baseline(args.cpu_sample_points, args.cpu_steps)
-        cpu = {"value": round(cn * csteps / cdt / 1e6, 4), "unit": "MLUPS", "cores": ccores, "kind": "oracle",
+        cn, csteps, runs = cpu_baseline(args.cpu_sample_points, args.cpu_steps)
+        cdt, _ = runs["one_thread"]
+        adt, acores = runs["all_threads"]
+        cpu = {"value": round(cn * csteps / cdt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
                "sample": f"the same generator at {cn} cells (graded Delaunay rectangle, SST, FP64), "
-                         f"{csteps} IMEX steps in {cdt:.1f} s (numpy oracle, {os.cpu_count()} host cores visible)"}
-        log(f"cpu oracle: {cpu['value']} MLUPS on {cn} cells")
+                         f"{csteps} IMEX steps in {cdt:.1f} s (numpy oracle, thread pools limited to one)",
+               "all_threads": {"value": round(cn * csteps / adt / 1e6, 4), "cores": acores,
+                               "host_cores_visible": os.cpu_count()}}
+        log(f"cpu oracle: {cpu['value']} MLUPS on {cn} cells (1 thread), "
+            f"{cpu['all_threads']['value']} MLUPS with {acores} threads busy")
 
     if args.copy_calibration:
         x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
