@@ -309,7 +309,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-points", type=int, default=40_000)
-    ap.add_argument("--cpu-steps", type=int, default=12)
+    ap.add_argument("--cpu-steps", type=int, default=30)
     ap.add_argument("--adjoint-steps", type=int, default=50, help="recorded steps of the adjoint timing (0: skip)")
     ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the adjoint")
     ap.add_argument("--no-explicit", action="store_true", help="skip the IMEX / explicit cost comparison")
