@@ -14,7 +14,7 @@ Paper: Wang, Zhong, Cao, Zhuo, "A simplified finite volume lattice Boltzmann met
 Extension towards turbulent flow simulation" (arXiv 1812.00394).  Citations below name the
 section and equation label of that paper.  Where the paper defers to its Part I (equilibrium,
 face values, gradients, boundary conditions) or is garbled, the readings used are listed at the
-top of each function and collected in the design notes (readings r1-r27).
+top of each function and collected in the design notes (readings r1-r34).
 
 Half-face convention: every cell edge, seen from its cell, is one "half-face" h with
   cell[h], nbr[h] (-1 on a boundary), bface[h] (-1 inside), nl[h] = outward normal times length,
@@ -64,10 +64,21 @@ def rmin_mask(a, b):
 def default_params(**kw):
     p = dict(nu=1e-3, dt=1e-2, rho0=1.0, sst=False, theta=0.0,
              group_u=None, group_rho=None, group_k=None, group_w=None, bface_vals=None,
-             jr_group=-1, jr_xmin=0.0, eps_tau=1.0, limiter=0, sst_stages=0)
+             jr_group=-1, jr_xmin=0.0, eps_tau=1.0, limiter=0, sst_stages=0, sst_sweeps=0)
     p.update(SST_DEFAULTS)
     p.update(kw)
     return p
+
+
+def jacobi(A, b, sweeps):
+    """`sweeps` Jacobi iterations x <- (b - (A - D) x) / D from x = 0, D = diag(A) (reading r34)."""
+    import scipy.sparse as sp
+    d = A.diagonal()
+    off = (A - sp.diags(d)).tocsr()
+    x = np.zeros(np.shape(b), dtype=np.result_type(A.dtype, b))
+    for _ in range(sweeps):
+        x = (b - off @ x) / d
+    return x
 
 
 # =============================================================================================
@@ -439,43 +450,34 @@ class Oracle:
         rc = G.xf - G.xc[hc]
         Gk_cell = mu + sig_k * mut
         Gw_cell = mu + sig_w * mut
-        out = []
-        for phi, gphi, ghost, Gcell in ((k, gkw[0], gk, Gk_cell), (w, gkw[1], gw, Gw_cell)):
-            # convective: mdot * upwind reconstructed value
-            # reading r28: the reconstructed upwind value is kept in [0, 2 phi_up] (positivity;
-            # inactive where |grad phi . r| <= phi_up, i.e. in smooth regions)
-            v_self = phi[hc] + gphi[0, hc] * rc[:, 0] + gphi[1, hc] * rc[:, 1]
-            v_self = rmin(rmax(v_self, 0.0), 2.0 * phi[hc])
-            fv = v_self.copy()
-            rn = G.xf[inner] - G.xs[inner]
-            v_nbr = phi[nb] + gphi[0, nb] * rn[:, 0] + gphi[1, nb] * rn[:, 1]
-            v_nbr = rmin(rmax(v_nbr, 0.0), 2.0 * phi[nb])
-            fv[inner] = np.where(np.real(mdot[inner]) >= 0, v_self[inner], v_nbr)
-            fv[bh] = np.where(np.real(mdot[bh]) >= 0, v_self[bh], ghost)
-            conv = mdot * fv
-            # diffusive (reading r30): Gamma_f (grad phi_f . n) dl with the two-point central
-            # difference along the centroid line, grad phi_f = (phi_N - phi_c) / |d| d^
-            diff = np.zeros(H, dtype=cdt)
-            dvec = G.d[inner]
-            dist = np.sqrt(dvec[:, 0] ** 2 + dvec[:, 1] ** 2)
-            dh = dvec / dist[:, None]
-            dq = (phi[nb] - phi[hc[inner]]) / dist
-            gfx = dq * dh[:, 0]
-            gfy = dq * dh[:, 1]
-            Gf = 0.5 * (Gcell[hc[inner]] + Gcell[nb])
-            diff[inner] = Gf * (gfx * G.nl[inner, 0] + gfy * G.nl[inner, 1])
-            dirichlet = ~zg
-            diff[bh] = np.where(dirichlet, Gcell[c] * (ghost - phi[c]) / dperp * G.l[bh], 0.0)
-            out.append(self._cell_sum(-conv + diff))
-        net_k, net_w = out
+        net_k = self._sst_net(k, gkw[0], gk, Gk_cell, mdot, zg, dperp)
+        net_w = self._sst_net(w, gkw[1], gw, Gw_cell, mdot, zg, dperp)
         # reading r29: the negative part of each explicit source moves into the implicit
         # denominator (divided by the old value), so a negative source cannot flip the sign
         src_k = P
         src_w = Pw + cross
         pos_k, neg_k = rmax(src_k, 0.0), rmax(-src_k, 0.0)
         pos_w, neg_w = rmax(src_w, 0.0), rmax(-src_w, 0.0)
-        k1 = (k + dt / (rho * G.area) * net_k + dt / rho * pos_k) / (1 + dt * bstar * w + dt / rho * neg_k / k)
-        w1 = (w + dt / (rho * G.area) * net_w + dt / rho * pos_w) / (1 + dt * beta * w + dt / rho * neg_w / w)
+        sweeps = int(p.get("sst_sweeps", 0))
+        if sweeps > 0:
+            # reading r34 (the Code_Saturne-style implicit variant): backward Euler for the
+            # increment delta = phi^{n+1} - phi^n, with the first-order upwind convection and the
+            # two-point diffusion taken at n+1 (level-n mass fluxes, coefficients and upwind
+            # sides), the rest of the second-order flux deferred to level n, the sinks as in r29:
+            #   (sink - dt / (rho A) L) delta = R,  R = the explicit increment before the sinks act,
+            # solved with `sweeps` Jacobi sweeps from delta = 0
+            fac = dt / (rho * G.area)
+            sink_k = 1 + dt * bstar * w + dt / rho * neg_k / k
+            sink_w = 1 + dt * beta * w + dt / rho * neg_w / w
+            R_k = fac * net_k + dt / rho * src_k - dt * bstar * w * k
+            R_w = fac * net_w + dt / rho * src_w - dt * beta * w * w
+            A_k = self.sst_system(sink_k, fac, Gk_cell, mdot, zg, dperp)
+            A_w = self.sst_system(sink_w, fac, Gw_cell, mdot, zg, dperp)
+            k1 = k + jacobi(A_k, R_k, sweeps)
+            w1 = w + jacobi(A_w, R_w, sweeps)
+        else:
+            k1 = (k + dt / (rho * G.area) * net_k + dt / rho * pos_k) / (1 + dt * bstar * w + dt / rho * neg_k / k)
+            w1 = (w + dt / (rho * G.area) * net_w + dt / rho * pos_w) / (1 + dt * beta * w + dt / rho * neg_w / w)
         k1 = rmax(k1, 1e-20)
         w1 = rmax(w1, 1e-20)
         # eddy viscosity from the updated k, omega (F2 re-evaluated), strain from level n
@@ -486,6 +488,80 @@ class Oracle:
         tau = (nu + nut) / CS2                                     # Eq. (turbtau)
         self.last_sst = dict(F1=F1, F2=F2, mut=mut, S=S, P=P, CD=CD, div=div)
         return k1, w1, nut, tau
+
+
+    def sst_flux_matrix(self, Gcell, mdot, zg, dperp):
+        """L [N, N] (scipy sparse): the net inflow of a transported SST variable with first-order
+        upwind convection (mass fluxes mdot fixed) and the two-point diffusion of Eq. (SSTequint)
+        (cell coefficients Gcell fixed), as a linear function of the variable; the fixed boundary
+        values contribute a constant, not part of L (reading r34)."""
+        import scipy.sparse as sp
+        G = self.g
+        inner = np.nonzero(G.interior)[0]
+        ci, nb = G.cell[inner], G.nbr[inner]
+        mi = mdot[inner]
+        dv = G.d[inner]
+        D = 0.5 * (Gcell[ci] + Gcell[nb]) * (dv[:, 0] * G.nl[inner, 0] + dv[:, 1] * G.nl[inner, 1]) \
+            / (dv[:, 0] ** 2 + dv[:, 1] ** 2)
+        own = np.real(mi) >= 0
+        # interior edge, seen from c: -mdot phi_upwind + D (phi_N - phi_c)
+        a_cc = -np.where(own, mi, 0.0) - D
+        a_cn = -np.where(own, 0.0, mi) + D
+        bh, cb = G.bidx, self.b_cell
+        mb = mdot[bh]
+        # boundary edge: the cell's value leaves (outflow) or stands for the ghost (zero-gradient);
+        # Dirichlet diffusion Gamma_c (phi_b - phi_c) l / d_perp
+        a_bb = -np.where(zg | (np.real(mb) >= 0), mb, 0.0) - np.where(zg, 0.0, Gcell[cb] * G.l[bh] / dperp)
+        rows = np.concatenate([ci, ci, cb])
+        cols = np.concatenate([ci, nb, cb])
+        vals = np.concatenate([a_cc, a_cn, a_bb])
+        return sp.csr_matrix((vals, (rows, cols)), shape=(G.n, G.n))
+
+    def sst_system(self, sink, fac, Gcell, mdot, zg, dperp):
+        """The implicit SST system matrix diag(sink) - diag(dt / (rho A)) L (reading r34)."""
+        import scipy.sparse as sp
+        return (sp.diags(sink) - sp.diags(fac) @ self.sst_flux_matrix(Gcell, mdot, zg, dperp)).tocsr()
+
+    def _sst_net(self, phi, gphi, ghost, Gcell, mdot, zg, dperp):
+        """Net inflow of one transported SST variable per cell (Eq. (SSTequint) summed over the
+        edges): second-order upwind convection with the level-n face mass fluxes mdot, central
+        diffusion with the cell coefficients Gcell; boundary ghost values ghost [nb], zero-gradient
+        edges zg.  gphi [2, N] is the LSQ gradient of phi (zero: first-order upwind)."""
+        G = self.g
+        hc = G.cell
+        inner = np.nonzero(G.interior)[0]
+        nb = G.nbr[inner]
+        bh = G.bidx
+        c = self.b_cell
+        H = len(hc)
+        rc = G.xf - G.xc[hc]
+        cdt = np.result_type(mdot, phi, Gcell, ghost)
+        # convective: mdot * upwind reconstructed value
+        # reading r28: the reconstructed upwind value is kept in [0, 2 phi_up] (positivity;
+        # inactive where |grad phi . r| <= phi_up, i.e. in smooth regions)
+        v_self = phi[hc] + gphi[0, hc] * rc[:, 0] + gphi[1, hc] * rc[:, 1]
+        v_self = rmin(rmax(v_self, 0.0), 2.0 * phi[hc])
+        fv = v_self.copy()
+        rn = G.xf[inner] - G.xs[inner]
+        v_nbr = phi[nb] + gphi[0, nb] * rn[:, 0] + gphi[1, nb] * rn[:, 1]
+        v_nbr = rmin(rmax(v_nbr, 0.0), 2.0 * phi[nb])
+        fv[inner] = np.where(np.real(mdot[inner]) >= 0, v_self[inner], v_nbr)
+        fv[bh] = np.where(np.real(mdot[bh]) >= 0, v_self[bh], ghost)
+        conv = mdot * fv
+        # diffusive (reading r30): Gamma_f (grad phi_f . n) dl with the two-point central
+        # difference along the centroid line, grad phi_f = (phi_N - phi_c) / |d| d^
+        diff = np.zeros(H, dtype=cdt)
+        dvec = G.d[inner]
+        dist = np.sqrt(dvec[:, 0] ** 2 + dvec[:, 1] ** 2)
+        dh = dvec / dist[:, None]
+        dq = (phi[nb] - phi[hc[inner]]) / dist
+        gfx = dq * dh[:, 0]
+        gfy = dq * dh[:, 1]
+        Gf = 0.5 * (Gcell[hc[inner]] + Gcell[nb])
+        diff[inner] = Gf * (gfx * G.nl[inner, 0] + gfy * G.nl[inner, 1])
+        dirichlet = ~zg
+        diff[bh] = np.where(dirichlet, Gcell[c] * (ghost - phi[c]) / dperp * G.l[bh], 0.0)
+        return self._cell_sum(-conv + diff)
 
     # ---------------------------------------------------------------------------------------
     # One IMEX step, Section 3.1: Eqs. (imexone), (sumimeximplicitnew), (fnewstage),

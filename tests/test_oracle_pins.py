@@ -768,3 +768,109 @@ def test_sst_per_stage_uses_the_second_stage_moments():
     k_once = ref.step(f, k, w)[1]
     assert np.abs(k1 - k_once).max() > 1e-6 * np.abs(k_once).max()
 
+
+
+# ------------------------------------------------------------------------------------------------
+# Reading r34, the implicit SST variant: backward Euler for the increment with first-order upwind
+# convection and two-point diffusion at n+1, the rest of the second-order flux deferred, the linear
+# system solved with a fixed number of Jacobi sweeps.
+# ------------------------------------------------------------------------------------------------
+def test_sst_flux_matrix_is_the_first_order_flux():
+    """L (sst_flux_matrix) against the SST flux routine with zero gradients (first-order upwind,
+    the bounds inactive for positive values): net(a) - net(b) = L (a - b) for any fixed mass
+    fluxes, diffusion coefficients, Dirichlet ghost values and zero-gradient edges, on a mesh of
+    triangles and quads with inlet, outlet and far-field edges."""
+    m = mg.rectangle(7, 6, kind="duct", split="random", jitter=0.2, seed=91)
+    orc = O.Oracle(m, O.default_params(nu=1e-3, dt=1e-2, sst=True))
+    G = orc.g
+    rng = np.random.default_rng(92)
+    H, n, nbf = len(G.cell), G.n, len(G.bidx)
+    mdot = 0.05 * rng.standard_normal(H)
+    Gc = 1e-3 * (1 + rng.random(n))
+    zg = rng.random(nbf) < 0.4
+    dperp = G.dperp[G.bidx]
+    fixed = 1e-3 * (1 + rng.random(nbf))
+    cb = orc.b_cell
+    zero = np.zeros((2, n))
+
+    def net(phi):
+        return orc._sst_net(phi, zero, np.where(zg, phi[cb], fixed), Gc, mdot, zg, dperp)
+
+    a, b = 1e-3 * (1 + rng.random(n)), 1e-3 * (1 + rng.random(n))
+    L = orc.sst_flux_matrix(Gc, mdot, zg, dperp)
+    lhs = net(a) - net(b)
+    np.testing.assert_allclose(L @ (a - b), lhs, rtol=0, atol=1e-13 * np.abs(lhs).max())
+    assert zg.any() and (~zg).any() and np.abs(lhs).max() > 0
+
+
+def test_jacobi_is_the_neumann_series():
+    """m Jacobi sweeps from zero equal the first m terms of the Neumann series
+    sum_j (-D^-1 N)^j D^-1 b (D the diagonal, N the rest), here on an implicit SST system."""
+    m = mg.rectangle(5, 4, kind="duct", split="random", jitter=0.2, seed=93)
+    orc = O.Oracle(m, O.default_params(nu=1e-3, dt=5e-2, sst=True))
+    G = orc.g
+    rng = np.random.default_rng(94)
+    H, n, nbf = len(G.cell), G.n, len(G.bidx)
+    A = orc.sst_system(1 + rng.random(n), 5e-2 / G.area, 1e-3 * (1 + rng.random(n)),
+                       0.05 * rng.standard_normal(H), rng.random(nbf) < 0.4, G.dperp[G.bidx]).toarray()
+    b = rng.standard_normal(n)
+    D = np.diag(A)
+    Mj = -(A - np.diag(D)) / D[:, None]
+    for sweeps in (1, 2, 5):
+        term, ref = b / D, np.zeros(n)
+        for _ in range(sweeps):
+            ref += term
+            term = Mj @ term
+        np.testing.assert_allclose(O.jacobi(_sparse(A), b, sweeps), ref, rtol=1e-13, atol=0)
+
+
+def _sparse(A):
+    import scipy.sparse as sp
+    return sp.csr_matrix(A)
+
+
+def test_sst_implicit_fourier_mode_on_uniform_mesh():
+    """A k wave carried by a uniform stream on a uniform periodic quad mesh (omega uniform, k so
+    small that nu_t is 1e-10 of nu, no strain: no production and no cross diffusion).  There the
+    scheme reduces to finite differences along x: Fromm's upwind-biased face values (the LSQ
+    gradient is the central difference) and the three-point Laplacian at level n, first-order
+    upwind and the Laplacian for the increment,
+        (1 + dt beta* w + c (1 - S_W) - a (S_E + S_W - 2)) delta
+            = -c (k_e - k_w) + a (S_E + S_W - 2) k - dt beta* w k,
+    c = dt U / h, a = dt nu / h^2, k_e = k + (S_E k - S_W k) / 4,
+    k_w = S_W k_e.  At c = 2, a = 1 (past the explicit limits) enough sweeps reach this solution, and a few sweeps do not."""
+    nx, ny, U, w0 = 16, 4, 0.05, 0.5
+    h = 1.0 / nx
+    nu = U * h / 2
+    m = mg.rectangle(nx, ny, Lx=1.0, Ly=ny * h, kind="periodic", jitter=0.0, split="none")
+    dt = 2 * h / U
+    orc = O.Oracle(m, O.default_params(nu=nu, dt=dt, sst=True, sst_sweeps=400))
+    G = orc.g
+    x = G.xc[:, 0]
+    k0 = 1e-12 * (1 + 0.3 * np.sin(2 * np.pi * 2 * x) + 0.2 * np.cos(2 * np.pi * 3 * x))
+    n = G.n
+    k1, w1, _, _ = orc.sst_update(np.ones(n), np.full(n, U), np.zeros(n), k0, np.full(n, w0))
+    # rows of cells along x, each ordered by x
+    order = np.lexsort((x, np.floor(G.xc[:, 1] / h).astype(int)))
+    row = order[:nx]
+    kr = k0[row]
+    I = np.eye(nx)
+    SW = np.roll(I, -1, axis=1)          # (SW k)_j = k_{j-1}
+    SE = np.roll(I, 1, axis=1)           # (SE k)_j = k_{j+1}
+    np.testing.assert_allclose(SW @ kr, np.roll(kr, 1))
+    c, a, bs = dt * U / h, dt * nu / h ** 2, O.SST_DEFAULTS["beta_star"]
+    lap = SE + SW - 2 * I
+    ke = kr + (SE @ kr - SW @ kr) / 4
+    R = -c * (ke - SW @ ke) + a * (lap @ kr) - dt * bs * w0 * kr
+    Mimp = (1 + dt * bs * w0) * I + c * (I - SW) - a * lap
+    expect = kr + np.linalg.solve(Mimp, R)
+    np.testing.assert_allclose(k1[row], expect, rtol=1e-8)
+    # every row alike
+    for j in range(ny):
+        np.testing.assert_allclose(k1[order[j * nx:(j + 1) * nx]], expect, rtol=1e-8)
+    # omega uniform: its increment is the sink's alone, 1 / (1 + dt beta2 w)
+    np.testing.assert_allclose(w1, w0 / (1 + dt * O.SST_DEFAULTS["beta2"] * w0), rtol=1e-12)
+    # three sweeps are not converged (the variant is iterative, not a direct solve)
+    orc3 = O.Oracle(m, O.default_params(nu=nu, dt=dt, sst=True, sst_sweeps=3))
+    k3 = orc3.sst_update(np.ones(n), np.full(n, U), np.zeros(n), k0, np.full(n, w0))[0]
+    assert np.abs(k3[row] - expect).max() > 1e-4 * np.abs(expect).max()
