@@ -83,6 +83,15 @@ typedef struct fvlbm_state fvlbm_state;
  *              the cell gradient); 1: it is also kept between the values of the two cells that
  *              share the edge (first order at local extrema; for flows around sharp edges).  The
  *              adjoint entry points reject a limited state (FVLBM_ESTATE).
+ *   sst_sweeps 0: the SST equations advance point-implicitly (sinks implicit, face fluxes
+ *              explicit).  m in [1, 1000]: they advance implicitly as Section 3.2 says of the
+ *              Code_Saturne integration: backward Euler for the increments of k and omega with
+ *              first-order upwind convection and two-point diffusion at the new level (level-n
+ *              mass fluxes and coefficients), the rest of the second-order flux at level n, and
+ *              the point-implicit sinks; the linear system is solved with m Jacobi sweeps from a
+ *              zero increment (one SST launch that writes the system, then m - 1 sweep launches,
+ *              one launch when m = 1).  Ignored when sst = 0.  The adjoint entry points reject it
+ *              (FVLBM_ESTATE).  Errors: FVLBM_EINVAL outside [0, 1000].
  */
 typedef struct {
     double nu, dt, rho0;
@@ -96,6 +105,7 @@ typedef struct {
     const double *bface_vals;
     int32_t jr_group, limiter;
     double jr_xmin, eps_tau;
+    int32_t sst_sweeps;
 } fvlbm_params;
 
 /*
@@ -221,7 +231,8 @@ enum {
     FVLBM_K_SWEEP3 = 6,    /* stage-3 convection + combination + macro update */
     FVLBM_K_SST = 7,       /* SST in one ring-tiled launch (replaces SST_A + SST_B) */
     FVLBM_K_EXPLICIT = 8,  /* convection + collision of the explicit scheme */
-    FVLBM_K_COUNT = 9
+    FVLBM_K_SST_JACOBI = 9, /* Jacobi sweeps of the implicit SST variant (all of a solve) */
+    FVLBM_K_COUNT = 10
 };
 fvlbm_status fvlbm_timing(fvlbm_state *st, int32_t enable);
 fvlbm_status fvlbm_timing_read(fvlbm_state *st, double ms[FVLBM_K_COUNT], int64_t launches[FVLBM_K_COUNT]);

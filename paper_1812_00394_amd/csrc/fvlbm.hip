@@ -29,6 +29,7 @@ void check(hipError_t e, const char *what) {
 
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 512;   // fixed reduction grid (deterministic sums)
+constexpr int kMaxSstSweeps = 1000;
 
 inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -398,32 +399,73 @@ void stage_ring(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, const Sta
 }
 
 // The SST update (Step 1) from the macro variables M and k, omega = K0, W0 into K1, W1, the
-// relaxation time tau_out and nu_t: one ring launch, or the two split kernels.
+// relaxation time tau_out and nu_t: one ring launch, or the two split kernels.  With
+// params.sst_sweeps = m > 0 (the implicit variant) that launch writes the increments' linear system
+// into the G buffer instead (free at both points a step solves the SST), and m Jacobi sweeps follow.
+template <typename T, int S>
+void launch_sst_jacobi(fvlbm_state *st, const T *K0, const T *W0, T *K1, T *W1, T *tau_out, const StepPar<T> &p) {
+    const Geo<T> &g = geo_of<T>(st);
+    hipStream_t s = st->stream;
+    T *J = (T *)st->G, *nut = (T *)st->nut;
+    const size_t n = (size_t)g.n;
+    const int nbk = blocks_for(g.n);
+    const int m = st->par.sst_sweeps;
+    Timed t(st, FVLBM_K_SST_JACOBI);
+    if (m == 1) {
+        k_sst_jacobi<T, S, false, true><<<nbk, kBlock, 0, s>>>(g, J, J + 8 * n, nullptr, K0, W0, K1, W1, tau_out, nut, p);
+        return;
+    }
+    // sweep 1 gave R' (planes 8, 9); sweeps 2 .. m alternate between planes 10-11 and 12-13
+    const T *din = J + 8 * n;
+    for (int i = 2; i < m; ++i) {
+        T *dout = J + (i % 2 ? 12 : 10) * n;
+        k_sst_jacobi<T, S, true, false><<<nbk, kBlock, 0, s>>>(g, J, din, dout, K0, W0, K1, W1, tau_out, nut, p);
+        din = dout;
+    }
+    k_sst_jacobi<T, S, true, true><<<nbk, kBlock, 0, s>>>(g, J, din, nullptr, K0, W0, K1, W1, tau_out, nut, p);
+}
+
 template <typename T>
 void launch_sst(fvlbm_state *st, const T *M, const T *K0, const T *W0, T *K1, T *W1, T *tau_out, const StepPar<T> &p) {
     const Geo<T> &g = geo_of<T>(st);
     hipStream_t s = st->stream;
     T *aux = (T *)st->aux, *nut = (T *)st->nut;
+    const bool impl = st->par.sst_sweeps > 0;
+    T *J = (T *)st->G;
     if (st->ring) {
         const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
         const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
         const size_t lds = st->sst_lds_bytes;
         Timed t(st, FVLBM_K_SST);
         if (st->ring_s == 3) {
-            if (st->want_aux)
-                k_sst_ring<T, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+            if (impl)
+                k_sst_ring<T, 3, false, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+            else if (st->want_aux)
+                k_sst_ring<T, 3, true, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
             else
-                k_sst_ring<T, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+                k_sst_ring<T, 3, false, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
         } else {
-            if (st->want_aux)
-                k_sst_ring<T, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+            if (impl)
+                k_sst_ring<T, 4, false, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+            else if (st->want_aux)
+                k_sst_ring<T, 4, true, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
             else
-                k_sst_ring<T, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p);
+                k_sst_ring<T, 4, false, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
         }
     } else {
         const int nbk = blocks_for(g.n);
         { Timed t(st, FVLBM_K_SST_A); k_sst_a<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, M, K0, W0, aux, p); }
-        { Timed t(st, FVLBM_K_SST_B); k_sst_b<T><<<nbk, kBlock, 0, s>>>(g, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, p); }
+        Timed t(st, FVLBM_K_SST_B);
+        if (impl)
+            k_sst_b<T, true><<<nbk, kBlock, 0, s>>>(g, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+        else
+            k_sst_b<T, false><<<nbk, kBlock, 0, s>>>(g, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+    }
+    if (impl) {
+        if (st->ring_s == 3)
+            launch_sst_jacobi<T, 3>(st, K0, W0, K1, W1, tau_out, p);
+        else
+            launch_sst_jacobi<T, 4>(st, K0, W0, K1, W1, tau_out, p);
     }
 }
 
@@ -1171,6 +1213,7 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         if (p->sst < 0 || p->sst > 2) throw Error(FVLBM_EINVAL, "init: sst must be 0, 1 or 2");
         if (p->sst && (!k || !omega)) throw Error(FVLBM_EINVAL, "init: SST needs k and omega");
         if (p->limiter != 0 && p->limiter != 1) throw Error(FVLBM_EINVAL, "init: limiter must be 0 or 1");
+        if (p->sst_sweeps < 0 || p->sst_sweeps > kMaxSstSweeps) throw Error(FVLBM_EINVAL, "init: sst_sweeps must be in [0, " + std::to_string(kMaxSstSweeps) + "]");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "init: workspace must be 256-byte aligned");
         const size_t need = layout_bytes(m, precision, p->sst ? 1 : 0);
         if (ws_bytes < need) throw Error(FVLBM_EINVAL, "init: workspace too small (" + std::to_string(ws_bytes) + " < " + std::to_string(need) + ")");
@@ -1409,6 +1452,7 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
         if (st->par.limiter) throw Error(FVLBM_ESTATE, "record: the limited convection has no adjoint here");
         if (st->sst_stages) throw Error(FVLBM_ESTATE, "record: the per-stage SST coupling has no adjoint here");
+        if (st->sst && st->par.sst_sweeps > 0) throw Error(FVLBM_ESTATE, "record: the implicit SST variant has no adjoint here");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");
         size_t need = 0;
         fvlbm_status e = fvlbm_adjoint_bytes(st->mesh, st->precision, n_steps, ckpt_every, &need);

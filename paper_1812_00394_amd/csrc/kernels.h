@@ -1035,6 +1035,16 @@ __device__ __forceinline__ void sst_bface(const S xc[11], bool zg, S ubx, S uby,
     }
 }
 
+// Eddy viscosity a1 k / max(a1 omega, S F2) from the updated k, omega (F2 evaluated again) and the
+// level-n strain rate S.
+template <typename S, typename T>
+__device__ __forceinline__ S sst_nut(S k1, S w1, S Sr, T d, const StepPar<T> &p, const SstParams<S> &q) {
+    const S iw1 = recip(w1), idd = cst<S>(recip(d));
+    const S arg2 = tmax(cst<S>(2.0 / 0.09) * ssqrt(k1) * iw1 * idd, cst<S>(500) * cst<S>(p.nu) * iw1 * idd * idd);
+    const S F2 = stanh(arg2 * arg2);
+    return q.a1 * k1 * recip(tmax(q.a1 * w1, Sr * F2));
+}
+
 // Point-implicit update (negative parts of the explicit sources join the denominator), floor,
 // and the eddy viscosity from the updated k, omega with the level-n strain rate.
 template <typename S, typename T>
@@ -1047,15 +1057,120 @@ __device__ __forceinline__ void sst_update(S rho, S k, S w, S net_k, S net_w, S 
     w1 = (w + fac * net_w + tmax(sw, zero)) * recip(one + dt * beta * w + tmax(-sw, zero) * recip(w));
     k1 = tmax(k1, cst<S>(1e-20));
     w1 = tmax(w1, cst<S>(1e-20));
-    const S iw1 = recip(w1), idd = cst<S>(recip(d));
-    const S arg2 = tmax(cst<S>(2.0 / 0.09) * ssqrt(k1) * iw1 * idd, cst<S>(500) * cst<S>(p.nu) * iw1 * idd * idd);
-    const S F2 = stanh(arg2 * arg2);
-    nut = q.a1 * k1 * recip(tmax(q.a1 * w1, Sr * F2));
+    nut = sst_nut<S, T>(k1, w1, Sr, d, p, q);
 }
 
 template <typename T>
 __device__ __forceinline__ SstParams<T> sst_params(const StepPar<T> &p) {
     return SstParams<T>{p.a1, p.bstar, p.sk1, p.sw1};
+}
+
+// ---- implicit variant (params.sst_sweeps = m > 0) ----
+// Per cell and variable phi in {k, omega} the increment delta = phi^{n+1} - phi^n solves
+//   (sigma - dt / (rho A) L) delta = R,
+// L the net inflow with first-order upwind convection and the two-point diffusion (level-n mass
+// fluxes, diffusion coefficients and upwind sides), sigma the point-implicit denominator of
+// sst_update, R the explicit increment before the sinks act (the second-order flux stays at level n).
+// Each row is stored divided by its diagonal, for the Jacobi sweeps delta <- R' + sum_s c_s delta_N
+// from delta = 0 (the first sweep gives R').  System planes J [kSysPlanes][n]: 0-3 c_s of k per
+// edge slot (0 without an interior neighbour), 4-7 c_s of omega, 8, 9 R' of k, omega, 10, 11 and
+// 12, 13 the two increment buffers (k, omega), 14 the strain rate S for nu_t.
+constexpr int kSysPlanes = 15;
+
+template <typename S>
+struct SstRow {
+    S dk, dw;   // flux parts of the two diagonals (outflow and diffusion conductances)
+};
+
+// Interior edge: its parts of the diagonals, and the (unscaled) couplings of the neighbour's
+// increments: mdot^- + D for the upwind inflow and the diffusion.
+template <typename S, typename T>
+__device__ __forceinline__ void sst_row_edge(const S xc[11], const S xn[11], T nlx, T nly, T rx, T ry, T qx, T qy,
+                                             SstRow<S> &r, S &ck, S &cw) {
+    const S mdot = cst<S>(0.5) * ((xc[0] * xc[1] + xn[0] * xn[1]) * cst<S>(nlx) + (xc[0] * xc[2] + xn[0] * xn[2]) * cst<S>(nly));
+    const T ddx = rx - qx, ddy = ry - qy;
+    const T hn = (ddx * nlx + ddy * nly) * recip(ddx * ddx + ddy * ddy);
+    const S Dk = cst<S>(0.5) * (xc[9] + xn[9]) * cst<S>(hn);
+    const S Dw = cst<S>(0.5) * (xc[10] + xn[10]) * cst<S>(hn);
+    const S out = tmax(mdot, cst<S>(0)), in = tmax(-mdot, cst<S>(0));
+    r.dk = r.dk + out + Dk;
+    r.dw = r.dw + out + Dw;
+    ck = in + Dk;
+    cw = in + Dw;
+}
+
+// Boundary edge: the cell's own value leaves through an outflow edge or stands for the ghost of a
+// zero-gradient edge; Dirichlet diffusion Gamma_c l / d_perp.  Fixed ghost values enter R only.
+template <typename S, typename T>
+__device__ __forceinline__ void sst_row_bedge(const S xc[11], bool zg, S ubx, S uby, T nlx, T nly, T l_over_dp,
+                                              SstRow<S> &r) {
+    const S bux = zg ? xc[1] : ubx, buy = zg ? xc[2] : uby;
+    const S mdot = xc[0] * (bux * cst<S>(nlx) + buy * cst<S>(nly));
+    const S own = (zg || sval(mdot) >= 0) ? mdot : cst<S>(0);
+    r.dk = r.dk + own;
+    r.dw = r.dw + own;
+    if (!zg) {
+        r.dk = r.dk + xc[9] * cst<S>(l_over_dp);
+        r.dw = r.dw + xc[10] * cst<S>(l_over_dp);
+    }
+}
+
+// sigma, R and the diagonals; returns R' and the factors fac / diag that scale the couplings.
+template <typename S, typename T>
+__device__ __forceinline__ void sst_row_finish(S rho, S k, S w, S net_k, S net_w, S sk, S sw, S beta, T inv_area,
+                                               const StepPar<T> &p, const SstParams<S> &q, const SstRow<S> &r,
+                                               S &Rk, S &Rw, S &gk, S &gw) {
+    const S fac = cst<S>(p.dt * inv_area) * recip(rho);
+    const S zero = cst<S>(0), one = cst<S>(1), dt = cst<S>(p.dt);
+    const S dstk = dt * q.bstar * w, dstw = dt * beta * w;
+    const S sig_k = one + dstk + tmax(-sk, zero) * recip(k);
+    const S sig_w = one + dstw + tmax(-sw, zero) * recip(w);
+    const S ik = recip(sig_k + fac * r.dk), iw = recip(sig_w + fac * r.dw);
+    Rk = (fac * net_k + sk - dstk * k) * ik;
+    Rw = (fac * net_w + sw - dstw * w) * iw;
+    gk = fac * ik;
+    gw = fac * iw;
+}
+
+// One Jacobi sweep of both increments, cell per thread: delta <- R' + sum_s c_s delta_N (ITER), or
+// delta taken as it is (the single-sweep case).  FIN: k^{n+1} = max(k^n + delta, floor), omega
+// likewise, then nu_t and tau; else the new increments go to dout.
+template <typename T, int S, bool ITER, bool FIN>
+__global__ void __launch_bounds__(256) k_sst_jacobi(Geo<T> g, const T *__restrict__ J, const T *__restrict__ din,
+                                                    T *__restrict__ dout, const T *__restrict__ K0,
+                                                    const T *__restrict__ W0, T *__restrict__ K1,
+                                                    T *__restrict__ W1, T *__restrict__ tau, T *__restrict__ nut,
+                                                    StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const size_t n = (size_t)g.n;
+    T dk, dw;
+    if constexpr (ITER) {
+        dk = J[8 * n + c];
+        dw = J[9 * n + c];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int nb = g.nbr[s * n + c];
+            if (nb >= 0) {
+                dk += J[s * n + c] * din[nb];
+                dw += J[(4 + s) * n + c] * din[n + nb];
+            }
+        }
+    } else {
+        dk = din[c];
+        dw = din[n + c];
+    }
+    if constexpr (FIN) {
+        const T k1 = tmax(K0[c] + dk, T(1e-20)), w1 = tmax(W0[c] + dw, T(1e-20));
+        const T nt = sst_nut<T, T>(k1, w1, J[14 * n + c], T(g.wdist[c]), p, sst_params(p));
+        K1[c] = k1;
+        W1[c] = w1;
+        nut[c] = nt;
+        tau[c] = T(3) * (p.nu + nt);
+    } else {
+        dout[c] = dk;
+        dout[n + c] = dw;
+    }
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -1143,17 +1258,21 @@ __device__ __forceinline__ void sst_cell_x(int n, int c, T rho0, const T *__rest
     for (int i = 0; i < 6; ++i) x[5 + i] = aux[(size_t)i * n + c];
 }
 
-template <typename T>
+// IMPL: the implicit variant's system rows into J (see kSysPlanes) instead of the update.
+template <typename T, bool IMPL>
 __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restrict__ bzg, const T *__restrict__ M,
                                                const T *__restrict__ K, const T *__restrict__ W,
                                                T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
-                                               T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
+                                               T *__restrict__ tau, T *__restrict__ nut, T *__restrict__ J,
+                                               StepPar<T> p) {
     const int c = cell_index();
     if (c >= g.n) return;
     const int n = g.n;
     T xc[11];
     sst_cell_x(n, c, p.rho0, M, K, W, aux, xc);
     T net_k = 0, net_w = 0;
+    SstRow<T> row{T(0), T(0)};
+    T ck[4] = {T(0), T(0), T(0), T(0)}, cw[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
         const size_t si = (size_t)s * n + c;
@@ -1164,10 +1283,15 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
             T xn[11];
             sst_cell_x(n, nb, p.rho0, M, K, W, aux, xn);
             sst_face<T, T>(xc, xn, g.nlx[si], g.nly[si], g.rfx[si], g.rfy[si], g.qx[si], g.qy[si], tk, tw);
+            if constexpr (IMPL)
+                sst_row_edge<T, T>(xc, xn, g.nlx[si], g.nly[si], g.rfx[si], g.rfy[si], g.qx[si], g.qy[si], row, ck[s], cw[s]);
         } else {
             const int b = -2 - nb;
             sst_bface<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), T(g.b_k[b]), T(g.b_w[b]), g.nlx[si], g.nly[si],
                             g.rfx[si], g.rfy[si], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
+            if constexpr (IMPL)
+                sst_row_bedge<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), g.nlx[si], g.nly[si],
+                                    T(g.b_l[b] / g.b_dperp[b]), row);
         }
         net_k += tk;
         net_w += tw;
@@ -1177,6 +1301,20 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
     aux[(size_t)12 * n + c] = M[c];
     aux[(size_t)13 * n + c] = M[(size_t)n + c];
     aux[(size_t)14 * n + c] = M[(size_t)2 * n + c];
+    if constexpr (IMPL) {
+        T Rk, Rw, gk, gw;
+        sst_row_finish<T, T>(xc[0], xc[3], xc[4], net_k, net_w, aux[(size_t)6 * n + c], aux[(size_t)7 * n + c],
+                             aux[(size_t)8 * n + c], g.inv_area[c], p, sst_params(p), row, Rk, Rw, gk, gw);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            J[(size_t)s * n + c] = ck[s] * gk;
+            J[(size_t)(4 + s) * n + c] = cw[s] * gw;
+        }
+        J[(size_t)8 * n + c] = Rk;
+        J[(size_t)9 * n + c] = Rw;
+        J[(size_t)14 * n + c] = aux[(size_t)9 * n + c];
+        return;
+    }
     T k1, w1, nt;
     sst_update<T, T>(xc[0], xc[3], xc[4], net_k, net_w, aux[(size_t)6 * n + c], aux[(size_t)7 * n + c],
                      aux[(size_t)8 * n + c], aux[(size_t)9 * n + c], T(g.wdist[c]), g.inv_area[c], p, sst_params(p),
@@ -1236,12 +1374,13 @@ __device__ __forceinline__ void sst_grad_ring(const Geo<T> &g, const int32_t *__
     }
 }
 
-template <typename T, int S, bool AUX>
+// IMPL: the implicit variant's system rows into J (see kSysPlanes) instead of the update.
+template <typename T, int S, bool AUX, bool IMPL>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_sst_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg,
                const int32_t *__restrict__ bzg, const T *__restrict__ M, const T *__restrict__ K,
                const T *__restrict__ W, T *__restrict__ aux, T *__restrict__ K1, T *__restrict__ W1,
-               T *__restrict__ tau, T *__restrict__ nut, StepPar<T> p) {
+               T *__restrict__ tau, T *__restrict__ nut, T *__restrict__ J, StepPar<T> p) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *Vv = reinterpret_cast<T *>(smem);
     T *Vx = Vv + 8 * Wv;
@@ -1352,6 +1491,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     // ---- phase 2: fluxes (interior edges straight-line, boundary edges after) and the update ----
     T net_k = 0, net_w = 0;
     bool bnd = false;
+    SstRow<T> row{T(0), T(0)};
+    T ck[S], cw[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const bool in = nb[s] >= 0;
@@ -1367,6 +1508,15 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         sst_face<T, T>(xc, xn, nlx[s], nly[s], rx[s], ry[s], qx[s], qy[s], tk, tw);
         net_k += in ? tk : T(0);
         net_w += in ? tw : T(0);
+        if constexpr (IMPL) {
+            SstRow<T> re{T(0), T(0)};
+            T a, b;
+            sst_row_edge<T, T>(xc, xn, nlx[s], nly[s], rx[s], ry[s], qx[s], qy[s], re, a, b);
+            row.dk += in ? re.dk : T(0);
+            row.dw += in ? re.dw : T(0);
+            ck[s] = in ? a : T(0);
+            cw[s] = in ? b : T(0);
+        }
     }
     if (bnd) {
 #pragma unroll
@@ -1379,11 +1529,27 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
                             g.rfx[si], g.rfy[si], T(g.b_l[b] / g.b_dperp[b]), tk, tw);
             net_k += tk;
             net_w += tw;
+            if constexpr (IMPL)
+                sst_row_bedge<T, T>(xc, bzg[b] != 0, T(g.b_ux[b]), T(g.b_uy[b]), g.nlx[si], g.nly[si],
+                                    T(g.b_l[b] / g.b_dperp[b]), row);
         }
     }
     if constexpr (AUX) {
         aux[(size_t)10 * n + c] = net_k;
         aux[(size_t)11 * n + c] = net_w;
+    }
+    if constexpr (IMPL) {
+        T Rk, Rw, gk, gw;
+        sst_row_finish<T, T>(rho, kc, wc, net_k, net_w, oc.sk, oc.sw, oc.beta, ia, p, q, row, Rk, Rw, gk, gw);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            J[(size_t)s * n + c] = ck[s] * gk;
+            J[(size_t)(4 + s) * n + c] = cw[s] * gw;
+        }
+        J[(size_t)8 * n + c] = Rk;
+        J[(size_t)9 * n + c] = Rw;
+        J[(size_t)14 * n + c] = oc.Sr;
+        return;
     }
     T k1, w1, nt;
     sst_update<T, T>(rho, kc, wc, net_k, net_w, oc.sk, oc.sw, oc.beta, oc.Sr, dc, ia, p, q, k1, w1, nt);

@@ -45,7 +45,7 @@ class Params(C.Structure):
                 ("group_w", C.c_double * FVLBM_MAX_GROUPS),
                 ("bface_vals", C.POINTER(C.c_double)),
                 ("jr_group", C.c_int32), ("limiter", C.c_int32),
-                ("jr_xmin", C.c_double), ("eps_tau", C.c_double)]
+                ("jr_xmin", C.c_double), ("eps_tau", C.c_double), ("sst_sweeps", C.c_int32)]
 
 
 _lib = None
@@ -56,7 +56,7 @@ EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlb
            "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read",
            "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
            "fvlbm_adjoint_state", "fvlbm_lift_drag", "fvlbm_step_explicit"]
-KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit"]
+KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit", "sst_jacobi"]
 
 
 def lib():
@@ -203,6 +203,7 @@ def make_params(p, n_groups, n_bfaces=None):
         s.bface_vals = keep.ctypes.data_as(C.POINTER(C.c_double))
     s.jr_group = int(p.get("jr_group", -1))
     s.limiter = int(p.get("limiter", 0))
+    s.sst_sweeps = int(p.get("sst_sweeps", 0))
     s.jr_xmin = float(p.get("jr_xmin", 0.0))
     s.eps_tau = float(p.get("eps_tau", 1.0))
     return s, keep

@@ -442,3 +442,65 @@ def test_explicit_sst_step_parity(F):
     st.step_explicit(2)
     assert rel(st.get_f(), fo, dev_scale(fo)) < 1e-11
     assert rel(st.moments()["omega"], wo, np.abs(wo).max()) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("name", sorted(SST_MESHES))
+def test_sst_implicit_step_parity(F, name, sweep, precision, monkeypatch):
+    """The implicit SST variant (params.sst_sweeps = m, reading r34): the system rows written by
+    the SST launch (ring or split), then the Jacobi sweeps, for m = 1 (one finishing launch) and
+    m = 4 (two increment buffers in turn).  FP64 to the SST gates over 1 and 3 steps; FP32-dev to
+    2e-6 of U for u and 2e-6 relative for k, omega after one step."""
+    make, extra = SST_MESHES[name]
+    m = make()
+    _, p0, f, k, w = _sst_case(m, extra, 54)
+    point = O.Oracle(m, p0).step(f, k, w)
+    for sweeps in (1, 4):
+        say("sst implicit step", name, sweep, precision, "sweeps", sweeps)
+        monkeypatch.setenv("FVLBM_SWEEP", sweep)
+        p = dict(p0, sst_sweeps=sweeps)
+        orc = O.Oracle(m, p)
+        st = F.State(F.Mesh(m), p, precision=precision, k=k, omega=w)
+        st.set_state(f, k, w)
+        fo, ko, wo = f, k, w
+        for nsteps, tol in ((1, 1e-12), (2, 1e-11)):
+            fo, ko, wo = orc.run(fo, ko, wo, nsteps)
+            st.step(nsteps)
+            mo = st.moments()
+            if precision == "fp64":
+                got = st.get_f()
+                assert rel(got, fo, dev_scale(fo)) < tol, ("f", nsteps, rel(got, fo, dev_scale(fo)))
+                assert rel(mo["k"], ko, np.abs(ko).max()) < tol * 10, ("k", nsteps, rel(mo["k"], ko, np.abs(ko).max()))
+                assert rel(mo["omega"], wo, np.abs(wo).max()) < tol * 10, ("w", nsteps)
+                assert rel(mo["nu_t"], orc.last_nut, np.abs(orc.last_nut).max()) < tol * 10, ("nu_t", nsteps)
+            elif nsteps == 1:
+                _, ux, uy, _ = orc.macro(fo)
+                du = max(np.abs(mo["u"][:, 0] - ux).max(), np.abs(mo["u"][:, 1] - uy).max()) / 0.05
+                assert du < 2e-6, du
+                assert rel(mo["k"], ko, np.abs(ko).max()) < 2e-6, rel(mo["k"], ko, np.abs(ko).max())
+                assert rel(mo["omega"], wo, np.abs(wo).max()) < 2e-6, rel(mo["omega"], wo, np.abs(wo).max())
+            if nsteps == 1:
+                # the variant is active: its k differs from the point-implicit one's
+                assert rel(ko, point[1], np.abs(point[1]).max()) > 1e-9
+        with pytest.raises(F.FvlbmError):
+            st.record(2, ckpt_every=1)
+
+
+def test_sst_implicit_per_stage_step_parity(F, monkeypatch):
+    """The implicit variant with the per-stage coupling (both SST solves implicit), ring path."""
+    say("sst implicit + per-stage, backstep_coarse, ring")
+    monkeypatch.setenv("FVLBM_SWEEP", "ring")
+    make, extra = SST_MESHES["backstep_coarse"]
+    m = make()
+    _, p0, f, k, w = _sst_case(m, extra, 55)
+    p = dict(p0, sst_sweeps=3, sst_stages=1)
+    orc = O.Oracle(m, p)
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k, omega=w)
+    st.set_state(f, k, w)
+    fo, ko, wo = orc.run(f, k, w, 2)
+    st.step(2)
+    mo = st.moments()
+    assert rel(st.get_f(), fo, dev_scale(fo)) < 1e-11
+    assert rel(mo["k"], ko, np.abs(ko).max()) < 1e-10
+    assert rel(mo["omega"], wo, np.abs(wo).max()) < 1e-10
