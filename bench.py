@@ -125,6 +125,12 @@ def kernel_bytes(T, S, variant="ring", recover=False):
         "sweep1": ((28 if variant == "ring" else 37) - (9 if recover else 0)) * T + geo + extra,
         "sweep2": (46 - (9 if recover else 0)) * T + geo + extra,
         "sweep3": 30 * T + geo + extra,
+        # implicit SST variant, one Jacobi sweep launch: S int32 neighbour ids and 2 couplings per
+        # edge slot, R' of k and omega, the previous increments (gathers counted once), the new
+        # ones; the finishing sweep reads k^n, omega^n, the strain rate and the wall distance and
+        # writes k, omega, nu_t, tau instead of increments
+        "sst_jacobi": (4 + 2 * T) * S + 6 * T,
+        "sst_jacobi_fin": (4 + 2 * T) * S + 4 * T + 3 * T + 8 + 4 * T,
     }
 
 
@@ -442,6 +448,30 @@ def main():
         log(f"per-stage SST: {ms_p:.3f} ms/step")
         del stp
 
+    implicit = None
+    if p.get("sst") and not args.no_explicit:
+        # the implicit SST variant (params.sst_sweeps): the SST launch writes the system, then the
+        # Jacobi sweep launches
+        sweeps = 4
+        sti, _ = make_state(F, M, dict(flow, sst_sweeps=sweeps), init, args.precision, dt_frac)
+        nst = max(20, args.steps // 4)
+        ms_i, _, _ = time_steps(F, sti, nst, args.warmup, stream, kernel_timing=False)
+        _, _, kti = time_steps(F, sti, nst, 0, stream, kernel_timing=True)
+        # the library times a solve's sweep launches (sweeps - 1 of them) as one interval
+        jac_ms, jac_n = kti["sst_jacobi"]
+        solve_ms = jac_ms / jac_n
+        jb = n * ((sweeps - 2) * kb["sst_jacobi"] + kb["sst_jacobi_fin"])
+        asm_key = "sst" if kti["sst"][1] else "sst_b"
+        implicit = {"sst_sweeps": sweeps, "ms_per_step": round(ms_i / nst, 4),
+                    "over_point_implicit": round((ms_i / nst) / (ms / args.steps), 3),
+                    "system_launch_ms": round(kti[asm_key][0] / kti[asm_key][1], 5),
+                    "jacobi_launches_per_solve": sweeps - 1,
+                    "jacobi_solve_ms": round(solve_ms, 5),
+                    "jacobi_algorithmic_gbs": round(jb / (solve_ms * 1e-3) / 1e9, 1)}
+        log(f"implicit SST ({sweeps} sweeps): {ms_i / nst:.3f} ms/step, {sweeps - 1} Jacobi launches "
+            f"{solve_ms * 1e3:.1f} us ({implicit['jacobi_algorithmic_gbs']} GB/s)")
+        del sti
+
     airfoil = airfoil_run(F, args.airfoil_steps) if args.airfoil_steps > 0 else None
     cost_ratio = None if args.no_explicit else imex_vs_explicit(F, M, flow, init, dt_frac)
 
@@ -494,6 +524,7 @@ def main():
         "airfoil_lift_drag": airfoil,
         "imex_over_explicit_per_step": cost_ratio,
         "sst_per_stage": per_stage,
+        "sst_implicit": implicit,
         "cpu_baseline": cpu,
         "kernel_source_sha256": source_hash(),
     }
