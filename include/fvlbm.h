@@ -172,6 +172,17 @@ fvlbm_status fvlbm_set_state(fvlbm_state *st, const double *f, const double *k, 
 fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *residual);
 
 /*
+ * Run toward a steady state, the residual-driven long runs of Section 4: fvlbm_step in blocks of
+ * check_every steps, the velocity residual of fvlbm_step evaluated after each block (one host
+ * synchronisation per block), until it falls below tol or max_steps steps were taken (the last
+ * block is shortened to end there).  steps_out (may be NULL): steps taken; residual_out (may be
+ * NULL): the last residual.  Errors: FVLBM_EINVAL (NULL state, max_steps < 1, check_every < 1,
+ * tol < 0), FVLBM_EDIVERGED (non-finite residual; the state is left as it is).
+ */
+fvlbm_status fvlbm_run_to_residual(fvlbm_state *st, int64_t max_steps, int32_t check_every, double tol,
+                                   int64_t *steps_out, double *residual_out);
+
+/*
  * Advance n_steps steps of the explicit scheme the paper compares the IMEX scheme with (Section
  * 3.1): forward Euler of the semi-discrete equation, Eq. (semibgk), f^{n+1} = f^n + dt (Ga(f^n) +
  * (f_eq(f^n) - f^n) / tau), with the SST update first as in fvlbm_step.  Stable for dt < 2 tau

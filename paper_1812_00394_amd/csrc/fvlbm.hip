@@ -1273,6 +1273,35 @@ fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *res) {
     });
 }
 
+fvlbm_status fvlbm_run_to_residual(fvlbm_state *st, int64_t max_steps, int32_t check_every, double tol,
+                                   int64_t *steps_out, double *residual_out) {
+    return guarded([&] {
+        if (!st) throw Error(FVLBM_EINVAL, "run_to_residual: NULL state");
+        if (max_steps < 1 || check_every < 1 || !(tol >= 0))
+            throw Error(FVLBM_EINVAL, "run_to_residual: needs max_steps >= 1, check_every >= 1, tol >= 0");
+        int64_t done = 0;
+        double r = 0;
+        if (steps_out) *steps_out = 0;
+        while (done < max_steps) {
+            const int32_t blk = (int32_t)std::min<int64_t>(check_every, max_steps - done);
+            for (int32_t i = 0; i < blk; ++i) {
+                if (st->precision == FVLBM_FP64)
+                    launch_step<double>(st);
+                else
+                    launch_step<float>(st);
+                if (st->timing && st->events.size() > 4096) drain_events(st);
+            }
+            done += blk;
+            st->steps_done += blk;
+            r = st->precision == FVLBM_FP64 ? residual<double>(st) : residual<float>(st);
+            if (steps_out) *steps_out = done;
+            if (residual_out) *residual_out = r;
+            if (!std::isfinite(r)) throw Error(FVLBM_EDIVERGED, "run_to_residual: non-finite velocity residual");
+            if (r < tol) break;
+        }
+    });
+}
+
 fvlbm_status fvlbm_step_explicit(fvlbm_state *st, int32_t n_steps, double *res) {
     return guarded([&] {
         if (!st) throw Error(FVLBM_EINVAL, "step_explicit: NULL state");

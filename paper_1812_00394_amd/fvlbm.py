@@ -55,7 +55,8 @@ EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlb
            "fvlbm_moments", "fvlbm_get_f", "fvlbm_forces", "fvlbm_apply_advection", "fvlbm_state_destroy",
            "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read",
            "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
-           "fvlbm_adjoint_state", "fvlbm_lift_drag", "fvlbm_step_explicit"]
+           "fvlbm_adjoint_state", "fvlbm_lift_drag", "fvlbm_step_explicit",
+           "fvlbm_run_to_residual"]
 KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit", "sst_jacobi"]
 
 
@@ -82,6 +83,7 @@ def lib():
     L.fvlbm_set_state.argtypes = [P, P, P, P]
     L.fvlbm_step.argtypes = [P, I32, P]
     L.fvlbm_step_explicit.argtypes = [P, I32, P]
+    L.fvlbm_run_to_residual.argtypes = [P, I64, I32, C.c_double, P, P]
     L.fvlbm_moments.argtypes = [P, I32, P, P, P, P, P, P]
     L.fvlbm_get_f.argtypes = [P, I32, P]
     L.fvlbm_forces.argtypes = [P, C.c_uint64, P, P]
@@ -240,6 +242,15 @@ class State:
         r = C.c_double()
         _check(lib().fvlbm_step(self.handle, int(n_steps), C.byref(r) if residual else None))
         return r.value if residual else None
+
+    def run_to_residual(self, tol, max_steps, check_every=1000):
+        """Step until the velocity residual is below tol (checked every check_every steps) or
+        max_steps steps were taken; returns (steps taken, last residual)."""
+        n = C.c_int64()
+        r = C.c_double()
+        _check(lib().fvlbm_run_to_residual(self.handle, int(max_steps), int(check_every), float(tol),
+                                           C.byref(n), C.byref(r)))
+        return n.value, r.value
 
     def step_explicit(self, n_steps=1, residual=False):
         """n_steps of the explicit (forward Euler) scheme; stable for dt < 2 tau only."""
