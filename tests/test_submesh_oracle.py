@@ -45,11 +45,13 @@ def test_wall_segments_reproduce_own_walls():
     np.testing.assert_array_equal(a, b)
 
 
-@pytest.mark.parametrize("R,exact", [(10, True), (2, False)])
-def test_piece_reproduces_full_step(R, exact):
+@pytest.mark.parametrize("R,exact,extra", [(10, True, {}), (2, False, {}), (12, True, {"sst_sweeps": 4})])
+def test_piece_reproduces_full_step(R, exact, extra):
     """R = 10 rings: the sample cells match the full run to rounding; R = 2 (less than the reach)
-    must not, which shows the check can fail."""
+    must not, which shows the check can fail.  The implicit SST variant with 4 Jacobi sweeps (three
+    rings more in the SST) on 12 rings, as the full-size check of that variant uses."""
     m, p, u, k, w = _case()
+    p = dict(p, **extra)
     n = len(m["cell_ptr"]) - 1
     full = O.Oracle(m, p)
     f0, k0, w0 = full.init_state(np.ones(n), u[:, 0], u[:, 1], k, w)
