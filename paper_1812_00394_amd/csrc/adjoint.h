@@ -592,6 +592,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             V[(kTileCells + t) * 8 + (a - 1)] = hmu[a];
         }
     }
+    // ring-2 cells beyond one per thread (tiles of stretched cells): their values only
+    for (int e = t + kTileCells; e < nx; e += kTileCells) {
+        const int ec = rt.cell[x0 + e];
+        const T eia = g.inv_area[ec];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) V[(kTileCells + e) * 8 + (a - 1)] = -(lscale * L[(size_t)a * n + ec]) * eia;
+    }
     __syncthreads();
 
     // ---- phase 1: adv_T1 ----
@@ -1015,6 +1022,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
                 for (int k = 0; k < 3; ++k) Mi[(kTileCells + t) * 3 + k] = hmi[k];
             }
         }
+    }
+    // ring-2 cells beyond one per thread (tiles of stretched cells): their LDS rows only (the
+    // other outputs of a ring-2 cell are not used)
+    for (int e = t + kTileCells; e < nx; e += kTileCells) {
+        T ex[11], elx[3], eown[4];
+        SstParBar<T> epb;
+        load_update(rt.cell[x0 + e], kTileCells + e, ex, elx, eown, epb);
     }
     __syncthreads();
 

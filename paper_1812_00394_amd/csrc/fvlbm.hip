@@ -95,6 +95,9 @@ struct fvlbm_state {
     char *adj_ws = nullptr;
     size_t adj_bytes = 0;
     int32_t rec_steps = 0, rec_ckpt = 0;
+    // the reverse recomputes the next segment on a second stream while it reverses the current one
+    hipStream_t side = nullptr;
+    hipEvent_t ev_rev = nullptr, ev_rec = nullptr;
     // per-kernel event timing (fvlbm_timing)
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
@@ -107,6 +110,9 @@ struct fvlbm_state {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
+        if (ev_rev) (void)hipEventDestroy(ev_rev);
+        if (ev_rec) (void)hipEventDestroy(ev_rec);
+        if (side) (void)hipStreamDestroy(side);
     }
 };
 
@@ -634,7 +640,8 @@ void choose_sweep(fvlbm_state *st) {
     const size_t ring_lds = ((size_t)8 * st->ring_wv + (size_t)16 * st->ring_wg) * sizeof(T);
     // the adjoint's ring kernels must fit as well: transposed convection and the SST reverse
     const size_t adj_lds = std::max(adj_t_lds<T>(st), adj_sst_lds<T>(st));
-    st->ring = (mode.empty() || mode == "ring") && st->mesh->ext_max <= kTileCells &&
+    // one thread per ring-1 cell; ring-2 cells beyond one per thread are looped over
+    st->ring = (mode.empty() || mode == "ring") && st->mesh->halo_max <= kTileCells &&
                std::max(ring_lds, adj_lds) <= (size_t)max_lds;
     if (st->ring) {
         st->lds_bytes = ring_lds;
@@ -819,10 +826,23 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
 template <typename T>
 struct AdjLayout {
     T *ckpt, *seg, *stg, *lF, *lF2, *lK, *lW, *lK2, *lW2, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
+    T *seg2, *stg2;     // a second set of segment buffers when the run has more than one segment
     double *pbar;
     size_t state_len;
     size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [15][n]
 };
+
+// The layout with segment set k (0 or 1) as its segment buffers: segment sg of a run lives in set
+// sg % 2, so that one segment can be recomputed while the next is reversed.
+template <typename T>
+AdjLayout<T> segment_set(const AdjLayout<T> &L, int k) {
+    AdjLayout<T> r = L;
+    if (k & 1) {
+        r.seg = L.seg2;
+        r.stg = L.stg2;
+    }
+    return r;
+}
 
 template <typename T>
 size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout<T> &L) {
@@ -833,6 +853,11 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     L.seg = cv.take<T>((size_t)(ckpt + 1) * sl);
     L.stage_len = 43 * (size_t)n;
     L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
+    L.seg2 = L.stg2 = nullptr;
+    if (nck > 2) {
+        L.seg2 = cv.take<T>((size_t)(ckpt + 1) * sl);
+        L.stg2 = cv.take<T>((size_t)ckpt * L.stage_len);
+    }
     L.lF = cv.take<T>(9 * (size_t)n);
     L.lF2 = cv.take<T>(9 * (size_t)n);
     L.lK = cv.take<T>(n);
@@ -961,9 +986,10 @@ void record(fvlbm_state *st) {
     int first_last, last_last;
     segment_bounds(N, C, nseg - 1, first_last, last_last);
     save_state<T>(st, L.ckpt + (size_t)(nseg - 1) * L.state_len);
-    save_state<T>(st, L.seg);
-    for (int32_t i = first_last; i < N; ++i) step_seg<T>(st, L, i - first_last);
-    load_state<T>(st, L.seg + (size_t)(N - first_last) * L.state_len);
+    const AdjLayout<T> Ls = segment_set(L, (nseg - 1) % 2);
+    save_state<T>(st, Ls.seg);
+    for (int32_t i = first_last; i < N; ++i) step_seg<T>(st, Ls, i - first_last);
+    load_state<T>(st, Ls.seg + (size_t)(N - first_last) * L.state_len);
     const size_t nck = (size_t)nseg;
     save_state<T>(st, L.ckpt + nck * L.state_len);
     st->last_seg_valid = true;
@@ -1016,32 +1042,68 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
 }
 
 // Reverse of the whole recorded run (L.lF / lK / lW seeded with the adjoint of the final state).
-// Each segment is recomputed once from its checkpoint in the segment buffers, keeping every step's
-// input state and stage data (the last segment comes from the record pass while those buffers
-// still hold it); then its steps are reversed from the last.
+// Each segment is recomputed once from its checkpoint in its set of segment buffers, keeping every
+// step's input state and stage data (the last segment comes from the record pass while its buffers
+// still hold it); then its steps are reversed from the last.  On the ring path the recompute of
+// segment sg - 1 runs on a second stream while segment sg is reversed: the two touch disjoint
+// buffers (the recompute: its segment set, the macro buffers and nu_t; the reverse: the other set
+// and the adjoint fields), and each waits only for the work on the set it is about to reuse.
 template <typename T>
 void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
     AdjLayout<T> L = L0;         // lF / lF2 (and lK, lW / lK2, lW2) alternate between steps
     const int N = st->rec_steps, C = st->rec_ckpt;
     const int nseg = (N + C - 1) / C;
     const size_t n = st->n_cells;
+    const bool overlap = st->ring && nseg > 1 && L.seg2;
+    if (overlap && !st->side) {
+        // non-blocking: no implicit ordering with a legacy default stream; the events order the two
+        check(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+        check(hipEventCreateWithFlags(&st->ev_rev, hipEventDisableTiming), "hipEventCreate");
+        check(hipEventCreateWithFlags(&st->ev_rec, hipEventDisableTiming), "hipEventCreate");
+    }
+    hipStream_t main_stream = st->stream;
+    struct Restore {
+        fvlbm_state *st;
+        hipStream_t s;
+        ~Restore() { st->stream = s; }
+    } restore{st, main_stream};
+    auto recompute = [&](int sg, hipStream_t s) {
+        const AdjLayout<T> Ls = segment_set(L, sg % 2);
+        int first, last;
+        segment_bounds(N, C, sg, first, last);
+        st->stream = s;
+        check(hipMemcpyAsync(Ls.seg, L.ckpt + (size_t)sg * L.state_len, L.state_len * sizeof(T), hipMemcpyDeviceToDevice, s),
+              "hipMemcpyAsync D2D");
+        k_macro<T><<<blocks_for(n), kBlock, 0, s>>>((int)n, Ls.seg, (T *)st->M[st->cur_m], T(st->par.rho0));
+        for (int i = first; i < last; ++i) step_seg<T>(st, Ls, i - first);
+        st->stream = main_stream;
+    };
+    if (!st->last_seg_valid) recompute(nseg - 1, main_stream);
+    st->last_seg_valid = false;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         int first, last;
         segment_bounds(N, C, sg, first, last);
-        if (!(sg == nseg - 1 && st->last_seg_valid)) {
-            st->last_seg_valid = false;
-            check(hipMemcpyAsync(L.seg, L.ckpt + (size_t)sg * L.state_len, L.state_len * sizeof(T), hipMemcpyDeviceToDevice,
-                                 st->stream), "hipMemcpyAsync D2D");
-            k_macro<T><<<blocks_for(n), kBlock, 0, st->stream>>>((int)n, L.seg, (T *)st->M[st->cur_m], T(st->par.rho0));
-            for (int i = first; i < last; ++i) step_seg<T>(st, L, i - first);
+        if (overlap && sg > 0) {
+            // set (sg - 1) % 2 was last read by the reverse of segment sg + 1, all of it queued
+            check(hipEventRecord(st->ev_rev, main_stream), "hipEventRecord");
+            check(hipStreamWaitEvent(st->side, st->ev_rev, 0), "hipStreamWaitEvent");
+            recompute(sg - 1, st->side);
+            check(hipEventRecord(st->ev_rec, st->side), "hipEventRecord");
         }
+        const AdjLayout<T> Ls = segment_set(L, sg % 2);
         for (int i = last - 1; i >= first; --i) {
-            reverse_step<T>(st, L, L.seg + (size_t)(i - first) * L.state_len, stage_slot<T>(st, L, i - first));
+            reverse_step<T>(st, L, Ls.seg + (size_t)(i - first) * L.state_len, stage_slot<T>(st, Ls, i - first));
             std::swap(L.lF, L.lF2);
             if (st->sst) {
                 std::swap(L.lK, L.lK2);
                 std::swap(L.lW, L.lW2);
             }
+        }
+        if (sg > 0) {
+            if (overlap)
+                check(hipStreamWaitEvent(main_stream, st->ev_rec, 0), "hipStreamWaitEvent");
+            else
+                recompute(sg - 1, main_stream);
         }
     }
     if (L.lF != L0.lF)

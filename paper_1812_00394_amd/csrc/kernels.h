@@ -777,6 +777,22 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             decode_slots<S>(g.bfirst, hc, hcol, hnb);
         }
     }
+    // ring-2 cells beyond one per thread (tiles of stretched cells): their values only
+    for (int e = t + kTileCells; e < nx; e += kTileCells) {
+        const int ec = rt.cell[x0 + e];
+        T ev[9];
+        if constexpr (J == 1) {
+            T ef[9], fe[9];
+#pragma unroll
+            for (int a = 0; a < 9; ++a) ef[a] = b.F_in[(size_t)a * n + ec];
+            stage_collide(ef, p.dt * T(0.25) * recip(b.tau[ec]), p.rho0, ev, fe);
+        } else {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) ev[a] = b.src[(size_t)a * n + ec];
+        }
+#pragma unroll
+        for (int a = 1; a < 9; ++a) V[vrow<T>(kTileCells + e, a - 1)] = ev[a];
+    }
     __syncthreads();
 
     // ---- phase 1 ----
@@ -1446,6 +1462,16 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             decode_slots<S>(g.bfirst, hc, hcol, hnb);
             hd = T(g.wdist[hc]);
         }
+    }
+    // ring-2 cells beyond one per thread (tiles of stretched cells): their values only
+    for (int e = t + kTileCells; e < nx; e += kTileCells) {
+        const int ec = rt.cell[x0 + e];
+        const int j = kTileCells + e;
+        Vv[j * 8 + 0] = M[(size_t)n + ec];
+        Vv[j * 8 + 1] = M[(size_t)2 * n + ec];
+        Vv[j * 8 + 2] = K[ec];
+        Vv[j * 8 + 3] = W[ec];
+        Vv[j * 8 + 4] = p.rho0 + M[ec];
     }
     __syncthreads();
 

@@ -252,3 +252,56 @@ def test_autograd_function_and_fp32(F):
         print(precision, "adjoint gradient", g, "relative error", rel)
         scale = np.abs(ref).max()
         assert np.all(np.abs(g - ref) <= tol * np.maximum(np.abs(ref), 1e-6 * scale)), (precision, g, ref)
+
+
+def test_wide_halo_ring_adjoint_fp32(F):
+    """The ring adjoint kernels with ring-2 cells beyond one per thread (the 16,844-cell backstep of
+    the forward wide-halo test, FP32-dev on the ring path): the autograd gradient of the force
+    objective against the oracle's complex step, to the FP32 gates of test_autograd_function_and_fp32."""
+    say("wide-halo backstep adjoint, fp32dev ring")
+    import torch
+    from paper_1812_00394_amd.autograd import FVLBMObjective, Problem, PARAM_NAMES
+    m = mg.backstep(core=0.3, dx_core=0.6, dx_corner=0.02, y1=1e-3)
+    dt = _courant_dt(m, 0.5)
+    p = O.default_params(nu=dt / 40, dt=dt, sst=True, group_u=[[0, 0], [0.05, 0.004], [0, 0]],
+                         group_k=[0, 2e-4, 0], group_w=[0, 0.4, 0], theta=0.05, jr_group=0, jr_xmin=0.0,
+                         eps_tau=1e-7)
+    orc = O.Oracle(m, p)
+    n = orc.g.n
+    rng = np.random.default_rng(92)
+    x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+    ux = 0.04 * np.tanh(2 * (y - y.mean())) + 0.004 * rng.standard_normal(n)
+    uy = 0.006 * np.sin(2 * x) + 0.004 * rng.standard_normal(n)
+    f0 = O.feq(1 + 0.002 * rng.standard_normal(n), ux, uy) + 2e-5 * O.WT[:, None] * rng.standard_normal((9, n))
+    k0, w0 = 2e-4 * (1 + 0.5 * rng.random(n)), 0.4 * (1 + 0.5 * rng.random(n))
+    M = F.Mesh(m)
+    probe = F.State(M, p, precision="fp32dev", k=k0, omega=w0)
+    probe.timing(True)
+    probe.step(1)
+    kt = probe.timing_read()
+    assert kt["sst"][1] == 1 and kt["collide1"][1] == 0, kt     # the ring path
+    del probe
+    N = 3
+    wts = torch.tensor([0.3, -0.8, 1.5], dtype=torch.float64)
+    ref = []
+    for key in PARAM_NAMES:
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        o = O.Oracle(m, pc)
+        fN, _, _ = o.run(f0.astype(complex), k0.astype(complex), w0.astype(complex), N)
+        Fv, JR = o.forces(fN, 1)
+        ref.append(np.imag(wts[0].item() * Fv[0] + wts[1].item() * Fv[1] + wts[2].item() * JR) / H)
+    ref = np.array(ref)
+    rho0, ux0, uy0, _ = orc.macro(f0)
+    neq_rms = np.sqrt(np.mean((f0 - O.feq(rho0, ux0, uy0)) ** 2))
+    res32 = 2.0 ** -24 * np.abs(f0 - O.WT[:, None] * p["rho0"]).max() / neq_rms
+    tol32 = np.array([1e-3] + [max(1e-3, 10 * res32)] * (len(PARAM_NAMES) - 1))
+    prob = Problem(M, p, rho=np.ones(n), u=np.zeros((n, 2)), k=k0, omega=w0, n_steps=N, ckpt_every=2,
+                   wall_mask=1, precision="fp32dev", f0=f0)
+    params = torch.tensor([p[k] for k in PARAM_NAMES], dtype=torch.float64, requires_grad=True)
+    J = FVLBMObjective.apply(params, prob)
+    (J @ wts).backward()
+    g = params.grad.numpy()
+    print("fp32dev adjoint gradient", g, "reference", ref, "gates", tol32)
+    scale = np.abs(ref).max()
+    assert np.all(np.abs(g - ref) <= tol32 * np.maximum(np.abs(ref), 1e-6 * scale)), (g, ref)

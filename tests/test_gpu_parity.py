@@ -504,3 +504,45 @@ def test_sst_implicit_per_stage_step_parity(F, monkeypatch):
     assert rel(st.get_f(), fo, dev_scale(fo)) < 1e-11
     assert rel(mo["k"], ko, np.abs(ko).max()) < 1e-10
     assert rel(mo["omega"], wo, np.abs(wo).max()) < 1e-10
+
+
+def _wide_halo_backstep():
+    """A backstep (16,844 cells) whose stretched wall cells give Morton tiles with up to 473
+    ring-2 cells (tests/test_host_library.py checks the count): more than one per thread."""
+    return mg.backstep(core=0.3, dx_core=0.6, dx_corner=0.02, y1=1e-3)
+
+
+def test_wide_halo_ring_step_parity(F):
+    """The ring kernels loop over ring-2 cells beyond one per thread.  SST steps against the oracle:
+    FP32-dev on the ring path (its LDS fits), FP64 on whichever path fits; gates as the SST
+    parity tests (FP64 1e-12 / 1e-11, FP32-dev 2e-6 after one step)."""
+    m = _wide_halo_backstep()
+    extra = dict(group_u=[[0, 0], [0.05, 0], [0, 0]], group_k=[0, 1e-4, 0], group_w=[0, 0.5, 0])
+    orc, p, f, k, w = _sst_case(m, extra, 56)
+    f1, k1, w1 = orc.step(f, k, w)
+    nut1 = orc.last_nut
+    M = F.Mesh(m)
+    for precision in ("fp64", "fp32dev"):
+        say("wide-halo backstep", precision)
+        st = F.State(M, p, precision=precision, k=k, omega=w)
+        st.set_state(f, k, w)
+        st.timing(True)
+        st.step(1)
+        kt = st.timing_read()
+        st.timing(False)
+        ring = kt["sst"][1] == 1 and kt["collide1"][1] == 0
+        print(precision, "ring path" if ring else "tiled / split path")
+        if precision == "fp32dev":
+            assert ring, kt
+        mo = st.moments()
+        if precision == "fp64":
+            got = st.get_f()
+            assert rel(got, f1, dev_scale(f1)) < 1e-12
+            assert rel(mo["k"], k1, np.abs(k1).max()) < 1e-11
+            assert rel(mo["omega"], w1, np.abs(w1).max()) < 1e-11
+            assert rel(mo["nu_t"], nut1, np.abs(nut1).max()) < 1e-11
+        else:
+            _, ux, uy, _ = orc.macro(f1)
+            du = max(np.abs(mo["u"][:, 0] - ux).max(), np.abs(mo["u"][:, 1] - uy).max()) / 0.05
+            assert du < 2e-6, du
+            assert rel(mo["k"], k1, np.abs(k1).max()) < 2e-6 and rel(mo["omega"], w1, np.abs(w1).max()) < 2e-6

@@ -112,3 +112,27 @@ def test_invalid_arguments():
     b32 = M.state_bytes("fp32dev")
     assert b64 > (9 * 4 + 16) * 8 * M.n_cells
     assert b32 < b64
+
+
+def test_wide_halo_backstep_tiles():
+    """The mesh of the wide-halo GPU tests: its 256-cell Morton tiles (the library's renumbering)
+    have at most 256 ring-1 cells (one thread each) but more than 256 cells in ring 1 + ring 2,
+    so the ring kernels must loop over the ring-2 cells beyond one per thread."""
+    import scipy.sparse as sp
+    m = mg.backstep(core=0.3, dx_core=0.6, dx_corner=0.02, y1=1e-3)
+    M = F.Mesh(m)
+    perm = M.permutation()
+    n = len(perm)
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    G = O.Geometry(m)
+    inner = np.nonzero(G.interior)[0]
+    A = sp.csr_matrix((np.ones(len(inner)), (inv[G.cell[inner]], inv[G.nbr[inner]])), shape=(n, n))
+    r1, ext = [], []
+    for t in range((n + 255) // 256):
+        cells = np.arange(t * 256, min(n, t * 256 + 256))
+        h1 = np.setdiff1d(np.unique(A[cells].indices), cells)
+        h2 = np.setdiff1d(np.unique(A[h1].indices), np.concatenate([cells, h1]))
+        r1.append(len(h1))
+        ext.append(len(h1) + len(h2))
+    assert max(r1) <= 256 < max(ext), (max(r1), max(ext))
