@@ -269,6 +269,37 @@ def imex_vs_explicit(F, M_big, flow_big, init_big, dt_frac_big):
     return out
 
 
+def backstep_run(F, stream, warmup, steps=2000, adj_steps=400, ckpt=20):
+    """The backward-facing step (about 123k hybrid cells, SST, 34 tau0): forward MLUPS in FP32-dev and
+    FP64 over `steps` steps, and the adjoint of `adj_steps` recorded steps with a checkpoint every
+    `ckpt` steps in both precisions, against the forward time of the same steps."""
+    import torch
+    mesh, flow, init, dt_frac = workload("backstep")
+    M = F.Mesh(mesh, order="morton")
+    n = M.n_cells
+    out = {"cells": n, "steps": steps}
+    for prec in ("fp32dev", "fp64"):
+        st, p = make_state(F, M, flow, init, prec, dt_frac)
+        ms, _, kt = time_steps(F, st, steps, warmup, stream, kernel_timing=False)
+        del st
+        sta, _ = make_state(F, M, flow, init, prec, dt_frac)
+        sta.step(warmup)
+        sta.record(adj_steps, ckpt_every=ckpt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sta.adjoint(1, [1.0, 0.0, 0.0])
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        t_fwd = ms / steps * 1e-3 * adj_steps
+        del sta
+        out[prec] = {"ms_per_step": round(ms / steps, 4), "mlups": round(n * steps / (ms * 1e-3) / 1e6, 1),
+                     "adjoint": {"steps": adj_steps, "ckpt_every": ckpt, "adjoint_s": round(t_adj, 4),
+                                 "ratio": round(t_adj / t_fwd, 3)}}
+        log(f"backstep {prec}: {ms / steps:.4f} ms/step, adjoint/forward {t_adj / t_fwd:.2f}")
+    out["dt_over_tau0"] = round(p["dt"] / (3 * p["nu"]), 2)
+    return out
+
+
 def airfoil_run(F, steps):
     """The airfoil workload: 512 x 384 O-mesh (196,608 quads) around the sharp-trailing-edge 12 %
     section, Re 6e6 on the chord, 10 degrees incidence, u_inf = 0.05, dt = 0.9 of the advective
@@ -319,6 +350,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=50, help="recorded steps of the adjoint timing (0: skip)")
     ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the adjoint")
     ap.add_argument("--no-explicit", action="store_true", help="skip the IMEX / explicit cost comparison")
+    ap.add_argument("--no-backstep", action="store_true",
+                    help="skip the backward-facing step's forward and adjoint timing")
     ap.add_argument("--airfoil-steps", type=int, default=3000,
                     help="steps of the airfoil run (lift and drag in FP32-dev and FP64; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -473,6 +506,7 @@ def main():
         del sti
 
     airfoil = airfoil_run(F, args.airfoil_steps) if args.airfoil_steps > 0 else None
+    backstep = None if args.no_backstep else backstep_run(F, stream, args.warmup)
     cost_ratio = None if args.no_explicit else imex_vs_explicit(F, M, flow, init, dt_frac)
 
     cpu = None
@@ -522,6 +556,7 @@ def main():
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
         "airfoil_lift_drag": airfoil,
+        "backstep": backstep,
         "imex_over_explicit_per_step": cost_ratio,
         "sst_per_stage": per_stage,
         "sst_implicit": implicit,

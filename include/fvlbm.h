@@ -262,7 +262,8 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  * fvlbm_adjoint_bytes: device bytes of the adjoint workspace for n_steps recorded steps with a
  *   checkpoint every ckpt_every steps: checkpoints (11 n values each), one segment of states
  *   (ckpt_every + 1 of 11 n values) and of stage data (43 n values per step), a second such
- *   segment when the run has more than one, adjoint fields.
+ *   segment when the run has more than one and the mesh at most 262,144 cells (1,024 tiles),
+ *   adjoint fields.
  * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
  *   (f, k, omega) at the start of every segment and at the end in `workspace` (device memory owned
  *   by the caller, 256-byte aligned, kept alive until the adjoint has run).  Segments have at most
@@ -274,8 +275,9 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   step exactly (branches of max / min / upwind choices as taken).  Each segment of ckpt_every
  *   steps is recomputed once from its checkpoint, keeping every step's input state and stage data
  *   (the record pass leaves the last segment in that form); its steps are then reversed from the
- *   last.  With the ring-tiled sweep the recompute of the next segment (into the second set of
- *   segment buffers) runs on a stream of the library's own, created on first use, while the current
+ *   last.  With the ring-tiled sweep on meshes of at most 262,144 cells, where one launch leaves
+ *   most of the GPU idle, the recompute of the next segment (into the second set of segment
+ *   buffers) runs on a stream of the library's own, created on first use, while the current
  *   segment is reversed on the caller's stream; the two are ordered by events and the call returns
  *   with all work on the caller's stream.  The reverse: the combination and stage collisions in closed
  *   form, the convection term by its transpose, the SST update, fluxes, closure and LSQ gradients

@@ -98,6 +98,7 @@ struct fvlbm_state {
     // the reverse recomputes the next segment on a second stream while it reverses the current one
     hipStream_t side = nullptr;
     hipEvent_t ev_rev = nullptr, ev_rec = nullptr;
+    bool adj_two_sets = false;   // the recorded workspace holds the second set of segment buffers
     // per-kernel event timing (fvlbm_timing)
     bool timing = false;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> events;
@@ -833,19 +834,34 @@ struct AdjLayout {
 };
 
 // The layout with segment set k (0 or 1) as its segment buffers: segment sg of a run lives in set
-// sg % 2, so that one segment can be recomputed while the next is reversed.
+// sg % 2, so that one segment can be recomputed while the next is reversed; without a second set
+// every segment uses the first.
 template <typename T>
 AdjLayout<T> segment_set(const AdjLayout<T> &L, int k) {
     AdjLayout<T> r = L;
-    if (k & 1) {
+    if ((k & 1) && L.seg2) {
         r.seg = L.seg2;
         r.stg = L.stg2;
     }
     return r;
 }
 
+// The adjoint recomputes the next segment concurrently with the reverse of the current one only on
+// meshes of at most this many tiles: a launch there leaves most of the GPU idle, while on larger
+// meshes each launch fills it and the two streams only compete (measured: backstep, 481 tiles,
+// adjoint / forward 3.05 -> 2.29; 4.0M cells, 15,608 tiles, 2.91 -> 3.02).
+constexpr int32_t kOverlapMaxTiles = 1024;
+
+// Whether the adjoint workspace of this mesh holds the second set of segment buffers (and the
+// reverse overlaps); FVLBM_ADJ_OVERLAP=0 in the environment turns it off.
+inline bool adjoint_two_sets(const fvlbm_mesh *m) {
+    const char *e = std::getenv("FVLBM_ADJ_OVERLAP");
+    if (e && std::string(e) == "0") return false;
+    return m->n_tiles <= kOverlapMaxTiles;
+}
+
 template <typename T>
-size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout<T> &L) {
+size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, bool overlap, AdjLayout<T> &L) {
     const size_t sl = 11 * (size_t)n;
     const size_t nck = (size_t)((n_steps + ckpt - 1) / ckpt) + 1;
     L.state_len = sl;
@@ -854,7 +870,7 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, AdjLayout
     L.stage_len = 43 * (size_t)n;
     L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
     L.seg2 = L.stg2 = nullptr;
-    if (nck > 2) {
+    if (overlap && nck > 2) {
         L.seg2 = cv.take<T>((size_t)(ckpt + 1) * sl);
         L.stg2 = cv.take<T>((size_t)ckpt * L.stage_len);
     }
@@ -883,7 +899,7 @@ AdjLayout<T> adj_layout(fvlbm_state *st) {
     Carver cv;
     cv.base = st->adj_ws;
     AdjLayout<T> L;
-    adj_carve<T>(cv, st->n_cells, st->rec_steps, st->rec_ckpt, L);
+    adj_carve<T>(cv, st->n_cells, st->rec_steps, st->rec_ckpt, st->adj_two_sets, L);
     return L;
 }
 
@@ -1529,10 +1545,10 @@ fvlbm_status fvlbm_adjoint_bytes(const fvlbm_mesh *m, int32_t precision, int32_t
         Carver cv;
         if (precision == FVLBM_FP64) {
             AdjLayout<double> L;
-            *bytes = adj_carve<double>(cv, m->n, n_steps, std::min(ckpt_every, n_steps), L);
+            *bytes = adj_carve<double>(cv, m->n, n_steps, std::min(ckpt_every, n_steps), adjoint_two_sets(m), L);
         } else {
             AdjLayout<float> L;
-            *bytes = adj_carve<float>(cv, m->n, n_steps, std::min(ckpt_every, n_steps), L);
+            *bytes = adj_carve<float>(cv, m->n, n_steps, std::min(ckpt_every, n_steps), adjoint_two_sets(m), L);
         }
     });
 }
@@ -1545,9 +1561,18 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
         if (st->sst_stages) throw Error(FVLBM_ESTATE, "record: the per-stage SST coupling has no adjoint here");
         if (st->sst && st->par.sst_sweeps > 0) throw Error(FVLBM_ESTATE, "record: the implicit SST variant has no adjoint here");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");
+        // the layout (as fvlbm_adjoint_bytes sizes it), fixed here for the adjoint calls that follow
+        st->adj_two_sets = adjoint_two_sets(st->mesh);
+        Carver cv;
+        const int32_t ck = std::min(ckpt_every, n_steps);
         size_t need = 0;
-        fvlbm_status e = fvlbm_adjoint_bytes(st->mesh, st->precision, n_steps, ckpt_every, &need);
-        if (e != FVLBM_OK) throw Error(e, fvlbm_last_error());
+        if (st->precision == FVLBM_FP64) {
+            AdjLayout<double> L;
+            need = adj_carve<double>(cv, st->n_cells, n_steps, ck, st->adj_two_sets, L);
+        } else {
+            AdjLayout<float> L;
+            need = adj_carve<float>(cv, st->n_cells, n_steps, ck, st->adj_two_sets, L);
+        }
         if (ws_bytes < need) throw Error(FVLBM_EINVAL, "record: workspace too small (" + std::to_string(ws_bytes) + " < " + std::to_string(need) + ")");
         st->adj_ws = reinterpret_cast<char *>(workspace);
         st->adj_bytes = ws_bytes;

@@ -305,3 +305,28 @@ def test_wide_halo_ring_adjoint_fp32(F):
     print("fp32dev adjoint gradient", g, "reference", ref, "gates", tol32)
     scale = np.abs(ref).max()
     assert np.all(np.abs(g - ref) <= tol32 * np.maximum(np.abs(ref), 1e-6 * scale)), (g, ref)
+
+
+def test_adjoint_single_segment_set_equals_overlapped(F, monkeypatch):
+    """Large meshes keep one set of segment buffers and recompute on the caller's stream; small ones
+    recompute the next segment on a second stream into a second set.  Forced here on one small mesh
+    (FVLBM_ADJ_OVERLAP=0) with three segments: the same adjoint state and parameter gradient to the
+    last bit, and the same as a recording without checkpoints."""
+    say("adjoint, one segment set vs two, backstep sst")
+    m, p, orc, f0, k0, w0, sst = _run_case("backstep_sst", seed=93)
+    n = orc.g.n
+    rng = np.random.default_rng(94)
+    lf, lk, lw = rng.standard_normal((9, n)), rng.standard_normal(n) * 1e3, rng.standard_normal(n)
+    M = F.Mesh(m)
+    out = {}
+    for key, env, ckpt in (("two", "1", 2), ("one", "0", 2), ("whole", "1", 5)):
+        monkeypatch.setenv("FVLBM_ADJ_OVERLAP", env)
+        st = F.State(M, p, precision="fp64", k=k0, omega=w0)
+        st.set_state(f0, k0, w0)
+        st.record(5, ckpt_every=ckpt)
+        out[key] = st.adjoint_state(lf, lk, lw)
+        del st
+    for a, b in zip(out["two"], out["one"]):
+        np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
+    for a, b in zip(out["two"], out["whole"]):
+        np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
