@@ -123,3 +123,68 @@ def test_fullsize_sampled_parity_implicit_sst(F, full):
     extra = dict(sst_sweeps=4)
     ref = _reference(full, 12, extra)
     _check(F, full, ref, extra, {"sst": 1, "sst_jacobi": 1, "sweep2": 1, "collide1": 0})
+
+
+@pytest.mark.timeout(900)
+def test_backstep_fullsize_parity(F):
+    """The backward-facing step the benchmark times (122,956 hybrid cells, SST, about 34 tau0) on the
+    whole mesh, which the oracle can step: one step in FP64 and FP32-deviation storage on the ring
+    path (its tiles have up to 298 ring-2 cells) against the oracle on every cell, and the FP64
+    adjoint of two recorded steps with a checkpoint every step (the next segment recomputed on the
+    second stream) against the oracle's complex step along one direction of the initial state."""
+    H_CS = 1e-30
+    mesh, flow, init, dt_frac = bench.workload("backstep")
+    say("backstep full size: library preprocessing and oracle geometry")
+    M = F.Mesh(mesh, order="morton")
+    p = O.default_params(**dict(flow, dt=min(flow["dt"], dt_frac * M.max_dt())))
+    orc = O.Oracle(mesh, p)
+    n = orc.g.n
+    assert n == M.n_cells > 120_000
+    rng = np.random.default_rng(12)
+    x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+    ux = 0.04 + 0.01 * np.sin(0.5 * x) * np.cos(3 * y) + 0.002 * rng.standard_normal(n)
+    uy = 0.004 * np.sin(2 * y) + 0.002 * rng.standard_normal(n)
+    rho = 1 + 0.001 * rng.standard_normal(n)
+    f0 = O.feq(rho, ux, uy) + 1e-5 * O.WT[:, None] * rng.standard_normal((9, n))
+    k0 = 1e-6 * (1 + 0.5 * rng.random(n))
+    w0 = 1e-2 * (1 + 0.5 * rng.random(n))
+    say("oracle step")
+    f1, k1, w1 = orc.step(f0, k0, w0)
+    nut1 = orc.last_nut
+    for precision in ("fp64", "fp32dev"):
+        say("one step on the GPU,", precision)
+        st = F.State(M, p, precision=precision, k=k0, omega=w0)
+        st.set_state(f0, k0, w0)
+        st.timing(True)
+        st.step(1)
+        kt = st.timing_read()
+        st.timing(False)
+        assert kt["sst"][1] == 1 and kt["collide1"][1] == 0, kt     # the ring path
+        mo = st.moments()
+        if precision == "fp64":
+            err = np.abs(st.get_f() - f1).max() / np.abs(f1 - O.WT[:, None]).max()
+            assert err < 1e-12, err
+            for name, got, ref in (("k", mo["k"], k1), ("omega", mo["omega"], w1), ("nu_t", mo["nu_t"], nut1)):
+                e = np.abs(got - ref).max() / np.abs(ref).max()
+                assert e < 1e-11, (name, e)
+        else:
+            _, ux1, uy1, _ = orc.macro(f1)
+            du = max(np.abs(mo["u"][:, 0] - ux1).max(), np.abs(mo["u"][:, 1] - uy1).max()) / 0.05
+            dk = np.abs(mo["k"] - k1).max() / np.abs(k1).max()
+            dw = np.abs(mo["omega"] - w1).max() / np.abs(w1).max()
+            say("fp32dev errors: du/U", du, "dk", dk, "dw", dw)
+            assert du < 2e-6 and dk < 2e-6 and dw < 2e-6, (du, dk, dw)
+        del st
+    say("FP64 adjoint of two steps against the complex step")
+    st = F.State(M, p, precision="fp64", k=k0, omega=w0)
+    st.set_state(f0, k0, w0)
+    st.record(2, ckpt_every=1)
+    lf, lk, lw = rng.standard_normal((9, n)), rng.standard_normal(n) * 1e3, rng.standard_normal(n)
+    lf0, lk0, lw0, _ = st.adjoint_state(lf, lk, lw)
+    vf = rng.standard_normal((9, n)) * O.WT[:, None] * 1e-3
+    vk, vw = rng.standard_normal(n) * 1e-7, rng.standard_normal(n) * 1e-3
+    fN, kN, wN = O.Oracle(mesh, p).run(f0 + 1j * H_CS * vf, k0 + 1j * H_CS * vk, w0 + 1j * H_CS * vw, 2)
+    rhs = (np.sum(lf * np.imag(fN)) + np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))) / H_CS
+    lhs = np.sum(lf0 * vf) + np.sum(lk0 * vk) + np.sum(lw0 * vw)
+    say("adjoint dot product", lhs, rhs)
+    assert abs(lhs - rhs) <= 1e-9 * abs(rhs), (lhs, rhs)
