@@ -151,6 +151,10 @@ def survey_step_bytes(T):
     return 95 * T + 584
 
 
+# cell renumbering of every mesh the benchmark builds (the --order option)
+ORDER = ["tiles"]
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1812_00394_amd", "csrc")
@@ -247,7 +251,7 @@ def imex_vs_explicit(F, M_big, flow_big, init_big, dt_frac_big):
         return (time.perf_counter() - t0) / steps * 1e3
 
     out = {}
-    cav = F.Mesh(mg.cavity())
+    cav = F.Mesh(mg.cavity(), order=ORDER[0])
     nu = 0.1 / 1000
     n = cav.n_cells
     for name, dt in (("imex", 10 * 3 * nu), ("explicit", 3 * nu)):
@@ -275,7 +279,7 @@ def backstep_run(F, stream, warmup, steps=2000, adj_steps=400, ckpt=20):
     `ckpt` steps in both precisions, against the forward time of the same steps."""
     import torch
     mesh, flow, init, dt_frac = workload("backstep")
-    M = F.Mesh(mesh, order="morton")
+    M = F.Mesh(mesh, order=ORDER[0])
     n = M.n_cells
     out = {"cells": n, "steps": steps}
     for prec in ("fp32dev", "fp64"):
@@ -307,7 +311,7 @@ def airfoil_run(F, steps):
     steps in FP32-dev and FP64, and the throughput of both."""
     import torch
     from paper_1812_00394_amd import meshgen as mg
-    M = F.Mesh(mg.naca_omesh())
+    M = F.Mesh(mg.naca_omesh(), order=ORDER[0])
     n = M.n_cells
     _, _, wd = M.geometry()
     U, c, Re, alpha = 0.05, 1.0, 6e6, np.deg2rad(10.0)
@@ -350,6 +354,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=50, help="recorded steps of the adjoint timing (0: skip)")
     ap.add_argument("--ckpt", type=int, default=20, help="checkpoint interval of the adjoint")
     ap.add_argument("--no-explicit", action="store_true", help="skip the IMEX / explicit cost comparison")
+    ap.add_argument("--order", default="tiles", choices=["morton", "tiles", "rcm", "none"],
+                    help="cell renumbering of the meshes (fvlbm_mesh_create order)")
     ap.add_argument("--no-backstep", action="store_true",
                     help="skip the backward-facing step's forward and adjoint timing")
     ap.add_argument("--airfoil-steps", type=int, default=3000,
@@ -357,6 +363,7 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for rocprof byte counters)")
     args = ap.parse_args()
+    ORDER[0] = args.order
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of this "
               "path is a design note, not built", file=sys.stderr)
@@ -371,7 +378,7 @@ def main():
     mesh, flow, init, dt_frac = workload(args.workload)
     log(f"mesh {mesh['name']}: {len(mesh['cell_ptr']) - 1} cells generated in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    M = F.Mesh(mesh, order="morton")
+    M = F.Mesh(mesh, order=ORDER[0])
     log(f"library preprocessing {time.perf_counter() - t0:.1f}s")
     n = M.n_cells
     S = float(np.mean(np.diff(mesh["cell_ptr"])))
@@ -447,7 +454,11 @@ def main():
         torch.cuda.synchronize()
         t_adj = time.perf_counter() - t0
         t_fwd = ms / args.steps * 1e-3 * args.adjoint_steps
-        adjoint = {"steps": args.adjoint_steps, "ckpt_every": args.ckpt, "record_s": round(t_rec, 4),
+        # the record pass keeps the tapes of the last two segments (counted from the end of the run)
+        nseg = -(-args.adjoint_steps // args.ckpt)
+        recomputed = max(0, args.adjoint_steps - 2 * args.ckpt) if nseg > 1 else 0
+        adjoint = {"steps": args.adjoint_steps, "ckpt_every": args.ckpt, "steps_recomputed": recomputed,
+                   "record_s": round(t_rec, 4),
                    "adjoint_s": round(t_adj, 4), "forward_s": round(t_fwd, 4),
                    "ratio": round(t_adj / t_fwd, 3), "functional": "x-force on the walls",
                    "gradient": [float(x) for x in grad]}
@@ -542,9 +553,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.precision == "fp32dev" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {n} cells, D2Q9 + k-omega SST, {args.precision}, "
-                               f"dt {p['dt']:.3g} ({p['dt'] / (3 * p['nu']):.0f} tau0)",
-                   "cells": n, "precision": args.precision, "sst": bool(p.get("sst"))},
+        "config": {"workload": f"{args.workload}: {n} cells, D2Q9{' + k-omega SST' if p.get('sst') else ''}, "
+                               f"{args.precision}, dt {p['dt']:.3g} ({p['dt'] / (3 * p['nu']):.0f} tau0)",
+                   "cells": n, "precision": args.precision, "sst": bool(p.get("sst")), "order": args.order},
         "roofline": roofline,
         "step_roofline": {"bytes_per_cell": round(sb, 1), "achieved_gbs": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4),

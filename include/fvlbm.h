@@ -54,7 +54,7 @@ enum {
 };
 
 enum { FVLBM_FP64 = 0, FVLBM_FP32_DEV = 1 };                  /* storage / arithmetic of f */
-enum { FVLBM_ORDER_NONE = 0, FVLBM_ORDER_MORTON = 1, FVLBM_ORDER_RCM = 2 };
+enum { FVLBM_ORDER_NONE = 0, FVLBM_ORDER_MORTON = 1, FVLBM_ORDER_RCM = 2, FVLBM_ORDER_TILES = 3 };
 
 #define FVLBM_MAX_GROUPS 16
 
@@ -118,7 +118,10 @@ typedef struct {
  *   group_kind    [n_groups] FVLBM_WALL ... FVLBM_PERIODIC
  *   periodic_shift [n_groups][2] or NULL: translation taking a periodic group's edges onto their
  *                 partner edges
- *   order         internal renumbering (FVLBM_ORDER_*)
+ *   order         internal renumbering (FVLBM_ORDER_*): MORTON sorts the centroids along a Morton
+ *                 curve; TILES grows tiles of 256 cells breadth-first on the cell graph from
+ *                 Morton-ordered seeds (compact tiles, small halos, on stretched meshes too);
+ *                 RCM is reverse Cuthill-McKee; NONE keeps the user's order
  * Computes, in FP64 on the host: cell areas and centroids, edge normals and midpoints, the
  * weighted least-squares gradient coefficients, the wall distance (exact nearest point on the
  * WALL / MOVING_WALL edges) and the renumbering.  Errors: FVLBM_EINVAL, FVLBM_EMESH.
@@ -262,20 +265,20 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  * fvlbm_adjoint_bytes: device bytes of the adjoint workspace for n_steps recorded steps with a
  *   checkpoint every ckpt_every steps: checkpoints (11 n values each), one segment of states
  *   (ckpt_every + 1 of 11 n values) and of stage data (43 n values per step), a second such
- *   segment when the run has more than one and the mesh at most 262,144 cells (1,024 tiles),
- *   adjoint fields.
+ *   segment when the run has more than one, adjoint fields.
  * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
  *   (f, k, omega) at the start of every segment and at the end in `workspace` (device memory owned
  *   by the caller, 256-byte aligned, kept alive until the adjoint has run).  Segments have at most
  *   ckpt_every steps and are counted from the end of the run (only the first may be shorter); the
- *   last one is kept whole, with its stage data, so that the reverse starts without recomputing it.
+ *   last two (the last one when the run has one segment) are kept whole, with their stage data, in
+ *   the two sets of segment buffers, so that the reverse recomputes neither.
  * fvlbm_adjoint_step: for J = seed[0] F_x + seed[1] F_y + seed[2] J_R of the final state (forces of
  *   the walls in wall_group_mask and the reversed-flow length, as fvlbm_forces), returns
  *   dparams = dJ/d(theta, sigma_k1, sigma_omega1, beta*, a1) in FP64, differentiating the discrete
  *   step exactly (branches of max / min / upwind choices as taken).  Each segment of ckpt_every
  *   steps is recomputed once from its checkpoint, keeping every step's input state and stage data
- *   (the record pass leaves the last segment in that form); its steps are then reversed from the
- *   last.  With the ring-tiled sweep on meshes of at most 262,144 cells, where one launch leaves
+ *   (the record pass leaves the last two segments in that form); its steps are then reversed from
+ *   the last.  With the ring-tiled sweep on meshes of at most 262,144 cells, where one launch leaves
  *   most of the GPU idle, the recompute of the next segment (into the second set of segment
  *   buffers) runs on a stream of the library's own, created on first use, while the current
  *   segment is reversed on the caller's stream; the two are ordered by events and the call returns

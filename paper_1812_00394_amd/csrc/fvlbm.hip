@@ -78,7 +78,7 @@ struct fvlbm_state {
     size_t sst_lds_bytes = 0;
     bool want_aux = false;       // the SST launch also stores the aux planes (adjoint recompute)
     void *F_out = nullptr;       // where a step writes f^{n+1} (nullptr: over f^n)
-    bool last_seg_valid = false; // the segment buffers hold the recorded run's last segment
+    int held_segs = 0;           // trailing segments of the recorded run whose tapes the segment buffers hold
     int32_t *hptr = nullptr, *hcell = nullptr;
     int32_t *xptr = nullptr, *xn1 = nullptr, *xcell = nullptr;
     int16_t *xlnb = nullptr;
@@ -852,12 +852,12 @@ AdjLayout<T> segment_set(const AdjLayout<T> &L, int k) {
 // adjoint / forward 3.05 -> 2.29; 4.0M cells, 15,608 tiles, 2.91 -> 3.02).
 constexpr int32_t kOverlapMaxTiles = 1024;
 
-// Whether the adjoint workspace of this mesh holds the second set of segment buffers (and the
-// reverse overlaps); FVLBM_ADJ_OVERLAP=0 in the environment turns it off.
-inline bool adjoint_two_sets(const fvlbm_mesh *m) {
+// Whether the adjoint workspace holds a second set of segment buffers (runs of more than one
+// segment): the record pass then keeps the tapes of the last two segments, and on small meshes the
+// reverse overlaps.  FVLBM_ADJ_OVERLAP=0 in the environment keeps one set.
+inline bool adjoint_two_sets(const fvlbm_mesh *) {
     const char *e = std::getenv("FVLBM_ADJ_OVERLAP");
-    if (e && std::string(e) == "0") return false;
-    return m->n_tiles <= kOverlapMaxTiles;
+    return !(e && std::string(e) == "0");
 }
 
 template <typename T>
@@ -986,29 +986,31 @@ inline void segment_bounds(int N, int C, int sg, int &first, int &last) {
 }
 
 // Advances the recorded run, storing a checkpoint at the start of every segment and the final
-// state.  The last segment is run through the segment buffers, so that the reverse starts without
-// recomputing it.
+// state.  The last segment, and with two sets of segment buffers the one before it too, is run
+// through its set of segment buffers, so that the reverse starts without recomputing them.
 template <typename T>
 void record(fvlbm_state *st) {
     AdjLayout<T> L = adj_layout<T>(st);
     const int N = st->rec_steps, C = st->rec_ckpt;
     const int nseg = (N + C - 1) / C;
-    for (int sg = 0; sg < nseg - 1; ++sg) {
+    const int held = (L.seg2 && nseg > 1) ? 2 : 1;
+    for (int sg = 0; sg < nseg - held; ++sg) {
         int first, last;
         segment_bounds(N, C, sg, first, last);
         save_state<T>(st, L.ckpt + (size_t)sg * L.state_len);
         for (int i = first; i < last; ++i) launch_step<T>(st);
     }
-    int first_last, last_last;
-    segment_bounds(N, C, nseg - 1, first_last, last_last);
-    save_state<T>(st, L.ckpt + (size_t)(nseg - 1) * L.state_len);
-    const AdjLayout<T> Ls = segment_set(L, (nseg - 1) % 2);
-    save_state<T>(st, Ls.seg);
-    for (int32_t i = first_last; i < N; ++i) step_seg<T>(st, Ls, i - first_last);
-    load_state<T>(st, Ls.seg + (size_t)(N - first_last) * L.state_len);
-    const size_t nck = (size_t)nseg;
-    save_state<T>(st, L.ckpt + nck * L.state_len);
-    st->last_seg_valid = true;
+    for (int sg = nseg - held; sg < nseg; ++sg) {
+        int first, last;
+        segment_bounds(N, C, sg, first, last);
+        save_state<T>(st, L.ckpt + (size_t)sg * L.state_len);
+        const AdjLayout<T> Ls = segment_set(L, sg % 2);
+        save_state<T>(st, Ls.seg);
+        for (int i = first; i < last; ++i) step_seg<T>(st, Ls, i - first);
+        load_state<T>(st, Ls.seg + (size_t)(last - first) * L.state_len);
+    }
+    save_state<T>(st, L.ckpt + (size_t)nseg * L.state_len);
+    st->held_segs = held;
     st->steps_done += N;
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
 }
@@ -1059,9 +1061,10 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
 
 // Reverse of the whole recorded run (L.lF / lK / lW seeded with the adjoint of the final state).
 // Each segment is recomputed once from its checkpoint in its set of segment buffers, keeping every
-// step's input state and stage data (the last segment comes from the record pass while its buffers
-// still hold it); then its steps are reversed from the last.  On the ring path the recompute of
-// segment sg - 1 runs on a second stream while segment sg is reversed: the two touch disjoint
+// step's input state and stage data (the last one or two segments come from the record pass while
+// their buffers still hold them); then its steps are reversed from the last.  On the ring path and
+// small meshes the recompute of segment sg - 1 runs on a second stream while segment sg is
+// reversed: the two touch disjoint
 // buffers (the recompute: its segment set, the macro buffers and nu_t; the reverse: the other set
 // and the adjoint fields), and each waits only for the work on the set it is about to reuse.
 template <typename T>
@@ -1070,7 +1073,9 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
     const int N = st->rec_steps, C = st->rec_ckpt;
     const int nseg = (N + C - 1) / C;
     const size_t n = st->n_cells;
-    const bool overlap = st->ring && nseg > 1 && L.seg2;
+    const bool overlap = st->ring && nseg > 1 && L.seg2 && st->mesh->n_tiles <= kOverlapMaxTiles;
+    const int held = st->held_segs;   // trailing segments whose tapes the record pass left
+    auto is_held = [&](int sg) { return sg >= nseg - held; };
     if (overlap && !st->side) {
         // non-blocking: no implicit ordering with a legacy default stream; the events order the two
         check(hipStreamCreateWithFlags(&st->side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
@@ -1094,12 +1099,12 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
         for (int i = first; i < last; ++i) step_seg<T>(st, Ls, i - first);
         st->stream = main_stream;
     };
-    if (!st->last_seg_valid) recompute(nseg - 1, main_stream);
-    st->last_seg_valid = false;
+    if (!is_held(nseg - 1)) recompute(nseg - 1, main_stream);
+    st->held_segs = 0;
     for (int sg = nseg - 1; sg >= 0; --sg) {
         int first, last;
         segment_bounds(N, C, sg, first, last);
-        if (overlap && sg > 0) {
+        if (overlap && sg > 0 && !is_held(sg - 1)) {
             // set (sg - 1) % 2 was last read by the reverse of segment sg + 1, all of it queued
             check(hipEventRecord(st->ev_rev, main_stream), "hipEventRecord");
             check(hipStreamWaitEvent(st->side, st->ev_rev, 0), "hipStreamWaitEvent");
@@ -1115,7 +1120,7 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
                 std::swap(L.lW, L.lW2);
             }
         }
-        if (sg > 0) {
+        if (sg > 0 && !is_held(sg - 1)) {
             if (overlap)
                 check(hipStreamWaitEvent(main_stream, st->ev_rec, 0), "hipStreamWaitEvent");
             else
@@ -1128,7 +1133,6 @@ void reverse_run(fvlbm_state *st, const AdjLayout<T> &L0) {
         check(hipMemcpyAsync(L0.lK, L.lK, n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
         check(hipMemcpyAsync(L0.lW, L.lW, n * sizeof(T), hipMemcpyDeviceToDevice, st->stream), "hipMemcpyAsync D2D");
     }
-    st->last_seg_valid = false;
     // restore the final state
     load_state<T>(st, L.ckpt + (size_t)nseg * L.state_len);
     // macro buffers for a residual of a later step: both hold the final macro variables

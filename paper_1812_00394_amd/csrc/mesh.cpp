@@ -156,7 +156,7 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
         throw Error(FVLBM_EINVAL, "mesh_create: boundary arrays missing");
     if (n_groups < 0 || n_groups > FVLBM_MAX_GROUPS || (n_groups > 0 && !group_kind))
         throw Error(FVLBM_EINVAL, "mesh_create: n_groups must be in [0, 16]");
-    if (order < FVLBM_ORDER_NONE || order > FVLBM_ORDER_RCM) throw Error(FVLBM_EINVAL, "mesh_create: bad order");
+    if (order < FVLBM_ORDER_NONE || order > FVLBM_ORDER_TILES) throw Error(FVLBM_EINVAL, "mesh_create: bad order");
     auto m = std::make_unique<fvlbm_mesh>();
     m->n = n_cells;
     m->n_nodes = n_nodes;
@@ -313,7 +313,7 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
     // ---- renumbering ----
     std::vector<int64_t> perm(n_cells);
     std::iota(perm.begin(), perm.end(), 0);
-    if (order == FVLBM_ORDER_MORTON) {
+    if (order == FVLBM_ORDER_MORTON || order == FVLBM_ORDER_TILES) {
         double xmin = *std::min_element(cxu.begin(), cxu.end()), xmax = *std::max_element(cxu.begin(), cxu.end());
         double ymin = *std::min_element(cyu.begin(), cyu.end()), ymax = *std::max_element(cyu.begin(), cyu.end());
         double span = std::max(xmax - xmin, ymax - ymin);
@@ -326,6 +326,45 @@ fvlbm_mesh *build_mesh(int64_t n_nodes, const double *xy, int64_t n_cells, const
             code[c] = spread_bits(ix) | (spread_bits(iy) << 1);
         }
         std::stable_sort(perm.begin(), perm.end(), [&](int64_t a, int64_t b) { return code[a] < code[b]; });
+        if (order == FVLBM_ORDER_TILES) {
+            // Tiles of kTile cells grown breadth-first on the cell graph, each from the first cell
+            // (in Morton order) not yet placed; a region that runs out of unplaced neighbours
+            // continues from the next such cell.  The tiles keep the Morton order of their seeds and
+            // the cells inside a tile their Morton order.  On anisotropic meshes a Morton tile of thin
+            // cells is a long strip with a large halo; a graph-grown tile stays compact.
+            std::vector<int64_t> rank(n_cells);
+            for (int64_t i = 0; i < n_cells; ++i) rank[perm[i]] = i;
+            std::vector<char> placed(n_cells, 0);
+            std::vector<int64_t> out, queue;
+            out.reserve(n_cells);
+            int64_t next = 0;
+            while ((int64_t)out.size() < n_cells) {
+                const size_t start = out.size(), limit = std::min<size_t>(n_cells, start + kTile);
+                queue.clear();
+                size_t head = 0;
+                while (out.size() < limit) {
+                    if (head == queue.size()) {
+                        while (next < n_cells && placed[perm[next]]) ++next;
+                        if (next == n_cells) break;
+                        queue.push_back(perm[next]);
+                        placed[perm[next]] = 1;
+                    }
+                    const int64_t c = queue[head++];
+                    out.push_back(c);
+                    for (int64_t h = cell_ptr[c]; h < cell_ptr[c + 1]; ++h) {
+                        if (partner[h] < 0) continue;
+                        const int64_t v = hcell[partner[h]];
+                        if (!placed[v]) {
+                            placed[v] = 1;
+                            queue.push_back(v);
+                        }
+                    }
+                }
+                for (size_t i = head; i < queue.size(); ++i) placed[queue[i]] = 0;   // queued, not taken
+                std::sort(out.begin() + start, out.end(), [&](int64_t a, int64_t b) { return rank[a] < rank[b]; });
+            }
+            perm = out;
+        }
     } else if (order == FVLBM_ORDER_RCM) {
         std::vector<int32_t> deg(n_cells, 0);
         for (int64_t h = 0; h < H; ++h)

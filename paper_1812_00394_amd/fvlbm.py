@@ -18,7 +18,7 @@ from .build import LIB
 
 FVLBM_MAX_GROUPS = 16
 FP64, FP32_DEV = 0, 1
-ORDERS = {"none": 0, "morton": 1, "rcm": 2}
+ORDERS = {"none": 0, "morton": 1, "rcm": 2, "tiles": 3}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED", -6: "ESTATE"}
 
 # k-omega SST constants as listed in Section 2 of the paper

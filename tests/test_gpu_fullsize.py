@@ -1,6 +1,6 @@
 """Parity at the benchmark's full size and launch configuration: the 4.0M-cell graded Delaunay
-rectangle with SST, the developed-stream initial state and the sweep variant the benchmark times
-(ring-tiled), one step in FP64 and in FP32-deviation storage, against the oracle on sampled cells.
+rectangle with SST, the developed-stream initial state, the cell renumbering (graph-grown tiles) and
+the sweep variant (ring-tiled) the benchmark times, one step in FP64 and in FP32-deviation storage, against the oracle on sampled cells.
 
 The oracle cannot step four million cells, but one step reaches only six edge rings (measured in
 test_submesh_oracle.py, which also checks the method against full oracle runs): for sample cells
@@ -63,7 +63,7 @@ def full(F):
     seeds = np.unique(np.r_[rng.choice(n, 6, replace=False), rng.choice(bottom, 3), rng.choice(top, 2),
                             rng.choice(inlet, 2), rng.choice(outlet, 2), corners[:4]])
     say("library mesh preprocessing")
-    M = F.Mesh(m)
+    M = F.Mesh(m, order="tiles")
     return m, n, u, k, w, seeds, M
 
 
@@ -135,7 +135,7 @@ def test_backstep_fullsize_parity(F):
     H_CS = 1e-30
     mesh, flow, init, dt_frac = bench.workload("backstep")
     say("backstep full size: library preprocessing and oracle geometry")
-    M = F.Mesh(mesh, order="morton")
+    M = F.Mesh(mesh, order="tiles")
     p = O.default_params(**dict(flow, dt=min(flow["dt"], dt_frac * M.max_dt())))
     orc = O.Oracle(mesh, p)
     n = orc.g.n
@@ -188,3 +188,55 @@ def test_backstep_fullsize_parity(F):
     lhs = np.sum(lf0 * vf) + np.sum(lk0 * vk) + np.sum(lw0 * vw)
     say("adjoint dot product", lhs, rhs)
     assert abs(lhs - rhs) <= 1e-9 * abs(rhs), (lhs, rhs)
+
+
+@pytest.mark.timeout(900)
+def test_airfoil_fullsize_parity(F):
+    """The airfoil the benchmark times (512 x 384 O-mesh, 196,608 quads, Re 6e6, 10 degrees, about
+    74 tau0, limiter on, developed near-wall start), whole mesh: one step against the oracle on every
+    cell in both precisions, and the wall force (fvlbm_forces) against the oracle's in FP64."""
+    say("airfoil full size: mesh, library preprocessing, oracle geometry")
+    m = mg.naca_omesh()
+    M = F.Mesh(m, order="tiles")
+    n = M.n_cells
+    _, _, wd = M.geometry()
+    Uinf, c, Re, alpha = 0.05, 1.0, 6e6, np.deg2rad(10.0)
+    nu = Uinf * c / Re
+    kinf, winf = 1e-3 * Uinf * Uinf / Re, 5 * Uinf / c
+    p = O.default_params(nu=nu, dt=min(180 * 3 * nu, 0.9 * M.max_dt()), sst=True, theta=alpha, limiter=1,
+                         group_u=[[0, 0], [Uinf, 0]], group_rho=[1, 1], group_k=[0, kinf], group_w=[0, winf])
+    fac = np.minimum(1.0, (wd / 0.01) ** (1 / 7))
+    u0 = np.stack([Uinf * np.cos(alpha) * fac, Uinf * np.sin(alpha) * fac], axis=1)
+    w0 = np.maximum(winf, 6 * nu / (0.075 * wd ** 2))
+    k0 = np.full(n, kinf)
+    orc = O.Oracle(m, p)
+    f0, k0o, w0o = orc.init_state(np.ones(n), u0[:, 0], u0[:, 1], k0, w0)
+    say("oracle step")
+    f1, k1, w1 = orc.step(f0, k0o, w0o)
+    nut1 = orc.last_nut
+    F1, _ = orc.forces(f1, 1)
+    for precision in ("fp64", "fp32dev"):
+        say("one step on the GPU,", precision)
+        st = F.State(M, p, precision=precision, rho=np.ones(n), u=u0, k=k0, omega=w0)
+        st.timing(True)
+        st.step(1)
+        kt = st.timing_read()
+        st.timing(False)
+        assert kt["sst"][1] == 1 and kt["collide1"][1] == 0, kt     # the ring path
+        mo = st.moments()
+        if precision == "fp64":
+            err = np.abs(st.get_f() - f1).max() / np.abs(f1 - O.WT[:, None]).max()
+            assert err < 1e-12, err
+            for name, got, ref in (("k", mo["k"], k1), ("omega", mo["omega"], w1), ("nu_t", mo["nu_t"], nut1)):
+                e = np.abs(got - ref).max() / np.abs(ref).max()
+                assert e < 1e-11, (name, e)
+            Fg, _ = st.forces(1)
+            assert np.abs(Fg - F1).max() <= 1e-10 * np.abs(F1).max(), (Fg, F1)
+        else:
+            _, ux1, uy1, _ = orc.macro(f1)
+            du = max(np.abs(mo["u"][:, 0] - ux1).max(), np.abs(mo["u"][:, 1] - uy1).max()) / Uinf
+            dk = np.abs(mo["k"] - k1).max() / np.abs(k1).max()
+            dw = np.abs(mo["omega"] - w1).max() / np.abs(w1).max()
+            say("fp32dev errors: du/U", du, "dk", dk, "dw", dw)
+            assert du < 2e-6 and dk < 2e-6 and dw < 2e-6, (du, dk, dw)
+        del st

@@ -382,7 +382,7 @@ def test_airfoil_full_size_lift_drag_fp32_vs_fp64(F):
     drag in FP32-deviation storage agree with FP64 within 1e-4 relative (stated gate)."""
     say("airfoil 196608 quads, 3000 steps, fp64 and fp32dev")
     m = mg.naca_omesh()
-    M = F.Mesh(m)
+    M = F.Mesh(m, order="tiles")     # the benchmark's renumbering
     n = M.n_cells
     _, _, wd = M.geometry()
     U, c, Re, alpha = 0.05, 1.0, 6e6, np.deg2rad(10.0)

@@ -40,7 +40,7 @@ MESHES = {
 
 
 @pytest.mark.parametrize("name", sorted(MESHES))
-@pytest.mark.parametrize("order", ["none", "morton", "rcm"])
+@pytest.mark.parametrize("order", ["none", "morton", "rcm", "tiles"])
 def test_geometry_matches_oracle(name, order):
     m = MESHES[name]()
     M = F.Mesh(m, order=order)
@@ -136,3 +136,35 @@ def test_wide_halo_backstep_tiles():
         r1.append(len(h1))
         ext.append(len(h1) + len(h2))
     assert max(r1) <= 256 < max(ext), (max(r1), max(ext))
+
+
+def _tile_rings(m, order):
+    """Ring-1 and ring-1 + ring-2 cell counts of every 256-cell tile of the library's renumbering."""
+    import scipy.sparse as sp
+    M = F.Mesh(m, order=order)
+    perm = M.permutation()
+    n = len(perm)
+    inv = np.empty(n, np.int64)
+    inv[perm] = np.arange(n)
+    G = O.Geometry(m)
+    inner = np.nonzero(G.interior)[0]
+    A = sp.csr_matrix((np.ones(len(inner)), (inv[G.cell[inner]], inv[G.nbr[inner]])), shape=(n, n))
+    r1, ext = [], []
+    for t in range((n + 255) // 256):
+        cells = np.arange(t * 256, min(n, t * 256 + 256))
+        h1 = np.setdiff1d(np.unique(A[cells].indices), cells)
+        h2 = np.setdiff1d(np.unique(A[h1].indices), np.concatenate([cells, h1]))
+        r1.append(len(h1))
+        ext.append(len(h1) + len(h2))
+    return np.array(r1), np.array(ext)
+
+
+def test_graph_tiles_are_compact_on_stretched_meshes():
+    """The graph-grown tiles (order "tiles") on an O-mesh with thin wall cells (256 x 192 quads, first
+    cell 4.5e-6 chord): Morton tiles there are strips whose ring-1 halos exceed one thread per cell;
+    graph-grown tiles keep every ring-1 halo within 256 and the mean halo at less than half."""
+    m = mg.naca_omesh(n_wall=256, n_normal=192, y1=4.5e-6)
+    r1m, extm = _tile_rings(m, "morton")
+    r1t, extt = _tile_rings(m, "tiles")
+    assert r1m.max() > 256 >= r1t.max(), (r1m.max(), r1t.max())
+    assert r1t.mean() < 0.5 * r1m.mean() and extt.mean() < 0.5 * extm.mean(), (r1t.mean(), r1m.mean())
