@@ -144,10 +144,10 @@ def step_bytes(T, S):
     return (81 + 14) * T + 4 * geo + 8
 
 
-# The survey's whole-step model: the same 95 state values, with the geometry of four sweeps priced
-# in FP64 (area, centroid, neighbour and face ids, LSQ coefficients, 1.5 faces of normal and
-# midpoint per triangle: 144 B per sweep) plus the wall distance: 584 B per triangle.
-def survey_step_bytes(T):
+# The whole-step model with FP64 geometry: the same 95 state values, with the geometry of four
+# sweeps priced in FP64 (area, centroid, neighbour and face ids, LSQ coefficients, 1.5 faces of
+# normal and midpoint per triangle: 144 B per sweep) plus the wall distance: 584 B per triangle.
+def fp64_geometry_step_bytes(T):
     return 95 * T + 584
 
 
@@ -560,9 +560,9 @@ def main():
         "step_roofline": {"bytes_per_cell": round(sb, 1), "achieved_gbs": round(step_gbs, 1),
                           "frac": round(step_gbs / HBM_PEAK_GBS, 4),
                           "as_built_bytes_per_cell": sum(kb[k] for k in per_kernel),
-                          "survey_bytes_per_cell": survey_step_bytes(T) if S == 3 and p.get("sst") else None,
-                          "survey_frac": (round(survey_step_bytes(T) * n * args.steps / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-                                          if S == 3 and p.get("sst") else None)},
+                          "fp64_geometry_bytes_per_cell": fp64_geometry_step_bytes(T) if S == 3 and p.get("sst") else None,
+                          "fp64_geometry_frac": (round(fp64_geometry_step_bytes(T) * n * args.steps / (ms * 1e-3) / 1e9
+                                                       / HBM_PEAK_GBS, 4) if S == 3 and p.get("sst") else None)},
         "kernels": per_kernel,
         "adjoint_forward_ratio": adjoint["ratio"] if adjoint else None,
         "adjoint": adjoint,
