@@ -13,11 +13,17 @@
  *     fvlbm_last_error() returns a message (thread-local, valid until the next call on the
  *     same thread).
  *   - Host arrays are plain C arrays in the caller's cell order ("user order"); the library
- *     renumbers cells internally (Morton or RCM) and never exposes that order.
+ *     renumbers cells internally (Morton, graph-grown tiles or RCM) and never exposes that order.
  *   - Device memory is owned by the caller: fvlbm_state_bytes() says how much, fvlbm_init()
  *     receives it.  The library itself allocates no device memory.
- *   - All device work is enqueued on the HIP stream given to fvlbm_init().  Calls that return
- *     host values synchronise that stream; the others are asynchronous.
+ *   - All device work is enqueued on the HIP stream given to fvlbm_init() (the adjoint's
+ *     overlapped recompute on small meshes uses a stream of its own, joined to that stream before
+ *     the call returns).  Calls that return host values synchronise that stream; the others are
+ *     asynchronous.
+ *   - Environment (diagnostics and tests): FVLBM_SWEEP = ring | tiled | tiled-grads | split forces
+ *     a sweep variant (ring: only where it fits); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
+ *     of segment buffers (no kept second tape, no overlap).  Both are read when a state is created
+ *     or a run recorded.
  *   - Distribution functions are indexed by the D2Q9 direction a = 0..8 with lattice
  *     velocities e_a = (0,0),(1,0),(0,1),(-1,0),(0,-1),(1,1),(-1,1),(-1,-1),(1,-1) and
  *     weights 4/9, 1/9 (a=1..4), 1/36 (a=5..8); c_s^2 = 1/3.  Arrays of f are [9][n_cells].
