@@ -522,7 +522,7 @@ __global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__
 // Interior edges are summed in straight-line code (an edge without an interior neighbour reads
 // row 0 with weight 0), open-boundary edges after them.
 template <typename T, int S, bool ACC, int EPI>
-__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
+__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
                  int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, const T *__restrict__ f,
                  const T *__restrict__ tau1, T a_dt, double *__restrict__ dth, T rho0, AdjBufs<T> ab,
@@ -937,7 +937,7 @@ __global__ void __launch_bounds__(256) k_adj_sst_grad(Geo<T> g, SstAdj sa, const
 // adjoints), Lg [Wg][8] (gradient adjoints), Mi [Wg][3] (triangle meshes: inverse LSQ matrices,
 // from which the neighbours' LSQ coefficients pointing back are formed; other meshes gather them).
 template <typename T, int S>
-__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
+__global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     k_adj_sst_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
                    int Wg, SstAdj sa, const T *__restrict__ M, const T *__restrict__ K, const T *__restrict__ W,
                    const T *__restrict__ aux, const T *__restrict__ lk1, const T *__restrict__ lw1,
