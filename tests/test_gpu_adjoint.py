@@ -330,3 +330,63 @@ def test_adjoint_single_segment_set_equals_overlapped(F, monkeypatch):
         np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
     for a, b in zip(out["two"], out["whole"]):
         np.testing.assert_array_equal(np.asarray(a), np.asarray(b))
+
+
+def test_c4_derivatives_on_an_800_cell_piece_of_the_step(F):
+    """The adjoint check on a seeded 800-cell submesh of the step the benchmark times (122,956 cells):
+    the cells within R edge rings of the wall cell nearest (h, 0.01 h) behind the step, R the least
+    giving at least 800 (cut edges become outlet edges), the step's flow parameters, a reversed
+    near-wall stream (so J_R counts reversed wall shear).  theta turns only inlet and far-field
+    velocities, which the piece lacks: its derivative is zero on both sides.  d(F_x, F_y,
+    J_R)/d(theta, sigma_k1, sigma_w1, beta*, a1) over 4 steps (a checkpoint every 2) against the
+    oracle's complex step on the same piece: FP64 to 1e-8, FP32-deviation to the gates of
+    test_autograd_function_and_fp32."""
+    import bench
+    from tests import submesh as sm
+    mesh, flow, init, dt_frac = bench.workload("backstep")
+    xc = sm.centroids(mesh)
+    seed_cell = int(np.argmin((xc[:, 0] - 1.0) ** 2 + (xc[:, 1] - 0.01) ** 2))
+    R = 1
+    while sm.rings(mesh, [seed_cell], R).sum() < 800:
+        R += 1
+    piece, cells = sm.cut(mesh, sm.rings(mesh, [seed_cell], R))
+    n = len(cells)
+    say("C4 check on the piece of", n, "cells within", R, "rings")
+    assert 800 <= n < 1200 and (np.asarray(piece["bface_group"]) == 0).sum() > 10   # wall edges
+    extra = dict(group_u=list(flow["group_u"]) + [[0, 0]], group_rho=list(flow["group_rho"]) + [1],
+                 group_k=list(flow["group_k"]) + [1e-6], group_w=list(flow["group_w"]) + [1e-2])
+    M = F.Mesh(piece)
+    p = O.default_params(**dict(flow, **extra, dt=min(flow["dt"], dt_frac * M.max_dt()), theta=0.03,
+                                jr_group=0, jr_xmin=0.0, eps_tau=1e-4))
+    orc = O.Oracle(piece, p)
+    rng = np.random.default_rng(95)
+    x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+    ux = 0.03 * np.tanh(4 * (y - 0.5)) + 0.002 * rng.standard_normal(n)
+    uy = 0.003 * np.sin(3 * x) + 0.002 * rng.standard_normal(n)
+    f0 = O.feq(1 + 0.001 * rng.standard_normal(n), ux, uy) + 1e-5 * O.WT[:, None] * rng.standard_normal((9, n))
+    k0, w0 = 1e-6 * (1 + 0.5 * rng.random(n)), 1e-2 * (1 + 0.5 * rng.random(n))
+    N = 4
+    seed = np.array([0.7, -1.3, 2.0])
+    ref = []
+    for key in PARAMS:
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        o = O.Oracle(piece, pc)
+        fN, _, _ = o.run(f0.astype(complex), k0.astype(complex), w0.astype(complex), N)
+        Fv, JR = o.forces(fN, 1)
+        ref.append(np.imag(seed[0] * Fv[0] + seed[1] * Fv[1] + seed[2] * JR) / H)
+    ref = np.array(ref)
+    assert ref[0] == 0.0 and np.all(ref[1:] != 0.0), ref
+    rho0, ux0, uy0, _ = orc.macro(f0)
+    neq_rms = np.sqrt(np.mean((f0 - O.feq(rho0, ux0, uy0)) ** 2))
+    res32 = 2.0 ** -24 * np.abs(f0 - O.WT[:, None] * p["rho0"]).max() / neq_rms
+    tol32 = np.array([1e-3] + [max(1e-3, 10 * res32)] * (len(PARAMS) - 1))
+    scale = np.abs(ref).max()
+    for precision, tol in (("fp64", 1e-8), ("fp32dev", tol32)):
+        st = F.State(M, p, precision=precision, k=k0, omega=w0)
+        st.set_state(f0, k0, w0)
+        st.record(N, ckpt_every=2)
+        g = np.asarray(st.adjoint(1, seed))
+        print(precision, "gradient", g, "reference", ref)
+        assert np.all(np.abs(g - ref) <= tol * np.maximum(np.abs(ref), 1e-6 * scale)), (precision, g, ref)
+        del st
