@@ -124,9 +124,10 @@ def _f64(a, shape=None):
 
 
 class Mesh:
-    """Mesh preprocessed by the library (host, FP64)."""
+    """Mesh preprocessed by the library (host, FP64); order: "tiles" (graph-grown tiles, the
+    default), "morton", "rcm" or "none" (the fvlbm_mesh_create renumbering)."""
 
-    def __init__(self, m, order="morton"):
+    def __init__(self, m, order="tiles"):
         L = lib()
         self._keep = dict(
             nodes=_f64(m["nodes"]),

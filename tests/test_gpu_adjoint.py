@@ -274,7 +274,7 @@ def test_wide_halo_ring_adjoint_fp32(F):
     uy = 0.006 * np.sin(2 * x) + 0.004 * rng.standard_normal(n)
     f0 = O.feq(1 + 0.002 * rng.standard_normal(n), ux, uy) + 2e-5 * O.WT[:, None] * rng.standard_normal((9, n))
     k0, w0 = 2e-4 * (1 + 0.5 * rng.random(n)), 0.4 * (1 + 0.5 * rng.random(n))
-    M = F.Mesh(m)
+    M = F.Mesh(m, order="morton")     # Morton tiles: the ring-2 cells beyond one per thread
     probe = F.State(M, p, precision="fp32dev", k=k0, omega=w0)
     probe.timing(True)
     probe.step(1)

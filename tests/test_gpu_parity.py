@@ -521,7 +521,7 @@ def test_wide_halo_ring_step_parity(F):
     orc, p, f, k, w = _sst_case(m, extra, 56)
     f1, k1, w1 = orc.step(f, k, w)
     nut1 = orc.last_nut
-    M = F.Mesh(m)
+    M = F.Mesh(m, order="morton")     # Morton tiles: the ring-2 cells beyond one per thread
     for precision in ("fp64", "fp32dev"):
         say("wide-halo backstep", precision)
         st = F.State(M, p, precision=precision, k=k, omega=w)

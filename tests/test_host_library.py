@@ -115,12 +115,12 @@ def test_invalid_arguments():
 
 
 def test_wide_halo_backstep_tiles():
-    """The mesh of the wide-halo GPU tests: its 256-cell Morton tiles (the library's renumbering)
+    """The mesh of the wide-halo GPU tests: its 256-cell Morton tiles (the order those tests use)
     have at most 256 ring-1 cells (one thread each) but more than 256 cells in ring 1 + ring 2,
     so the ring kernels must loop over the ring-2 cells beyond one per thread."""
     import scipy.sparse as sp
     m = mg.backstep(core=0.3, dx_core=0.6, dx_corner=0.02, y1=1e-3)
-    M = F.Mesh(m)
+    M = F.Mesh(m, order="morton")
     perm = M.permutation()
     n = len(perm)
     inv = np.empty(n, np.int64)
