@@ -285,6 +285,8 @@ def backstep_run(F, stream, warmup, steps=2000, adj_steps=400, ckpt=20):
     for prec in ("fp32dev", "fp64"):
         st, p = make_state(F, M, flow, init, prec, dt_frac)
         ms, _, kt = time_steps(F, st, steps, warmup, stream, kernel_timing=False)
+        if not np.all(np.isfinite(st.moments()["totals"])):
+            raise SystemExit(f"backstep {prec}: non-finite state after the timed steps")
         del st
         sta, _ = make_state(F, M, flow, init, prec, dt_frac)
         sta.step(warmup)
@@ -331,6 +333,8 @@ def airfoil_run(F, steps):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         cl, cd = st.lift_drag(1, U, c)
+        if not (np.isfinite(cl) and np.isfinite(cd) and np.all(np.isfinite(st.moments()["totals"]))):
+            raise SystemExit(f"airfoil {prec}: non-finite state after {steps} steps")
         out[prec] = {"cl": cl, "cd": cd, "mlups": round(n * steps / dt / 1e6, 1)}
         del st
     out["rel_diff_cl"] = abs(out["fp32dev"]["cl"] - out["fp64"]["cl"]) / abs(out["fp64"]["cl"])
