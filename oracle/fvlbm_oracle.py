@@ -709,3 +709,18 @@ class Oracle:
         jsel = wall & (grp == jr_group) & (G.xf[bh, 0] > jr_xmin)
         JR = np.sum(np.where(jsel, l * 0.5 * (1.0 - np.tanh(tx / eps)), 0.0))
         return F, JR
+
+    # ---------------------------------------------------------------------------------------
+    # Lift and drag coefficients of the airfoil test (Section 4, the NACA0012 lift/drag table):
+    # the wall force resolved along the free-stream direction (cos theta, sin theta) for the drag
+    # and along (-sin theta, cos theta) for the lift, each divided by the dynamic pressure times
+    # the chord, rho0 u_ref^2 chord / 2.  theta is the inflow angle (reading r20), i.e. the angle
+    # of attack of a body whose chord lies along x.
+    # ---------------------------------------------------------------------------------------
+    def lift_drag(self, f, group_mask, u_ref, chord=1.0):
+        F, _ = self.forces(f, group_mask)
+        th = self.p["theta"]
+        drag_dir = np.array([np.cos(th), np.sin(th)])
+        lift_dir = np.array([-np.sin(th), np.cos(th)])
+        q = 0.5 * self.p["rho0"] * u_ref * u_ref * chord
+        return np.array([F @ lift_dir, F @ drag_dir]) / q

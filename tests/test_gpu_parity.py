@@ -316,6 +316,58 @@ def test_forces_parity(F):
     assert abs(JRg - JRo) < 1e-12 * max(1.0, abs(JRo))
 
 
+def _airfoil_stream_case(alpha):
+    """The small O-mesh around the 12 % section in a developed stream at incidence alpha (SST on,
+    limiter on, dt half the advective Courant limit)."""
+    m = mg.naca_omesh(n_wall=64, n_normal=24, y1=2e-3, radius=5.0)
+    U = 0.05
+    p = O.default_params(nu=U / 2e3, dt=courant_dt(m), sst=True, theta=alpha, limiter=1,
+                         group_u=[[0, 0], [U, 0]], group_k=[0, 1e-3 * U * U / 2e3], group_w=[0, 5 * U])
+    orc = O.Oracle(m, p)
+    G = orc.g
+    fac = np.minimum(1.0, (G.wall_dist / 0.01) ** (1 / 7))
+    f, k, w = orc.init_state(np.ones(G.n), U * np.cos(alpha) * fac, U * np.sin(alpha) * fac,
+                             np.full(G.n, p["group_k"][1]), np.full(G.n, 5 * U))
+    return m, p, orc, f, k, w, U
+
+
+def test_lift_drag_parity(F):
+    """fvlbm_lift_drag against the oracle's lift_drag (Section 4, the NACA0012 lift/drag table).
+    (i) the pressure closed form at rest: C_l = cos(alpha) K, C_d = sin(alpha) K, K = 2 delta / (3 U^2);
+    (ii) after 3 steps of a developed stream at 10 degrees: FP64 within 1e-11 of the oracle, FP32-dev
+    within 1e-3 relative (the stated FP32-dev gate for lift and drag);
+    (iii) at zero incidence on the mirror-symmetric mesh: |C_l| <= 1e-11 C_d after 3 steps."""
+    alpha = np.deg2rad(10.0)
+    m, p, orc, f, k, w, U = _airfoil_stream_case(alpha)
+    n = orc.g.n
+    say("lift/drag pressure closed form, naca 64x24")
+    delta = 0.01
+    fr = O.feq(np.where(orc.g.xc[:, 1] < 0, 1 + delta, 1.0), np.zeros(n), np.zeros(n))
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k, omega=w)
+    st.set_state(fr, k, w)
+    K = 2 * delta / (3 * U * U)
+    np.testing.assert_allclose(st.lift_drag(1, U), [np.cos(alpha) * K, np.sin(alpha) * K], rtol=1e-12)
+    say("lift/drag after 3 steps at 10 degrees, fp64 and fp32dev")
+    fo, ko, wo = orc.run(f, k, w, 3)
+    ref = orc.lift_drag(fo, 1, U)
+    for prec, tol in (("fp64", 1e-11), ("fp32dev", 1e-3)):
+        st = F.State(F.Mesh(m), p, precision=prec, k=k, omega=w)
+        st.set_state(f, k, w)
+        st.step(3)
+        got = np.array(st.lift_drag(1, U))
+        err = np.abs(got - ref) / np.abs(ref)
+        print(prec, "C_l, C_d", got, "oracle", ref, "relative error", err)
+        assert (err < tol).all(), (prec, got, ref)
+    say("lift/drag at zero incidence, symmetric mesh")
+    m0, p0, orc0, f0, k0, w0, _ = _airfoil_stream_case(0.0)
+    st = F.State(F.Mesh(m0), p0, precision="fp64", k=k0, omega=w0)
+    st.set_state(f0, k0, w0)
+    st.step(3)
+    cl, cd = st.lift_drag(1, U)
+    print("zero incidence: C_l", cl, "C_d", cd)
+    assert cd > 0 and abs(cl) <= 1e-11 * cd
+
+
 # ------------------------------------------------------------------------------------------------
 # Optional face-value limiter (params["limiter"] = 1): same parity gates as the plain scheme.
 # ------------------------------------------------------------------------------------------------

@@ -331,6 +331,75 @@ def test_forces_exact_for_linear_shear():
     assert abs(JR2 - 0.75) < 1e-12         # reversed everywhere: the whole wall length
 
 
+# ------------------------------------------------------------------------------------------
+# Lift and drag coefficients (Section 4, the NACA0012 lift/drag table): drag along the inflow
+# direction, lift normal to it, over rho0 u_ref^2 chord / 2.
+# ------------------------------------------------------------------------------------------
+def _small_airfoil():
+    return mg.naca_omesh(n_wall=64, n_normal=24, y1=2e-3, radius=5.0)
+
+
+def test_lift_drag_pressure_closed_form():
+    """At rest with the density raised by delta below the chord line, only the pressure term acts.
+    The lower surface's edges telescope from the trailing edge (1, 0) to the leading edge (0, 0), so
+    the force is exactly (0, delta / 3 * chord): C_l = cos(alpha) K and C_d = sin(alpha) K with
+    K = 2 delta / (3 u_ref^2).  A uniform raise of the density gives no force (closed contour)."""
+    m = _small_airfoil()
+    U, delta, alpha = 0.05, 0.01, np.deg2rad(10.0)
+    orc = O.Oracle(m, O.default_params(nu=1e-4, dt=1e-2, theta=alpha))
+    n = orc.g.n
+    y = orc.g.xc[:, 1]
+    f = O.feq(np.where(y < 0, 1 + delta, 1.0), np.zeros(n), np.zeros(n))
+    K = 2 * delta / (3 * U * U)
+    np.testing.assert_allclose(orc.lift_drag(f, 1, U), [np.cos(alpha) * K, np.sin(alpha) * K], rtol=1e-12)
+    F, _ = orc.forces(O.feq(np.full(n, 1 + delta), np.zeros(n), np.zeros(n)), 1)
+    assert np.abs(F).max() < 1e-15
+
+
+def test_lift_drag_symmetric_airfoil_at_zero_incidence():
+    """A symmetric section on a mirror-symmetric mesh in a stream along its chord: the lift
+    vanishes to roundoff, after some steps of the scheme as well (the D2Q9 lattice and the boundary
+    treatment are mirror-symmetric), while the drag does not."""
+    m = _small_airfoil()
+    U = 0.05
+    p = O.default_params(nu=U / 2e3, dt=0.5, sst=True, theta=0.0, limiter=1,
+                         group_u=[[0, 0], [U, 0]], group_k=[0, 1e-3 * U * U / 2e3], group_w=[0, 5 * U])
+    orc = O.Oracle(m, p)
+    G = orc.g
+    n = G.n
+    en = np.maximum(O.EX[:, None] * G.nl[:, 0] + O.EY[:, None] * G.nl[:, 1], 0.0)
+    out = np.stack([np.bincount(G.cell, weights=en[a], minlength=n) for a in range(9)])
+    orc.p["dt"] = 0.5 / (out / G.area).max()
+    ux = U * np.minimum(1.0, (G.wall_dist / 0.01) ** (1 / 7))
+    f, k, w = orc.init_state(np.ones(n), ux, np.zeros(n), np.full(n, p["group_k"][1]), np.full(n, 5 * U))
+    cl0, cd0 = orc.lift_drag(f, 1, U)
+    f, k, w = orc.run(f, k, w, 3)
+    cl, cd = orc.lift_drag(f, 1, U)
+    assert cd0 > 0 and cd > 0
+    assert abs(cl0) < 1e-13 * cd0 and abs(cl) < 1e-11 * cd, (cl0, cd0, cl, cd)
+
+
+def test_lift_drag_rotation_invariance():
+    """Turning the mesh, the flow and the inflow angle together by the same angle leaves both
+    coefficients unchanged (they are defined relative to the inflow), for a state with pressure and
+    shear on every wall edge."""
+    m = _small_airfoil()
+    U, alpha, beta = 0.05, np.deg2rad(7.0), np.deg2rad(33.0)
+    rng = np.random.default_rng(41)
+    orc = O.Oracle(m, O.default_params(nu=1e-3, dt=1e-2, theta=alpha))
+    n = orc.g.n
+    rho = 1 + 0.01 * rng.standard_normal(n)
+    ux, uy = U * np.cos(alpha) + 0.01 * rng.standard_normal(n), U * np.sin(alpha) + 0.01 * rng.standard_normal(n)
+    c0 = orc.lift_drag(O.feq(rho, ux, uy), 1, U)
+    R = np.array([[np.cos(beta), -np.sin(beta)], [np.sin(beta), np.cos(beta)]])
+    m2 = dict(m, nodes=m["nodes"] @ R.T)
+    orc2 = O.Oracle(m2, O.default_params(nu=1e-3, dt=1e-2, theta=alpha + beta))
+    vx, vy = R[0, 0] * ux + R[0, 1] * uy, R[1, 0] * ux + R[1, 1] * uy
+    c1 = orc2.lift_drag(O.feq(rho, vx, vy), 1, U)
+    assert np.abs(c0).min() > 1e-3
+    np.testing.assert_allclose(c1, c0, rtol=1e-10)
+
+
 def test_taylor_green_decay_second_order():
     """Taylor-Green vortex on doubly periodic jittered triangles: the velocity amplitude decays
     as exp(-2 nu k^2 t).  The measured viscosity error must fall at about second order."""
@@ -390,6 +459,136 @@ def test_sst_homogeneous_decay():
         np.testing.assert_allclose(nut, k1 / w1, rtol=1e-13)
         np.testing.assert_allclose(tau, 3 * (nu + k1 / w1), rtol=1e-13)
         k, w = k1, w1
+
+
+# ------------------------------------------------------------------------------------------
+# The inner (set-1) constants of the SST blend.  Every pin above runs where F1 = 0 (no wall
+# nearby), which leaves sigma_k1, sigma_w1, beta1 and C_w1 unchecked.  Passing wall segments a
+# hair's breadth from every centroid drives d -> 0, so arg1 -> infinity and F1 = F2 = 1 exactly:
+# the blend then selects set 1 alone (Section 2, the constant list; readings r6-r8).
+# ------------------------------------------------------------------------------------------
+def _near_wall_segments(G, eps=1e-8):
+    """One short wall segment at distance eps beside every cell centroid."""
+    c = G.xc
+    p = c + np.array([eps, -eps])
+    q = c + np.array([eps, eps])
+    return np.stack([p, q], axis=1)
+
+
+C_W1 = 0.075 / 0.09 - 0.5 * 0.41 ** 2 / np.sqrt(0.09)      # Section 2: C_w1 = beta1/beta* - sigma_w1 kappa^2/sqrt(beta*)
+
+
+def test_sst_set1_homogeneous_decay():
+    """F1 = 1, no flow gradients: k1 = k / (1 + dt beta* w), w1 = w / (1 + dt beta1 w) exactly, with
+    beta1 = 0.075 (set 1), and nu_t = k1 / w1."""
+    mesh = mg.rectangle(5, 6, kind="periodic", jitter=0.2, seed=22)
+    G0 = O.Geometry(mesh)
+    nu, dt = 1e-4, 0.3
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True), wall_segments=_near_wall_segments(G0))
+    n = orc.g.n
+    assert orc.g.wall_dist.max() < 2e-8
+    rho, ux, uy = np.full(n, 1.0), np.full(n, 0.03), np.full(n, 0.01)
+    k, w = np.full(n, 2e-4), np.full(n, 0.5)
+    for _ in range(5):
+        k1, w1, nut, tau = orc.sst_update(rho, ux, uy, k, w)
+        assert (orc.last_sst["F1"] == 1.0).all() and (orc.last_sst["F2"] == 1.0).all()
+        np.testing.assert_allclose(k1, k / (1 + dt * 0.09 * w), rtol=1e-13)
+        np.testing.assert_allclose(w1, w / (1 + dt * 0.075 * w), rtol=1e-13)
+        np.testing.assert_allclose(nut, k1 / w1, rtol=1e-13)
+        k, w = k1, w1
+
+
+def test_sst_set1_manufactured_diffusion():
+    """F1 = 1, no flow, quadratic k and w = c k on uniform quads (the two-point face gradient is
+    exact there, reading r30): interior cells obey
+        k1 = (k + dt (nu + sigma_k1 / c) lap k) / (1 + dt beta* w)
+        w1 = (w + dt (nu + sigma_w1 / c) c lap k) / (1 + dt beta1 w)
+    with sigma_k1 = 0.85, sigma_w1 = 0.5, beta1 = 0.075, and no cross-diffusion term (its weight
+    is 1 - F1 = 0)."""
+    mesh = mg.rectangle(10, 10, kind="open", split="none")
+    G0 = O.Geometry(mesh)
+    nu, dt = 1e-3, 0.01
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True, group_u=[[0.0, 0.0]],
+                                          group_k=[1e-3], group_w=[1.0]),
+                   wall_segments=_near_wall_segments(G0))
+    G = orc.g
+    x, y = G.xc[:, 0], G.xc[:, 1]
+    a = 2e-3
+    k = 1e-3 + a * ((x - 0.4) ** 2 + (y - 0.6) ** 2)
+    cc = 300.0
+    w = cc * k
+    n = G.n
+    k1, w1, _, _ = orc.sst_update(np.ones(n), np.zeros(n), np.zeros(n), k, w)
+    cells = _two_ring_interior(G)
+    assert (orc.last_sst["F1"][cells] == 1.0).all()
+    lap = 4 * a
+    ek = (k + dt * (nu + 0.85 / cc) * lap) / (1 + dt * 0.09 * w)
+    ew = (w + dt * (nu + 0.5 / cc) * cc * lap) / (1 + dt * 0.075 * w)
+    np.testing.assert_allclose(k1[cells], ek[cells], rtol=1e-11)
+    np.testing.assert_allclose(w1[cells], ew[cells], rtol=1e-11)
+
+
+@pytest.mark.parametrize("shear", [0.2, 2.0])
+def test_sst_set1_production(shear):
+    """F1 = F2 = 1, uniform k and w, the shear flow u = (u0 + a y, v0) on uniform quads (S = |a|,
+    div u = 0, no net convection or diffusion of uniform k, w):
+        mu_t = a1 rho k / max(a1 w, S)                        (Section 2, the eddy viscosity)
+        k1 = (k + dt mu_t S^2 / rho) / (1 + dt beta* w)
+        w1 = (w + dt C_w1 S^2) / (1 + dt beta1 w)
+    with C_w1 from the constant list.  a = 0.2 < a1 w keeps mu_t = rho k / w; a = 2 > a1 w takes
+    the strain branch of the limiter."""
+    mesh = mg.rectangle(10, 10, kind="open", split="none")
+    G0 = O.Geometry(mesh)
+    nu, dt = 1e-5, 0.05
+    U0 = (0.02, -0.01)
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True, group_u=[[U0[0], U0[1]]],
+                                          group_k=[1e-4], group_w=[2.0]),
+                   wall_segments=_near_wall_segments(G0))
+    G = orc.g
+    y = G.xc[:, 1]
+    n = G.n
+    k, w = np.full(n, 1e-4), np.full(n, 2.0)
+    k1, w1, nut, _ = orc.sst_update(np.ones(n), U0[0] + shear * y, np.full(n, U0[1]), k, w)
+    cells = _two_ring_interior(G)
+    assert (orc.last_sst["F1"][cells] == 1.0).all()
+    S2 = shear ** 2
+    mut = 0.31 * k[0] / max(0.31 * w[0], shear)
+    ek = (k[0] + dt * mut * S2) / (1 + dt * 0.09 * w[0])
+    ew = (w[0] + dt * C_W1 * S2) / (1 + dt * 0.075 * w[0])
+    np.testing.assert_allclose(k1[cells], ek, rtol=1e-12)
+    np.testing.assert_allclose(w1[cells], ew, rtol=1e-12)
+    np.testing.assert_allclose(nut[cells], 0.31 * k1[cells] / np.maximum(0.31 * w1[cells], shear), rtol=1e-12)
+
+
+def test_sst_wall_omega_value():
+    """The wall value of omega (Menter 1994, the SST model the paper cites in Section 2):
+    w_wall = 60 nu / (beta1 d1^2), d1 the distance from the wall cell's centroid to the wall
+    edge.  No flow, uniform w0 and a negligible k (mu_t / mu ~ 1e-13) between two resting walls on
+    uniform quads, periodic in x.  500 nu / (w d^2) > 5 on every cell puts F1 = 1 (set 1), so the
+    only flux of a wall cell is the diffusion through its wall edge and exactly
+        w1 = (w0 + dt nu l (w_wall - w0) / (A d1)) / (1 + dt beta1 w0)
+        k1 = (k0 - dt nu l k0 / (A d1)) / (1 + dt beta* w0)          (k_wall = 0)
+    while cells away from the walls keep w1 = w0 / (1 + dt beta1 w0)."""
+    nx, ny = 6, 10
+    mesh = mg.rectangle(nx, ny, kind="couette", split="none")
+    nu, dt = 1e-3, 0.05
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True, group_u=[[0, 0], [0, 0], [0, 0], [0, 0]]))
+    G = orc.g
+    n = G.n
+    w0, k0 = 0.5, 1e-16
+    k1, w1, _, _ = orc.sst_update(np.ones(n), np.zeros(n), np.zeros(n), np.full(n, k0), np.full(n, w0))
+    assert (orc.last_sst["F1"] == 1.0).all()
+    h = 1.0 / ny
+    A, l, d1 = h * (1.0 / nx), 1.0 / nx, h / 2
+    w_wall = 60 * nu / (0.075 * d1 ** 2)
+    y = G.xc[:, 1]
+    wall_cells = (y < h) | (y > 1 - h)
+    ew = (w0 + dt * nu * l * (w_wall - w0) / (A * d1)) / (1 + dt * 0.075 * w0)
+    ek = (k0 - dt * nu * l * k0 / (A * d1)) / (1 + dt * 0.09 * w0)
+    np.testing.assert_allclose(w1[wall_cells], ew, rtol=1e-12)
+    np.testing.assert_allclose(k1[wall_cells], ek, rtol=1e-12)
+    far = (y > 2 * h) & (y < 1 - 2 * h)
+    np.testing.assert_allclose(w1[far], w0 / (1 + dt * 0.075 * w0), rtol=1e-13)
 
 
 def _mp_sst_point(rho, nu, d, gu, gk, gw, k, w, c):
