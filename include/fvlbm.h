@@ -176,7 +176,10 @@ fvlbm_status fvlbm_set_state(fvlbm_state *st, const double *f, const double *k, 
 /*
  * Advance n_steps IMEX steps (Steps 1-7 each).  If residual != NULL, the velocity residual
  * ||u^{n+1} - u^n||_2 / ||u^{n+1}||_2 of the last step is computed in FP64 and returned (this
- * synchronises); a non-finite residual returns FVLBM_EDIVERGED.
+ * synchronises; for a flow at rest, ||u^{n+1}|| = 0, the absolute norm ||u^{n+1} - u^n||_2); a
+ * non-finite residual returns FVLBM_EDIVERGED.  Without a residual nothing is checked: a NaN or an
+ * overflow surfaces at the next call that reduces (a residual, fvlbm_moments' totals,
+ * fvlbm_forces), which returns FVLBM_EDIVERGED.
  */
 fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *residual);
 
@@ -291,7 +294,10 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   with all work on the caller's stream.  The reverse: the combination and stage collisions in closed
  *   form, the convection term by its transpose, the SST update, fluxes, closure and LSQ gradients
  *   by their transposes.  The state is restored to the
- *   final recorded state afterwards.  Errors: FVLBM_ESTATE without a recording, FVLBM_EDIVERGED.
+ *   final recorded state afterwards.  A call that changes the state after fvlbm_record
+ *   (fvlbm_step, fvlbm_step_explicit, fvlbm_run_to_residual, fvlbm_set_state) drops the recording:
+ *   the tape would no longer end at the current state.  Errors: FVLBM_ESTATE without a recording
+ *   (never recorded, or dropped), FVLBM_EDIVERGED.
  * fvlbm_adjoint_state: the same reverse run seeded with the adjoint of the final state (host [9][n],
  *   [n], [n] FP64 user order; lam_k / lam_w may be NULL), returning the adjoint of the recorded
  *   initial state and dparams (for dot-product checks).

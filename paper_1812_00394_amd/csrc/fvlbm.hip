@@ -581,7 +581,8 @@ double residual(fvlbm_state *st) {
     double r[2];
     check(hipMemcpyAsync(r, st->result, sizeof(r), hipMemcpyDeviceToHost, st->stream), "hipMemcpyAsync D2H");
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
-    return std::sqrt(r[0] / r[1]);
+    // relative L2 change of the velocity; a flow at rest (zero denominator) gives the absolute norm
+    return r[1] > 0 ? std::sqrt(r[0] / r[1]) : std::sqrt(r[0]);
 }
 
 template <typename T>
@@ -1207,6 +1208,14 @@ void adjoint_state(fvlbm_state *st, const double *lf, const double *lk, const do
     reduce_pbar<T>(st, L, dparams);
 }
 
+// A state-changing call (step, set_state) after fvlbm_record: the tape no longer ends at the current
+// state, so the recording is dropped and a later adjoint call returns FVLBM_ESTATE.
+void drop_recording(fvlbm_state *st) {
+    st->adj_ws = nullptr;
+    st->adj_bytes = 0;
+    st->held_segs = 0;
+}
+
 template <typename F>
 fvlbm_status guarded(F &&fn) {
     try {
@@ -1327,6 +1336,7 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
 fvlbm_status fvlbm_set_state(fvlbm_state *st, const double *f, const double *k, const double *omega) {
     return guarded([&] {
         if (!st) throw Error(FVLBM_EINVAL, "set_state: NULL state");
+        drop_recording(st);
         if ((k || omega) && !st->sst) throw Error(FVLBM_ESTATE, "set_state: k / omega given to a laminar state");
         if (st->precision == FVLBM_FP64)
             import_state<double>(st, f, k, omega);
@@ -1339,6 +1349,7 @@ fvlbm_status fvlbm_step(fvlbm_state *st, int32_t n_steps, double *res) {
     return guarded([&] {
         if (!st) throw Error(FVLBM_EINVAL, "step: NULL state");
         if (n_steps < 0) throw Error(FVLBM_EINVAL, "step: n_steps < 0");
+        drop_recording(st);
         for (int32_t i = 0; i < n_steps; ++i) {
             if (st->precision == FVLBM_FP64)
                 launch_step<double>(st);
@@ -1361,6 +1372,7 @@ fvlbm_status fvlbm_run_to_residual(fvlbm_state *st, int64_t max_steps, int32_t c
         if (!st) throw Error(FVLBM_EINVAL, "run_to_residual: NULL state");
         if (max_steps < 1 || check_every < 1 || !(tol >= 0))
             throw Error(FVLBM_EINVAL, "run_to_residual: needs max_steps >= 1, check_every >= 1, tol >= 0");
+        drop_recording(st);
         int64_t done = 0;
         double r = 0;
         if (steps_out) *steps_out = 0;
@@ -1388,6 +1400,7 @@ fvlbm_status fvlbm_step_explicit(fvlbm_state *st, int32_t n_steps, double *res) 
     return guarded([&] {
         if (!st) throw Error(FVLBM_EINVAL, "step_explicit: NULL state");
         if (n_steps < 0) throw Error(FVLBM_EINVAL, "step_explicit: n_steps < 0");
+        drop_recording(st);
         for (int32_t i = 0; i < n_steps; ++i) {
             if (st->precision == FVLBM_FP64)
                 launch_explicit<double>(st);
@@ -1592,7 +1605,7 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
 fvlbm_status fvlbm_adjoint_step(fvlbm_state *st, uint64_t wall_group_mask, const double seed[3], double dparams[5]) {
     return guarded([&] {
         if (!st || !seed || !dparams) throw Error(FVLBM_EINVAL, "adjoint_step: NULL argument");
-        if (!st->adj_ws) throw Error(FVLBM_ESTATE, "adjoint_step: no recorded run (call fvlbm_record first)");
+        if (!st->adj_ws) throw Error(FVLBM_ESTATE, "adjoint_step: no recorded run (call fvlbm_record first; a step or set_state since then drops it)");
         if (st->precision == FVLBM_FP64)
             adjoint_forces<double>(st, wall_group_mask, seed, dparams);
         else
@@ -1606,7 +1619,7 @@ fvlbm_status fvlbm_adjoint_state(fvlbm_state *st, const double *lam_f, const dou
                                  double *lam_f0, double *lam_k0, double *lam_w0, double dparams[5]) {
     return guarded([&] {
         if (!st || !lam_f || !lam_f0 || !dparams) throw Error(FVLBM_EINVAL, "adjoint_state: NULL argument");
-        if (!st->adj_ws) throw Error(FVLBM_ESTATE, "adjoint_state: no recorded run (call fvlbm_record first)");
+        if (!st->adj_ws) throw Error(FVLBM_ESTATE, "adjoint_state: no recorded run (call fvlbm_record first; a step or set_state since then drops it)");
         if (st->precision == FVLBM_FP64)
             adjoint_state<double>(st, lam_f, lam_k, lam_w, lam_f0, lam_k0, lam_w0, dparams);
         else
