@@ -39,10 +39,27 @@ def log(*a):
 # ----------------------------------------------------------------------------------------------
 # Workloads
 # ----------------------------------------------------------------------------------------------
+def cached_mesh(key, make):
+    """The generated mesh, kept as an .npz under MESH_CACHE[0] (when set) for later runs."""
+    from paper_1812_00394_amd import meshgen as mg
+    if not MESH_CACHE[0]:
+        return make()
+    path = os.path.join(MESH_CACHE[0], key + ".npz")
+    if os.path.exists(path):
+        return mg.load(path)
+    mesh = make()
+    os.makedirs(MESH_CACHE[0], exist_ok=True)
+    mg.save(mesh, path)
+    return mesh
+
+
+MESH_CACHE = [None]
+
+
 def workload(name):
     from paper_1812_00394_amd import meshgen as mg
     if name == "delaunay4m":
-        mesh = mg.delaunay_rect(n_points=2_000_000, seed=5)
+        mesh = cached_mesh("delaunay4m_seed5", lambda: mg.delaunay_rect(n_points=2_000_000, seed=5))
         U, H, Re = 0.05, 1.0, 3.6e4
         flow = dict(nu=U * H / Re, sst=True, group_u=[[0, 0], [U, 0], [0, 0]], group_rho=[1, 1, 1],
                     group_k=[0, 1e-6, 0], group_w=[0, 1e-2, 0])
@@ -366,8 +383,11 @@ def main():
                     help="steps of the airfoil run (lift and drag in FP32-dev and FP64; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for rocprof byte counters)")
+    ap.add_argument("--mesh-cache", default=None,
+                    help="directory where the generated benchmark mesh is kept as .npz for later runs")
     args = ap.parse_args()
     ORDER[0] = args.order
+    MESH_CACHE[0] = args.mesh_cache
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of this "
               "path is a design note, not built", file=sys.stderr)
