@@ -65,6 +65,7 @@ def default_params(**kw):
     p = dict(nu=1e-3, dt=1e-2, rho0=1.0, sst=False, theta=0.0,
              group_u=None, group_rho=None, group_k=None, group_w=None, bface_vals=None,
              jr_group=-1, jr_xmin=0.0, eps_tau=1.0, limiter=0, sst_stages=0, sst_sweeps=0)
+    # limiter: 0 none, 1 the face-value clip of reading r32, 2 the gradient limiter of reading r35
     p.update(SST_DEFAULTS)
     p.update(kw)
     return p
@@ -358,6 +359,8 @@ class Oracle:
         ux, uy = jx / rho, jy / rho
         gb = self.ghost_f(g_arr, rho, ux, uy)
         grad = self.lsq_grad(g_arr, gb)                           # [9, 2, N]
+        if self.p.get("limiter", 0) == 2:
+            grad = self.limit_gradient(g_arr, gb, grad)
         c = G.cell
         en = EX[:, None] * G.nl[:, 0] + EY[:, None] * G.nl[:, 1]  # (e.n) dl, [9, H]
         rc = G.xf - G.xc[c]
@@ -368,7 +371,7 @@ class Oracle:
         rn = G.xf[inner] - G.xs[inner]                            # from the (shifted) neighbour centroid
         v_nbr = g_arr[:, nb] + grad[:, 0, nb] * rn[:, 0] + grad[:, 1, nb] * rn[:, 1]
         face[:, inner] = np.where(en[:, inner] >= 0, v_self[:, inner], v_nbr)
-        if self.p.get("limiter", 0):
+        if self.p.get("limiter", 0) == 1:
             # optional limiter (a reading; Part I's reconstruction is not in this paper): an
             # interior face value stays between the values of the two cells that share the edge
             a_, b_ = g_arr[:, c[inner]], g_arr[:, nb]
@@ -380,6 +383,46 @@ class Oracle:
         wall = (self.b_kind == WALL) | (self.b_kind == MOVING_WALL)
         face[:, bh] = np.where(wall | (en[:, bh] < 0), gb, v_self[:, bh])
         return en, face
+
+    # ---------------------------------------------------------------------------------------
+    # Reading r35 (limiter = 2), Barth and Jespersen's gradient limiter for the reconstruction of
+    # reading r2 (Part I's reconstruction is not in this paper): each cell's gradient of each
+    # direction is scaled by the largest psi in [0, 1] that keeps the reconstructed values at all
+    # of the cell's edge midpoints between the least and the greatest of the cell's value and its
+    # stencil values (the values the LSQ gradient is built from: interior neighbours and boundary
+    # ghosts).  psi = min over the edges of (bound - g_c) / (grad g_c . (x_f - x_c)), the bound being
+    # the greatest value for a positive increment and the least for a negative one, and 1 for a
+    # zero increment.
+    # ---------------------------------------------------------------------------------------
+    def limit_gradient(self, g_arr, gb, grad):
+        G = self.g
+        c = G.cell
+        H = len(c)
+        n = G.n
+        pj = np.zeros((9, H), dtype=np.result_type(g_arr, gb))
+        inner = np.nonzero(G.interior)[0]
+        pj[:, inner] = g_arr[:, G.nbr[inner]]
+        pj[:, G.bidx] = gb
+        # half-faces of a cell are consecutive: slot k of cell i is half-face start[i] + k
+        nv = np.bincount(c, minlength=n)
+        start = np.concatenate([[0], np.cumsum(nv)[:-1]])
+        hi, lo = g_arr.copy(), g_arr.copy()
+        for k in range(nv.max()):
+            cells = np.nonzero(nv > k)[0]
+            h = start[cells] + k
+            hi[:, cells] = rmax(hi[:, cells], pj[:, h])
+            lo[:, cells] = rmin(lo[:, cells], pj[:, h])
+        rc = G.xf - G.xc[c]
+        inc = grad[:, 0, c] * rc[:, 0] + grad[:, 1, c] * rc[:, 1]      # [9, H]
+        up = np.real(inc) > 0
+        down = np.real(inc) < 0
+        safe = np.where(up | down, inc, 1.0)
+        ratio = np.where(up, (hi[:, c] - g_arr[:, c]) / safe, np.where(down, (lo[:, c] - g_arr[:, c]) / safe, 1.0))
+        psi = np.ones_like(g_arr)
+        for k in range(nv.max()):
+            cells = np.nonzero(nv > k)[0]
+            psi[:, cells] = rmin(psi[:, cells], ratio[:, start[cells] + k])
+        return grad * psi[:, None, :]
 
     # ---------------------------------------------------------------------------------------
     # k-omega SST update (Section 2 equations; Section 3.2 coupling; readings r5-r13).

@@ -873,6 +873,111 @@ def test_limiter_removes_the_overshoot_next_to_a_step():
 # ------------------------------------------------------------------------------------------------
 # The explicit (forward Euler) scheme the IMEX scheme is compared with.
 # ------------------------------------------------------------------------------------------------
+# ------------------------------------------------------------------------------------------------
+# Reading r35 (limiter = 2): Barth and Jespersen's gradient limiter on the reconstruction of r2.
+# ------------------------------------------------------------------------------------------------
+def _stencil_bounds(orc, g):
+    """Least and greatest of each cell's value and its stencil values (neighbour values, boundary
+    ghost values), by a plain loop over the half-faces."""
+    G = orc.g
+    rho, jx, jy = O.moments(g)
+    gb = orc.ghost_f(g, rho, jx / rho, jy / rho)
+    lo, hi = g.copy(), g.copy()
+    bpos = {int(h): i for i, h in enumerate(G.bidx)}
+    for h in range(len(G.cell)):
+        c = G.cell[h]
+        v = g[:, G.nbr[h]] if G.interior[h] else gb[:, bpos[h]]
+        lo[:, c] = np.minimum(lo[:, c], v)
+        hi[:, c] = np.maximum(hi[:, c], v)
+    return lo, hi, gb
+
+
+def test_gradient_limiter_inactive_for_linear_field_on_orthogonal_mesh():
+    """On uniform quads the reconstructed midpoint value of a linear field is the mean of the two
+    cells' values, inside the bounds: the limiter leaves the gradient alone, and the convection term
+    keeps its linear exactness (-w_a e_a . grad) on cells two rings inside."""
+    mesh = mg.rectangle(10, 10, kind="open", split="none")
+    orc = O.Oracle(mesh, O.default_params(group_u=[[0.0, 0.0]], limiter=2))
+    G = orc.g
+    rng = np.random.default_rng(61)
+    a = 1.0 + 0.1 * rng.standard_normal(9)
+    b = 0.1 * rng.standard_normal((9, 2))
+    g = O.WT[:, None] * (a[:, None] + b[:, 0:1] * G.xc[:, 0] + b[:, 1:2] * G.xc[:, 1])
+    Ga = orc.advection(g)
+    cells = _two_ring_interior(G)
+    expect = -O.WT[:, None] * (O.EX[:, None] * b[:, 0:1] + O.EY[:, None] * b[:, 1:2])
+    np.testing.assert_allclose(Ga[:, cells], np.broadcast_to(expect, Ga[:, cells].shape), atol=1e-13)
+
+
+def test_gradient_limiter_bounds_and_is_the_largest_such_scale():
+    """A random field on jittered triangles: unlimited, some reconstructed edge-midpoint values leave
+    the bounds of their cell's stencil; limited, none does, and wherever the limiter acts (psi < 1)
+    some edge's value sits on a bound (psi is the largest admissible scale, not just an admissible
+    one).  The bounds here come from a plain loop over half-faces, ghost values included."""
+    mesh = mg.rectangle(9, 8, kind="duct", jitter=0.25, seed=62)
+    p = O.default_params(group_u=[[0.05, 0.01], [0, 0], [0.05, 0.0]], group_rho=[1.0, 1.002, 1.0], limiter=2)
+    orc = O.Oracle(mesh, p)
+    G = orc.g
+    rng = np.random.default_rng(63)
+    n = G.n
+    g = O.feq(1 + 0.01 * rng.standard_normal(n), 0.05 * rng.standard_normal(n), 0.05 * rng.standard_normal(n))
+    g = g + 1e-3 * O.WT[:, None] * rng.standard_normal((9, n))
+    lo, hi, gb = _stencil_bounds(orc, g)
+    grad = orc.lsq_grad(g, gb)
+    lim = orc.limit_gradient(g, gb, grad)
+    c = G.cell
+    rc = G.xf - G.xc[c]
+    tol = 1e-15
+    def recon(gr):
+        return g[:, c] + gr[:, 0, c] * rc[:, 0] + gr[:, 1, c] * rc[:, 1]
+    v0, v1 = recon(grad), recon(lim)
+    out0 = (v0 > hi[:, c] + tol) | (v0 < lo[:, c] - tol)
+    out1 = (v1 > hi[:, c] + tol) | (v1 < lo[:, c] - tol)
+    assert out0.sum() > 20 and out1.sum() == 0, (out0.sum(), out1.sum())
+    # psi per cell and direction, and the edges that sit on a bound
+    psi = np.ones((9, n))
+    gx = np.where(np.abs(grad[:, 0]) > 0, lim[:, 0] / np.where(grad[:, 0] == 0, 1, grad[:, 0]), 1.0)
+    psi = np.minimum(psi, gx)
+    on = (np.abs(v1 - hi[:, c]) <= 1e-14 * np.abs(hi[:, c])) | (np.abs(v1 - lo[:, c]) <= 1e-14 * np.abs(lo[:, c]))
+    touched = np.zeros((9, n), bool)
+    np.logical_or.at(touched, (slice(None), c), on)
+    acted = psi < 1 - 1e-12
+    assert acted.sum() > 20 and touched[acted].all(), (acted.sum(), touched[acted].sum())
+
+
+def test_gradient_limiter_keeps_the_sliver_step_bounded():
+    """The laminar step (Re_h 100, from rest) on the coarse step mesh, whose quad-to-triangle
+    transition has sliver triangles (height 0.03, width 0.4): unlimited, the linear reconstruction
+    there has a growing mode (the run leaves all bounds within 300 steps at dt = 0.8 of the Courant
+    limit, the time to blow up being the same in Courant time units at every dt tried, while first-
+    order upwind stays bounded); with the gradient limiter the same run stays bounded."""
+    m = mg.backstep(core=0.35, dx_core=0.7, y1=1.5e-2, dx_corner=0.08, wall_layers=2)
+    G = O.Geometry(m)
+    en = np.maximum(O.EX[:, None] * G.nl[:, 0] + O.EY[:, None] * G.nl[:, 1], 0.0)
+    out = np.stack([np.bincount(G.cell, weights=en[a], minlength=G.n) for a in range(9)])
+    dt = 0.8 / (out / G.area).max()
+    U = 0.01
+    res = {}
+    import warnings
+    for lim in (0, 2):
+        orc = O.Oracle(m, O.default_params(nu=0.05 / 100, dt=dt, limiter=lim, group_u=[[0, 0], [U, 0], [0, 0]],
+                                           group_rho=[1, 1, 1]))
+        f, _, _ = orc.init_state(np.ones(G.n), np.zeros(G.n), np.zeros(G.n))
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            for i in range(300):
+                f, _, _ = orc.step(f)
+                rho, ux, uy, _ = orc.macro(f)
+                if not (np.abs(ux).max() < 1.0):
+                    break
+        res[lim] = (i, rho, ux, uy)
+    i0, _, ux0, _ = res[0]
+    i2, rho2, ux2, uy2 = res[2]
+    assert not (np.abs(ux0).max() < 1.0), "the unlimited run was expected to blow up"
+    assert i2 == 299 and np.abs(ux2).max() < 3 * U and np.abs(uy2).max() < 3 * U
+    assert 0.98 < rho2.min() and rho2.max() < 1.05
+
+
 @pytest.mark.parametrize("ratio", [0.5, 1.0, 1.9])
 def test_explicit_uniform_relaxation_factor(ratio):
     """A uniform non-equilibrium perturbation on a periodic mesh (no convection) relaxes by the
