@@ -120,14 +120,15 @@ def make_state(F, M, flow, init, precision, dt_frac):
 def kernel_bytes(T, S, variant="ring", recover=False):
     # ring kernels, triangles: per edge the int16 slot code and the neighbour-centroid offset q
     # (2 values), per cell the vertex offsets from the centroid (2 vertices in FP32, 3 in FP64);
-    # normals, midpoints, area and LSQ coefficients are formed from them.  Other meshes: per edge
-    # the slot code and normal, midpoint and neighbour offsets (6 values), per cell 1/area and the
-    # inverse LSQ matrix.  The first-boundary-edge index is read by boundary cells only.  Split
-    # kernels: both int32 ids and 8 edge values per edge.
+    # normals, midpoints and area are formed from them, and in FP64 the LSQ coefficients too, while
+    # FP32 reads the host's LSQ coefficients (2 values per edge).  Other meshes: per edge the slot
+    # code and normal, midpoint and neighbour offsets (6 values), per cell 1/area, and the inverse
+    # LSQ matrix (FP64) or the LSQ coefficients (FP32, 2 per edge).  The first-boundary-edge index is
+    # read by boundary cells only.  Split kernels: both int32 ids and 8 edge values per edge.
     if variant == "ring" and S == 3:
-        geo = 2 * S + 2 * T * S + (4 if T == 4 else 6) * T
+        geo = 2 * S + 2 * T * S + (4 * T + 2 * T * S if T == 4 else 6 * T)
     elif variant == "ring":
-        geo = 2 * S + 6 * T * S + 4 * T
+        geo = 2 * S + 6 * T * S + T + (2 * T * S if T == 4 else 3 * T)
     else:
         geo = 24 + 8 * T * S + T
     extra = 16 * T if variant == "split" else 0

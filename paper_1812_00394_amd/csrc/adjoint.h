@@ -531,6 +531,9 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     T *V = reinterpret_cast<T *>(smem);
     T *Gl = V + 8 * Wv;
     T *Mi = Gl + 16 * Wg;
+    // FP64 triangles form the coefficient of a neighbour's edge pointing back, c_(j->t) = w M_j^-1 (-d),
+    // from M_j^-1 in LDS; FP32 gathers it from the stored coefficients, the ones its forward uses
+    constexpr bool FORM = S == 3 && sizeof(T) == 8;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
@@ -554,7 +557,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
             mu[a] = -(lscale * Lc[a]) * ia;
             V[t * 8 + (a - 1)] = mu[a];
         }
-        if constexpr (S == 3) {
+        if constexpr (FORM) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) Mi[t * 3 + k] = mi[k];
         } else {
@@ -579,7 +582,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
         if (ring1) {
             cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy, hmi,
                              hia);
-            if constexpr (S == 3) {
+            if constexpr (FORM) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) Mi[(kTileCells + t) * 3 + k] = hmi[k];
             }
@@ -683,7 +686,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
         const bool in = nb[s] >= 0;
         const int r = in ? col[s] : 0;
         T bx, by;
-        if constexpr (S == 3) {
+        if constexpr (FORM) {
             // neighbour r's LSQ coefficient of its edge back to this cell: w M_r^-1 (-d)
             const T dx = rx[s] - qx[s], dy = ry[s] - qy[s];
             const T w = in ? recip(dx * dx + dy * dy) : T(0);
@@ -948,6 +951,9 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     T *Ln = X + 12 * Wv;
     T *Lg = Ln + 2 * Wv;
     T *Mi = Lg + 8 * Wg;   // [Wg][3] inverse LSQ matrices (S = 3)
+    // FP64 triangles form the coefficient of a neighbour's edge pointing back, c_(j->t) = w M_j^-1 (-d),
+    // from M_j^-1 in LDS; FP32 gathers it from the stored coefficients, the ones its forward uses
+    constexpr bool FORM = S == 3 && sizeof(T) == 8;
     const int tile = xcd_block(blockIdx.x, gridDim.x);
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
@@ -988,7 +994,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
         load_update(c, t, xc, lxc, lownc, pbc);
         T mi[3], ia;
         cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
-        if constexpr (S == 3) {
+        if constexpr (FORM) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) Mi[t * 3 + k] = mi[k];
         } else {
@@ -1017,7 +1023,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
             T hmi[3], hia;
             cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnx, hny, hrx, hry, hqx, hqy, hcx, hcy, hmi,
                              hia);
-            if constexpr (S == 3) {
+            if constexpr (FORM) {
 #pragma unroll
                 for (int k = 0; k < 3; ++k) Mi[(kTileCells + t) * 3 + k] = hmi[k];
             }
@@ -1107,7 +1113,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
         bnd = bnd || nb[s] <= -2;
         const int r = in ? col[s] : 0;
         T bx, by;
-        if constexpr (S == 3) {
+        if constexpr (FORM) {
             // neighbour r's LSQ coefficient of its edge back to this cell: w M_r^-1 (-d)
             const T dx = rx[s] - qx[s], dy = ry[s] - qy[s];
             const T w = in ? recip(dx * dx + dy * dy) : T(0);

@@ -513,8 +513,9 @@ __global__ void __launch_bounds__(kTileCells + kHaloThreads)
 // neighbours of ring-1 cells outside tile and ring 1) is listed per tile, so every global load a
 // workgroup needs is issued early, at most one dependent step behind the tile's own loads:
 //   phase 0: thread t loads tile cell t (stage values, its edge geometry; stage 1 also f^n and
-//            tau) and ext cell t (stage values; for a ring-1 cell also its LSQ coefficients and
-//            neighbour columns); the stage values of directions 1..8 go to LDS;
+//            tau) and ext cell t (stage values; for a ring-1 cell also its neighbour columns and
+//            the edge data its LSQ coefficients are formed from, as in its own tile); the stage
+//            values of directions 1..8 go to LDS;
 //   phase 1: LSQ gradients of ring-1 cell t and tile cell t from the LDS values, into LDS; the
 //            epilogue operands of stages 2, 3 (and of the explicit scheme) are loaded between the
 //            two, so that they are not live during phase 0 and the ring-1 gradient;
@@ -681,6 +682,10 @@ __device__ __forceinline__ void lsq_coef(T m00, T m01, T m11, T rx, T ry, T qx, 
 // x length, midpoint and neighbour-centroid offsets, LSQ coefficients, inverse LSQ matrix, inverse
 // area.  Triangle meshes (S = 3) form normals, midpoints, area and LSQ data from the vertex
 // offsets and q; other meshes read them, with the LSQ coefficients from the stored inverse matrix.
+// FP32 takes the LSQ coefficients themselves from the host's FP64 values, rounded once: formed in
+// FP32 on skewed, stretched cells they lose up to 2e-5 relative (cancellation in w M^-1 d), which
+// the FP32-deviation error gates resolve.  Tile cells and halo cells of other tiles go through this
+// one function, so a cell's coefficients never depend on the tile that evaluates them.
 template <typename T, int S>
 __device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__restrict__ lnb, size_t ls, size_t li,
                                            int c, int col[S], int nb[S], T nlx[S], T nly[S], T rx[S], T ry[S],
@@ -710,6 +715,13 @@ __device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__res
 #pragma unroll
         for (int s = 0; s < S; ++s) lsq_coef(mi[0], mi[1], mi[2], rx[s], ry[s], qx[s], qy[s], nb[s] != -1, cxs[s], cys[s]);
         ia = g.inv_area[c];
+    }
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            cxs[s] = g.cx[(size_t)s * n + c];
+            cys[s] = g.cy[(size_t)s * n + c];
+        }
     }
 }
 
@@ -767,14 +779,12 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
         for (int a = 1; a < 9; ++a) V[vrow<T>(kTileCells + t, a - 1)] = hv[a];
         if (ring1) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const size_t si = (size_t)s * n + hc;
-                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
-                hcx[s] = g.cx[si];
-                hcy[s] = g.cy[si];
-            }
-            decode_slots<S>(g.bfirst, hc, hcol, hnb);
+            // the ring-1 cell's LSQ coefficients formed exactly as in its own tile (same data, same
+            // code), so that its gradient, and the face values built from it, do not depend on
+            // which tile evaluates them
+            T hnlx[S], hnly[S], hrx[S], hry[S], hqx[S], hqy[S], hmi[3], hia;
+            cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy,
+                             hmi, hia);
         }
     }
     // ring-2 cells beyond one per thread (tiles of stretched cells): their values only
@@ -1452,14 +1462,10 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         Vv[j * 8 + 3] = hw;
         Vv[j * 8 + 4] = hr;
         if (ring1) {
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const size_t si = (size_t)s * n + hc;
-                hcol[s] = rt.lnb[(size_t)s * rt.n_ext + x0 + t];
-                hcx[s] = g.cx[si];
-                hcy[s] = g.cy[si];
-            }
-            decode_slots<S>(g.bfirst, hc, hcol, hnb);
+            // LSQ coefficients formed as in the cell's own tile (see k_stage_ring)
+            T hnlx[S], hnly[S], hrx[S], hry[S], hqx[S], hqy[S], hmi[3], hia;
+            cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy,
+                             hmi, hia);
             hd = T(g.wdist[hc]);
         }
     }

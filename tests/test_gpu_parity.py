@@ -564,18 +564,20 @@ def _wide_halo_backstep():
     return mg.backstep(core=0.3, dx_core=0.6, dx_corner=0.02, y1=1e-3)
 
 
-def test_wide_halo_ring_step_parity(F):
-    """The ring kernels loop over ring-2 cells beyond one per thread.  SST steps against the oracle:
-    FP32-dev on the ring path (its LDS fits), FP64 on whichever path fits; gates as the SST
-    parity tests (FP64 1e-12 / 1e-11, FP32-dev 2e-6 after one step)."""
+@pytest.mark.parametrize("order", ["morton", "tiles"])
+def test_wide_halo_ring_step_parity(F, order):
+    """The ring kernels loop over ring-2 cells beyond one per thread (Morton tiles of this mesh need
+    it).  SST steps against the oracle, under Morton tiles and under the graph-grown tiles the
+    library uses by default: FP32-dev on the ring path (its LDS fits), FP64 on whichever path fits;
+    gates as the SST parity tests (FP64 1e-12 / 1e-11, FP32-dev 2e-6 after one step)."""
     m = _wide_halo_backstep()
     extra = dict(group_u=[[0, 0], [0.05, 0], [0, 0]], group_k=[0, 1e-4, 0], group_w=[0, 0.5, 0])
     orc, p, f, k, w = _sst_case(m, extra, 56)
     f1, k1, w1 = orc.step(f, k, w)
     nut1 = orc.last_nut
-    M = F.Mesh(m, order="morton")     # Morton tiles: the ring-2 cells beyond one per thread
+    M = F.Mesh(m, order=order)
     for precision in ("fp64", "fp32dev"):
-        say("wide-halo backstep", precision)
+        say("wide-halo backstep", order, precision)
         st = F.State(M, p, precision=precision, k=k, omega=w)
         st.set_state(f, k, w)
         st.timing(True)
@@ -596,5 +598,31 @@ def test_wide_halo_ring_step_parity(F):
         else:
             _, ux, uy, _ = orc.macro(f1)
             du = max(np.abs(mo["u"][:, 0] - ux).max(), np.abs(mo["u"][:, 1] - uy).max()) / 0.05
+            print(order, "fp32dev max |du| / U after one step:", du)
             assert du < 2e-6, du
             assert rel(mo["k"], k1, np.abs(k1).max()) < 2e-6 and rel(mo["omega"], w1, np.abs(w1).max()) < 2e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
+def test_step_is_independent_of_the_tile_layout(F, precision):
+    """Every cell forms its LSQ coefficients, gradient, face values and update from its own data with
+    the same code whether it is a tile cell or a halo cell of another tile, so the ring path's result
+    must not depend on how the cells are grouped into tiles: three SST steps under Morton tiles and
+    under graph-grown tiles agree to the last bit (f, k, omega in the caller's cell order)."""
+    say("tile-layout independence", precision)
+    m = _wide_halo_backstep()
+    extra = dict(group_u=[[0, 0], [0.05, 0], [0, 0]], group_k=[0, 1e-4, 0], group_w=[0, 0.5, 0])
+    orc, p, f, k, w = _sst_case(m, extra, 57)
+    out = {}
+    for order in ("morton", "tiles"):
+        st = F.State(F.Mesh(m, order=order), p, precision=precision, k=k, omega=w)
+        st.set_state(f, k, w)
+        st.timing(True)
+        st.step(3)
+        kt = st.timing_read()
+        assert kt["sst"][1] == 3 and kt["collide1"][1] == 0, kt      # the ring path
+        mo = st.moments()
+        out[order] = (st.get_f(), mo["k"], mo["omega"])
+        del st
+    for a, b in zip(out["morton"], out["tiles"]):
+        np.testing.assert_array_equal(a, b)
