@@ -324,6 +324,34 @@ def backstep_run(F, stream, warmup, steps=2000, adj_steps=400, ckpt=20):
     return out
 
 
+def sweep_variants(F, M, flow, init, dt_frac, stream, args):
+    """The step with each sweep variant on the benchmark mesh, both precisions: the ring-tiled cell
+    loop the library chooses, the two-kernel cell loop (gradient planes in HBM, then one thread per
+    cell) and the edge loop with atomics (gradient planes in HBM, one thread per interior edge adding
+    its flux to both cells, then one thread per cell for boundary edges and the stage epilogue).
+    Per step and per kernel (HIP events)."""
+    out = {}
+    steps = max(20, args.steps // 4)
+    for prec in ("fp32dev", "fp64"):
+        for variant in ("ring", "split", "face"):
+            os.environ["FVLBM_SWEEP"] = variant
+            try:
+                st, _ = make_state(F, M, flow, init, prec, dt_frac)
+            finally:
+                del os.environ["FVLBM_SWEEP"]
+            ms, _, _ = time_steps(F, st, steps, args.warmup, stream, kernel_timing=False)
+            _, _, kt = time_steps(F, st, steps, 0, stream, kernel_timing=True)
+            if not np.all(np.isfinite(st.moments()["totals"])):
+                raise SystemExit(f"sweep variant {variant} {prec}: non-finite state")
+            out.setdefault(prec, {})[variant] = {
+                "ms_per_step": round(ms / steps, 4),
+                "kernels_ms": {k: round(v[0] / v[1], 5) for k, v in kt.items() if v[1]},
+                "launches_per_step": {k: v[1] / steps for k, v in kt.items() if v[1]}}
+            log(f"sweep variant {variant} {prec}: {ms / steps:.3f} ms/step")
+            del st
+    return out
+
+
 def airfoil_run(F, steps):
     """The airfoil workload: 512 x 384 O-mesh (196,608 quads) around the sharp-trailing-edge 12 %
     section, Re 6e6 on the chord, 10 degrees incidence, u_inf = 0.05, dt = 0.9 of the advective
@@ -384,6 +412,8 @@ def main():
                     help="steps of the airfoil run (lift and drag in FP32-dev and FP64; 0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference kernel for rocprof byte counters)")
+    ap.add_argument("--sweep-variants", action="store_true",
+                    help="also time the step with the edge loop with atomics and the two-kernel cell loop")
     ap.add_argument("--mesh-cache", default=None,
                     help="directory where the generated benchmark mesh is kept as .npz for later runs")
     args = ap.parse_args()
@@ -541,6 +571,7 @@ def main():
             f"{solve_ms * 1e3:.1f} us ({implicit['jacobi_algorithmic_gbs']} GB/s)")
         del sti
 
+    variants = sweep_variants(F, M, flow, init, dt_frac, stream, args) if args.sweep_variants else None
     airfoil = airfoil_run(F, args.airfoil_steps) if args.airfoil_steps > 0 else None
     backstep = None if args.no_backstep else backstep_run(F, stream, args.warmup)
     cost_ratio = None if args.no_explicit else imex_vs_explicit(F, M, flow, init, dt_frac)
@@ -596,6 +627,7 @@ def main():
         "imex_over_explicit_per_step": cost_ratio,
         "sst_per_stage": per_stage,
         "sst_implicit": implicit,
+        "sweep_variants": variants,
         "cpu_baseline": cpu,
         "kernel_source_sha256": source_hash(),
     }

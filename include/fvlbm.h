@@ -20,8 +20,10 @@
  *     overlapped recompute on small meshes uses a stream of its own, joined to that stream before
  *     the call returns).  Calls that return host values synchronise that stream; the others are
  *     asynchronous.
- *   - Environment (diagnostics and tests): FVLBM_SWEEP = ring | tiled | tiled-grads | split forces
- *     a sweep variant (ring: only where it fits); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
+ *   - Environment (diagnostics and tests): FVLBM_SWEEP = ring | tiled | tiled-grads | split | face
+ *     forces a sweep variant (ring: only where it fits; face: the edge loop with atomics, kept for
+ *     the measured comparison with the cell loops; its sums' order, and so the last bits of its
+ *     results, vary from run to run); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
  *     of segment buffers (no kept second tape, no overlap).  Both are read when a state is created
  *     or a run recorded.
  *   - Distribution functions are indexed by the D2Q9 direction a = 0..8 with lattice
@@ -255,7 +257,8 @@ enum {
     FVLBM_K_SST = 7,       /* SST in one ring-tiled launch (replaces SST_A + SST_B) */
     FVLBM_K_EXPLICIT = 8,  /* convection + collision of the explicit scheme */
     FVLBM_K_SST_JACOBI = 9, /* Jacobi sweeps of the implicit SST variant (all of a solve) */
-    FVLBM_K_COUNT = 10
+    FVLBM_K_FACE = 10,     /* edge loop with atomics (FVLBM_SWEEP=face): the interior edges' fluxes */
+    FVLBM_K_COUNT = 11
 };
 fvlbm_status fvlbm_timing(fvlbm_state *st, int32_t enable);
 fvlbm_status fvlbm_timing_read(fvlbm_state *st, double ms[FVLBM_K_COUNT], int64_t launches[FVLBM_K_COUNT]);

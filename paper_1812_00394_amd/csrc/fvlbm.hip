@@ -74,6 +74,10 @@ struct fvlbm_state {
     // tiles of the fused stage kernels: ring (extended halo lists), tiled (ring 1 only, with or
     // without the stage values in LDS) or the two-kernel split path
     bool ring = true, tiled = true, tile_vals = true;
+    bool face = false;           // the edge loop with atomics (FVLBM_SWEEP=face)
+    int32_t n_faces = 0;         // interior edges, each once
+    int32_t *faces = nullptr;    // [n_faces] face codes 4 c + s
+    void *acc = nullptr;         // [8][n] outflow sums of the edge loop
     int ring_s = 4, ring_wv = 0, ring_wg = 0;
     size_t sst_lds_bytes = 0;
     bool want_aux = false;       // the SST launch also stores the aux planes (adjoint recompute)
@@ -125,6 +129,21 @@ template <>
 Geo<double> &geo_of<double>(fvlbm_state *st) { return st->geo64; }
 template <>
 Geo<float> &geo_of<float>(fvlbm_state *st) { return st->geo32; }
+
+// Interior edges, each once, in cell order: slot s of cell c with neighbour c' > c (face code
+// 4 c + s).  A periodic edge joining a cell to itself does not occur (it would need a period of one
+// cell).
+std::vector<int32_t> face_list(const fvlbm_mesh *m) {
+    std::vector<int32_t> f;
+    const int64_t n = m->n;
+    f.reserve((size_t)(2 * n));
+    for (int64_t c = 0; c < n; ++c)
+        for (int s = 0; s < kSlots; ++s) {
+            const int32_t nb = m->nbr[(size_t)s * n + c];
+            if (nb > c) f.push_back((int32_t)(4 * c + s));
+        }
+    return f;
+}
 
 // Layout of the workspace.  Geometry arrays are written by fvlbm_init; the rest is state.
 template <typename T>
@@ -194,6 +213,9 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
     st->scratch = cv.take<double>(9 * n);
     st->partial = cv.take<double>((size_t)kRedBlocks * 4);
     st->result = cv.take<double>(4);
+    st->n_faces = (int32_t)m->n_interior_edges;
+    st->faces = cv.take<int32_t>(std::max<size_t>(1, (size_t)m->n_interior_edges));
+    st->acc = cv.take<T>(8 * n);
 }
 
 size_t layout_bytes(const fvlbm_mesh *m, int precision, int sst) {
@@ -318,6 +340,12 @@ void upload_geometry(fvlbm_state *st) {
     std::vector<int32_t> perm(m->n);
     for (int64_t i = 0; i < m->n; ++i) perm[i] = (int32_t)m->perm[i];
     h2d(const_cast<int32_t *>(g.perm), perm, s);
+    if (st->face) {
+        const std::vector<int32_t> faces = face_list(m);
+        if ((int64_t)faces.size() != m->n_interior_edges)
+            throw Error(FVLBM_EMESH, "init: the edge loop needs every interior edge between two distinct cells");
+        if (!faces.empty()) h2d(st->faces, faces, s);
+    }
     h2d(const_cast<int32_t *>(g.b_kind), m->b_kind, s);
     h2d(const_cast<int32_t *>(g.b_cell), m->b_cell, s);
     h2d(const_cast<int32_t *>(g.b_group), m->b_group, s);
@@ -476,6 +504,31 @@ void launch_sst(fvlbm_state *st, const T *M, const T *K0, const T *W0, T *K1, T 
     }
 }
 
+// One stage sweep of the edge loop: the LSQ gradient planes of the stage field, the interior
+// edges' fluxes summed per cell with atomics, then per cell the boundary edges and the stage
+// epilogue.
+template <typename T, int J>
+void face_stage(fvlbm_state *st, const Geo<T> &g, const StageBufs<T> &b, const StepPar<T> &p) {
+    hipStream_t s = st->stream;
+    const int n = g.n, nbk = blocks_for(n);
+    T *G = (T *)st->G, *acc = (T *)st->acc;
+    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, b.src, G, p.rho0); }
+    {
+        Timed t(st, FVLBM_K_FACE);
+        k_fill<T><<<blocks_for(8 * (size_t)n), kBlock, 0, s>>>(8 * n, acc, T(0));
+        const int nf = st->n_faces;
+        if (nf > 0) {
+            if (p.limiter)
+                k_face_flux<T, true><<<blocks_for(nf), kBlock, 0, s>>>(g, st->faces, nf, b.src, G, acc);
+            else
+                k_face_flux<T, false><<<blocks_for(nf), kBlock, 0, s>>>(g, st->faces, nf, b.src, G, acc);
+        }
+    }
+    constexpr int kid = J == 1 ? FVLBM_K_SWEEP1 : (J == 2 ? FVLBM_K_SWEEP2 : FVLBM_K_SWEEP3);
+    Timed t(st, kid);
+    k_face_epilogue<T, J><<<nbk, kBlock, 0, s>>>(g, G, acc, b, p);
+}
+
 template <typename T>
 void launch_step(fvlbm_state *st) {
     const Geo<T> &g = geo_of<T>(st);
@@ -519,7 +572,12 @@ void launch_step(fvlbm_state *st) {
         return;
     }
     { Timed t(st, FVLBM_K_COLLIDE1); k_collide1<T><<<nbk, kBlock, 0, s>>>(n, F, tau, X, p); }
-    if (st->tiled) {
+    if (st->face) {
+        face_stage<T, 1>(st, g, b1, p);
+        sst_stage3();
+        face_stage<T, 2>(st, g, b2, p);
+        face_stage<T, 3>(st, g, b3, p);
+    } else if (st->tiled) {
         const int nt = st->mesh->n_tiles;
         const size_t lds = st->lds_bytes;
         const int nth = kTileCells + kHaloThreads;
@@ -639,6 +697,14 @@ void choose_sweep(fvlbm_state *st) {
     st->ring_s = st->mesh->max_faces <= 3 ? 3 : 4;
     st->ring_wv = kTile + st->mesh->ext_max;
     st->ring_wg = kTile + st->mesh->halo_max;
+    if (mode == "face") {
+        // the edge loop with atomics: gradients in HBM, then one thread per interior edge
+        st->face = true;
+        st->ring = false;
+        st->tiled = false;
+        st->lds_bytes = 0;
+        return;
+    }
     const size_t ring_lds = ((size_t)8 * st->ring_wv + (size_t)16 * st->ring_wg) * sizeof(T);
     // the adjoint's ring kernels must fit as well: transposed convection and the SST reverse
     const size_t adj_lds = std::max(adj_t_lds<T>(st), adj_sst_lds<T>(st));

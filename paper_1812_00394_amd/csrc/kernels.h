@@ -382,6 +382,84 @@ __global__ void __launch_bounds__(256) k_sweep(Geo<T> g, const T *__restrict__ G
     stage_epilogue<T, J>(c, n, gc, ga, b, p);
 }
 
+// ---- edge loop with atomics: the alternative to the cell loop, kept for the measured choice ----
+// One thread per interior edge, each edge once (face code 4 c + s: slot s of cell c, the lower
+// index of the two cells): the upwind face value of every moving direction from the gradient
+// planes of k_grad (clipped between the two cells' values with the limiter of reading r32), and
+// its flux (e.n) dl times the face value added to the outflow sum of c and subtracted from that of
+// the neighbour with global atomics.  Consecutive edges belong to nearby cells; workgroups are
+// mapped so that each XCD takes one contiguous range of edges.  acc ([8][n], directions 1..8)
+// starts at zero.  The order in which the atomics add up differs from run to run, so results vary
+// at rounding level, where the cell loop is deterministic.
+template <typename T, bool LIM>
+__global__ void __launch_bounds__(256) k_face_flux(Geo<T> g, const int32_t *__restrict__ faces, int nf,
+                                                   const T *__restrict__ f, const T *__restrict__ G,
+                                                   T *__restrict__ acc) {
+    const int i = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    const int code = faces[i];
+    const int c = code >> 2, s = code & 3, n = g.n;
+    const size_t si = (size_t)s * n + c;
+    const int nb = g.nbr[si];
+    const T nlx = g.nlx[si], nly = g.nly[si], rx = g.rfx[si], ry = g.rfy[si], qx = g.qx[si], qy = g.qy[si];
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        const T end = T(ex(a)) * nlx + T(ey(a)) * nly;
+        const size_t pa = (size_t)a * n, px = (size_t)(2 * (a - 1)) * n, py = px + n;
+        const T vc = f[pa + c], vn = f[pa + nb];
+        T val = end >= T(0) ? vc + G[px + c] * rx + G[py + c] * ry : vn + G[px + nb] * qx + G[py + nb] * qy;
+        if constexpr (LIM) val = clip_between(val, vc, vn);
+        const T flux = end * val;
+        atomicAdd(&acc[(size_t)(a - 1) * n + c], flux);
+        atomicAdd(&acc[(size_t)(a - 1) * n + nb], -flux);
+    }
+}
+
+// After k_face_flux: the boundary edges of the cell (ghost states at walls and for incoming
+// directions, the cell's own reconstruction for outgoing ones, as the cell loop), the convection
+// term -(1/A) times the outflow sum, and the stage-J epilogue.
+template <typename T, int J>
+__global__ void __launch_bounds__(256) k_face_epilogue(Geo<T> g, const T *__restrict__ G, const T *__restrict__ acc,
+                                                       StageBufs<T> b, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], sum[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
+    sum[0] = T(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) sum[a] = acc[(size_t)(a - 1) * n + c];
+    if (g.bfirst[c] >= 0) {
+        T drho, rho, ux, uy;
+        moments(gc, p.rho0, drho, rho, ux, uy);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const size_t si = (size_t)s * n + c;
+            const int nb = g.nbr[si];
+            if (nb > -2) continue;
+            const int bi = -2 - nb;
+            const T nlx = g.nlx[si], nly = g.nly[si], rx = g.rfx[si], ry = g.rfy[si];
+            T gb[9];
+            ghost(g, bi, nlx, nly, gc, drho, rho, ux, uy, gb);
+            const int kind = g.b_kind[bi];
+            const bool wall = (kind == kWall || kind == kMovingWall);
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const T end = T(ex(a)) * nlx + T(ey(a)) * nly;
+                const T own = gc[a] + G[(size_t)(2 * (a - 1)) * n + c] * rx + G[(size_t)(2 * (a - 1) + 1) * n + c] * ry;
+                sum[a] += end * ((wall || end < T(0)) ? gb[a] : own);
+            }
+        }
+    }
+    const T ia = g.inv_area[c];
+    T ga[9];
+    ga[0] = T(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) ga[a] = -sum[a] * ia;
+    stage_epilogue<T, J>(c, n, gc, ga, b, p);
+}
+
 // Tiled sweep: one workgroup per tile of kTileCells consecutive cells plus kHaloThreads extra
 // threads for the tile's halo (the interior neighbours outside the tile).
 //   VALS = true : phase 0 stages the stage field of the tile and its halo in LDS (directions 1..8);

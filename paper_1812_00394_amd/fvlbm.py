@@ -57,7 +57,7 @@ EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlb
            "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
            "fvlbm_adjoint_state", "fvlbm_lift_drag", "fvlbm_step_explicit",
            "fvlbm_run_to_residual"]
-KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit", "sst_jacobi"]
+KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit", "sst_jacobi", "face"]
 
 
 def lib():

@@ -144,7 +144,7 @@ def _oracle_final(m, p, f0, k0, w0, N):
 PARAMS = ["theta", "sigma_k1", "sigma_w1", "beta_star", "a1"]
 
 
-@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("sweep", ["ring", "split", "face"])
 @pytest.mark.parametrize("name", sorted(RUNS))
 def test_run_adjoint_dot_product_and_params(F, name, sweep, monkeypatch):
     say("run adjoint", name, sweep)

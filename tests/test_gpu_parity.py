@@ -82,11 +82,12 @@ def test_advection_operator_parity(F, name):
     assert rel(got, ref, np.abs(ref).max()) < 1e-12
 
 
-@pytest.mark.parametrize("sweep", ["ring", "tiled", "tiled-grads", "split"])
+@pytest.mark.parametrize("sweep", ["ring", "tiled", "tiled-grads", "split", "face"])
 @pytest.mark.parametrize("name", sorted(MESHES))
 def test_laminar_step_parity(F, name, sweep, monkeypatch):
     """Every sweep variant: ring-tiled (both halo rings staged in LDS, stage 1 collision fused),
-    tiled with values and gradients in LDS, tiled with gradients only, and the two-kernel path."""
+    tiled with values and gradients in LDS, tiled with gradients only, the two-kernel path, and the
+    edge loop with atomics."""
     say("laminar step", name, sweep)
     monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = MESHES[name]
@@ -188,10 +189,10 @@ SST_MESHES = {
 }
 
 
-@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("sweep", ["ring", "split", "face"])
 @pytest.mark.parametrize("name", sorted(SST_MESHES))
 def test_sst_step_parity(F, name, sweep, monkeypatch):
-    """The SST in one ring-tiled launch and as the two-kernel pair."""
+    """The SST in one ring-tiled launch and as the two-kernel pair (which the edge loop also uses)."""
     say("sst step", name, sweep)
     monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = SST_MESHES[name]
@@ -386,7 +387,7 @@ def test_limited_advection_operator_parity(F, name):
     assert rel(got, ref, np.abs(ref).max()) < 1e-12
 
 
-@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("sweep", ["ring", "split", "face"])
 @pytest.mark.parametrize("name", ["cavity", "channel", "naca"])
 def test_limited_laminar_step_parity(F, name, sweep, monkeypatch):
     say("limited laminar step", name, sweep)
