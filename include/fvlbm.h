@@ -214,6 +214,19 @@ fvlbm_status fvlbm_step_explicit(fvlbm_state *st, int32_t n_steps, double *resid
 fvlbm_status fvlbm_moments(fvlbm_state *st, int32_t on_device, double *rho, double *u, double *k,
                            double *omega, double *nu_t, double totals[3]);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the totals of fvlbm_moments (sum A rho, sum A rho u_x, sum A rho u_y, FP64,
+ * same kernels and summation order) written to totals_dev, a device pointer to 3 doubles, enqueued
+ * on the state's stream without synchronising and without allocating.  The partial sums live in a
+ * reduction buffer the library holds itself, 16 KiB per GPU until the process ends (the fixed grid
+ * of 512 blocks x 3 sums needs 12 KiB; every size of state fits).  Calls that overlap on one GPU
+ * (states on different streams, several host threads) share that buffer and race: order them on one
+ * stream.  No non-finite check (read the result).  Errors: FVLBM_EINVAL (NULL, empty state),
+ * FVLBM_EDEVICE (launch).
+ */
+fvlbm_status fvlbm_totals_noalloc(fvlbm_state *st, double *totals_dev);
+
 /* f [9][n] in FP64, user order (for FP32 storage: w_a rho0 added back). */
 fvlbm_status fvlbm_get_f(fvlbm_state *st, int32_t on_device, double *f);
 

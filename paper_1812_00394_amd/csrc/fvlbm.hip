@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -52,7 +53,33 @@ void set_last_error(const std::string &msg) { g_last_error = msg; }
 
 }  // namespace fvlbm
 
+
 using namespace fvlbm;
+
+// ---- the reduction buffer of fvlbm_totals_noalloc: device memory the library holds itself ----
+// One per GPU the library runs on, for the whole process: 16 KiB, of which the per-block partial
+// sums of the fixed reduction grid (kRedBlocks blocks x 3 sums) use 12 KiB.  In host code the array's name is a host-side
+// stand-in, not a device address: its device address is looked up once per device (when a state is
+// created on it) and kept in g_scratch_dev; host code uses only that address.
+namespace {
+constexpr size_t kNoAllocScratchDoubles = 2048;
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[kMaxDevices] = {};
+
+// The device address of `scratch` on `dev` (which must be the current device), looked up once.
+double *scratch_on(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) throw Error(FVLBM_EDEVICE, "device index out of range for the reduction buffer");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        g_scratch_dev[dev] = static_cast<double *>(ptr);
+    }
+    return g_scratch_dev[dev];
+}
+}  // namespace
 
 struct fvlbm_state {
     const fvlbm_mesh *mesh = nullptr;
@@ -63,6 +90,8 @@ struct fvlbm_state {
     Geo<double> geo64{};
     Geo<float> geo32{};
     int32_t n_cells = 0;
+    int device = 0;              // the HIP device current when the state was created
+    double *noalloc = nullptr;   // that device's reduction buffer of fvlbm_totals_noalloc
     int32_t *bzg = nullptr;
     void *F = nullptr, *X = nullptr, *Y = nullptr, *A = nullptr, *G = nullptr;
     void *M[2] = {nullptr, nullptr};
@@ -775,6 +804,16 @@ void totals(fvlbm_state *st, double out[3]) {
     check(hipStreamSynchronize(st->stream), "hipStreamSynchronize");
 }
 
+// The totals of fvlbm_moments into a caller device buffer, asynchronously, with the partial sums in
+// the library's own reduction buffer instead of the workspace (same kernels, same summation order).
+template <typename T>
+void totals_noalloc(fvlbm_state *st, double *out_dev) {
+    static_assert((size_t)kRedBlocks * 3 <= kNoAllocScratchDoubles, "the reduction buffer is too small");
+    k_totals<T><<<kRedBlocks, kBlock, 0, st->stream>>>(geo_of<T>(st), (const T *)st->M[st->cur_m], st->par.rho0, st->noalloc);
+    k_finish<3><<<1, kBlock, 0, st->stream>>>(st->noalloc, kRedBlocks, out_dev);
+    check(hipGetLastError(), "kernel launch");
+}
+
 template <typename T>
 void forces(fvlbm_state *st, uint64_t mask, double out[3]) {
     k_forces<T><<<kRedBlocks, kBlock, 0, st->stream>>>(geo_of<T>(st), (const T *)st->M[st->cur_m], st->par.rho0, st->par.nu,
@@ -1382,6 +1421,8 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         st->par = *p;
         st->par.bface_vals = nullptr;   // only used here, the caller's array is not kept
         st->stream = reinterpret_cast<hipStream_t>(hip_stream);
+        check(hipGetDevice(&st->device), "hipGetDevice");
+        st->noalloc = scratch_on(st->device);
         Carver cv;
         cv.base = reinterpret_cast<char *>(workspace);
         fvlbm_params pv = *p;
@@ -1500,6 +1541,17 @@ fvlbm_status fvlbm_moments(fvlbm_state *st, int32_t on_device, double *rho, doub
             for (int i = 0; i < 3; ++i)
                 if (!std::isfinite(tot[i])) throw Error(FVLBM_EDIVERGED, "moments: non-finite totals");
         }
+    });
+}
+
+fvlbm_status fvlbm_totals_noalloc(fvlbm_state *st, double *totals_dev) {
+    return guarded([&] {
+        if (!st || !totals_dev) throw Error(FVLBM_EINVAL, "totals_noalloc: NULL argument");
+        if (st->n_cells < 1) throw Error(FVLBM_EINVAL, "totals_noalloc: empty state");
+        if (st->precision == FVLBM_FP64)
+            totals_noalloc<double>(st, totals_dev);
+        else
+            totals_noalloc<float>(st, totals_dev);
     });
 }
 

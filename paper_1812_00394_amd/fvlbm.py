@@ -56,7 +56,7 @@ EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlb
            "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read",
            "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
            "fvlbm_adjoint_state", "fvlbm_lift_drag", "fvlbm_step_explicit",
-           "fvlbm_run_to_residual"]
+           "fvlbm_run_to_residual", "fvlbm_totals_noalloc"]
 KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit", "sst_jacobi", "face"]
 
 
@@ -88,6 +88,7 @@ def lib():
     L.fvlbm_get_f.argtypes = [P, I32, P]
     L.fvlbm_forces.argtypes = [P, C.c_uint64, P, P]
     L.fvlbm_lift_drag.argtypes = [P, C.c_uint64, C.c_double, C.c_double, P]
+    L.fvlbm_totals_noalloc.argtypes = [P, P]
     L.fvlbm_apply_advection.argtypes = [P, P, P]
     L.fvlbm_mesh_max_dt.argtypes = [P, P]
     L.fvlbm_timing.argtypes = [P, I32]
@@ -287,6 +288,15 @@ class State:
         jr = C.c_double()
         _check(lib().fvlbm_forces(self.handle, C.c_uint64(group_mask), _ptr(F), C.byref(jr)))
         return F, jr.value
+
+    def totals_noalloc(self, out):
+        """fvlbm_totals_noalloc: the totals into `out`, a torch float64 device tensor of 3 elements,
+        enqueued on the state's stream (no synchronisation, no allocation in the library)."""
+        import torch
+        if not (out.is_cuda and out.dtype == torch.float64 and out.numel() >= 3 and out.is_contiguous()):
+            raise ValueError("out must be a contiguous float64 device tensor of at least 3 elements")
+        _check(lib().fvlbm_totals_noalloc(self.handle, C.c_void_p(out.data_ptr())))
+        return out
 
     def lift_drag(self, group_mask, u_ref, chord=1.0):
         """(C_l, C_d) of the walls in group_mask: drag along the free stream (theta), lift normal to it."""
