@@ -89,8 +89,12 @@ typedef struct fvlbm_state fvlbm_state;
  *   jr_group, jr_xmin, eps_tau   the reattachment proxy J_R of fvlbm_forces
  *   limiter    0: the upwind face value of f is the linear reconstruction (Eq. (advection) with
  *              the cell gradient); 1: it is also kept between the values of the two cells that
- *              share the edge (first order at local extrema; for flows around sharp edges).  The
- *              adjoint entry points reject a limited state (FVLBM_ESTATE).
+ *              share the edge (first order at local extrema; for flows around sharp edges);
+ *              2: each cell's gradient is scaled (Barth and Jespersen) by the largest factor in
+ *              [0, 1] that keeps its reconstructed values at all its edge midpoints within the
+ *              least and greatest of its own value and its stencil values (neighbours, boundary
+ *              ghosts): bounded on meshes with sliver cells, where the plain reconstruction has
+ *              a growing mode.  The adjoint entry points reject a limited state (FVLBM_ESTATE).
  *   sst_sweeps 0: the SST equations advance point-implicitly (sinks implicit, face fluxes
  *              explicit).  m in [1, 1000]: they advance implicitly as Section 3.2 says of the
  *              Code_Saturne integration: backward Euler for the increments of k and omega with

@@ -450,15 +450,19 @@ void stage_ring(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, const Sta
     const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
     const size_t lds = st->lds_bytes;
     if (st->ring_s == 3) {
-        if (p.limiter)
-            k_stage_ring<T, J, 3, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+        if (p.limiter == 1)
+            k_stage_ring<T, J, 3, 1><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+        else if (p.limiter == 2)
+            k_stage_ring<T, J, 3, 2><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
         else
-            k_stage_ring<T, J, 3, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            k_stage_ring<T, J, 3, 0><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
     } else {
-        if (p.limiter)
-            k_stage_ring<T, J, 4, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+        if (p.limiter == 1)
+            k_stage_ring<T, J, 4, 1><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+        else if (p.limiter == 2)
+            k_stage_ring<T, J, 4, 2><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
         else
-            k_stage_ring<T, J, 4, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            k_stage_ring<T, J, 4, 0><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
     }
 }
 
@@ -541,13 +545,17 @@ void face_stage(fvlbm_state *st, const Geo<T> &g, const StageBufs<T> &b, const S
     hipStream_t s = st->stream;
     const int n = g.n, nbk = blocks_for(n);
     T *G = (T *)st->G, *acc = (T *)st->acc;
-    { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, b.src, G, p.rho0); }
+    {
+        Timed t(st, FVLBM_K_GRAD);
+        k_grad<T><<<nbk, kBlock, 0, s>>>(g, b.src, G, p.rho0);
+        if (p.limiter == 2) k_bj<T><<<nbk, kBlock, 0, s>>>(g, b.src, G, p.rho0);
+    }
     {
         Timed t(st, FVLBM_K_FACE);
         k_fill<T><<<blocks_for(8 * (size_t)n), kBlock, 0, s>>>(8 * n, acc, T(0));
         const int nf = st->n_faces;
         if (nf > 0) {
-            if (p.limiter)
+            if (p.limiter == 1)
                 k_face_flux<T, true><<<blocks_for(nf), kBlock, 0, s>>>(g, st->faces, nf, b.src, G, acc);
             else
                 k_face_flux<T, false><<<blocks_for(nf), kBlock, 0, s>>>(g, st->faces, nf, b.src, G, acc);
@@ -622,12 +630,18 @@ void launch_step(fvlbm_state *st) {
             { Timed t(st, FVLBM_K_SWEEP3); k_stage_tiled<T, 3, false><<<nt, nth, lds, s>>>(g, st->hptr, st->hcell, st->lnb, st->tile_w, b3, p); }
         }
     } else {
-        { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
+        // gradient planes of a stage field, limited by reading r35 when asked
+        auto grads = [&](const T *src) {
+            Timed t(st, FVLBM_K_GRAD);
+            k_grad<T><<<nbk, kBlock, 0, s>>>(g, src, G, p.rho0);
+            if (p.limiter == 2) k_bj<T><<<nbk, kBlock, 0, s>>>(g, src, G, p.rho0);
+        };
+        grads(X);
         { Timed t(st, FVLBM_K_SWEEP1); k_sweep<T, 1><<<nbk, kBlock, 0, s>>>(g, G, b1, p); }
         sst_stage3();
-        { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, Y, G, p.rho0); }
+        grads(Y);
         { Timed t(st, FVLBM_K_SWEEP2); k_sweep<T, 2><<<nbk, kBlock, 0, s>>>(g, G, b2, p); }
-        { Timed t(st, FVLBM_K_GRAD); k_grad<T><<<nbk, kBlock, 0, s>>>(g, X, G, p.rho0); }
+        grads(X);
         { Timed t(st, FVLBM_K_SWEEP3); k_sweep<T, 3><<<nbk, kBlock, 0, s>>>(g, G, b3, p); }
     }
     st->cur_m ^= 1;
@@ -751,7 +765,8 @@ void choose_sweep(fvlbm_state *st) {
     const size_t with_vals = (size_t)24 * st->tile_w * sizeof(T), grads = (size_t)16 * st->tile_w * sizeof(T);
     st->tile_vals = mode != "tiled-grads" && with_vals <= (size_t)std::min(max_lds, 160 * 1024 / 3);
     st->lds_bytes = st->tile_vals ? with_vals : grads;
-    st->tiled = st->lds_bytes <= (size_t)max_lds && mode != "split";
+    // the tiled kernels form gradients in LDS without the limiter of r35: with it, the two-kernel path
+    st->tiled = st->lds_bytes <= (size_t)max_lds && mode != "split" && st->par.limiter != 2;
 }
 
 template <typename T>
@@ -832,6 +847,7 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
     upload_scratch(st, gin, 9 * (size_t)n);
     k_import_f<T><<<nbk, kBlock, 0, s>>>(g, st->scratch, (T *)st->X, st->par.rho0);
     k_grad<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (T *)st->G, T(st->par.rho0));
+    if (st->par.limiter == 2) k_bj<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (T *)st->G, T(st->par.rho0));
     k_advect<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->X, (const T *)st->G, (T *)st->Y, T(st->par.rho0), st->par.limiter);
     // Gamma^a is exported without the w_a rho0 shift
     k_export_f<T><<<nbk, kBlock, 0, s>>>(g, (const T *)st->Y, st->scratch, 0.0);
@@ -1408,7 +1424,7 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         if (!(p->nu > 0) || !(p->dt > 0) || !(p->rho0 > 0)) throw Error(FVLBM_EINVAL, "init: nu, dt and rho0 must be > 0 (tau = 3 nu)");
         if (p->sst < 0 || p->sst > 2) throw Error(FVLBM_EINVAL, "init: sst must be 0, 1 or 2");
         if (p->sst && (!k || !omega)) throw Error(FVLBM_EINVAL, "init: SST needs k and omega");
-        if (p->limiter != 0 && p->limiter != 1) throw Error(FVLBM_EINVAL, "init: limiter must be 0 or 1");
+        if (p->limiter < 0 || p->limiter > 2) throw Error(FVLBM_EINVAL, "init: limiter must be 0, 1 or 2");
         if (p->sst_sweeps < 0 || p->sst_sweeps > kMaxSstSweeps) throw Error(FVLBM_EINVAL, "init: sst_sweeps must be in [0, " + std::to_string(kMaxSstSweeps) + "]");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "init: workspace must be 256-byte aligned");
         const size_t need = layout_bytes(m, precision, p->sst ? 1 : 0);

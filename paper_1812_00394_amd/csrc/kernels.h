@@ -26,7 +26,8 @@ template <typename T>
 struct StepPar {
     T rho0, dt, nu;
     T a1, bstar, sk1, sk2, sw1, sw2, b1, b2, kappa;
-    int limiter;   // keep interior face values of f between the two cells' values
+    int limiter;   // 1: keep interior face values of f between the two cells' values (reading r32);
+                   // 2: Barth and Jespersen's gradient limiter (reading r35)
     int recover;   // stage 2 recovers Ga1 from f^(2) instead of reading it (stage 1 does not store it)
 };
 
@@ -147,7 +148,7 @@ __device__ __forceinline__ void advect_cell(const Geo<T> &g, int c, T rho0, cons
             for (int a = 1; a < 9; ++a) {
                 const T end = T(ex(a)) * nlx + T(ey(a)) * nly;
                 T val = end >= T(0) ? gc[a] + gxc[a] * rx + gyc[a] * ry : nbr_acc.recon(a, nb, qx, qy);
-                if (limiter) val = clip_between(val, gc[a], nbr_acc.value(a, nb));
+                if (limiter == 1) val = clip_between(val, gc[a], nbr_acc.value(a, nb));
                 acc[a] += end * val;
             }
         } else {
@@ -635,12 +636,19 @@ __device__ __forceinline__ int grow(int r, int k) {
 // slot; the normal of a boundary edge is read when needed).  The interior edges are summed in
 // straight-line code (an edge without an interior neighbour reads row 0 with weight 0), the
 // boundary edges' ghost states after them, in a branch that only boundary cells take.
-template <typename T, int S>
+// BOUNDS: also the least and greatest difference between a stencil value (neighbour or ghost) and
+// the cell's own value, each bounded by 0 (dlo <= 0 <= dhi), for the gradient limiter of r35.
+template <typename T, int S, bool BOUNDS = false>
 __device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int nb[S], const int col[S], const T cxs[S],
-                                          const T cys[S], const T *V, T rho0, const T gc[9], T gx[9], T gy[9]) {
+                                          const T cys[S], const T *V, T rho0, const T gc[9], T gx[9], T gy[9],
+                                          T *dlo = nullptr, T *dhi = nullptr) {
     const int n = g.n;
 #pragma unroll
     for (int a = 0; a < 9; ++a) gx[a] = gy[a] = T(0);
+    if constexpr (BOUNDS) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) dlo[a] = dhi[a] = T(0);
+    }
     bool bnd = false;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -653,6 +661,10 @@ __device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int n
             const T d = V[vrow<T>(r, a - 1)] - gc[a];
             gx[a] += wx * d;
             gy[a] += wy * d;
+            if constexpr (BOUNDS) {
+                dlo[a] = in && d < dlo[a] ? d : dlo[a];
+                dhi[a] = in && d > dhi[a] ? d : dhi[a];
+            }
         }
     }
     if (bnd) {
@@ -669,8 +681,86 @@ __device__ __forceinline__ void grad_ring(const Geo<T> &g, int cell, const int n
                 const T d = gb[a] - gc[a];
                 gx[a] += cxs[s] * d;
                 gy[a] += cys[s] * d;
+                if constexpr (BOUNDS) {
+                    dlo[a] = d < dlo[a] ? d : dlo[a];
+                    dhi[a] = d > dhi[a] ? d : dhi[a];
+                }
             }
         }
+    }
+}
+
+// Reading r35 (Barth and Jespersen): scales the gradient of each direction by the largest psi in
+// [0, 1] that keeps the reconstructed values at all the cell's edge midpoints (offsets rx, ry from
+// the centroid) within the cell's value plus [dlo, dhi], the stencil's bounds from grad_ring:
+// psi = min over the edges of dhi / increment (positive increments), dlo / increment (negative).
+template <typename T, int S>
+__device__ __forceinline__ void bj_scale(const int nb[S], const T rx[S], const T ry[S], const T dlo[9], const T dhi[9],
+                                         T gx[9], T gy[9]) {
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        T psi = T(1);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (nb[s] == -1) continue;
+            const T inc = gx[a] * rx[s] + gy[a] * ry[s];
+            const T r = inc > T(0) ? dhi[a] / inc : (inc < T(0) ? dlo[a] / inc : T(1));
+            psi = r < psi ? r : psi;
+        }
+        gx[a] *= psi;
+        gy[a] *= psi;
+    }
+}
+
+// Reading r35 on the gradient planes of k_grad (the two-kernel, edge-loop and diagnostic paths):
+// each cell's stencil bounds from its neighbours' values and boundary ghost states, then the scaling
+// of bj_scale, in place.
+template <typename T>
+__global__ void __launch_bounds__(256) k_bj(Geo<T> g, const T *__restrict__ f, T *__restrict__ G, T rho0) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    T gc[9], lo[9], hi[9], gx[9], gy[9], rx[4], ry[4];
+    int nbs[4];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        gc[a] = f[(size_t)a * n + c];
+        lo[a] = hi[a] = T(0);
+    }
+    T drho, rho, ux, uy;
+    moments(gc, rho0, drho, rho, ux, uy);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        nbs[s] = nb;
+        rx[s] = g.rfx[si];
+        ry[s] = g.rfy[si];
+        if (nb == -1) continue;
+        T v[9];
+        if (nb >= 0) {
+#pragma unroll
+            for (int a = 1; a < 9; ++a) v[a] = f[(size_t)a * n + nb];
+        } else {
+            ghost(g, -2 - nb, g.nlx[si], g.nly[si], gc, drho, rho, ux, uy, v);
+        }
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const T d = v[a] - gc[a];
+            lo[a] = d < lo[a] ? d : lo[a];
+            hi[a] = d > hi[a] ? d : hi[a];
+        }
+    }
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        gx[a] = G[(size_t)(2 * (a - 1)) * n + c];
+        gy[a] = G[(size_t)(2 * (a - 1) + 1) * n + c];
+    }
+    bj_scale<T, 4>(nbs, rx, ry, lo, hi, gx, gy);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        G[(size_t)(2 * (a - 1)) * n + c] = gx[a];
+        G[(size_t)(2 * (a - 1) + 1) * n + c] = gy[a];
     }
 }
 
@@ -803,7 +893,7 @@ __device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__res
     }
 }
 
-template <typename T, int J, int S, bool LIM>
+template <typename T, int J, int S, int LIM>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_stage_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg, StageBufs<T> b,
                  StepPar<T> p) {
@@ -840,7 +930,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     }
     T hv[9];
     int hc = 0, hnb[S], hcol[S];
-    T hcx[S], hcy[S];
+    T hcx[S], hcy[S], hrx[S], hry[S];   // hrx, hry: used by the gradient limiter of r35 only
     if (ext) {
         hc = rt.cell[x0 + t];
         if constexpr (J == 1) {
@@ -860,7 +950,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             // the ring-1 cell's LSQ coefficients formed exactly as in its own tile (same data, same
             // code), so that its gradient, and the face values built from it, do not depend on
             // which tile evaluates them
-            T hnlx[S], hnly[S], hrx[S], hry[S], hqx[S], hqy[S], hmi[3], hia;
+            T hnlx[S], hnly[S], hqx[S], hqy[S], hmi[3], hia;
             cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy,
                              hmi, hia);
         }
@@ -886,7 +976,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     // ---- phase 1 ----
     if (ring1) {
         T hx[9], hy[9];
-        grad_ring<T, S>(g, hc, hnb, hcol, hcx, hcy, V, p.rho0, hv, hx, hy);
+        if constexpr (LIM == 2) {
+            T lo[9], hi[9];
+            grad_ring<T, S, true>(g, hc, hnb, hcol, hcx, hcy, V, p.rho0, hv, hx, hy, lo, hi);
+            bj_scale<T, S>(hnb, hrx, hry, lo, hi, hx, hy);
+        } else {
+            grad_ring<T, S>(g, hc, hnb, hcol, hcx, hcy, V, p.rho0, hv, hx, hy);
+        }
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             Gl[grow<T>(kTileCells + t, 2 * (a - 1))] = hx[a];
@@ -898,7 +994,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         // the epilogue operands of stages other than 1 are loaded here, after the ring-1 work:
         // they are in flight during the gradient and the barrier without being live in phase 0
         if constexpr (J != 1) load_ops<T, J>(b, c, n, ops, p.recover);
-        grad_ring<T, S>(g, c, nb, col, cxs, cys, V, p.rho0, gc, gx, gy);
+        if constexpr (LIM == 2) {
+            T lo[9], hi[9];
+            grad_ring<T, S, true>(g, c, nb, col, cxs, cys, V, p.rho0, gc, gx, gy, lo, hi);
+            bj_scale<T, S>(nb, rx, ry, lo, hi, gx, gy);
+        } else {
+            grad_ring<T, S>(g, c, nb, col, cxs, cys, V, p.rho0, gc, gx, gy);
+        }
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             Gl[grow<T>(t, 2 * (a - 1))] = gx[a];
@@ -928,7 +1030,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             const T up_n = vn + Gl[grow<T>(loc, 2 * (a - 1))] * qx[s] + Gl[grow<T>(loc, 2 * (a - 1) + 1)] * qy[s];
             const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
             T val = end >= T(0) ? up_c : up_n;
-            if constexpr (LIM) val = clip_between(val, gc[a], vn);
+            if constexpr (LIM == 1) val = clip_between(val, gc[a], vn);
             acc[a] += end * val;
         }
         // one edge's LDS reads in flight at a time (bounds the registers they occupy)

@@ -372,12 +372,13 @@ def test_lift_drag_parity(F):
 # ------------------------------------------------------------------------------------------------
 # Optional face-value limiter (params["limiter"] = 1): same parity gates as the plain scheme.
 # ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("limiter", [1, 2])
 @pytest.mark.parametrize("name", ["cavity", "duct", "naca"])
-def test_limited_advection_operator_parity(F, name):
-    say("limited advection", name)
+def test_limited_advection_operator_parity(F, name, limiter):
+    say("limited advection", name, "limiter", limiter)
     make, extra = MESHES[name]
     m = make()
-    p = O.default_params(nu=1e-3, dt=1e-2, limiter=1, **extra)
+    p = O.default_params(nu=1e-3, dt=1e-2, limiter=limiter, **extra)
     orc = O.Oracle(m, p)
     rng = np.random.default_rng(43)
     g = _random_state(orc.g.n, rng)
@@ -387,15 +388,16 @@ def test_limited_advection_operator_parity(F, name):
     assert rel(got, ref, np.abs(ref).max()) < 1e-12
 
 
+@pytest.mark.parametrize("limiter", [1, 2])
 @pytest.mark.parametrize("sweep", ["ring", "split", "face"])
 @pytest.mark.parametrize("name", ["cavity", "channel", "naca"])
-def test_limited_laminar_step_parity(F, name, sweep, monkeypatch):
-    say("limited laminar step", name, sweep)
+def test_limited_laminar_step_parity(F, name, sweep, limiter, monkeypatch):
+    say("limited laminar step", name, sweep, "limiter", limiter)
     monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = MESHES[name]
     m = make()
     dt = courant_dt(m)
-    p = O.default_params(nu=dt / 30, dt=dt, limiter=1, **extra)
+    p = O.default_params(nu=dt / 30, dt=dt, limiter=limiter, **extra)
     orc = O.Oracle(m, p)
     f = _random_state(orc.g.n, np.random.default_rng(44))
     st = F.State(F.Mesh(m), p, precision="fp64")
@@ -408,12 +410,13 @@ def test_limited_laminar_step_parity(F, name, sweep, monkeypatch):
         assert rel(st.get_f(), fo, dev_scale(fo)) < tol
 
 
-def test_limited_sst_step_parity_and_no_adjoint(F):
-    say("limited sst step, backstep_coarse")
+@pytest.mark.parametrize("limiter", [1, 2])
+def test_limited_sst_step_parity_and_no_adjoint(F, limiter):
+    say("limited sst step, backstep_coarse, limiter", limiter)
     make, extra = SST_MESHES["backstep_coarse"]
     m = make()
     orc, p, f, k, w = _sst_case(m, extra, 52)
-    p = dict(p, limiter=1)
+    p = dict(p, limiter=limiter)
     orc = O.Oracle(m, p)
     st = F.State(F.Mesh(m), p, precision="fp64", k=k, omega=w)
     st.set_state(f, k, w)
