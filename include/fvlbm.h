@@ -329,6 +329,20 @@ fvlbm_status fvlbm_adjoint_step(fvlbm_state *st, uint64_t wall_group_mask, const
 fvlbm_status fvlbm_adjoint_state(fvlbm_state *st, const double *lam_f, const double *lam_k, const double *lam_w,
                                  double *lam_f0, double *lam_k0, double *lam_w0, double dparams[5]);
 
+/*
+ * The adjoint of the lift and drag coefficients of the airfoil test (Section 4, the NACA0012
+ * lift/drag table): for J = seed[0] C_l + seed[1] C_d of the final recorded state, with C_l, C_d as
+ * fvlbm_lift_drag defines them (the wall force of the groups in wall_group_mask along the lift and
+ * drag directions of the inflow angle theta, over rho0 u_ref^2 chord / 2), returns
+ * dparams = dJ/d(theta, sigma_k1, sigma_omega1, beta*, a1) in FP64: the reverse run of
+ * fvlbm_adjoint_step seeded with dJ/dF, plus the explicit dependence on theta of the two directions
+ * (dC_l/dtheta = -C_d, dC_d/dtheta = C_l at fixed force).  coeffs (may be NULL) receives (C_l, C_d)
+ * of the final state.  Errors: FVLBM_EINVAL (NULL, u_ref or chord <= 0), FVLBM_ESTATE (no
+ * recording), FVLBM_EDIVERGED.
+ */
+fvlbm_status fvlbm_adjoint_lift_drag(fvlbm_state *st, uint64_t wall_group_mask, double u_ref, double chord,
+                                     const double seed[2], double coeffs[2], double dparams[5]);
+
 void fvlbm_state_destroy(fvlbm_state *st);
 
 const char *fvlbm_last_error(void);

@@ -65,3 +65,28 @@ class FVLBMObjective(torch.autograd.Function):
         seed = grad_out.detach().cpu().numpy().astype(np.float64)
         dp = ctx.state.adjoint(ctx.mask, seed)
         return torch.tensor(dp, dtype=ctx.dtype), None
+
+
+class LiftDragObjective(torch.autograd.Function):
+    """(C_l, C_d) of the final recorded state as a function of the five parameters; backward runs
+    fvlbm_adjoint_lift_drag (the reverse run plus the explicit turn of the lift and drag directions
+    with theta).  problem.lift_drag_ref = (u_ref, chord)."""
+
+    @staticmethod
+    def forward(ctx, params, problem: Problem, u_ref: float, chord: float = 1.0):
+        pv = params.detach().cpu().numpy().astype(np.float64)
+        st = F.State(problem.mesh, problem.with_params(pv), precision=problem.precision, rho=problem.rho,
+                     u=problem.u, k=problem.k, omega=problem.omega)
+        if problem.f0 is not None:
+            st.set_state(problem.f0, problem.k, problem.omega)
+        st.record(problem.n_steps, problem.ckpt_every)
+        cl, cd = st.lift_drag(problem.wall_mask, u_ref, chord)
+        ctx.state, ctx.mask, ctx.ref, ctx.dtype = st, problem.wall_mask, (u_ref, chord), params.dtype
+        problem.last_state = st
+        return torch.tensor([cl, cd], dtype=params.dtype)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        seed = grad_out.detach().cpu().numpy().astype(np.float64)
+        dp, _ = ctx.state.adjoint_lift_drag(ctx.mask, ctx.ref[0], ctx.ref[1], seed)
+        return torch.tensor(dp, dtype=ctx.dtype), None, None, None

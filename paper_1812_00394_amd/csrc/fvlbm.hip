@@ -1749,6 +1749,40 @@ fvlbm_status fvlbm_adjoint_step(fvlbm_state *st, uint64_t wall_group_mask, const
     });
 }
 
+fvlbm_status fvlbm_adjoint_lift_drag(fvlbm_state *st, uint64_t wall_group_mask, double u_ref, double chord,
+                                     const double seed[2], double coeffs[2], double dparams[5]) {
+    return guarded([&] {
+        if (!st || !seed || !dparams) throw Error(FVLBM_EINVAL, "adjoint_lift_drag: NULL argument");
+        if (!(u_ref > 0) || !(chord > 0)) throw Error(FVLBM_EINVAL, "adjoint_lift_drag: u_ref and chord must be positive");
+        if (!st->adj_ws) throw Error(FVLBM_ESTATE, "adjoint_lift_drag: no recorded run (call fvlbm_record first; a step or set_state since then drops it)");
+        // the force of the final (current) state
+        double r[3];
+        if (st->precision == FVLBM_FP64)
+            forces<double>(st, wall_group_mask, r);
+        else
+            forces<float>(st, wall_group_mask, r);
+        if (!std::isfinite(r[0]) || !std::isfinite(r[1])) throw Error(FVLBM_EDIVERGED, "adjoint_lift_drag: non-finite force");
+        // C_l = F . (-sin, cos) / q, C_d = F . (cos, sin) / q with q = rho0 u_ref^2 chord / 2
+        const double c = std::cos(st->par.theta), sn = std::sin(st->par.theta);
+        const double q = 0.5 * st->par.rho0 * u_ref * u_ref * chord;
+        const double cl = (-sn * r[0] + c * r[1]) / q, cd = (c * r[0] + sn * r[1]) / q;
+        if (coeffs) {
+            coeffs[0] = cl;
+            coeffs[1] = cd;
+        }
+        // J = seed . (C_l, C_d): the adjoint of the force, then the explicit turn of the lift and drag
+        // directions with theta, dC_l/dtheta = -C_d and dC_d/dtheta = C_l at fixed force
+        const double sf[3] = {(-seed[0] * sn + seed[1] * c) / q, (seed[0] * c + seed[1] * sn) / q, 0.0};
+        if (st->precision == FVLBM_FP64)
+            adjoint_forces<double>(st, wall_group_mask, sf, dparams);
+        else
+            adjoint_forces<float>(st, wall_group_mask, sf, dparams);
+        dparams[0] += -seed[0] * cd + seed[1] * cl;
+        for (int i = 0; i < 5; ++i)
+            if (!std::isfinite(dparams[i])) throw Error(FVLBM_EDIVERGED, "adjoint_lift_drag: non-finite gradient");
+    });
+}
+
 fvlbm_status fvlbm_adjoint_state(fvlbm_state *st, const double *lam_f, const double *lam_k, const double *lam_w,
                                  double *lam_f0, double *lam_k0, double *lam_w0, double dparams[5]) {
     return guarded([&] {

@@ -56,7 +56,7 @@ EXPORTS = ["fvlbm_mesh_create", "fvlbm_mesh_destroy", "fvlbm_mesh_counts", "fvlb
            "fvlbm_last_error", "fvlbm_mesh_max_dt", "fvlbm_timing", "fvlbm_timing_read",
            "fvlbm_apply_advection_adjoint", "fvlbm_adjoint_bytes", "fvlbm_record", "fvlbm_adjoint_step",
            "fvlbm_adjoint_state", "fvlbm_lift_drag", "fvlbm_step_explicit",
-           "fvlbm_run_to_residual", "fvlbm_totals_noalloc"]
+           "fvlbm_run_to_residual", "fvlbm_totals_noalloc", "fvlbm_adjoint_lift_drag"]
 KERNELS = ["sst_a", "sst_b", "collide1", "grad", "sweep1", "sweep2", "sweep3", "sst", "explicit", "sst_jacobi", "face"]
 
 
@@ -89,6 +89,7 @@ def lib():
     L.fvlbm_forces.argtypes = [P, C.c_uint64, P, P]
     L.fvlbm_lift_drag.argtypes = [P, C.c_uint64, C.c_double, C.c_double, P]
     L.fvlbm_totals_noalloc.argtypes = [P, P]
+    L.fvlbm_adjoint_lift_drag.argtypes = [P, C.c_uint64, C.c_double, C.c_double, P, P, P]
     L.fvlbm_apply_advection.argtypes = [P, P, P]
     L.fvlbm_mesh_max_dt.argtypes = [P, P]
     L.fvlbm_timing.argtypes = [P, I32]
@@ -338,6 +339,16 @@ class State:
         out = np.zeros(5)
         _check(lib().fvlbm_adjoint_step(self.handle, C.c_uint64(group_mask), _ptr(sd), _ptr(out)))
         return out
+
+    def adjoint_lift_drag(self, group_mask, u_ref, chord, seed):
+        """dJ/d(theta, sigma_k1, sigma_w1, beta*, a1) for J = seed . (C_l, C_d) of the final state;
+        returns (gradient, (C_l, C_d))"""
+        sd = _f64(seed, (2,))
+        out = np.zeros(5)
+        co = np.zeros(2)
+        _check(lib().fvlbm_adjoint_lift_drag(self.handle, C.c_uint64(group_mask), float(u_ref), float(chord),
+                                             _ptr(sd), _ptr(co), _ptr(out)))
+        return out, (float(co[0]), float(co[1]))
 
     def adjoint_state(self, lam_f, lam_k=None, lam_w=None):
         n = self.mesh.n_cells
