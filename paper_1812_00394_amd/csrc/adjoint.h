@@ -521,12 +521,16 @@ __global__ void __launch_bounds__(256) k_adv_T1b(Geo<T> g, const T *__restrict__
 // LDS, cell-major: V [Wv][8] mu, Gl [Wg][16] Gbar (x, y interleaved), Mi [Wg][3] (S = 3).
 // Interior edges are summed in straight-line code (an edge without an interior neighbour reads
 // row 0 with weight 0), open-boundary edges after them.
-template <typename T, int S, bool ACC, int EPI>
+// CLIP: the convection was limited by the face-value clip of reading r32, whose per-edge states the
+// forward sweep recorded in clip (StageBufs::clip): an edge whose value was clipped passes its
+// adjoint to the cell whose value it took (from that cell's own edge loop: its own value when the
+// bound was its own), an unclipped one to the upwind reconstruction as without the limiter.
+template <typename T, int S, bool ACC, int EPI, bool CLIP = false>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     k_adv_T_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, const int8_t *__restrict__ rev, int Wv,
                  int Wg, const T *__restrict__ L, T lscale, T *__restrict__ out, const T *__restrict__ f,
                  const T *__restrict__ tau1, T a_dt, double *__restrict__ dth, T rho0, AdjBufs<T> ab,
-                 StepPar<T> p) {
+                 StepPar<T> p, const uint64_t *__restrict__ clip = nullptr) {
     extern __shared__ __align__(16) unsigned char smem[];
     T *V = reinterpret_cast<T *>(smem);
     T *Gl = V + 8 * Wv;
@@ -606,9 +610,11 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
 
     // ---- phase 1: adv_T1 ----
     // weights of the edges whose face value cell x reconstructs: interior edges (mu_x - mu_N) and
-    // outgoing directions of open boundaries (mu_x); gd: the part on g_x itself
+    // outgoing directions of open boundaries (mu_x); gd: the part on g_x itself.  With CLIP, cm holds
+    // x's recorded clip states: a clipped edge puts its weight on g_x when the bound was x's value
+    // (either upwind side), and nothing on x's gradient
     auto t1 = [&](const T m[9], const int *nbs, const int *cols, const T *nx_, const T *ny_, const T *rx_,
-                  const T *ry_, T gd[9], T Gx[9], T Gy[9]) {
+                  const T *ry_, uint64_t cm, T gd[9], T Gx[9], T Gy[9]) {
 #pragma unroll
         for (int a = 0; a < 9; ++a) gd[a] = Gx[a] = Gy[a] = T(0);
         bool bnd = false;
@@ -621,10 +627,20 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
 #pragma unroll
             for (int a = 1; a < 9; ++a) {
                 const T en = T(ex(a)) * mx + T(ey(a)) * my;
-                const T w = en > T(0) ? en * (m[a] - V[r * 8 + (a - 1)]) : T(0);
-                gd[a] += w;
-                Gx[a] += w * rx_[s];
-                Gy[a] += w * ry_[s];
+                if constexpr (CLIP) {
+                    const int bit = 2 * (8 * s + a - 1);
+                    const bool clipped = (cm >> bit) & 1, self = (cm >> (bit + 1)) & 1;
+                    const T wa = en * (m[a] - V[r * 8 + (a - 1)]);
+                    const T wr = (!clipped && en > T(0)) ? wa : T(0);
+                    gd[a] += clipped ? (self ? wa : T(0)) : wr;
+                    Gx[a] += wr * rx_[s];
+                    Gy[a] += wr * ry_[s];
+                } else {
+                    const T w = en > T(0) ? en * (m[a] - V[r * 8 + (a - 1)]) : T(0);
+                    gd[a] += w;
+                    Gx[a] += w * rx_[s];
+                    Gy[a] += w * ry_[s];
+                }
             }
         }
         if (bnd) {
@@ -648,7 +664,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     };
     if (ring1) {
         T gd[9], Gx[9], Gy[9];
-        t1(hmu, hnb, hcol, hnlx, hnly, hrx, hry, gd, Gx, Gy);
+        t1(hmu, hnb, hcol, hnlx, hnly, hrx, hry, CLIP ? clip[rt.cell[x0 + t]] : 0, gd, Gx, Gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             Gl[(kTileCells + t) * 16 + 2 * (a - 1)] = Gx[a];
@@ -657,7 +673,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     }
     T gd[9], Gx[9], Gy[9];
     if (own) {
-        t1(mu, nb, col, nlx, nly, rx, ry, gd, Gx, Gy);
+        t1(mu, nb, col, nlx, nly, rx, ry, CLIP ? clip[c] : 0, gd, Gx, Gy);
 #pragma unroll
         for (int a = 1; a < 9; ++a) {
             Gl[t * 16 + 2 * (a - 1)] = Gx[a];

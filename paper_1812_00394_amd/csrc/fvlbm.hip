@@ -111,6 +111,7 @@ struct fvlbm_state {
     size_t sst_lds_bytes = 0;
     bool want_aux = false;       // the SST launch also stores the aux planes (adjoint recompute)
     void *F_out = nullptr;       // where a step writes f^{n+1} (nullptr: over f^n)
+    uint64_t *clip = nullptr;    // while a recorded step runs with the r32 limiter: its clip states [3][n]
     int held_segs = 0;           // trailing segments of the recorded run whose tapes the segment buffers hold
     int32_t *hptr = nullptr, *hcell = nullptr;
     int32_t *xptr = nullptr, *xn1 = nullptr, *xcell = nullptr;
@@ -592,9 +593,12 @@ void launch_step(fvlbm_state *st) {
     // stage's SST inputs are the first's (the first stage's solve keeps rho and u).
     const bool per_stage = st->sst && st->sst_stages;
     T *tau3 = (T *)st->tau3;
-    const StageBufs<T> b1{X, F, tau, A, Y, nullptr, per_stage ? Mnew : nullptr};
-    const StageBufs<T> b2{Y, F, tau, A, X, nullptr, nullptr, per_stage ? tau3 : nullptr};
-    const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, st->F_out ? (T *)st->F_out : F, Mnew};
+    const size_t nn = (size_t)n;
+    uint64_t *clip = st->clip;
+    const StageBufs<T> b1{X, F, tau, A, Y, nullptr, per_stage ? Mnew : nullptr, nullptr, clip};
+    const StageBufs<T> b2{Y, F, tau, A, X, nullptr, nullptr, per_stage ? tau3 : nullptr, clip ? clip + nn : nullptr};
+    const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, st->F_out ? (T *)st->F_out : F, Mnew, nullptr,
+                          clip ? clip + 2 * nn : nullptr};
     auto sst_stage3 = [&] {
         if (per_stage) launch_sst<T>(st, Mnew, K0, W0, K1, W1, tau3, p);
     };
@@ -858,9 +862,19 @@ void apply_advection(fvlbm_state *st, const double *gin, double *out) {
 
 template <typename T, int S, bool ACC, int EPI>
 void launch_T_ring(fvlbm_state *st, const T *f, const T *tau1, T a_dt, const T *lam, T lscale, T *out, double *dth,
-                   const AdjBufs<T> &ab, const StepPar<T> &p) {
+                   const AdjBufs<T> &ab, const StepPar<T> &p, const uint64_t *clip) {
     const Geo<T> &g = geo_of<T>(st);
     const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+    if constexpr (EPI != 0) {
+        // the stage reverses of a step limited by r32: the edges' recorded clip states
+        if (clip) {
+            k_adv_T_ring<T, S, ACC, EPI, true><<<st->mesh->n_tiles, kTileCells, adj_t_lds<T>(st), st->stream>>>(
+                g, rt, st->lnb, st->rev, st->ring_wv, st->ring_wg, lam, lscale, out, f, tau1, a_dt, dth, T(st->par.rho0),
+                ab, p, clip);
+            return;
+        }
+    }
+    if (clip) throw Error(FVLBM_ESTATE, "adv_transpose: clip states only in a stage reverse");
     k_adv_T_ring<T, S, ACC, EPI><<<st->mesh->n_tiles, kTileCells, adj_t_lds<T>(st), st->stream>>>(
         g, rt, st->lnb, st->rev, st->ring_wv, st->ring_wg, lam, lscale, out, f, tau1, a_dt, dth, T(st->par.rho0), ab, p);
 }
@@ -872,7 +886,8 @@ void launch_T_ring(fvlbm_state *st, const T *f, const T *tau1, T a_dt, const T *
 // Uses st->G for the gradient adjoints.
 template <typename T>
 void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T lscale, T *out, double *dth, bool acc,
-                   int epi = 0, const AdjBufs<T> &ab = AdjBufs<T>{}, const StepPar<T> &p = StepPar<T>{}) {
+                   int epi = 0, const AdjBufs<T> &ab = AdjBufs<T>{}, const StepPar<T> &p = StepPar<T>{},
+                   const uint64_t *clip = nullptr) {
     const T a_dt = T(st->par.dt / 4.0);
     const Geo<T> &g = geo_of<T>(st);
     const int nbk = blocks_for(g.n);
@@ -886,7 +901,7 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
     if (st->ring) {
         // one launch: the boundary cells' ghost parts are fused into the ring kernel
         const bool s3 = st->ring_s == 3;
-#define FVLBM_T_RING(S_, ACC_, EPI_) launch_T_ring<T, S_, ACC_, EPI_>(st, f, tau1, a_dt, lam, lscale, out, dth, ab, p)
+#define FVLBM_T_RING(S_, ACC_, EPI_) launch_T_ring<T, S_, ACC_, EPI_>(st, f, tau1, a_dt, lam, lscale, out, dth, ab, p, clip)
         if (!acc && epi == 3)
             s3 ? FVLBM_T_RING(3, false, 3) : FVLBM_T_RING(4, false, 3);
         else if (!acc)
@@ -900,6 +915,7 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
 #undef FVLBM_T_RING
         return;
     }
+    if (clip) throw Error(FVLBM_ESTATE, "adv_transpose: the limited convection's adjoint needs the ring-tiled sweep");
     if (!acc) k_fill<T><<<blocks_for(9 * (size_t)g.n), kBlock, 0, s>>>(9 * g.n, out, T(0));
     k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, (T *)st->G);
     if (g.nb > 0)
@@ -950,6 +966,7 @@ template <typename T>
 struct AdjLayout {
     T *ckpt, *seg, *stg, *lF, *lF2, *lK, *lW, *lK2, *lW2, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
     T *seg2, *stg2;     // a second set of segment buffers when the run has more than one segment
+    uint64_t *clip, *clip2;   // per step of a segment: the r32 clip states of its three sweeps [3][n]
     double *pbar;
     size_t state_len;
     size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [15][n]
@@ -964,6 +981,7 @@ AdjLayout<T> segment_set(const AdjLayout<T> &L, int k) {
     if ((k & 1) && L.seg2) {
         r.seg = L.seg2;
         r.stg = L.stg2;
+        r.clip = L.clip2;
     }
     return r;
 }
@@ -991,10 +1009,13 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, bool over
     L.seg = cv.take<T>((size_t)(ckpt + 1) * sl);
     L.stage_len = 43 * (size_t)n;
     L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
+    L.clip = cv.take<uint64_t>((size_t)ckpt * 3 * n);
     L.seg2 = L.stg2 = nullptr;
+    L.clip2 = nullptr;
     if (overlap && nck > 2) {
         L.seg2 = cv.take<T>((size_t)(ckpt + 1) * sl);
         L.stg2 = cv.take<T>((size_t)ckpt * L.stage_len);
+        L.clip2 = cv.take<uint64_t>((size_t)ckpt * 3 * n);
     }
     L.lF = cv.take<T>(9 * (size_t)n);
     L.lF2 = cv.take<T>(9 * (size_t)n);
@@ -1051,13 +1072,15 @@ void load_state(fvlbm_state *st, const T *slot) {
 template <typename T>
 struct StageSlot {
     T *Y, *X, *A, *tau, *aux;
+    uint64_t *clip;   // [3][n]: the clip states of sweeps 1, 2, 3 (face-value limiter of r32)
 };
 
 template <typename T>
 StageSlot<T> stage_slot(const fvlbm_state *st, const AdjLayout<T> &L, int i) {
     const size_t n = st->n_cells;
     T *b = L.stg + (size_t)i * L.stage_len;
-    return StageSlot<T>{b, b + 9 * n, b + 18 * n, st->sst ? b + 27 * n : (T *)st->tau, b + 28 * n};
+    return StageSlot<T>{b, b + 9 * n, b + 18 * n, st->sst ? b + 27 * n : (T *)st->tau, b + 28 * n,
+                        L.clip + (size_t)i * 3 * n};
 }
 
 // Step j of a segment, in place in the segment buffers: reads the state in segment slot j, writes
@@ -1075,6 +1098,7 @@ void step_seg(fvlbm_state *st, const AdjLayout<T> &L, int j) {
     st->X = ss.X;
     st->Y = ss.Y;
     st->A = ss.A;
+    st->clip = st->par.limiter == 1 ? ss.clip : nullptr;
     if (st->sst) {
         st->K[st->cur_kw] = in + 9 * n;
         st->K[st->cur_kw ^ 1] = out + 9 * n;
@@ -1087,6 +1111,7 @@ void step_seg(fvlbm_state *st, const AdjLayout<T> &L, int j) {
     launch_step<T>(st);
     st->F = F;
     st->F_out = nullptr;
+    st->clip = nullptr;
     st->X = X;
     st->Y = Y;
     st->A = A;
@@ -1153,11 +1178,13 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     AdjBufs<T> b{fn, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lF2, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
     // stage 3: Ga3 enters f^{n+1} with weight dt/3, its transpose is applied to dt/3 lF; then the
     // reverse of the combination and of the third stage
-    adv_transpose<T>(st, ss.X, nullptr, L.lF, p.dt / T(3), L.lf3, L.pbar, false, 3, b, p);
+    // with the face-value limiter of r32: the clip states the forward sweeps recorded
+    const bool lim = st->par.limiter == 1;
+    adv_transpose<T>(st, ss.X, nullptr, L.lF, p.dt / T(3), L.lf3, L.pbar, false, 3, b, p, lim ? ss.clip + 2 * (size_t)n : nullptr);
     // stage 2: transpose at f^(2), then its stage reverse (the Ga1 adjoint goes to lg1)
-    adv_transpose<T>(st, ss.Y, nullptr, L.lam, T(1), L.lf2, L.pbar, true, 2, b, p);
+    adv_transpose<T>(st, ss.Y, nullptr, L.lam, T(1), L.lf2, L.pbar, true, 2, b, p, lim ? ss.clip + (size_t)n : nullptr);
     // stage 1: transpose at f^(1), formed from f^n, then its stage reverse
-    adv_transpose<T>(st, fn, ss.tau, L.lg1, T(1), L.lf1, L.pbar, true, 1, b, p);
+    adv_transpose<T>(st, fn, ss.tau, L.lg1, T(1), L.lf1, L.pbar, true, 1, b, p, lim ? ss.clip : nullptr);
     if (st->sst && st->ring) {
         // one ring-tiled launch
         SstAdj sa{st->bzg, L.pbar};
@@ -1708,7 +1735,9 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
     return guarded([&] {
         if (!st || !workspace) throw Error(FVLBM_EINVAL, "record: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
-        if (st->par.limiter) throw Error(FVLBM_ESTATE, "record: the limited convection has no adjoint here");
+        if (st->par.limiter == 2) throw Error(FVLBM_ESTATE, "record: the gradient limiter (limiter 2) has no adjoint here");
+        if (st->par.limiter == 1 && !st->ring)
+            throw Error(FVLBM_ESTATE, "record: the face-value limiter's adjoint needs the ring-tiled sweep");
         if (st->sst_stages) throw Error(FVLBM_ESTATE, "record: the per-stage SST coupling has no adjoint here");
         if (st->sst && st->par.sst_sweeps > 0) throw Error(FVLBM_ESTATE, "record: the implicit SST variant has no adjoint here");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");

@@ -217,6 +217,10 @@ struct StageBufs {
     const T *src, *F_in, *tau;
     T *A, *out, *F_out, *M;
     const T *tau3;
+    // with the face-value limiter of r32, while a step is recorded for the adjoint: per cell the
+    // state of every interior edge's clip, 2 bits per edge slot s and direction a at bit
+    // 2 (8 s + a - 1): clipped, and (if clipped) the bound is the cell's own value
+    uint64_t *clip;
 };
 
 template <typename T, int J>
@@ -1016,6 +1020,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
     for (int a = 1; a < 9; ++a) acc[a] = T(0);
     bool bnd = false;
+    uint64_t cm = 0;   // clip states (LIM == 1, recorded steps)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const bool in = nb[s] >= 0;
@@ -1030,7 +1035,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             const T up_n = vn + Gl[grow<T>(loc, 2 * (a - 1))] * qx[s] + Gl[grow<T>(loc, 2 * (a - 1) + 1)] * qy[s];
             const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
             T val = end >= T(0) ? up_c : up_n;
-            if constexpr (LIM == 1) val = clip_between(val, gc[a], vn);
+            if constexpr (LIM == 1) {
+                const T lim = clip_between(val, gc[a], vn);
+                const bool clipped = in && lim != val;
+                cm |= (uint64_t)clipped << (2 * (8 * s + a - 1));
+                cm |= (uint64_t)(clipped && lim == gc[a]) << (2 * (8 * s + a - 1) + 1);
+                val = lim;
+            }
             acc[a] += end * val;
         }
         // one edge's LDS reads in flight at a time (bounds the registers they occupy)
@@ -1059,6 +1070,9 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
                 acc[a] += end * val;
             }
         }
+    }
+    if constexpr (LIM == 1) {
+        if (b.clip) b.clip[c] = cm;
     }
     T ga[9];
     ga[0] = T(0);

@@ -445,3 +445,80 @@ def test_lift_drag_adjoint_against_complex_step(F, precision):
         st.record(N, ckpt_every=2)
         g, coeffs = st.adjoint_lift_drag(1, U, 1.0, s)
         check_fp32_gradient(g, ref)
+
+
+
+@pytest.mark.parametrize("name", ["duct_laminar", "naca_sst"])
+def test_limited_adjoint_against_complex_step(F, name):
+    """The adjoint through the face-value limiter of reading r32 (ring path): the forward sweeps
+    record which edges were clipped and to which cell's value, the transposed convection routes each
+    clipped edge's adjoint to that value.  Dot product of the adjoint of a 3-step recorded run
+    (checkpoint every 2) with the oracle's complex-step derivative along a random direction, within
+    1e-9, and the parameter gradient within 1e-8; on the O-mesh the lift/drag adjoint as well.  The
+    case must clip: the limited oracle run differs from the unlimited one."""
+    say("limited adjoint", name)
+    m, p, orc, f0, k0, w0, sst = _run_case(name, seed=97)
+    p = dict(p, limiter=1)
+    n = orc.g.n
+    N = 3
+    f_lim, _, _ = O.Oracle(m, p).run(f0, k0, w0, N)
+    f_pln, _, _ = O.Oracle(m, dict(p, limiter=0)).run(f0, k0, w0, N)
+    change = np.abs(f_lim - f_pln).max() / np.abs(f_pln - O.WT[:, None]).max()
+    print("effect of the limiter on the state after", N, "steps:", change)
+    assert change > 1e-6, change
+    rng = np.random.default_rng(98)
+    lf = rng.standard_normal((9, n))
+    lk = rng.standard_normal(n) * 1e3 if sst else None
+    lw = rng.standard_normal(n) if sst else None
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k0, omega=w0)
+    st.set_state(f0, k0, w0)
+    st.record(N, ckpt_every=2)
+    lf0, lk0, lw0, dp = st.adjoint_state(lf, lk, lw)
+    vf = rng.standard_normal((9, n)) * O.WT[:, None] * 1e-3
+    vk = rng.standard_normal(n) * 1e-5 if sst else None
+    vw = rng.standard_normal(n) * 1e-2 if sst else None
+    o = O.Oracle(m, p)
+    if sst:
+        fN, kN, wN = o.run(f0 + 1j * H * vf, k0 + 1j * H * vk, w0 + 1j * H * vw, N)
+        rhs = (np.sum(lf * np.imag(fN)) + np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))) / H
+        lhs = np.sum(lf0 * vf) + np.sum(lk0 * vk) + np.sum(lw0 * vw)
+    else:
+        fN, _, _ = o.run(f0 + 1j * H * vf, None, None, N)
+        rhs = np.sum(lf * np.imag(fN)) / H
+        lhs = np.sum(lf0 * vf)
+    print("dot products", lhs, rhs)
+    assert abs(lhs - rhs) <= 1e-9 * abs(rhs), (lhs, rhs)
+    # the parameter gradient of lambda . state against the complex step of each parameter
+    keys = PARAMS if sst else PARAMS[:1]
+    ref = []
+    for key in keys:
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        oc = O.Oracle(m, pc)
+        fN, kN, wN = oc.run(f0.astype(complex), k0.astype(complex) if sst else None, w0.astype(complex) if sst else None, N)
+        v = np.sum(lf * np.imag(fN))
+        if sst:
+            v += np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))
+        ref.append(v / H)
+    ref = np.array(ref)
+    scale = np.abs(ref).max()
+    print("parameter gradient", dp[:len(keys)], "complex step", ref)
+    assert np.all(np.abs(dp[:len(keys)] - ref) <= 1e-8 * np.maximum(np.abs(ref), 1e-6 * scale)), (dp, ref)
+    if name == "naca_sst":
+        U = 0.05
+        s_ = np.array([0.8, -1.7])
+        ld_ref = []
+        for key in PARAMS:
+            pc = dict(p)
+            pc[key] = p[key] + 1j * H
+            oc = O.Oracle(m, pc)
+            fN, _, _ = oc.run(f0.astype(complex), k0.astype(complex), w0.astype(complex), N)
+            ld_ref.append(np.imag(s_ @ oc.lift_drag(fN, 1, U)) / H)
+        ld_ref = np.array(ld_ref)
+        st2 = F.State(F.Mesh(m), p, precision="fp64", k=k0, omega=w0)
+        st2.set_state(f0, k0, w0)
+        st2.record(N, ckpt_every=2)
+        g, _ = st2.adjoint_lift_drag(1, U, 1.0, s_)
+        rel = np.abs(g - ld_ref) / np.abs(ld_ref)
+        print("limited lift/drag gradient", g, "complex step", ld_ref, "relative error", rel)
+        assert np.all(rel <= 1e-8), rel
