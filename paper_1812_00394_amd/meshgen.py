@@ -209,7 +209,7 @@ def _graded(a, b, d_end, ratio, d_core, both=True):
     return x
 
 
-def backstep(h=1.0, y1=5.4e-4, ratio=1.12, core=0.035, dx_core=0.07, dx_corner=0.004,
+def backstep(h=1.0, y1=5.4e-4, ratio=1.12, core=0.035, dx_core=0.058, dx_corner=0.004,
              wall_layers=24, jitter=0.15, seed=2):
     rng = _rng(seed)
     # y: lower block [0, h] and upper block [h, 2h], clustered at 0, h and 2h.
@@ -231,8 +231,11 @@ def backstep(h=1.0, y1=5.4e-4, ratio=1.12, core=0.035, dx_core=0.07, dx_corner=0
     J, I = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
     rows_to_wall = np.minimum(J, ny - 1 - J)               # bottom / top walls
     rows_to_wall = np.where(I < i0, np.minimum(ny - 1 - J, J - jh), rows_to_wall)  # inlet channel
-    cols_to_step = np.where(J < jh, np.abs(I - i0), 10 ** 6)
-    split = (rows_to_wall >= wall_layers) & (cols_to_step >= wall_layers) & keep
+    # the grid lines clustered like walls (y = h downstream of the step, x = 0 above it) keep quads
+    # as well: their thin cells cut in two would be sliver triangles
+    rows_to_line = np.where(I >= i0, np.where(J >= jh, J - jh, jh - 1 - J), 10 ** 6)
+    cols_to_step = np.where(I >= i0, I - i0, i0 - 1 - I)
+    split = (rows_to_wall >= wall_layers) & (rows_to_line >= wall_layers) & (cols_to_step >= wall_layers) & keep
     nodes = lattice_nodes(xs, ys)
     cells = _lattice_cells(nx, ny, split, rng, keep=keep)
     # jitter only the nodes surrounded by triangle cells (core), by a fraction of local spacing

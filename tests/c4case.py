@@ -2,7 +2,7 @@
 workload: 400 IMEX steps with a checkpoint every 20).
 
 The piece: the cells within R edge rings of the wall cell nearest (h, 0.01 h) behind the step of the
-122,956-cell backstep mesh, R the least giving at least 800 cells.  Its original edges keep their
+122,876-cell backstep mesh, R the least giving at least 800 cells.  Its original edges keep their
 groups (the walls); the edges cut from the rest of the mesh form one far-field group, so that the
 inflow angle (which turns far-field and inlet velocities) acts on the piece.  The initial fields are a
 reversed near-wall shear stream with seeded noise, uniform-ish k and omega.  Plain numpy: mesh

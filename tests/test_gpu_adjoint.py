@@ -278,7 +278,7 @@ def test_autograd_function_and_fp32(F, amp):
 
 @pytest.mark.parametrize("order", ["morton", "tiles"])
 def test_wide_halo_ring_adjoint_fp32(F, order):
-    """The ring adjoint kernels with ring-2 cells beyond one per thread (the 16,844-cell backstep of
+    """The ring adjoint kernels with ring-2 cells beyond one per thread (the 13,196-cell backstep of
     the forward wide-halo test, FP32-dev on the ring path): the autograd gradient of the force
     objective against the oracle's complex step, to the gate of check_fp32_gradient."""
     say("wide-halo backstep adjoint, fp32dev ring", order)

@@ -127,7 +127,7 @@ def test_fullsize_sampled_parity_implicit_sst(F, full):
 
 @pytest.mark.timeout(900)
 def test_backstep_fullsize_parity(F):
-    """The backward-facing step the benchmark times (122,956 hybrid cells, SST, about 34 tau0) on the
+    """The backward-facing step the benchmark times (122,876 hybrid cells, SST, about 34 tau0) on the
     whole mesh, which the oracle can step: one step in FP64 and FP32-deviation storage on the ring
     path (its tiles have up to 298 ring-2 cells) against the oracle on every cell, and the FP64
     adjoint of two recorded steps with a checkpoint every step (the next segment recomputed on the

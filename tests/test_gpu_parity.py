@@ -564,8 +564,9 @@ def test_sst_implicit_per_stage_step_parity(F, monkeypatch):
 
 
 def _wide_halo_backstep():
-    """A backstep (16,844 cells) whose stretched wall cells give Morton tiles with up to 473
-    ring-2 cells (tests/test_host_library.py checks the count): more than one per thread."""
+    """A backstep (13,196 cells) whose stretched wall cells give Morton tiles with more than 256
+    cells in ring 1 and ring 2 together (tests/test_host_library.py checks the count): more than
+    one per thread."""
     return mg.backstep(core=0.3, dx_core=0.6, dx_corner=0.02, y1=1e-3)
 
 
