@@ -240,3 +240,73 @@ def test_airfoil_fullsize_parity(F):
             say("fp32dev errors: du/U", du, "dk", dk, "dw", dw)
             assert du < 2e-6 and dk < 2e-6 and dw < 2e-6, (du, dk, dw)
         del st
+
+
+def _compare_run(F, M, p, orc, f0, k0, w0, steps, gates, u_ref, label, rho=None, u=None):
+    """Both precisions, `steps` steps from (f0, k0, w0) on the ring path, against the oracle's run on
+    every cell.  gates: (FP64 f, FP64 k / omega / nu_t, FP32-dev u / u_ref, FP32-dev k / omega)."""
+    say(label, "oracle run of", steps, "steps")
+    fo, ko, wo = orc.run(f0, k0, w0, steps)
+    nuto = orc.last_nut
+    _, uxo, uyo, _ = orc.macro(fo)
+    for precision in ("fp64", "fp32dev"):
+        say(label, steps, "steps on the GPU,", precision)
+        st = F.State(M, p, precision=precision, k=k0, omega=w0)
+        st.set_state(f0, k0, w0)
+        st.step(steps)
+        mo = st.moments()
+        if precision == "fp64":
+            ef = np.abs(st.get_f() - fo).max() / np.abs(fo - O.WT[:, None]).max()
+            ek = [np.abs(mo[key] - ref).max() / np.abs(ref).max()
+                  for key, ref in (("k", ko), ("omega", wo), ("nu_t", nuto))]
+            print(label, "fp64 after", steps, "steps: f", ef, "k, omega, nu_t", ek)
+            assert ef < gates[0] and max(ek) < gates[1], (ef, ek)
+        else:
+            du = max(np.abs(mo["u"][:, 0] - uxo).max(), np.abs(mo["u"][:, 1] - uyo).max()) / u_ref
+            dk = np.abs(mo["k"] - ko).max() / np.abs(ko).max()
+            dw = np.abs(mo["omega"] - wo).max() / np.abs(wo).max()
+            print(label, "fp32dev after", steps, "steps: du/U", du, "dk", dk, "dw", dw)
+            assert du < gates[2] and dk < gates[3] and dw < gates[3], (du, dk, dw)
+        del st
+
+
+@pytest.mark.timeout(900)
+def test_backstep_ten_steps_whole_mesh(F):
+    """The backstep the benchmark times (122,876 cells, SST, 34 tau0), from the seeded developed state
+    of test_backstep_fullsize_parity, 10 steps on the ring path against the oracle on every cell, at
+    ten times the one-step gates: FP64 1e-11 of max |f - w rho0| and 1e-10 for k, omega, nu_t;
+    FP32-deviation 2e-5 of U and 2e-5 relative for k, omega."""
+    mesh, flow, init, dt_frac = bench.workload("backstep")
+    M = F.Mesh(mesh, order="tiles")
+    p = O.default_params(**dict(flow, dt=min(flow["dt"], dt_frac * M.max_dt())))
+    orc = O.Oracle(mesh, p)
+    n = orc.g.n
+    rng = np.random.default_rng(12)
+    x, y = orc.g.xc[:, 0], orc.g.xc[:, 1]
+    ux = 0.04 + 0.01 * np.sin(0.5 * x) * np.cos(3 * y) + 0.002 * rng.standard_normal(n)
+    uy = 0.004 * np.sin(2 * y) + 0.002 * rng.standard_normal(n)
+    f0 = O.feq(1 + 0.001 * rng.standard_normal(n), ux, uy) + 1e-5 * O.WT[:, None] * rng.standard_normal((9, n))
+    k0 = 1e-6 * (1 + 0.5 * rng.random(n))
+    w0 = 1e-2 * (1 + 0.5 * rng.random(n))
+    _compare_run(F, M, p, orc, f0, k0, w0, 10, (1e-11, 1e-10, 2e-5, 2e-5), 0.05, "backstep")
+
+
+@pytest.mark.timeout(900)
+def test_airfoil_ten_steps_whole_mesh(F):
+    """The airfoil the benchmark times (196,608 quads, Re 6e6, 10 degrees, 74 tau0, limiter r32,
+    developed near-wall start), 10 steps on the ring path against the oracle on every cell, at ten
+    times the one-step gates (as test_backstep_ten_steps_whole_mesh)."""
+    m = mg.naca_omesh()
+    M = F.Mesh(m, order="tiles")
+    n = M.n_cells
+    Uinf, c, Re, alpha = 0.05, 1.0, 6e6, np.deg2rad(10.0)
+    nu = Uinf * c / Re
+    kinf, winf = 1e-3 * Uinf * Uinf / Re, 5 * Uinf / c
+    p = O.default_params(nu=nu, dt=min(180 * 3 * nu, 0.9 * M.max_dt()), sst=True, theta=alpha, limiter=1,
+                         group_u=[[0, 0], [Uinf, 0]], group_rho=[1, 1], group_k=[0, kinf], group_w=[0, winf])
+    orc = O.Oracle(m, p)
+    wd = orc.g.wall_dist
+    fac = np.minimum(1.0, (wd / 0.01) ** (1 / 7))
+    f0, k0, w0 = orc.init_state(np.ones(n), Uinf * np.cos(alpha) * fac, Uinf * np.sin(alpha) * fac,
+                                np.full(n, kinf), np.maximum(winf, 6 * nu / (0.075 * wd ** 2)))
+    _compare_run(F, M, p, orc, f0, k0, w0, 10, (1e-11, 1e-10, 2e-5, 2e-5), Uinf, "airfoil")

@@ -113,3 +113,34 @@ def test_cavity_kinetic_energy_converges_under_refinement(F):
     print("kinetic energy", E)
     assert E[0] < E[1] < E[2]
     assert (E[1] - E[0]) > 1.8 * (E[2] - E[1])
+
+
+@pytest.mark.timeout(300)
+def test_laminar_step_with_gradient_limiter_runs_to_a_developed_state(F):
+    """The laminar backward-facing step (Re_h 100 on the step height, u_in 0.05, from rest) on the
+    coarse step mesh, whose sliver triangles give the plain reconstruction a growing mode (the
+    unlimited run diverges, tests/test_oracle_pins.py), with the gradient limiter of reading r35:
+    the run reaches a velocity residual of 1e-5 within 400,000 steps and stays bounded; from that
+    developed state one GPU step equals one oracle step (FP64, 1e-12).  The residual levels off near
+    1e-6 beyond that, with a slow density oscillation between inlet and outlet: the paper reports
+    the same for its step (the inlet and outlet conditions do not balance the mass in the channel)."""
+    say("laminar step, r35, run to residual 1e-5")
+    m = mg.backstep(core=0.35, dx_core=0.7, y1=1.5e-2, dx_corner=0.08, wall_layers=2)
+    M = F.Mesh(m)
+    n = M.n_cells
+    U = 0.05
+    dt = 0.5 * M.max_dt()
+    p = O.default_params(nu=U / 100, dt=dt, limiter=2, group_u=[[0, 0], [U, 0], [0, 0]], group_rho=[1, 1, 1])
+    st = F.State(M, p, precision="fp64", rho=np.ones(n), u=np.zeros((n, 2)))
+    steps, r = st.run_to_residual(1e-5, 400_000, check_every=10_000)
+    mo = st.moments()
+    print("steps", steps, "residual", r, "rho range", mo["rho"].min(), mo["rho"].max(), "max |u|", np.abs(mo["u"]).max())
+    assert r < 1e-5, (steps, r)
+    assert 0.98 < mo["rho"].min() and mo["rho"].max() < 1.05 and np.abs(mo["u"]).max() < 2 * U
+    f = st.get_f()
+    orc = O.Oracle(m, p)
+    fo, _, _ = orc.step(f)
+    st.step(1)
+    err = np.abs(st.get_f() - fo).max() / np.abs(fo - O.WT[:, None]).max()
+    print("one step from the developed state against the oracle:", err)
+    assert err < 1e-12, err
