@@ -1,0 +1,143 @@
+"""Long runs of the two full-size workloads against stored oracle runs (tests/golden/longrun_*.json,
+written by tests/golden/make_longrun_fixtures.py, which calls only the oracle and the seeded mesh
+generator): the backward-facing step from rest (Re_h 3.6e4, SST, 2000 steps) and the airfoil (Re 6e6,
+10 degrees, SST, face-value limiter of reading r32, developed near-wall start, 3000 steps).  At
+every stored checkpoint the GPU state at the sampled cells (anywhere, at the walls and where the
+flow starts) is compared with the oracle's, in FP64 and in FP32-deviation storage, as are the wall
+force and, for the airfoil, the lift and drag coefficients.
+
+Gates (per checkpoint, after N steps), on the scales rounding acts on: FP64 f within 2e-14 N rho0
+(f itself is O(w rho0), and from rest its deviation from w rho0 is small), k, omega and nu_t within
+1e-12 N of their sample maxima, the wall force within 1e-14 N of p0 times the wall length (it sums
+pressures of O(p0) over the wall, which cancel to a small net force); FP32-deviation u within
+1e-6 N of the reference speed, k and omega within 1e-6 N relative (the FP32 differences grow about
+linearly: 1.3e-6, 7.7e-6 and 3.4e-5 of U on the airfoil after 10, 100 and 500 steps),
+the wall force within 2e-7 N of p0 times the wall length; lift and drag coefficients within 1e-11 N
+(FP64) and 1e-3 (FP32) relative.  Every checkpoint is compared and printed before the gates are
+applied, so a failure shows how the differences grew."""
+import hashlib
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fvlbm_oracle as O
+from paper_1812_00394_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1812_00394_amd import fvlbm
+    fvlbm.lib()
+    return fvlbm
+
+
+def _mesh_sha(m):
+    h = hashlib.sha256()
+    for key in ("nodes", "cell_ptr", "cell_nodes", "bface_nodes", "bface_group", "group_kind"):
+        h.update(np.ascontiguousarray(m[key]).tobytes())
+    return h.hexdigest()
+
+
+def _load(name):
+    path = os.path.join(GOLDEN, f"longrun_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"no stored run {path}")
+    return json.load(open(path))
+
+
+def _params(d):
+    return {k: (np.asarray(v) if isinstance(v, list) else v) for k, v in d.items()}
+
+
+def _initial(name, M, p):
+    """The initial state of each stored run, from the same recipe (rho, u, k, omega per cell)."""
+    n = M.n_cells
+    if name == "backstep":
+        return np.ones(n), np.zeros((n, 2)), np.full(n, 1e-6), np.full(n, 1e-2), 0.05
+    _, _, wd = M.geometry()
+    Uinf, c, Re, alpha = 0.05, 1.0, 6e6, np.deg2rad(10.0)
+    nu = Uinf * c / Re
+    assert abs(p["nu"] - nu) <= 1e-15 * nu and abs(p["theta"] - alpha) < 1e-15
+    kinf, winf = 1e-3 * Uinf * Uinf / Re, 5 * Uinf / c
+    fac = np.minimum(1.0, (wd / 0.01) ** (1 / 7))
+    u = np.stack([Uinf * np.cos(alpha) * fac, Uinf * np.sin(alpha) * fac], axis=1)
+    return np.ones(n), u, np.full(n, kinf), np.maximum(winf, 6 * nu / (0.075 * wd ** 2)), Uinf
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name", ["backstep", "airfoil"])
+def test_long_run_against_stored_oracle_run(F, name):
+    d = _load(name)
+    m = mg.backstep() if name == "backstep" else mg.naca_omesh()
+    assert _mesh_sha(m) == d["mesh_sha256"], "the mesh generator no longer makes the stored run's mesh"
+    M = F.Mesh(m, order="tiles")
+    assert M.n_cells == d["n_cells"]
+    p = _params(d["params"])
+    rho, u, k, w, u_ref = _initial(name, M, p)
+    cells = np.asarray(d["cells"])
+    cps = sorted((int(s), rec) for s, rec in d["checkpoints"].items())
+    assert cps, "no checkpoint stored"
+    mask, ld = d["wall_mask"], d["lift_drag_ref"]
+    force_scale = p["rho0"] / 3.0 * _wall_length(m, mask)
+    fails = []
+    for precision in ("fp64", "fp32dev"):
+        st = F.State(M, p, precision=precision, rho=rho, u=u, k=k, omega=w)
+        done = 0
+        for steps, rec in cps:
+            assert rec["finite"]
+            say(name, precision, "to step", steps)
+            st.step(steps - done)
+            done = steps
+            mo = st.moments()
+            fo = np.asarray(rec["f"])
+            ko, wo, nuto = (np.asarray(rec[key]) for key in ("k", "omega", "nu_t"))
+            Fg, _ = st.forces(mask)
+            eF = np.abs(Fg - np.asarray(rec["force"])).max() / force_scale
+            if precision == "fp64":
+                ef = np.abs(st.get_f()[:, cells] - fo).max() / p["rho0"]
+                ek = [np.abs(mo[key][cells] - ref).max() / np.abs(ref).max()
+                      for key, ref in (("k", ko), ("omega", wo), ("nu_t", nuto))]
+                say(name, "fp64 step", steps, "f", ef, "k, omega, nu_t", ek, "force", eF)
+                if not (ef < 2e-14 * steps and max(ek) < 1e-12 * steps and eF < 1e-14 * steps):
+                    fails.append((precision, steps, ef, ek, eF))
+            else:
+                rho_o, jxo, jyo = O.moments(fo)
+                uxo, uyo = jxo / rho_o, jyo / rho_o
+                du = max(np.abs(mo["u"][cells, 0] - uxo).max(), np.abs(mo["u"][cells, 1] - uyo).max()) / u_ref
+                dk = np.abs(mo["k"][cells] - ko).max() / np.abs(ko).max()
+                dw = np.abs(mo["omega"][cells] - wo).max() / np.abs(wo).max()
+                gate = 1e-6 * steps
+                say(name, "fp32dev step", steps, "du/U", du, "dk", dk, "dw", dw, "force", eF)
+                if not (du < gate and dk < gate and dw < gate and eF < 2e-7 * steps):
+                    fails.append((precision, steps, du, dk, dw, eF))
+            if ld:
+                cl = st.lift_drag(mask, ld[0], ld[1])
+                ref = np.asarray(rec["lift_drag"])
+                e = np.abs(cl - ref).max() / np.abs(ref).max()
+                say(name, precision, "step", steps, "drag, lift", cl, "oracle", ref, "error", e)
+                if not e < (1e-11 * steps if precision == "fp64" else 1e-3):
+                    fails.append((precision, steps, "lift/drag", e))
+        del st
+    assert not fails, fails
+
+
+def _wall_length(m, mask):
+    """Total length of the boundary edges in the groups of `mask`."""
+    x = np.asarray(m["nodes"])
+    e = np.asarray(m["bface_nodes"])
+    sel = ((mask >> np.asarray(m["bface_group"])) & 1).astype(bool)
+    return float(np.linalg.norm(x[e[sel, 1]] - x[e[sel, 0]], axis=1).sum())
