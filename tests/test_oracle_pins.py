@@ -702,6 +702,57 @@ def test_sst_manufactured_diffusion():
     np.testing.assert_allclose(w1[cells], ew[cells], rtol=1e-11)
 
 
+def _sheared_periodic(nx, ny, h, s):
+    """Periodic parallelogram cells spanned by a = (h, 0) and b = (s h, h): the uniform quad mesh
+    sheared by x -> x + s y (its top/bottom periodic shift becomes (s Ly, Ly))."""
+    m = mg.rectangle(nx, ny, Lx=nx * h, Ly=ny * h, kind="periodic", jitter=0.0, split="none")
+    m = dict(m)
+    nodes = m["nodes"].copy()
+    nodes[:, 0] += s * nodes[:, 1]
+    m["nodes"] = nodes
+    sh = m["periodic_shift"].copy()
+    sh[2] = (s * ny * h, ny * h)
+    sh[3] = (-s * ny * h, -ny * h)
+    m["periodic_shift"] = sh
+    return m
+
+
+@pytest.mark.parametrize("s", [0.6, 1.5])
+def test_sst_two_point_diffusion_on_sheared_cells(s):
+    """Reading r30 on skewed cells: the diffusive flux across a face is Gamma (phi_N - phi_c) / |d|
+    times d^.n times the face length, d the centroid offset.  On parallelogram cells a = (h, 0),
+    b = (s h, h) the offset across the slanted faces is a, where d^.n l = h, and across the
+    horizontal faces it is b, where d^.n l / |d| = 1 / (1 + s^2); so with uniform Gamma = nu the
+    update of k is, by hand,
+        k1 = (k + dt nu / h^2 [(d_a^2 k) + (d_b^2 k) / (1 + s^2)]) / (1 + dt beta* w),
+    d_a^2, d_b^2 the second differences along the two lattice directions.  A Fourier mode of the
+    lattice indices (p, q) is an eigenvector: d_a^2 -> 2 (cos(2 pi p / nx) - 1), d_b^2 likewise.
+    No flow (no convection, no production), uniform omega (no cross-diffusion), no wall (F1 = 0,
+    set 2), k so small that nu_t is 2e-14 of nu.  Using n for d^, or dropping d^.n, changes the
+    1 / (1 + s^2) weight (and the slanted faces' unit weight) and fails this pin."""
+    nx, ny, h = 12, 10, 0.1
+    m = _sheared_periodic(nx, ny, h, s)
+    nu, dt, w0 = 1e-2, 0.05, 0.5
+    orc = O.Oracle(m, O.default_params(nu=nu, dt=dt, sst=True))
+    G = orc.g
+    np.testing.assert_allclose(G.area, h * h, rtol=1e-13)
+    y = G.xc[:, 1]
+    i = np.rint((G.xc[:, 0] - s * y) / h - 0.5).astype(int)
+    j = np.rint(y / h - 0.5).astype(int)
+    assert sorted(zip(i.tolist(), j.tolist())) == [(a, b) for a in range(nx) for b in range(ny)]
+    p, q = 2, 3
+    th = 2 * np.pi * (p * i / nx + q * j / ny)
+    k0, eps = 1e-16, 3e-17
+    k = k0 + eps * np.cos(th)
+    n = G.n
+    k1, w1, _, _ = orc.sst_update(np.ones(n), np.zeros(n), np.zeros(n), k, np.full(n, w0))
+    assert orc.last_sst["F1"].max() < 1e-200
+    lam = 2 * (np.cos(2 * np.pi * p / nx) - 1) + 2 * (np.cos(2 * np.pi * q / ny) - 1) / (1 + s * s)
+    expect = (k + dt * nu / h ** 2 * lam * eps * np.cos(th)) / (1 + dt * 0.09 * w0)
+    np.testing.assert_allclose(k1, expect, rtol=1e-12)
+    np.testing.assert_allclose(w1, w0 / (1 + dt * 0.0828 * w0), rtol=1e-13)
+
+
 def test_sst_upwind_translation():
     """A smooth k wave in uniform flow is carried downstream (second-order upwind is stable and
     accurate; a downwind choice would grow without bound over these steps)."""
