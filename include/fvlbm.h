@@ -121,7 +121,11 @@ typedef struct {
 } fvlbm_params;
 
 /*
- * Build a mesh from host arrays (copied; the caller keeps ownership of its arrays).
+ * Build a mesh from host arrays (copied; the caller keeps ownership of its arrays): the cells of
+ * the cell-centred finite-volume discretisation of Section 3.1, with what the method needs of
+ * them: the edge normals and lengths of the flux sum of Eq. (advection), the least-squares
+ * gradient of its linear upwind reconstruction, and the wall distance d of the SST blending
+ * functions F1 and F2 (Section 2).
  *   node_xy       [n_nodes][2]
  *   cell_ptr      [n_cells+1] CSR offsets into cell_nodes; every cell has 3 or 4 nodes listed
  *                 counter-clockwise (positive shoelace area)
@@ -160,7 +164,9 @@ fvlbm_status fvlbm_mesh_permutation(const fvlbm_mesh *mesh, int64_t *perm);
  * stages): 1 / max over cells c and directions a of sum_edges max(e_a.n, 0) dl / A_c. */
 fvlbm_status fvlbm_mesh_max_dt(const fvlbm_mesh *mesh, double *dt);
 
-/* Device bytes fvlbm_init needs for this mesh, precision and SST switch. */
+/* Device bytes fvlbm_init needs for this mesh, precision and SST switch (a forward state; the
+ * memory of a recorded run for the adjoint is sized by fvlbm_adjoint_bytes and passed to
+ * fvlbm_record). */
 fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *mesh, int32_t precision, int32_t sst, size_t *bytes);
 
 /*
@@ -235,7 +241,9 @@ fvlbm_status fvlbm_totals_noalloc(fvlbm_state *st, double *totals_dev);
 fvlbm_status fvlbm_get_f(fvlbm_state *st, int32_t on_device, double *f);
 
 /*
- * Surface functionals in FP64 (host results; synchronises).  force[2]: the force of the fluid
+ * Surface functionals in FP64 (host results; synchronises): the wall force behind the airfoil's
+ * lift and drag and the wall shear behind the backward-facing step's reattachment length, the
+ * quantities Section 4 reports for its two turbulent tests.  force[2]: the force of the fluid
  * on the WALL / MOVING_WALL edges of the groups whose bit is set in wall_group_mask, gauge
  * pressure (p - rho0/3) n l plus the wall shear mu (u_c - u_w)_t / d_perp l with mu = rho_c nu.
  * j_r (may be NULL): sum over the walls of group params->jr_group with x_f > jr_xmin of
