@@ -20,8 +20,9 @@
  *     overlapped recompute on small meshes uses a stream of its own, joined to that stream before
  *     the call returns).  Calls that return host values synchronise that stream; the others are
  *     asynchronous.
- *   - Environment (diagnostics and tests): FVLBM_SWEEP = ring | tiled | tiled-grads | split | face
- *     forces a sweep variant (ring: only where it fits; face: the edge loop with atomics, kept for
+ *   - Environment (diagnostics and tests): FVLBM_SWEEP = ring | pair | tiled | tiled-grads | split | face
+ *     forces a sweep variant (ring, pair: only where it fits, one or two threads per cell in the
+ *     stage sweeps; face: the edge loop with atomics, kept for
  *     the measured comparison with the cell loops; its sums' order, and so the last bits of its
  *     results, vary from run to run); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
  *     of segment buffers (no kept second tape, no overlap).  Both are read when a state is created

@@ -14,6 +14,7 @@
 #include "internal.h"
 #include "adjoint.h"
 #include "kernels.h"
+#include "pair.h"
 
 namespace fvlbm {
 
@@ -104,6 +105,7 @@ struct fvlbm_state {
     // without the stage values in LDS) or the two-kernel split path
     bool ring = true, tiled = true, tile_vals = true;
     bool face = false;           // the edge loop with atomics (FVLBM_SWEEP=face)
+    bool pair = false;           // the ring-tiled stage sweeps with two threads per cell (k_stage_pair)
     int32_t n_faces = 0;         // interior edges, each once
     int32_t *faces = nullptr;    // [n_faces] face codes 4 c + s
     void *acc = nullptr;         // [8][n] outflow sums of the edge loop
@@ -445,25 +447,36 @@ void drain_events(fvlbm_state *st) {
 
 // One ring-tiled stage sweep (stage J; J = 0 the explicit scheme) over all tiles; edges per cell
 // and the face-value limiter are template switches of the kernel.
+template <typename T, int J, int S, int LIM>
+void stage_ring_launch(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, const StageBufs<T> &b,
+                       const StepPar<T> &p, hipStream_t s) {
+    const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+    const size_t lds = st->lds_bytes;
+    if (st->pair)
+        k_stage_pair<T, J, S, LIM><<<nt, 2 * kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+    else
+        k_stage_ring<T, J, S, LIM><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+}
+
+// One ring-tiled stage sweep (stage J; J = 0 the explicit scheme) over all tiles; edges per cell
+// and the face-value limiter are template switches of the kernel.
 template <typename T, int J>
 void stage_ring(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, const StageBufs<T> &b, const StepPar<T> &p,
                 hipStream_t s) {
-    const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
-    const size_t lds = st->lds_bytes;
     if (st->ring_s == 3) {
         if (p.limiter == 1)
-            k_stage_ring<T, J, 3, 1><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            stage_ring_launch<T, J, 3, 1>(st, g, rt, b, p, s);
         else if (p.limiter == 2)
-            k_stage_ring<T, J, 3, 2><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            stage_ring_launch<T, J, 3, 2>(st, g, rt, b, p, s);
         else
-            k_stage_ring<T, J, 3, 0><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            stage_ring_launch<T, J, 3, 0>(st, g, rt, b, p, s);
     } else {
         if (p.limiter == 1)
-            k_stage_ring<T, J, 4, 1><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            stage_ring_launch<T, J, 4, 1>(st, g, rt, b, p, s);
         else if (p.limiter == 2)
-            k_stage_ring<T, J, 4, 2><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            stage_ring_launch<T, J, 4, 2>(st, g, rt, b, p, s);
         else
-            k_stage_ring<T, J, 4, 0><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            stage_ring_launch<T, J, 4, 0>(st, g, rt, b, p, s);
     }
 }
 
@@ -718,7 +731,7 @@ void import_state(fvlbm_state *st, const double *f, const double *k, const doubl
 // Chooses the sweep variant: the ring-tiled kernels when every tile's extended halo fits one
 // thread per ext cell and their LDS fits; else the ring-1 tiled kernels unless their LDS would not
 // fit; else the two-kernel path.  The environment variable FVLBM_SWEEP (ring, tiled, tiled-grads,
-// split) restricts the choice.
+// split, face; pair: the ring-tiled stage sweeps with two threads per cell) restricts the choice.
 // LDS of the ring-tiled transposed convection: values, gradient adjoints and, on triangle meshes,
 // the inverse LSQ matrices of tile and ring-1 cells.
 template <typename T>
@@ -756,9 +769,11 @@ void choose_sweep(fvlbm_state *st) {
     // the adjoint's ring kernels must fit as well: transposed convection and the SST reverse
     const size_t adj_lds = std::max(adj_t_lds<T>(st), adj_sst_lds<T>(st));
     // one thread per ring-1 cell; ring-2 cells beyond one per thread are looped over
-    st->ring = (mode.empty() || mode == "ring") && st->mesh->halo_max <= kTileCells &&
+    st->ring = (mode.empty() || mode == "ring" || mode == "pair") && st->mesh->halo_max <= kTileCells &&
                std::max(ring_lds, adj_lds) <= (size_t)max_lds;
     if (st->ring) {
+        // the stage sweeps with two threads per cell (pair) or one (ring)
+        st->pair = mode == "pair";
         st->lds_bytes = ring_lds;
         st->sst_lds_bytes = ((size_t)8 * st->ring_wv + (size_t)6 * st->ring_wg) * sizeof(T);
         st->tiled = false;

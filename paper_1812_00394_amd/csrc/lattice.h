@@ -30,11 +30,22 @@ __device__ __forceinline__ S cst(double x) { return S(typename ScalarBase<S>::ty
 
 // 1 / x.  FP32: the hardware reciprocal (v_rcp_f32, within 1 ulp), one instruction instead of the
 // correctly rounded division sequence; its error is below the FP32 rounding of the quantities it
-// scales.  FP64 and dual numbers: the division.
+// scales.  Dual numbers: the division.
 template <class S>
 __device__ __forceinline__ S recip(S x) { return cst<S>(1) / x; }
 template <>
 __device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+// FP64: the hardware reciprocal estimate (v_rcp_f64) refined by two steps of Newton's iteration for
+// 1/x, r <- r + r (1 - x r), each of which squares the relative error, instead of the IEEE division
+// sequence (measured on gfx950: the correctly rounded 1/x for 4.2M random x over 24 decades; the
+// FP64 step 2 % faster).  x = 0 gives NaN where the division gives infinity: non-finite either way.
+template <>
+__device__ __forceinline__ double recip<double>(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-x, r, 1.0), r, r);
+    return r;
+}
 
 // Lattice velocities of Qian's D2Q9 model and their weights (a = 0 rest, 1-4 axes, 5-8 diagonals).
 __host__ __device__ constexpr int ex(int a) { return (a == 1 || a == 5 || a == 8) ? 1 : ((a == 3 || a == 6 || a == 7) ? -1 : 0); }

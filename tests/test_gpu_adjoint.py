@@ -144,7 +144,7 @@ def _oracle_final(m, p, f0, k0, w0, N):
 PARAMS = ["theta", "sigma_k1", "sigma_w1", "beta_star", "a1"]
 
 
-@pytest.mark.parametrize("sweep", ["ring", "split", "face"])
+@pytest.mark.parametrize("sweep", ["ring", "pair", "split", "face"])
 @pytest.mark.parametrize("name", sorted(RUNS))
 def test_run_adjoint_dot_product_and_params(F, name, sweep, monkeypatch):
     say("run adjoint", name, sweep)
@@ -448,15 +448,17 @@ def test_lift_drag_adjoint_against_complex_step(F, precision):
 
 
 
+@pytest.mark.parametrize("sweep", ["ring", "pair"])
 @pytest.mark.parametrize("name", ["duct_laminar", "naca_sst"])
-def test_limited_adjoint_against_complex_step(F, name):
+def test_limited_adjoint_against_complex_step(F, name, sweep, monkeypatch):
     """The adjoint through the face-value limiter of reading r32 (ring path): the forward sweeps
     record which edges were clipped and to which cell's value, the transposed convection routes each
     clipped edge's adjoint to that value.  Dot product of the adjoint of a 3-step recorded run
     (checkpoint every 2) with the oracle's complex-step derivative along a random direction, within
     1e-9, and the parameter gradient within 1e-8; on the O-mesh the lift/drag adjoint as well.  The
     case must clip: the limited oracle run differs from the unlimited one."""
-    say("limited adjoint", name)
+    say("limited adjoint", name, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     m, p, orc, f0, k0, w0, sst = _run_case(name, seed=97)
     p = dict(p, limiter=1)
     n = orc.g.n

@@ -82,7 +82,7 @@ def test_advection_operator_parity(F, name):
     assert rel(got, ref, np.abs(ref).max()) < 1e-12
 
 
-@pytest.mark.parametrize("sweep", ["ring", "tiled", "tiled-grads", "split", "face"])
+@pytest.mark.parametrize("sweep", ["ring", "pair", "tiled", "tiled-grads", "split", "face"])
 @pytest.mark.parametrize("name", sorted(MESHES))
 def test_laminar_step_parity(F, name, sweep, monkeypatch):
     """Every sweep variant: ring-tiled (both halo rings staged in LDS, stage 1 collision fused),
@@ -189,7 +189,7 @@ SST_MESHES = {
 }
 
 
-@pytest.mark.parametrize("sweep", ["ring", "split", "face"])
+@pytest.mark.parametrize("sweep", ["ring", "pair", "split", "face"])
 @pytest.mark.parametrize("name", sorted(SST_MESHES))
 def test_sst_step_parity(F, name, sweep, monkeypatch):
     """The SST in one ring-tiled launch and as the two-kernel pair (which the edge loop also uses)."""
@@ -213,7 +213,7 @@ def test_sst_step_parity(F, name, sweep, monkeypatch):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
-@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("sweep", ["ring", "pair", "split"])
 @pytest.mark.parametrize("name", ["backstep_coarse", "naca"])
 def test_sst_per_stage_step_parity(F, name, sweep, precision, monkeypatch):
     """The SST solved again before the third stage (params.sst = 2, reading r33): the second SST
@@ -389,7 +389,7 @@ def test_limited_advection_operator_parity(F, name, limiter):
 
 
 @pytest.mark.parametrize("limiter", [1, 2])
-@pytest.mark.parametrize("sweep", ["ring", "split", "face"])
+@pytest.mark.parametrize("sweep", ["ring", "pair", "split", "face"])
 @pytest.mark.parametrize("name", ["cavity", "channel", "naca"])
 def test_limited_laminar_step_parity(F, name, sweep, limiter, monkeypatch):
     say("limited laminar step", name, sweep, "limiter", limiter)
@@ -465,9 +465,11 @@ def test_airfoil_full_size_lift_drag_fp32_vs_fp64(F):
 # ------------------------------------------------------------------------------------------------
 # The explicit scheme the IMEX scheme is compared with (forward Euler, dt < 2 tau).
 # ------------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("sweep", ["ring", "pair"])
 @pytest.mark.parametrize("name", ["cavity", "periodic", "naca"])
-def test_explicit_step_parity(F, name):
-    say("explicit step", name)
+def test_explicit_step_parity(F, name, sweep, monkeypatch):
+    say("explicit step", name, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = MESHES[name]
     m = make()
     dt = courant_dt(m)
@@ -484,8 +486,10 @@ def test_explicit_step_parity(F, name):
         assert rel(st.get_f(), fo, dev_scale(fo)) < tol
 
 
-def test_explicit_sst_step_parity(F):
-    say("explicit sst step, duct")
+@pytest.mark.parametrize("sweep", ["ring", "pair"])
+def test_explicit_sst_step_parity(F, sweep, monkeypatch):
+    say("explicit sst step, duct", sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     make, extra = SST_MESHES["duct"]
     m = make()
     orc, p, f, k, w = _sst_case(m, extra, 53)
@@ -502,7 +506,7 @@ def test_explicit_sst_step_parity(F):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
-@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("sweep", ["ring", "pair", "split"])
 @pytest.mark.parametrize("name", sorted(SST_MESHES))
 def test_sst_implicit_step_parity(F, name, sweep, precision, monkeypatch):
     """The implicit SST variant (params.sst_sweeps = m, reading r34): the system rows written by
@@ -570,12 +574,14 @@ def _wide_halo_backstep():
     return mg.backstep(core=0.3, dx_core=0.6, dx_corner=0.02, y1=1e-3)
 
 
+@pytest.mark.parametrize("sweep", ["ring", "pair"])
 @pytest.mark.parametrize("order", ["morton", "tiles"])
-def test_wide_halo_ring_step_parity(F, order):
+def test_wide_halo_ring_step_parity(F, order, sweep, monkeypatch):
     """The ring kernels loop over ring-2 cells beyond one per thread (Morton tiles of this mesh need
     it).  SST steps against the oracle, under Morton tiles and under the graph-grown tiles the
     library uses by default: FP32-dev on the ring path (its LDS fits), FP64 on whichever path fits;
     gates as the SST parity tests (FP64 1e-12 / 1e-11, FP32-dev 2e-6 after one step)."""
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     m = _wide_halo_backstep()
     extra = dict(group_u=[[0, 0], [0.05, 0], [0, 0]], group_k=[0, 1e-4, 0], group_w=[0, 0.5, 0])
     orc, p, f, k, w = _sst_case(m, extra, 56)
@@ -583,7 +589,7 @@ def test_wide_halo_ring_step_parity(F, order):
     nut1 = orc.last_nut
     M = F.Mesh(m, order=order)
     for precision in ("fp64", "fp32dev"):
-        say("wide-halo backstep", order, precision)
+        say("wide-halo backstep", order, sweep, precision)
         st = F.State(M, p, precision=precision, k=k, omega=w)
         st.set_state(f, k, w)
         st.timing(True)
@@ -609,13 +615,15 @@ def test_wide_halo_ring_step_parity(F, order):
             assert rel(mo["k"], k1, np.abs(k1).max()) < 2e-6 and rel(mo["omega"], w1, np.abs(w1).max()) < 2e-6
 
 
+@pytest.mark.parametrize("sweep", ["ring", "pair"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32dev"])
-def test_step_is_independent_of_the_tile_layout(F, precision):
+def test_step_is_independent_of_the_tile_layout(F, precision, sweep, monkeypatch):
     """Every cell forms its LSQ coefficients, gradient, face values and update from its own data with
     the same code whether it is a tile cell or a halo cell of another tile, so the ring path's result
     must not depend on how the cells are grouped into tiles: three SST steps under Morton tiles and
     under graph-grown tiles agree to the last bit (f, k, omega in the caller's cell order)."""
-    say("tile-layout independence", precision)
+    say("tile-layout independence", precision, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
     m = _wide_halo_backstep()
     extra = dict(group_u=[[0, 0], [0.05, 0], [0, 0]], group_k=[0, 1e-4, 0], group_w=[0, 0.5, 0])
     orc, p, f, k, w = _sst_case(m, extra, 57)
