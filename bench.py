@@ -428,6 +428,7 @@ def main():
     ap.add_argument("--workload", default="delaunay4m")
     ap.add_argument("--precision", default="fp32dev", choices=["fp32dev", "fp64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-geo64", action="store_true", help="skip the FP32 run with FP64 geometry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-points", type=int, default=40_000)
     ap.add_argument("--cpu-steps", type=int, default=30)
@@ -528,7 +529,25 @@ def main():
         extra = {"fp64_mlups": round(mlups64, 1), "fp64_ms_per_step": round(ms64 / steps64, 4),
                  "fp32dev_vs_fp64": {"steps": args.warmup + steps64, "max_du_over_U": err_u,
                                      "max_drho": err_rho}}
-        del st64, st32
+        del st32
+        if not args.no_geo64 and variant == "ring":
+            # the same FP32-deviation step with the geometry streamed in FP64 and the edge data formed
+            # in FP64 (precision fp32dev_geo64): its time and its error against the same FP64 run
+            stg, _ = make_state(F, M, flow, init, "fp32dev_geo64", dt_frac)
+            msg, _, _ = time_steps(F, stg, args.steps, args.warmup, stream, kernel_timing=False)
+            _, _, ktg = time_steps(F, stg, 20, 0, stream, kernel_timing=True)
+            stg2, _ = make_state(F, M, flow, init, "fp32dev_geo64", dt_frac)
+            stg2.step(args.warmup + steps64)
+            mg_ = stg2.moments()
+            extra["fp32dev_geo64"] = {
+                "ms_per_step": round(msg / args.steps, 4), "mlups": round(n * args.steps / (msg * 1e-3) / 1e6, 1),
+                "kernels_ms": {k: round(v[0] / v[1], 5) for k, v in ktg.items() if v[1]},
+                "vs_fp64": {"steps": args.warmup + steps64,
+                            "max_du_over_U": float(np.abs(mg_["u"] - m64["u"]).max() / U),
+                            "max_drho": float(np.abs(mg_["rho"] - m64["rho"]).max())}}
+            log(f"fp32dev_geo64: {msg / args.steps:.3f} ms/step")
+            del stg, stg2
+        del st64
 
     adjoint = None
     if args.adjoint_steps > 0 and p.get("sst"):

@@ -62,7 +62,11 @@ enum {
     FVLBM_PERIODIC = 6     /* paired with the edges found at midpoint + periodic_shift */
 };
 
-enum { FVLBM_FP64 = 0, FVLBM_FP32_DEV = 1 };                  /* storage / arithmetic of f */
+/* storage / arithmetic of f: FP64; FP32 deviations from w_a rho0 (the ring sweeps stream FP32 copies
+ * of the geometry, with the LSQ coefficients rounded once from FP64); FP32 deviations whose ring
+ * sweeps stream FP64 geometry and form normals, midpoint offsets and LSQ coefficients in FP64 before
+ * the FP32 flux arithmetic (forward only: ring-tiled sweeps, no adjoint) */
+enum { FVLBM_FP64 = 0, FVLBM_FP32_DEV = 1, FVLBM_FP32_DEV_GEO64 = 2 };
 enum { FVLBM_ORDER_NONE = 0, FVLBM_ORDER_MORTON = 1, FVLBM_ORDER_RCM = 2, FVLBM_ORDER_TILES = 3 };
 
 #define FVLBM_MAX_GROUPS 16

@@ -9,6 +9,8 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "internal.h"
@@ -106,6 +108,7 @@ struct fvlbm_state {
     bool ring = true, tiled = true, tile_vals = true;
     bool face = false;           // the edge loop with atomics (FVLBM_SWEEP=face)
     bool pair = false;           // the ring-tiled stage sweeps with two threads per cell (k_stage_pair)
+    bool fp64_geometry = false;  // FP32 state whose ring sweeps form the edge data from FP64 geometry
     int32_t n_faces = 0;         // interior edges, each once
     int32_t *faces = nullptr;    // [n_faces] face codes 4 c + s
     void *acc = nullptr;         // [8][n] outflow sums of the edge loop
@@ -179,7 +182,7 @@ std::vector<int32_t> face_list(const fvlbm_mesh *m) {
 
 // Layout of the workspace.  Geometry arrays are written by fvlbm_init; the rest is state.
 template <typename T>
-void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
+void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st, bool geo64 = false) {
     const size_t n = (size_t)m->n, nb = m->b_cell.size(), S = kSlots * n;
     Geo<T> &g = geo_of<T>(st);
     st->n_cells = (int32_t)n;
@@ -248,6 +251,22 @@ void carve(Carver &cv, const fvlbm_mesh *m, int sst, fvlbm_state *st) {
     st->n_faces = (int32_t)m->n_interior_edges;
     st->faces = cv.take<int32_t>(std::max<size_t>(1, (size_t)m->n_interior_edges));
     st->acc = cv.take<T>(8 * n);
+    if (geo64) {
+        GeoF64 &d = g.g64;
+        d.n = (int32_t)n;
+        d.nlx = cv.take<double>(S);
+        d.nly = cv.take<double>(S);
+        d.rfx = cv.take<double>(S);
+        d.rfy = cv.take<double>(S);
+        d.qx = cv.take<double>(S);
+        d.qy = cv.take<double>(S);
+        d.cx = cv.take<double>(S);
+        d.cy = cv.take<double>(S);
+        d.inv_area = cv.take<double>(n);
+        d.mi = cv.take<double>(3 * n);
+        d.tp = cv.take<double>(6 * n);
+        d.bfirst = g.bfirst;
+    }
 }
 
 size_t layout_bytes(const fvlbm_mesh *m, int precision, int sst) {
@@ -256,7 +275,7 @@ size_t layout_bytes(const fvlbm_mesh *m, int precision, int sst) {
     if (precision == FVLBM_FP64)
         carve<double>(cv, m, sst, &tmp);
     else
-        carve<float>(cv, m, sst, &tmp);
+        carve<float>(cv, m, sst, &tmp, precision == FVLBM_FP32_DEV_GEO64);
     return cv.off + 256;
 }
 
@@ -366,6 +385,28 @@ void upload_geometry(fvlbm_state *st) {
     h2d(const_cast<T *>(g.mi), mi, s);
     const std::vector<T> tp = as_t(m->tri_p);
     h2d(const_cast<T *>(g.tp), tp, s);
+    std::vector<double> mi64;
+    if (st->fp64_geometry) {
+        // the FP64 masters themselves
+        const GeoF64 &d = g.g64;
+        mi64.resize(3 * (size_t)m->n);
+        for (int64_t i = 0; i < m->n; ++i) {
+            mi64[i] = m->mi00[i];
+            mi64[m->n + i] = m->mi01[i];
+            mi64[2 * m->n + i] = m->mi11[i];
+        }
+        h2d(const_cast<double *>(d.nlx), m->nlx, s);
+        h2d(const_cast<double *>(d.nly), m->nly, s);
+        h2d(const_cast<double *>(d.rfx), m->rfx, s);
+        h2d(const_cast<double *>(d.rfy), m->rfy, s);
+        h2d(const_cast<double *>(d.qx), qx, s);
+        h2d(const_cast<double *>(d.qy), qy, s);
+        h2d(const_cast<double *>(d.cx), m->cx, s);
+        h2d(const_cast<double *>(d.cy), m->cy, s);
+        h2d(const_cast<double *>(d.inv_area), ia, s);
+        h2d(const_cast<double *>(d.mi), mi64, s);
+        h2d(const_cast<double *>(d.tp), m->tri_p, s);
+    }
     h2d(const_cast<int32_t *>(g.bfirst), m->bfirst, s);
     h2d(const_cast<double *>(g.area), m->area, s);
     h2d(const_cast<double *>(g.wdist), m->wdist, s);
@@ -452,6 +493,12 @@ void stage_ring_launch(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, co
                        const StepPar<T> &p, hipStream_t s) {
     const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
     const size_t lds = st->lds_bytes;
+    if constexpr (std::is_same_v<T, float>) {
+        if (st->fp64_geometry) {
+            k_stage_ring<T, J, S, LIM, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
+            return;
+        }
+    }
     if (st->pair)
         k_stage_pair<T, J, S, LIM><<<nt, 2 * kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
     else
@@ -507,6 +554,24 @@ void launch_sst_jacobi(fvlbm_state *st, const T *K0, const T *W0, T *K1, T *W1, 
     k_sst_jacobi<T, S, true, true><<<nbk, kBlock, 0, s>>>(g, J, din, nullptr, K0, W0, K1, W1, tau_out, nut, p);
 }
 
+// One ring launch of the SST kernel; FP32 states with FP64 geometry take the kernel that forms the
+// edge data from the FP64 copies (the aux planes are written only for the adjoint, which such
+// states do not support).
+template <typename T, int S, bool AUX, bool IMPL, typename Args>
+void sst_ring_launch(const fvlbm_state *st, int nt, size_t lds, hipStream_t s, const Args &a) {
+    std::apply(
+        [&](auto &&...x) {
+            if constexpr (std::is_same_v<T, float> && !AUX) {
+                if (st->fp64_geometry) {
+                    k_sst_ring<T, S, AUX, IMPL, true><<<nt, kTileCells, lds, s>>>(x...);
+                    return;
+                }
+            }
+            k_sst_ring<T, S, AUX, IMPL><<<nt, kTileCells, lds, s>>>(x...);
+        },
+        a);
+}
+
 template <typename T>
 void launch_sst(fvlbm_state *st, const T *M, const T *K0, const T *W0, T *K1, T *W1, T *tau_out, const StepPar<T> &p) {
     const Geo<T> &g = geo_of<T>(st);
@@ -519,20 +584,21 @@ void launch_sst(fvlbm_state *st, const T *M, const T *K0, const T *W0, T *K1, T 
         const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
         const size_t lds = st->sst_lds_bytes;
         Timed t(st, FVLBM_K_SST);
+        const auto args = std::make_tuple(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
         if (st->ring_s == 3) {
             if (impl)
-                k_sst_ring<T, 3, false, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+                sst_ring_launch<T, 3, false, true>(st, nt, lds, s, args);
             else if (st->want_aux)
-                k_sst_ring<T, 3, true, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+                sst_ring_launch<T, 3, true, false>(st, nt, lds, s, args);
             else
-                k_sst_ring<T, 3, false, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+                sst_ring_launch<T, 3, false, false>(st, nt, lds, s, args);
         } else {
             if (impl)
-                k_sst_ring<T, 4, false, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+                sst_ring_launch<T, 4, false, true>(st, nt, lds, s, args);
             else if (st->want_aux)
-                k_sst_ring<T, 4, true, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+                sst_ring_launch<T, 4, true, false>(st, nt, lds, s, args);
             else
-                k_sst_ring<T, 4, false, false><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
+                sst_ring_launch<T, 4, false, false>(st, nt, lds, s, args);
         }
     } else {
         const int nbk = blocks_for(g.n);
@@ -757,6 +823,7 @@ void choose_sweep(fvlbm_state *st) {
     st->ring_s = st->mesh->max_faces <= 3 ? 3 : 4;
     st->ring_wv = kTile + st->mesh->ext_max;
     st->ring_wg = kTile + st->mesh->halo_max;
+    if (mode == "face" && st->fp64_geometry) throw Error(FVLBM_EINVAL, "init: FP32 storage with FP64 geometry needs the ring-tiled sweep");
     if (mode == "face") {
         // the edge loop with atomics: gradients in HBM, then one thread per interior edge
         st->face = true;
@@ -771,9 +838,11 @@ void choose_sweep(fvlbm_state *st) {
     // one thread per ring-1 cell; ring-2 cells beyond one per thread are looped over
     st->ring = (mode.empty() || mode == "ring" || mode == "pair") && st->mesh->halo_max <= kTileCells &&
                std::max(ring_lds, adj_lds) <= (size_t)max_lds;
+    if (st->fp64_geometry && !st->ring)
+        throw Error(FVLBM_EINVAL, "init: FP32 storage with FP64 geometry needs the ring-tiled sweep");
     if (st->ring) {
         // the stage sweeps with two threads per cell (pair) or one (ring)
-        st->pair = mode == "pair";
+        st->pair = mode == "pair" && !st->fp64_geometry;
         st->lds_bytes = ring_lds;
         st->sst_lds_bytes = ((size_t)8 * st->ring_wv + (size_t)6 * st->ring_wg) * sizeof(T);
         st->tiled = false;
@@ -1449,7 +1518,7 @@ fvlbm_status fvlbm_mesh_permutation(const fvlbm_mesh *m, int64_t *perm) {
 fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *m, int32_t precision, int32_t sst, size_t *bytes) {
     return guarded([&] {
         if (!m || !bytes) throw Error(FVLBM_EINVAL, "state_bytes: NULL argument");
-        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV) throw Error(FVLBM_EINVAL, "state_bytes: bad precision");
+        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV && precision != FVLBM_FP32_DEV_GEO64) throw Error(FVLBM_EINVAL, "state_bytes: bad precision");
         *bytes = layout_bytes(m, precision, sst ? 1 : 0);
     });
 }
@@ -1461,7 +1530,7 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         if (!out) throw Error(FVLBM_EINVAL, "init: out is NULL");
         *out = nullptr;
         if (!m || !p || !rho || !u || !workspace) throw Error(FVLBM_EINVAL, "init: NULL argument");
-        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV) throw Error(FVLBM_EINVAL, "init: bad precision");
+        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV && precision != FVLBM_FP32_DEV_GEO64) throw Error(FVLBM_EINVAL, "init: bad precision");
         if (p->n_groups != m->n_groups) throw Error(FVLBM_EINVAL, "init: params.n_groups differs from the mesh");
         if (!(p->nu > 0) || !(p->dt > 0) || !(p->rho0 > 0)) throw Error(FVLBM_EINVAL, "init: nu, dt and rho0 must be > 0 (tau = 3 nu)");
         if (p->sst < 0 || p->sst > 2) throw Error(FVLBM_EINVAL, "init: sst must be 0, 1 or 2");
@@ -1489,7 +1558,8 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
             st->par = pv;
             do_init<double>(st.get(), rho, u, k, omega);
         } else {
-            carve<float>(cv, m, st->sst, st.get());
+            st->fp64_geometry = precision == FVLBM_FP32_DEV_GEO64;
+            carve<float>(cv, m, st->sst, st.get(), st->fp64_geometry);
             st->par = pv;
             do_init<float>(st.get(), rho, u, k, omega);
         }
@@ -1735,6 +1805,7 @@ fvlbm_status fvlbm_adjoint_bytes(const fvlbm_mesh *m, int32_t precision, int32_t
     return guarded([&] {
         if (!m || !bytes) throw Error(FVLBM_EINVAL, "adjoint_bytes: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "adjoint_bytes: n_steps and ckpt_every must be >= 1");
+        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV) throw Error(FVLBM_EINVAL, "adjoint_bytes: bad precision (the adjoint supports FP64 and FP32_DEV)");
         Carver cv;
         if (precision == FVLBM_FP64) {
             AdjLayout<double> L;
@@ -1751,6 +1822,7 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
         if (!st || !workspace) throw Error(FVLBM_EINVAL, "record: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
         if (st->par.limiter == 2) throw Error(FVLBM_ESTATE, "record: the gradient limiter (limiter 2) has no adjoint here");
+        if (st->fp64_geometry) throw Error(FVLBM_ESTATE, "record: FP32 storage with FP64 geometry has no adjoint here");
         if (st->par.limiter == 1 && !st->ring)
             throw Error(FVLBM_ESTATE, "record: the face-value limiter's adjoint needs the ring-tiled sweep");
         if (st->sst_stages) throw Error(FVLBM_ESTATE, "record: the per-stage SST coupling has no adjoint here");

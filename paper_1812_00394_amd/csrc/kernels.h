@@ -786,8 +786,8 @@ __device__ __forceinline__ void decode_slots(const int32_t *__restrict__ bfirst,
 // runs from vertex k to vertex k+1, counter-clockwise): outward normal x length, midpoint minus
 // centroid, and the inverse area.  FP32 reads p0, p1 and takes p2 = -p0 - p1 (the centroid of a
 // triangle is its vertex mean; the difference is far below FP32 resolution); FP64 reads all three.
-template <typename T>
-__device__ __forceinline__ void tri_edges(const Geo<T> &g, int c, T nlx[3], T nly[3], T rx[3], T ry[3], T &ia) {
+template <typename T, typename GG>
+__device__ __forceinline__ void tri_edges(const GG &g, int c, T nlx[3], T nly[3], T rx[3], T ry[3], T &ia) {
     const size_t n = g.n;
     T px[3], py[3];
     px[0] = g.tp[c];
@@ -858,8 +858,8 @@ __device__ __forceinline__ void lsq_coef(T m00, T m01, T m11, T rx, T ry, T qx, 
 // FP32 on skewed, stretched cells they lose up to 2e-5 relative (cancellation in w M^-1 d), which
 // the FP32-deviation error gates resolve.  Tile cells and halo cells of other tiles go through this
 // one function, so a cell's coefficients never depend on the tile that evaluates them.
-template <typename T, int S>
-__device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__restrict__ lnb, size_t ls, size_t li,
+template <typename T, int S, typename GG>
+__device__ __forceinline__ void cell_edges(const GG &g, const int16_t *__restrict__ lnb, size_t ls, size_t li,
                                            int c, int col[S], int nb[S], T nlx[S], T nly[S], T rx[S], T ry[S],
                                            T qx[S], T qy[S], T cxs[S], T cys[S], T mi[3], T &ia) {
     const int n = g.n;
@@ -878,7 +878,7 @@ __device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__res
     }
     decode_slots<S>(g.bfirst, c, col, nb);
     if constexpr (S == 3) {
-        tri_edges(g, c, nlx, nly, rx, ry, ia);
+        tri_edges<T>(g, c, nlx, nly, rx, ry, ia);
         lsq_cell<T, S>(rx, ry, qx, qy, nb, cxs, cys, mi);
     } else {
         mi[0] = g.mi[c];
@@ -897,7 +897,44 @@ __device__ __forceinline__ void cell_edges(const Geo<T> &g, const int16_t *__res
     }
 }
 
-template <typename T, int J, int S, int LIM>
+// FP32 edge data of an FP32_DEV_GEO64 state: formed in FP64 from the FP64 geometry copies exactly as
+// an FP64 state forms it (LSQ coefficients from the FP64 centroid offsets), then each value rounded
+// once to FP32 for the FP32 flux arithmetic.
+template <int S>
+__device__ __forceinline__ void cell_edges_g64(const Geo<float> &g, const int16_t *__restrict__ lnb, size_t ls,
+                                               size_t li, int c, int col[S], int nb[S], float nlx[S], float nly[S],
+                                               float rx[S], float ry[S], float qx[S], float qy[S], float cxs[S],
+                                               float cys[S], float mi[3], float &ia) {
+    double dnx[S], dny[S], drx[S], dry[S], dqx[S], dqy[S], dcx[S], dcy[S], dmi[3], dia;
+    cell_edges<double, S>(g.g64, lnb, ls, li, c, col, nb, dnx, dny, drx, dry, dqx, dqy, dcx, dcy, dmi, dia);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        nlx[s] = (float)dnx[s];
+        nly[s] = (float)dny[s];
+        rx[s] = (float)drx[s];
+        ry[s] = (float)dry[s];
+        qx[s] = (float)dqx[s];
+        qy[s] = (float)dqy[s];
+        cxs[s] = (float)dcx[s];
+        cys[s] = (float)dcy[s];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) mi[k] = (float)dmi[k];
+    ia = (float)dia;
+}
+
+// The edge data of a cell from the state's geometry (G64: from the FP64 copies, FP32 states only).
+template <typename T, int S, bool G64>
+__device__ __forceinline__ void edges_of(const Geo<T> &g, const int16_t *__restrict__ lnb, size_t ls, size_t li,
+                                         int c, int col[S], int nb[S], T nlx[S], T nly[S], T rx[S], T ry[S], T qx[S],
+                                         T qy[S], T cxs[S], T cys[S], T mi[3], T &ia) {
+    if constexpr (G64)
+        cell_edges_g64<S>(g, lnb, ls, li, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
+    else
+        cell_edges<T, S>(g, lnb, ls, li, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
+}
+
+template <typename T, int J, int S, int LIM, bool G64 = false>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_stage_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg, StageBufs<T> b,
                  StepPar<T> p) {
@@ -928,7 +965,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             for (int a = 0; a < 9; ++a) gc[a] = b.src[(size_t)a * n + c];
         }
         T mi[3];
-        cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
+        edges_of<T, S, G64>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
 #pragma unroll
         for (int a = 1; a < 9; ++a) V[vrow<T>(t, a - 1)] = gc[a];
     }
@@ -955,7 +992,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             // code), so that its gradient, and the face values built from it, do not depend on
             // which tile evaluates them
             T hnlx[S], hnly[S], hqx[S], hqy[S], hmi[3], hia;
-            cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy,
+            edges_of<T, S, G64>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy,
                              hmi, hia);
         }
     }
@@ -1595,7 +1632,7 @@ __device__ __forceinline__ void sst_grad_ring(const Geo<T> &g, const int32_t *__
 }
 
 // IMPL: the implicit variant's system rows into J (see kSysPlanes) instead of the update.
-template <typename T, int S, bool AUX, bool IMPL>
+template <typename T, int S, bool AUX, bool IMPL, bool G64 = false>
 __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
     k_sst_ring(Geo<T> g, RingTiles rt, const int16_t *__restrict__ lnb, int Wv, int Wg,
                const int32_t *__restrict__ bzg, const T *__restrict__ M, const T *__restrict__ K,
@@ -1631,7 +1668,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             aux[(size_t)14 * n + c] = uy;
         }
         T mi[3];
-        cell_edges<T, S>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
+        edges_of<T, S, G64>(g, lnb, n, c, c, col, nb, nlx, nly, rx, ry, qx, qy, cxs, cys, mi, ia);
         dc = T(g.wdist[c]);
         Vv[t * 8 + 0] = ux;
         Vv[t * 8 + 1] = uy;
@@ -1658,7 +1695,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         if (ring1) {
             // LSQ coefficients formed as in the cell's own tile (see k_stage_ring)
             T hnlx[S], hnly[S], hrx[S], hry[S], hqx[S], hqy[S], hmi[3], hia;
-            cell_edges<T, S>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy,
+            edges_of<T, S, G64>(g, rt.lnb, rt.n_ext, x0 + t, hc, hcol, hnb, hnlx, hnly, hrx, hry, hqx, hqy, hcx, hcy,
                              hmi, hia);
             hd = T(g.wdist[hc]);
         }

@@ -70,6 +70,18 @@ __device__ __forceinline__ int cell_index() { return xcd_block(blockIdx.x, gridD
 // arrays a sweep streams are held in the arithmetic type T of the state (FP64 masters of every
 // quantity stay on the host and in the FP64 fields below): nl = outward normal x length,
 // rf = x_f - x_c, q = x_f - x_N' (from the neighbour's centroid image), c = LSQ coefficients.
+// FP64 copies of the geometry the ring sweeps stream, for FP32-deviation states that keep geometry
+// and least-squares data in FP64 on the GPU (precision FVLBM_FP32_DEV_GEO64).  The members carry
+// the names of Geo<double>'s, so one function forms the edge data from either.
+struct GeoF64 {
+    int32_t n;
+    const double *nlx, *nly, *rfx, *rfy, *qx, *qy, *cx, *cy;         // [4][n]
+    const double *inv_area;                                          // [n]
+    const double *mi;                                                // [3][n]
+    const double *tp;                                                // [6][n]
+    const int32_t *bfirst;                                           // [n]
+};
+
 template <typename T>
 struct Geo {
     int32_t n;    // cells
@@ -86,6 +98,7 @@ struct Geo {
     const double *b_nx, *b_ny, *b_l, *b_dperp, *b_xfx;               // [nb]
     const double *b_ux, *b_uy, *b_rho, *b_drho, *b_k, *b_w;          // [nb] boundary values
     const int32_t *b_group;                                          // [nb]
+    GeoF64 g64;                                                      // FP32_DEV_GEO64 only
 };
 
 // Equilibrium deviation f_eq,a(rho, u) - w_a rho0, with drho = rho - rho0 (second-order D2Q9

@@ -17,7 +17,8 @@ import numpy as np
 from .build import LIB
 
 FVLBM_MAX_GROUPS = 16
-FP64, FP32_DEV = 0, 1
+FP64, FP32_DEV, FP32_DEV_GEO64 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32dev": FP32_DEV, "fp32dev_geo64": FP32_DEV_GEO64}
 ORDERS = {"none": 0, "morton": 1, "rcm": 2, "tiles": 3}
 STATUS = {0: "OK", -1: "EINVAL", -2: "EMESH", -3: "ENOMEM", -4: "EDEVICE", -5: "EDIVERGED", -6: "ESTATE"}
 
@@ -171,7 +172,7 @@ class Mesh:
 
     def state_bytes(self, precision="fp64", sst=False):
         b = C.c_size_t()
-        _check(lib().fvlbm_state_bytes(self.handle, FP64 if precision == "fp64" else FP32_DEV, int(bool(sst)), C.byref(b)))
+        _check(lib().fvlbm_state_bytes(self.handle, PRECISIONS[precision], int(bool(sst)), C.byref(b)))
         return b.value
 
     def __del__(self):
@@ -236,7 +237,7 @@ class State:
         kk = _f64(k, (n,)) if k is not None else None
         ww = _f64(omega, (n,)) if omega is not None else None
         h = C.c_void_p()
-        _check(L.fvlbm_init(mesh.handle, C.byref(self.params), FP64 if precision == "fp64" else FP32_DEV,
+        _check(L.fvlbm_init(mesh.handle, C.byref(self.params), PRECISIONS[precision],
                             _ptr(rho), _ptr(u), _ptr(kk), _ptr(ww), C.c_void_p(self.workspace.data_ptr()),
                             nbytes, C.c_void_p(stream.cuda_stream), C.byref(h)))
         self.handle = h
@@ -327,7 +328,7 @@ class State:
         """advance n_steps steps, storing checkpoints for the adjoint"""
         import torch
         b = C.c_size_t()
-        prec = FP64 if self.precision == "fp64" else FP32_DEV
+        prec = PRECISIONS[self.precision]
         _check(lib().fvlbm_adjoint_bytes(self.mesh.handle, prec, int(n_steps), int(ckpt_every), C.byref(b)))
         self.adj_workspace = torch.empty(b.value, dtype=torch.uint8, device=self.workspace.device)
         _check(lib().fvlbm_record(self.handle, int(n_steps), int(ckpt_every),

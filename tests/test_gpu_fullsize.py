@@ -81,7 +81,7 @@ def _reference(full, rings, extra):
 
 def _check(F, full, ref, extra, expect):
     m, n, u, k, w, seeds, M = full
-    for precision in ("fp64", "fp32dev"):
+    for precision in ("fp64", "fp32dev", "fp32dev_geo64"):
         say("one step on the GPU,", precision, extra)
         st = F.State(M, dict(_params(), **extra), precision=precision, rho=np.ones(n), u=u, k=k, omega=w)
         st.timing(True)
@@ -104,7 +104,7 @@ def _check(F, full, ref, extra, expect):
             du = max(np.abs(mo["u"][seeds, 0] - ref["ux"]).max(), np.abs(mo["u"][seeds, 1] - ref["uy"]).max()) / U
             dk = np.abs(mo["k"][seeds] - ref["k"]).max() / np.abs(ref["k"]).max()
             dw = np.abs(mo["omega"][seeds] - ref["w"]).max() / np.abs(ref["w"]).max()
-            say("fp32dev errors at the samples: du/U", du, "dk", dk, "dw", dw)
+            say(precision, "errors at the samples: du/U", du, "dk", dk, "dw", dw)
             assert du < 2e-6 and dk < 2e-6 and dw < 2e-6, (du, dk, dw)
         del st
 

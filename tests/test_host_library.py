@@ -112,6 +112,8 @@ def test_invalid_arguments():
     b32 = M.state_bytes("fp32dev")
     assert b64 > (9 * 4 + 16) * 8 * M.n_cells
     assert b32 < b64
+    # FP32 storage with FP64 geometry: the FP32 state plus FP64 copies of the streamed geometry
+    assert M.state_bytes("fp32dev_geo64") >= b32 + (8 * 4 + 10) * 8 * M.n_cells
 
 
 def test_wide_halo_backstep_tiles():
