@@ -185,10 +185,15 @@ def compulsory_kernel_bytes(T):
 ORDER = ["tiles"]
 
 
+# the sources of the forward kernels the PMC summaries measure (their launch code in fvlbm.hip sets
+# only grid and LDS sizes)
+FORWARD_SOURCES = ("dual.h", "internal.h", "kernels.h", "lattice.h")
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1812_00394_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in FORWARD_SOURCES:
         with open(os.path.join(csrc, name), "rb") as fh:
             h.update(name.encode())
             h.update(fh.read())
@@ -379,11 +384,12 @@ def sweep_variants(F, M, flow, init, dt_frac, stream, args):
     return out
 
 
-def airfoil_run(F, steps):
+def airfoil_run(F, steps, adj_steps=200, ckpt=20):
     """The airfoil workload: 512 x 384 O-mesh (196,608 quads) around the sharp-trailing-edge 12 %
     section, Re 6e6 on the chord, 10 degrees incidence, u_inf = 0.05, dt = 0.9 of the advective
     Courant limit, developed near-wall start, face-value limiter on; lift and drag after `steps`
-    steps in FP32-dev and FP64, and the throughput of both."""
+    steps in FP32-dev and FP64, the throughput of both, and the time of the lift coefficient's
+    adjoint over `adj_steps` recorded steps."""
     import torch
     from paper_1812_00394_amd import meshgen as mg
     M = F.Mesh(mg.naca_omesh(), order=ORDER[0])
@@ -413,6 +419,21 @@ def airfoil_run(F, steps):
             raise SystemExit(f"airfoil {prec}: non-finite state after {steps} steps")
         out[prec] = {"cl": cl, "cd": cd, "mlups": round(n * steps / dt / 1e6, 1)}
         del st
+        if adj_steps > 0:
+            # the lift coefficient's gradient over adj_steps recorded steps (through the limiter's
+            # recorded clip states), against the forward time of the same steps
+            st = F.State(M, p, precision=prec, rho=np.ones(n), u=u0, k=np.full(n, kinf), omega=w0)
+            st.record(adj_steps, ckpt_every=ckpt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g, _ = st.adjoint_lift_drag(1, U, c, [1.0, 0.0])
+            torch.cuda.synchronize()
+            ta = time.perf_counter() - t0
+            tf = dt * adj_steps / steps
+            out[prec]["adjoint"] = {"steps": adj_steps, "ckpt_every": ckpt, "functional": "lift coefficient",
+                                    "adjoint_s": round(ta, 4), "ratio": round(ta / tf, 3),
+                                    "gradient": [float(x) for x in g]}
+            del st
     out["rel_diff_cl"] = abs(out["fp32dev"]["cl"] - out["fp64"]["cl"]) / abs(out["fp64"]["cl"])
     out["rel_diff_cd"] = abs(out["fp32dev"]["cd"] - out["fp64"]["cd"]) / abs(out["fp64"]["cd"])
     log(f"airfoil {steps} steps: Cl {out['fp64']['cl']:.6g} / {out['fp32dev']['cl']:.6g}, "
