@@ -493,7 +493,7 @@ void stage_ring_launch(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, co
                        const StepPar<T> &p, hipStream_t s) {
     const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
     const size_t lds = st->lds_bytes;
-    if constexpr (std::is_same_v<T, float>) {
+    if constexpr (std::is_same_v<T, float> && LIM != 3) {   // such states record no steps
         if (st->fp64_geometry) {
             k_stage_ring<T, J, S, LIM, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
             return;
@@ -510,15 +510,21 @@ void stage_ring_launch(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, co
 template <typename T, int J>
 void stage_ring(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, const StageBufs<T> &b, const StepPar<T> &p,
                 hipStream_t s) {
+    // LIM: 0 none, 1 the face-value clip of r32, 2 the gradient limiter of r35, 3 the clip of r32
+    // with its states recorded for the adjoint
     if (st->ring_s == 3) {
-        if (p.limiter == 1)
+        if (p.limiter == 1 && b.clip)
+            stage_ring_launch<T, J, 3, 3>(st, g, rt, b, p, s);
+        else if (p.limiter == 1)
             stage_ring_launch<T, J, 3, 1>(st, g, rt, b, p, s);
         else if (p.limiter == 2)
             stage_ring_launch<T, J, 3, 2>(st, g, rt, b, p, s);
         else
             stage_ring_launch<T, J, 3, 0>(st, g, rt, b, p, s);
     } else {
-        if (p.limiter == 1)
+        if (p.limiter == 1 && b.clip)
+            stage_ring_launch<T, J, 4, 3>(st, g, rt, b, p, s);
+        else if (p.limiter == 1)
             stage_ring_launch<T, J, 4, 1>(st, g, rt, b, p, s);
         else if (p.limiter == 2)
             stage_ring_launch<T, J, 4, 2>(st, g, rt, b, p, s);

@@ -1057,7 +1057,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
 #pragma unroll
     for (int a = 1; a < 9; ++a) acc[a] = T(0);
     bool bnd = false;
-    uint64_t cm = 0;   // clip states (LIM == 1, recorded steps)
+    uint64_t cm = 0;   // clip states (LIM == 3: the r32 clip of a recorded step)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const bool in = nb[s] >= 0;
@@ -1072,11 +1072,13 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             const T up_n = vn + Gl[grow<T>(loc, 2 * (a - 1))] * qx[s] + Gl[grow<T>(loc, 2 * (a - 1) + 1)] * qy[s];
             const T up_c = gc[a] + gx[a] * rx[s] + gy[a] * ry[s];
             T val = end >= T(0) ? up_c : up_n;
-            if constexpr (LIM == 1) {
+            if constexpr (LIM == 1 || LIM == 3) {
                 const T lim = clip_between(val, gc[a], vn);
-                const bool clipped = in && lim != val;
-                cm |= (uint64_t)clipped << (2 * (8 * s + a - 1));
-                cm |= (uint64_t)(clipped && lim == gc[a]) << (2 * (8 * s + a - 1) + 1);
+                if constexpr (LIM == 3) {
+                    const bool clipped = in && lim != val;
+                    cm |= (uint64_t)clipped << (2 * (8 * s + a - 1));
+                    cm |= (uint64_t)(clipped && lim == gc[a]) << (2 * (8 * s + a - 1) + 1);
+                }
                 val = lim;
             }
             acc[a] += end * val;
@@ -1108,9 +1110,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
             }
         }
     }
-    if constexpr (LIM == 1) {
-        if (b.clip) b.clip[c] = cm;
-    }
+    if constexpr (LIM == 3) b.clip[c] = cm;
     T ga[9];
     ga[0] = T(0);
 #pragma unroll

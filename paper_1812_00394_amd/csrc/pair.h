@@ -464,7 +464,7 @@ __global__ void __launch_bounds__(2 * kTileCells, 4)
 #pragma unroll
     for (int k = 0; k < 4; ++k) acc[k] = T(0);
     bool bnd = false;
-    uint64_t cm = 0;   // clip states (LIM == 1, recorded steps): bit 2 (8 s + a - 1) per slot and direction
+    uint64_t cm = 0;   // clip states (LIM == 3, recorded steps): bit 2 (8 s + a - 1) per slot and direction
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const bool in = nb[s] >= 0;
@@ -478,12 +478,14 @@ __global__ void __launch_bounds__(2 * kTileCells, 4)
             const T up_n = vn + Gl[grow<T>(loc, 8 * hf.h + 2 * k)] * qx[s] + Gl[grow<T>(loc, 8 * hf.h + 2 * k + 1)] * qy[s];
             const T up_c = gc[k] + gx[k] * rx[s] + gy[k] * ry[s];
             T val = end >= T(0) ? up_c : up_n;
-            if constexpr (LIM == 1) {
+            if constexpr (LIM == 1 || LIM == 3) {
                 const T lim = clip_between(val, gc[k], vn);
-                const bool clipped = in && lim != val;
-                const int bit = 16 * s + 8 * hf.h + 2 * k;
-                cm |= (uint64_t)clipped << bit;
-                cm |= (uint64_t)(clipped && lim == gc[k]) << (bit + 1);
+                if constexpr (LIM == 3) {
+                    const bool clipped = in && lim != val;
+                    const int bit = 16 * s + 8 * hf.h + 2 * k;
+                    cm |= (uint64_t)clipped << bit;
+                    cm |= (uint64_t)(clipped && lim == gc[k]) << (bit + 1);
+                }
                 val = lim;
             }
             acc[k] += end * val;
@@ -512,11 +514,9 @@ __global__ void __launch_bounds__(2 * kTileCells, 4)
             }
         }
     }
-    if constexpr (LIM == 1) {
-        if (b.clip) {
-            cm |= pair_swap(cm);
-            if (hf.h == 0) b.clip[c] = cm;
-        }
+    if constexpr (LIM == 3) {
+        cm |= pair_swap(cm);
+        if (hf.h == 0) b.clip[c] = cm;
     }
     // the epilogue operands after the convection term (stage 1 reads f^n and tau a second time):
     // they are not live through the gradients and the edge loop
