@@ -127,7 +127,7 @@ def test_fullsize_sampled_parity_implicit_sst(F, full):
 
 @pytest.mark.timeout(900)
 def test_backstep_fullsize_parity(F):
-    """The backward-facing step the benchmark times (122,876 hybrid cells, SST, about 34 tau0) on the
+    """The backward-facing step the benchmark times (122,876 hybrid cells, SST, 60 tau0) on the
     whole mesh, which the oracle can step: one step in FP64 and FP32-deviation storage on the ring
     path (its tiles have up to 298 ring-2 cells) against the oracle on every cell, and the FP64
     adjoint of two recorded steps with a checkpoint every step (the next segment recomputed on the
@@ -272,7 +272,7 @@ def _compare_run(F, M, p, orc, f0, k0, w0, steps, gates, u_ref, label, rho=None,
 
 @pytest.mark.timeout(900)
 def test_backstep_ten_steps_whole_mesh(F):
-    """The backstep the benchmark times (122,876 cells, SST, 34 tau0), from the seeded developed state
+    """The backstep the benchmark times (122,876 cells, SST, 60 tau0), from the seeded developed state
     of test_backstep_fullsize_parity, 10 steps on the ring path against the oracle on every cell, at
     ten times the one-step gates: FP64 1e-11 of max |f - w rho0| and 1e-10 for k, omega, nu_t;
     FP32-deviation 2e-5 of U and 2e-5 relative for k, omega."""
