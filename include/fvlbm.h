@@ -84,8 +84,9 @@ typedef struct fvlbm_state fvlbm_state;
  *              Step 1); 2: the SST solved again before the third stage, from k^n, omega^n with the
  *              second stage's macro variables, for that stage's relaxation time, the step keeping
  *              this solve's k, omega, nu_t (Step 5 read literally; the second stage's SST inputs
- *              equal the first's, whose stage solve keeps rho and u).  The adjoint entry points
- *              reject sst = 2 (FVLBM_ESTATE).
+ *              equal the first's, whose stage solve keeps rho and u).  Its adjoint reverses both
+ *              solves: the second from the third stage's tau and the step's k, omega onto the
+ *              second stage's field, the first from the tau of stages 1 and 2.
  *   a1 ... beta2  the SST constants listed in Section 2 (C_omega1/2 are derived from them)
  *   theta      inflow angle [rad]: rotates every INLET and FARFIELD velocity
  *   group_*    per boundary group: velocity (u, v), density, k, omega
@@ -99,7 +100,8 @@ typedef struct fvlbm_state fvlbm_state;
  *              [0, 1] that keeps its reconstructed values at all its edge midpoints within the
  *              least and greatest of its own value and its stencil values (neighbours, boundary
  *              ghosts): bounded on meshes with sliver cells, where the plain reconstruction has
- *              a growing mode.  The adjoint entry points reject a limited state (FVLBM_ESTATE).
+ *              a growing mode.  The adjoint differentiates limiter 1 (through the clip states its
+ *              recorded steps keep) and rejects limiter 2 (FVLBM_ESTATE).
  *   sst_sweeps 0: the SST equations advance point-implicitly (sinks implicit, face fluxes
  *              explicit).  m in [1, 1000]: they advance implicitly as Section 3.2 says of the
  *              Code_Saturne integration: backward Euler for the increments of k and omega with

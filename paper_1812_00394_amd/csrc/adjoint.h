@@ -246,6 +246,13 @@ __device__ __forceinline__ T collide_vjp(const T f[9], T m0, T mx, T my, T a, T 
 }
 
 // Buffers of the step reverse.
+// y += x over n values (the per-stage SST's two parts of the k^n, omega^n adjoints).
+template <typename T>
+__global__ void k_add(int n, const T *__restrict__ x, T *__restrict__ y) {
+    const int c = cell_index();
+    if (c < n) y[c] += x[c];
+}
+
 template <typename T>
 struct AdjBufs {
     const T *fn, *f2, *f3, *Q, *tau;        // forward data of the step (f^(1) is formed from f^n)
@@ -255,6 +262,10 @@ struct AdjBufs {
     T *lam;    // input of the transposed convection (adjoint of a convection term)
     T *lg1;    // adjoint of Ga1
     T *ltau;   // adjoint of tau
+    // per-stage SST coupling (reading r33): the third stage's relaxation time and the adjoint of it
+    // (nullptr: the third stage uses tau, whose adjoint takes its part)
+    const T *tau3 = nullptr;
+    T *ltau3 = nullptr;
 };
 
 // Reverse of the third stage and of the combination f^{n+1} = Q + dt/3 Ga3, given lf3 (the
@@ -291,7 +302,8 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
     T lg12[9];
 #pragma unroll
     for (int a = 0; a < 9; ++a) lg12[a] = -dt * T(1.0 / 6.0) * lq[a];
-    const T a3 = dt * T(1.0 / 3.0) * itau;
+    const T itau3 = b.tau3 ? recip(b.tau3[c]) : itau;
+    const T a3 = dt * T(1.0 / 3.0) * itau3;
     const T inv3 = recip(T(1) + a3);
     const T rho3 = p.rho0 + m0, ir3 = recip(rho3), ux3 = mx * ir3, uy3 = my * ir3;
     T lrhs[9], lfe[9], mb[3], abar = 0;
@@ -301,7 +313,11 @@ __device__ __forceinline__ void adj_stage3_cell(int c, int n, const T lf3[9], co
         lfe[a] = a3 * inv3 * l3[a];
         abar += l3[a] * (dfeq(a, m0, rho3, ux3, uy3) - f3d[a]) * inv3;
     }
-    T ltau = -abar * a3 * itau;
+    T ltau = T(0);
+    if (b.tau3)
+        b.ltau3[c] = -abar * a3 * itau3;
+    else
+        ltau = -abar * a3 * itau;
     feq_vjp(m0, mx, my, p.rho0, lfe, mb);
     T lfn[9];
 #pragma unroll

@@ -101,6 +101,7 @@ struct fvlbm_state {
     void *K[2] = {nullptr, nullptr}, *W[2] = {nullptr, nullptr};
     void *tau = nullptr, *nut = nullptr, *aux = nullptr;
     void *tau3 = nullptr;        // the third stage's relaxation time (per-stage SST)
+    void *aux2 = nullptr;        // while a recorded step runs with the per-stage SST: its second solve's aux planes
     int sst_stages = 0;          // the SST is solved before every stage (params.sst = 2)
     int cur_m = 0, cur_kw = 0;
     // tiles of the fused stage kernels: ring (extended halo lists), tiled (ring 1 only, with or
@@ -685,7 +686,12 @@ void launch_step(fvlbm_state *st) {
     const StageBufs<T> b3{X, nullptr, nullptr, A, nullptr, st->F_out ? (T *)st->F_out : F, Mnew, nullptr,
                           clip ? clip + 2 * nn : nullptr};
     auto sst_stage3 = [&] {
-        if (per_stage) launch_sst<T>(st, Mnew, K0, W0, K1, W1, tau3, p);
+        if (!per_stage) return;
+        // a recorded step keeps the second solve's aux planes apart from the first's
+        void *aux1 = st->aux;
+        if (st->want_aux && st->aux2) st->aux = st->aux2;
+        launch_sst<T>(st, Mnew, K0, W0, K1, W1, tau3, p);
+        st->aux = aux1;
     };
     if (st->ring) {
         // stage 1 takes f^(1) from f^n on the fly: no separate collision launch
@@ -1055,11 +1061,13 @@ void apply_advection_adjoint(fvlbm_state *st, const double *gin, const double *l
 template <typename T>
 struct AdjLayout {
     T *ckpt, *seg, *stg, *lF, *lF2, *lK, *lW, *lK2, *lW2, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
+    T *ltau3, *lK3, *lW3, *zero2;   // per-stage SST: the adjoints of tau3 and of the second solve's k^n, omega^n; [2][n] zeros
     T *seg2, *stg2;     // a second set of segment buffers when the run has more than one segment
     uint64_t *clip, *clip2;   // per step of a segment: the r32 clip states of its three sweeps [3][n]
     double *pbar;
     size_t state_len;
-    size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [15][n]
+    size_t stage_len;   // per step of a segment: f^(2), f^(3), Q [9][n] each, tau [n], aux [15][n], and for the
+                        // per-stage SST tau3 [n] and the second solve's aux [15][n]
 };
 
 // The layout with segment set k (0 or 1) as its segment buffers: segment sg of a run lives in set
@@ -1097,7 +1105,7 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, bool over
     L.state_len = sl;
     L.ckpt = cv.take<T>(nck * sl);
     L.seg = cv.take<T>((size_t)(ckpt + 1) * sl);
-    L.stage_len = 43 * (size_t)n;
+    L.stage_len = 59 * (size_t)n;
     L.stg = cv.take<T>((size_t)ckpt * L.stage_len);
     L.clip = cv.take<uint64_t>((size_t)ckpt * 3 * n);
     L.seg2 = L.stg2 = nullptr;
@@ -1123,6 +1131,10 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, bool over
     L.lnet = cv.take<T>(2 * (size_t)n);
     L.lown = cv.take<T>(4 * (size_t)n);
     L.lgrad = cv.take<T>(8 * (size_t)n);
+    L.ltau3 = cv.take<T>(n);
+    L.lK3 = cv.take<T>(n);
+    L.lW3 = cv.take<T>(n);
+    L.zero2 = cv.take<T>(2 * (size_t)n);
     L.pbar = cv.take<double>(5 * (size_t)n);
     return cv.off + 256;
 }
@@ -1163,6 +1175,7 @@ template <typename T>
 struct StageSlot {
     T *Y, *X, *A, *tau, *aux;
     uint64_t *clip;   // [3][n]: the clip states of sweeps 1, 2, 3 (face-value limiter of r32)
+    T *tau3, *aux2;   // per-stage SST: the third stage's relaxation time, the second solve's aux planes
 };
 
 template <typename T>
@@ -1170,7 +1183,7 @@ StageSlot<T> stage_slot(const fvlbm_state *st, const AdjLayout<T> &L, int i) {
     const size_t n = st->n_cells;
     T *b = L.stg + (size_t)i * L.stage_len;
     return StageSlot<T>{b, b + 9 * n, b + 18 * n, st->sst ? b + 27 * n : (T *)st->tau, b + 28 * n,
-                        L.clip + (size_t)i * 3 * n};
+                        L.clip + (size_t)i * 3 * n, b + 43 * n, b + 44 * n};
 }
 
 // Step j of a segment, in place in the segment buffers: reads the state in segment slot j, writes
@@ -1181,7 +1194,7 @@ void step_seg(fvlbm_state *st, const AdjLayout<T> &L, int j) {
     const size_t n = st->n_cells;
     T *in = L.seg + (size_t)j * L.state_len, *out = in + L.state_len;
     const StageSlot<T> ss = stage_slot<T>(st, L, j);
-    void *F = st->F, *X = st->X, *Y = st->Y, *A = st->A, *tau = st->tau, *aux = st->aux;
+    void *F = st->F, *X = st->X, *Y = st->Y, *A = st->A, *tau = st->tau, *aux = st->aux, *tau3 = st->tau3;
     void *K0 = st->K[0], *K1 = st->K[1], *W0 = st->W[0], *W1 = st->W[1];
     st->F = in;
     st->F_out = out;
@@ -1197,6 +1210,10 @@ void step_seg(fvlbm_state *st, const AdjLayout<T> &L, int j) {
         st->tau = ss.tau;
         st->aux = ss.aux;
         st->want_aux = true;
+        if (st->sst_stages) {
+            st->tau3 = ss.tau3;
+            st->aux2 = ss.aux2;
+        }
     }
     launch_step<T>(st);
     st->F = F;
@@ -1207,6 +1224,8 @@ void step_seg(fvlbm_state *st, const AdjLayout<T> &L, int j) {
     st->A = A;
     st->tau = tau;
     st->aux = aux;
+    st->tau3 = tau3;
+    st->aux2 = nullptr;
     st->K[0] = K0;
     st->K[1] = K1;
     st->W[0] = W0;
@@ -1265,35 +1284,59 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     const T *fn = slot;
     const T *Mn = st->sst ? ss.aux + 12 * (size_t)n : nullptr;
     const T *Kn = st->sst ? slot + 9 * (size_t)n : nullptr, *Wn = st->sst ? slot + 10 * (size_t)n : nullptr;
+    // per-stage SST (reading r33): the third stage's tau3 comes from a second SST solve on the
+    // stage-2 macro variables, which gives the step's k, omega; the first solve gives tau only
+    const bool per_stage = st->sst && st->sst_stages;
     AdjBufs<T> b{fn, ss.Y, ss.X, ss.A, ss.tau, L.lF, L.lF2, L.lf1, L.lf2, L.lf3, L.lam, L.lg1, L.ltau};
+    if (per_stage) {
+        b.tau3 = ss.tau3;
+        b.ltau3 = L.ltau3;
+    }
+    // the SST reverse of one solve: from the adjoints of its outputs (k, omega: lk, lw; tau: lt) to
+    // those of its inputs (the macro variables M, added onto lf through the moments of the field they
+    // came from; k^n, omega^n into lk_out, lw_out)
+    auto sst_reverse = [&](const T *M, const T *aux, const T *lk, const T *lw, const T *lt, T *lf, T *lk_out,
+                           T *lw_out) {
+        SstAdj sa{st->bzg, L.pbar};
+        if (st->ring) {
+            const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
+            const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
+            const size_t lds = adj_sst_lds<T>(st);
+            if (st->ring_s == 3)
+                k_adj_sst_ring<T, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, M, Kn, Wn, aux, lk, lw,
+                                                              lt, lf, lk_out, lw_out, p);
+            else
+                k_adj_sst_ring<T, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, M, Kn, Wn, aux, lk, lw,
+                                                              lt, lf, lk_out, lw_out, p);
+        } else {
+            k_fill<T><<<blocks_for(11 * (size_t)n), kBlock, 0, s>>>(11 * n, L.lx, T(0));
+            k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, M, Kn, Wn, aux, lk, lw, lt, L.lx, L.lnet, L.lown, p);
+            k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, M, Kn, Wn, aux, L.lnet, L.lx, p);
+            k_adj_sst_local<T><<<nbk, kBlock, 0, s>>>(g, sa, M, Kn, Wn, L.lown, L.lx, L.lgrad, p);
+            k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, M, L.lgrad, L.lx, lf, lk_out, lw_out, p.rho0);
+        }
+    };
     // stage 3: Ga3 enters f^{n+1} with weight dt/3, its transpose is applied to dt/3 lF; then the
     // reverse of the combination and of the third stage
     // with the face-value limiter of r32: the clip states the forward sweeps recorded
     const bool lim = st->par.limiter == 1;
     adv_transpose<T>(st, ss.X, nullptr, L.lF, p.dt / T(3), L.lf3, L.pbar, false, 3, b, p, lim ? ss.clip + 2 * (size_t)n : nullptr);
+    // per-stage SST: the second solve's reverse adds its part to the f^(2) adjoint before the second
+    // stage's reverse consumes it
+    if (per_stage)
+        sst_reverse(ss.aux2 + 12 * (size_t)n, ss.aux2, L.lK, L.lW, L.ltau3, L.lf2, L.lK3, L.lW3);
     // stage 2: transpose at f^(2), then its stage reverse (the Ga1 adjoint goes to lg1)
     adv_transpose<T>(st, ss.Y, nullptr, L.lam, T(1), L.lf2, L.pbar, true, 2, b, p, lim ? ss.clip + (size_t)n : nullptr);
     // stage 1: transpose at f^(1), formed from f^n, then its stage reverse
     adv_transpose<T>(st, fn, ss.tau, L.lg1, T(1), L.lf1, L.pbar, true, 1, b, p, lim ? ss.clip : nullptr);
-    if (st->sst && st->ring) {
-        // one ring-tiled launch
-        SstAdj sa{st->bzg, L.pbar};
-        const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
-        const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
-        const size_t lds = adj_sst_lds<T>(st);
-        if (st->ring_s == 3)
-            k_adj_sst_ring<T, 3><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
-                                                          L.ltau, L.lF2, L.lK2, L.lW2, p);
-        else
-            k_adj_sst_ring<T, 4><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, st->rev, wv, wg, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW,
-                                                          L.ltau, L.lF2, L.lK2, L.lW2, p);
+    if (per_stage) {
+        // the first solve's k, omega are overwritten by the second's: only its tau has an adjoint
+        k_fill<T><<<blocks_for(2 * (size_t)n), kBlock, 0, s>>>(2 * n, L.zero2, T(0));
+        sst_reverse(Mn, ss.aux, L.zero2, L.zero2 + n, L.ltau, L.lF2, L.lK2, L.lW2);
+        k_add<T><<<nbk, kBlock, 0, s>>>(n, L.lK3, L.lK2);
+        k_add<T><<<nbk, kBlock, 0, s>>>(n, L.lW3, L.lW2);
     } else if (st->sst) {
-        SstAdj sa{st->bzg, L.pbar};
-        k_fill<T><<<blocks_for(11 * (size_t)n), kBlock, 0, s>>>(11 * n, L.lx, T(0));
-        k_adj_sst_update<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lK, L.lW, L.ltau, L.lx, L.lnet, L.lown, p);
-        k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, ss.aux, L.lnet, L.lx, p);
-        k_adj_sst_local<T><<<nbk, kBlock, 0, s>>>(g, sa, Mn, Kn, Wn, L.lown, L.lx, L.lgrad, p);
-        k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, Mn, L.lgrad, L.lx, L.lF2, L.lK2, L.lW2, p.rho0);
+        sst_reverse(Mn, ss.aux, L.lK, L.lW, L.ltau, L.lF2, L.lK2, L.lW2);
     }
     check(hipGetLastError(), "kernel launch");
 }
@@ -1831,7 +1874,6 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
         if (st->fp64_geometry) throw Error(FVLBM_ESTATE, "record: FP32 storage with FP64 geometry has no adjoint here");
         if (st->par.limiter == 1 && !st->ring)
             throw Error(FVLBM_ESTATE, "record: the face-value limiter's adjoint needs the ring-tiled sweep");
-        if (st->sst_stages) throw Error(FVLBM_ESTATE, "record: the per-stage SST coupling has no adjoint here");
         if (st->sst && st->par.sst_sweeps > 0) throw Error(FVLBM_ESTATE, "record: the implicit SST variant has no adjoint here");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");
         // the layout (as fvlbm_adjoint_bytes sizes it), fixed here for the adjoint calls that follow
