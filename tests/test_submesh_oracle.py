@@ -71,3 +71,28 @@ def test_piece_reproduces_full_step(R, exact, extra):
         assert err_f < 1e-13 and err_k < 1e-13, (err_f, err_k)
     else:
         assert err_f > 1e-10, err_f
+
+
+def test_piece_reproduces_three_full_steps():
+    """Three steps reach 18 rings: a piece of 22 rings gives the sample cells' state after three full
+    oracle steps bit for bit, while one of 10 rings (short of the reach) differs in the last bits
+    (the influence of the piece's artificial boundary decays fast, so only the exact comparison
+    shows the depth matters).  The three-step full-size check cuts 22 rings."""
+    m, p, u, k, w = _case(3000)
+    n = len(m["cell_ptr"]) - 1
+    full = O.Oracle(m, p)
+    f0, k0, w0 = full.init_state(np.ones(n), u[:, 0], u[:, 1], k, w)
+    f3, k3, w3 = full.run(f0, k0, w0, 3)
+    rng = np.random.default_rng(8)
+    seeds = np.unique(np.r_[rng.choice(n, 3, replace=False), sm.boundary_cells(m, 0)[:1], sm.boundary_cells(m, 2)[:1]])
+    errs = {}
+    for R in (10, 22):
+        piece, cells = sm.cut(m, sm.rings(m, seeds, R))
+        assert len(cells) < n
+        po = O.Oracle(piece, _piece_params(p), wall_segments=sm.wall_segments(m))
+        g0, kk0, ww0 = po.init_state(np.ones(len(cells)), u[cells, 0], u[cells, 1], k[cells], w[cells])
+        g3, kk3, ww3 = po.run(g0, kk0, ww0, 3)
+        where = np.searchsorted(cells, seeds)
+        errs[R] = (np.abs(g3[:, where] - f3[:, seeds]).max(), np.abs(kk3[where] - k3[seeds]).max())
+    assert errs[22] == (0.0, 0.0), errs
+    assert errs[10][0] > 0.0, errs
