@@ -109,8 +109,9 @@ typedef struct fvlbm_state fvlbm_state;
  *              mass fluxes and coefficients), the rest of the second-order flux at level n, and
  *              the point-implicit sinks; the linear system is solved with m Jacobi sweeps from a
  *              zero increment (one SST launch that writes the system, then m - 1 sweep launches,
- *              one launch when m = 1).  Ignored when sst = 0.  The adjoint entry points reject it
- *              (FVLBM_ESTATE).  Errors: FVLBM_EINVAL outside [0, 1000].
+ *              one launch when m = 1).  Ignored when sst = 0.  The adjoint differentiates it for
+ *              m <= 16 (it keeps every sweep's increments; fvlbm_record rejects m > 16 with
+ *              FVLBM_ESTATE).  Errors: FVLBM_EINVAL outside [0, 1000].
  */
 typedef struct {
     double nu, dt, rho0;
@@ -308,8 +309,9 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *
  * fvlbm_adjoint_bytes: device bytes of the adjoint workspace for n_steps recorded steps with a
  *   checkpoint every ckpt_every steps: checkpoints (11 n values each), one segment of states
- *   (ckpt_every + 1 of 11 n values) and of stage data (43 n values per step), a second such
- *   segment when the run has more than one, adjoint fields.
+ *   (ckpt_every + 1 of 11 n values) and of stage data (59 n values per step), a second such
+ *   segment when the run has more than one, adjoint fields (including those of the implicit SST
+ *   variant's reverse, 70 n values).
  * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
  *   (f, k, omega) at the start of every segment and at the end in `workspace` (device memory owned
  *   by the caller, 256-byte aligned, kept alive until the adjoint has run).  Segments have at most
@@ -327,8 +329,9 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   buffers) runs on a stream of the library's own, created on first use, while the current
  *   segment is reversed on the caller's stream; the two are ordered by events and the call returns
  *   with all work on the caller's stream.  The reverse: the combination and stage collisions in closed
- *   form, the convection term by its transpose, the SST update, fluxes, closure and LSQ gradients
- *   by their transposes.  The state is restored to the
+ *   form, the convection term by its transpose, the SST update (or the implicit variant's system,
+ *   by its transposed Jacobi sweeps and rows), fluxes, closure and LSQ gradients by their
+ *   transposes.  The state is restored to the
  *   final recorded state afterwards.  A call that changes the state after fvlbm_record
  *   (fvlbm_step, fvlbm_step_explicit, fvlbm_run_to_residual, fvlbm_set_state) drops the recording:
  *   the tape would no longer end at the current state.  Errors: FVLBM_ESTATE without a recording

@@ -957,6 +957,328 @@ __global__ void __launch_bounds__(256) k_adj_sst_grad(Geo<T> g, SstAdj sa, const
         lfn[(size_t)a * n + s0] += lrho + (T(ex(a)) - ux) * ir * lu + (T(ey(a)) - uy) * ir * lv;
 }
 
+// ---- reverse of the implicit SST variant (params.sst_sweeps = m > 0, reading r34) ----
+// The forward (sst_row_edge, sst_row_bedge, sst_row_finish, k_sst_jacobi), per cell and phi in
+// {k, omega} with explicit source s (sk or sw) and sink dst (dt beta* omega or dt beta omega):
+//   R' = (fac net + s - dst phi) q,  C_s = c_s fac q,  q = 1 / (sigma + fac d),  fac = dt / (A rho),
+//   sigma = 1 + dst + max(-s, 0) / phi,  d = sum_s (out_s + D_s) + the boundary parts,
+//   c_s = in_s + D_s,  out_s = max(mdot_s, 0),  in_s = max(-mdot_s, 0),  D_s = (Gamma_c + Gamma_N) hn_s / 2,
+//   delta^1 = R',  delta^{i+1} = R' + sum_s C_s delta^i_N,  phi^{n+1} = max(phi + delta^m, floor),
+// then nu_t from k^{n+1}, omega^{n+1} and the strain rate S.  Its reverse replaces that of the
+// point-implicit update (k_adj_sst_update): it writes the adjoints of net, of s, beta, S (lown) and
+// adds those of the cell values (lx: rho, u, v, k, omega, Gamma_k, Gamma_omega) before the face,
+// closure and gradient reverses run as for the point-implicit update.
+
+// The floor and nu_t: from the adjoints of k^{n+1}, omega^{n+1}, tau to that of delta^m (ld) and of
+// k^n, omega^n (lx); the strain rate's (aux plane 9) goes to lown[3].  dm: delta^m [2][n].
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_impl_fin(Geo<T> g, SstAdj sa, const T *__restrict__ aux,
+                                                      const T *__restrict__ dm, const T *__restrict__ K,
+                                                      const T *__restrict__ W, const T *__restrict__ lk1,
+                                                      const T *__restrict__ lw1, const T *__restrict__ ltau,
+                                                      T *__restrict__ ld, T *__restrict__ lx, T *__restrict__ lown,
+                                                      StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const size_t n = (size_t)g.n;
+    const T kr = K[c] + dm[c], wr = W[c] + dm[n + c];
+    const bool kpass = kr >= T(1e-20), wpass = wr >= T(1e-20);
+    const T k1 = kpass ? kr : T(1e-20), w1 = wpass ? wr : T(1e-20);
+    T kb = lk1[c], wb = lw1[c], Srb = 0;
+    SstParBar<T> pb;
+    sst_nut_rev(k1, w1, aux[9 * n + c], T(g.wdist[c]), p, sst_params(p), T(3) * ltau[c], kb, wb, Srb, pb);
+    kb = kpass ? kb : T(0);
+    wb = wpass ? wb : T(0);
+    ld[c] = kb;
+    ld[n + c] = wb;
+    lx[3 * n + c] += kb;
+    lx[4 * n + c] += wb;
+    lown[3 * n + c] = Srb;
+    sa.pbar[4 * n + c] += (double)pb.a1;
+}
+
+// One transposed Jacobi sweep: lin = the adjoint of delta^i.  Adds lin to lR (the adjoint of R'),
+// lin_c delta^{i-1}_N to lC (the adjoints of the couplings C_s, [8][n] as in J), and gathers the
+// adjoint of delta^{i-1} through the couplings that point back: lout_j = sum_s C_(N, rev) lin_N.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_impl_sweep(Geo<T> g, const int8_t *__restrict__ rev,
+                                                        const T *__restrict__ J, const T *__restrict__ lin,
+                                                        const T *__restrict__ dprev, T *__restrict__ lR,
+                                                        T *__restrict__ lC, T *__restrict__ lout) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const size_t n = (size_t)g.n;
+    const T lk = lin[c], lw = lin[n + c];
+    lR[c] += lk;
+    lR[n + c] += lw;
+    T ok = T(0), ow = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb < 0) continue;
+        lC[si] += lk * dprev[nb];
+        lC[4 * n + si] += lw * dprev[n + nb];
+        const size_t sj = (size_t)rev[si] * n + nb;
+        ok += J[sj] * lin[nb];
+        ow += J[4 * n + sj] * lin[n + nb];
+    }
+    if (lout) {
+        lout[c] = ok;
+        lout[n + c] = ow;
+    }
+}
+
+// The row of cell c, formed again from the solve's recorded inputs (as sst_row_edge, sst_row_bedge
+// and sst_row_finish form it): M, K, W the macro variables and k, omega the solve started from;
+// aux its closure outputs (Gamma in planes 4, 5, s in 6, 7, beta in 8) and net inflows (10, 11).
+// Slots without an interior neighbour keep mdot = hn = c = 0.
+template <typename T>
+struct ImplRow {
+    T rho, ux, uy, kc, wc, Gk, Gw, sk, sw, beta, net_k, net_w;
+    T dk, dw, fac, dstk, dstw, mk, mw, ik_k, ik_w, qk, qw, Nk, Nw;
+    T mdot[4], hn[4], ck[4], cw[4];
+};
+
+template <typename T>
+__device__ __forceinline__ void impl_row(const Geo<T> &g, const SstAdj &sa, const T *__restrict__ M,
+                                         const T *__restrict__ K, const T *__restrict__ W, const T *__restrict__ aux,
+                                         int c, const StepPar<T> &p, ImplRow<T> &r) {
+    const size_t n = (size_t)g.n;
+    const T zero = T(0), one = T(1), dt = p.dt;
+    r.rho = p.rho0 + M[c];
+    r.ux = M[n + c];
+    r.uy = M[2 * n + c];
+    r.kc = K[c];
+    r.wc = W[c];
+    r.Gk = aux[4 * n + c];
+    r.Gw = aux[5 * n + c];
+    r.sk = aux[6 * n + c];
+    r.sw = aux[7 * n + c];
+    r.beta = aux[8 * n + c];
+    r.net_k = aux[10 * n + c];
+    r.net_w = aux[11 * n + c];
+    r.dk = r.dw = zero;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        r.mdot[s] = r.hn[s] = r.ck[s] = r.cw[s] = zero;
+        if (nb >= 0) {
+            const T rn = p.rho0 + M[nb], un = M[n + nb], vn = M[2 * n + nb];
+            const T nlx = g.nlx[si], nly = g.nly[si];
+            r.mdot[s] = T(0.5) * ((r.rho * r.ux + rn * un) * nlx + (r.rho * r.uy + rn * vn) * nly);
+            const T ddx = g.rfx[si] - g.qx[si], ddy = g.rfy[si] - g.qy[si];
+            r.hn[s] = (ddx * nlx + ddy * nly) * recip(ddx * ddx + ddy * ddy);
+            const T Dk = T(0.5) * (r.Gk + aux[4 * n + nb]) * r.hn[s], Dw = T(0.5) * (r.Gw + aux[5 * n + nb]) * r.hn[s];
+            const T out = tmax(r.mdot[s], zero), in = tmax(-r.mdot[s], zero);
+            r.dk = r.dk + out + Dk;
+            r.dw = r.dw + out + Dw;
+            r.ck[s] = in + Dk;
+            r.cw[s] = in + Dw;
+        } else if (nb <= -2) {
+            const int b = -2 - nb;
+            const bool zg = sa.bzg[b] != 0;
+            const T bux = zg ? r.ux : T(g.b_ux[b]), buy = zg ? r.uy : T(g.b_uy[b]);
+            const T mb = r.rho * (bux * g.nlx[si] + buy * g.nly[si]);
+            const T own = (zg || mb >= zero) ? mb : zero;
+            r.dk = r.dk + own;
+            r.dw = r.dw + own;
+            if (!zg) {
+                const T lod = T(g.b_l[b] / g.b_dperp[b]);
+                r.dk = r.dk + r.Gk * lod;
+                r.dw = r.dw + r.Gw * lod;
+            }
+        }
+    }
+    r.fac = T(dt * g.inv_area[c]) * recip(r.rho);
+    r.dstk = dt * p.bstar * r.wc;
+    r.dstw = dt * r.beta * r.wc;
+    r.mk = tmax(-r.sk, zero);
+    r.mw = tmax(-r.sw, zero);
+    r.ik_k = recip(r.kc);
+    r.ik_w = recip(r.wc);
+    r.qk = recip(one + r.dstk + r.mk * r.ik_k + r.fac * r.dk);
+    r.qw = recip(one + r.dstw + r.mw * r.ik_w + r.fac * r.dw);
+    r.Nk = r.fac * r.net_k + r.sk - r.dstk * r.kc;
+    r.Nw = r.fac * r.net_w + r.sw - r.dstw * r.wc;
+}
+
+// The system again (planes 0-9 of the forward's J: the couplings of k and omega per slot, R' of
+// both), for the recomputed sweeps and their transposes.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_impl_sys(Geo<T> g, SstAdj sa, const T *__restrict__ M,
+                                                      const T *__restrict__ K, const T *__restrict__ W,
+                                                      const T *__restrict__ aux, T *__restrict__ J, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const size_t n = (size_t)g.n;
+    ImplRow<T> r;
+    impl_row(g, sa, M, K, W, aux, c, p, r);
+    const T gk = r.fac * r.qk, gw = r.fac * r.qw;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        J[(size_t)s * n + c] = r.ck[s] * gk;
+        J[(size_t)(4 + s) * n + c] = r.cw[s] * gw;
+    }
+    J[8 * n + c] = r.Nk * r.qk;
+    J[9 * n + c] = r.Nw * r.qw;
+}
+
+// The rows' reverse, cell c: from the adjoints of R' (lR) and of the couplings (lC) to those of net
+// (lnet), s and beta (lown[0..2]), of the cell's rho, u, v, k, omega, Gamma_k, Gamma_omega (lx) and
+// of beta* and theta (pbar); the parts that belong to the neighbours' rho, u, v (through mdot) and
+// Gamma (through D) go per edge slot to lslot [4][4][n]: (dJ/dmdot) nl / 2 (x, y), and
+// (dJ/dD) hn / 2 for k and omega.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_impl_rows(Geo<T> g, SstAdj sa, const T *__restrict__ M,
+                                                       const T *__restrict__ K, const T *__restrict__ W,
+                                                       const T *__restrict__ aux, const T *__restrict__ lR,
+                                                       const T *__restrict__ lC, T *__restrict__ lx,
+                                                       T *__restrict__ lnet, T *__restrict__ lown,
+                                                       T *__restrict__ lslot, StepPar<T> p) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const size_t n = (size_t)g.n;
+    const T zero = T(0), dt = p.dt;
+    ImplRow<T> r;
+    impl_row(g, sa, M, K, W, aux, c, p, r);
+    const T gk = r.fac * r.qk, gw = r.fac * r.qw;
+    // R' = N q and C_s = c_s fac q
+    const T lRk = lR[c], lRw = lR[n + c];
+    T lgk = zero, lgw = zero, lck[4], lcw[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const T a = lC[(size_t)s * n + c], b = lC[(size_t)(4 + s) * n + c];
+        lgk += a * r.ck[s];
+        lgw += b * r.cw[s];
+        lck[s] = a * gk;
+        lcw[s] = b * gw;
+    }
+    const T lNk = lRk * r.qk, lNw = lRw * r.qw;
+    const T lqk = lRk * r.Nk + lgk * r.fac, lqw = lRw * r.Nw + lgw * r.fac;
+    T lfac = lgk * r.qk + lgw * r.qw;
+    // q = 1 / (sigma + fac d): the adjoint of the denominator is that of sigma
+    const T lsk_ = -lqk * r.qk * r.qk, lsw_ = -lqw * r.qw * r.qw;
+    lfac += lsk_ * r.dk + lsw_ * r.dw;
+    const T ldk = lsk_ * r.fac, ldw = lsw_ * r.fac;
+    // N = fac net + s - dst phi
+    lfac += lNk * r.net_k + lNw * r.net_w;
+    T lsk = lNk, lsw = lNw;
+    const T ldstk = -lNk * r.kc + lsk_, ldstw = -lNw * r.wc + lsw_;
+    T lk = -lNk * r.dstk, lw = -lNw * r.dstw;
+    // sigma = 1 + dst + max(-s, 0) / phi
+    if (-r.sk >= zero) lsk -= lsk_ * r.ik_k;
+    lk -= lsk_ * r.mk * r.ik_k * r.ik_k;
+    if (-r.sw >= zero) lsw -= lsw_ * r.ik_w;
+    lw -= lsw_ * r.mw * r.ik_w * r.ik_w;
+    // dst = dt beta* omega (k), dt beta omega (omega)
+    lw += ldstk * dt * p.bstar + ldstw * dt * r.beta;
+    const T lbeta = ldstw * dt * r.wc;
+    const double lbstar = (double)(ldstk * dt * r.wc);
+    // fac = dt / (A rho)
+    T lrho = -lfac * r.fac * recip(r.rho), lu = zero, lv = zero, lGk = zero, lGw = zero;
+    double lth = 0.0;
+    // d = sum (out + D) + the boundary parts, c = in + D
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        T sA = zero, sB = zero, sK = zero, sW = zero;
+        if (nb >= 0) {
+            const T lDk = ldk + lck[s], lDw = ldw + lcw[s];
+            T lm = zero;
+            if (r.mdot[s] >= zero) lm += ldk + ldw;          // out = max(mdot, 0)
+            if (-r.mdot[s] >= zero) lm -= lck[s] + lcw[s];   // in = max(-mdot, 0)
+            const T nlx = g.nlx[si], nly = g.nly[si];
+            // mdot = (rho u + rho_N u_N) . nl / 2
+            lrho += T(0.5) * lm * (r.ux * nlx + r.uy * nly);
+            lu += T(0.5) * lm * r.rho * nlx;
+            lv += T(0.5) * lm * r.rho * nly;
+            sA = T(0.5) * lm * nlx;
+            sB = T(0.5) * lm * nly;
+            // D = (Gamma_c + Gamma_N) hn / 2
+            sK = T(0.5) * r.hn[s] * lDk;
+            sW = T(0.5) * r.hn[s] * lDw;
+            lGk += sK;
+            lGw += sW;
+        } else if (nb <= -2) {
+            const int b = -2 - nb;
+            const bool zg = sa.bzg[b] != 0;
+            const T bux = zg ? r.ux : T(g.b_ux[b]), buy = zg ? r.uy : T(g.b_uy[b]);
+            const T nlx = g.nlx[si], nly = g.nly[si];
+            const T mb = r.rho * (bux * nlx + buy * nly);
+            if (zg || mb >= zero) {
+                const T lm = ldk + ldw;
+                lrho += lm * (bux * nlx + buy * nly);
+                if (zg) {
+                    lu += lm * r.rho * nlx;
+                    lv += lm * r.rho * nly;
+                } else {
+                    const int kind = g.b_kind[b];
+                    if (kind == kInlet || kind == kFarfield)   // the rotated inflow: d ub / d theta = (-ub_y, ub_x)
+                        lth += (double)(lm * r.rho * (-T(g.b_uy[b]) * nlx + T(g.b_ux[b]) * nly));
+                }
+            }
+            if (!zg) {
+                const T lod = T(g.b_l[b] / g.b_dperp[b]);
+                lGk += ldk * lod;
+                lGw += ldw * lod;
+            }
+        }
+        lslot[si] = sA;
+        lslot[4 * n + si] = sB;
+        lslot[8 * n + si] = sK;
+        lslot[12 * n + si] = sW;
+    }
+    lnet[c] = lNk * r.fac;
+    lnet[n + c] = lNw * r.fac;
+    lown[c] = lsk;
+    lown[n + c] = lsw;
+    lown[2 * n + c] = lbeta;
+    lx[c] += lrho;
+    lx[n + c] += lu;
+    lx[2 * n + c] += lv;
+    lx[3 * n + c] += lk;
+    lx[4 * n + c] += lw;
+    lx[9 * n + c] += lGk;
+    lx[10 * n + c] += lGw;
+    sa.pbar[3 * n + c] += lbstar;
+    sa.pbar[c] += lth;
+}
+
+// The neighbours' parts of the rows' reverse, gathered per cell j: each interior edge's slot seen
+// from the neighbour N (through rev) gives the adjoint of j's rho, u, v through N's mdot and of j's
+// Gamma through N's D.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adj_impl_gather(Geo<T> g, const int8_t *__restrict__ rev,
+                                                         const T *__restrict__ M, const T *__restrict__ lslot,
+                                                         T *__restrict__ lx, T rho0) {
+    const int j = cell_index();
+    if (j >= g.n) return;
+    const size_t n = (size_t)g.n;
+    const T rho = rho0 + M[j], ux = M[n + j], uy = M[2 * n + j];
+    T lrho = 0, lu = 0, lv = 0, lGk = 0, lGw = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + j;
+        const int nb = g.nbr[si];
+        if (nb < 0) continue;
+        const size_t sn = (size_t)rev[si] * n + nb;
+        const T A = lslot[sn], B = lslot[4 * n + sn];
+        lrho += A * ux + B * uy;
+        lu += A * rho;
+        lv += B * rho;
+        lGk += lslot[8 * n + sn];
+        lGw += lslot[12 * n + sn];
+    }
+    lx[j] += lrho;
+    lx[n + j] += lu;
+    lx[2 * n + j] += lv;
+    lx[9 * n + j] += lGk;
+    lx[10 * n + j] += lGw;
+}
+
 // ---- ring-tiled SST reverse: update, faces, closure and LSQ gradients in one launch ----
 // The layout of the ring-tiled forward kernels.  x = the 11 cell values of the face fluxes
 // (rho, u, v, k, omega, grad k, grad omega, Gamma_k, Gamma_omega).

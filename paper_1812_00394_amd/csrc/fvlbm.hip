@@ -34,6 +34,9 @@ void check(hipError_t e, const char *what) {
 constexpr int kBlock = 256;
 constexpr int kRedBlocks = 512;   // fixed reduction grid (deterministic sums)
 constexpr int kMaxSstSweeps = 1000;
+// the adjoint reverses the implicit SST variant for at most this many sweeps (it keeps every
+// sweep's increments)
+constexpr int kMaxAdjSstSweeps = 16;
 
 inline int blocks_for(int64_t n) { return (int)((n + kBlock - 1) / kBlock); }
 
@@ -593,14 +596,18 @@ void launch_sst(fvlbm_state *st, const T *M, const T *K0, const T *W0, T *K1, T 
         Timed t(st, FVLBM_K_SST);
         const auto args = std::make_tuple(g, rt, st->lnb, wv, wg, st->bzg, M, K0, W0, aux, K1, W1, tau_out, nut, J, p);
         if (st->ring_s == 3) {
-            if (impl)
+            if (impl && st->want_aux)
+                sst_ring_launch<T, 3, true, true>(st, nt, lds, s, args);
+            else if (impl)
                 sst_ring_launch<T, 3, false, true>(st, nt, lds, s, args);
             else if (st->want_aux)
                 sst_ring_launch<T, 3, true, false>(st, nt, lds, s, args);
             else
                 sst_ring_launch<T, 3, false, false>(st, nt, lds, s, args);
         } else {
-            if (impl)
+            if (impl && st->want_aux)
+                sst_ring_launch<T, 4, true, true>(st, nt, lds, s, args);
+            else if (impl)
                 sst_ring_launch<T, 4, false, true>(st, nt, lds, s, args);
             else if (st->want_aux)
                 sst_ring_launch<T, 4, true, false>(st, nt, lds, s, args);
@@ -1062,6 +1069,10 @@ template <typename T>
 struct AdjLayout {
     T *ckpt, *seg, *stg, *lF, *lF2, *lK, *lW, *lK2, *lW2, *lf1, *lf2, *lf3, *lam, *lg1, *ltau, *lx, *lnet, *lown, *lgrad;
     T *ltau3, *lK3, *lW3, *zero2;   // per-stage SST: the adjoints of tau3 and of the second solve's k^n, omega^n; [2][n] zeros
+    // the implicit SST variant's reverse: its system again (planes 0-9 of J), the increments of
+    // sweeps 2 .. m [kMaxAdjSstSweeps - 1][2][n], the adjoints of R' [2][n], of the couplings [8][n],
+    // of the increments (two [2][n] buffers), and the neighbours' parts of the rows' reverse [16][n]
+    T *Jr, *dlt, *lR, *lC, *ld0, *ld1, *lslot;
     T *seg2, *stg2;     // a second set of segment buffers when the run has more than one segment
     uint64_t *clip, *clip2;   // per step of a segment: the r32 clip states of its three sweeps [3][n]
     double *pbar;
@@ -1135,6 +1146,13 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, bool over
     L.lK3 = cv.take<T>(n);
     L.lW3 = cv.take<T>(n);
     L.zero2 = cv.take<T>(2 * (size_t)n);
+    L.Jr = cv.take<T>(10 * (size_t)n);
+    L.dlt = cv.take<T>((size_t)(kMaxAdjSstSweeps - 1) * 2 * n);
+    L.lR = cv.take<T>(2 * (size_t)n);
+    L.lC = cv.take<T>(8 * (size_t)n);
+    L.ld0 = cv.take<T>(2 * (size_t)n);
+    L.ld1 = cv.take<T>(2 * (size_t)n);
+    L.lslot = cv.take<T>(16 * (size_t)n);
     L.pbar = cv.take<double>(5 * (size_t)n);
     return cv.off + 256;
 }
@@ -1298,7 +1316,33 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     auto sst_reverse = [&](const T *M, const T *aux, const T *lk, const T *lw, const T *lt, T *lf, T *lk_out,
                            T *lw_out) {
         SstAdj sa{st->bzg, L.pbar};
-        if (st->ring) {
+        const int m = st->par.sst_sweeps;
+        if (m > 0) {
+            // the implicit variant (reading r34): its system again, the increments of sweeps 2 .. m,
+            // the reverse of the floor and nu_t, the transposed sweeps, the rows' reverse; then the
+            // face, closure and gradient reverses as for the point-implicit update
+            const size_t nn = (size_t)n;
+            auto delta = [&](int i) { return i == 1 ? L.Jr + 8 * nn : L.dlt + (size_t)(i - 2) * 2 * nn; };
+            k_adj_impl_sys<T><<<nbk, kBlock, 0, s>>>(g, sa, M, Kn, Wn, aux, L.Jr, p);
+            for (int i = 2; i <= m; ++i)
+                k_sst_jacobi<T, 4, true, false><<<nbk, kBlock, 0, s>>>(g, L.Jr, delta(i - 1), delta(i), nullptr, nullptr,
+                                                                    nullptr, nullptr, nullptr, nullptr, p);
+            k_fill<T><<<blocks_for(11 * nn), kBlock, 0, s>>>(11 * n, L.lx, T(0));
+            k_fill<T><<<blocks_for(2 * nn), kBlock, 0, s>>>(2 * n, L.lR, T(0));
+            k_fill<T><<<blocks_for(8 * nn), kBlock, 0, s>>>(8 * n, L.lC, T(0));
+            T *lin = L.ld0, *lout = L.ld1;
+            k_adj_impl_fin<T><<<nbk, kBlock, 0, s>>>(g, sa, aux, delta(m), Kn, Wn, lk, lw, lt, lin, L.lx, L.lown, p);
+            for (int i = m; i >= 2; --i) {
+                k_adj_impl_sweep<T><<<nbk, kBlock, 0, s>>>(g, st->rev, L.Jr, lin, delta(i - 1), L.lR, L.lC, lout);
+                std::swap(lin, lout);
+            }
+            k_add<T><<<blocks_for(2 * nn), kBlock, 0, s>>>(2 * n, lin, L.lR);
+            k_adj_impl_rows<T><<<nbk, kBlock, 0, s>>>(g, sa, M, Kn, Wn, aux, L.lR, L.lC, L.lx, L.lnet, L.lown, L.lslot, p);
+            k_adj_impl_gather<T><<<nbk, kBlock, 0, s>>>(g, st->rev, M, L.lslot, L.lx, p.rho0);
+            k_adj_sst_faces<T><<<nbk, kBlock, 0, s>>>(g, sa, M, Kn, Wn, aux, L.lnet, L.lx, p);
+            k_adj_sst_local<T><<<nbk, kBlock, 0, s>>>(g, sa, M, Kn, Wn, L.lown, L.lx, L.lgrad, p);
+            k_adj_sst_grad<T><<<nbk, kBlock, 0, s>>>(g, sa, st->rev, M, L.lgrad, L.lx, lf, lk_out, lw_out, p.rho0);
+        } else if (st->ring) {
             const RingTiles rt{st->xptr, st->xn1, st->xcell, st->xlnb, (int32_t)std::max<size_t>(1, st->mesh->ext_cell.size())};
             const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
             const size_t lds = adj_sst_lds<T>(st);
@@ -1874,7 +1918,8 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
         if (st->fp64_geometry) throw Error(FVLBM_ESTATE, "record: FP32 storage with FP64 geometry has no adjoint here");
         if (st->par.limiter == 1 && !st->ring)
             throw Error(FVLBM_ESTATE, "record: the face-value limiter's adjoint needs the ring-tiled sweep");
-        if (st->sst && st->par.sst_sweeps > 0) throw Error(FVLBM_ESTATE, "record: the implicit SST variant has no adjoint here");
+        if (st->sst && st->par.sst_sweeps > kMaxAdjSstSweeps)
+            throw Error(FVLBM_ESTATE, "record: the implicit SST variant's adjoint takes at most " + std::to_string(kMaxAdjSstSweeps) + " sweeps");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");
         // the layout (as fvlbm_adjoint_bytes sizes it), fixed here for the adjoint calls that follow
         st->adj_two_sets = adjoint_two_sets(st->mesh);

@@ -295,6 +295,44 @@ __device__ __forceinline__ T sst_bface_rev(const T xc[11], bool zg, bool rot, T 
     return rot ? bux_b * (-uby) + buy_b * ubx : T(0);
 }
 
+// Reverse of sst_nut: given the adjoint of nu_t, adds to the adjoints of k1, omega1 (kb, wb) and of
+// the strain rate (Sr_b), and to that of a1.
+template <typename T>
+__device__ __forceinline__ void sst_nut_rev(T k1, T w1, T Sr, T d, const StepPar<T> &p, const SstParams<T> &q, T nut_bar,
+                                            T &kb, T &wb, T &Sr_b, SstParBar<T> &pb) {
+    const T idd = recip(d);
+    const T sk1 = ssqrt(k1);
+    const T iw1 = recip(w1);
+    const T A = T(2.0 / 0.09) * sk1 * iw1 * idd;
+    const T B = T(500) * p.nu * iw1 * idd * idd;
+    const bool a_first = A >= B;
+    const T arg2 = a_first ? A : B;
+    const T F2 = stanh(arg2 * arg2);
+    const bool den_first = q.a1 * w1 >= Sr * F2;
+    const T den = den_first ? q.a1 * w1 : Sr * F2;
+    const T iden = recip(den);
+    const T nut = q.a1 * k1 * iden;
+    kb += nut_bar * q.a1 * iden;
+    pb.a1 += nut_bar * k1 * iden;
+    const T den_b = -nut_bar * nut * iden;
+    T F2_b = 0;
+    if (den_first) {
+        pb.a1 += den_b * w1;
+        wb += den_b * q.a1;
+    } else {
+        Sr_b += den_b * F2;
+        F2_b += den_b * Sr;
+    }
+    const T arg2_b = F2_b * sech2(arg2 * arg2) * T(2) * arg2;
+    if (a_first) {
+        const T sk1_b = arg2_b * T(2.0 / 0.09) * iw1 * idd;
+        wb -= arg2_b * A * iw1;
+        kb += sk1 > T(0) ? sk1_b * T(0.5) * recip(sk1) : T(0);
+    } else {
+        wb -= arg2_b * B * iw1;
+    }
+}
+
 // Reverse of sst_update: given the adjoints of k1, omega1 and nu_t, adds to the adjoints of rho,
 // k, omega (xb[0..2]) and returns those of net_k, net_w, sk, sw, beta, Sr in ob[0..5].
 template <typename T>
@@ -314,39 +352,9 @@ __device__ __forceinline__ void sst_update_rev(T rho, T k, T w, T net_k, T net_w
     const T kr = kn * ikd, wr = wn * iwd;
     const bool kpass = kr >= T(1e-20), wpass = wr >= T(1e-20);
     const T k1 = kpass ? kr : T(1e-20), w1 = wpass ? wr : T(1e-20);
-    const T idd = recip(d);
-    const T sk1 = ssqrt(k1);
-    const T iw1 = recip(w1);
-    const T A = T(2.0 / 0.09) * sk1 * iw1 * idd;
-    const T B = T(500) * p.nu * iw1 * idd * idd;
-    const bool a_first = A >= B;
-    const T arg2 = a_first ? A : B;
-    const T F2 = stanh(arg2 * arg2);
-    const bool den_first = q.a1 * w1 >= Sr * F2;
-    const T den = den_first ? q.a1 * w1 : Sr * F2;
-    const T iden = recip(den);
-    const T nut = q.a1 * k1 * iden;
     // reverse
-    T kb = k1_bar + nut_bar * q.a1 * iden;
-    T wb = w1_bar;
-    pb.a1 += nut_bar * k1 * iden;
-    const T den_b = -nut_bar * nut * iden;
-    T Sr_b = 0, F2_b = 0;
-    if (den_first) {
-        pb.a1 += den_b * w1;
-        wb += den_b * q.a1;
-    } else {
-        Sr_b += den_b * F2;
-        F2_b += den_b * Sr;
-    }
-    const T arg2_b = F2_b * sech2(arg2 * arg2) * T(2) * arg2;
-    if (a_first) {
-        const T sk1_b = arg2_b * T(2.0 / 0.09) * iw1 * idd;
-        wb -= arg2_b * A * iw1;
-        kb += sk1 > T(0) ? sk1_b * T(0.5) * recip(sk1) : T(0);
-    } else {
-        wb -= arg2_b * B * iw1;
-    }
+    T kb = k1_bar, wb = w1_bar, Sr_b = 0;
+    sst_nut_rev(k1, w1, Sr, d, p, q, nut_bar, kb, wb, Sr_b, pb);
     const T kr_b = kpass ? kb : T(0), wr_b = wpass ? wb : T(0);
     const T kn_b = kr_b * ikd, kd_b = -kr_b * kr * ikd;
     const T wn_b = wr_b * iwd, wd_b = -wr_b * wr * iwd;

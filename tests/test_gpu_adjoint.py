@@ -173,6 +173,38 @@ def test_per_stage_sst_adjoint(F, name, sweep, monkeypatch):
     _check_run_adjoint(F, m, p, f0, k0, w0, sst, 3)
 
 
+@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("m_sweeps", [1, 5])
+@pytest.mark.parametrize("name", ["backstep_sst", "naca_sst"])
+def test_implicit_sst_adjoint(F, name, m_sweeps, sweep, monkeypatch):
+    """The adjoint of the implicit SST variant (params.sst_sweeps = m, reading r34): the increments'
+    system formed again from the recorded closure, m - 1 transposed Jacobi sweeps, the reverse of
+    the rows (mass fluxes, diffusion conductances, sinks, sources) onto the macro variables, k^n,
+    omega^n, Gamma, s, beta and the parameters.  Dot product of a 3-step recorded run's adjoint
+    (checkpoint every 2) with the oracle's complex step, within 1e-9, and the parameter gradients
+    within 1e-8."""
+    say("implicit sst adjoint", name, m_sweeps, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
+    m, p, orc, f0, k0, w0, sst = _run_case(name, seed=85)
+    p = dict(p, sst_sweeps=m_sweeps)
+    # the variant is active: its k differs from the point-implicit update's
+    a = O.Oracle(m, p).run(f0, k0, w0, 2)[1]
+    b = O.Oracle(m, dict(p, sst_sweeps=0)).run(f0, k0, w0, 2)[1]
+    assert np.abs(a - b).max() > 1e-6 * np.abs(a).max()
+    _check_run_adjoint(F, m, p, f0, k0, w0, sst, 3)
+
+
+def test_implicit_sst_adjoint_sweep_limit(F):
+    """Recording refuses the implicit variant beyond 16 sweeps (the reverse keeps every sweep's
+    increments), before it changes the state."""
+    m, p, orc, f0, k0, w0, sst = _run_case("backstep_sst", seed=85)
+    st = F.State(F.Mesh(m), dict(p, sst_sweeps=17), precision="fp64", k=k0, omega=w0)
+    st.set_state(f0, k0, w0)
+    with pytest.raises(F.FvlbmError, match="ESTATE"):
+        st.record(2, ckpt_every=2)
+    np.testing.assert_array_equal(st.get_f(), f0)
+
+
 def _check_run_adjoint(F, m, p, f0, k0, w0, sst, N):
     """Records N steps (checkpoint every 2) and checks the adjoint's dot product with the oracle's
     complex-step derivative along a random direction (1e-9) and the five parameter gradients of
