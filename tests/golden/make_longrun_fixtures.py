@@ -1,12 +1,16 @@
 #!/usr/bin/env python3
 """Writes tests/golden/longrun_<case>.json: the oracle's state at sampled cells after 10, 100, 500,
-1000, 2000 (and 3000) steps of two full-size workloads, for the GPU long-run parity tests.
+1000 and 2000 steps (the backstep) or 10, 100 and 500 steps (the airfoil) of two full-size workloads, for the GPU long-run parity tests.
 
   backstep: the 122,876-cell backward-facing step (Re_h 3.6e4, SST, dt = min(60 tau0, 0.9 of the
             advective Courant limit)), from rest, 2000 steps;
   airfoil:  the 512 x 384 O-mesh around the 12 % section (Re 6e6, 10 degrees, dt = min(180 tau0, 0.9
-            of the Courant limit), face-value limiter of reading r32, developed near-wall start), 3000
-            steps.
+            of the Courant limit), face-value limiter of reading r32, developed near-wall start), 500
+            steps.  From about step 900 omega falls in a few cells at the trailing edge and reaches
+            its floor (1e-20) by step 1300; nu_t = a1 k / max(a1 omega, S F2) is then bounded only
+            by S F2, and runs that differ by rounding separate (the oracle's own run had left the
+            GPU's by step 1000, while the oracle restarted from the GPU's FP64 state at step 500
+            still tracked it at step 1000).
 
 Per checkpoint: f (9 values), k, omega, nu_t at 160 sampled cells (seeded: anywhere, wall cells, and where
 the flow starts), the
@@ -30,7 +34,7 @@ sys.path.insert(0, ROOT)
 from oracle import fvlbm_oracle as O                  # noqa: E402
 from paper_1812_00394_amd import meshgen as mg        # noqa: E402
 
-CHECKPOINTS = (10, 100, 500, 1000, 2000, 3000)
+CHECKPOINTS = (10, 100, 500, 1000, 2000)
 
 
 def mesh_sha(m):
@@ -74,7 +78,7 @@ def case(name):
         orc = O.Oracle(m, p)
         n = G.n
         f0, k0, w0 = orc.init_state(np.ones(n), U * np.cos(alpha) * fac, U * np.sin(alpha) * fac, np.full(n, kinf), w0)
-        return m, p, orc, f0, k0, w0, 3000, 1, (U, c)
+        return m, p, orc, f0, k0, w0, 500, 1, (U, c)
     raise SystemExit(f"unknown case {name}")
 
 

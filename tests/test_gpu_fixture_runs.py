@@ -1,10 +1,10 @@
 """Long runs of the two full-size workloads against stored oracle runs (tests/golden/longrun_*.json,
 written by tests/golden/make_longrun_fixtures.py, which calls only the oracle and the seeded mesh
 generator): the backward-facing step from rest (Re_h 3.6e4, SST, 2000 steps) and the airfoil (Re 6e6,
-10 degrees, SST, face-value limiter of reading r32, developed near-wall start, 3000 steps).  At
-every stored checkpoint the GPU state at the sampled cells (anywhere, at the walls and where the
-flow starts) is compared with the oracle's, in FP64 and in FP32-deviation storage, as are the wall
-force and, for the airfoil, the lift and drag coefficients.
+10 degrees, SST, face-value limiter of reading r32, developed near-wall start, 500 steps; the generator
+says why it stops there).  At every stored checkpoint the GPU state at the sampled cells (anywhere,
+at the walls and where the flow starts) is compared with the oracle's, in FP64 and in FP32-deviation
+storage, as are the wall force and, for the airfoil, the lift and drag coefficients.
 
 Gates (per checkpoint, after N steps), on the scales rounding acts on: FP64 f within 2e-14 N rho0
 (f itself is O(w rho0), and from rest its deviation from w rho0 is small), k, omega and nu_t within
