@@ -101,7 +101,8 @@ typedef struct fvlbm_state fvlbm_state;
  *              least and greatest of its own value and its stencil values (neighbours, boundary
  *              ghosts): bounded on meshes with sliver cells, where the plain reconstruction has
  *              a growing mode.  The adjoint differentiates limiter 1 (through the clip states its
- *              recorded steps keep) and rejects limiter 2 (FVLBM_ESTATE).
+ *              recorded steps keep) and limiter 2 on the two-kernel sweeps (FVLBM_SWEEP=split or
+ *              face; recording rejects it on the ring-tiled sweeps with FVLBM_ESTATE).
  *   sst_sweeps 0: the SST equations advance point-implicitly (sinks implicit, face fluxes
  *              explicit).  m in [1, 1000]: they advance implicitly as Section 3.2 says of the
  *              Code_Saturne integration: backward Euler for the increments of k and omega with

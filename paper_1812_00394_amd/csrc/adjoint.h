@@ -96,7 +96,9 @@ __device__ __forceinline__ T ghost_vjp(const Geo<T> &g, int b, T nlx, T nly, con
 
 // L, gbar: [9][n] (direction 0 of L unused); Gbar: [16][n].  Every edge except the ghost-state
 // parts, which k_adv_T1b adds.
-template <typename T>
+// OWN = false leaves out the own part of the transposed LSQ gradient (the gradient limiter's reverse,
+// k_adv_T_bj, adds it from the adjoint of the unlimited gradient).
+template <typename T, bool OWN = true>
 __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ L, T lscale, T *__restrict__ gbar,
                                                 T *__restrict__ Gbar) {
     const int j = cell_index();
@@ -144,16 +146,18 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
         }
     }
     // own part of the transposed LSQ gradient: grad g_j = sum_k c_jk (v_k - g_j)
-    T sx = 0, sy = 0;
+    if constexpr (OWN) {
+        T sx = 0, sy = 0;
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-        const size_t si = (size_t)s * n + j;
-        if (g.nbr[si] == -1) continue;
-        sx += g.cx[si];
-        sy += g.cy[si];
+        for (int s = 0; s < 4; ++s) {
+            const size_t si = (size_t)s * n + j;
+            if (g.nbr[si] == -1) continue;
+            sx += g.cx[si];
+            sy += g.cy[si];
+        }
+#pragma unroll
+        for (int a = 1; a < 9; ++a) gd[a] -= sx * Gx[a] + sy * Gy[a];
     }
-#pragma unroll
-    for (int a = 1; a < 9; ++a) gd[a] -= sx * Gx[a] + sy * Gy[a];
 #pragma unroll
     for (int a = 0; a < 9; ++a) gbar[(size_t)a * n + j] += gd[a];
 #pragma unroll
@@ -165,9 +169,12 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
 
 // Interior neighbours' part of the transposed LSQ gradient.  rev[k][s]: the slot of neighbour
 // nbr[k][s] that points back to s.
-template <typename T>
+// BJ: also the gradient limiter's bound parts (k_adv_T_bj): a neighbour whose limiting bound was
+// this cell's value (its code, the slot it reached this cell through) passes lD on.
+template <typename T, bool BJ = false>
 __global__ void __launch_bounds__(256) k_adv_T2(Geo<T> g, const int8_t *__restrict__ rev, const T *__restrict__ Gbar,
-                                                T *__restrict__ gbar) {
+                                                T *__restrict__ gbar, const T *__restrict__ lD = nullptr,
+                                                const int8_t *__restrict__ code = nullptr) {
     const int s0 = cell_index();
     if (s0 >= g.n) return;
     const int n = g.n;
@@ -184,9 +191,172 @@ __global__ void __launch_bounds__(256) k_adv_T2(Geo<T> g, const int8_t *__restri
 #pragma unroll
         for (int a = 1; a < 9; ++a)
             acc[a] += cx * Gbar[(size_t)(2 * (a - 1)) * n + j] + cy * Gbar[(size_t)(2 * (a - 1) + 1) * n + j];
+        if constexpr (BJ) {
+            const int8_t back = rev[si];
+#pragma unroll
+            for (int a = 1; a < 9; ++a) {
+                const size_t aj = (size_t)(a - 1) * n + j;
+                if (code[aj] == back) acc[a] += lD[aj];
+            }
+        }
     }
 #pragma unroll
     for (int a = 1; a < 9; ++a) gbar[(size_t)a * n + s0] += acc[a];
+}
+
+// Reverse of the gradient limiter of reading r35 on the two-kernel paths (after k_adv_T1 without
+// its own part, before k_adv_T1b and k_adv_T2), cell c per thread.  The forward, per direction a of
+// the stage field v (f, or its stage solve with a = a_dt / tau1): g the LSQ gradient, lo <= 0 <= hi
+// the least and greatest difference v_s - v_c over the stencil (neighbours and ghost states, in slot
+// order, the first extreme kept), psi = min(1, min over the edges of hi / (g . r_s) for increments
+// g . r_s > 0 and lo / (g . r_s) for negative ones), and the limited gradient psi g.  Where the
+// minimum is an edge s*, psi = D / (g . r_s*) with D = hi or lo, so with lambda the adjoint of
+// psi g (Gbar on entry):
+//   adjoint of g = psi lambda - (lambda . g) (psi / (g . r_s*)) r_s*,
+//   adjoint of D = (lambda . g) / (g . r_s*), which goes to the value that set the bound (minus to
+// the cell's own): to a ghost state through its Jacobian here, to an interior neighbour through
+// lD / code [8][n] (the slot of that neighbour, -1 for none), gathered by k_adv_T2<T, true>.  Gbar
+// leaves as the adjoint of g, and the own part of the transposed LSQ gradient is added to gbar.
+template <typename T>
+__global__ void __launch_bounds__(256) k_adv_T_bj(Geo<T> g, const T *__restrict__ f, const T *__restrict__ tau1,
+                                                  T a_dt, T rho0, T *__restrict__ Gbar, T *__restrict__ gbar,
+                                                  T *__restrict__ lD, int8_t *__restrict__ code,
+                                                  double *__restrict__ dth) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    // the stage field at the cell
+    T vc[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) vc[a] = f[(size_t)a * n + c];
+    if (tau1) {
+        T f1[9], fe[9];
+        stage_collide(vc, a_dt * recip(tau1[c]), rho0, f1, fe);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) vc[a] = f1[a];
+    }
+    T drho, rho, ux, uy;
+    moments(vc, rho0, drho, rho, ux, uy);
+    // the forward: unlimited gradient and stencil bounds with the slots that set them
+    T gx[9], gy[9], lo[9], hi[9];
+    int8_t slo[9], shi[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) {
+        gx[a] = gy[a] = lo[a] = hi[a] = T(0);
+        slo[a] = shi[a] = -1;
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb == -1) continue;
+        T v[9];
+        if (nb >= 0) {
+#pragma unroll
+            for (int a = 0; a < 9; ++a) v[a] = f[(size_t)a * n + nb];
+            if (tau1) {
+                T f1[9], fe[9];
+                stage_collide(v, a_dt * recip(tau1[nb]), rho0, f1, fe);
+#pragma unroll
+                for (int a = 0; a < 9; ++a) v[a] = f1[a];
+            }
+        } else {
+            ghost(g, -2 - nb, g.nlx[si], g.nly[si], vc, drho, rho, ux, uy, v);
+        }
+        const T cxs = g.cx[si], cys = g.cy[si];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const T d = v[a] - vc[a];
+            gx[a] += cxs * d;
+            gy[a] += cys * d;
+            if (d < lo[a]) {
+                lo[a] = d;
+                slo[a] = (int8_t)s;
+            }
+            if (d > hi[a]) {
+                hi[a] = d;
+                shi[a] = (int8_t)s;
+            }
+        }
+    }
+    // psi and the edge that sets it; the reverse
+    T gbx[4][9];   // adjoints of the ghost states, per boundary slot
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int a = 0; a < 9; ++a) gbx[s][a] = T(0);
+    T own[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) own[a] = T(0);
+#pragma unroll
+    for (int a = 1; a < 9; ++a) {
+        T psi = T(1), inc_s = T(0), rsx = T(0), rsy = T(0);
+        int ss = -1;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const size_t si = (size_t)s * n + c;
+            if (g.nbr[si] == -1) continue;
+            const T rx = g.rfx[si], ry = g.rfy[si];
+            const T inc = gx[a] * rx + gy[a] * ry;
+            const T r = inc > T(0) ? hi[a] / inc : (inc < T(0) ? lo[a] / inc : T(1));
+            if (r < psi) {
+                psi = r;
+                ss = s;
+                inc_s = inc;
+                rsx = rx;
+                rsy = ry;
+            }
+        }
+        const size_t ga = (size_t)(2 * (a - 1)) * n + c, gb = (size_t)(2 * (a - 1) + 1) * n + c;
+        const T lx = Gbar[ga], ly = Gbar[gb];
+        T ogx = lx, ogy = ly, dD = T(0);
+        int js = -1;
+        if (ss >= 0) {
+            const T lpsi = lx * gx[a] + ly * gy[a];
+            const T q = psi / inc_s;
+            ogx = psi * lx - lpsi * q * rsx;
+            ogy = psi * ly - lpsi * q * rsy;
+            js = inc_s > T(0) ? shi[a] : slo[a];
+            dD = lpsi / inc_s;
+        }
+        Gbar[ga] = ogx;
+        Gbar[gb] = ogy;
+        const size_t aj = (size_t)(a - 1) * n + c;
+        lD[aj] = T(0);
+        code[aj] = -1;
+        if (js >= 0) {
+            own[a] -= dD;
+            const int nbj = g.nbr[(size_t)js * n + c];
+            if (nbj >= 0) {
+                lD[aj] = dD;
+                code[aj] = (int8_t)js;
+            } else {
+                gbx[js][a] += dD;
+            }
+        }
+        // own part of the transposed LSQ gradient, with the unlimited gradient's adjoint
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const size_t si = (size_t)s * n + c;
+            if (g.nbr[si] == -1) continue;
+            own[a] -= g.cx[si] * ogx + g.cy[si] * ogy;
+        }
+    }
+    // ghost states that set a bound
+    T th = T(0);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb > -2) continue;
+        bool any = false;
+#pragma unroll
+        for (int a = 1; a < 9; ++a) any = any || gbx[s][a] != T(0);
+        if (any) th += ghost_vjp(g, -2 - nb, g.nlx[si], g.nly[si], vc, rho0, gbx[s], own);
+    }
+    if (th != T(0)) dth[c] += (double)th;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) gbar[(size_t)a * n + c] += own[a];
 }
 
 }  // namespace fvlbm
@@ -266,6 +436,9 @@ struct AdjBufs {
     // (nullptr: the third stage uses tau, whose adjoint takes its part)
     const T *tau3 = nullptr;
     T *ltau3 = nullptr;
+    // gradient limiter of reading r35: the bound parts k_adv_T_bj passes to the neighbours [8][n]
+    T *lD = nullptr;
+    int8_t *bjc = nullptr;
 };
 
 // Reverse of the third stage and of the combination f^{n+1} = Q + dt/3 Ga3, given lf3 (the

@@ -128,7 +128,7 @@ def test_long_run_against_stored_oracle_run(F, name):
                 cl = st.lift_drag(mask, ld[0], ld[1])
                 ref = np.asarray(rec["lift_drag"])
                 e = np.abs(cl - ref).max() / np.abs(ref).max()
-                say(name, precision, "step", steps, "drag, lift", cl, "oracle", ref, "error", e)
+                say(name, precision, "step", steps, "lift, drag", cl, "oracle", ref, "error", e)
                 if not e < (1e-11 * steps if precision == "fp64" else 1e-3):
                     fails.append((precision, steps, "lift/drag", e))
         del st

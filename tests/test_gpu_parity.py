@@ -456,7 +456,8 @@ def test_limited_sst_step_parity_and_no_adjoint(F, limiter):
     st.step(2)
     assert rel(st.get_f(), fo, dev_scale(fo)) < 1e-11
     assert rel(st.moments()["k"], ko, np.abs(ko).max()) < 1e-10
-    # the adjoint differentiates the face-value clip (limiter 1), not the gradient limiter (2)
+    # on the ring sweeps the adjoint differentiates the face-value clip (limiter 1), not the gradient
+    # limiter (2), whose adjoint runs on the two-kernel sweeps
     if limiter == 2:
         with pytest.raises(F.FvlbmError, match="ESTATE"):
             st.record(2, 1)
