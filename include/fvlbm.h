@@ -65,7 +65,9 @@ enum {
 /* storage / arithmetic of f: FP64; FP32 deviations from w_a rho0 (the ring sweeps stream FP32 copies
  * of the geometry, with the LSQ coefficients rounded once from FP64); FP32 deviations whose ring
  * sweeps stream FP64 geometry and form normals, midpoint offsets and LSQ coefficients in FP64 before
- * the FP32 flux arithmetic (forward only: ring-tiled sweeps, no adjoint) */
+ * the FP32 flux arithmetic (ring-tiled sweeps only; its recorded steps run the same kernels, and
+ * the adjoint's transposed sweeps take the FP32 copies of the geometry, so its gradient is that of
+ * the forward to within the FP32 rounding of the geometry) */
 enum { FVLBM_FP64 = 0, FVLBM_FP32_DEV = 1, FVLBM_FP32_DEV_GEO64 = 2 };
 enum { FVLBM_ORDER_NONE = 0, FVLBM_ORDER_MORTON = 1, FVLBM_ORDER_RCM = 2, FVLBM_ORDER_TILES = 3 };
 

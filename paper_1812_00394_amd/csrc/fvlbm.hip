@@ -497,7 +497,7 @@ void stage_ring_launch(fvlbm_state *st, const Geo<T> &g, const RingTiles &rt, co
                        const StepPar<T> &p, hipStream_t s) {
     const int nt = st->mesh->n_tiles, wv = st->ring_wv, wg = st->ring_wg;
     const size_t lds = st->lds_bytes;
-    if constexpr (std::is_same_v<T, float> && LIM != 3) {   // such states record no steps
+    if constexpr (std::is_same_v<T, float>) {
         if (st->fp64_geometry) {
             k_stage_ring<T, J, S, LIM, true><<<nt, kTileCells, lds, s>>>(g, rt, st->lnb, wv, wg, b, p);
             return;
@@ -565,13 +565,12 @@ void launch_sst_jacobi(fvlbm_state *st, const T *K0, const T *W0, T *K1, T *W1, 
 }
 
 // One ring launch of the SST kernel; FP32 states with FP64 geometry take the kernel that forms the
-// edge data from the FP64 copies (the aux planes are written only for the adjoint, which such
-// states do not support).
+// edge data from the FP64 copies.
 template <typename T, int S, bool AUX, bool IMPL, typename Args>
 void sst_ring_launch(const fvlbm_state *st, int nt, size_t lds, hipStream_t s, const Args &a) {
     std::apply(
         [&](auto &&...x) {
-            if constexpr (std::is_same_v<T, float> && !AUX) {
+            if constexpr (std::is_same_v<T, float>) {
                 if (st->fp64_geometry) {
                     k_sst_ring<T, S, AUX, IMPL, true><<<nt, kTileCells, lds, s>>>(x...);
                     return;
@@ -1917,7 +1916,8 @@ fvlbm_status fvlbm_adjoint_bytes(const fvlbm_mesh *m, int32_t precision, int32_t
     return guarded([&] {
         if (!m || !bytes) throw Error(FVLBM_EINVAL, "adjoint_bytes: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "adjoint_bytes: n_steps and ckpt_every must be >= 1");
-        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV) throw Error(FVLBM_EINVAL, "adjoint_bytes: bad precision (the adjoint supports FP64 and FP32_DEV)");
+        if (precision != FVLBM_FP64 && precision != FVLBM_FP32_DEV && precision != FVLBM_FP32_DEV_GEO64)
+            throw Error(FVLBM_EINVAL, "adjoint_bytes: bad precision");
         Carver cv;
         if (precision == FVLBM_FP64) {
             AdjLayout<double> L;
@@ -1935,7 +1935,6 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
         if (st->par.limiter == 2 && st->ring)
             throw Error(FVLBM_ESTATE, "record: the gradient limiter's (limiter 2) adjoint needs the two-kernel sweeps (FVLBM_SWEEP=split or face)");
-        if (st->fp64_geometry) throw Error(FVLBM_ESTATE, "record: FP32 storage with FP64 geometry has no adjoint here");
         if (st->par.limiter == 1 && !st->ring)
             throw Error(FVLBM_ESTATE, "record: the face-value limiter's adjoint needs the ring-tiled sweep");
         if (st->sst && st->par.sst_sweeps > kMaxAdjSstSweeps)

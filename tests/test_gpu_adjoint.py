@@ -205,6 +205,46 @@ def test_implicit_sst_adjoint_sweep_limit(F):
     np.testing.assert_array_equal(st.get_f(), f0)
 
 
+@pytest.mark.parametrize("name", ["backstep_sst", "naca_sst"])
+def test_fp32_with_fp64_geometry_adjoint(F, name, monkeypatch):
+    """The adjoint of an FP32-deviation state whose ring sweeps form the edge data from FP64 geometry
+    (precision fp32dev_geo64): its recorded steps run those kernels, its reverse the FP32-geometry
+    transposes.  The gradient of lam . final state over 3 recorded steps (checkpoint every 2) meets
+    the FP32 gate of check_fp32_gradient against the oracle's complex step, and stays within that
+    gate of the FP32-geometry state's gradient; the recorded run ends at the unrecorded run's state."""
+    say("fp32dev_geo64 adjoint", name)
+    monkeypatch.setenv("FVLBM_SWEEP", "ring")
+    m, p, orc, f0, k0, w0, sst = _run_case(name, seed=87)
+    n = f0.shape[1]
+    N = 3
+    rng = np.random.default_rng(88)
+    lf = rng.standard_normal((9, n))
+    lk = rng.standard_normal(n) * 1e3
+    lw = rng.standard_normal(n)
+    M = F.Mesh(m)
+    grads = {}
+    for precision in ("fp32dev", "fp32dev_geo64"):
+        plain = F.State(M, p, precision=precision, k=k0, omega=w0)
+        plain.set_state(f0, k0, w0)
+        plain.step(N)
+        st = F.State(M, p, precision=precision, k=k0, omega=w0)
+        st.set_state(f0, k0, w0)
+        st.record(N, ckpt_every=2)
+        np.testing.assert_array_equal(st.get_f(), plain.get_f())
+        grads[precision] = st.adjoint_state(lf, lk, lw)[3]
+        del st, plain
+    ref = []
+    for key in PARAMS:
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        fN, kN, wN = _oracle_final(m, pc, f0.astype(complex), k0.astype(complex), w0.astype(complex), N)
+        ref.append((np.sum(lf * np.imag(fN)) + np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))) / H)
+    ref = np.asarray(ref)
+    print("fp32dev", grads["fp32dev"], "fp32dev_geo64", grads["fp32dev_geo64"], "complex step", ref)
+    check_fp32_gradient(grads["fp32dev_geo64"], ref)
+    check_fp32_gradient(grads["fp32dev_geo64"], grads["fp32dev"])
+
+
 def _check_run_adjoint(F, m, p, f0, k0, w0, sst, N):
     """Records N steps (checkpoint every 2) and checks the adjoint's dot product with the oracle's
     complex-step derivative along a random direction (1e-9) and the five parameter gradients of
