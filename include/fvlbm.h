@@ -103,8 +103,8 @@ typedef struct fvlbm_state fvlbm_state;
  *              least and greatest of its own value and its stencil values (neighbours, boundary
  *              ghosts): bounded on meshes with sliver cells, where the plain reconstruction has
  *              a growing mode.  The adjoint differentiates limiter 1 (through the clip states its
- *              recorded steps keep) and limiter 2 on the two-kernel sweeps (FVLBM_SWEEP=split or
- *              face; recording rejects it on the ring-tiled sweeps with FVLBM_ESTATE).
+ *              recorded steps keep) and limiter 2 (its reverse runs on the two-kernel transposes,
+ *              whichever sweep ran forward).
  *   sst_sweeps 0: the SST equations advance point-implicitly (sinks implicit, face fluxes
  *              explicit).  m in [1, 1000]: they advance implicitly as Section 3.2 says of the
  *              Code_Saturne integration: backward Euler for the increments of k and omega with
@@ -314,7 +314,7 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   checkpoint every ckpt_every steps: checkpoints (11 n values each), one segment of states
  *   (ckpt_every + 1 of 11 n values) and of stage data (59 n values per step), a second such
  *   segment when the run has more than one, adjoint fields (including those of the implicit SST
- *   variant's reverse, 70 n values).
+ *   variant's reverse, 70 n values, and of the two-kernel transposes, 24 n values and 8 n bytes).
  * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
  *   (f, k, omega) at the start of every segment and at the end in `workspace` (device memory owned
  *   by the caller, 256-byte aligned, kept alive until the adjoint has run).  Segments have at most

@@ -14,7 +14,7 @@ Paper: Wang, Zhong, Cao, Zhuo, "A simplified finite volume lattice Boltzmann met
 Extension towards turbulent flow simulation" (arXiv 1812.00394).  Citations below name the
 section and equation label of that paper.  Where the paper defers to its Part I (equilibrium,
 face values, gradients, boundary conditions) or is garbled, the readings used are listed at the
-top of each function and collected in the design notes (readings r1-r34).
+top of each function and collected in the design notes (readings r1-r35).
 
 Half-face convention: every cell edge, seen from its cell, is one "half-face" h with
   cell[h], nbr[h] (-1 on a boundary), bface[h] (-1 inside), nl[h] = outward normal times length,

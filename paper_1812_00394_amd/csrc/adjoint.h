@@ -439,6 +439,9 @@ struct AdjBufs {
     // gradient limiter of reading r35: the bound parts k_adv_T_bj passes to the neighbours [8][n]
     T *lD = nullptr;
     int8_t *bjc = nullptr;
+    // the gradient-plane adjoints of the two-kernel transposes [16][n] (nullptr: the state's own
+    // gradient planes, which a recompute on the side stream of a ring-tiled state may be using)
+    T *Gb = nullptr;
 };
 
 // Reverse of the third stage and of the combination f^{n+1} = Q + dt/3 Ga3, given lf3 (the

@@ -1000,9 +1000,9 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
     // the ring kernel hands its input values to the stage-3 / 2 reverse, which read the same arrays
     if ((epi == 3 && lam != ab.lnext) || (epi == 2 && lam != ab.lam))
         throw Error(FVLBM_EINVAL, "adv_transpose: the transposed input is not the stage reverse's");
-    if (st->ring && p.limiter == 2)
-        throw Error(FVLBM_ESTATE, "adv_transpose: the gradient limiter's adjoint needs the two-kernel sweeps");
-    if (st->ring) {
+    // the gradient limiter of r35 reverses on the two-kernel transposes, whatever sweep ran forward
+    // (they read the global geometry and gradient planes, which every state holds)
+    if (st->ring && p.limiter != 2) {
         // one launch: the boundary cells' ghost parts are fused into the ring kernel
         const bool s3 = st->ring_s == 3;
 #define FVLBM_T_RING(S_, ACC_, EPI_) launch_T_ring<T, S_, ACC_, EPI_>(st, f, tau1, a_dt, lam, lscale, out, dth, ab, p, clip)
@@ -1021,22 +1021,23 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
     }
     if (clip) throw Error(FVLBM_ESTATE, "adv_transpose: the limited convection's adjoint needs the ring-tiled sweep");
     if (!acc) k_fill<T><<<blocks_for(9 * (size_t)g.n), kBlock, 0, s>>>(9 * g.n, out, T(0));
+    T *Gb = ab.Gb ? ab.Gb : (T *)st->G;
     // the gradient limiter of r35: its reverse between the edge part and the LSQ transposes
     const bool bj = p.limiter == 2;
     if (bj && !(ab.lD && ab.bjc)) throw Error(FVLBM_ESTATE, "adv_transpose: the gradient limiter's reverse has no buffers");
     if (bj) {
-        k_adv_T1<T, false><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, (T *)st->G);
-        k_adv_T_bj<T><<<nbk, kBlock, 0, s>>>(g, f, tau1, a_dt, T(st->par.rho0), (T *)st->G, out, ab.lD, ab.bjc, dth);
+        k_adv_T1<T, false><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, Gb);
+        k_adv_T_bj<T><<<nbk, kBlock, 0, s>>>(g, f, tau1, a_dt, T(st->par.rho0), Gb, out, ab.lD, ab.bjc, dth);
     } else {
-        k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, (T *)st->G);
+        k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, Gb);
     }
     if (g.nb > 0)
-        k_adv_T1b<T, 0><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)st->G, dth,
+        k_adv_T1b<T, 0><<<blocks_for(g.nb), kBlock, 0, s>>>(g, f, tau1, a_dt, lam, lscale, out, (const T *)Gb, dth,
                                                             T(st->par.rho0), ab, p);
     if (bj)
-        k_adv_T2<T, true><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, out, ab.lD, ab.bjc);
+        k_adv_T2<T, true><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)Gb, out, ab.lD, ab.bjc);
     else
-        k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)st->G, out);
+        k_adv_T2<T><<<nbk, kBlock, 0, s>>>(g, st->rev, (const T *)Gb, out);
     if (epi == 3)
         k_adj_stage<T, 3><<<nbk, kBlock, 0, s>>>(g.n, ab, p, out);
     else if (epi == 2)
@@ -1087,6 +1088,7 @@ struct AdjLayout {
     T *Jr, *dlt, *lR, *lC, *ld0, *ld1, *lslot;
     T *lD;              // the gradient limiter's reverse (reading r35): bound parts [8][n] and their codes
     int8_t *bjc;
+    T *Gb;              // gradient-plane adjoints of the two-kernel transposes [16][n]
     T *seg2, *stg2;     // a second set of segment buffers when the run has more than one segment
     uint64_t *clip, *clip2;   // per step of a segment: the r32 clip states of its three sweeps [3][n]
     double *pbar;
@@ -1169,6 +1171,7 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, bool over
     L.lslot = cv.take<T>(16 * (size_t)n);
     L.lD = cv.take<T>(8 * (size_t)n);
     L.bjc = cv.take<int8_t>(8 * (size_t)n);
+    L.Gb = cv.take<T>(16 * (size_t)n);
     L.pbar = cv.take<double>(5 * (size_t)n);
     return cv.off + 256;
 }
@@ -1328,6 +1331,7 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     }
     b.lD = L.lD;
     b.bjc = L.bjc;
+    b.Gb = L.Gb;
     // the SST reverse of one solve: from the adjoints of its outputs (k, omega: lk, lw; tau: lt) to
     // those of its inputs (the macro variables M, added onto lf through the moments of the field they
     // came from; k^n, omega^n into lk_out, lw_out)
@@ -1933,8 +1937,6 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
     return guarded([&] {
         if (!st || !workspace) throw Error(FVLBM_EINVAL, "record: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
-        if (st->par.limiter == 2 && st->ring)
-            throw Error(FVLBM_ESTATE, "record: the gradient limiter's (limiter 2) adjoint needs the two-kernel sweeps (FVLBM_SWEEP=split or face)");
         if (st->par.limiter == 1 && !st->ring)
             throw Error(FVLBM_ESTATE, "record: the face-value limiter's adjoint needs the ring-tiled sweep");
         if (st->sst && st->par.sst_sweeps > kMaxAdjSstSweeps)

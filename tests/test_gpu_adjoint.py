@@ -546,15 +546,16 @@ def test_lift_drag_adjoint_against_complex_step(F, precision):
 
 
 
-@pytest.mark.parametrize("sweep", ["split", "face"])
+@pytest.mark.parametrize("sweep", ["ring", "split", "face"])
 @pytest.mark.parametrize("name", ["duct_laminar", "naca_sst"])
 def test_gradient_limiter_adjoint_against_complex_step(F, name, sweep, monkeypatch):
-    """The adjoint through the gradient limiter of reading r35 (the two-kernel sweeps): the reverse
-    finds again, from the recorded stage fields, each direction's limiting edge and the stencil value
-    that set its bound, and passes the adjoint of psi on to the unlimited gradient, that value and the
-    cell's own.  Dot product of a 3-step recorded run's adjoint (checkpoint every 2) with the oracle's
-    complex step, within 1e-9, and the parameter gradients within 1e-8.  The case must limit: the
-    limited oracle run differs from the unlimited one.  On the ring sweeps recording refuses it."""
+    """The adjoint through the gradient limiter of reading r35 (on the two-kernel transposes, whichever
+    sweep ran forward): the reverse finds again, from the recorded stage fields, each direction's
+    limiting edge and the stencil value that set its bound, and passes the adjoint of psi on to the
+    unlimited gradient, that value and the cell's own.  Dot product of a 3-step recorded run's
+    adjoint (checkpoint every 2) with the oracle's complex step, within 1e-9, and the parameter
+    gradients within 1e-8.  The case must limit: the limited oracle run differs from the unlimited
+    one."""
     say("gradient limiter adjoint", name, sweep)
     monkeypatch.setenv("FVLBM_SWEEP", sweep)
     m, p, orc, f0, k0, w0, sst = _run_case(name, seed=99)
@@ -565,10 +566,6 @@ def test_gradient_limiter_adjoint_against_complex_step(F, name, sweep, monkeypat
     print("effect of the limiter on the state after 3 steps:", change)
     assert change > 1e-6, change
     _check_run_adjoint(F, m, p, f0, k0, w0, sst, 3)
-    monkeypatch.setenv("FVLBM_SWEEP", "ring")
-    st = F.State(F.Mesh(m), p, precision="fp64", k=k0, omega=w0)
-    with pytest.raises(F.FvlbmError, match="ESTATE"):
-        st.record(2, ckpt_every=1)
 
 
 @pytest.mark.parametrize("sweep", ["ring", "pair"])
