@@ -205,16 +205,19 @@ def test_implicit_sst_adjoint_sweep_limit(F):
     np.testing.assert_array_equal(st.get_f(), f0)
 
 
-@pytest.mark.parametrize("name", ["backstep_sst", "naca_sst"])
-def test_fp32_with_fp64_geometry_adjoint(F, name, monkeypatch):
+@pytest.mark.parametrize("name, limiter", [("backstep_sst", 0), ("naca_sst", 0), ("naca_sst", 1)])
+def test_fp32_with_fp64_geometry_adjoint(F, name, limiter, monkeypatch):
     """The adjoint of an FP32-deviation state whose ring sweeps form the edge data from FP64 geometry
     (precision fp32dev_geo64): its recorded steps run those kernels, its reverse the FP32-geometry
     transposes.  The gradient of lam . final state over 3 recorded steps (checkpoint every 2) meets
     the FP32 gate of check_fp32_gradient against the oracle's complex step, and stays within that
-    gate of the FP32-geometry state's gradient; the recorded run ends at the unrecorded run's state."""
-    say("fp32dev_geo64 adjoint", name)
+    gate of the FP32-geometry state's gradient; the recorded run ends at the unrecorded run's state
+    (bitwise; with the face-value limiter, whose recorded sweeps also keep the clip states, to FP32
+    rounding)."""
+    say("fp32dev_geo64 adjoint", name, "limiter", limiter)
     monkeypatch.setenv("FVLBM_SWEEP", "ring")
     m, p, orc, f0, k0, w0, sst = _run_case(name, seed=87)
+    p = dict(p, limiter=limiter)
     n = f0.shape[1]
     N = 3
     rng = np.random.default_rng(88)
@@ -230,7 +233,12 @@ def test_fp32_with_fp64_geometry_adjoint(F, name, monkeypatch):
         st = F.State(M, p, precision=precision, k=k0, omega=w0)
         st.set_state(f0, k0, w0)
         st.record(N, ckpt_every=2)
-        np.testing.assert_array_equal(st.get_f(), plain.get_f())
+        if limiter == 0:
+            np.testing.assert_array_equal(st.get_f(), plain.get_f())
+        else:
+            # the recording kernels of the clip are other instantiations: FP32 rounding apart
+            fp = plain.get_f()
+            assert np.abs(st.get_f() - fp).max() <= 1e-6 * np.abs(fp - O.WT[:, None]).max()
         grads[precision] = st.adjoint_state(lf, lk, lw)[3]
         del st, plain
     ref = []
