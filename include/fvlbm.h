@@ -321,8 +321,8 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   ckpt_every steps and are counted from the end of the run (only the first may be shorter); the
  *   last two (the last one when the run has one segment) are kept whole, with their stage data, in
  *   the two sets of segment buffers, so that the reverse recomputes neither.  With the face-value
- *   limiter (limiter 1) the recorded sweeps keep its clip states, which only the ring-tiled sweeps
- *   record: on the other sweeps fvlbm_record returns FVLBM_ESTATE.  Errors: FVLBM_EINVAL (NULL,
+ *   limiter (limiter 1) the ring-tiled sweeps keep its clip states in the stage data; after the
+ *   other sweeps the reverse forms them again from the recorded stage fields.  Errors: FVLBM_EINVAL (NULL,
  *   n_steps or ckpt_every < 1, workspace misaligned or too small), FVLBM_ESTATE.
  * fvlbm_adjoint_step: for J = seed[0] F_x + seed[1] F_y + seed[2] J_R of the final state (forces of
  *   the walls in wall_group_mask and the reversed-flow length, as fvlbm_forces), returns

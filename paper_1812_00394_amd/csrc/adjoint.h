@@ -97,10 +97,12 @@ __device__ __forceinline__ T ghost_vjp(const Geo<T> &g, int b, T nlx, T nly, con
 // L, gbar: [9][n] (direction 0 of L unused); Gbar: [16][n].  Every edge except the ghost-state
 // parts, which k_adv_T1b adds.
 // OWN = false leaves out the own part of the transposed LSQ gradient (the gradient limiter's reverse,
-// k_adv_T_bj, adds it from the adjoint of the unlimited gradient).
-template <typename T, bool OWN = true>
+// k_adv_T_bj, adds it from the adjoint of the unlimited gradient).  CLIP: the face-value limiter of
+// reading r32 with the clip states of k_clip_states (as the ring-tiled transpose takes them: a
+// clipped edge's weight goes to the cell whose value bounded it, from that cell's own edge loop).
+template <typename T, bool OWN = true, bool CLIP = false>
 __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ L, T lscale, T *__restrict__ gbar,
-                                                T *__restrict__ Gbar) {
+                                                T *__restrict__ Gbar, const uint64_t *__restrict__ clip = nullptr) {
     const int j = cell_index();
     if (j >= g.n) return;
     const int n = g.n;
@@ -120,14 +122,29 @@ __global__ void __launch_bounds__(256) k_adv_T1(Geo<T> g, const T *__restrict__ 
         const T nlx = g.nlx[si], nly = g.nly[si], rx = g.rfx[si], ry = g.rfy[si];
         if (nb >= 0) {
             const T ian = g.inv_area[nb];
+            if constexpr (CLIP) {
+                const uint64_t cm = clip[j];
 #pragma unroll
-            for (int a = 1; a < 9; ++a) {
-                const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
-                if (en > T(0)) {
-                    const T w = en * (mu[a] + (lscale * L[(size_t)a * n + nb]) * ian);
-                    gd[a] += w;
-                    Gx[a] += w * rx;
-                    Gy[a] += w * ry;
+                for (int a = 1; a < 9; ++a) {
+                    const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+                    const int bit = 2 * (8 * s + a - 1);
+                    const bool clipped = (cm >> bit) & 1, self = (cm >> (bit + 1)) & 1;
+                    const T wa = en * (mu[a] + (lscale * L[(size_t)a * n + nb]) * ian);
+                    const T wr = (!clipped && en > T(0)) ? wa : T(0);
+                    gd[a] += clipped ? (self ? wa : T(0)) : wr;
+                    Gx[a] += wr * rx;
+                    Gy[a] += wr * ry;
+                }
+            } else {
+#pragma unroll
+                for (int a = 1; a < 9; ++a) {
+                    const T en = T(ex(a)) * nlx + T(ey(a)) * nly;
+                    if (en > T(0)) {
+                        const T w = en * (mu[a] + (lscale * L[(size_t)a * n + nb]) * ian);
+                        gd[a] += w;
+                        Gx[a] += w * rx;
+                        Gy[a] += w * ry;
+                    }
                 }
             }
         } else {
@@ -202,6 +219,40 @@ __global__ void __launch_bounds__(256) k_adv_T2(Geo<T> g, const int8_t *__restri
     }
 #pragma unroll
     for (int a = 1; a < 9; ++a) gbar[(size_t)a * n + s0] += acc[a];
+}
+
+// The clip states of the face-value limiter of reading r32 found again from a stage field f and its
+// LSQ gradient planes G (k_grad), for the two-kernel transposes: per cell and interior edge slot s
+// and direction a, bit 2 (8 s + a - 1) = the edge's upwind value was clipped, the next bit = to the
+// cell's own value (the layout the ring-tiled sweeps record).  The upwind value and the clip are
+// formed as the two-kernel sweeps form them.
+template <typename T>
+__global__ void __launch_bounds__(256) k_clip_states(Geo<T> g, const T *__restrict__ f, const T *__restrict__ G,
+                                                     uint64_t *__restrict__ clip) {
+    const int c = cell_index();
+    if (c >= g.n) return;
+    const int n = g.n;
+    uint64_t cm = 0;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const size_t si = (size_t)s * n + c;
+        const int nb = g.nbr[si];
+        if (nb < 0) continue;
+        const T nlx = g.nlx[si], nly = g.nly[si], rx = g.rfx[si], ry = g.rfy[si], qx = g.qx[si], qy = g.qy[si];
+#pragma unroll
+        for (int a = 1; a < 9; ++a) {
+            const T end = T(ex(a)) * nlx + T(ey(a)) * nly;
+            const size_t pa = (size_t)a * n, px = (size_t)(2 * (a - 1)) * n, py = px + n;
+            const T vc = f[pa + c], vn = f[pa + nb];
+            const T val = end >= T(0) ? vc + G[px + c] * rx + G[py + c] * ry : vn + G[px + nb] * qx + G[py + nb] * qy;
+            const T lim = clip_between(val, vc, vn);
+            const bool clipped = lim != val;
+            const int bit = 2 * (8 * s + a - 1);
+            cm |= (uint64_t)clipped << bit;
+            cm |= (uint64_t)(clipped && lim == vc) << (bit + 1);
+        }
+    }
+    clip[c] = cm;
 }
 
 // Reverse of the gradient limiter of reading r35 on the two-kernel paths (after k_adv_T1 without
@@ -442,6 +493,10 @@ struct AdjBufs {
     // the gradient-plane adjoints of the two-kernel transposes [16][n] (nullptr: the state's own
     // gradient planes, which a recompute on the side stream of a ring-tiled state may be using)
     T *Gb = nullptr;
+    // the face-value limiter of r32 on the two-kernel transposes: the stage field [9][n] and the
+    // clip states [n] formed again there
+    T *sf = nullptr;
+    uint64_t *clipr = nullptr;
 };
 
 // Reverse of the third stage and of the combination f^{n+1} = Q + dt/3 Ga3, given lf3 (the

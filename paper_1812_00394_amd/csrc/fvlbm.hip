@@ -1019,15 +1019,31 @@ void adv_transpose(fvlbm_state *st, const T *f, const T *tau1, const T *lam, T l
 #undef FVLBM_T_RING
         return;
     }
-    if (clip) throw Error(FVLBM_ESTATE, "adv_transpose: the limited convection's adjoint needs the ring-tiled sweep");
     if (!acc) k_fill<T><<<blocks_for(9 * (size_t)g.n), kBlock, 0, s>>>(9 * g.n, out, T(0));
     T *Gb = ab.Gb ? ab.Gb : (T *)st->G;
+    // the face-value limiter of r32: its clip states formed again from the stage field and its
+    // gradient planes (the two-kernel sweeps record none); the planes go to the state's own gradient
+    // buffer, free here (these states recompute on the caller's stream only)
+    const bool lim1 = p.limiter == 1;
+    if (lim1) {
+        if (!(ab.sf && ab.clipr && Gb != (T *)st->G))
+            throw Error(FVLBM_ESTATE, "adv_transpose: the face-value limiter's reverse has no buffers");
+        const T *sf = f;
+        if (tau1) {
+            k_collide1<T><<<nbk, kBlock, 0, s>>>(g.n, f, tau1, ab.sf, p);
+            sf = ab.sf;
+        }
+        k_grad<T><<<nbk, kBlock, 0, s>>>(g, sf, (T *)st->G, T(st->par.rho0));
+        k_clip_states<T><<<nbk, kBlock, 0, s>>>(g, sf, (const T *)st->G, ab.clipr);
+    }
     // the gradient limiter of r35: its reverse between the edge part and the LSQ transposes
     const bool bj = p.limiter == 2;
     if (bj && !(ab.lD && ab.bjc)) throw Error(FVLBM_ESTATE, "adv_transpose: the gradient limiter's reverse has no buffers");
     if (bj) {
         k_adv_T1<T, false><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, Gb);
         k_adv_T_bj<T><<<nbk, kBlock, 0, s>>>(g, f, tau1, a_dt, T(st->par.rho0), Gb, out, ab.lD, ab.bjc, dth);
+    } else if (lim1) {
+        k_adv_T1<T, true, true><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, Gb, ab.clipr);
     } else {
         k_adv_T1<T><<<nbk, kBlock, 0, s>>>(g, lam, lscale, out, Gb);
     }
@@ -1089,6 +1105,8 @@ struct AdjLayout {
     T *lD;              // the gradient limiter's reverse (reading r35): bound parts [8][n] and their codes
     int8_t *bjc;
     T *Gb;              // gradient-plane adjoints of the two-kernel transposes [16][n]
+    T *sf;              // the face-value limiter on the two-kernel transposes: a stage field [9][n] and
+    uint64_t *clipr;    // its clip states [n]
     T *seg2, *stg2;     // a second set of segment buffers when the run has more than one segment
     uint64_t *clip, *clip2;   // per step of a segment: the r32 clip states of its three sweeps [3][n]
     double *pbar;
@@ -1172,6 +1190,8 @@ size_t adj_carve(Carver &cv, int64_t n, int32_t n_steps, int32_t ckpt, bool over
     L.lD = cv.take<T>(8 * (size_t)n);
     L.bjc = cv.take<int8_t>(8 * (size_t)n);
     L.Gb = cv.take<T>(16 * (size_t)n);
+    L.sf = cv.take<T>(9 * (size_t)n);
+    L.clipr = cv.take<uint64_t>(n);
     L.pbar = cv.take<double>(5 * (size_t)n);
     return cv.off + 256;
 }
@@ -1332,6 +1352,8 @@ void reverse_step(fvlbm_state *st, const AdjLayout<T> &L, const T *slot, const S
     b.lD = L.lD;
     b.bjc = L.bjc;
     b.Gb = L.Gb;
+    b.sf = L.sf;
+    b.clipr = L.clipr;
     // the SST reverse of one solve: from the adjoints of its outputs (k, omega: lk, lw; tau: lt) to
     // those of its inputs (the macro variables M, added onto lf through the moments of the field they
     // came from; k^n, omega^n into lk_out, lw_out)
@@ -1939,8 +1961,6 @@ fvlbm_status fvlbm_record(fvlbm_state *st, int32_t n_steps, int32_t ckpt_every, 
     return guarded([&] {
         if (!st || !workspace) throw Error(FVLBM_EINVAL, "record: NULL argument");
         if (n_steps < 1 || ckpt_every < 1) throw Error(FVLBM_EINVAL, "record: n_steps and ckpt_every must be >= 1");
-        if (st->par.limiter == 1 && !st->ring)
-            throw Error(FVLBM_ESTATE, "record: the face-value limiter's adjoint needs the ring-tiled sweep");
         if (st->sst && st->par.sst_sweeps > kMaxAdjSstSweeps)
             throw Error(FVLBM_ESTATE, "record: the implicit SST variant's adjoint takes at most " + std::to_string(kMaxAdjSstSweeps) + " sweeps");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "record: workspace must be 256-byte aligned");

@@ -576,12 +576,13 @@ def test_gradient_limiter_adjoint_against_complex_step(F, name, sweep, monkeypat
     _check_run_adjoint(F, m, p, f0, k0, w0, sst, 3)
 
 
-@pytest.mark.parametrize("sweep", ["ring", "pair"])
+@pytest.mark.parametrize("sweep", ["ring", "pair", "split", "face"])
 @pytest.mark.parametrize("name", ["duct_laminar", "naca_sst"])
 def test_limited_adjoint_against_complex_step(F, name, sweep, monkeypatch):
-    """The adjoint through the face-value limiter of reading r32 (ring path): the forward sweeps
-    record which edges were clipped and to which cell's value, the transposed convection routes each
-    clipped edge's adjoint to that value.  Dot product of the adjoint of a 3-step recorded run
+    """The adjoint through the face-value limiter of reading r32: the ring-tiled forward sweeps record
+    which edges were clipped and to which cell's value (the two-kernel reverse forms those states again
+    from the stage field and its gradient planes), the transposed convection routes each clipped
+    edge's adjoint to that value.  Dot product of the adjoint of a 3-step recorded run
     (checkpoint every 2) with the oracle's complex-step derivative along a random direction, within
     1e-9, and the parameter gradient within 1e-8; on the O-mesh the lift/drag adjoint as well.  The
     case must clip: the limited oracle run differs from the unlimited one."""
