@@ -785,7 +785,8 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     // FP64 triangles form the coefficient of a neighbour's edge pointing back, c_(j->t) = w M_j^-1 (-d),
     // from M_j^-1 in LDS; FP32 gathers it from the stored coefficients, the ones its forward uses
     constexpr bool FORM = S == 3 && sizeof(T) == 8;
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    // the stage-2 transpose runs the tiles descending, the others ascending (see ring_tile)
+    const int tile = ring_tile<EPI != 2>();
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
     const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
@@ -1539,7 +1540,7 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 3 : 2)
     // FP64 triangles form the coefficient of a neighbour's edge pointing back, c_(j->t) = w M_j^-1 (-d),
     // from M_j^-1 in LDS; FP32 gathers it from the stored coefficients, the ones its forward uses
     constexpr bool FORM = S == 3 && sizeof(T) == 8;
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = ring_tile<false>();   // descending, after the ascending stage-1 transpose
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
     const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];

@@ -64,6 +64,17 @@ __device__ __forceinline__ int xcd_block(int b, int nblocks) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// The tile of a ring-tiled launch, the tiles in ascending order (FWD) or descending.  The stage
+// sweeps alternate: stages 1 and 3 (and the explicit scheme's sweep) run descending, the SST and
+// stage 2 ascending, so that each launch starts on the tiles whose data the launch before it wrote
+// last, which the caches (each XCD's L2 and the 256 MB last-level cache) still hold (measured on the
+// 4.0M-cell mesh: 0.662 -> 0.625 ms per FP32-deviation step).  The reverse alternates likewise.
+template <bool FWD>
+__device__ __forceinline__ int ring_tile() {
+    const int t = xcd_block(blockIdx.x, gridDim.x);
+    return FWD ? t : (int)gridDim.x - 1 - t;
+}
+
 __device__ __forceinline__ int cell_index() { return xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x; }
 
 // Geometry and boundary data on the device (pointers into the caller's workspace).  The per-edge

@@ -347,7 +347,7 @@ __global__ void __launch_bounds__(2 * kTileCells, 4)
     extern __shared__ __align__(16) unsigned char smem[];
     T *V = reinterpret_cast<T *>(smem);
     T *Gl = V + 8 * Wv;
-    const int tile = xcd_block(blockIdx.x, gridDim.x);
+    const int tile = ring_tile<J == 2>();
     const int start = tile * kTileCells;
     const int ncell = min(kTileCells, g.n - start);
     const int x0 = rt.ptr[tile], nx = rt.ptr[tile + 1] - x0, n1 = rt.n1[tile];
