@@ -205,6 +205,35 @@ def test_implicit_sst_adjoint_sweep_limit(F):
     np.testing.assert_array_equal(st.get_f(), f0)
 
 
+@pytest.mark.parametrize("sweep", ["ring", "split"])
+@pytest.mark.parametrize("limiter", [1, 2])
+def test_fp32_limited_adjoint(F, limiter, sweep, monkeypatch):
+    """The FP32-deviation adjoint through the limiters (face-value clip of r32, gradient limiter of
+    r35) on the SST O-mesh: the gradient of lam . final state over 3 recorded steps (checkpoint every
+    2) meets the FP32 gate of check_fp32_gradient against the oracle's complex step."""
+    say("fp32dev limited adjoint", limiter, sweep)
+    monkeypatch.setenv("FVLBM_SWEEP", sweep)
+    m, p, orc, f0, k0, w0, sst = _run_case("naca_sst", seed=89)
+    p = dict(p, limiter=limiter)
+    n = f0.shape[1]
+    N = 3
+    rng = np.random.default_rng(90)
+    lf = rng.standard_normal((9, n))
+    lk = rng.standard_normal(n) * 1e3
+    lw = rng.standard_normal(n)
+    st = F.State(F.Mesh(m), p, precision="fp32dev", k=k0, omega=w0)
+    st.set_state(f0, k0, w0)
+    st.record(N, ckpt_every=2)
+    g = st.adjoint_state(lf, lk, lw)[3]
+    ref = []
+    for key in PARAMS:
+        pc = dict(p)
+        pc[key] = p[key] + 1j * H
+        fN, kN, wN = _oracle_final(m, pc, f0.astype(complex), k0.astype(complex), w0.astype(complex), N)
+        ref.append((np.sum(lf * np.imag(fN)) + np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))) / H)
+    check_fp32_gradient(g, np.asarray(ref))
+
+
 @pytest.mark.parametrize("name, limiter", [("backstep_sst", 0), ("naca_sst", 0), ("naca_sst", 1)])
 def test_fp32_with_fp64_geometry_adjoint(F, name, limiter, monkeypatch):
     """The adjoint of an FP32-deviation state whose ring sweeps form the edge data from FP64 geometry
