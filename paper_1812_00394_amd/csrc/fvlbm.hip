@@ -550,18 +550,25 @@ void launch_sst_jacobi(fvlbm_state *st, const T *K0, const T *W0, T *K1, T *W1, 
     const int nbk = blocks_for(g.n);
     const int m = st->par.sst_sweeps;
     Timed t(st, FVLBM_K_SST_JACOBI);
+    // the launches alternate their block order, the first descending after the ascending system launch
     if (m == 1) {
-        k_sst_jacobi<T, S, false, true><<<nbk, kBlock, 0, s>>>(g, J, J + 8 * n, nullptr, K0, W0, K1, W1, tau_out, nut, p);
+        k_sst_jacobi<T, S, false, true, false><<<nbk, kBlock, 0, s>>>(g, J, J + 8 * n, nullptr, K0, W0, K1, W1, tau_out, nut, p);
         return;
     }
     // sweep 1 gave R' (planes 8, 9); sweeps 2 .. m alternate between planes 10-11 and 12-13
     const T *din = J + 8 * n;
     for (int i = 2; i < m; ++i) {
         T *dout = J + (i % 2 ? 12 : 10) * n;
-        k_sst_jacobi<T, S, true, false><<<nbk, kBlock, 0, s>>>(g, J, din, dout, K0, W0, K1, W1, tau_out, nut, p);
+        if (i % 2 == 0)
+            k_sst_jacobi<T, S, true, false, false><<<nbk, kBlock, 0, s>>>(g, J, din, dout, K0, W0, K1, W1, tau_out, nut, p);
+        else
+            k_sst_jacobi<T, S, true, false, true><<<nbk, kBlock, 0, s>>>(g, J, din, dout, K0, W0, K1, W1, tau_out, nut, p);
         din = dout;
     }
-    k_sst_jacobi<T, S, true, true><<<nbk, kBlock, 0, s>>>(g, J, din, nullptr, K0, W0, K1, W1, tau_out, nut, p);
+    if (m % 2 == 0)
+        k_sst_jacobi<T, S, true, true, false><<<nbk, kBlock, 0, s>>>(g, J, din, nullptr, K0, W0, K1, W1, tau_out, nut, p);
+    else
+        k_sst_jacobi<T, S, true, true, true><<<nbk, kBlock, 0, s>>>(g, J, din, nullptr, K0, W0, K1, W1, tau_out, nut, p);
 }
 
 // One ring launch of the SST kernel; FP32 states with FP64 geometry take the kernel that forms the

@@ -1391,14 +1391,16 @@ __device__ __forceinline__ void sst_row_finish(S rho, S k, S w, S net_k, S net_w
 
 // One Jacobi sweep of both increments, cell per thread: delta <- R' + sum_s c_s delta_N (ITER), or
 // delta taken as it is (the single-sweep case).  FIN: k^{n+1} = max(k^n + delta, floor), omega
-// likewise, then nu_t and tau; else the new increments go to dout.
-template <typename T, int S, bool ITER, bool FIN>
+// likewise, then nu_t and tau; else the new increments go to dout.  FWD: the blocks' cell ranges in
+// ascending order, else descending within each XCD's range (consecutive sweeps alternate, as the ring
+// sweeps do).
+template <typename T, int S, bool ITER, bool FIN, bool FWD = true>
 __global__ void __launch_bounds__(256) k_sst_jacobi(Geo<T> g, const T *__restrict__ J, const T *__restrict__ din,
                                                     T *__restrict__ dout, const T *__restrict__ K0,
                                                     const T *__restrict__ W0, T *__restrict__ K1,
                                                     T *__restrict__ W1, T *__restrict__ tau, T *__restrict__ nut,
                                                     StepPar<T> p) {
-    const int c = cell_index();
+    const int c = ring_tile<FWD>() * (int)blockDim.x + (int)threadIdx.x;
     if (c >= g.n) return;
     const size_t n = (size_t)g.n;
     T dk, dw;
