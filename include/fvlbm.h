@@ -314,7 +314,8 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   checkpoint every ckpt_every steps: checkpoints (11 n values each), one segment of states
  *   (ckpt_every + 1 of 11 n values) and of stage data (59 n values per step), a second such
  *   segment when the run has more than one, adjoint fields (including those of the implicit SST
- *   variant's reverse, 70 n values, and of the two-kernel transposes, 24 n values and 8 n bytes).
+ *   variant's reverse, 70 n values, and of the two-kernel transposes with the limiters' reverses,
+ *   33 n values and 16 n bytes).
  * fvlbm_record: advances the state n_steps steps exactly as fvlbm_step does, storing the state
  *   (f, k, omega) at the start of every segment and at the end in `workspace` (device memory owned
  *   by the caller, 256-byte aligned, kept alive until the adjoint has run).  Segments have at most
@@ -322,8 +323,9 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   last two (the last one when the run has one segment) are kept whole, with their stage data, in
  *   the two sets of segment buffers, so that the reverse recomputes neither.  With the face-value
  *   limiter (limiter 1) the ring-tiled sweeps keep its clip states in the stage data; after the
- *   other sweeps the reverse forms them again from the recorded stage fields.  Errors: FVLBM_EINVAL (NULL,
- *   n_steps or ckpt_every < 1, workspace misaligned or too small), FVLBM_ESTATE.
+ *   other sweeps the reverse forms them again from the recorded stage fields.  Errors:
+ *   FVLBM_EINVAL (NULL, n_steps or ckpt_every < 1, workspace misaligned or too small),
+ *   FVLBM_ESTATE.
  * fvlbm_adjoint_step: for J = seed[0] F_x + seed[1] F_y + seed[2] J_R of the final state (forces of
  *   the walls in wall_group_mask and the reversed-flow length, as fvlbm_forces), returns
  *   dparams = dJ/d(theta, sigma_k1, sigma_omega1, beta*, a1) in FP64, differentiating the discrete
@@ -336,9 +338,9 @@ fvlbm_status fvlbm_apply_advection_adjoint(fvlbm_state *st, const double *g_in, 
  *   segment is reversed on the caller's stream; the two are ordered by events and the call returns
  *   with all work on the caller's stream.  The reverse: the combination and stage collisions in closed
  *   form, the convection term by its transpose, the SST update (or the implicit variant's system,
- *   by its transposed Jacobi sweeps and rows), fluxes, closure and LSQ gradients by their
- *   transposes.  The state is restored to the
- *   final recorded state afterwards.  A call that changes the state after fvlbm_record
+ *   by its transposed Jacobi sweeps and rows), fluxes, closure and LSQ gradients (with the
+ *   gradient limiter, through its selections found again) by their transposes.  The state is
+ *   restored to the final recorded state afterwards.  A call that changes the state after fvlbm_record
  *   (fvlbm_step, fvlbm_step_explicit, fvlbm_run_to_residual, fvlbm_set_state) drops the recording:
  *   the tape would no longer end at the current state.  Errors: FVLBM_ESTATE without a recording
  *   (never recorded, or dropped), FVLBM_EDIVERGED.
