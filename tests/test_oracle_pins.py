@@ -606,6 +606,7 @@ def _mp_sst_point(rho, nu, d, gu, gk, gw, k, w, c):
     arg1 = min(max(mp.sqrt(k) / (mp.mpf("0.09") * w * d), 500 * mu / (rho * w * d * d)),
                4 * rho * c["sigma_w2"] * k / (CD * d * d))
     F1 = mp.tanh(arg1 ** 4)
+    cd_branch = arg1 == 4 * rho * c["sigma_w2"] * k / (CD * d * d)
     arg2 = max(2 * mp.sqrt(k) / (mp.mpf("0.09") * w * d), 500 * mu / (rho * w * d * d))
     F2 = mp.tanh(arg2 ** 2)
     mut = c["a1"] * rho * k / max(c["a1"] * w, S * F2)
@@ -613,10 +614,16 @@ def _mp_sst_point(rho, nu, d, gu, gk, gw, k, w, c):
     tau_ij = [[mut * (2 * Sij[i][j] - mp.mpf(2) / 3 * div * (i == j)) - mp.mpf(2) / 3 * rho * k * (i == j)
                for j in range(2)] for i in range(2)]
     P = sum(tau_ij[i][j] * Sij[i][j] for i in range(2) for j in range(2))
-    return dict(S=S, div=div, CD=CD, F1=F1, F2=F2, mut=mut, P=P)
+    return dict(S=S, div=div, CD=CD, F1=F1, F2=F2, mut=mut, P=P, cd_branch=cd_branch)
 
 
-def test_sst_pointwise_against_printed_formulas():
+@pytest.mark.parametrize("k0, w0, gk, gw", [(1e-3, 2.0, (2e-4, -3e-4), (0.4, 0.9)),
+                                            (1e-4, 0.1, (5e-2, 2e-2), (0.5, 0.2))])
+def test_sst_pointwise_against_printed_formulas(k0, w0, gk, gw):
+    """S, div u, CD_kw, F1, F2, mu_t and P of the oracle's closure against the printed formulas of
+    Section 2 in 40-digit arithmetic, on linear fields over a jittered mesh.  The first gradient set
+    has grad k . grad omega < 0 (CD at its floor); the second a positive product large enough that
+    arg1 takes its third branch, 4 rho sigma_w2 k / (CD d^2), in some of the sampled cells."""
     mesh = mg.rectangle(14, 14, Lx=1.0, Ly=1.0, kind="channel", jitter=0.2, seed=23)
     nu = 2e-4
     orc = O.Oracle(mesh, O.default_params(nu=nu, dt=1e-3, sst=True, group_u=[[0.05, 0], [0, 0], [0, 0]],
@@ -626,23 +633,26 @@ def test_sst_pointwise_against_printed_formulas():
     gu = (0.02, 0.3, -0.1, 0.01)
     ux = 0.05 + gu[0] * x + gu[1] * y
     uy = 0.01 + gu[2] * x + gu[3] * y
-    gk, gw = (2e-4, -3e-4), (0.4, 0.9)
-    k = 1e-3 + gk[0] * x + gk[1] * y
-    w = 2.0 + gw[0] * x + gw[1] * y
+    k = k0 + gk[0] * x + gk[1] * y
+    w = w0 + gw[0] * x + gw[1] * y
     rho = np.ones(G.n)
     orc.sst_update(rho, ux, uy, k, w)
     diag = orc.last_sst
     bcell = set(G.cell[G.bidx].tolist())
     cells = [c for c in range(G.n) if c not in bcell]
     c = dict(O.SST_DEFAULTS)
+    branch = []
     for cc in cells[::5]:
         ref = _mp_sst_point(1.0, nu, G.wall_dist[cc], gu, gk, gw, k[cc], w[cc], c)
+        branch.append(bool(ref["cd_branch"]))
         for key in ("S", "div", "CD", "F1", "F2", "mut", "P"):
             got = diag[key][cc]
             assert abs(got - float(ref[key])) <= 1e-10 * max(abs(float(ref[key])), 1e-300), (key, cc, got, ref[key])
-    # the blending must really blend somewhere in this sample
+    # the blending must really blend somewhere in this sample; the second set reaches arg1's CD branch
     F1 = diag["F1"][cells]
     assert F1.min() < 0.5 < F1.max()
+    if gk[0] * gw[0] + gk[1] * gw[1] > 0:
+        assert any(branch) and not all(branch), branch
 
 
 def test_sst_manufactured_advection_and_cross_diffusion():
