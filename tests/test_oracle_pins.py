@@ -591,6 +591,43 @@ def test_sst_wall_omega_value():
     np.testing.assert_allclose(w1[far], w0 / (1 + dt * 0.075 * w0), rtol=1e-13)
 
 
+def test_inlet_prescribes_velocity_only():
+    """Reading r3 at an inlet: the ghost state takes the prescribed velocity and the cell's own
+    density (with its non-equilibrium part), so a uniform equilibrium stream at the inlet velocity is
+    steady under the convection term whatever density it has, even when the inlet group's density
+    value differs (it is not used)."""
+    U = 0.05
+    m = mg.rectangle(8, 4, kind="duct", split="none")
+    orc = O.Oracle(m, O.default_params(nu=0.01, dt=0.05, group_u=[[U, 0], [0, 0], [U, 0]],
+                                       group_rho=[1.3, 1.0, 1.0]))
+    n = orc.g.n
+    f = O.feq(np.ones(n), np.full(n, U), np.zeros(n))
+    assert np.abs(orc.advection(f)).max() < 1e-15
+
+
+def test_outlet_prescribes_density():
+    """Reading r3 at an outlet: the ghost state takes the prescribed density and the cell's own
+    velocity.  A laminar channel (inlet velocity U, walls, outlet density 1.05) started at density 1
+    settles to a flow whose density, extrapolated linearly from the last two cell columns to the
+    outlet edge, is the prescribed 1.05 (to 5e-4; the steady Poiseuille pressure gradient is what the
+    last half cell adds).  A ghost that kept the cell's density would impose nothing: the mass the
+    inlet feeds would pile up (the density then passes 2)."""
+    U = 0.05
+    m = mg.rectangle(12, 4, kind="channel", split="none")
+    orc = O.Oracle(m, O.default_params(nu=0.02, dt=0.05, group_u=[[U, 0], [0, 0], [0, 0]],
+                                       group_rho=[1.0, 1.05, 1.0]))
+    G = orc.g
+    n = G.n
+    f = O.feq(np.ones(n), np.full(n, U), np.zeros(n))
+    f = orc.run(f, None, None, 2000)[0]
+    rho = O.moments(f)[0]
+    x = G.xc[:, 0]
+    last = x > 1 - 1 / 12
+    prev = (x > 1 - 2 / 12) & ~last
+    r_last, r_prev = rho[last].mean(), rho[prev].mean()
+    assert abs(r_last + (r_last - r_prev) / 2 - 1.05) < 5e-4, (r_last, r_prev)
+
+
 def _mp_sst_point(rho, nu, d, gu, gk, gw, k, w, c):
     """Printed SST formulas (Section 2) evaluated in 40-digit arithmetic."""
     mp.mp.dps = 40
