@@ -853,6 +853,43 @@ def test_sst_negative_sources_implicit():
     np.testing.assert_allclose(w1[cells], ew, rtol=1e-12)
 
 
+def test_sst_negative_sources_implicit_variant():
+    """Readings r29 and r34 together, at density 1.3: the setting of the r29 pin (uniform k, omega,
+    linear velocity with positive divergence, both sources negative) solved by the implicit variant
+    with enough Jacobi sweeps to converge.  A uniform increment d has L d = -d rho div A (first-order
+    upwind of a constant, no diffusion), so in cells five rings from the boundary (whose influence
+    falls by the coupling ratio, about 1e-2, per ring) exactly
+        k1 = k + R_k / (sigma_k + dt div),  R_k = -dt k div + dt P / rho - dt beta* w k,
+        sigma_k = 1 + dt beta* w + dt |P| / (rho k),
+    and likewise omega with beta2 and P_w + cross diffusion (zero here)."""
+    mesh = mg.rectangle(14, 14, kind="open", split="none")
+    nu, dt, rho0 = 1e-5, 0.05, 1.3
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True, sst_sweeps=400, group_u=[[0.0, 0.0]],
+                                          group_rho=[rho0], group_k=[1e-4], group_w=[10.0]))
+    G = orc.g
+    x, y = G.xc[:, 0], G.xc[:, 1]
+    n = G.n
+    a = 0.1
+    ux, uy = 0.02 + a * x, -0.01 + a * y
+    k, w = np.full(n, 1e-4), np.full(n, 10.0)
+    k1, w1, _, _ = orc.sst_update(np.full(n, rho0), ux, uy, k, w)
+    h = 1.0 / 14
+    cells = np.nonzero((np.minimum(x, 1 - x) > 5 * h) & (np.minimum(y, 1 - y) > 5 * h))[0]
+    assert len(cells) >= 16
+    S2, div = 2 * (a * a + a * a), 2 * a
+    P = rho0 * k[0] * ((S2 - 2 / 3 * div ** 2) / w[0] - 2 / 3 * div)
+    c = dict(O.SST_DEFAULTS)
+    cw2 = c["beta2"] / c["beta_star"] - c["sigma_w2"] * c["kappa"] ** 2 / np.sqrt(c["beta_star"])
+    Pw = cw2 * rho0 * (S2 - 2 / 3 * div ** 2) - 2 / 3 * cw2 * rho0 * w[0] * div
+    assert P < 0 and Pw < 0
+    Rk = -dt * k[0] * div + dt * P / rho0 - dt * 0.09 * w[0] * k[0]
+    Rw = -dt * w[0] * div + dt * Pw / rho0 - dt * 0.0828 * w[0] * w[0]
+    sk = 1 + dt * 0.09 * w[0] + dt * (-P) / (rho0 * k[0])
+    sw = 1 + dt * 0.0828 * w[0] + dt * (-Pw) / (rho0 * w[0])
+    np.testing.assert_allclose(k1[cells], k[0] + Rk / (sk + dt * div), rtol=1e-10)
+    np.testing.assert_allclose(w1[cells], w[0] + Rw / (sw + dt * div), rtol=1e-10)
+
+
 def test_sst_stays_positive_from_impulsive_start():
     """Readings r28-r29: a uniform stream started impulsively between walls (large near-wall
     gradients, wall omega >> interior omega) keeps k and omega positive and the relaxation time
