@@ -890,6 +890,33 @@ def test_sst_negative_sources_implicit_variant():
     np.testing.assert_allclose(w1[cells], w[0] + Rw / (sw + dt * div), rtol=1e-10)
 
 
+def test_sst_face_value_upper_bound():
+    """Reading r28's upper bound: the upwind reconstructed k at an edge is kept at most twice the
+    upwind cell's value.  A uniform stream U in x over a periodic strip of uniform quads, omega
+    uniform (no production, no cross diffusion, F1 = 0 without walls), k = 1 except two adjacent
+    columns at eps = 1e-2.  In the downstream column of the two the LSQ gradient (1 - eps) / (2 dx)
+    would extrapolate eps + (1 - eps) / 4 to its outflow edge, so that value is 2 eps; its inflow edge
+    takes the upstream column's extrapolation eps - (1 - eps) / 4 < 0, bounded to 0.  With the
+    two-point diffusion through the edge to the k = 1 column, exactly
+        k1 = (eps + dt / A (-U h 2 eps + Gamma_f (1 - eps) h / dx)) / (1 + dt beta* w),
+    Gamma_f = nu + (eps + 1) / (2 w) (mu_t = rho k / w here)."""
+    nx, ny = 10, 3
+    mesh = mg.rectangle(nx, ny, kind="periodic", split="none")
+    nu, dt, U, w0, eps = 1e-9, 0.05, 0.05, 1e3, 1e-2
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True))
+    G = orc.g
+    n = G.n
+    dx, h = 1.0 / nx, 1.0 / ny
+    col = np.floor(G.xc[:, 0] / dx).astype(int)
+    j = 5
+    k = np.ones(n)
+    k[(col == j) | (col == j - 1)] = eps
+    k1, _, _, _ = orc.sst_update(np.ones(n), np.full(n, U), np.zeros(n), k, np.full(n, w0))
+    Gf = 0.5 * ((nu + eps / w0) + (nu + 1.0 / w0))
+    expect = (eps + dt / (dx * h) * (-U * h * 2 * eps + Gf * (1.0 - eps) / dx * h)) / (1 + dt * 0.09 * w0)
+    np.testing.assert_allclose(k1[col == j], expect, rtol=1e-12)
+
+
 def test_sst_stays_positive_from_impulsive_start():
     """Readings r28-r29: a uniform stream started impulsively between walls (large near-wall
     gradients, wall omega >> interior omega) keeps k and omega positive and the relaxation time
