@@ -18,10 +18,8 @@ top of each function and collected in the design notes (readings r1-r35).
 
 Parity unpinned (no closed form or property pins them; mutations of them pass every pin): the
 far-field ghost state's dropped non-equilibrium part and the reconstructed values of outgoing
-directions at open boundary edges (reading r3; its inlet and outlet treatments are pinned); in the
-SST fluxes the reconstructed outflow value at boundary edges and the cell density in the
-boundary mass flux (the pins with boundary fluxes run at rho = 1); the coupling choices r11-r12,
-and r33-r34 beyond their pins.
+directions at open boundary edges (reading r3; its inlet and outlet treatments are pinned); the
+coupling choices r11-r12, and r33-r34 beyond their pins.
 
 Half-face convention: every cell edge, seen from its cell, is one "half-face" h with
   cell[h], nbr[h] (-1 on a boundary), bface[h] (-1 inside), nl[h] = outward normal times length,

@@ -917,6 +917,37 @@ def test_sst_face_value_upper_bound():
     np.testing.assert_allclose(k1[col == j], expect, rtol=1e-12)
 
 
+def test_sst_outlet_cells_closed_form():
+    """The SST fluxes of an outlet cell, at density 1.2: a uniform stream U in x through a duct of
+    uniform quads (inlet, outlet, far field without flow through it), omega uniform (no sources,
+    F1 = 0 without walls), k linear in x with slope b.  The outlet's zero-gradient ghost (k_c at the
+    edge midpoint, dx / 2 away) makes the outlet cell's LSQ slope b / 2, so its reconstructed outflow
+    value is k_c + b dx / 4; its inflow edge takes the west cell's k_c - b dx / 2 (that cell's
+    gradient is exact); the two-point diffusion leaves through the west edge only.  Exactly
+        k1 = (k_c + dt / (rho A) (rho U h (k_c - b dx / 2) - rho U h (k_c + b dx / 4) - Gamma_f b h))
+             / (1 + dt beta* w),   Gamma_f = rho nu + rho (k_c + k_W) / (2 w).
+    This pins the boundary mass flux's density and the reconstructed outflow value at boundary
+    edges."""
+    nx, ny = 10, 4
+    mesh = mg.rectangle(nx, ny, kind="duct", split="none")
+    nu, dt, U, w0, r1 = 1e-4, 0.05, 0.05, 1.0, 1.2
+    a, b = 1e-3, 1e-3
+    orc = O.Oracle(mesh, O.default_params(nu=nu, dt=dt, sst=True, group_u=[[U, 0], [0, 0], [U, 0]],
+                                          group_rho=[r1, r1, r1], group_k=[a, a, a], group_w=[w0, w0, w0]))
+    G = orc.g
+    n = G.n
+    x = G.xc[:, 0]
+    dx, h = 1.0 / nx, 1.0 / ny
+    k = a + b * x
+    k1, _, _, _ = orc.sst_update(np.full(n, r1), np.full(n, U), np.zeros(n), k, np.full(n, w0))
+    last = x > 1 - dx
+    kc = k[last]
+    kW = kc - b * dx
+    Gf = r1 * nu + 0.5 * r1 * (kc + kW) / w0
+    net = r1 * U * h * (kc - b * dx / 2) - r1 * U * h * (kc + b * dx / 4) - Gf * b * h
+    np.testing.assert_allclose(k1[last], (kc + dt / (r1 * dx * h) * net) / (1 + dt * 0.09 * w0), rtol=1e-12)
+
+
 def test_sst_stays_positive_from_impulsive_start():
     """Readings r28-r29: a uniform stream started impulsively between walls (large near-wall
     gradients, wall omega >> interior omega) keeps k and omega positive and the relaxation time
