@@ -17,9 +17,9 @@ face values, gradients, boundary conditions) or is garbled, the readings used ar
 top of each function and collected in the design notes (readings r1-r35).
 
 Parity unpinned (no closed form or property pins them; mutations of them pass every pin): the
-far-field ghost state's dropped non-equilibrium part and the reconstructed values of outgoing
-directions at open boundary edges (reading r3; its inlet and outlet treatments are pinned); the
-coupling choices r11-r12, and r33-r34 beyond their pins.
+coupling choices r11-r12, and r33-r34 beyond their pins.  Reading r3's open edges are pinned: the
+inlet and outlet ghosts by properties of steady flows, the far-field ghost's free-stream
+equilibrium and the reconstructed values of outgoing directions by closed forms on a duct.
 
 Half-face convention: every cell edge, seen from its cell, is one "half-face" h with
   cell[h], nbr[h] (-1 on a boundary), bface[h] (-1 inside), nl[h] = outward normal times length,
@@ -330,7 +330,7 @@ class Oracle:
         """Ghost states at boundary midpoints (reading r3, non-equilibrium extrapolation): walls the
         wall velocity with the cell's density; inlets (incoming directions) the prescribed velocity
         with the cell's density; outlets the prescribed density with the cell's velocity; far field
-        the free-stream equilibrium alone (this last part parity unpinned)."""
+        the free-stream equilibrium alone."""
         c = self.b_cell
         gc = g_arr[:, c]
         rc, uxc, uyc = rho[c], ux[c], uy[c]

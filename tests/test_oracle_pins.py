@@ -605,6 +605,50 @@ def test_inlet_prescribes_velocity_only():
     assert np.abs(orc.advection(f)).max() < 1e-15
 
 
+def test_open_edges_closed_form():
+    """Reading r3 at open edges, in closed form on a duct of uniform quads (inlet, outlet, far field
+    at the top and bottom).  (1) A field linear in x, f_a = w_a (1 + s x): for the directions that
+    leave through the inlet or the outlet the ghost state is the cell's own value (dx / 2 away), so the
+    cell's LSQ slope is half the field's and its reconstructed value at the open edge is
+    f_c +- b dx / 4 (b = w_a s); with the neighbour's exact reconstruction on the other side the
+    convection term of those cells (away from the far-field rows) is exactly -(3/4) e_x b.
+    (2) A uniform state feq(rho_b, u_b) + n with a non-equilibrium part n of zero mass and momentum:
+    the far field gives the incoming directions the free-stream equilibrium alone, a value n below the
+    cell's, which also bends the cell's LSQ slope to -+n / h; the convection term of the far-field rows
+    (away from the ends) is exactly -(3/2) |e_y| n_a / h for those directions, 0 for the others, and
+    0 in the rows two or more cells away from the far field."""
+    nx, ny = 8, 6
+    dx, h = 1.0 / nx, 1.0 / ny
+    U = 0.05
+    mesh = mg.rectangle(nx, ny, kind="duct", split="none")
+    orc = O.Oracle(mesh, O.default_params(group_u=[[U, 0], [0, 0], [U, 0]], group_rho=[1.0, 1.0, 1.0]))
+    G = orc.g
+    n = G.n
+    col = np.floor(G.xc[:, 0] / dx).astype(int)
+    row = np.floor(G.xc[:, 1] / h).astype(int)
+    s = 0.2
+    Ga = orc.advection(O.WT[:, None] * (1 + s * G.xc[:, 0])[None, :])
+    mid = (row >= 2) & (row <= ny - 3)
+    checked = 0
+    for c_open, out in ((nx - 1, 1), (0, -1)):
+        sel = mid & (col == c_open)
+        for a in range(9):
+            if O.EX[a] * out > 0:
+                np.testing.assert_allclose(Ga[a, sel], -0.75 * O.EX[a] * O.WT[a] * s, rtol=1e-12)
+                checked += 1
+    assert checked == 6
+    neq = 1e-3 * O.WT * 3 * O.EX * O.EY
+    f = (O.feq(np.ones(1), np.full(1, U), np.zeros(1))[:, 0] + neq)[:, None] * np.ones(n)[None, :]
+    Ga = orc.advection(f)
+    for r, inward in ((ny - 1, -1), (0, 1)):
+        sel = (row == r) & (col >= 1) & (col <= nx - 2)
+        for a in range(9):
+            expect = -1.5 * abs(O.EY[a]) * neq[a] / h if O.EY[a] * inward > 0 else 0.0
+            np.testing.assert_allclose(Ga[a, sel], expect, rtol=1e-12, atol=1e-15)
+    # rows next to the far-field rows take those rows' bent slopes in their upwind values
+    assert np.abs(Ga[:, (row >= 2) & (row <= ny - 3)]).max() < 1e-15
+
+
 def test_outlet_prescribes_density():
     """Reading r3 at an outlet: the ghost state takes the prescribed density and the cell's own
     velocity.  A laminar channel (inlet velocity U, walls, outlet density 1.05) started at density 1
