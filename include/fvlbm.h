@@ -24,7 +24,8 @@
  *     forces a sweep variant (ring, pair: only where it fits, one or two threads per cell in the
  *     stage sweeps; face: the edge loop with atomics, kept for
  *     the measured comparison with the cell loops; its sums' order, and so the last bits of its
- *     results, vary from run to run); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
+ *     results, vary from run to run; creating a state fails with FVLBM_EMESH on a mesh where a
+ *     periodic cell is its own neighbour across an edge); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
  *     of segment buffers (no kept second tape, no overlap).  Both are read when a state is created
  *     or a run recorded.
  *   - Distribution functions are indexed by the D2Q9 direction a = 0..8 with lattice
