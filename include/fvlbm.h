@@ -115,7 +115,10 @@ typedef struct fvlbm_state fvlbm_state;
  *              zero increment (one SST launch that writes the system, then m - 1 sweep launches,
  *              one launch when m = 1).  Ignored when sst = 0.  The adjoint differentiates it for
  *              m <= 16 (it keeps every sweep's increments; fvlbm_record rejects m > 16 with
- *              FVLBM_ESTATE).  Errors: FVLBM_EINVAL outside [0, 1000].
+ *              FVLBM_ESTATE).  Errors: FVLBM_EINVAL outside [0, 1000]; FVLBM_EMESH (from
+ *              fvlbm_init) with m > 0 on a mesh where a periodic cell is its own neighbour across
+ *              an edge (a single row or column of periodic cells), whose coupling Jacobi would
+ *              have to keep on the diagonal.
  */
 typedef struct {
     double nu, dt, rho0;
