@@ -3,8 +3,9 @@ no halo), periodic cells that are their own neighbour across every edge or reach
 neighbour through two different edges, and cells whose every edge is a boundary edge (walls and a
 moving lid, inlet / outlet / walls, far field all round).  Against the FP64 oracle (Section 3.1
 Eqs. (imexone)-(imextwo) with the SST of Section 2 on each step): the FP64 step on every sweep
-variant, a laminar step, FP32-deviation storage at its gate, and the adjoint of three recorded
-steps against the oracle's complex step."""
+variant, a laminar step, FP32-deviation storage at its gate, the adjoint of three recorded steps
+against the oracle's complex step, the step's options (limiters, per-stage and implicit SST) and the
+explicit scheme."""
 import sys
 
 import numpy as np
@@ -234,3 +235,24 @@ def test_degenerate_variant_step_parity(F, name, variant):
     rhs = (np.sum(lf * np.imag(fN)) + np.sum(lk * np.imag(kN)) + np.sum(lw * np.imag(wN))) / H
     lhs = np.sum(lf0 * vf) + np.sum(lk0 * vk) + np.sum(lw0 * vw)
     assert abs(lhs - rhs) <= 1e-9 * abs(rhs), (lhs, rhs)
+
+
+@pytest.mark.parametrize("sst", [False, True])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_degenerate_explicit_step_parity(F, name, sst):
+    """The explicit scheme (forward Euler of the semi-discrete equation, Section 3.1) at dt = tau,
+    laminar and with the SST: one step at 1e-12, three more at 1e-11."""
+    say("degenerate explicit step", name, sst)
+    m, p, orc, f, k, w = _case(name, sst=sst, seed=14)
+    p = dict(p, nu=p["dt"] / 3)
+    orc = O.Oracle(m, p)
+    st = F.State(F.Mesh(m), p, precision="fp64", k=k, omega=w)
+    st.set_state(f, k, w)
+    fo, ko, wo = f, k, w
+    for nsteps, tol in ((1, 1e-12), (3, 1e-11)):
+        for _ in range(nsteps):
+            fo, ko, wo = orc.step_explicit(fo, ko, wo)
+        st.step_explicit(nsteps)
+        assert _rel(st.get_f(), fo, np.abs(fo - O.WT[:, None]).max()) < tol, (nsteps,)
+        if sst:
+            assert _rel(st.moments()["omega"], wo, np.abs(wo).max()) < 10 * tol, (nsteps,)
