@@ -190,7 +190,9 @@ fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *mesh, int32_t precision, int32_
  *   workspace: device memory of at least fvlbm_state_bytes() bytes, 256-byte aligned, owned by
  *              the caller and alive until fvlbm_state_destroy.
  *   hip_stream: the hipStream_t all work of this state is enqueued on (NULL = default stream).
- * The mesh must outlive the state.  Errors: FVLBM_EINVAL, FVLBM_EDEVICE.
+ * The mesh must outlive the state.  Errors: FVLBM_EINVAL, FVLBM_EDEVICE; FVLBM_EMESH where the
+ * edge loop (FVLBM_SWEEP=face) or the implicit SST (params->sst_sweeps > 0) meets a periodic cell
+ * that is its own neighbour across an edge.
  */
 fvlbm_status fvlbm_init(const fvlbm_mesh *mesh, const fvlbm_params *params, int32_t precision,
                         const double *rho, const double *u, const double *k, const double *omega,
