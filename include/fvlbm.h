@@ -24,8 +24,7 @@
  *     forces a sweep variant (ring, pair: only where it fits, one or two threads per cell in the
  *     stage sweeps; face: the edge loop with atomics, kept for
  *     the measured comparison with the cell loops; its sums' order, and so the last bits of its
- *     results, vary from run to run; creating a state fails with FVLBM_EMESH on a mesh where a
- *     periodic cell is its own neighbour across an edge); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
+ *     results, vary from run to run); FVLBM_ADJ_OVERLAP = 0 gives the adjoint one set
  *     of segment buffers (no kept second tape, no overlap).  Both are read when a state is created
  *     or a run recorded.
  *   - Distribution functions are indexed by the D2Q9 direction a = 0..8 with lattice
@@ -191,8 +190,8 @@ fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *mesh, int32_t precision, int32_
  *              the caller and alive until fvlbm_state_destroy.
  *   hip_stream: the hipStream_t all work of this state is enqueued on (NULL = default stream).
  * The mesh must outlive the state.  Errors: FVLBM_EINVAL, FVLBM_EDEVICE; FVLBM_EMESH where the
- * edge loop (FVLBM_SWEEP=face) or the implicit SST (params->sst_sweeps > 0) meets a periodic cell
- * that is its own neighbour across an edge.
+ * implicit SST (params->sst_sweeps > 0) meets a periodic cell that is its own neighbour across an
+ * edge.
  */
 fvlbm_status fvlbm_init(const fvlbm_mesh *mesh, const fvlbm_params *params, int32_t precision,
                         const double *rho, const double *u, const double *k, const double *omega,
