@@ -114,10 +114,9 @@ typedef struct fvlbm_state fvlbm_state;
  *              zero increment (one SST launch that writes the system, then m - 1 sweep launches,
  *              one launch when m = 1).  Ignored when sst = 0.  The adjoint differentiates it for
  *              m <= 16 (it keeps every sweep's increments; fvlbm_record rejects m > 16 with
- *              FVLBM_ESTATE).  Errors: FVLBM_EINVAL outside [0, 1000]; FVLBM_EMESH (from
- *              fvlbm_init) with m > 0 on a mesh where a periodic cell is its own neighbour across
- *              an edge (a single row or column of periodic cells), whose coupling Jacobi would
- *              have to keep on the diagonal.
+ *              FVLBM_ESTATE).  A periodic cell that is its own neighbour across an edge keeps
+ *              that coupling on the diagonal (Jacobi with the diagonal of the whole matrix).
+ *              Errors: FVLBM_EINVAL outside [0, 1000].
  */
 typedef struct {
     double nu, dt, rho0;
@@ -189,9 +188,7 @@ fvlbm_status fvlbm_state_bytes(const fvlbm_mesh *mesh, int32_t precision, int32_
  *   workspace: device memory of at least fvlbm_state_bytes() bytes, 256-byte aligned, owned by
  *              the caller and alive until fvlbm_state_destroy.
  *   hip_stream: the hipStream_t all work of this state is enqueued on (NULL = default stream).
- * The mesh must outlive the state.  Errors: FVLBM_EINVAL, FVLBM_EDEVICE; FVLBM_EMESH where the
- * implicit SST (params->sst_sweeps > 0) meets a periodic cell that is its own neighbour across an
- * edge.
+ * The mesh must outlive the state.  Errors: FVLBM_EINVAL, FVLBM_EDEVICE.
  */
 fvlbm_status fvlbm_init(const fvlbm_mesh *mesh, const fvlbm_params *params, int32_t precision,
                         const double *rho, const double *u, const double *k, const double *omega,

@@ -1323,6 +1323,14 @@ __device__ __forceinline__ void impl_row(const Geo<T> &g, const SstAdj &sa, cons
             }
         }
     }
+    // a periodic cell that is its own neighbour across an edge: that coupling is on the diagonal
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (g.nbr[(size_t)s * n + c] == c) {
+            r.dk = r.dk - r.ck[s];
+            r.dw = r.dw - r.cw[s];
+            r.ck[s] = r.cw[s] = zero;
+        }
     r.fac = T(dt * g.inv_area[c]) * recip(r.rho);
     r.dstk = dt * p.bstar * r.wc;
     r.dstw = dt * r.beta * r.wc;
@@ -1394,6 +1402,13 @@ __global__ void __launch_bounds__(256) k_adj_impl_rows(Geo<T> g, SstAdj sa, cons
     const T lsk_ = -lqk * r.qk * r.qk, lsw_ = -lqw * r.qw * r.qw;
     lfac += lsk_ * r.dk + lsw_ * r.dw;
     const T ldk = lsk_ * r.fac, ldw = lsw_ * r.fac;
+    // a self-neighbour slot's in + D enters the diagonal with a minus sign; its coupling is zero
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (g.nbr[(size_t)s * n + c] == c) {
+            lck[s] = -ldk;
+            lcw[s] = -ldw;
+        }
     // N = fac net + s - dst phi
     lfac += lNk * r.net_k + lNw * r.net_w;
     T lsk = lNk, lsw = lNw;

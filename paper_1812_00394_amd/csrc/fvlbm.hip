@@ -1688,12 +1688,6 @@ fvlbm_status fvlbm_init(const fvlbm_mesh *m, const fvlbm_params *p, int32_t prec
         if (p->sst && (!k || !omega)) throw Error(FVLBM_EINVAL, "init: SST needs k and omega");
         if (p->limiter < 0 || p->limiter > 2) throw Error(FVLBM_EINVAL, "init: limiter must be 0, 1 or 2");
         if (p->sst_sweeps < 0 || p->sst_sweeps > kMaxSstSweeps) throw Error(FVLBM_EINVAL, "init: sst_sweeps must be in [0, " + std::to_string(kMaxSstSweeps) + "]");
-        // the Jacobi sweeps take every coupling from a neighbour's previous iterate; a periodic cell
-        // that is its own neighbour would need that coupling on the diagonal instead
-        if (p->sst && p->sst_sweeps > 0)
-            for (size_t s = 0; s < m->nbr.size(); ++s)
-                if (m->nbr[s] == (int32_t)(s % (size_t)m->n))
-                    throw Error(FVLBM_EMESH, "init: the implicit SST needs every interior edge between two distinct cells");
         if (reinterpret_cast<uintptr_t>(workspace) % 256) throw Error(FVLBM_EINVAL, "init: workspace must be 256-byte aligned");
         const size_t need = layout_bytes(m, precision, p->sst ? 1 : 0);
         if (ws_bytes < need) throw Error(FVLBM_EINVAL, "init: workspace too small (" + std::to_string(ws_bytes) + " < " + std::to_string(need) + ")");

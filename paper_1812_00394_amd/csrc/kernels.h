@@ -1561,6 +1561,14 @@ __global__ void __launch_bounds__(256) k_sst_b(Geo<T> g, const int32_t *__restri
     aux[(size_t)13 * n + c] = M[(size_t)n + c];
     aux[(size_t)14 * n + c] = M[(size_t)2 * n + c];
     if constexpr (IMPL) {
+        // a periodic cell that is its own neighbour across an edge: that coupling is on the diagonal
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (g.nbr[(size_t)s * n + c] == c) {
+                row.dk = row.dk - ck[s];
+                row.dw = row.dw - cw[s];
+                ck[s] = cw[s] = T(0);
+            }
         T Rk, Rw, gk, gw;
         sst_row_finish<T, T>(xc[0], xc[3], xc[4], net_k, net_w, aux[(size_t)6 * n + c], aux[(size_t)7 * n + c],
                              aux[(size_t)8 * n + c], g.inv_area[c], p, sst_params(p), row, Rk, Rw, gk, gw);
@@ -1804,6 +1812,14 @@ __global__ void __launch_bounds__(kTileCells, sizeof(T) == 4 ? 4 : 2)
         aux[(size_t)11 * n + c] = net_w;
     }
     if constexpr (IMPL) {
+        // a periodic cell that is its own neighbour across an edge: that coupling is on the diagonal
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+            if (g.nbr[(size_t)s * n + c] == c) {   // nb[] holds tile-local codes here
+                row.dk -= ck[s];
+                row.dw -= cw[s];
+                ck[s] = cw[s] = T(0);
+            }
         T Rk, Rw, gk, gw;
         sst_row_finish<T, T>(rho, kc, wc, net_k, net_w, oc.sk, oc.sw, oc.beta, ia, p, q, row, Rk, Rw, gk, gw);
 #pragma unroll
